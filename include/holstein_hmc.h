@@ -1,0 +1,195 @@
+/*
+ * holstein_hmc.h - C ABI of the MI355X (gfx950) fermion solver for the
+ * Holstein-model hybrid Monte Carlo of Cohen-Stead et al.,
+ * "Fast and scalable quantum Monte Carlo simulations of electron-phonon
+ * models" (arXiv:2203.01291).
+ *
+ * The library applies the space-time fermion matrix M of Eq. (M_def),
+ * solves the normal equations (M^T M) u = Phi of Eqs. (psi_def, CG) with
+ * conjugate gradients, optionally preconditioned by the adiabatic
+ * preconditioner of Sec. V (Eqs. P_def, CG_precon, P_change_basis, App. C),
+ * evaluates the action S_F = Phi . u (Eq. Sf_Psi) and the phonon force
+ * dS_F/dx of Eq. (dSF_dx).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: L x L periodic square lattice, L even and >= 4, N = L*L sites,
+ *   site index i = x + L*y.  Hopping K_ij = -t between nearest neighbours
+ *   (Eq. V_K_def).  Ltau time slices, Ltau even and >= 2, tau = 0..Ltau-1.
+ * Field: x[tau][i] (FP64), row-major, site fastest.  E[tau][i] =
+ *   exp(-dtau*(alpha*x[tau][i] - mu)) is the diagonal of exp(-dtau V_tau)
+ *   (Eqs. B_def, V_K_def).
+ * Vectors: v[r][tau][i] for right-hand side r, site fastest; one
+ *   right-hand side holds d = N*Ltau elements.  FP64 (double) unless an
+ *   entry point says otherwise; FP32 buffers are float with the same layout.
+ * Operator: B_tau = diag(E_tau) C with the checkerboard product
+ *   C = P_A P_B ~ exp(-dtau K): P_A (P_B) exponentiates exactly the hopping
+ *   of the disjoint 2x2 plaquettes whose lower-left corner has even (odd)
+ *   x and y, wrapping periodically; P_B acts first (Sec. II D, "minimal
+ *   split" checkerboard; O(dtau^2) error).  Each plaquette factor is
+ *   kron(C2, C2), C2 = [[cosh(dtau t), sinh(dtau t)], [sinh(dtau t),
+ *   cosh(dtau t)]].
+ *   (M v)_tau  = v_tau - E_tau * (C v~_{tau-1}),  v~_{-1} = -v_{Ltau-1};
+ *   (M^T w)_tau = w_tau - C^T (E_{tau+1} * w~_{tau+1}),
+ *                 w~_{Ltau} = -w_0, E_{Ltau} = E_0.
+ *
+ * Memory and streams
+ * ------------------
+ * All data pointers named *_dev are device pointers owned by the caller;
+ * the library never frees or retains them past the call.  The library owns
+ * only the handle and the workspace allocated by fph_create.  Work is
+ * enqueued on the caller's hipStream_t (passed as void*; NULL means the
+ * null stream).  A handle must not be used from two streams at once.
+ * Entry points that return results on the host (pcg_solve statistics,
+ * fph_precond_info) synchronise that stream before returning; all others
+ * only enqueue.
+ *
+ * Errors
+ * ------
+ * Every entry point returns FPH_OK (0) on success, a negative FPH_E* code
+ * for an argument error detected on the host before anything is enqueued,
+ * or FPH_E_HIP for a failed HIP call.  fph_strerror() gives a message.
+ * Numerical outcomes of a solve are reported in fph_pcg_stats_t.status.
+ */
+#ifndef HOLSTEIN_HMC_H
+#define HOLSTEIN_HMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPH_OK 0
+#define FPH_E_NULL (-1)       /* a required pointer is NULL               */
+#define FPH_E_LATTICE (-2)    /* L odd or < 4, Ltau odd or < 2, bad param */
+#define FPH_E_NRHS (-3)       /* nrhs < 1 or above the handle's max_rhs   */
+#define FPH_E_PREC (-4)       /* unsupported precision / operator code    */
+#define FPH_E_NOFIELD (-5)    /* fph_set_field has not been called        */
+#define FPH_E_ALIGN (-6)      /* device pointer not 16-byte aligned       */
+#define FPH_E_ARG (-7)        /* other invalid argument                   */
+#define FPH_E_HIP (-100)      /* a HIP runtime call failed                */
+
+/* Status bits of fph_pcg_stats_t.status. */
+#define FPH_ST_CONVERGED 1    /* true relative residual below tol         */
+#define FPH_ST_MAXITER 2      /* iteration cap reached                    */
+#define FPH_ST_BREAKDOWN 4    /* p.Ap <= 0 or r.z <= 0 in CG              */
+#define FPH_ST_NONFINITE 8    /* NaN or Inf met in a scalar of the solve  */
+
+typedef struct fph_handle_s* fph_handle_t;
+
+typedef struct {
+  int32_t L;     /* lattice side, even, >= 4                             */
+  int32_t Ltau;  /* number of time slices, even, >= 2                    */
+  double dtau;   /* imaginary-time step                                  */
+  double t;      /* nearest-neighbour hopping                            */
+  double mu;     /* chemical potential                                   */
+  double alpha;  /* electron-phonon coupling                             */
+} fph_lattice_t;
+
+typedef enum { FPH_OP_M = 0, FPH_OP_MT = 1, FPH_OP_MTM = 2 } fph_op_t;
+
+typedef enum { FPH_F64 = 0, FPH_F32 = 1, FPH_F32_REFINED = 2 } fph_prec_t;
+
+/* Preconditioner operators: F ~ P^{-1}, its transpose, and F F^T. */
+typedef enum { FPH_PC_F = 0, FPH_PC_FT = 1, FPH_PC_FFT = 2 } fph_pc_op_t;
+
+typedef struct {
+  double tol;           /* stop when |b - M^T M u| / |b| < tol            */
+  int32_t maxiter;      /* cap on CG iterations (all precisions)           */
+  int32_t use_precond;  /* 1: z = F F^T r (Eq. CG_precon); 0: z = r        */
+  int32_t prec;         /* fph_prec_t: FP64 CG, or FP32 CG with FP64
+                           reliable updates of the residual (FP32_REFINED) */
+  int32_t zero_guess;   /* 1: start from u = 0; 0: u_dev holds the guess   */
+  double ru_delta;      /* FP32_REFINED: recompute the FP64 residual when
+                           the FP32 residual has fallen by this factor
+                           since the last recomputation (0 -> 0.1)        */
+  int32_t chunk;        /* CG iterations enqueued between host checks
+                           (0 -> library default)                         */
+  int32_t reserved;
+} fph_pcg_opts_t;
+
+typedef struct {
+  int32_t status;       /* FPH_ST_* bits                                   */
+  int32_t iters;        /* CG iterations performed                         */
+  int32_t outer_iters;  /* FP64 residual recomputations                    */
+  int32_t matvecs;      /* applications of M^T M, all precisions           */
+  double rel_resid;     /* final |b - M^T M u| / |b|, evaluated in FP64    */
+  double action;        /* S_F = b . u in FP64 (Eq. Sf_Psi)                */
+} fph_pcg_stats_t;
+
+/* Library version string. */
+const char* fph_version(void);
+
+/* Message for a return code. */
+const char* fph_strerror(int code);
+
+/* Create a handle for one lattice and up to max_rhs right-hand sides;
+ * allocates all device workspace once (Sec. II C defines the parameters).
+ * Returns FPH_E_LATTICE for an unsupported lattice, FPH_E_NRHS for
+ * max_rhs < 1.  On error *h is set to NULL. */
+int fph_create(fph_handle_t* h, const fph_lattice_t* lat, int32_t max_rhs);
+
+/* Release the handle and its workspace (synchronises the device). */
+int fph_destroy(fph_handle_t h);
+
+/* Per-field setup from x_dev[Ltau][N] (FP64, device): E = exp(-dtau V)
+ * in FP64 and FP32 (Eq. B_def), dbar_i = mean_tau E[tau][i] (Eq. expnVbar),
+ * spectral bounds of Bbar = diag(dbar) C enclosing its real eigenvalues,
+ * bmin = min(dbar) e^{-4 dtau |t|}, bmax = max(dbar) e^{4 dtau |t|}, and the
+ * Chebyshev tables of App. C: N_P(w) = max(1, floor(db (a1/phi_w + a2)))
+ * (Eq. NP_heuristic) and c_m(w) by Chebyshev-Gauss quadrature with
+ * 2 N_P points (Eq. Cheby-Gauss).  a1, a2 <= 0 select 1.  Enqueue only. */
+int fph_set_field(fph_handle_t h, const double* x_dev, double a1, double a2,
+                  void* stream);
+
+/* out = op(in) for nrhs right-hand sides sharing the current field
+ * (Eq. M_def): op is FPH_OP_M, FPH_OP_MT or FPH_OP_MTM (fused M^T M; the
+ * intermediate M v never leaves the chip).  prec FPH_F64: in/out are
+ * double; FPH_F32: float (E rounded to nearest FP32).  in and out must not
+ * overlap.  Enqueue only. */
+int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs,
+                   const void* in_dev, void* out_dev, void* stream);
+
+/* Solve (M^T M) u = b for nrhs right-hand sides with (preconditioned)
+ * conjugate gradients (Eqs. CG, CG_precon).  b_dev, u_dev: double
+ * [nrhs][Ltau][N]; u_dev is the initial guess unless opts->zero_guess and
+ * receives the solution.  stats_host: array of nrhs entries filled on
+ * return (may be NULL).  Blocks the calling thread until the solve has
+ * finished on `stream`.  Returns FPH_OK even when a right-hand side did
+ * not converge: check stats.status. */
+int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
+              const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
+              void* stream);
+
+/* grad_dev[Ltau][N] += scale * sum_r dS_F/dx for the solutions
+ * u_dev[nrhs][Ltau][N] of the current field (Eq. dSF_dx with Lambda = I):
+ *   dS_F/dx_{i,tau} = -2 dtau alpha (u - y)_{i,tau} y_{i,tau},
+ *   y_tau = E_tau * (C u~_{tau-1}),
+ * so that (u - y) = M u.  Enqueue only. */
+int fermion_force(fph_handle_t h, int32_t nrhs, const double* u_dev,
+                  double* grad_dev, double scale, void* stream);
+
+/* out_dev[r] = b_r . u_r in FP64 for r < nrhs (S_F of Eq. Sf_Psi).
+ * Enqueue only. */
+int fermion_action(fph_handle_t h, int32_t nrhs, const double* b_dev,
+                   const double* u_dev, double* out_dev, void* stream);
+
+/* out = op(in) with the preconditioner of the current field: F ~ P^{-1}
+ * = U^dagger Ptilde^{-1} U (Eq. P_change_basis) with each block inverse
+ * replaced by its truncated Chebyshev series (Eq. f_A_approx), F^T, or
+ * F F^T.  prec FPH_F64 (double) or FPH_F32 (float).  Enqueue only. */
+int fph_precond_apply(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs,
+                      const void* in_dev, void* out_dev, void* stream);
+
+/* Copy the preconditioner tables of the current field to the host:
+ * bounds_host[2] = {bmin, bmax}; np_host[Ltau] = N_P(w) (may be NULL).
+ * Synchronises `stream`. */
+int fph_precond_info(fph_handle_t h, double* bounds_host, int32_t* np_host,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOLSTEIN_HMC_H */

@@ -1,0 +1,29 @@
+"""Plain FP64 CPU oracle for the Holstein-model fermion solve.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import anything under
+``oracle/``.  The product path (the HIP library and its Python binding)
+never imports, links or calls it, and it shares no code with that path: the
+only common module is ``workloads`` (seeded random draws, no arithmetic of
+the method).
+
+Every routine is a direct, slow, obviously checkable transcription of a
+definition in the paper (arXiv:2203.01291):
+
+* ``lattice``  - hopping matrix K, checkerboard factors of exp(-dtau K),
+                 the blocks B_tau and the space-time matrix M
+                 (Sec. II C, Eqs. M_def, B_def, V_K_def).
+* ``solve``    - direct solves of (M^T M) u = Phi via LU of M, and a
+                 textbook (P)CG for sizes where LU does not fit
+                 (Sec. II D, Eqs. psi_def, CG; Sec. V, Eq. CG_precon).
+* ``force``    - the phonon force dS_F/dx (Sec. III A, Eq. dSF_dx), and
+                 complex-step / finite-difference derivatives of S_F.
+* ``precond``  - the adiabatic preconditioner P, its Fourier-space block
+                 form and its Chebyshev (KPM) apply (Sec. V A, Eqs. P_def,
+                 Bbar, udef, Mww, P_change_basis; App. C).
+
+Parity status of each function is stated in its docstring; a function with
+no independent pin says "parity unpinned".
+"""
+
+from . import lattice, solve, force, precond  # noqa: F401
