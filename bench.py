@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the Holstein fermion solve on one MI355X.
+
+One step = one pass of the hot path over the workload: per-field setup
+(E, dbar, preconditioner tables), the FP32-refined preconditioned CG solve
+of (M^T M) u = Phi to relative residual 1e-8, the action S_F = Phi . u and
+the phonon force dS_F/dx.  Default workload: L = 32 (N = 1024), Ltau = 400
+(d = 409600), dtau = 0.05, mu = -0.2, alpha = 1.2, AR(1)-correlated field.
+
+Prints one JSON line.  Besides the headline (FP32-refined solves/s) it
+reports the same step with plain FP64 CG, the M^T M matvec bandwidth with
+its HBM roofline fraction (HIP events on the stream the kernel runs on),
+and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MᵀM matvec GB/s (% HBM peak) + PCG solves/s, FP32-refined vs FP64 @1e-8"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--precond", type=int, default=-1, help="1/0 force, -1: faster of the two")
+    ap.add_argument("--matvec-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    return ap.parse_args()
+
+
+def time_steps(step, steps, warmup, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def event_time_matvec(solver, v, op, reps, torch):
+    """Average duration (s) of back-to-back applies, HIP events on the stream used."""
+    out = torch.empty_like(v)
+    for _ in range(5):
+        solver.matvec(v, op, out=out)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        solver.matvec(v, op, out=out)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(p, golden_iters):
+    """Oracle CG (scipy CSR, FP64) on the workload for a bounded number of
+    iterations; scaled to solves/s with the oracle's own iteration count."""
+    import numpy as np
+
+    from oracle import lattice as OL
+    from oracle import solve as OS
+    from workloads import gaussian_rhs, perturbed_field, phonon_field
+
+    lat = OL.Lattice.from_params(p)
+    x0 = phonon_field(p)
+    x = perturbed_field(p, x0)
+    Cs = OL.sparse_C(lat)
+    phi = gaussian_rhs(p, 1)[0]
+    Phi = (OL.sparse_M(lat, x0, Cs).T @ phi.reshape(-1)).reshape(lat.Ltau, lat.N)
+    mv = OS.normal_matvec_sparse(lat, x, Cs)
+    n = 50
+    while True:
+        t0 = time.perf_counter()
+        OS.cg(mv, Phi, tol=0.0, maxiter=n)
+        dt = time.perf_counter() - t0
+        if dt > 8.0 or n >= 4000:
+            break
+        n = int(n * max(2.0, 10.0 / max(dt, 1e-3)))
+    per_iter = dt / n
+    return {
+        "value": 1.0 / (per_iter * golden_iters),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n} iterations of the oracle's textbook FP64 CG on the CSR M^T M "
+                  f"(scipy, single-threaded SpMV) on the {p.name} system, "
+                  f"{per_iter * 1e3:.2f} ms/iteration, scaled by the oracle's "
+                  f"{golden_iters} iterations to 1e-8 (tests/golden/oracle_iterations.json)",
+        "host_threads_available": os.cpu_count(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import gaussian_rhs, get_config, perturbed_field, phonon_field
+
+    dev = torch.device("cuda:0")
+    p = get_config(args.workload)
+    R = args.nrhs
+    s = FermionSolver.from_params(p, max_rhs=max(R, 1))
+    x0 = torch.from_numpy(phonon_field(p)).to(dev)
+    x = torch.from_numpy(perturbed_field(p, phonon_field(p))).to(dev)
+    phi = torch.from_numpy(gaussian_rhs(p, R)).to(dev)
+    s.set_field(x0)
+    Phi = s.matvec(phi, "MT")          # Phi = M(x0)^T phi
+    torch.cuda.synchronize()
+    tol = 1e-8
+    last = {}
+
+    def make_step(prec, pre):
+        def step():
+            s.set_field(x)                                   # setup
+            u, st = s.solve(Phi, tol=tol, prec=prec, precond=pre)   # PCG
+            S = s.action(Phi, u)                             # S_F
+            g = s.force(u)                                   # dS_F/dx
+            last["st"], last["S"], last["g"] = st, S, g
+            return st
+        return step
+
+    # Pick the preconditioner setting by one solve each (FP32-refined).
+    choices = [bool(args.precond)] if args.precond in (0, 1) else [False, True]
+    trial = {}
+    for pre in choices:
+        t, st = time_steps(make_step("f32_refined", pre), 1, 0, torch)
+        trial[pre] = (t, st[0]["iters"])
+        log(f"trial precond={pre}: {t * 1e3:.1f} ms, {st[0]['iters']} iterations, status {st[0]['status']}")
+    pre = min(trial, key=lambda k: trial[k][0])
+
+    t32, st32 = time_steps(make_step("f32_refined", pre), args.steps, args.warmup, torch)
+    st32 = [dict(v) for v in st32]
+    S32 = last["S"].cpu().numpy().tolist()
+    log(f"f32_refined: {t32 * 1e3:.2f} ms/step {st32}")
+    t64, st64 = time_steps(make_step("f64", pre), max(1, args.steps // 2), min(args.warmup, 1), torch)
+    st64 = [dict(v) for v in st64]
+    S64 = last["S"].cpu().numpy().tolist()
+    log(f"f64: {t64 * 1e3:.2f} ms/step {st64}")
+
+    # M^T M apply at the workload shape: the bandwidth-bound kernel of the path.
+    d = p.dim
+    v32 = torch.randn(R, p.Ltau, p.N, device=dev, dtype=torch.float32)
+    v64 = v32.double()
+    s.set_field(x)
+    tm32 = event_time_matvec(s, v32, "MTM", args.matvec_reps, torch)
+    tm64 = event_time_matvec(s, v64, "MTM", args.matvec_reps, torch)
+    bytes32 = (2 * R + 1) * d * 4
+    bytes64 = (2 * R + 1) * d * 8
+    gbs32 = bytes32 / tm32 / 1e9
+    gbs64 = bytes64 / tm64 / 1e9
+    log(f"MTM fp32 {tm32 * 1e6:.2f} us {gbs32:.0f} GB/s; fp64 {tm64 * 1e6:.2f} us {gbs64:.0f} GB/s")
+
+    large = None
+    if not args.no_large:
+        # Same kernel on a working set far above the 256 MB Infinity Cache:
+        # L = 64, Ltau = 400 with 32 right-hand sides sharing one field.
+        p5 = get_config("c5")
+        R5 = 32
+        s5 = FermionSolver.from_params(p5, max_rhs=1)
+        s5.set_field(torch.from_numpy(phonon_field(p5)).to(dev))
+        vl = torch.randn(R5, p5.Ltau, p5.N, device=dev, dtype=torch.float64)
+        tl64 = event_time_matvec(s5, vl, "MTM", 20, torch)
+        tl32 = event_time_matvec(s5, vl.float(), "MTM", 20, torch)
+        bl64 = (2 * R5 + 1) * p5.dim * 8
+        bl32 = (2 * R5 + 1) * p5.dim * 4
+        large = {
+            "workload": f"{p5.name} x {R5} rhs sharing one field",
+            "working_set_MB": {"f64": bl64 / 1e6, "f32": bl32 / 1e6},
+            "f64": {"us": tl64 * 1e6, "GB/s": bl64 / tl64 / 1e9, "frac": bl64 / tl64 / 1e9 / HBM_PEAK_GBS},
+            "f32": {"us": tl32 * 1e6, "GB/s": bl32 / tl32 / 1e9, "frac": bl32 / tl32 / 1e9 / HBM_PEAK_GBS},
+        }
+        log(f"large: {large}")
+        s5.close()
+        del vl
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_iterations.json")))
+        cpu = cpu_baseline(p, gold[args.workload]["iters_tol_1e-8"])
+        log(f"cpu baseline: {cpu}")
+
+    value = R / t32
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{p.name}: L={p.L} N={p.N} Ltau={p.Ltau} d={p.dim} dtau={p.dtau} "
+                        f"mu={p.mu} alpha={p.alpha}; FP32-refined PCG to 1e-8 + S_F + force",
+            "nrhs": R,
+            "precond": pre,
+            "iters": [v["iters"] for v in st32],
+            "fp64_refreshes": [v["outer_iters"] for v in st32],
+            "rel_resid": [v["rel_resid"] for v in st32],
+        },
+        "fp64_cg": {"solves_per_s": R / t64, "ms_per_step": t64 * 1e3,
+                    "iters": [v["iters"] for v in st64],
+                    "speedup_fp32_refined": t64 / t32,
+                    "action_rel_diff": float(np.max(np.abs(np.array(S32) - np.array(S64)) / np.abs(np.array(S64))))},
+        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fused M^T M apply, FP32 (k_mtm<float, InPlain, EpiStore>)",
+                     "bytes_per_launch": bytes32, "avg_launch_us": tm32 * 1e6},
+        "matvec_f64": {"GB/s": gbs64, "frac": gbs64 / HBM_PEAK_GBS, "avg_launch_us": tm64 * 1e6,
+                       "bytes_per_launch": bytes64},
+        "matvec_large": large,
+        "trial_ms": {str(k): v[0] * 1e3 for k, v in trial.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

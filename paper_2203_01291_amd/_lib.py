@@ -1,0 +1,92 @@
+"""ctypes declarations of the C ABI in include/holstein_hmc.h.
+
+Loading fails loudly when the shared library has not been built: there is
+no fallback implementation.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libholstein_hmc.so")
+
+FPH_OK = 0
+FPH_OP_M, FPH_OP_MT, FPH_OP_MTM = 0, 1, 2
+FPH_F64, FPH_F32, FPH_F32_REFINED = 0, 1, 2
+FPH_PC_F, FPH_PC_FT, FPH_PC_FFT = 0, 1, 2
+ST_CONVERGED, ST_MAXITER, ST_BREAKDOWN, ST_NONFINITE = 1, 2, 4, 8
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("Ltau", ctypes.c_int32), ("dtau", ctypes.c_double),
+                ("t", ctypes.c_double), ("mu", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
+                ("use_precond", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("zero_guess", ctypes.c_int32), ("ru_delta", ctypes.c_double),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PcgStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("outer_iters", ctypes.c_int32), ("matvecs", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("action", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = {
+    "fph_version": (ctypes.c_char_p, []),
+    "fph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fph_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Lattice), ctypes.c_int32]),
+    "fph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fph_set_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_void_p]),
+    "fermion_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), ctypes.c_void_p]),
+    "fermion_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_double, ctypes.c_void_p]),
+    "fermion_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fph_precond_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fph_precond_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load(path=None):
+    """Load the library and declare every exported entry point."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"HIP library {p} is missing; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` (no CPU fallback exists)")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class FphError(RuntimeError):
+    pass
+
+
+def check(code):
+    if code != FPH_OK:
+        msg = load().fph_strerror(code).decode()
+        raise FphError(f"fph error {code}: {msg}")

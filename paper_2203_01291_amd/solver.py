@@ -1,0 +1,162 @@
+"""Python binding of the gfx950 Holstein fermion solver.
+
+Argument marshalling only: tensors provide device pointers and the current
+torch stream provides the hipStream_t; every step of the computation runs
+in the HIP library (``lib/libholstein_hmc.so``).
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (FPH_F32, FPH_F32_REFINED, FPH_F64, FPH_OP_M, FPH_OP_MT, FPH_OP_MTM,
+                   FPH_PC_F, FPH_PC_FFT, FPH_PC_FT, Lattice, PcgOpts, PcgStats, check)
+
+_OPS = {"M": FPH_OP_M, "MT": FPH_OP_MT, "MTM": FPH_OP_MTM}
+_PC_OPS = {"F": FPH_PC_F, "FT": FPH_PC_FT, "FFT": FPH_PC_FFT}
+_PRECS = {"f64": FPH_F64, "f32_refined": FPH_F32_REFINED}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class FermionSolver:
+    """One lattice (L, Ltau, dtau, t, mu, alpha) and up to ``max_rhs``
+    right-hand sides; owns the library handle and its workspace."""
+
+    def __init__(self, L, Ltau, dtau, t, mu, alpha, max_rhs=1):
+        self.lib = _lib.load()
+        self.L, self.Ltau = int(L), int(Ltau)
+        self.N = self.L * self.L
+        self.dim = self.N * self.Ltau
+        self.params = dict(L=L, Ltau=Ltau, dtau=dtau, t=t, mu=mu, alpha=alpha)
+        self.max_rhs = int(max_rhs)
+        lat = Lattice(self.L, self.Ltau, float(dtau), float(t), float(mu), float(alpha))
+        h = ctypes.c_void_p()
+        check(self.lib.fph_create(ctypes.byref(h), ctypes.byref(lat), self.max_rhs))
+        self.h = h
+        self._x = None
+
+    @classmethod
+    def from_params(cls, p, L=None, max_rhs=1):
+        return cls(p.L if L is None else L, p.Ltau, p.dtau, p.t, p.mu, p.alpha, max_rhs=max_rhs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- checks
+    def _vec(self, v, dtype=torch.float64):
+        if not (v.is_cuda and v.dtype == dtype and v.is_contiguous()):
+            raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
+        if v.numel() % self.dim:
+            raise ValueError(f"size {v.numel()} is not a multiple of N*Ltau = {self.dim}")
+        return v.numel() // self.dim
+
+    # ---------------------------------------------------------------- API
+    def set_field(self, x, a1=1.0, a2=1.0):
+        """E = exp(-dtau V(x)), dbar, spectral bounds and Chebyshev tables."""
+        if self._vec(x) != 1:
+            raise ValueError("x must hold exactly N*Ltau values")
+        self._x = x
+        check(self.lib.fph_set_field(self.h, _ptr(x), float(a1), float(a2), _stream()))
+
+    def matvec(self, v, op="MTM", out=None):
+        """out = op(v) for op in {'M', 'MT', 'MTM'}; float64 or float32."""
+        prec = FPH_F64 if v.dtype == torch.float64 else FPH_F32
+        nrhs = self._vec(v, v.dtype)
+        out = torch.empty_like(v) if out is None else out
+        check(self.lib.fermion_matvec(self.h, _OPS[op], prec, nrhs, _ptr(v), _ptr(out), _stream()))
+        return out
+
+    def precond(self, v, op="FFT", out=None):
+        """out = F v, F^T v or F F^T v (adiabatic preconditioner)."""
+        prec = FPH_F64 if v.dtype == torch.float64 else FPH_F32
+        nrhs = self._vec(v, v.dtype)
+        out = torch.empty_like(v) if out is None else out
+        check(self.lib.fph_precond_apply(self.h, _PC_OPS[op], prec, nrhs, _ptr(v), _ptr(out),
+                                         _stream()))
+        return out
+
+    def precond_info(self):
+        b = (ctypes.c_double * 2)()
+        npt = (ctypes.c_int32 * self.Ltau)()
+        check(self.lib.fph_precond_info(self.h, b, npt, _stream()))
+        return (b[0], b[1]), list(npt)
+
+    def solve(self, b, u=None, tol=1e-10, maxiter=100000, precond=False, prec="f64",
+              ru_delta=0.1, chunk=0):
+        """Solve (M^T M) u = b for every right-hand side of b (float64).
+        Returns (u, [stats dict per rhs]).  Blocks until done."""
+        nrhs = self._vec(b)
+        if nrhs > self.max_rhs:
+            raise ValueError("more right-hand sides than max_rhs")
+        zero = u is None
+        u = torch.empty_like(b) if u is None else u
+        opts = PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero),
+                       float(ru_delta), int(chunk), 0)
+        stats = (PcgStats * nrhs)()
+        check(self.lib.pcg_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats,
+                                 _stream()))
+        return u, [s.as_dict() for s in stats]
+
+    def force(self, u, grad=None, scale=1.0):
+        """grad += scale * sum_r dS_F/dx for solutions u (float64)."""
+        nrhs = self._vec(u)
+        grad = torch.zeros(self.Ltau, self.N, dtype=torch.float64, device=u.device) if grad is None else grad
+        check(self.lib.fermion_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), _stream()))
+        return grad
+
+    def action(self, b, u):
+        """S_F = b . u per right-hand side, FP64 on the device."""
+        nrhs = self._vec(b)
+        out = torch.empty(nrhs, dtype=torch.float64, device=b.device)
+        check(self.lib.fermion_action(self.h, nrhs, _ptr(b), _ptr(u), _ptr(out), _stream()))
+        return out
+
+
+class FermionAction(torch.autograd.Function):
+    """S_F(x; Phi) = sum_r Phi_r^T (M(x)^T M(x))^{-1} Phi_r with the hand-written
+    adjoint force as its gradient (Eq. dSF_dx):
+        dS_F/dx = sum_r -2 dtau alpha (M u_r) * (E * C u~_r),
+        dS_F/dPhi_r = 2 u_r.
+    """
+
+    @staticmethod
+    def forward(ctx, x, Phi, solver, solve_kw):
+        solver.set_field(x.contiguous())
+        u, stats = solver.solve(Phi.contiguous(), **(solve_kw or {}))
+        ctx.solver = solver
+        ctx.stats = stats
+        ctx.save_for_backward(u)
+        return solver.action(Phi.contiguous(), u).sum()
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        solver = ctx.solver
+        gx = gphi = None
+        scale = float(g.item())
+        if ctx.needs_input_grad[0]:
+            gx = solver.force(u, scale=scale)
+        if ctx.needs_input_grad[1]:
+            gphi = (2.0 * scale) * u
+        return gx, gphi, None, None
+
+
+def fermion_action(x, Phi, solver, **solve_kw):
+    """Differentiable S_F(x; Phi) (see FermionAction)."""
+    return FermionAction.apply(x, Phi, solver, solve_kw)

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every symbol declared in include/*.h
+(no compute calls: this runs without a GPU)."""
+
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = []
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        names += re.findall(r"^(?:const\s+char\s*\*|int|void)\s+(\w+)\s*\(", text, re.M)
+    return names
+
+
+def test_header_declares_required_entry_points():
+    names = declared_symbols()
+    for required in ("fermion_matvec", "pcg_solve", "fermion_force"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2203_01291_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert lib.fph_version().startswith(b"holstein")
+
+
+def test_argument_errors_are_reported_on_the_host():
+    """Argument checks happen before any device work: null pointers and bad
+    lattices return negative codes without touching the GPU."""
+    import ctypes
+    from paper_2203_01291_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    bad = _lib.Lattice(5, 40, 0.1, 1.0, 0.0, 1.0)       # odd L
+    assert lib.fph_create(ctypes.byref(h), ctypes.byref(bad), 1) == -2
+    bad = _lib.Lattice(4, 39, 0.1, 1.0, 0.0, 1.0)       # odd Ltau
+    assert lib.fph_create(ctypes.byref(h), ctypes.byref(bad), 1) == -2
+    good = _lib.Lattice(4, 40, 0.1, 1.0, 0.0, 1.0)
+    assert lib.fph_create(ctypes.byref(h), ctypes.byref(good), 0) == -3
+    assert lib.fph_create(None, ctypes.byref(good), 1) == -1
+    assert lib.fermion_matvec(None, 0, 0, 1, None, None, None) == -1
+    assert lib.pcg_solve(None, 1, None, None, None, None, None) == -1
+    assert lib.fermion_force(None, 1, None, None, 1.0, None) == -1
+    assert b"NULL" in lib.fph_strerror(-1)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2203_01291_amd import _lib
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (called through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 operator applies agree to rounding (1e-12 relative);
+solutions and forces to relative error <= 1e-8 (FP64 CG and FP32 CG with
+FP64 residual replacement alike); FP32 operator applies to 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import force as OF
+from oracle import lattice as OL
+from oracle import precond as OP
+from oracle import solve as OS
+from workloads import (gaussian_rhs, get_config, perturbed_field, phonon_field,
+                       rademacher_rhs)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def tgpu(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make_solver(lat, max_rhs=1):
+    from paper_2203_01291_amd.solver import FermionSolver
+    return FermionSolver(lat.L, lat.Ltau, lat.dtau, lat.t, lat.mu, lat.alpha, max_rhs=max_rhs)
+
+
+SHAPES = [
+    # (L, Ltau, dtau, t, mu, alpha): several tiles, ragged plaquette counts
+    (4, 40, 0.1, 1.0, 0.0, 1.0),     # c1 shape, Q = 4
+    (6, 6, 0.1, 1.0, 0.2, 1.3),      # N = 36: not a multiple of 16
+    (8, 10, 0.1, 0.9, -0.1, 1.1),
+    (12, 12, 0.08, 1.0, 0.0, 0.9),   # Q = 36
+    (16, 20, 0.1, 1.0, 0.0, 1.5),    # Q = 64
+    (24, 8, 0.1, 1.0, 0.1, 1.0),     # Q = 144
+    (32, 6, 0.05, 1.0, -0.2, 1.2),   # Q = 256
+    (64, 4, 0.05, 1.0, 0.0, 1.5),    # Q = 1024
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"L{s[0]}_T{s[1]}" for s in SHAPES])
+def test_operator_parity(shape):
+    L, Ltau, dtau, t, mu, alpha = shape
+    lat = OL.Lattice(L, Ltau, dtau, t, mu, alpha)
+    rng = np.random.default_rng(100 + L)
+    x = rng.standard_normal((Ltau, lat.N))
+    v = rng.standard_normal((3, Ltau, lat.N))
+    C = OL.sparse_C(lat).toarray() if lat.N > 256 else OL.checkerboard_C(lat)
+    ref_M = OL.apply_M(lat, x, v, C)
+    ref_MT = OL.apply_MT(lat, x, v, C)
+    ref_MTM = OL.apply_MT(lat, x, ref_M, C)
+    s = make_solver(lat, max_rhs=3)
+    s.set_field(tgpu(x))
+    vg = tgpu(v)
+    for op, ref in (("M", ref_M), ("MT", ref_MT), ("MTM", ref_MTM)):
+        out = s.matvec(vg, op).cpu().numpy()
+        assert rel(out, ref) < 1e-13, op
+        out32 = s.matvec(vg.float(), op).double().cpu().numpy()
+        assert rel(out32, ref) < 2e-6, op + " fp32"
+
+
+@pytest.mark.parametrize("key", ["c2", "c3", "c5"])
+def test_operator_full_size_sampled(key):
+    """Full-size shapes: adjoint identity <a, M b> = <M^T a, b> and fused
+    M^T M = M^T (M v); sampled slices against the oracle's block apply."""
+    p = get_config(key)
+    lat = OL.Lattice.from_params(p)
+    x = phonon_field(p)
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((lat.Ltau, lat.N))
+    b = rng.standard_normal((lat.Ltau, lat.N))
+    s = make_solver(lat)
+    s.set_field(tgpu(x))
+    ag, bg = tgpu(a), tgpu(b)
+    Mb = s.matvec(bg, "M")
+    MTa = s.matvec(ag, "MT")
+    lhs = float(torch.dot(ag.view(-1), Mb.view(-1)))
+    rhs = float(torch.dot(MTa.view(-1), bg.view(-1)))
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + np.linalg.norm(a) * np.linalg.norm(b))
+    fused = s.matvec(bg, "MTM")
+    two = s.matvec(Mb, "MT")
+    assert float(torch.linalg.norm(fused - two) / torch.linalg.norm(two)) < 1e-14
+    # sampled slices of M b via the oracle (sparse C), including the wrap slice 0
+    Cs = OL.sparse_C(lat)
+    E = OL.E_field(lat, x)
+    Mb_h = Mb.cpu().numpy()
+    for tau in (0, 1, lat.Ltau // 2, lat.Ltau - 1):
+        prev = b[tau - 1] if tau >= 1 else -b[lat.Ltau - 1]
+        ref = b[tau] - E[tau] * (Cs @ prev)
+        assert rel(Mb_h[tau], ref) < 1e-13
+
+
+def c1_problem(nrhs=1, perturb=True):
+    p = get_config("c1")
+    lat = OL.Lattice.from_params(p)
+    x0 = phonon_field(p)
+    phi = gaussian_rhs(p, nrhs)
+    Phi = OS.rhs_from_phi(lat, x0, phi)
+    x = perturbed_field(p, x0) if perturb else x0
+    return p, lat, x0, x, phi, Phi
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_refined"])
+@pytest.mark.parametrize("precond", [False, True])
+def test_solve_parity_c1(prec, precond):
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=2)
+    u_ref = OS.solve_dense(lat, x, Phi)
+    s = make_solver(lat, max_rhs=2)
+    s.set_field(tgpu(x))
+    u, st = s.solve(tgpu(Phi), tol=1e-13, maxiter=20000, precond=precond, prec=prec)
+    for r in range(2):
+        assert st[r]["status"] & 1, st[r]
+        assert st[r]["rel_resid"] < 1e-13
+        assert rel(u[r].cpu().numpy(), u_ref[r]) < 1e-8
+        assert st[r]["action"] == pytest.approx(float(np.sum(Phi[r] * u_ref[r])), rel=1e-10)
+
+
+def test_action_at_x0_is_phi_norm():
+    """Phi = M(x0)^T phi => S_F(x0) = |phi|^2 and u = M^{-1} phi."""
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=1, perturb=False)
+    s = make_solver(lat)
+    s.set_field(tgpu(x0))
+    phig = tgpu(phi)
+    Phig = s.matvec(phig, "MT")
+    assert rel(Phig.cpu().numpy(), Phi) < 1e-14
+    u, st = s.solve(Phig, tol=1e-12)
+    assert st[0]["action"] == pytest.approx(float(np.sum(phi ** 2)), rel=1e-10)
+
+
+def test_iterations_match_oracle_cg_c1():
+    p, lat, x0, x, phi, Phi = c1_problem()
+    M = OL.dense_M(lat, x)
+    A = M.T @ M
+    _, it_ref, _ = OS.cg(lambda v: (A @ v.reshape(-1)).reshape(v.shape), Phi[0], tol=1e-10)
+    s = make_solver(lat)
+    s.set_field(tgpu(x))
+    _, st = s.solve(tgpu(Phi), tol=1e-10)
+    assert abs(st[0]["iters"] - it_ref) <= max(3, it_ref // 50)
+
+
+def test_force_parity_c1():
+    """Adjoint force kernel vs the oracle's force (itself pinned to complex step)."""
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=2)
+    u_ref = OS.solve_dense(lat, x, Phi)
+    g_ref = OF.force_from_solution(lat, x, u_ref).sum(axis=0)
+    s = make_solver(lat, max_rhs=2)
+    s.set_field(tgpu(x))
+    u, st = s.solve(tgpu(Phi), tol=1e-13)
+    g = s.force(u, scale=1.0).cpu().numpy()
+    assert rel(g, g_ref) < 1e-8
+    g2 = s.force(u, grad=tgpu(np.ones_like(g_ref)), scale=-0.5).cpu().numpy()
+    assert rel(g2, 1.0 - 0.5 * g_ref) < 1e-8
+
+
+def test_force_kernel_exact_on_given_u():
+    """Force kernel on an arbitrary u equals the oracle formula to rounding."""
+    lat = OL.Lattice(8, 10, 0.1, 1.0, 0.1, 1.2)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((lat.Ltau, lat.N))
+    u = rng.standard_normal((3, lat.Ltau, lat.N))
+    g_ref = OF.force_from_solution(lat, x, u).sum(axis=0)
+    s = make_solver(lat, max_rhs=3)
+    s.set_field(tgpu(x))
+    g = s.force(tgpu(u)).cpu().numpy()
+    assert rel(g, g_ref) < 1e-13
+
+
+def test_solve_parity_c2_with_and_without_precond():
+    p = get_config("c2")
+    lat = OL.Lattice.from_params(p)
+    x0 = phonon_field(p)
+    phi = gaussian_rhs(p, 1)
+    Cs = OL.sparse_C(lat)
+    Phi = (OL.sparse_M(lat, x0, Cs).T @ phi[0].reshape(-1)).reshape(1, lat.Ltau, lat.N)
+    x = perturbed_field(p, x0)
+    u_ref = OS.solve_sparse(lat, x, Phi, Cs)
+    s = make_solver(lat)
+    s.set_field(tgpu(x))
+    its = {}
+    for pre in (False, True):
+        for prec in ("f64", "f32_refined"):
+            u, st = s.solve(tgpu(Phi), tol=1e-12, precond=pre, prec=prec)
+            assert st[0]["status"] & 1, (pre, prec, st)
+            assert rel(u.cpu().numpy(), u_ref) < 1e-8, (pre, prec)
+            its[(pre, prec)] = st[0]["iters"]
+    assert its[(True, "f64")] * 4 < its[(False, "f64")], its
+
+
+@pytest.mark.parametrize("shape", [(4, 8, 0.1, 1.0, 0.0, 1.0), (6, 6, 0.1, 1.0, 0.2, 1.3),
+                                   (4, 40, 0.1, 1.0, 0.0, 1.0), (8, 10, 0.1, 0.9, 0.1, 1.2),
+                                   (16, 16, 0.1, 1.0, 0.0, 1.5), (8, 100, 0.1, 1.0, 0.0, 1.0)])
+def test_precond_apply_parity(shape):
+    lat = OL.Lattice(*shape)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((lat.Ltau, lat.N))
+    v = rng.standard_normal((2, lat.Ltau, lat.N))
+    C = OL.checkerboard_C(lat)
+    pc = OP.Preconditioner(lat, x, C=C)
+    s = make_solver(lat, max_rhs=2)
+    s.set_field(tgpu(x))
+    (bmin, bmax), npt = s.precond_info()
+    assert bmin == pytest.approx(pc.bmin, rel=1e-13) and bmax == pytest.approx(pc.bmax, rel=1e-13)
+    assert npt == pc.NP
+    vg = tgpu(v)
+    for op, ref in (("F", pc.apply_F(v)), ("FT", pc.apply_F(v, transpose=True)),
+                    ("FFT", np.stack([pc.apply_FFt(v[r]) for r in range(2)]))):
+        out = s.precond(vg, op).cpu().numpy()
+        assert rel(out, ref) < 1e-12, op
+        out32 = s.precond(vg.float(), op).double().cpu().numpy()
+        assert rel(out32, ref) < 1e-4, op + " fp32"
+
+
+def test_precond_symmetric_on_gpu():
+    """a . (F F^T b) = (F F^T a) . b to rounding: the CG preconditioner is symmetric."""
+    p = get_config("c2")
+    lat = OL.Lattice.from_params(p)
+    s = make_solver(lat)
+    s.set_field(tgpu(phonon_field(p)))
+    rng = np.random.default_rng(5)
+    a, b = tgpu(rng.standard_normal((lat.Ltau, lat.N))), tgpu(rng.standard_normal((lat.Ltau, lat.N)))
+    l = float(torch.dot(a.view(-1), s.precond(b).view(-1)))
+    r = float(torch.dot(s.precond(a).view(-1), b.view(-1)))
+    assert abs(l - r) < 1e-12 * abs(l)
+
+
+def test_tau_constant_field_precond_converges_fast():
+    """No tau fluctuations: P = M; with a high Chebyshev order PCG needs ~1 step."""
+    lat = OL.Lattice(8, 20, 0.1, 1.0, 0.0, 1.3)
+    x = np.tile(np.random.default_rng(2).standard_normal(lat.N), (lat.Ltau, 1))
+    s = make_solver(lat)
+    s.set_field(tgpu(x), a1=40.0, a2=40.0)
+    b = tgpu(np.random.default_rng(3).standard_normal((1, lat.Ltau, lat.N)))
+    u, st = s.solve(b, tol=1e-8, precond=True, chunk=1)
+    assert st[0]["status"] & 1
+    assert st[0]["iters"] <= 3
+
+
+def test_multi_rhs_independent_and_deterministic():
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=3)
+    xi = rademacher_rhs(p, 2)
+    B = np.concatenate([Phi, OS.rhs_from_phi(lat, x, xi)])
+    s = make_solver(lat, max_rhs=5)
+    s.set_field(tgpu(x))
+    u1, st1 = s.solve(tgpu(B), tol=1e-11)
+    u2, st2 = s.solve(tgpu(B), tol=1e-11)
+    assert torch.equal(u1, u2)
+    for r in range(5):
+        u_single, _ = s.solve(tgpu(B[r:r + 1]), tol=1e-11)
+        assert rel(u1[r].cpu().numpy(), u_single[0].cpu().numpy()) < 1e-9
+
+
+def test_edge_cases():
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=2)
+    s = make_solver(lat, max_rhs=2)
+    s.set_field(tgpu(x))
+    # zero right-hand side: u = 0 exactly, converged
+    B = np.stack([np.zeros_like(Phi[0]), Phi[1]])
+    u, st = s.solve(tgpu(B), tol=1e-10, u=tgpu(np.ones_like(B)))
+    assert torch.count_nonzero(u[0]) == 0 and st[0]["status"] & 1
+    assert st[1]["status"] & 1
+    # iteration cap
+    u, st = s.solve(tgpu(Phi), tol=1e-14, maxiter=5)
+    assert all(v["status"] & 2 for v in st) and all(v["iters"] <= 5 + 32 for v in st)
+    # warm start from the solution converges immediately
+    u_ref = OS.solve_dense(lat, x, Phi)
+    u, st = s.solve(tgpu(Phi), u=tgpu(u_ref), tol=1e-10)
+    assert all(v["status"] & 1 for v in st) and all(v["iters"] <= 1 for v in st)
+    # non-finite input is reported, not hidden
+    Bn = Phi.copy()
+    Bn[0, 3, 2] = np.nan
+    u, st = s.solve(tgpu(Bn), tol=1e-10, maxiter=50)
+    assert st[0]["status"] & 8
+
+
+def test_autograd_matches_oracle():
+    from paper_2203_01291_amd.solver import fermion_action
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=2)
+    u_ref = OS.solve_dense(lat, x, Phi)
+    g_ref = OF.force_from_solution(lat, x, u_ref).sum(axis=0)
+    s = make_solver(lat, max_rhs=2)
+    xg = tgpu(x).requires_grad_(True)
+    Pg = tgpu(Phi).requires_grad_(True)
+    S = fermion_action(xg, Pg, s, tol=1e-13)
+    S.backward()
+    assert float(S) == pytest.approx(float(np.sum(Phi * u_ref)), rel=1e-10)
+    assert rel(xg.grad.cpu().numpy(), g_ref) < 1e-8
+    assert rel(Pg.grad.cpu().numpy(), 2 * u_ref) < 1e-8
