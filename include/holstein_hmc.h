@@ -62,7 +62,9 @@ extern "C" {
 
 #define FPH_OK 0
 #define FPH_E_NULL (-1)       /* a required pointer is NULL               */
-#define FPH_E_LATTICE (-2)    /* L odd or < 4, Ltau odd or < 2, bad param */
+#define FPH_E_LATTICE (-2)    /* L odd, < 4 or > 64; Ltau odd, < 2 or > 2048;
+                                 Ltau/2 not a product H1*H2 with H1 in
+                                 {1,2,3,4,5,8,10,16,20}, H2 <= 32; bad param */
 #define FPH_E_NRHS (-3)       /* nrhs < 1 or above the handle's max_rhs   */
 #define FPH_E_PREC (-4)       /* unsupported precision / operator code    */
 #define FPH_E_NOFIELD (-5)    /* fph_set_field has not been called        */
@@ -106,7 +108,10 @@ typedef struct {
                            since the last recomputation (0 -> 0.1)        */
   int32_t chunk;        /* CG iterations enqueued between host checks
                            (0 -> library default)                         */
-  int32_t reserved;
+  int32_t variant;      /* without preconditioner: 0 standard CG (two
+                           reductions, two launches per iteration); 1
+                           single-reduction CG (Chronopoulos and Gear, 1989:
+                           one launch per iteration, less stable in FP32)  */
 } fph_pcg_opts_t;
 
 typedef struct {
@@ -187,6 +192,48 @@ int fph_precond_apply(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs,
  * Synchronises `stream`. */
 int fph_precond_info(fph_handle_t h, double* bounds_host, int32_t* np_host,
                      void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Batched solves: many independent systems of uneven size.            */
+
+typedef struct {
+  fph_lattice_t lat;    /* L even in [4, 32], Ltau as for fph_create      */
+  const double* x_dev;  /* phonon field [Ltau][N] (FP64, device)          */
+  int32_t nrhs;         /* right-hand sides of this system (>= 1)          */
+  const double* b_dev;  /* [nrhs][Ltau][N] right-hand sides                */
+  double* u_dev;        /* [nrhs][Ltau][N] receives the solutions          */
+} fph_system_t;
+
+typedef struct fph_batch_s* fph_batch_t;
+
+/* Create a batch over nsys systems (the pointers in sys are recorded and
+ * read at every fph_batch_solve).  Allocates the fields E of every system
+ * and an FP32 workspace of 5 vectors per right-hand side, and sorts the
+ * (system, right-hand side) work items by size, largest first.  Errors:
+ * FPH_E_NULL, FPH_E_LATTICE (a system outside the supported range),
+ * FPH_E_NRHS (a system with nrhs < 1), FPH_E_HIP. */
+int fph_batch_create(fph_batch_t* bh, const fph_system_t* sys, int32_t nsys);
+
+/* Solve every right-hand side of every system, (M^T M) u = b as in
+ * pcg_solve, in ONE persistent launch (replayed from a captured hipGraph
+ * together with the per-system field setup): each workgroup pulls work
+ * items from a queue and runs the item's FP32 conjugate gradients with
+ * FP64 residual replacement to opts->tol (Sec. II D, Eq. CG; the paper's
+ * stochastic measurements solve many such vectors at once, Sec. VI).
+ * opts->prec must be FPH_F32_REFINED and opts->use_precond 0 (FPH_E_PREC /
+ * FPH_E_ARG otherwise).  stats_host: one entry per right-hand side in
+ * system order (may be NULL).  Blocks until done. */
+int fph_batch_solve(fph_batch_t bh, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
+                    void* stream);
+
+/* Autotune the launch shape of fph_batch_solve (threads per workgroup and
+ * workgroups per compute unit) by timing one solve of each candidate;
+ * keeps the fastest.  best_host[3] (may be NULL) receives {threads,
+ * plaquettes per thread, workgroups per CU}.  Blocks until done. */
+int fph_batch_tune(fph_batch_t bh, const fph_pcg_opts_t* opts, int32_t* best_host, void* stream);
+
+/* Release the batch (synchronises the device). */
+int fph_batch_destroy(fph_batch_t bh);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("use_precond", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("zero_guess", ctypes.c_int32), ("ru_delta", ctypes.c_double),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class PcgStats(ctypes.Structure):
@@ -36,6 +36,11 @@ class PcgStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class System(ctypes.Structure):
+    _fields_ = [("lat", Lattice), ("x_dev", ctypes.c_void_p), ("nrhs", ctypes.c_int32),
+                ("b_dev", ctypes.c_void_p), ("u_dev", ctypes.c_void_p)]
 
 
 EXPORTS = {
@@ -57,6 +62,13 @@ EXPORTS = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fph_precond_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "fph_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(System),
+                                        ctypes.c_int32]),
+    "fph_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PcgOpts),
+                                       ctypes.POINTER(PcgStats), ctypes.c_void_p]),
+    "fph_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PcgOpts),
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "fph_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _lib = None

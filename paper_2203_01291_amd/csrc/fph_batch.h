@@ -1,0 +1,226 @@
+// Batched solves of many independent systems in one persistent launch.
+//
+// A work item is one (system, right-hand side) pair.  Each workgroup takes
+// items from a queue (one atomic add per item, items sorted by size,
+// largest first) and runs the whole solve of its item: FP32 conjugate
+// gradients on M^T M (the operator sweep of fph_matvec.h over all slices
+// of the item, chunks side by side in the block), and, whenever the FP32
+// residual has fallen by `delta` or below the tolerance, an FP64 residual
+// replacement: u64 += u32, r = b - M^T M u64 evaluated in FP64 with the
+// FP64 field, iteration continues with the replaced residual.  All
+// reductions are workgroup-local, so no workgroup ever waits for another;
+// every workgroup leaves when the queue is empty.
+#pragma once
+
+#include "fph_blas.h"
+#include "fph_common.h"
+#include "fph_matvec.h"
+
+namespace fph {
+
+struct BatchItem {
+  Geom g;
+  double ch, sh;          // cosh(dtau t), sinh(dtau t)
+  const double* E64;      // [Ltau][N] of the item's system
+  const float* E32;
+  const double* b;        // right-hand side [Ltau][N]
+  double* u;              // solution (FP64)
+  float* r;               // FP32 workspace, d values each
+  float* pa;
+  float* pb;
+  float* Ap;
+  float* u32;
+  int out;                // index into the statistics array
+  int pad;
+};
+
+struct BatchStat {
+  int status, iters, outer, matvecs;
+  double rel_resid, action;
+};
+
+// Sum over the block, returned to every thread.
+template <int NT>
+FPH_DEVINL double block_allsum(double v, double* sh, double* bcast) {
+  const double s = block_sum<NT>(v, sh);
+  if (threadIdx.x == 0) *bcast = s;
+  __syncthreads();
+  const double out = *bcast;
+  __syncthreads();
+  return out;
+}
+
+// Input: p = r + beta p_old on the fly (fresh: p = r); owner stores p.
+template <typename T>
+struct InDir {
+  const T* __restrict__ z;
+  const T* __restrict__ pold;
+  T* __restrict__ pnew;
+  T beta;
+  int fresh;
+  FPH_DEVINL T load(long off) const { return fresh ? z[off] : z[off] + beta * pold[off]; }
+  FPH_DEVINL T load_owned(long off) const {
+    const T v = load(off);
+    pnew[off] = v;
+    return v;
+  }
+  FPH_DEVINL void load2(long off, T& a, T& b) const {
+    a = load(off);
+    b = load(off + 1);
+  }
+};
+
+template <int NT, int MS>
+FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, double delta,
+                                 unsigned char* lds, double* red_sh, double* bcast,
+                                 BatchStat* stats) {
+  const Geom& g = it.g;
+  const long d = g.d;
+  int S, sub, lane, nslot;
+  block_layout<NT>(g, threadIdx.x, S, sub, lane, nslot);
+  const int Tch = (g.Ltau + S - 1) / S;
+  const int tau0 = sub * Tch;
+  const bool active = (sub < S) && (tau0 < g.Ltau);
+  const int Tc = active ? min(Tch, g.Ltau - tau0) : 0;
+  const int so = (sub < S) ? sub : 0;
+
+  // Initial state: u = 0, r = b.
+  double bb = 0.0, rr = 0.0;
+  for (long k = threadIdx.x; k < d; k += NT) {
+    const double bv = it.b[k];
+    const float rv = (float)bv;
+    it.u[k] = 0.0;
+    it.u32[k] = 0.0f;
+    it.r[k] = rv;
+    bb += bv * bv;
+    rr += (double)rv * (double)rv;
+  }
+  bb = block_allsum<NT>(bb, red_sh, bcast);
+  rr = block_allsum<NT>(rr, red_sh, bcast);
+  const double tol2 = tol * tol * bb;
+  double rz = rr, rz_prev = rr, rr_ref = rr, rr_true = bb, beta = 0.0;
+  int fresh = 1, iter = 0, outer = 0, matvecs = 0, status = 0;
+  float* pold = it.pa;
+  float* pnew = it.pb;
+  if (bb == 0.0) status = 1;
+  if (!isfinite(bb)) status = 8;
+
+  while (status == 0) {
+    // Direction update fused into the operator: Ap = A (r + beta p).
+    {
+      float* buf = reinterpret_cast<float*>(lds) + (long)so * g.N;
+      float* wbuf = reinterpret_cast<float*>(lds) + (long)S * g.N + (long)so * g.N;
+      InDir<float> in{it.r, pold, pnew, (float)beta, fresh};
+      EpiDot<float> epi{it.Ap};
+      double acc = 0.0, acc2 = 0.0;
+      mtm_chunks<float, NT, MS>(g, it.E32, (float)it.ch, (float)it.sh, Tch, tau0, Tc, active,
+                                lane, nslot, buf, wbuf, 0, in, epi, acc, acc2);
+      const double pAp = block_allsum<NT>(acc, red_sh, bcast);
+      matvecs += 1;
+      if (!(pAp > 0.0) || !isfinite(pAp)) {
+        status = isfinite(pAp) ? 4 : 8;
+        break;
+      }
+      const float alpha = (float)(rz / pAp);
+      double acc_rr = 0.0;
+      for (long k = threadIdx.x; k < d; k += NT) {
+        const float rv = it.r[k] - alpha * it.Ap[k];
+        it.u32[k] += alpha * pnew[k];
+        it.r[k] = rv;
+        acc_rr += (double)rv * (double)rv;
+      }
+      rr = block_allsum<NT>(acc_rr, red_sh, bcast);
+    }
+    rz_prev = rz;
+    rz = rr;
+    beta = rz / rz_prev;
+    fresh = 0;
+    iter += 1;
+    float* t = pold;
+    pold = pnew;
+    pnew = t;
+    if (!isfinite(rr)) {
+      status = 8;
+      break;
+    }
+    if (!(rr <= tol2 || rr < delta * delta * rr_ref || iter >= maxiter)) continue;
+
+    // FP64 residual replacement.
+    const double rr_iter = rr;
+    for (long k = threadIdx.x; k < d; k += NT) {
+      it.u[k] += (double)it.u32[k];
+      it.u32[k] = 0.0f;
+    }
+    __syncthreads();
+    {
+      double* buf = reinterpret_cast<double*>(lds) + (long)so * g.N;
+      double* wbuf = reinterpret_cast<double*>(lds) + (long)S * g.N + (long)so * g.N;
+      InPlain<double> in{it.u};
+      EpiResidual<float> epi{it.b, it.r};
+      double acc = 0.0, acc2 = 0.0;
+      mtm_chunks<double, NT, MS>(g, it.E64, it.ch, it.sh, Tch, tau0, Tc, active, lane, nslot,
+                                 buf, wbuf, 0, in, epi, acc, acc2);
+      rr_true = block_allsum<NT>(acc, red_sh, bcast);
+    }
+    matvecs += 1;
+    outer += 1;
+    if (rr_true <= tol2) {
+      status = 1;
+      break;
+    }
+    if (iter >= maxiter) {
+      status = 2;
+      break;
+    }
+    double acc_rr = 0.0;
+    for (long k = threadIdx.x; k < d; k += NT) {
+      const double rv = it.r[k];
+      acc_rr += rv * rv;
+    }
+    rr = block_allsum<NT>(acc_rr, red_sh, bcast);
+    if (rr > 100.0 * rr_iter) fresh = 1;  // replaced residual far from the iterated one
+    rz = rr;
+    beta = rz / rz_prev;
+    rr_ref = rr;
+  }
+
+  // S_F = b . u in FP64.
+  double act = 0.0;
+  for (long k = threadIdx.x; k < d; k += NT) act += it.b[k] * it.u[k];
+  act = block_allsum<NT>(act, red_sh, bcast);
+  if (threadIdx.x == 0) {
+    BatchStat st;
+    st.status = status;
+    st.iters = iter;
+    st.outer = outer;
+    st.matvecs = matvecs;
+    st.rel_resid = bb > 0.0 ? sqrt(rr_true / bb) : 0.0;
+    st.action = act;
+    stats[it.out] = st;
+  }
+  __syncthreads();
+}
+
+// Persistent batched solve.  Launch: any number of blocks of NT threads;
+// LDS 2 * S * Nmax doubles (S = NT / Qmax chunks).  `queue` must be 0.
+template <int NT, int MS>
+__global__ void __launch_bounds__(NT)
+k_batch_solve(const BatchItem* __restrict__ items, int nitems, unsigned* queue, double tol,
+              int maxiter, double delta, BatchStat* stats) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red_sh[NT / 64];
+  __shared__ double bcast;
+  __shared__ int item_sh;
+  while (true) {
+    if (threadIdx.x == 0) item_sh = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int k = item_sh;
+    __syncthreads();
+    if (k >= nitems) break;
+    batch_solve_item<NT, MS>(items[k], tol, maxiter, delta, smem_raw, red_sh, &bcast, stats);
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+}  // namespace fph

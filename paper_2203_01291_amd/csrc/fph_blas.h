@@ -1,13 +1,37 @@
 // Setup, vector and CG-update kernels.
 //
-// Every reduction is deterministic: each block writes one partial sum, the
-// last block to arrive (per right-hand side) adds the partials in block
-// order and updates RhsState.  All dot products accumulate in FP64.
+// Reductions never synchronise blocks: each block writes one partial sum
+// and the next state-aware kernel folds them (see state_begin).  All dot
+// products accumulate in FP64.  Elementwise kernels move 4 elements per
+// thread per step (N = L^2 with even L is a multiple of 4).
 #pragma once
 
 #include "fph_common.h"
 
 namespace fph {
+
+// ------------------------------------------------------ 4-wide accessors
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+  using V = float4;
+  static FPH_DEVINL V ld(const float* p) { return *reinterpret_cast<const float4*>(p); }
+  static FPH_DEVINL void st(float* p, V v) { *reinterpret_cast<float4*>(p) = v; }
+};
+template <> struct Vec4<double> {
+  struct V { double x, y, z, w; };
+  static FPH_DEVINL V ld(const double* p) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    return V{a.x, a.y, b.x, b.y};
+  }
+  static FPH_DEVINL void st(double* p, V v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v.x, v.y);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v.z, v.w);
+  }
+};
+
+// ------------------------------------------------------------- set field
 
 // E = exp(-dtau (alpha x - mu)) in FP64 and its FP32 rounding (Eq. B_def).
 __global__ void k_set_field(long n, const double* __restrict__ x, double dtau,
@@ -33,158 +57,135 @@ __global__ void k_dbar(int N, int Ltau, const double* __restrict__ E64,
   dbar32[i] = (float)s;
 }
 
-// Zero-initialise the solver state and set bb = |b|^2 for each rhs.
+// ------------------------------------------------------- state kernels --
+
+// Fold pending partials and publish the state (one block per rhs).
+__global__ void __launch_bounds__(256) k_advance(StIO io) {
+  __shared__ double red_sh[4];
+  __shared__ RhsState s_sh;
+  const int r = blockIdx.x;
+  state_begin<256>(io, r, &s_sh, red_sh);
+  state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, true);
+}
+
+// |v|^2 published as partials of `kind` (P_BB at the start of a solve,
+// P_NRM for a replaced residual).  Launch: grid (nblk, nrhs).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_norm2(long d, const T* __restrict__ v, StIO io, int kind) {
+  __shared__ double red_sh[4];
+  __shared__ RhsState s_sh;
+  const int r = blockIdx.y;
+  state_begin<256>(io, r, &s_sh, red_sh);
+  if (s_sh.done) {
+    state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+    return;
+  }
+  const T* vr = v + (long)r * d;
+  double acc = 0.0;
+  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
+    const auto a = Vec4<T>::ld(vr + k);
+    acc += (double)a.x * (double)a.x + (double)a.y * (double)a.y +
+           (double)a.z * (double)a.z + (double)a.w * (double)a.w;
+  }
+  const double bs = block_sum<256>(acc, red_sh);
+  state_end(io, r, &s_sh, kind, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
+}
+
+// CG update without preconditioner: alpha = rz / pAp (from the pending
+// P_PAP partials), u += alpha p, r -= alpha Ap, and |r|^2 as P_RR partials.
+// The direction written by this iteration's operator kernel is pb when the
+// iteration count is even, pa when odd (see InPUpdate).
 // Launch: grid (nblk, nrhs), 256 threads.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_norm2(long d, const T* __restrict__ b, double* partial, unsigned* counter,
-        RhsState* st, double tol, int maxiter, int mode) {
+k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__ r,
+            const T* __restrict__ Ap, StIO io) {
   __shared__ double red_sh[4];
-  __shared__ int flag_sh;
-  const int r = blockIdx.y;
-  const T* br = b + (long)r * d;
+  __shared__ RhsState s_sh;
+  const int rh = blockIdx.y;
+  state_begin<256>(io, rh, &s_sh, red_sh);
+  if (s_sh.done) {
+    state_end(io, rh, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+    return;
+  }
+  const T* __restrict__ p = (s_sh.iter & 1) ? pa : pb;
+  const T a = (T)s_sh.alpha;
+  const long off = (long)rh * d;
   double acc = 0.0;
-  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
-    const double v = (double)br[k];
-    acc += v * v;
+  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
+    const long o = off + k;
+    auto uu = Vec4<T>::ld(u + o);
+    auto rr = Vec4<T>::ld(r + o);
+    const auto pp = Vec4<T>::ld(p + o);
+    const auto aa = Vec4<T>::ld(Ap + o);
+    uu.x += a * pp.x; uu.y += a * pp.y; uu.z += a * pp.z; uu.w += a * pp.w;
+    rr.x -= a * aa.x; rr.y -= a * aa.y; rr.z -= a * aa.z; rr.w -= a * aa.w;
+    Vec4<T>::st(u + o, uu);
+    Vec4<T>::st(r + o, rr);
+    acc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y +
+           (double)rr.z * (double)rr.z + (double)rr.w * (double)rr.w;
   }
   const double bs = block_sum<256>(acc, red_sh);
-  if (threadIdx.x == 0) partial[(long)r * gridDim.x + blockIdx.x] = bs;
-  if (last_block(counter + r, gridDim.x, &flag_sh)) {
-    const double tot = reduce_partials<256>(partial + (long)r * gridDim.x, gridDim.x, red_sh);
-    if (threadIdx.x == 0) {
-      RhsState& s = st[r];
-      if (mode == 0) {  // initialise a solve with |b|^2
-        s.bb = tot;
-        s.rr = tot;
-        s.rz = tot;
-        s.rz_prev = tot;
-        s.pAp = 0.0;
-        s.alpha = 0.0;
-        s.beta = 0.0;
-        s.rr_ref = tot;
-        s.rr_true = tot;
-        s.tol2 = tol * tol * tot;
-        s.ru_thresh = 0.0;
-        s.iter = 0;
-        s.done = (tot == 0.0) ? 1 : 0;
-        s.status = (tot == 0.0) ? 1 : (isfinite(tot) ? 0 : 8);
-        if (!isfinite(tot)) s.done = 1;
-        s.fresh = 1;
-        s.matvecs = 0;
-        s.maxiter = maxiter;
-      } else {  // |r|^2 of a replaced residual; without preconditioner rz = rr
-        s.rr = tot;
-        s.rz = tot;
-        s.rr_ref = tot;
-        s.beta = tot / s.rz_prev;
-        if (tot <= s.tol2) s.done = 1;
-      }
-      __threadfence();
-      atomicExch(counter + r, 0u);
-    }
-  }
+  state_end(io, rh, &s_sh, P_RR, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
 }
 
-// out_r = sum_k a_r[k] * b_r[k] (FP64).  Launch: grid (nblk, nrhs).
+// u64 += u32 (FP64 accumulation of the FP32 correction); u32 = 0.  Skips
+// right-hand sides marked done in `st` (no pending partials expected).
+// Launch: grid (nblk, nrhs).
 __global__ void __launch_bounds__(256)
-k_dot_out(long d, const double* __restrict__ a, const double* __restrict__ b,
-          double* partial, unsigned* counter, double* out) {
-  __shared__ double red_sh[4];
-  __shared__ int flag_sh;
-  const int r = blockIdx.y;
-  const double* ar = a + (long)r * d;
-  const double* br = b + (long)r * d;
-  double acc = 0.0;
-  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256)
-    acc += ar[k] * br[k];
-  const double bs = block_sum<256>(acc, red_sh);
-  if (threadIdx.x == 0) partial[(long)r * gridDim.x + blockIdx.x] = bs;
-  if (last_block(counter + r, gridDim.x, &flag_sh)) {
-    const double tot = reduce_partials<256>(partial + (long)r * gridDim.x, gridDim.x, red_sh);
-    if (threadIdx.x == 0) {
-      out[r] = tot;
-      __threadfence();
-      atomicExch(counter + r, 0u);
-    }
-  }
-}
-
-// dst = (TD) src, elementwise over n values.
-template <typename TS, typename TD>
-__global__ void k_cast(long n, const TS* __restrict__ src, TD* __restrict__ dst) {
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
-       k += (long)gridDim.x * blockDim.x)
-    dst[k] = (TD)src[k];
-}
-
-// u64 += u32 (FP64 accumulation of the FP32 correction); u32 = 0.
-// Skips right-hand sides with done set.  Launch: grid (nblk, nrhs).
-__global__ void k_flush(long d, float* __restrict__ u32, double* __restrict__ u64,
-                        const RhsState* st) {
+k_flush(long d, float* __restrict__ u32, double* __restrict__ u64, const RhsState* st) {
   const int r = blockIdx.y;
   if (st[r].done) return;
   float* a = u32 + (long)r * d;
   double* b = u64 + (long)r * d;
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < d;
-       k += (long)gridDim.x * blockDim.x) {
-    b[k] += (double)a[k];
-    a[k] = 0.0f;
+  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
+    const float4 x = Vec4<float>::ld(a + k);
+    auto y = Vec4<double>::ld(b + k);
+    y.x += (double)x.x; y.y += (double)x.y; y.z += (double)x.z; y.w += (double)x.w;
+    Vec4<double>::st(b + k, y);
+    Vec4<float>::st(a + k, make_float4(0.f, 0.f, 0.f, 0.f));
   }
 }
 
-// CG update without preconditioner: u += alpha p, r -= alpha Ap, then
-// |r|^2; the last block sets rz = |r|^2, beta = rz / rz_prev and tests
-// convergence (|r|^2 <= tol^2 |b|^2) and the iteration cap.
-// Launch: grid (nblk, nrhs), 256 threads; d multiple of 4.
-// The direction written by this iteration's operator kernel is pb when the
-// iteration count is even, pa when odd (see InPUpdate).
-template <typename T>
+// ------------------------------------------------------------ plain BLAS
+
+// part[r][block] = partial sums of a_r . b_r (FP64).  Launch: grid (nblk, nrhs).
 __global__ void __launch_bounds__(256)
-k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb,
-            T* __restrict__ r, const T* __restrict__ Ap, RhsState* st,
-            double* partial, unsigned* counter) {
+k_dot_partials(long d, const double* __restrict__ a, const double* __restrict__ b,
+               double* __restrict__ part) {
   __shared__ double red_sh[4];
-  __shared__ int flag_sh;
-  const int rh = blockIdx.y;
-  if (st[rh].done) return;
-  const T* __restrict__ p = (st[rh].iter & 1) ? pa : pb;
-  const T a = (T)st[rh].alpha;
-  const long off = (long)rh * d;
+  const int r = blockIdx.y;
+  const double* ar = a + (long)r * d;
+  const double* br = b + (long)r * d;
   double acc = 0.0;
-  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
-    const T pk = p[off + k];
-    const T rk = r[off + k] - a * Ap[off + k];
-    u[off + k] += a * pk;
-    r[off + k] = rk;
-    acc += (double)rk * (double)rk;
+  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
+    const auto x = Vec4<double>::ld(ar + k);
+    const auto y = Vec4<double>::ld(br + k);
+    acc += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
   }
   const double bs = block_sum<256>(acc, red_sh);
-  if (threadIdx.x == 0) partial[(long)rh * gridDim.x + blockIdx.x] = bs;
-  if (last_block(counter + rh, gridDim.x, &flag_sh)) {
-    const double tot = reduce_partials<256>(partial + (long)rh * gridDim.x, gridDim.x, red_sh);
-    if (threadIdx.x == 0) {
-      RhsState& s = st[rh];
-      s.rr = tot;
-      s.rz_prev = s.rz;
-      s.rz = tot;
-      s.beta = tot / s.rz_prev;
-      s.fresh = 0;
-      s.iter += 1;
-      if (!isfinite(tot)) {
-        s.status |= 8;
-        s.done = 1;
-      } else if (tot <= s.tol2) {
-        s.done = 1;
-      } else if (s.iter >= s.maxiter) {
-        s.status |= 2;
-        s.done = 1;
-      } else if (tot < s.ru_thresh) {
-        s.done = 1;  // pause for an FP64 residual replacement
-      }
-      __threadfence();
-      atomicExch(counter + rh, 0u);
-    }
+  if (threadIdx.x == 0) part[(long)r * kPStride + blockIdx.x] = bs;
+}
+
+// out[r] = sum of the nb partials of rhs r, in block order.  One block per rhs.
+__global__ void __launch_bounds__(256)
+k_sum_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red_sh[4];
+  const int r = blockIdx.x;
+  const double tot = reduce_partials<256>(part + (long)r * kPStride, nb, red_sh);
+  if (threadIdx.x == 0) out[r] = tot;
+}
+
+// dst = (TD) src, elementwise over n values (n multiple of 4).
+template <typename TS, typename TD>
+__global__ void k_cast(long n, const TS* __restrict__ src, TD* __restrict__ dst) {
+  for (long k = 4 * (blockIdx.x * (long)blockDim.x + threadIdx.x); k < n;
+       k += 4L * gridDim.x * blockDim.x) {
+    const auto x = Vec4<TS>::ld(src + k);
+    typename Vec4<TD>::V y;
+    y.x = (TD)x.x; y.y = (TD)x.y; y.z = (TD)x.z; y.w = (TD)x.w;
+    Vec4<TD>::st(dst + k, y);
   }
 }
 

@@ -73,27 +73,59 @@ FPH_DEVINL void plaq_rot(T v[4], T ch, T sh) {
 
 // ------------------------------------------------------------ solver state
 
-// Per right-hand-side scalars of a CG solve, resident in device memory.
-// Written only by the last workgroup of a reduction (see last_block()).
+// Kinds of pending partial sums: a kernel that reduces something writes one
+// partial per block; the next state-aware kernel in stream order sums them
+// (every block in the same order, so all blocks agree bit for bit) and
+// folds the total into the state.  No kernel waits for another block.
+enum Pend : int {
+  P_NONE = 0,
+  P_BB = 1,    // |b|^2 at the start of a solve
+  P_RR = 2,    // |r|^2 after a CG update (an iteration completed)
+  P_PAP = 3,   // p . A p
+  P_RZ = 4,    // r . z after preconditioning
+  P_TRUE = 5,  // |b - A u|^2 evaluated in FP64
+  P_NRM = 6,   // |r|^2 of a replaced residual
+  P_GD = 7     // (|r|^2, r . A r): both dots of single-reduction CG
+};
+
+constexpr int kPStride = 4096;  // partial slots per right-hand side
+constexpr int kPHalf = 2048;    // second value of two-value partials (P_GD)
+
+// Per right-hand-side scalars of a CG solve.  Two copies alternate: a
+// kernel reads copy `in` and its first block writes copy `out`.
 struct RhsState {
+  double tol;       // relative residual target
   double bb;        // |b|^2
-  double rr;        // |r|^2 (current residual, iterated)
-  double rz;        // r . z
-  double rz_prev;   // r . z of the previous iteration
+  double tol2;      // tol^2 |b|^2
+  double rr;        // |r|^2 of the iterated residual
+  double rz;        // r . z of the residual that built the current direction
+  double rz_next;   // r . z of the newest residual (becomes rz at the next
+                    // direction update)
   double pAp;       // p . A p
   double alpha;     // rz / pAp
-  double beta;      // rz / rz_prev
-  double rr_ref;    // |r|^2 at the last FP64 residual recomputation
-  double rr_true;   // |b - A u|^2 from the last FP64 recomputation
-  double tol2;      // tol^2 * bb
-  double ru_thresh; // >0: pause (done = 1) once rr < ru_thresh, so the host
-                    // can replace the FP32 residual by the FP64 one
-  int iter;         // CG iterations done
+  double beta;      // rz_next / rz
+  double rr_true;   // |b - A u|^2 from the last FP64 evaluation
+  double ru_thresh; // > 0: pause once rr < ru_thresh (FP32 residual replacement)
+  double gamma;     // single-reduction CG: gamma_i = r_i . r_i
+  double delta;     //   delta_i = r_i . A r_i
+  double gamma_prev;//   gamma_{i-1}
+  double alpha_prev;//   alpha_{i-1}
+  int iter;         // CG iterations completed
   int done;         // nonzero: kernels skip this right-hand side
   int status;       // FPH_ST_* bits
-  int fresh;        // 1: next direction update starts p = z
+  int fresh;        // 1: the next direction update starts p = z
   int matvecs;
   int maxiter;
+  int pend;         // Pend kind of the partials waiting in `pin`
+  int npart;        // number of waiting partials
+};
+
+struct StIO {
+  const RhsState* in;  // nullptr: no solver state (plain operator call)
+  RhsState* out;
+  const double* pin;   // pending partials, [rhs][kPStride]
+  double* pout;        // partials written by this kernel
+  int precond;         // preconditioned CG (z != r)
 };
 
 // Device constants of the preconditioner for the current field.
@@ -123,29 +155,149 @@ FPH_DEVINL double block_sum(double v, double* sh) {
   return s;
 }
 
-// Arrival at a per-right-hand-side counter after this block published its
-// partial sums (thread 0 wrote them).  Returns true in every thread of the
-// last arriving block; that block then reduces the partials in a fixed
-// order (deterministic) and resets the counter.
-FPH_DEVINL bool last_block(unsigned* counter, unsigned nblocks, int* flag_sh) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    *flag_sh = (prev == nblocks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *flag_sh != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 // Deterministic sum of n partials by the whole block; result in thread 0.
 template <int NT>
 FPH_DEVINL double reduce_partials(const double* part, int n, double* sh) {
   double v = 0.0;
   for (int k = threadIdx.x; k < n; k += NT) v += part[k];
   return block_sum<NT>(v, sh);
+}
+
+// Fold a completed reduction into the state (thread 0 only).
+FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, int precond) {
+  switch (kind) {
+    case P_BB:
+      s.bb = tot;
+      s.tol2 = s.tol * s.tol * tot;
+      s.rr = tot;
+      s.rr_true = tot;
+      s.rz_next = tot;
+      if (!isfinite(tot)) {
+        s.status |= 8;
+        s.done = 1;
+      } else if (tot == 0.0) {
+        s.status |= 1;
+        s.done = 1;
+      }
+      break;
+    case P_RR:
+      s.rr = tot;
+      s.iter += 1;
+      if (!precond) s.rz_next = tot;
+      if (!isfinite(tot)) {
+        s.status |= 8;
+        s.done = 1;
+      } else if (tot <= s.tol2) {
+        s.done = 1;
+      } else if (s.iter >= s.maxiter) {
+        s.status |= 2;
+        s.done = 1;
+      } else if (tot < s.ru_thresh) {
+        s.done = 1;  // pause for an FP64 residual replacement
+      }
+      break;
+    case P_PAP:
+      s.pAp = tot;
+      s.matvecs += 1;
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        s.status |= isfinite(tot) ? 4 : 8;
+        s.done = 1;
+        s.alpha = 0.0;
+      } else {
+        s.alpha = s.rz / tot;
+      }
+      break;
+    case P_RZ:
+      s.rz_next = tot;
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        s.status |= isfinite(tot) ? 4 : 8;
+        s.done = 1;
+      }
+      break;
+    case P_TRUE:
+      s.rr_true = tot;
+      s.matvecs += 1;
+      if (!isfinite(tot)) {
+        s.status |= 8;
+        s.done = 1;
+      }
+      break;
+    case P_NRM:
+      s.rr = tot;
+      if (!precond) s.rz_next = tot;
+      if (!isfinite(tot)) {
+        s.status |= 8;
+        s.done = 1;
+      }
+      break;
+    case P_GD:  // tot = gamma; delta was stored by the caller
+      s.gamma = tot;
+      s.rr = tot;
+      if (!isfinite(tot) || !isfinite(s.delta)) {
+        s.status |= 8;
+        s.done = 1;
+      } else if (tot <= s.tol2) {
+        s.done = 1;
+      } else if (s.iter >= s.maxiter) {
+        s.status |= 2;
+        s.done = 1;
+      } else if (tot < s.ru_thresh) {
+        s.done = 1;  // pause for an FP64 residual replacement
+      }
+      break;
+    default:
+      break;
+  }
+  s.pend = P_NONE;
+}
+
+// Load the state of right-hand side r into LDS and fold in any pending
+// partial sums.  Call from every thread; s_sh is valid afterwards.
+template <int NT>
+FPH_DEVINL void state_begin(const StIO& io, int r, RhsState* s_sh, double* red_sh) {
+  (void)red_sh;
+  if (threadIdx.x < 64) {
+    // The first wave reads the state and, if partials are pending, sums
+    // them: lane l adds partials l, l + 64, ... in order, then a fixed
+    // butterfly across the wave (same order in every block).
+    const RhsState st = io.in[r];
+    if (st.pend != P_NONE) {
+      const double* part = io.pin + (long)r * kPStride;
+      double v = 0.0, v2 = 0.0;
+      for (int k = threadIdx.x; k < st.npart; k += 64) v += part[k];
+      if (st.pend == P_GD)
+        for (int k = threadIdx.x; k < st.npart; k += 64) v2 += part[kPHalf + k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        v += __shfl_xor(v, off, 64);
+        v2 += __shfl_xor(v2, off, 64);
+      }
+      if (threadIdx.x == 0) {
+        RhsState t = st;
+        t.delta = v2;
+        apply_pending(t, st.pend, v, io.precond);
+        *s_sh = t;
+      }
+    } else if (threadIdx.x == 0) {
+      *s_sh = st;
+    }
+  }
+  __syncthreads();
+}
+
+// Publish this block's partial (thread 0 passes its block sum) and, from
+// the designated block, the state.  `kind` P_NONE: no partials produced.
+FPH_DEVINL void state_end(const StIO& io, int r, RhsState* s_sh, int kind, double blocksum,
+                          int block, int nblocks, bool writer, double blocksum2 = 0.0) {
+  if (threadIdx.x == 0) {
+    if (kind != P_NONE) {
+      io.pout[(long)r * kPStride + block] = blocksum;
+      if (kind == P_GD) io.pout[(long)r * kPStride + kPHalf + block] = blocksum2;
+      s_sh->pend = kind;
+      s_sh->npart = nblocks;
+    }
+    if (writer) io.out[r] = *s_sh;
+  }
 }
 
 }  // namespace fph

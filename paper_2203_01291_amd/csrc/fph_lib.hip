@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/holstein_hmc.h"
+#include "fph_batch.h"
 #include "fph_blas.h"
 #include "fph_common.h"
 #include "fph_matvec.h"
@@ -49,28 +50,31 @@ struct fph_handle_s {
   float* E32;
   double* dbar64;
   float* dbar32;
-  // CG workspace, max_rhs right-hand sides each
-  double *r64, *pa64, *pb64, *Ap64;
-  float *u32, *r32, *pa32, *pb32, *Ap32, *z32;
-  double* z64;
-  // reductions and state
-  RhsState* st;
+  // CG workspace, max_rhs right-hand sides each.  Standard PCG uses r, z,
+  // pa/pb, Ap; single-reduction CG uses r/rb, w/wb (w = A r), s/sb
+  // (s = A p) and pa/pb.
+  double *r64, *rb64, *pa64, *pb64, *Ap64, *wb64, *z64, *sb64;
+  float *u32, *r32, *rb32, *pa32, *pb32, *Ap32, *wb32, *z32, *sb32;
+  // CG state (two alternating copies) and partial sums (two buffers)
+  RhsState* st[2];
+  double* part[2];    // max_rhs * kPStride each
   RhsState* st_host;  // pinned mirror
-  double* partial;
-  long partial_len;
-  unsigned* counter;
   double* tmp64;      // max_rhs doubles
   double* tmp_host;   // pinned, max_rhs doubles
   // preconditioner
   PcTables pc;
+  // scratch partials for plain reductions outside a solve
+  double* tmp_part() const { return part[1]; }
 };
 
 namespace {
 
 size_t vbytes(const fph_handle_s* h, size_t elem) { return (size_t)h->g.d * h->max_rhs * elem; }
 
+// Blocks of 256 threads for an elementwise pass over d values with 4 values
+// per thread per step; at most 1024 blocks (partials fit kPStride).
 int elem_blocks(long d) {
-  long nb = (d + 2047) / 2048;
+  long nb = (d + 1023) / 1024;
   return (int)std::max(1L, std::min(nb, 1024L));
 }
 
@@ -78,7 +82,7 @@ int elem_blocks(long d) {
 
 template <typename T, int NT, int MS, class In, class Epi>
 hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi epi,
-                          RhsState* st, hipStream_t s) {
+                          StIO io, hipStream_t s) {
   const Geom& g = h->g;
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
   const int nchunks = (g.Ltau + Tch - 1) / Tch;
@@ -91,7 +95,7 @@ hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi e
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kern, dim3(nblk, nrhs), dim3(NT), lds, s, g, (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32),
-                     (T)h->ch, (T)h->sh, Tch, in, epi, st, h->partial, h->counter);
+                     (T)h->ch, (T)h->sh, Tch, in, epi, io);
   return hipGetLastError();
 }
 
@@ -111,14 +115,16 @@ int pick_chunk(const fph_handle_s* h, int nrhs, int NT) {
 }
 
 template <typename T, class In, class Epi>
-hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, RhsState* st,
-                      hipStream_t s) {
+hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, StIO io, hipStream_t s) {
+  // One plaquette per thread; up to 1024 plaquettes (L <= 64) per slice.
   const int Q = h->g.Q;
-  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, pick_chunk(h, nrhs, 64), in, epi, st, s);
-  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, st, s);
-  if (Q <= 512) return launch_mtm_cfg<T, 256, 2>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, st, s);
-  return launch_mtm_cfg<T, 256, 4>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, st, s);
+  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, pick_chunk(h, nrhs, 64), in, epi, io, s);
+  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, io, s);
+  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, pick_chunk(h, nrhs, 512), in, epi, io, s);
+  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, pick_chunk(h, nrhs, 1024), in, epi, io, s);
 }
+
+StIO no_state() { return StIO{nullptr, nullptr, nullptr, nullptr, 0}; }
 
 template <typename T, int NT, int MS, int MODE>
 hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, double coef,
@@ -145,8 +151,8 @@ hipError_t launch_M(const fph_handle_s* h, int nrhs, const T* v, T* out, double 
   const int Q = h->g.Q;
   if (Q <= 64) return launch_M_cfg<T, 64, 1, MODE>(h, nrhs, v, out, coef, s);
   if (Q <= 256) return launch_M_cfg<T, 256, 1, MODE>(h, nrhs, v, out, coef, s);
-  if (Q <= 512) return launch_M_cfg<T, 256, 2, MODE>(h, nrhs, v, out, coef, s);
-  return launch_M_cfg<T, 256, 4, MODE>(h, nrhs, v, out, coef, s);
+  if (Q <= 512) return launch_M_cfg<T, 512, 1, MODE>(h, nrhs, v, out, coef, s);
+  return launch_M_cfg<T, 1024, 1, MODE>(h, nrhs, v, out, coef, s);
 }
 
 template <typename T, int NT, int MS>
@@ -172,8 +178,8 @@ hipError_t launch_MT(const fph_handle_s* h, int nrhs, const T* w, T* out, hipStr
   const int Q = h->g.Q;
   if (Q <= 64) return launch_MT_cfg<T, 64, 1>(h, nrhs, w, out, s);
   if (Q <= 256) return launch_MT_cfg<T, 256, 1>(h, nrhs, w, out, s);
-  if (Q <= 512) return launch_MT_cfg<T, 256, 2>(h, nrhs, w, out, s);
-  return launch_MT_cfg<T, 256, 4>(h, nrhs, w, out, s);
+  if (Q <= 512) return launch_MT_cfg<T, 512, 1>(h, nrhs, w, out, s);
+  return launch_MT_cfg<T, 1024, 1>(h, nrhs, w, out, s);
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
@@ -190,7 +196,7 @@ const char* fph_strerror(int code) {
   switch (code) {
     case FPH_OK: return "ok";
     case FPH_E_NULL: return "required pointer is NULL";
-    case FPH_E_LATTICE: return "unsupported lattice (need even L in [4, 64], even Ltau >= 2, finite parameters)";
+    case FPH_E_LATTICE: return "unsupported lattice (need even L in [4, 64], even Ltau in [2, 2048] with Ltau/2 = H1*H2, finite parameters)";
     case FPH_E_NRHS: return "nrhs out of range for this handle";
     case FPH_E_PREC: return "unsupported precision or operator code";
     case FPH_E_NOFIELD: return "fph_set_field has not been called";
@@ -205,6 +211,7 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   if (out == nullptr || lat == nullptr) return FPH_E_NULL;
   *out = nullptr;
   if (lat->L < 4 || lat->L % 2 || lat->L > 64 || lat->Ltau < 2 || lat->Ltau % 2 ||
+      lat->Ltau > kPHalf ||
       !std::isfinite(lat->dtau) || !std::isfinite(lat->t) || !std::isfinite(lat->mu) ||
       !std::isfinite(lat->alpha) || lat->dtau <= 0.0)
     return FPH_E_LATTICE;
@@ -225,7 +232,7 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   h->a1 = h->a2 = 1.0;
   hipError_t e = hipGetDevice(&h->device);
   const long d = h->g.d;
-  h->partial_len = (long)max_rhs * std::max<long>(4096, d / 16 + 1);
+
 #define ALLOC(ptr, bytes)                                   \
   if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes));
   ALLOC(h->E64, d * sizeof(double));
@@ -233,25 +240,32 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   ALLOC(h->dbar64, h->g.N * sizeof(double));
   ALLOC(h->dbar32, h->g.N * sizeof(float));
   ALLOC(h->r64, vbytes(h, 8));
+  ALLOC(h->rb64, vbytes(h, 8));
   ALLOC(h->pa64, vbytes(h, 8));
   ALLOC(h->pb64, vbytes(h, 8));
   ALLOC(h->Ap64, vbytes(h, 8));
+  ALLOC(h->wb64, vbytes(h, 8));
   ALLOC(h->z64, vbytes(h, 8));
+  ALLOC(h->sb64, vbytes(h, 8));
   ALLOC(h->u32, vbytes(h, 4));
   ALLOC(h->r32, vbytes(h, 4));
+  ALLOC(h->rb32, vbytes(h, 4));
   ALLOC(h->pa32, vbytes(h, 4));
   ALLOC(h->pb32, vbytes(h, 4));
   ALLOC(h->Ap32, vbytes(h, 4));
+  ALLOC(h->wb32, vbytes(h, 4));
   ALLOC(h->z32, vbytes(h, 4));
-  ALLOC(h->st, max_rhs * sizeof(RhsState));
-  ALLOC(h->partial, h->partial_len * sizeof(double));
-  ALLOC(h->counter, max_rhs * sizeof(unsigned));
+  ALLOC(h->sb32, vbytes(h, 4));
+  ALLOC(h->st[0], max_rhs * sizeof(RhsState));
+  ALLOC(h->st[1], max_rhs * sizeof(RhsState));
+  ALLOC(h->part[0], (size_t)max_rhs * kPStride * sizeof(double));
+  ALLOC(h->part[1], (size_t)max_rhs * kPStride * sizeof(double));
   ALLOC(h->tmp64, max_rhs * sizeof(double));
 #undef ALLOC
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->st_host, max_rhs * sizeof(RhsState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->tmp_host, max_rhs * sizeof(double), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMemset(h->counter, 0, max_rhs * sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemset(h->st, 0, max_rhs * sizeof(RhsState));
+  if (e == hipSuccess) e = hipMemset(h->st[0], 0, max_rhs * sizeof(RhsState));
+  if (e == hipSuccess) e = hipMemset(h->st[1], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = pc_create(&h->pc, h->g, max_rhs);
   h->pc.ch = h->ch;
   h->pc.sh = h->sh;
@@ -267,9 +281,10 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
 int fph_destroy(fph_handle_t h) {
   if (h == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* devptrs[] = {h->E64, h->E32, h->dbar64, h->dbar32, h->r64, h->pa64, h->pb64,
-                     h->Ap64, h->z64, h->u32, h->r32, h->pa32, h->pb32, h->Ap32, h->z32,
-                     h->st, h->partial, h->counter, h->tmp64};
+  void* devptrs[] = {h->E64, h->E32, h->dbar64, h->dbar32, h->r64, h->rb64, h->pa64,
+                     h->pb64, h->Ap64, h->wb64, h->z64, h->sb64, h->u32, h->r32, h->rb32,
+                     h->pa32, h->pb32, h->Ap32, h->wb32, h->z32, h->sb32,
+                     h->st[0], h->st[1], h->part[0], h->part[1], h->tmp64};
   for (void* p : devptrs)
     if (p) (void)hipFree(p);
   if (h->st_host) (void)hipHostFree(h->st_host);
@@ -310,13 +325,13 @@ int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, const
     double* out = (double*)out_dev;
     if (op == FPH_OP_M) e = launch_M<double, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<double>(h, nrhs, in, out, s);
-    else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, nullptr, s);
+    else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, no_state(), s);
   } else {
     const float* in = (const float*)in_dev;
     float* out = (float*)out_dev;
     if (op == FPH_OP_M) e = launch_M<float, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<float>(h, nrhs, in, out, s);
-    else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, nullptr, s);
+    else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, no_state(), s);
   }
   if (e != hipSuccess) return fail_hip(e);
   return FPH_OK;
@@ -339,8 +354,12 @@ int fermion_action(fph_handle_t h, int32_t nrhs, const double* b_dev, const doub
   if (h == nullptr || b_dev == nullptr || u_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
   if (nrhs < 1 || nrhs > h->max_rhs) return FPH_E_NRHS;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_dot_out, dim3(elem_blocks(h->g.d), nrhs), dim3(256), 0, s, h->g.d, b_dev,
-                     u_dev, h->partial, h->counter, out_dev);
+  const int nb = elem_blocks(h->g.d);
+  hipLaunchKernelGGL(k_dot_partials, dim3(nb, nrhs), dim3(256), 0, s, h->g.d, b_dev, u_dev,
+                     h->tmp_part());
+  FPH_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, s, nb, (const double*)h->tmp_part(),
+                     out_dev);
   FPH_CHECK(hipGetLastError());
   return FPH_OK;
 }
@@ -353,12 +372,13 @@ int fph_precond_apply(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, co
   if (op < 0 || op > 2 || (prec != FPH_F64 && prec != FPH_F32)) return FPH_E_PREC;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
+  StateSeq sq{{nullptr, nullptr}, {nullptr, nullptr}, 0, 0, false};
   if (prec == FPH_F64)
     e = pc_apply<double>(&h->pc, h->g, h->dbar64, op, nrhs, (const double*)in_dev,
-                         (double*)out_dev, nullptr, nullptr, nullptr, h->partial, h->counter, s);
+                         (double*)out_dev, nullptr, sq, s);
   else
     e = pc_apply<float>(&h->pc, h->g, h->dbar32, op, nrhs, (const float*)in_dev,
-                        (float*)out_dev, nullptr, nullptr, nullptr, h->partial, h->counter, s);
+                        (float*)out_dev, nullptr, sq, s);
   if (e != hipSuccess) return fail_hip(e);
   return FPH_OK;
 }
@@ -389,42 +409,91 @@ namespace {
 // skip the iteration without flipping it).
 template <typename T>
 hipError_t cg_iteration(fph_handle_s* h, int nrhs, bool precond, T* u, T* r, T* z, T* pa,
-                        T* pb, T* Ap, const T* dbar, hipStream_t s) {
+                        T* pb, T* Ap, const T* dbar, StateSeq& sq, hipStream_t s) {
   const long d = h->g.d;
   const T* zz = precond ? z : r;
   InPUpdate<T> in{zz, pa, pb, nullptr, nullptr, (T)0, 0};
-  hipError_t e = launch_mtm<T>(h, nrhs, in, EpiDotAlpha<T>{Ap}, h->st, s);
+  hipError_t e = launch_mtm<T>(h, nrhs, in, EpiDot<T>{Ap}, sq.next(), s);
   if (e != hipSuccess) return e;
   if (!precond) {
     hipLaunchKernelGGL(k_cg_update<T>, dim3(elem_blocks(d), nrhs), dim3(256), 0, s, d, u,
-                       (const T*)pa, (const T*)pb, r, (const T*)Ap, h->st, h->partial,
-                       h->counter);
+                       (const T*)pa, (const T*)pb, r, (const T*)Ap, sq.next());
     e = hipGetLastError();
   } else {
-    e = pc_cg_update<T>(&h->pc, h->g, dbar, nrhs, u, pa, pb, r, Ap, z, h->st, h->partial,
-                        h->counter, s);
+    e = pc_cg_update<T>(&h->pc, h->g, dbar, nrhs, u, pa, pb, r, Ap, z, sq, s);
   }
   return e;
 }
 
-// z = F F^T r and r.z for the current residual, updating rz/beta (after a
-// residual replacement).
+// Buffers of one precision for the CG driver.
 template <typename T>
-hipError_t precondition_residual(fph_handle_s* h, int nrhs, T* r, T* z, const T* dbar,
-                                 hipStream_t s) {
-  return pc_apply<T>(&h->pc, h->g, dbar, FPH_PC_FFT, nrhs, r, z, h->st, r, nullptr, h->partial,
-                     h->counter, s);
+struct Work {
+  T *u, *r, *rb, *z, *pa, *pb, *Ap, *wb, *sb;
+  const T* dbar;
+};
+
+Work<double> work64(fph_handle_s* h, double* u) {
+  return Work<double>{u, h->r64, h->rb64, h->z64, h->pa64, h->pb64, h->Ap64, h->wb64, h->sb64,
+                      h->dbar64};
+}
+Work<float> work32(fph_handle_s* h) {
+  return Work<float>{h->u32, h->r32, h->rb32, h->z32, h->pa32, h->pb32, h->Ap32, h->wb32,
+                     h->sb32, h->dbar32};
 }
 
-hipError_t sync_state(fph_handle_s* h, int nrhs, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(h->st_host, h->st, nrhs * sizeof(RhsState),
-                                hipMemcpyDeviceToHost, s);
+// Single-reduction CG: w = A r for the current residual buffer and both
+// dots (P_GD).  Starts a solve and follows every residual replacement.
+template <typename T>
+hipError_t cgcg_start(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq, hipStream_t s) {
+  InParity<T> in{{w.r, w.rb}, nullptr};
+  EpiGD<T> epi{{w.Ap, w.wb}, 0, nullptr};
+  return launch_mtm<T>(h, nrhs, in, epi, sq.next(), s);
+}
+
+// One single-reduction CG iteration (one launch).
+template <typename T>
+hipError_t cgcg_iteration(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq,
+                          hipStream_t s) {
+  InCGCG<T> in{{w.r, w.rb}, {w.z, w.sb}, {w.pa, w.pb}, {w.Ap, w.wb}, w.u,
+               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (T)0, (T)0, 0};
+  EpiGD<T> epi{{w.Ap, w.wb}, 1, nullptr};
+  return launch_mtm<T>(h, nrhs, in, epi, sq.next(), s);
+}
+
+// Fold pending partials, copy the state to the host and wait.
+hipError_t sync_state(fph_handle_s* h, int nrhs, StateSeq& sq, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(nrhs), dim3(256), 0, s, sq.next());
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(h->st_host, sq.latest(), nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(s);
 }
 
-hipError_t push_state(fph_handle_s* h, int nrhs, hipStream_t s) {
-  return hipMemcpyAsync(h->st, h->st_host, nrhs * sizeof(RhsState), hipMemcpyHostToDevice, s);
+hipError_t push_state(fph_handle_s* h, int nrhs, StateSeq& sq, hipStream_t s) {
+  return hipMemcpyAsync(sq.latest(), h->st_host, nrhs * sizeof(RhsState), hipMemcpyHostToDevice, s);
+}
+
+// r = b - A u in FP64 (stored as TR), |r|^2 as P_NRM partials, and with a
+// preconditioner z = F F^T r with r.z.  Used to start a solve from a guess
+// and for every residual replacement.
+// For single-reduction CG (no preconditioner) the residual goes to the
+// buffer of the current iteration parity `par` and is followed by w = A r
+// and both dots; with the preconditioner r and z = F F^T r with r.z.
+template <typename TR>
+hipError_t fp64_residual(fph_handle_s* h, int nrhs, bool pre, bool cgcg, int par,
+                         const double* b, const double* u, const Work<TR>& w, StateSeq& sq,
+                         hipStream_t s) {
+  const long d = h->g.d;
+  TR* r = (cgcg && par == 1) ? w.rb : w.r;
+  hipError_t e = launch_mtm<double>(h, nrhs, InPlain<double>{u}, EpiResidual<TR>{b, r}, sq.next(), s);
+  if (e != hipSuccess) return e;
+  if (cgcg) return cgcg_start<TR>(h, nrhs, w, sq, s);
+  hipLaunchKernelGGL(k_norm2<TR>, dim3(elem_blocks(d), nrhs), dim3(256), 0, s, d, (const TR*)r,
+                     sq.next(), (int)P_NRM);
+  e = hipGetLastError();
+  if (e != hipSuccess || !pre) return e;
+  return pc_apply<TR>(&h->pc, h->g, w.dbar, FPH_PC_FFT, nrhs, r, w.z, r, sq, s);
 }
 
 }  // namespace
@@ -435,86 +504,108 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   if (!h->have_field) return FPH_E_NOFIELD;
   if (nrhs < 1 || nrhs > h->max_rhs) return FPH_E_NRHS;
   if (opts->prec != FPH_F64 && opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
-  if (!(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
+  if (!(opts->tol >= 0.0) || opts->maxiter < 1 || opts->variant < 0 || opts->variant > 1)
+    return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   const long d = h->g.d;
   const int nb = elem_blocks(d);
   const bool pre = opts->use_precond != 0;
   const bool mixed = opts->prec == FPH_F32_REFINED;
   const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
+  // Single-reduction CG only without preconditioner and when asked for.
+  const bool cgcg = !pre && opts->variant == 1;
+  StateSeq sq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true};
 
-  // State: bb = |b|^2, tol2, counters.
-  hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, b_dev, h->partial,
-                     h->counter, h->st, opts->tol, opts->maxiter, 0);
+  // Initial state, then |b|^2 (P_BB) and the first residual.
+  for (int r = 0; r < nrhs; ++r) {
+    RhsState& st = h->st_host[r];
+    std::memset(&st, 0, sizeof(st));
+    st.tol = opts->tol;
+    st.maxiter = opts->maxiter;
+    st.fresh = 1;
+  }
+  FPH_CHECK(push_state(h, nrhs, sq, s));
+  hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, b_dev, sq.next(),
+                     (int)P_BB);
   FPH_CHECK(hipGetLastError());
   if (opts->zero_guess) FPH_CHECK(hipMemsetAsync(u_dev, 0, nrhs * d * sizeof(double), s));
-
-  // Initial residual.
+  const Work<double> w64 = work64(h, u_dev);
+  const Work<float> w32 = work32(h);
   if (!mixed) {
     if (opts->zero_guess) {
-      FPH_CHECK(hipMemcpyAsync(h->r64, b_dev, nrhs * d * sizeof(double), hipMemcpyDeviceToDevice, s));
+      FPH_CHECK(hipMemcpyAsync(w64.r, b_dev, nrhs * d * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (pre)
+        FPH_CHECK(pc_apply<double>(&h->pc, h->g, w64.dbar, FPH_PC_FFT, nrhs, w64.r, w64.z, w64.r, sq, s));
+      else if (cgcg)
+        FPH_CHECK(cgcg_start<double>(h, nrhs, w64, sq, s));
     } else {
-      FPH_CHECK(launch_mtm<double>(h, nrhs, InPlain<double>{u_dev},
-                                   EpiResidual<double>{b_dev, h->r64}, h->st, s));
-      hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, h->r64,
-                         h->partial, h->counter, h->st, opts->tol, opts->maxiter, 1);
-      FPH_CHECK(hipGetLastError());
+      FPH_CHECK(fp64_residual<double>(h, nrhs, pre, cgcg, 0, b_dev, u_dev, w64, sq, s));
     }
-    if (pre) FPH_CHECK(precondition_residual<double>(h, nrhs, h->r64, h->z64, h->dbar64, s));
   } else {
     FPH_CHECK(hipMemsetAsync(h->u32, 0, nrhs * d * sizeof(float), s));
     if (opts->zero_guess) {
-      hipLaunchKernelGGL((k_cast<double, float>), dim3(nb), dim3(256), 0, s, nrhs * d, b_dev, h->r32);
+      hipLaunchKernelGGL((k_cast<double, float>), dim3(nb), dim3(256), 0, s, nrhs * d, b_dev, w32.r);
       FPH_CHECK(hipGetLastError());
+      if (cgcg) {
+        FPH_CHECK(cgcg_start<float>(h, nrhs, w32, sq, s));
+      } else {
+        hipLaunchKernelGGL(k_norm2<float>, dim3(nb, nrhs), dim3(256), 0, s, d, (const float*)w32.r,
+                           sq.next(), (int)P_NRM);
+        FPH_CHECK(hipGetLastError());
+        if (pre)
+          FPH_CHECK(pc_apply<float>(&h->pc, h->g, w32.dbar, FPH_PC_FFT, nrhs, w32.r, w32.z, w32.r, sq, s));
+      }
     } else {
-      FPH_CHECK(launch_mtm<double>(h, nrhs, InPlain<double>{u_dev},
-                                   EpiResidual<float>{b_dev, h->r32}, h->st, s));
+      FPH_CHECK(fp64_residual<float>(h, nrhs, pre, cgcg, 0, b_dev, u_dev, w32, sq, s));
     }
-    hipLaunchKernelGGL(k_norm2<float>, dim3(nb, nrhs), dim3(256), 0, s, d, h->r32, h->partial,
-                       h->counter, h->st, opts->tol, opts->maxiter, 1);
-    FPH_CHECK(hipGetLastError());
-    if (pre) FPH_CHECK(precondition_residual<float>(h, nrhs, h->r32, h->z32, h->dbar32, s));
   }
+  FPH_CHECK(sync_state(h, nrhs, sq, s));
 
   std::vector<int> final_(nrhs, 0);
   std::vector<int> outer(nrhs, 0);
   std::vector<int> iter_at_ru(nrhs, 0);
   std::vector<double> rr_iter(nrhs, 0.0);
-  FPH_CHECK(sync_state(h, nrhs, s));
   for (int r = 0; r < nrhs; ++r) {
     RhsState& st = h->st_host[r];
     if (st.bb == 0.0) {  // b = 0: u = 0 exactly
       final_[r] = 1;
+      st.status |= 1;
+      st.done = 1;
       FPH_CHECK(hipMemsetAsync(u_dev + (long)r * d, 0, d * sizeof(double), s));
-    } else if (st.status & 8) {  // non-finite b
+    } else if (st.status & (4 | 8)) {  // non-finite input or breakdown
       final_[r] = 1;
+      st.done = 1;
     }
-    if (mixed) st.ru_thresh = delta * delta * st.rr;
+    if (mixed && !st.done) st.ru_thresh = delta * delta * st.rr;
   }
-  FPH_CHECK(push_state(h, nrhs, s));
+  FPH_CHECK(push_state(h, nrhs, sq, s));
 
   // Iterations enqueued between host checks.  FP32 with residual
   // replacement: about 1.5 times the length of the last replacement cycle,
   // so that few launches are wasted on paused right-hand sides.
   int chunk = opts->chunk > 0 ? opts->chunk : (mixed ? 8 : 32);
-  int guard = 0;
+  long guard = 0;
   while (true) {
     bool all_final = true;
     for (int r = 0; r < nrhs; ++r) all_final = all_final && final_[r];
     if (all_final) break;
-    if (++guard > 10000000) break;
+    if (++guard > 100000000L) break;
 
     for (int it = 0; it < chunk; ++it) {
       hipError_t e;
-      if (!mixed)
-        e = cg_iteration<double>(h, nrhs, pre, u_dev, h->r64, h->z64, h->pa64, h->pb64, h->Ap64,
-                                 h->dbar64, s);
+      if (cgcg && !mixed)
+        e = cgcg_iteration<double>(h, nrhs, w64, sq, s);
+      else if (cgcg)
+        e = cgcg_iteration<float>(h, nrhs, w32, sq, s);
+      else if (!mixed)
+        e = cg_iteration<double>(h, nrhs, pre, u_dev, w64.r, w64.z, w64.pa, w64.pb, w64.Ap,
+                                 w64.dbar, sq, s);
       else
-        e = cg_iteration<float>(h, nrhs, pre, h->u32, h->r32, h->z32, h->pa32, h->pb32, h->Ap32,
-                                h->dbar32, s);
+        e = cg_iteration<float>(h, nrhs, pre, w32.u, w32.r, w32.z, w32.pa, w32.pb, w32.Ap,
+                                w32.dbar, sq, s);
       if (e != hipSuccess) return fail_hip(e);
     }
-    FPH_CHECK(sync_state(h, nrhs, s));
+    FPH_CHECK(sync_state(h, nrhs, sq, s));
 
     // Right-hand sides that stopped (converged iterate, pause, cap) get an
     // FP64 residual evaluation.
@@ -532,29 +623,30 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
 
     // FP64 residual of the current iterate for every non-final rhs (the
     // others are cheap to include and keep their direction).
-    for (int r = 0; r < nrhs; ++r) {
-      rr_iter[r] = h->st_host[r].rr;
-      h->st_host[r].done = final_[r];
+    // Single-reduction CG keeps its residual in the buffer of the current
+    // iteration parity; right-hand sides with another parity would need a
+    // launch of their own, so each parity class is replaced separately.
+    for (int r = 0; r < nrhs; ++r) rr_iter[r] = h->st_host[r].rr;
+    for (int par = 0; par < (cgcg ? 2 : 1); ++par) {
+      bool any = false;
+      for (int r = 0; r < nrhs; ++r) {
+        const bool mine = !final_[r] && (!cgcg || (h->st_host[r].iter & 1) == par);
+        h->st_host[r].done = mine ? 0 : 1;
+        any = any || mine;
+      }
+      if (!any) continue;
+      FPH_CHECK(push_state(h, nrhs, sq, s));
+      if (mixed) {
+        hipLaunchKernelGGL(k_flush, dim3(nb, nrhs), dim3(256), 0, s, d, h->u32, u_dev,
+                           (const RhsState*)sq.latest());
+        FPH_CHECK(hipGetLastError());
+        FPH_CHECK(fp64_residual<float>(h, nrhs, pre, cgcg, par, b_dev, u_dev, w32, sq, s));
+      } else {
+        FPH_CHECK(fp64_residual<double>(h, nrhs, pre, cgcg, par, b_dev, u_dev, w64, sq, s));
+      }
+      FPH_CHECK(sync_state(h, nrhs, sq, s));
     }
-    FPH_CHECK(push_state(h, nrhs, s));
-    if (mixed) {
-      hipLaunchKernelGGL(k_flush, dim3(nb, nrhs), dim3(256), 0, s, d, h->u32, u_dev, h->st);
-      FPH_CHECK(hipGetLastError());
-      FPH_CHECK(launch_mtm<double>(h, nrhs, InPlain<double>{u_dev},
-                                   EpiResidual<float>{b_dev, h->r32}, h->st, s));
-      hipLaunchKernelGGL(k_norm2<float>, dim3(nb, nrhs), dim3(256), 0, s, d, h->r32,
-                         h->partial, h->counter, h->st, opts->tol, opts->maxiter, 1);
-      FPH_CHECK(hipGetLastError());
-      if (pre) FPH_CHECK(precondition_residual<float>(h, nrhs, h->r32, h->z32, h->dbar32, s));
-    } else {
-      FPH_CHECK(launch_mtm<double>(h, nrhs, InPlain<double>{u_dev},
-                                   EpiResidual<double>{b_dev, h->r64}, h->st, s));
-      hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, h->r64,
-                         h->partial, h->counter, h->st, opts->tol, opts->maxiter, 1);
-      FPH_CHECK(hipGetLastError());
-      if (pre) FPH_CHECK(precondition_residual<double>(h, nrhs, h->r64, h->z64, h->dbar64, s));
-    }
-    FPH_CHECK(sync_state(h, nrhs, s));
+    for (int r = 0; r < nrhs; ++r) h->st_host[r].done = final_[r];
     int cycle = 0;
     for (int r = 0; r < nrhs; ++r) {
       if (final_[r]) continue;
@@ -579,10 +671,10 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
         // them (reliable update) unless the replaced residual is far from
         // the iterated one.
         if (!mixed || st.rr > 100.0 * rr_iter[r]) st.fresh = 1;
-        if (mixed) st.ru_thresh = delta * delta * st.rr;
+        st.ru_thresh = mixed ? delta * delta * st.rr : 0.0;
       }
     }
-    FPH_CHECK(push_state(h, nrhs, s));
+    FPH_CHECK(push_state(h, nrhs, sq, s));
     if (mixed && opts->chunk <= 0) chunk = std::max(2, std::min(64, cycle + cycle / 2 + 1));
   }
 
@@ -590,7 +682,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   FPH_CHECK(fermion_action(h, nrhs, b_dev, u_dev, h->tmp64, stream) == FPH_OK ? hipSuccess
                                                                                 : hipErrorUnknown);
   FPH_CHECK(hipMemcpyAsync(h->tmp_host, h->tmp64, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-  FPH_CHECK(sync_state(h, nrhs, s));
+  FPH_CHECK(hipStreamSynchronize(s));
   if (stats) {
     for (int r = 0; r < nrhs; ++r) {
       const RhsState& st = h->st_host[r];
@@ -604,3 +696,289 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   }
   return FPH_OK;
 }
+
+// ============================================================ batches
+
+struct fph_batch_s {
+  int nsys;
+  int nitems;
+  std::vector<fph_system_t> sys;
+  std::vector<long> eoff;     // offset of each system's field in E64/E32
+  double* E64;
+  float* E32;
+  float* work;
+  BatchItem* items;
+  BatchStat* stats;
+  BatchStat* stats_host;      // pinned
+  unsigned* queue;
+  int nt, ms, per_cu;         // launch shape
+  int num_cu;
+  int qmax;
+  hipStream_t cap;            // capture stream
+  hipGraphExec_t exec;
+  bool have_graph;
+  double g_tol, g_delta;
+  int g_maxiter;
+};
+
+namespace {
+
+template <int NT, int MS>
+hipError_t batch_launch(fph_batch_s* b, double tol, int maxiter, double delta, hipStream_t s) {
+  // LDS: two FP64 slices per chunk, chunks side by side (largest over systems).
+  long sn = 0;
+  for (const auto& sy : b->sys) {
+    const int N = sy.lat.L * sy.lat.L, Q = N / 4;
+    const int S = (Q <= NT) ? NT / Q : 1;
+    sn = std::max<long>(sn, (long)S * N);
+  }
+  const size_t lds = 2 * (size_t)sn * sizeof(double);
+  auto kern = k_batch_solve<NT, MS>;
+  if (lds > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int grid = std::max(1, std::min(b->nitems, b->num_cu * b->per_cu));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, b->items, b->nitems, b->queue, tol,
+                     maxiter, delta, b->stats);
+  return hipGetLastError();
+}
+
+// Field setup of every system, queue reset and the persistent solve.
+hipError_t batch_enqueue(fph_batch_s* b, double tol, int maxiter, double delta, hipStream_t s) {
+  for (int k = 0; k < b->nsys; ++k) {
+    const fph_lattice_t& L = b->sys[k].lat;
+    const long d = (long)L.L * L.L * L.Ltau;
+    hipLaunchKernelGGL(k_set_field, dim3(elem_blocks(d)), dim3(256), 0, s, d, b->sys[k].x_dev,
+                       L.dtau, L.alpha, L.mu, b->E64 + b->eoff[k], b->E32 + b->eoff[k]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, b->queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (b->nt == 256 && b->ms == 1) return batch_launch<256, 1>(b, tol, maxiter, delta, s);
+  if (b->nt == 128 && b->ms == 2) return batch_launch<128, 2>(b, tol, maxiter, delta, s);
+  if (b->nt == 512 && b->ms == 1) return batch_launch<512, 1>(b, tol, maxiter, delta, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t batch_graph(fph_batch_s* b, double tol, int maxiter, double delta) {
+  if (b->have_graph) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->have_graph = false;
+  }
+  hipGraph_t graph;
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e2 = batch_enqueue(b, tol, maxiter, delta, b->cap);
+  e = hipStreamEndCapture(b->cap, &graph);
+  if (e2 != hipSuccess) return e2;
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  b->have_graph = true;
+  b->g_tol = tol;
+  b->g_maxiter = maxiter;
+  b->g_delta = delta;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
+  if (out == nullptr || sys == nullptr) return FPH_E_NULL;
+  *out = nullptr;
+  if (nsys < 1) return FPH_E_ARG;
+  long etot = 0, wtot = 0;
+  int nitems = 0, qmax = 1;
+  for (int k = 0; k < nsys; ++k) {
+    const fph_lattice_t& L = sys[k].lat;
+    if (sys[k].x_dev == nullptr || sys[k].b_dev == nullptr || sys[k].u_dev == nullptr)
+      return FPH_E_NULL;
+    if (L.L < 4 || L.L % 2 || L.L > 32 || L.Ltau < 2 || L.Ltau % 2 || L.Ltau > kPHalf ||
+        !(L.dtau > 0.0) || !std::isfinite(L.t) || !std::isfinite(L.mu) || !std::isfinite(L.alpha))
+      return FPH_E_LATTICE;
+    if (sys[k].nrhs < 1) return FPH_E_NRHS;
+    const long d = (long)L.L * L.L * L.Ltau;
+    etot += d;
+    wtot += 5 * d * sys[k].nrhs;
+    nitems += sys[k].nrhs;
+    qmax = std::max(qmax, L.L * L.L / 4);
+  }
+  fph_batch_s* b = new fph_batch_s();
+  b->nsys = nsys;
+  b->nitems = nitems;
+  b->qmax = qmax;
+  b->sys.assign(sys, sys + nsys);
+  b->E64 = nullptr;
+  b->E32 = nullptr;
+  b->work = nullptr;
+  b->items = nullptr;
+  b->stats = nullptr;
+  b->stats_host = nullptr;
+  b->queue = nullptr;
+  b->have_graph = false;
+  b->nt = 256;
+  b->ms = 1;
+  b->per_cu = 2;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  b->num_cu = (e == hipSuccess) ? prop.multiProcessorCount : 256;
+  if (e == hipSuccess) e = hipMalloc((void**)&b->E64, etot * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->E32, etot * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->work, wtot * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->items, nitems * sizeof(BatchItem));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->stats, nitems * sizeof(BatchStat));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->queue, sizeof(unsigned));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->stats_host, nitems * sizeof(BatchStat), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    fph_batch_destroy(b);
+    return fail_hip(e);
+  }
+  // Work items, largest first (stable: system order within equal sizes).
+  std::vector<BatchItem> items;
+  items.reserve(nitems);
+  long eo = 0, wo = 0;
+  int gidx = 0;
+  for (int k = 0; k < nsys; ++k) {
+    const fph_lattice_t& L = sys[k].lat;
+    Geom g;
+    g.L = L.L;
+    g.hL = L.L / 2;
+    g.N = L.L * L.L;
+    g.Q = g.N / 4;
+    g.Ltau = L.Ltau;
+    g.d = (long)g.N * L.Ltau;
+    b->eoff.push_back(eo);
+    for (int j = 0; j < sys[k].nrhs; ++j) {
+      BatchItem it;
+      std::memset(&it, 0, sizeof(it));
+      it.g = g;
+      it.ch = std::cosh(L.dtau * L.t);
+      it.sh = std::sinh(L.dtau * L.t);
+      it.E64 = b->E64 + eo;
+      it.E32 = b->E32 + eo;
+      it.b = sys[k].b_dev + (long)j * g.d;
+      it.u = sys[k].u_dev + (long)j * g.d;
+      it.r = b->work + wo;
+      it.pa = it.r + g.d;
+      it.pb = it.pa + g.d;
+      it.Ap = it.pb + g.d;
+      it.u32 = it.Ap + g.d;
+      it.out = gidx++;
+      wo += 5 * g.d;
+      items.push_back(it);
+    }
+    eo += g.d;
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const BatchItem& a, const BatchItem& c) { return a.g.d > c.g.d; });
+  e = hipMemcpy(b->items, items.data(), nitems * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fph_batch_destroy(b);
+    return fail_hip(e);
+  }
+  *out = b;
+  return FPH_OK;
+}
+
+int fph_batch_destroy(fph_batch_t b) {
+  if (b == nullptr) return FPH_E_NULL;
+  (void)hipDeviceSynchronize();
+  if (b->have_graph) (void)hipGraphExecDestroy(b->exec);
+  void* ptrs[] = {b->E64, b->E32, b->work, b->items, b->stats, b->queue};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->stats_host) (void)hipHostFree(b->stats_host);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return FPH_OK;
+}
+
+int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats,
+                    void* stream) {
+  if (b == nullptr || opts == nullptr) return FPH_E_NULL;
+  if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
+  if (opts->use_precond != 0 || !(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
+  if (!b->have_graph || b->g_tol != opts->tol || b->g_maxiter != opts->maxiter ||
+      b->g_delta != delta)
+    FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
+  FPH_CHECK(hipGraphLaunch(b->exec, s));
+  FPH_CHECK(hipMemcpyAsync(b->stats_host, b->stats, b->nitems * sizeof(BatchStat),
+                           hipMemcpyDeviceToHost, s));
+  FPH_CHECK(hipStreamSynchronize(s));
+  if (stats) {
+    for (int k = 0; k < b->nitems; ++k) {
+      const BatchStat& st = b->stats_host[k];
+      stats[k].status = st.status;
+      stats[k].iters = st.iters;
+      stats[k].outer_iters = st.outer;
+      stats[k].matvecs = st.matvecs;
+      stats[k].rel_resid = st.rel_resid;
+      stats[k].action = st.action;
+    }
+  }
+  return FPH_OK;
+}
+
+int fph_batch_tune(fph_batch_t b, const fph_pcg_opts_t* opts, int32_t* best, void* stream) {
+  if (b == nullptr || opts == nullptr) return FPH_E_NULL;
+  if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
+  if (opts->use_precond != 0 || !(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
+  struct Cfg { int nt, ms, per_cu; };
+  std::vector<Cfg> cands;
+  for (int pc : {1, 2, 4}) {
+    if (b->qmax <= 256) cands.push_back({256, 1, pc});
+    cands.push_back({128, 2, pc});
+    if (b->qmax <= 512) cands.push_back({512, 1, pc});
+  }
+  hipEvent_t e0, e1;
+  FPH_CHECK(hipEventCreate(&e0));
+  FPH_CHECK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  Cfg best_cfg = {b->nt, b->ms, b->per_cu};
+  for (const Cfg& c : cands) {
+    if (c.ms * c.nt < b->qmax) continue;  // a slice must fit one block
+    b->nt = c.nt;
+    b->ms = c.ms;
+    b->per_cu = c.per_cu;
+    FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
+    FPH_CHECK(hipGraphLaunch(b->exec, s));  // warm-up
+    FPH_CHECK(hipEventRecord(e0, s));
+    FPH_CHECK(hipGraphLaunch(b->exec, s));
+    FPH_CHECK(hipEventRecord(e1, s));
+    FPH_CHECK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    FPH_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_cfg = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->nt = best_cfg.nt;
+  b->ms = best_cfg.ms;
+  b->per_cu = best_cfg.per_cu;
+  FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
+  if (best) {
+    best[0] = b->nt;
+    best[1] = b->ms;
+    best[2] = b->per_cu;
+  }
+  return FPH_OK;
+}
+
+}  // extern "C"

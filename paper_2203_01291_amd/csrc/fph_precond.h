@@ -30,7 +30,6 @@
 namespace fph {
 
 constexpr int kNPMax = 1024;   // cap on the Chebyshev order N_P(w)
-constexpr int kSites = 16;     // sites per transform block (one 128-byte row in FP64)
 
 template <typename T> struct Cplx;
 template <> struct Cplx<double> { using type = double2; };
@@ -51,8 +50,10 @@ struct PcTables {
   double ch, sh;   // checkerboard rotation cosh(dtau t), sinh(dtau t)
 };
 
+// First factor of the length-H DFT split H = H1 * H2: at most 10 when
+// possible (H1 complex values per thread stay in registers), H2 <= 32.
 inline int pick_h1(int H) {
-  static const int cand[] = {20, 16, 10, 8, 5, 4, 3, 2, 1};
+  static const int cand[] = {10, 8, 5, 4, 3, 2, 16, 20, 1};
   for (int h1 : cand)
     if (H % h1 == 0 && H / h1 <= 32) return h1;
   return 0;
@@ -175,178 +176,214 @@ FPH_DEVINL T2 cmulc(T2 a, T2 b) {  // a * conj(b)
   return r;
 }
 
-// Forward transform of KSITES sites per block: Z[r][k][i] = (U in)_{2k}.
-// With CGUPD, first the CG update of the tile: u += alpha p,
-// r -= alpha Ap (r is `in`, updated in place) and |r|^2, after which the
-// last block sets rr, advances the iteration count and tests convergence.
-// The direction is pb on even iteration counts, pa on odd (see InPUpdate).
-// Launch: grid (ceil(N / kSites), nrhs), NT threads, LDS H * kSites complex.
+// Sites per transform block: 64 bytes of one slice row (8 in FP64, 16 in FP32).
+template <typename T> struct Tile { static constexpr int kS = 64 / sizeof(T); };
+
+// Forward transform of Tile<T>::kS sites per block: Z[r][k][i] = (U in)_{2k}.
+// Stage 0 (all threads, coalesced): the tile in[tau][i0..i0+kS) goes to
+// LDS; with CGUPD it first receives the CG update u += alpha p,
+// r -= alpha Ap (r is `in`, updated in place), publishing |r|^2 as P_RR
+// partials (the direction is pb on even iteration counts, pa on odd).
+// Step 1, item (site, n2): the H1-point DFT over n1 of the twisted input
+// y_tau = e^{-i pi tau/Ltau} (in_tau - i in_{tau+H}), tau = H2 n1 + n2,
+// times W_H^{n2 k1}, into LDS.  Step 2, item (site, k1, k2): the H2-point
+// DFT over n2 -> Z_{k1 + H1 k2}.  Twiddles live in LDS.
+// Launch: grid (ceil(N / kS), nrhs), NT threads,
+// LDS 2H complex + Ltau kS reals + H kS complex.
 template <typename T, int H1, int NT, bool CGUPD>
 __global__ void __launch_bounds__(NT)
 k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
-       const typename Cplx<T>::type* __restrict__ W, T* in, typename Cplx<T>::type* __restrict__ Z,
-       T* __restrict__ u, const T* pa, const T* pb, const T* __restrict__ Ap, RhsState* st,
-       double* partial, unsigned* counter) {
+       const typename Cplx<T>::type* __restrict__ W, T* __restrict__ in,
+       typename Cplx<T>::type* __restrict__ Z, T* __restrict__ u, const T* pa, const T* pb,
+       const T* __restrict__ Ap, StIO io) {
   using T2 = typename Cplx<T>::type;
+  constexpr int KS = Tile<T>::kS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T2* Y = reinterpret_cast<T2*>(smem_raw);
-  __shared__ double red_sh[NT / 64];
-  __shared__ int flag_sh;
-  const int r = blockIdx.y;
-  if (st != nullptr && st[r].done) return;
   const int H = H1 * H2;
-  const int i0 = blockIdx.x * kSites;
+  T2* Wl = reinterpret_cast<T2*>(smem_raw);
+  T2* twl = Wl + H;
+  T2* Y = twl + H;
+  T* Rt = reinterpret_cast<T*>(Y + H * KS);
+  __shared__ double red_sh[NT / 64];
+  __shared__ RhsState s_sh;
+  const int r = blockIdx.y;
+  for (int k = threadIdx.x; k < H; k += NT) {
+    Wl[k] = W[k];
+    twl[k] = tw[k];
+  }
+  if (io.in != nullptr) {
+    state_begin<NT>(io, r, &s_sh, red_sh);
+    if (s_sh.done) {
+      state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+      return;
+    }
+  }
+  const int i0 = blockIdx.x * KS;
   const long base = (long)r * g.d;
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
-  T alpha = (T)0;
-  const T* __restrict__ p = pa;
-  if (CGUPD) {
-    alpha = (T)st[r].alpha;
-    p = (st[r].iter & 1) ? pa : pb;  // direction written by this iteration
-  }
   double acc_rr = 0.0;
 
-  // Step 1: per (site, n2), H1-point DFT over n1 of the twisted input.
-  for (int it = threadIdx.x; it < kSites * H2; it += NT) {
-    const int s = it % kSites, n2 = it / kSites;
-    if (i0 + s >= g.N) continue;
-    T2 acc[H1];
-#pragma unroll
-    for (int k1 = 0; k1 < H1; ++k1) acc[k1] = T2{(T)0, (T)0};
+  // Stage 0.
+  {
+    T alpha = (T)0;
+    const T* __restrict__ p = pa;
+    if (CGUPD) {
+      alpha = (T)s_sh.alpha;
+      p = (s_sh.iter & 1) ? pa : pb;  // direction written by this iteration
+    }
+    for (int e = threadIdx.x; e < g.Ltau * KS; e += NT) {
+      const int tau = e / KS, sidx = e - tau * KS;
+      T a = (T)0;
+      if (i0 + sidx < g.N) {
+        const long off = base + (long)tau * g.N + i0 + sidx;
+        a = in[off];
+        if (CGUPD) {
+          a -= alpha * Ap[off];
+          in[off] = a;
+          u[off] += alpha * p[off];
+          acc_rr += (double)a * (double)a;
+        }
+      }
+      Rt[e] = a;
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < KS * H2; it += NT) {
+    const int sidx = it % KS, n2 = it / KS;
+    T2 y[H1];
 #pragma unroll
     for (int n1 = 0; n1 < H1; ++n1) {
       const int tau = H2 * n1 + n2;
-      const long oa = base + (long)tau * g.N + i0 + s;
-      const long ob = oa + (long)H * g.N;
-      T a = in[oa], b = in[ob];
-      if (CGUPD) {
-        a -= alpha * Ap[oa];
-        b -= alpha * Ap[ob];
-        in[oa] = a;
-        in[ob] = b;
-        u[oa] += alpha * p[oa];
-        u[ob] += alpha * p[ob];
-        acc_rr += (double)a * (double)a + (double)b * (double)b;
-      }
-      const T2 y = cmul<T2, T>(tw[tau], T2{a, -b});
-#pragma unroll
-      for (int k1 = 0; k1 < H1; ++k1) {
-        const T2 wv = W[(H2 * n1 * k1) % H];
-        acc[k1].x += wv.x * y.x - wv.y * y.y;
-        acc[k1].y += wv.x * y.y + wv.y * y.x;
-      }
+      const T a = Rt[tau * KS + sidx], b = Rt[(tau + H) * KS + sidx];
+      y[n1] = cmul<T2, T>(twl[tau], T2{a, -b});
     }
 #pragma unroll
-    for (int k1 = 0; k1 < H1; ++k1)
-      Y[(n2 * H1 + k1) * kSites + s] = cmul<T2, T>(acc[k1], W[(n2 * k1) % H]);
+    for (int k1 = 0; k1 < H1; ++k1) {
+      const int step = (H2 * k1) % H;  // W_H1^{n1 k1} = W_H^{H2 n1 k1}
+      int idx = 0;
+      T2 acc = T2{(T)0, (T)0};
+#pragma unroll
+      for (int n1 = 0; n1 < H1; ++n1) {
+        const T2 wv = Wl[idx];
+        acc.x += wv.x * y[n1].x - wv.y * y[n1].y;
+        acc.y += wv.x * y[n1].y + wv.y * y[n1].x;
+        idx += step;
+        if (idx >= H) idx -= H;
+      }
+      Y[(n2 * H1 + k1) * KS + sidx] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
+    }
   }
   __syncthreads();
-  // Step 2: per (site, k1, k2), H2-point DFT over n2.
-  for (int it = threadIdx.x; it < kSites * H; it += NT) {
-    const int s = it % kSites;
-    const int kk = it / kSites;
+  for (int it = threadIdx.x; it < KS * H; it += NT) {
+    const int sidx = it % KS;
+    const int kk = it / KS;
     const int k1 = kk % H1, k2 = kk / H1;
-    if (i0 + s >= g.N) continue;
+    if (i0 + sidx >= g.N) continue;
+    const int step = (H1 * k2) % H;  // W_H2^{n2 k2} = W_H^{H1 n2 k2}
+    int idx = 0;
     T2 x = T2{(T)0, (T)0};
     for (int n2 = 0; n2 < H2; ++n2) {
-      const T2 wv = W[(H1 * n2 * k2) % H];
-      const T2 yv = Y[(n2 * H1 + k1) * kSites + s];
+      const T2 wv = Wl[idx];
+      const T2 yv = Y[(n2 * H1 + k1) * KS + sidx];
       x.x += wv.x * yv.x - wv.y * yv.y;
       x.y += wv.x * yv.y + wv.y * yv.x;
+      idx += step;
+      if (idx >= H) idx -= H;
     }
     const int k = k1 + H1 * k2;
-    Z[((long)r * H + k) * g.N + i0 + s] = T2{x.x * scale, x.y * scale};
+    Z[((long)r * H + k) * g.N + i0 + sidx] = T2{x.x * scale, x.y * scale};
   }
 
-  if (CGUPD) {
-    const double bs = block_sum<NT>(acc_rr, red_sh);
-    if (threadIdx.x == 0) partial[(long)r * gridDim.x + blockIdx.x] = bs;
-    if (last_block(counter + r, gridDim.x, &flag_sh)) {
-      const double tot = reduce_partials<NT>(partial + (long)r * gridDim.x, gridDim.x, red_sh);
-      if (threadIdx.x == 0) {
-        RhsState& sst = st[r];
-        sst.rr = tot;
-        sst.rz_prev = sst.rz;  // r.z of the residual before this update
-        sst.fresh = 0;
-        sst.iter += 1;
-        if (!isfinite(tot)) {
-          sst.status |= 8;
-          sst.done = 1;
-        } else if (tot <= sst.tol2) {
-          sst.done = 1;
-        } else if (sst.iter >= sst.maxiter) {
-          sst.status |= 2;
-          sst.done = 1;
-        } else if (tot < sst.ru_thresh) {
-          sst.done = 1;  // pause for an FP64 residual replacement
-        }
-        __threadfence();
-        atomicExch(counter + r, 0u);
-      }
-    }
+  if (io.in != nullptr) {
+    double bs = 0.0;
+    if (CGUPD) bs = block_sum<NT>(acc_rr, red_sh);
+    state_end(io, r, &s_sh, CGUPD ? P_RR : P_NONE, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
   }
 }
 
-// Inverse transform: out[r][tau][i] from Zh[r][k][i].  With dot != 0 also
-// accumulates rdot . out; the last block then sets rz = r.z and
-// beta = rz / rz_prev (rz_prev holds r.z of the previous residual: the CG
-// update shifts it, a residual replacement keeps it).
+// Inverse transform: out[r][tau][i] from Zh[r][k][i] (the same two-step
+// DFT with conjugated twiddles, then the conjugate twist and the real
+// split into tau and tau + H).  Stage 0 copies the tile Zh[k][i0..i0+kS)
+// to LDS with coalesced loads.  With dot != 0 also publishes rdot . out as
+// P_RZ partials.  LDS: 2H complex + 2 H kS complex.
 template <typename T, int H1, int NT>
 __global__ void __launch_bounds__(NT)
 k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
        const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ Zh,
-       T* __restrict__ out, int dot, const T* __restrict__ rdot, RhsState* st, double* partial,
-       unsigned* counter) {
+       T* __restrict__ out, int dot, const T* __restrict__ rdot, StIO io) {
   using T2 = typename Cplx<T>::type;
+  constexpr int KS = Tile<T>::kS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T2* Y = reinterpret_cast<T2*>(smem_raw);
-  __shared__ double red_sh[NT / 64];
-  __shared__ int flag_sh;
-  const int r = blockIdx.y;
-  if (st != nullptr && st[r].done) return;
   const int H = H1 * H2;
-  const int i0 = blockIdx.x * kSites;
+  T2* Wl = reinterpret_cast<T2*>(smem_raw);
+  T2* twl = Wl + H;
+  T2* Y = twl + H;
+  T2* Zt = Y + H * KS;
+  __shared__ double red_sh[NT / 64];
+  __shared__ RhsState s_sh;
+  const int r = blockIdx.y;
+  for (int k = threadIdx.x; k < H; k += NT) {
+    Wl[k] = W[k];
+    twl[k] = tw[k];
+  }
+  if (io.in != nullptr) {
+    state_begin<NT>(io, r, &s_sh, red_sh);
+    if (s_sh.done) {
+      state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+      return;
+    }
+  }
+  const int i0 = blockIdx.x * KS;
   const long base = (long)r * g.d;
   const T scale = (T)(2.0 / sqrt((double)g.Ltau));
   double acc_dot = 0.0;
 
-  for (int it = threadIdx.x; it < kSites * H2; it += NT) {
-    const int s = it % kSites, n2 = it / kSites;
-    if (i0 + s >= g.N) continue;
-    T2 acc[H1];
-#pragma unroll
-    for (int k1 = 0; k1 < H1; ++k1) acc[k1] = T2{(T)0, (T)0};
-#pragma unroll
-    for (int n1 = 0; n1 < H1; ++n1) {
-      const int kin = H2 * n1 + n2;
-      const T2 y = Zh[((long)r * H + kin) * g.N + i0 + s];
-#pragma unroll
-      for (int k1 = 0; k1 < H1; ++k1) {
-        const T2 wv = W[(H2 * n1 * k1) % H];   // used conjugated
-        acc[k1].x += wv.x * y.x + wv.y * y.y;
-        acc[k1].y += wv.x * y.y - wv.y * y.x;
-      }
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < H1; ++k1)
-      Y[(n2 * H1 + k1) * kSites + s] = cmulc<T2, T>(acc[k1], W[(n2 * k1) % H]);
+  for (int e = threadIdx.x; e < H * KS; e += NT) {
+    const int k = e / KS, sidx = e - k * KS;
+    Zt[e] = (i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx] : T2{(T)0, (T)0};
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < kSites * H; it += NT) {
-    const int s = it % kSites;
-    const int kk = it / kSites;
+  for (int it = threadIdx.x; it < KS * H2; it += NT) {
+    const int sidx = it % KS, n2 = it / KS;
+    T2 y[H1];
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) y[n1] = Zt[(H2 * n1 + n2) * KS + sidx];
+#pragma unroll
+    for (int k1 = 0; k1 < H1; ++k1) {
+      const int step = (H2 * k1) % H;
+      int idx = 0;
+      T2 acc = T2{(T)0, (T)0};
+#pragma unroll
+      for (int n1 = 0; n1 < H1; ++n1) {
+        const T2 wv = Wl[idx];  // used conjugated
+        acc.x += wv.x * y[n1].x + wv.y * y[n1].y;
+        acc.y += wv.x * y[n1].y - wv.y * y[n1].x;
+        idx += step;
+        if (idx >= H) idx -= H;
+      }
+      Y[(n2 * H1 + k1) * KS + sidx] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
+    }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < KS * H; it += NT) {
+    const int sidx = it % KS;
+    const int kk = it / KS;
     const int k1 = kk % H1, k2 = kk / H1;
-    if (i0 + s >= g.N) continue;
+    if (i0 + sidx >= g.N) continue;
+    const int step = (H1 * k2) % H;
+    int idx = 0;
     T2 x = T2{(T)0, (T)0};
     for (int n2 = 0; n2 < H2; ++n2) {
-      const T2 wv = W[(H1 * n2 * k2) % H];
-      const T2 yv = Y[(n2 * H1 + k1) * kSites + s];
+      const T2 wv = Wl[idx];
+      const T2 yv = Y[(n2 * H1 + k1) * KS + sidx];
       x.x += wv.x * yv.x + wv.y * yv.y;
       x.y += wv.x * yv.y - wv.y * yv.x;
+      idx += step;
+      if (idx >= H) idx -= H;
     }
     const int tau = k1 + H1 * k2;
-    const T2 sv = cmulc<T2, T>(x, tw[tau]);
-    const long oa = base + (long)tau * g.N + i0 + s;
+    const T2 sv = cmulc<T2, T>(x, twl[tau]);
+    const long oa = base + (long)tau * g.N + i0 + sidx;
     const long ob = oa + (long)H * g.N;
     const T va = scale * sv.x, vb = -scale * sv.y;
     out[oa] = va;
@@ -354,34 +391,37 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     if (dot) acc_dot += (double)rdot[oa] * (double)va + (double)rdot[ob] * (double)vb;
   }
 
-  if (dot) {
-    const double bs = block_sum<NT>(acc_dot, red_sh);
-    if (threadIdx.x == 0) partial[(long)r * gridDim.x + blockIdx.x] = bs;
-    if (last_block(counter + r, gridDim.x, &flag_sh)) {
-      const double tot = reduce_partials<NT>(partial + (long)r * gridDim.x, gridDim.x, red_sh);
-      if (threadIdx.x == 0) {
-        RhsState& sst = st[r];
-        sst.rz = tot;
-        sst.beta = tot / sst.rz_prev;
-        if (!(tot > 0.0) || !isfinite(tot)) {
-          sst.status |= isfinite(tot) ? 4 : 8;
-          sst.done = 1;
-        }
-        __threadfence();
-        atomicExch(counter + r, 0u);
-      }
-    }
+  if (io.in != nullptr) {
+    double bs = 0.0;
+    if (dot) bs = block_sum<NT>(acc_dot, red_sh);
+    state_end(io, r, &s_sh, dot ? P_RZ : P_NONE, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
   }
 }
 
 // ------------------------------------------------------------ KPM kernel
 
+// Entry (j, k) of kron(C2, C2) in the local plaquette order index = dx + 2 dy.
+template <typename T>
+FPH_DEVINL T kron_entry(int j, int k, T ch, T sh) {
+  const T cx = ((j ^ k) & 1) ? sh : ch;
+  const T cy = ((j ^ k) & 2) ? sh : ch;
+  return cx * cy;
+}
+
 // Bbar x (TRANS = false: dbar * P_A (P_B x)) or Bbar^T x (TRANS = true:
 // P_B (P_A (dbar * x))) for a complex vector held on even plaquettes.
+// One LDS exchange per apply: the thread publishes its four sites (x, or
+// P_A(dbar x)) into buffer `cur`, and after one barrier reads, for each of
+// its sites, the odd plaquette that covers the site and forms that site's
+// component of P_B.  Site m of the even plaquette at (x0, y0) lies in the
+// odd plaquette with corner (x0 + 1 - 2 [m even in x], y0 + 1 - 2 [m even
+// in y]) at local index 3 - m.  Buffers alternate between applies, so one
+// barrier per apply suffices.
 template <typename T, int NT, int MS, bool TRANS>
 FPH_DEVINL void bbar_apply(const Geom& g, int nslot, T (&xr)[MS][4], T (&xi)[MS][4],
-                           const T (&db)[MS][4], T* lr, T* li, T ch, T sh) {
-  // (1) even layout: TRANS -> dbar*, P_A ; write
+                           const T (&db)[MS][4], T* lbuf, int& cur, T ch, T sh) {
+  T* lr = lbuf + (long)cur * 2 * g.N;
+  T* li = lr + g.N;
 #pragma unroll
   for (int k = 0; k < MS; ++k) {
     const int q = threadIdx.x + k * NT;
@@ -405,40 +445,30 @@ FPH_DEVINL void bbar_apply(const Geom& g, int nslot, T (&xr)[MS][4], T (&xi)[MS]
     }
   }
   __syncthreads();
-  // (2) odd layout: P_B in place
 #pragma unroll
   for (int k = 0; k < MS; ++k) {
     const int q = threadIdx.x + k * NT;
     if (k < nslot && q < g.Q) {
-      int s[4];
-      odd_sites(g, q, s);
-      T tr[4], ti[4];
+      const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        tr[m] = lr[s[m]];
-        ti[m] = li[s[m]];
-      }
-      plaq_rot(tr, ch, sh);
-      plaq_rot(ti, ch, sh);
+        int ox = x0 + 1 - ((m & 1) ? 0 : 2);
+        int oy = y0 + 1 - ((m & 2) ? 0 : 2);
+        if (ox < 0) ox += g.L;
+        if (oy < 0) oy += g.L;
+        const int xb = (ox + 1 == g.L) ? 0 : ox + 1;
+        const int yb = (oy + 1 == g.L) ? 0 : oy + 1;
+        const int os[4] = {ox + g.L * oy, xb + g.L * oy, ox + g.L * yb, xb + g.L * yb};
+        const int j = 3 - m;
+        T ar = (T)0, ai = (T)0;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        lr[s[m]] = tr[m];
-        li[s[m]] = ti[m];
-      }
-    }
-  }
-  __syncthreads();
-  // (3) even layout: read; !TRANS -> P_A, dbar*
-#pragma unroll
-  for (int k = 0; k < MS; ++k) {
-    const int q = threadIdx.x + k * NT;
-    if (k < nslot && q < g.Q) {
-      int s[4];
-      even_sites(g, q, s);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        xr[k][m] = lr[s[m]];
-        xi[k][m] = li[s[m]];
+        for (int kk = 0; kk < 4; ++kk) {
+          const T c = kron_entry<T>(j, kk, ch, sh);
+          ar += c * lr[os[kk]];
+          ai += c * li[os[kk]];
+        }
+        xr[k][m] = ar;
+        xi[k][m] = ai;
       }
       if (!TRANS) {
         plaq_rot(xr[k], ch, sh);
@@ -451,6 +481,7 @@ FPH_DEVINL void bbar_apply(const Geom& g, int nslot, T (&xr)[MS][4], T (&xi)[MS]
       }
     }
   }
+  cur ^= 1;
 }
 
 // acc = sum_{m < NP} c'_m T_m(A') x with A' = A (TRANS false, c' = c) or
@@ -459,7 +490,7 @@ FPH_DEVINL void bbar_apply(const Geom& g, int nslot, T (&xr)[MS][4], T (&xi)[MS]
 template <typename T, int NT, int MS, bool TRANS>
 FPH_DEVINL void cheb_series(const Geom& g, int nslot, int NP, const typename Cplx<T>::type* cf,
                             T sA, T cA, T (&xr)[MS][4], T (&xi)[MS][4], const T (&db)[MS][4],
-                            T* lr, T* li, T ch, T sh, T (&ar)[MS][4], T (&ai)[MS][4]) {
+                            T* lbuf, int& cur, T ch, T sh, T (&ar)[MS][4], T (&ai)[MS][4]) {
   const T cj = TRANS ? (T)-1 : (T)1;
   T pr[MS][4], pi_[MS][4];  // alpha_{m-1}
   {
@@ -484,7 +515,7 @@ FPH_DEVINL void cheb_series(const Geom& g, int nslot, int NP, const typename Cpl
         cr[k][q] = xr[k][q];
         ci[k][q] = xi[k][q];
       }
-    bbar_apply<T, NT, MS, TRANS>(g, nslot, xr, xi, db, lr, li, ch, sh);
+    bbar_apply<T, NT, MS, TRANS>(g, nslot, xr, xi, db, lbuf, cur, ch, sh);
     const T two = (m == 1) ? (T)1 : (T)2;
     const auto cm = cf[m];
 #pragma unroll
@@ -510,23 +541,35 @@ FPH_DEVINL void cheb_series(const Geom& g, int nslot, int NP, const typename Cpl
 // Per-block Chebyshev apply.  op 0: F (series in A), 1: F^T (conjugate
 // series in A^T), 2: F F^T (conjugate series, then series).  Block b
 // serves frequency order b / nrhs (longest series first: k = 0, H-1, 1,
-// H-2, ...) and right-hand side b % nrhs.  LDS: 2 * N * sizeof(T).
+// H-2, ...) and right-hand side b % nrhs.  LDS: two complex exchange
+// buffers (4 N values of T) and the block's Chebyshev coefficients.
 template <typename T, int NT, int MS>
 __global__ void __launch_bounds__(NT)
 k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       const int* __restrict__ np, const typename Cplx<T>::type* __restrict__ coef,
       const T* __restrict__ dbar, T ch, T sh, const typename Cplx<T>::type* __restrict__ Z,
-      typename Cplx<T>::type* __restrict__ Zo, const RhsState* st) {
+      typename Cplx<T>::type* __restrict__ Zo, StIO io) {
   using T2 = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lr = reinterpret_cast<T*>(smem_raw);
-  T* li = lr + g.N;
+  __shared__ double red_sh[NT / 64];
+  __shared__ RhsState s_sh;
+  T* lbuf = reinterpret_cast<T*>(smem_raw);          // 2 buffers x (re, im) x N
+  T2* cfs = reinterpret_cast<T2*>(lbuf + 4 * g.N);   // coefficients of this block's frequency
+  int cur = 0;
   const int ko = blockIdx.x / nrhs;
   const int r = blockIdx.x % nrhs;
-  if (st != nullptr && st[r].done) return;
+  if (io.in != nullptr) {
+    state_begin<NT>(io, r, &s_sh, red_sh);
+    if (s_sh.done) {
+      state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+      return;
+    }
+  }
   const int k = (ko % 2 == 0) ? ko / 2 : H - 1 - ko / 2;
   const int NP = np[2 * k];
-  const T2* cf = coef + (long)k * kNPMax;
+  for (int m = threadIdx.x; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
+  __syncthreads();
+  const T2* cf = cfs;
   const T sA = (T)info->s, cA = (T)info->c;
   const int nslot = (g.Q + NT - 1) / NT;
 
@@ -551,9 +594,9 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
     }
   }
   if (op == 0) {
-    cheb_series<T, NT, MS, false>(g, nslot, NP, cf, sA, cA, xr, xi, db, lr, li, ch, sh, ar, ai);
+    cheb_series<T, NT, MS, false>(g, nslot, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
   } else {
-    cheb_series<T, NT, MS, true>(g, nslot, NP, cf, sA, cA, xr, xi, db, lr, li, ch, sh, ar, ai);
+    cheb_series<T, NT, MS, true>(g, nslot, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
     if (op == 2) {
 #pragma unroll
       for (int kk = 0; kk < MS; ++kk)
@@ -562,7 +605,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
           xr[kk][m] = ar[kk][m];
           xi[kk][m] = ai[kk][m];
         }
-      cheb_series<T, NT, MS, false>(g, nslot, NP, cf, sA, cA, xr, xi, db, lr, li, ch, sh, ar, ai);
+      cheb_series<T, NT, MS, false>(g, nslot, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
     }
   }
   T2* Zout = Zo + ((long)r * H + k) * g.N;
@@ -576,6 +619,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       for (int m = 0; m < 4; ++m) Zout[s[m]] = T2{ar[kk][m], ai[kk][m]};
     }
   }
+  if (io.in != nullptr) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
 }
 
 // ----------------------------------------------------------------- host
@@ -627,20 +671,22 @@ inline hipError_t pc_set_field(PcTables* pc, const Geom& g, const double* dbar64
 
 template <typename T, int H1>
 hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
-                         typename Cplx<T>::type* Z, T* u, const T* pa, const T* pb, const T* Ap, RhsState* st,
-                         double* partial, unsigned* counter, bool cgupd, hipStream_t s) {
-  const size_t lds = (size_t)pc->H * kSites * sizeof(typename Cplx<T>::type);
+                         typename Cplx<T>::type* Z, T* u, const T* pa, const T* pb, const T* Ap,
+                         StIO io, bool cgupd, hipStream_t s) {
+  constexpr int KS = Tile<T>::kS;
+  const size_t lds = (size_t)pc->H * (KS + 2) * sizeof(typename Cplx<T>::type) +
+                     (size_t)g.Ltau * KS * sizeof(T);
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
-  dim3 grid((g.N + kSites - 1) / kSites, nrhs);
+  dim3 grid((g.N + KS - 1) / KS, nrhs);
   if (cgupd) {
     auto kern = k_tfwd<T, H1, 256, true>;
     if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, st, partial, counter);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, io);
   } else {
     auto kern = k_tfwd<T, H1, 256, false>;
     if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, st, partial, counter);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, io);
   }
   return hipGetLastError();
 }
@@ -648,24 +694,25 @@ hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
 template <typename T, int H1>
 hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs,
                          const typename Cplx<T>::type* Zh, T* out, int dot, const T* rdot,
-                         RhsState* st, double* partial, unsigned* counter, hipStream_t s) {
-  const size_t lds = (size_t)pc->H * kSites * sizeof(typename Cplx<T>::type);
+                         StIO io, hipStream_t s) {
+  constexpr int KS = Tile<T>::kS;
+  const size_t lds = (size_t)pc->H * (2 * KS + 2) * sizeof(typename Cplx<T>::type);
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
   auto kern = k_tinv<T, H1, 256>;
   if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(kern, dim3((g.N + kSites - 1) / kSites, nrhs), dim3(256), lds, s, g, pc->H2, tw, W, Zh, out,
-                     dot, rdot, st, partial, counter);
+  hipLaunchKernelGGL(kern, dim3((g.N + KS - 1) / KS, nrhs), dim3(256), lds, s, g, pc->H2, tw, W, Zh, out,
+                     dot, rdot, io);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pc_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in, typename Cplx<T>::type* Z,
-                  T* u, const T* pa, const T* pb, const T* Ap, RhsState* st, double* partial,
-                  unsigned* counter, bool cgupd, hipStream_t s) {
+                  T* u, const T* pa, const T* pb, const T* Ap, StIO io, bool cgupd,
+                  hipStream_t s) {
   switch (pc->H1) {
 #define FPH_FWD_CASE(h1) \
-  case h1: return pc_launch_fwd<T, h1>(pc, g, nrhs, in, Z, u, pa, pb, Ap, st, partial, counter, cgupd, s);
+  case h1: return pc_launch_fwd<T, h1>(pc, g, nrhs, in, Z, u, pa, pb, Ap, io, cgupd, s);
     FPH_FWD_CASE(1) FPH_FWD_CASE(2) FPH_FWD_CASE(3) FPH_FWD_CASE(4) FPH_FWD_CASE(5)
     FPH_FWD_CASE(8) FPH_FWD_CASE(10) FPH_FWD_CASE(16) FPH_FWD_CASE(20)
 #undef FPH_FWD_CASE
@@ -675,11 +722,10 @@ hipError_t pc_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in, typename C
 
 template <typename T>
 hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cplx<T>::type* Zh,
-                  T* out, int dot, const T* rdot, RhsState* st, double* partial,
-                  unsigned* counter, hipStream_t s) {
+                  T* out, int dot, const T* rdot, StIO io, hipStream_t s) {
   switch (pc->H1) {
 #define FPH_INV_CASE(h1) \
-  case h1: return pc_launch_inv<T, h1>(pc, g, nrhs, Zh, out, dot, rdot, st, partial, counter, s);
+  case h1: return pc_launch_inv<T, h1>(pc, g, nrhs, Zh, out, dot, rdot, io, s);
     FPH_INV_CASE(1) FPH_INV_CASE(2) FPH_INV_CASE(3) FPH_INV_CASE(4) FPH_INV_CASE(5)
     FPH_INV_CASE(8) FPH_INV_CASE(10) FPH_INV_CASE(16) FPH_INV_CASE(20)
 #undef FPH_INV_CASE
@@ -690,58 +736,74 @@ hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cp
 template <typename T, int NT, int MS>
 hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
-                         const RhsState* st, T ch, T sh, hipStream_t s) {
-  const size_t lds = 2 * (size_t)g.N * sizeof(T);
+                         StIO io, T ch, T sh, hipStream_t s) {
+  const size_t lds = 4 * (size_t)g.N * sizeof(T) + kNPMax * sizeof(typename Cplx<T>::type);
   auto kern = k_kpm<T, NT, MS>;
   if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const auto* cf = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->coef64 : (const void*)pc->coef32);
   hipLaunchKernelGGL(kern, dim3(pc->H * nrhs), dim3(NT), lds, s, g, pc->H, nrhs, op, pc->info,
-                     pc->np, cf, dbar, ch, sh, Z, Zo, st);
+                     pc->np, cf, dbar, ch, sh, Z, Zo, io);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pc_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
-                  const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, const RhsState* st,
+                  const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, StIO io,
                   T ch, T sh, hipStream_t s) {
-  if (g.Q <= 64) return pc_launch_kpm<T, 64, 1>(pc, g, dbar, op, nrhs, Z, Zo, st, ch, sh, s);
-  if (g.Q <= 256) return pc_launch_kpm<T, 256, 1>(pc, g, dbar, op, nrhs, Z, Zo, st, ch, sh, s);
-  if (g.Q <= 512) return pc_launch_kpm<T, 512, 1>(pc, g, dbar, op, nrhs, Z, Zo, st, ch, sh, s);
-  return pc_launch_kpm<T, 1024, 1>(pc, g, dbar, op, nrhs, Z, Zo, st, ch, sh, s);
+  if (g.Q <= 64) return pc_launch_kpm<T, 64, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  if (g.Q <= 256) return pc_launch_kpm<T, 256, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  if (g.Q <= 512) return pc_launch_kpm<T, 512, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  return pc_launch_kpm<T, 1024, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
 }
 
+// Ping-pong bookkeeping of the CG state for a sequence of launches: each
+// state-aware kernel reads copy `cur`, writes copy `cur ^ 1`.
+struct StateSeq {
+  RhsState* st[2];
+  double* part[2];
+  int cur;
+  int precond;
+  bool active;  // false: plain operator calls without solver state
+  StIO next() {
+    if (!active) return StIO{nullptr, nullptr, nullptr, nullptr, precond};
+    StIO io{st[cur], st[cur ^ 1], part[cur], part[cur ^ 1], precond};
+    cur ^= 1;
+    return io;
+  }
+  RhsState* latest() const { return st[cur]; }
+};
+
 // out = op(in) (op: 0 F, 1 F^T, 2 F F^T).  With rdot != nullptr the inverse
-// transform also forms rdot . out and updates rz / beta (residual replaced).
+// transform also publishes rdot . out as P_RZ partials.
 template <typename T>
 hipError_t pc_apply(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
-                    const T* in, T* out, RhsState* st, const T* rdot, void* /*reserved*/,
-                    double* partial, unsigned* counter, hipStream_t s) {
+                    const T* in, T* out, const T* rdot, StateSeq& sq, hipStream_t s) {
   using T2 = typename Cplx<T>::type;
   T2* Z = reinterpret_cast<T2*>(pc->Z);
   T2* Z2 = reinterpret_cast<T2*>(pc->Z2);
   hipError_t e = pc_fwd<T>(pc, g, nrhs, const_cast<T*>(in), Z, nullptr, nullptr, nullptr,
-                           nullptr, st, partial, counter, false, s);
+                           nullptr, sq.next(), false, s);
   if (e != hipSuccess) return e;
-  e = pc_kpm<T>(pc, g, dbar, op, nrhs, Z, Z2, st, (T)pc->ch, (T)pc->sh, s);
+  e = pc_kpm<T>(pc, g, dbar, op, nrhs, Z, Z2, sq.next(), (T)pc->ch, (T)pc->sh, s);
   if (e != hipSuccess) return e;
-  return pc_inv<T>(pc, g, nrhs, Z2, out, rdot ? 2 : 0, rdot, st, partial, counter, s);
+  return pc_inv<T>(pc, g, nrhs, Z2, out, rdot ? 1 : 0, rdot, sq.next(), s);
 }
 
-// Preconditioned CG update: u += alpha p, r -= alpha Ap (with |r|^2 and the
-// convergence test), then z = F F^T r and rz_prev = rz, rz = r.z,
-// beta = rz / rz_prev.  Three launches.
+// Preconditioned CG update: u += alpha p, r -= alpha Ap (|r|^2 as P_RR),
+// then z = F F^T r (the KPM kernel folds P_RR and skips finished
+// right-hand sides) and r.z as P_RZ.  Three launches.
 template <typename T>
 hipError_t pc_cg_update(const PcTables* pc, const Geom& g, const T* dbar, int nrhs, T* u,
-                        const T* pa, const T* pb, T* r, const T* Ap, T* z, RhsState* st,
-                        double* partial, unsigned* counter, hipStream_t s) {
+                        const T* pa, const T* pb, T* r, const T* Ap, T* z, StateSeq& sq,
+                        hipStream_t s) {
   using T2 = typename Cplx<T>::type;
   T2* Z = reinterpret_cast<T2*>(pc->Z);
   T2* Z2 = reinterpret_cast<T2*>(pc->Z2);
-  hipError_t e = pc_fwd<T>(pc, g, nrhs, r, Z, u, pa, pb, Ap, st, partial, counter, true, s);
+  hipError_t e = pc_fwd<T>(pc, g, nrhs, r, Z, u, pa, pb, Ap, sq.next(), true, s);
   if (e != hipSuccess) return e;
-  e = pc_kpm<T>(pc, g, dbar, 2, nrhs, Z, Z2, st, (T)pc->ch, (T)pc->sh, s);
+  e = pc_kpm<T>(pc, g, dbar, 2, nrhs, Z, Z2, sq.next(), (T)pc->ch, (T)pc->sh, s);
   if (e != hipSuccess) return e;
-  return pc_inv<T>(pc, g, nrhs, Z2, z, 1, r, st, partial, counter, s);
+  return pc_inv<T>(pc, g, nrhs, Z2, z, 1, r, sq.next(), s);
 }
 
 }  // namespace fph

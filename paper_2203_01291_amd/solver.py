@@ -11,7 +11,7 @@ import torch
 
 from . import _lib
 from ._lib import (FPH_F32, FPH_F32_REFINED, FPH_F64, FPH_OP_M, FPH_OP_MT, FPH_OP_MTM,
-                   FPH_PC_F, FPH_PC_FFT, FPH_PC_FT, Lattice, PcgOpts, PcgStats, check)
+                   FPH_PC_F, FPH_PC_FFT, FPH_PC_FT, Lattice, PcgOpts, PcgStats, System, check)
 
 _OPS = {"M": FPH_OP_M, "MT": FPH_OP_MT, "MTM": FPH_OP_MTM}
 _PC_OPS = {"F": FPH_PC_F, "FT": FPH_PC_FT, "FFT": FPH_PC_FFT}
@@ -98,7 +98,7 @@ class FermionSolver:
         return (b[0], b[1]), list(npt)
 
     def solve(self, b, u=None, tol=1e-10, maxiter=100000, precond=False, prec="f64",
-              ru_delta=0.1, chunk=0):
+              ru_delta=0.1, chunk=0, variant=0):
         """Solve (M^T M) u = b for every right-hand side of b (float64).
         Returns (u, [stats dict per rhs]).  Blocks until done."""
         nrhs = self._vec(b)
@@ -107,7 +107,7 @@ class FermionSolver:
         zero = u is None
         u = torch.empty_like(b) if u is None else u
         opts = PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero),
-                       float(ru_delta), int(chunk), 0)
+                       float(ru_delta), int(chunk), int(variant))
         stats = (PcgStats * nrhs)()
         check(self.lib.pcg_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats,
                                  _stream()))
@@ -126,6 +126,66 @@ class FermionSolver:
         out = torch.empty(nrhs, dtype=torch.float64, device=b.device)
         check(self.lib.fermion_action(self.h, nrhs, _ptr(b), _ptr(u), _ptr(out), _stream()))
         return out
+
+
+class FermionBatch:
+    """Many independent systems (lattice, field x, right-hand sides b) solved
+    in one persistent launch.  ``systems`` is a list of (params, x, b) with
+    params having L, Ltau, dtau, t, mu, alpha; x [Ltau, N] and b
+    [nrhs, Ltau, N] float64 CUDA tensors.  Solutions land in ``self.u``
+    (one tensor per system, same shape as b).  The tensors are referenced
+    by the library: keep them alive and update them in place."""
+
+    def __init__(self, systems):
+        self.lib = _lib.load()
+        self.keep = []
+        self.u = []
+        arr = (System * len(systems))()
+        self.nrhs_total = 0
+        for k, (p, x, b) in enumerate(systems):
+            L, Ltau = int(p.L), int(p.Ltau)
+            d = L * L * Ltau
+            for t in (x, b):
+                if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                    raise ValueError("x and b must be contiguous float64 CUDA tensors")
+            if x.numel() != d or b.numel() % d:
+                raise ValueError("shape mismatch between lattice and tensors")
+            u = torch.zeros_like(b)
+            nrhs = b.numel() // d
+            self.keep += [x, b]
+            self.u.append(u)
+            arr[k] = System(Lattice(L, Ltau, float(p.dtau), float(p.t), float(p.mu), float(p.alpha)),
+                            x.data_ptr(), nrhs, b.data_ptr(), u.data_ptr())
+            self.nrhs_total += nrhs
+        h = ctypes.c_void_p()
+        check(self.lib.fph_batch_create(ctypes.byref(h), arr, len(systems)))
+        self.h = h
+
+    def _opts(self, tol, maxiter, ru_delta):
+        return PcgOpts(float(tol), int(maxiter), 0, FPH_F32_REFINED, 1, float(ru_delta), 0, 0)
+
+    def solve(self, tol=1e-8, maxiter=100000, ru_delta=0.1):
+        stats = (PcgStats * self.nrhs_total)()
+        opts = self._opts(tol, maxiter, ru_delta)
+        check(self.lib.fph_batch_solve(self.h, ctypes.byref(opts), stats, _stream()))
+        return [s.as_dict() for s in stats]
+
+    def tune(self, tol=1e-8, maxiter=100000, ru_delta=0.1):
+        best = (ctypes.c_int32 * 3)()
+        opts = self._opts(tol, maxiter, ru_delta)
+        check(self.lib.fph_batch_tune(self.h, ctypes.byref(opts), best, _stream()))
+        return {"threads": best[0], "plaquettes_per_thread": best[1], "blocks_per_cu": best[2]}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fph_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FermionAction(torch.autograd.Function):
