@@ -65,8 +65,17 @@ struct InDir {
     return v;
   }
   FPH_DEVINL void load2(long off, T& a, T& b) const {
-    a = load(off);
-    b = load(off + 1);
+    ld2(z + off, a, b);
+    if (!fresh) {
+      T c, d;
+      ld2(pold + off, c, d);
+      a += beta * c;
+      b += beta * d;
+    }
+  }
+  FPH_DEVINL void load2_owned(long off, T& a, T& b) const {
+    load2(off, a, b);
+    st2(pnew + off, a, b);
   }
 };
 
@@ -108,13 +117,12 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
   while (status == 0) {
     // Direction update fused into the operator: Ap = A (r + beta p).
     {
-      float* buf = reinterpret_cast<float*>(lds) + (long)so * g.N;
-      float* wbuf = reinterpret_cast<float*>(lds) + (long)S * g.N + (long)so * g.N;
+      float* lds4 = reinterpret_cast<float*>(lds) + 4L * so * g.N;
       InDir<float> in{it.r, pold, pnew, (float)beta, fresh};
       EpiDot<float> epi{it.Ap};
       double acc = 0.0, acc2 = 0.0;
-      mtm_chunks<float, NT, MS>(g, it.E32, (float)it.ch, (float)it.sh, Tch, tau0, Tc, active,
-                                lane, nslot, buf, wbuf, 0, in, epi, acc, acc2);
+      mtm_sweep<float, NT, MS>(g, it.E32, (float)it.ch, (float)it.sh, Tch, tau0, Tc, active,
+                               lane, nslot, lds4, 0, in, epi, acc, acc2);
       const double pAp = block_allsum<NT>(acc, red_sh, bcast);
       matvecs += 1;
       if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -153,13 +161,12 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
     }
     __syncthreads();
     {
-      double* buf = reinterpret_cast<double*>(lds) + (long)so * g.N;
-      double* wbuf = reinterpret_cast<double*>(lds) + (long)S * g.N + (long)so * g.N;
+      double* lds4 = reinterpret_cast<double*>(lds) + 4L * so * g.N;
       InPlain<double> in{it.u};
       EpiResidual<float> epi{it.b, it.r};
       double acc = 0.0, acc2 = 0.0;
-      mtm_chunks<double, NT, MS>(g, it.E64, it.ch, it.sh, Tch, tau0, Tc, active, lane, nslot,
-                                 buf, wbuf, 0, in, epi, acc, acc2);
+      mtm_sweep<double, NT, MS>(g, it.E64, it.ch, it.sh, Tch, tau0, Tc, active, lane, nslot,
+                                lds4, 0, in, epi, acc, acc2);
       rr_true = block_allsum<NT>(acc, red_sh, bcast);
     }
     matvecs += 1;
@@ -202,7 +209,7 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
 }
 
 // Persistent batched solve.  Launch: any number of blocks of NT threads;
-// LDS 2 * S * Nmax doubles (S = NT / Qmax chunks).  `queue` must be 0.
+// LDS 4 * S * Nmax doubles (S = NT / Qmax chunks).  `queue` must be 0.
 template <int NT, int MS>
 __global__ void __launch_bounds__(NT)
 k_batch_solve(const BatchItem* __restrict__ items, int nitems, unsigned* queue, double tol,

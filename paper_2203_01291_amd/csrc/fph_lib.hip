@@ -87,7 +87,7 @@ hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi e
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
   const int nchunks = (g.Ltau + Tch - 1) / Tch;
   const int nblk = (nchunks + S - 1) / S;
-  const size_t lds = 2 * (size_t)S * g.N * sizeof(T);
+  const size_t lds = 4 * (size_t)S * g.N * sizeof(T);
   auto kern = k_mtm<T, NT, MS, In, Epi>;
   if (lds > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -725,14 +725,14 @@ namespace {
 
 template <int NT, int MS>
 hipError_t batch_launch(fph_batch_s* b, double tol, int maxiter, double delta, hipStream_t s) {
-  // LDS: two FP64 slices per chunk, chunks side by side (largest over systems).
+  // LDS: four FP64 slices per chunk, chunks side by side (largest over systems).
   long sn = 0;
   for (const auto& sy : b->sys) {
     const int N = sy.lat.L * sy.lat.L, Q = N / 4;
     const int S = (Q <= NT) ? NT / Q : 1;
     sn = std::max<long>(sn, (long)S * N);
   }
-  const size_t lds = 2 * (size_t)sn * sizeof(double);
+  const size_t lds = 4 * (size_t)sn * sizeof(double);
   auto kern = k_batch_solve<NT, MS>;
   if (lds > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,

@@ -2,20 +2,18 @@
 //
 // (M v)_tau   = v_tau - E_tau * (C v~_{tau-1}),      v~_{-1} = -v_{Ltau-1}
 // (M^T w)_tau = w_tau - C^T (E_{tau+1} * w~_{tau+1}), w~_{Ltau} = -w_0
-// (Eq. M_def of the paper; B_tau = diag(E_tau) C, Eq. B_def.)
+// (Eq. M_def of the paper; B_tau = diag(E_tau) C, Eq. B_def, C = P_A P_B
+// with P_B acting first; both factors are symmetric, so C^T = P_B P_A.)
 //
 // Fused M^T M over a chunk of consecutive slices [tau0, tau0 + Tc): step j
 // (tau = tau0 + j, j = 0..Tc) forms w_tau = (M v)_tau in registers and, for
-// j >= 1, emits out_{tau-1} = w_{tau-1} - C^T (E_tau w_tau).  Per step:
-//   a) load v~_{tau-1} on odd plaquettes, apply P_B, write LDS  | barrier
-//   b) read even plaquettes, apply P_A, w = v_tau - E_tau (.);
-//      y = P_A (E_tau w) -> LDS (in place), w -> LDS            | barrier
-//   c) read odd plaquettes of y, apply P_B: out = w_{tau-1} - P_B y;
-//      keep w_tau on the odd plaquettes for the next step.
-// Each thread reads and writes only its own plaquette's sites between
-// barriers where no other thread can touch them, so two barriers per step
-// suffice and LDS holds two slices per chunk.  Only v, E and out touch
-// global memory: 3 vectors per application for one right-hand side.
+// j >= 1, emits out_{tau-1} = w_{tau-1} - C^T (E_tau w_tau).  Each thread
+// owns one even plaquette (four sites, two aligned pairs of consecutive
+// indices), so every global access is a paired load or store.  P_A acts
+// within the thread; P_B couples the four sites to their odd-plaquette
+// neighbours, which the thread reads from the slice in LDS (a 4x4 window).
+// Only v, E and out touch global memory: 3 vectors per application for one
+// right-hand side.
 #pragma once
 
 #include "fph_common.h"
@@ -35,6 +33,13 @@ FPH_DEVINL void ld2(const float* p, float& a, float& b) {
   b = v.y;
 }
 
+FPH_DEVINL void st2(double* p, double a, double b) {
+  *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
+FPH_DEVINL void st2(float* p, float a, float b) {
+  *reinterpret_cast<float2*>(p) = make_float2(a, b);
+}
+
 // ------------------------------------------------------- input functors --
 
 // v read directly.
@@ -47,6 +52,7 @@ struct InPlain {
   FPH_DEVINL T load(long off) const { return v[off]; }
   FPH_DEVINL T load_owned(long off) const { return v[off]; }
   FPH_DEVINL void load2(long off, T& a, T& b) const { ld2(v + off, a, b); }
+  FPH_DEVINL void load2_owned(long off, T& a, T& b) const { ld2(v + off, a, b); }
 };
 
 // v = one of two buffers chosen by the parity of the iteration count
@@ -61,6 +67,7 @@ struct InParity {
   FPH_DEVINL T load(long off) const { return v[off]; }
   FPH_DEVINL T load_owned(long off) const { return v[off]; }
   FPH_DEVINL void load2(long off, T& a, T& b) const { ld2(v + off, a, b); }
+  FPH_DEVINL void load2_owned(long off, T& a, T& b) const { ld2(v + off, a, b); }
 };
 
 // p = z + beta p_old computed on the fly (the CG direction update fused
@@ -105,6 +112,10 @@ struct InPUpdate {
       a += beta * c;
       b += beta * d;
     }
+  }
+  FPH_DEVINL void load2_owned(long off, T& a, T& b) const {
+    load2(off, a, b);
+    st2(pnew + off, a, b);
   }
 };
 
@@ -203,6 +214,10 @@ struct InCGCG {
     a = r0 - alpha * w0;
     b = r1 - alpha * w1;
   }
+  FPH_DEVINL void load2_owned(long off, T& a, T& b) const {
+    a = load_owned(off);
+    b = load_owned(off + 1);
+  }
 };
 
 // ---------------------------------------------------- epilogue functors --
@@ -213,6 +228,7 @@ struct EpiStore {
   T* __restrict__ out;
   FPH_DEVINL void begin(const RhsState&) {}
   FPH_DEVINL void put(long off, T o, T /*v*/, double& /*acc*/, double& /*acc2*/) const { out[off] = o; }
+  FPH_DEVINL void put2(long off, T o0, T o1, T, T, double&, double&) const { st2(out + off, o0, o1); }
   static constexpr int kKind = P_NONE;
 };
 
@@ -224,6 +240,10 @@ struct EpiDot {
   FPH_DEVINL void put(long off, T o, T v, double& acc, double& /*acc2*/) const {
     out[off] = o;
     acc += (double)v * (double)o;
+  }
+  FPH_DEVINL void put2(long off, T o0, T o1, T v0, T v1, double& acc, double&) const {
+    st2(out + off, o0, o1);
+    acc += (double)v0 * (double)o0 + (double)v1 * (double)o1;
   }
   static constexpr int kKind = P_PAP;
 };
@@ -241,6 +261,11 @@ struct EpiGD {
     acc += (double)v * (double)v;
     acc2 += (double)v * (double)o;
   }
+  FPH_DEVINL void put2(long off, T o0, T o1, T v0, T v1, double& acc, double& acc2) const {
+    st2(out + off, o0, o1);
+    acc += (double)v0 * (double)v0 + (double)v1 * (double)v1;
+    acc2 += (double)v0 * (double)o0 + (double)v1 * (double)o1;
+  }
   static constexpr int kKind = P_GD;
 };
 
@@ -255,6 +280,13 @@ struct EpiResidual {
     const double res = b[off] - o;
     r[off] = (TR)res;
     acc += res * res;
+  }
+  FPH_DEVINL void put2(long off, double o0, double o1, double, double, double& acc, double&) const {
+    double b0, b1;
+    ld2(b + off, b0, b1);
+    const double r0 = b0 - o0, r1 = b1 - o1;
+    st2(r + off, (TR)r0, (TR)r1);
+    acc += r0 * r0 + r1 * r1;
   }
   static constexpr int kKind = P_TRUE;
 };
@@ -279,149 +311,174 @@ FPH_DEVINL void block_layout(const Geom& g, int tid, int& S, int& sub, int& lane
   }
 }
 
-// The fused M^T M sweep of one chunk of slices [tau0, tau0 + Tc) of one
-// right-hand side (offset `base`), see the file comment.  Every thread of
-// the block calls it (inactive threads keep the barriers).  `in` supplies
-// the input vector, `epi` consumes the output and accumulates dots.
-template <typename T, int NT, int MAXSLOT, class In, class Epi>
-FPH_DEVINL void mtm_chunks(const Geom& g, const T* __restrict__ E, T ch, T sh, int Tch, int tau0,
-                           int Tc, bool active, int lane, int nslot, T* buf, T* wbuf, long base,
-                           const In& in, const Epi& epi, double& acc, double& acc2) {
-  T wprev[MAXSLOT][4];
-  T vodd[MAXSLOT][4];
-  // Software pipeline: the global loads of step j + 1 (odd plaquettes of
-  // slice tau-1 for (a), even plaquettes of v and E at slice tau for (b))
-  // are issued while step j works on LDS.
-  T na[MAXSLOT][4];             // next (a): v at odd sites of slice tau-1
-  T nv[MAXSLOT][4], ne[MAXSLOT][4];  // next (b): v, E at even sites of slice tau
+// P_B at the four sites of the even plaquette with corner (x0, y0), read
+// from the slice in LDS: the odd plaquettes covering those sites span the
+// 4x4 window x0-1..x0+2, y0-1..y0+2 (periodic).  Site (dx, dy) of the even
+// plaquette is local site (1-dx, 1-dy) of its odd plaquette, so with
+// C2 = [[ch, sh], [sh, ch]] along each axis
+//   out(dx, dy) = sum_{a,b} c(1-dy, b) c(1-dx, a) W[2dy + b][2dx + a].
+template <typename T>
+FPH_DEVINL void pb_window(const Geom& g, const T* __restrict__ sl, int x0, int y0, T ch, T sh,
+                          T out[4]) {
+  const int xm = (x0 == 0) ? g.L - 1 : x0 - 1;
+  const int xp = (x0 + 2 == g.L) ? 0 : x0 + 2;
+  const int ym = (y0 == 0) ? g.L - 1 : y0 - 1;
+  const int yp = (y0 + 2 == g.L) ? 0 : y0 + 2;
+  const int rows[4] = {ym, y0, y0 + 1, yp};
+  T h0[4], h1[4];  // x-combinations for dx = 0 (cols xm, x0) and dx = 1 (cols x0+1, xp)
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const T* row = sl + g.L * rows[rr];
+    T a, b;
+    ld2(row + x0, a, b);
+    const T wm = row[xm], wp = row[xp];
+    h0[rr] = sh * wm + ch * a;
+    h1[rr] = ch * b + sh * wp;
+  }
+  out[0] = sh * h0[0] + ch * h0[1];
+  out[1] = sh * h1[0] + ch * h1[1];
+  out[2] = ch * h0[2] + sh * h0[3];
+  out[3] = ch * h1[2] + sh * h1[3];
+}
 
+// The fused M^T M sweep of one chunk of slices [tau0, tau0 + Tc) of one
+// right-hand side (offset `base`), see the file comment; every thread of
+// the block calls it (inactive threads keep the barrier).  All global
+// traffic is in the even-plaquette layout (pairs of consecutive sites).
+// Per step tau (one barrier):
+//   (i)  t = P_B v~_{tau-1} from LDS buffer A[j&1]; w_tau = v_tau - E_tau
+//        P_A t; y = P_A(E_tau w_tau) -> B[j&1]; v~_tau -> A[(j+1)&1]
+//   (ii) out_{tau-1} = w_{tau-1} - P_B y (read from B[j&1]).
+// LDS: 4 slices (A[2], B[2]) per chunk.
+template <typename T, int NT, int MAXSLOT, class In, class Epi>
+FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, int Tch, int tau0,
+                          int Tc, bool active, int lane, int nslot, T* lds4, long base,
+                          const In& in, const Epi& epi, double& acc, double& acc2) {
+  T* A0 = lds4;
+  T* A1 = lds4 + g.N;
+  T* B0 = lds4 + 2 * g.N;
+  T* B1 = lds4 + 3 * g.N;
+  T cv[MAXSLOT][4], ce[MAXSLOT][4];   // v_tau, E_tau (even layout)
+  T wprev[MAXSLOT][4], vprev[MAXSLOT][4];
+
+  // loads of slice tau0 + jj into cv/ce (v owned when jj < Tc)
   auto issue = [&](int jj) {
     const int tau = tau0 + jj;
     const int tm = (tau >= g.Ltau) ? tau - g.Ltau : tau;
-    const int pt = (tm == 0) ? g.Ltau - 1 : tm - 1;
-    const long poff = base + (long)pt * g.N;
     const long toff = base + (long)tm * g.N;
     const T* Et = E + (long)tm * g.N;
 #pragma unroll
     for (int k = 0; k < MAXSLOT; ++k) {
       const int q = lane + k * NT;
       if (k < nslot && q < g.Q) {
-        int so[4], se[4];
-        odd_sites(g, q, so);
-        even_sites(g, q, se);
-        if (jj >= 1) {  // slice tau-1 is owned by this chunk: elementwise updates
-#pragma unroll
-          for (int m = 0; m < 4; ++m) na[k][m] = in.load_owned(poff + so[m]);
+        const int i0 = 2 * (q % g.hL) + g.L * 2 * (q / g.hL);
+        if (jj < Tc) {
+          in.load2_owned(toff + i0, cv[k][0], cv[k][1]);
+          in.load2_owned(toff + i0 + g.L, cv[k][2], cv[k][3]);
         } else {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) na[k][m] = in.load(poff + so[m]);
+          in.load2(toff + i0, cv[k][0], cv[k][1]);
+          in.load2(toff + i0 + g.L, cv[k][2], cv[k][3]);
         }
-        in.load2(toff + se[0], nv[k][0], nv[k][1]);
-        in.load2(toff + se[2], nv[k][2], nv[k][3]);
-        ld2(Et + se[0], ne[k][0], ne[k][1]);
-        ld2(Et + se[2], ne[k][2], ne[k][3]);
+        ld2(Et + i0, ce[k][0], ce[k][1]);
+        ld2(Et + i0 + g.L, ce[k][2], ce[k][3]);
       }
     }
   };
 
-  if (active) issue(0);
+  // Prologue: v~_{tau0 - 1} into A0 (antiperiodic sign at the wrap).
+  if (active) {
+    const int pt = (tau0 == 0) ? g.Ltau - 1 : tau0 - 1;
+    const T psg = (tau0 == 0) ? (T)-1 : (T)1;
+    const long poff = base + (long)pt * g.N;
+#pragma unroll
+    for (int k = 0; k < MAXSLOT; ++k) {
+      const int q = lane + k * NT;
+      if (k < nslot && q < g.Q) {
+        const int i0 = 2 * (q % g.hL) + g.L * 2 * (q / g.hL);
+        T a, b, c, d;
+        in.load2(poff + i0, a, b);
+        in.load2(poff + i0 + g.L, c, d);
+        st2(A0 + i0, psg * a, psg * b);
+        st2(A0 + i0 + g.L, psg * c, psg * d);
+      }
+    }
+    issue(0);
+  }
+  __syncthreads();
+
   for (int j = 0; j <= Tch; ++j) {
     const int tau = tau0 + j;
     const bool act = active && (j <= Tc);
-    const int tm = (tau >= g.Ltau) ? tau - g.Ltau : tau;
-    // (a) v~_{tau-1} on odd plaquettes -> P_B -> LDS
-    if (act) {
-      const T psg = (tm == 0) ? (T)-1 : (T)1;
-#pragma unroll
-      for (int k = 0; k < MAXSLOT; ++k) {
-        const int q = lane + k * NT;
-        if (k < nslot && q < g.Q) {
-          int s[4];
-          odd_sites(g, q, s);
-          T t[4];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const T val = na[k][m];
-            vodd[k][m] = val;
-            t[m] = psg * val;
-          }
-          plaq_rot(t, ch, sh);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) buf[s[m]] = t[m];
-        }
-      }
-    }
-    __syncthreads();
-    // (b) even plaquettes: P_A, w = v - E (.), y = P_A(E w); then issue the
-    // loads of the next step
-    T cv[MAXSLOT][4], ce[MAXSLOT][4];
+    const T* Acur = (j & 1) ? A1 : A0;
+    T* Anext = (j & 1) ? A0 : A1;
+    T* Bcur = (j & 1) ? B1 : B0;
+    T nv[MAXSLOT][4], ne[MAXSLOT][4];
 #pragma unroll
     for (int k = 0; k < MAXSLOT; ++k)
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        cv[k][m] = nv[k][m];
-        ce[k][m] = ne[k][m];
+        nv[k][m] = cv[k][m];
+        ne[k][m] = ce[k][m];
       }
     if (active && j + 1 <= Tc) issue(j + 1);
+    T wcur[MAXSLOT][4];
     if (act) {
-      const T sg = (tau >= g.Ltau) ? (T)-1 : (T)1;
+      const T sg = (tau >= g.Ltau) ? (T)-1 : (T)1;          // w_{Ltau} = -w_0
+      const T nsg = (tau + 1 == g.Ltau) ? (T)-1 : (T)1;     // v~ for the next step
 #pragma unroll
       for (int k = 0; k < MAXSLOT; ++k) {
         const int q = lane + k * NT;
         if (k < nslot && q < g.Q) {
-          int s[4];
-          even_sites(g, q, s);
-          T t[4], w[4];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) t[m] = buf[s[m]];
+          const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
+          const int i0 = x0 + g.L * y0;
+          T t[4];
+          pb_window(g, Acur, x0, y0, ch, sh, t);
           plaq_rot(t, ch, sh);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const T e = ce[k][m];
-            w[m] = sg * (cv[k][m] - e * t[m]);
-            t[m] = e * w[m];
+            wcur[k][m] = sg * (nv[k][m] - ne[k][m] * t[m]);
+            t[m] = ne[k][m] * wcur[k][m];
           }
           plaq_rot(t, ch, sh);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            buf[s[m]] = t[m];
-            wbuf[s[m]] = w[m];
-          }
+          st2(Bcur + i0, t[0], t[1]);
+          st2(Bcur + i0 + g.L, t[2], t[3]);
+          st2(Anext + i0, nsg * nv[k][0], nsg * nv[k][1]);
+          st2(Anext + i0 + g.L, nsg * nv[k][2], nsg * nv[k][3]);
         }
       }
     }
     __syncthreads();
-    // (c) odd plaquettes: out_{tau-1} = w_{tau-1} - P_B y; keep w_tau
     if (act) {
       const long ooff = base + (long)(tau - 1) * g.N;
 #pragma unroll
       for (int k = 0; k < MAXSLOT; ++k) {
         const int q = lane + k * NT;
         if (k < nslot && q < g.Q) {
-          int s[4];
-          odd_sites(g, q, s);
-          T t[4];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) t[m] = buf[s[m]];
-          plaq_rot(t, ch, sh);
+          const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
+          const int i0 = x0 + g.L * y0;
           if (j >= 1) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-              epi.put(ooff + s[m], wprev[k][m] - t[m], vodd[k][m], acc, acc2);
+            T t[4];
+            pb_window(g, Bcur, x0, y0, ch, sh, t);
+            epi.put2(ooff + i0, wprev[k][0] - t[0], wprev[k][1] - t[1], vprev[k][0],
+                     vprev[k][1], acc, acc2);
+            epi.put2(ooff + i0 + g.L, wprev[k][2] - t[2], wprev[k][3] - t[3], vprev[k][2],
+                     vprev[k][3], acc, acc2);
           }
 #pragma unroll
-          for (int m = 0; m < 4; ++m) wprev[k][m] = wbuf[s[m]];
+          for (int m = 0; m < 4; ++m) {
+            wprev[k][m] = wcur[k][m];
+            vprev[k][m] = nv[k][m];
+          }
         }
       }
     }
   }
-
 }
 
 // Launch: grid (nblk, nrhs).  Block b of right-hand side r serves `S`
 // chunks of `Tch` slices each; with Q <= NT plaquettes per slice, S = NT/Q
 // chunks run side by side (one plaquette per thread), otherwise S = 1 and a
-// thread serves up to MAXSLOT plaquettes.  LDS: 2 * S * N elements of T.
+// thread serves up to MAXSLOT plaquettes.  LDS: 4 * S * N elements of T.
 // With io.in set, the kernel takes part in the CG state machine: it folds
 // pending partials, skips finished right-hand sides and publishes its own
 // partials (Epi::kKind).
@@ -453,12 +510,11 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, In in, Epi epi, StIO
   const int tau0 = chunk * Tch;
   const bool active = (sub < S) && (tau0 < g.Ltau);
   const int Tc = active ? min(Tch, g.Ltau - tau0) : 0;
-  T* buf = reinterpret_cast<T*>(smem_raw) + (long)(sub < S ? sub : 0) * g.N;
-  T* wbuf = reinterpret_cast<T*>(smem_raw) + (long)S * g.N + (long)(sub < S ? sub : 0) * g.N;
+  T* lds4 = reinterpret_cast<T*>(smem_raw) + 4L * (sub < S ? sub : 0) * g.N;
   const long base = (long)r * g.d;
   double acc = 0.0, acc2 = 0.0;
-  mtm_chunks<T, NT, MAXSLOT>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, buf, wbuf, base,
-                             in, epi, acc, acc2);
+  mtm_sweep<T, NT, MAXSLOT>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, lds4, base, in,
+                            epi, acc, acc2);
 
   if (io.in != nullptr) {
     double bs = 0.0, bs2 = 0.0;
