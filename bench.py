@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--profile-roofline", action="store_true",
+                    help="only the roofline kernel (M^T M, FP32, L=64 Ltau=400 x 32 rhs) and a "
+                         "plain copy of the same byte count, for hardware-counter runs")
     return ap.parse_args()
 
 
@@ -178,6 +181,57 @@ def cpu_baseline(p, golden_iters):
     }
 
 
+# HBM traffic of the roofline kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of `bench.py --profile-roofline`, each scaled by the same
+# counter read for a copy kernel of known size.  Valid only while the
+# kernel sources hash to `source_sha1`; otherwise reported as null.
+TRAFFIC = None
+KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
+                  "paper_2203_01291_amd/csrc/fph_lib.hip"]
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def large_matvec_setup(torch, dev):
+    """The roofline workload: fused M^T M at L = 64, Ltau = 400 (c5 shape)
+    with 32 right-hand sides sharing one field: 852 MB (FP64) / 426 MB
+    (FP32) of algorithmic traffic per launch, far above the 256 MB
+    Infinity Cache."""
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import get_config, phonon_field
+    p5 = get_config("c5")
+    R5 = 32
+    s5 = FermionSolver.from_params(p5, max_rhs=1)
+    s5.set_field(torch.from_numpy(phonon_field(p5)).to(dev))
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    vl = torch.randn(R5, p5.Ltau, p5.N, device=dev, dtype=torch.float64, generator=g)
+    return p5, R5, s5, vl
+
+
+def profile_roofline(torch, dev):
+    p5, R5, s5, vl = large_matvec_setup(torch, dev)
+    v32 = vl.float()
+    out = torch.empty_like(v32)
+    for _ in range(10):
+        s5.matvec(v32, "MTM", out=out)
+    nbytes = (2 * R5 + 1) * p5.dim * 4
+    src = torch.empty(nbytes // 8, dtype=torch.float32, device=dev).normal_()
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mtm_launches": 10, "mtm_bytes": nbytes, "copy_launches": 10,
+                      "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -185,6 +239,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.profile_roofline:
+        profile_roofline(torch, torch.device("cuda:0"))
+        return
 
     from paper_2203_01291_amd.solver import FermionSolver
     from workloads import gaussian_rhs, get_config, perturbed_field, phonon_field
@@ -244,13 +302,8 @@ def main():
 
     large = None
     if not args.no_large:
-        # Same kernel on a working set far above the 256 MB Infinity Cache:
-        # L = 64, Ltau = 400 with 32 right-hand sides sharing one field.
-        p5 = get_config("c5")
-        R5 = 32
-        s5 = FermionSolver.from_params(p5, max_rhs=1)
-        s5.set_field(torch.from_numpy(phonon_field(p5)).to(dev))
-        vl = torch.randn(R5, p5.Ltau, p5.N, device=dev, dtype=torch.float64)
+        # Same kernel on a working set far above the 256 MB Infinity Cache.
+        p5, R5, s5, vl = large_matvec_setup(torch, dev)
         tl64 = event_time_matvec(s5, vl, "MTM", 20, torch)
         tl32 = event_time_matvec(s5, vl.float(), "MTM", 20, torch)
         bl64 = (2 * R5 + 1) * p5.dim * 8
@@ -274,6 +327,22 @@ def main():
         gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_iterations.json")))
         cpu = cpu_baseline(p, gold[args.workload]["iters_tol_1e-8"])
         log(f"cpu baseline: {cpu}")
+
+    if large is not None:
+        traffic = None
+        if TRAFFIC is not None and TRAFFIC["source_sha1"] == kernel_sources_sha1():
+            traffic = TRAFFIC["bytes_per_launch"]
+        roofline = {"bound": "hbm", "achieved": large["f32"]["GB/s"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": large["f32"]["frac"], "traffic": traffic,
+                    "kernel": "fused M^T M apply, FP32 (k_mtm<float, 1024, 1, InPlain, EpiStore>)",
+                    "workload": large["workload"],
+                    "bytes_per_launch": large["working_set_MB"]["f32"] * 1e6,
+                    "avg_launch_us": large["f32"]["us"]}
+    else:
+        roofline = {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs32 / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "fused M^T M apply, FP32 (k_mtm<float, 256, 1, InPlain, EpiStore>)",
+                    "workload": p.name, "bytes_per_launch": bytes32, "avg_launch_us": tm32 * 1e6}
 
     value = R / t32
     rec = {
@@ -302,12 +371,13 @@ def main():
                     "iters": [v["iters"] for v in st64],
                     "speedup_fp32_refined": t64 / t32,
                     "action_rel_diff": float(np.max(np.abs(np.array(S32) - np.array(S64)) / np.abs(np.array(S64))))},
-        "roofline": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "fused M^T M apply, FP32 (k_mtm<float, InPlain, EpiStore>)",
-                     "bytes_per_launch": bytes32, "avg_launch_us": tm32 * 1e6},
-        "matvec_f64": {"GB/s": gbs64, "frac": gbs64 / HBM_PEAK_GBS, "avg_launch_us": tm64 * 1e6,
-                       "bytes_per_launch": bytes64},
+        "roofline": roofline,
+        "matvec_workload": {
+            "note": "single system at the workload shape: cache resident, latency bound",
+            "f32": {"GB/s": gbs32, "frac": gbs32 / HBM_PEAK_GBS, "avg_launch_us": tm32 * 1e6,
+                    "bytes_per_launch": bytes32},
+            "f64": {"GB/s": gbs64, "frac": gbs64 / HBM_PEAK_GBS, "avg_launch_us": tm64 * 1e6,
+                    "bytes_per_launch": bytes64}},
         "matvec_large": large,
         "batched": batch,
         "precond_trial": {("precond" if k else "plain"): {"ms": v[0] * 1e3, "iters": v[1]}

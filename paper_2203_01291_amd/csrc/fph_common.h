@@ -73,6 +73,16 @@ FPH_DEVINL void plaq_rot(T v[4], T ch, T sh) {
 
 // ------------------------------------------------------------ solver state
 
+// Workgroup i of a 1-D launch of n runs on XCD i % 8 (round-robin
+// dispatch).  Returns a renumbering that is a bijection of [0, n) and gives
+// each XCD a contiguous range, XCDs with one workgroup more first.
+FPH_DEVINL int xcd_contiguous(int i, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, rem = n % kXcd;
+  const int x = i % kXcd, slot = i / kXcd;
+  return (x < rem) ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+}
+
 // Kinds of pending partial sums: a kernel that reduces something writes one
 // partial per block; the next state-aware kernel in stream order sums them
 // (every block in the same order, so all blocks agree bit for bit) and

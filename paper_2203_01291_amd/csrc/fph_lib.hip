@@ -94,8 +94,9 @@ hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi e
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(nblk, nrhs), dim3(NT), lds, s, g, (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32),
-                     (T)h->ch, (T)h->sh, Tch, in, epi, io);
+  hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g,
+                     (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32),
+                     (T)h->ch, (T)h->sh, Tch, nblk, in, epi, io);
   return hipGetLastError();
 }
 

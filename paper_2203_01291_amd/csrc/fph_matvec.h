@@ -475,7 +475,7 @@ FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
   }
 }
 
-// Launch: grid (nblk, nrhs).  Block b of right-hand side r serves `S`
+// Launch: grid (nblk * nrhs) (see xcd_contiguous).  Block b of right-hand side r serves `S`
 // chunks of `Tch` slices each; with Q <= NT plaquettes per slice, S = NT/Q
 // chunks run side by side (one plaquette per thread), otherwise S = 1 and a
 // thread serves up to MAXSLOT plaquettes.  LDS: 4 * S * N elements of T.
@@ -484,17 +484,24 @@ FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
 // partials (Epi::kKind).
 template <typename T, int NT, int MAXSLOT, class In, class Epi>
 __global__ void __launch_bounds__(NT)
-k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, In in, Epi epi, StIO io) {
+k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi epi, StIO io) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
-  const int r = blockIdx.y;
+  // Workgroups are handed to the 8 XCDs round robin; renumber them so each
+  // XCD gets a contiguous range of (chunk-major, right-hand side minor)
+  // work: neighbouring chunks (which share halo slices) and the chunks of
+  // all right-hand sides at the same slices (which share E) meet in one L2.
+  const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int nrhs = gridDim.x / nblk;
+  const int r = logical % nrhs;
+  const int bx = logical / nrhs;
   if (io.in != nullptr) {
     state_begin<NT>(io, r, &s_sh, red_sh);
     if (threadIdx.x == 0 && !s_sh.done) In::prepare(s_sh);
     __syncthreads();
     if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+      state_end(io, r, &s_sh, P_NONE, 0.0, bx, nblk, bx == 0);
       return;
     }
     in.begin(s_sh);
@@ -506,7 +513,7 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, In in, Epi epi, StIO
   const int tid = threadIdx.x;
   int S, sub, lane, nslot;
   block_layout<NT>(g, tid, S, sub, lane, nslot);
-  const int chunk = blockIdx.x * S + sub;
+  const int chunk = bx * S + sub;
   const int tau0 = chunk * Tch;
   const bool active = (sub < S) && (tau0 < g.Ltau);
   const int Tc = active ? min(Tch, g.Ltau - tau0) : 0;
@@ -520,7 +527,7 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, In in, Epi epi, StIO
     double bs = 0.0, bs2 = 0.0;
     if constexpr (Epi::kKind != P_NONE) bs = block_sum<NT>(acc, red_sh);
     if constexpr (Epi::kKind == P_GD) bs2 = block_sum<NT>(acc2, red_sh);
-    state_end(io, r, &s_sh, Epi::kKind, bs, blockIdx.x, gridDim.x, blockIdx.x == 0, bs2);
+    state_end(io, r, &s_sh, Epi::kKind, bs, bx, nblk, bx == 0, bs2);
   }
 }
 
