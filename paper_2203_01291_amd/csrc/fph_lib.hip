@@ -446,8 +446,8 @@ Work<float> work32(fph_handle_s* h) {
 // dots (P_GD).  Starts a solve and follows every residual replacement.
 template <typename T>
 hipError_t cgcg_start(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq, hipStream_t s) {
-  InParity<T> in{{w.r, w.rb}, nullptr};
-  EpiGD<T> epi{{w.Ap, w.wb}, 0, nullptr};
+  InParity<T> in{w.r, w.rb, nullptr};
+  EpiGD<T> epi{w.Ap, w.wb, 0, nullptr};
   return launch_mtm<T>(h, nrhs, in, epi, sq.next(), s);
 }
 
@@ -455,9 +455,9 @@ hipError_t cgcg_start(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq,
 template <typename T>
 hipError_t cgcg_iteration(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq,
                           hipStream_t s) {
-  InCGCG<T> in{{w.r, w.rb}, {w.z, w.sb}, {w.pa, w.pb}, {w.Ap, w.wb}, w.u,
+  InCGCG<T> in{w.r, w.rb, w.z, w.sb, w.pa, w.pb, w.Ap, w.wb, w.u,
                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (T)0, (T)0, 0};
-  EpiGD<T> epi{{w.Ap, w.wb}, 1, nullptr};
+  EpiGD<T> epi{w.Ap, w.wb, 1, nullptr};
   return launch_mtm<T>(h, nrhs, in, epi, sq.next(), s);
 }
 

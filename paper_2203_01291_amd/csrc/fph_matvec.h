@@ -42,6 +42,15 @@ FPH_DEVINL void st2(float* p, float a, float b) {
 
 // ------------------------------------------------------- input functors --
 
+// c ? b : a for two pointers, selected by value.  A plain conditional on
+// two members of a by-value kernel argument is turned into a load from a
+// computed address, which forces the whole argument into scratch memory.
+template <typename P>
+FPH_DEVINL P pick(bool c, P a, P b) {
+  const uintptr_t m = (uintptr_t)0 - (uintptr_t)c;
+  return (P)(((uintptr_t)a & ~m) | ((uintptr_t)b & m));
+}
+
 // v read directly.
 template <typename T>
 struct InPlain {
@@ -59,10 +68,11 @@ struct InPlain {
 // (single-reduction CG keeps its residual double-buffered).
 template <typename T>
 struct InParity {
-  const T* buf[2];
+  const T* buf0;
+  const T* buf1;
   const T* __restrict__ v;
   static FPH_DEVINL void prepare(RhsState&) {}
-  FPH_DEVINL void begin(const RhsState& s) { v = buf[s.iter & 1]; }
+  FPH_DEVINL void begin(const RhsState& s) { v = pick((s.iter & 1) != 0, buf0, buf1); }
   static FPH_DEVINL void on_state(RhsState&) {}
   FPH_DEVINL T load(long off) const { return v[off]; }
   FPH_DEVINL T load_owned(long off) const { return v[off]; }
@@ -88,8 +98,8 @@ struct InPUpdate {
     fresh = s.fresh;
     beta = fresh ? (T)0 : (T)(s.rz_next / s.rz);
     const bool odd = (s.iter & 1) != 0;
-    pold = odd ? pb : pa;
-    pnew = odd ? pa : pb;
+    pold = pick(odd, pa, pb);
+    pnew = pick(odd, pb, pa);
   }
   // Direction-update bookkeeping, applied once to the shared state.
   static FPH_DEVINL void on_state(RhsState& s) {
@@ -132,10 +142,14 @@ struct InPUpdate {
 // parity of i.
 template <typename T>
 struct InCGCG {
-  T* R[2];
-  T* S[2];
-  T* P[2];
-  const T* W[2];
+  T* R0;
+  T* R1;
+  T* S0;
+  T* S1;
+  T* P0;
+  T* P1;
+  const T* W0;
+  const T* W1;
   T* x;
   const T* __restrict__ ri;
   const T* __restrict__ wi;
@@ -167,14 +181,14 @@ struct InCGCG {
     }
   }
   FPH_DEVINL void begin(const RhsState& s) {
-    const int c = s.iter & 1, n = c ^ 1;
-    ri = R[c];
-    wi = W[c];
-    rn = R[n];
-    so = S[n];
-    sn = S[c];
-    po = P[n];
-    pn = P[c];
+    const bool c = (s.iter & 1) != 0;
+    ri = pick(c, R0, R1);
+    wi = pick(c, W0, W1);
+    rn = pick(c, R1, R0);
+    so = pick(c, S1, S0);
+    sn = pick(c, S0, S1);
+    po = pick(c, P1, P0);
+    pn = pick(c, P0, P1);
     alpha = (T)s.alpha;
     beta = (T)s.beta;
     fresh = s.fresh;
@@ -252,10 +266,11 @@ struct EpiDot {
 // r.r and r.w (consumed as P_GD by single-reduction CG).
 template <typename T>
 struct EpiGD {
-  T* W[2];
+  T* W0;
+  T* W1;
   int shift;
   T* __restrict__ out;
-  FPH_DEVINL void begin(const RhsState& s) { out = W[(s.iter + shift) & 1]; }
+  FPH_DEVINL void begin(const RhsState& s) { out = pick(((s.iter + shift) & 1) != 0, W0, W1); }
   FPH_DEVINL void put(long off, T o, T v, double& acc, double& acc2) const {
     out[off] = o;
     acc += (double)v * (double)v;

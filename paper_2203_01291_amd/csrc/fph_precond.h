@@ -176,10 +176,13 @@ FPH_DEVINL T2 cmulc(T2 a, T2 b) {  // a * conj(b)
   return r;
 }
 
-// Sites per transform block: 64 bytes of one slice row (8 in FP64, 16 in FP32).
-template <typename T> struct Tile { static constexpr int kS = 64 / sizeof(T); };
+// Transform workgroups own a tile of KS = 2^lks consecutive sites (all
+// slices of them): KS <= 64 bytes of a slice row, smaller when that leaves
+// too few workgroups to fill the chip.  Workgroups are numbered with
+// xcd_contiguous so neighbouring tiles (which share cache lines) run on
+// one XCD.
 
-// Forward transform of Tile<T>::kS sites per block: Z[r][k][i] = (U in)_{2k}.
+// Forward transform of one tile of sites: Z[r][k][i] = (U in)_{2k}.
 // Stage 0 (all threads, coalesced): the tile in[tau][i0..i0+kS) goes to
 // LDS; with CGUPD it first receives the CG update u += alpha p,
 // r -= alpha Ap (r is `in`, updated in place), publishing |r|^2 as P_RR
@@ -188,16 +191,16 @@ template <typename T> struct Tile { static constexpr int kS = 64 / sizeof(T); };
 // y_tau = e^{-i pi tau/Ltau} (in_tau - i in_{tau+H}), tau = H2 n1 + n2,
 // times W_H^{n2 k1}, into LDS.  Step 2, item (site, k1, k2): the H2-point
 // DFT over n2 -> Z_{k1 + H1 k2}.  Twiddles live in LDS.
-// Launch: grid (ceil(N / kS), nrhs), NT threads,
-// LDS 2H complex + Ltau kS reals + H kS complex.
+// Launch: grid ntiles * nrhs (ntiles = ceil(N / KS)), NT threads,
+// LDS 2H complex + Ltau KS reals + H KS complex.
 template <typename T, int H1, int NT, bool CGUPD>
 __global__ void __launch_bounds__(NT)
 k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
        const typename Cplx<T>::type* __restrict__ W, T* __restrict__ in,
        typename Cplx<T>::type* __restrict__ Z, T* __restrict__ u, const T* pa, const T* pb,
-       const T* __restrict__ Ap, StIO io) {
+       const T* __restrict__ Ap, int lks, int ntiles, StIO io) {
   using T2 = typename Cplx<T>::type;
-  constexpr int KS = Tile<T>::kS;
+  const int KS = 1 << lks;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = H1 * H2;
   T2* Wl = reinterpret_cast<T2*>(smem_raw);
@@ -206,7 +209,9 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   T* Rt = reinterpret_cast<T*>(Y + H * KS);
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
-  const int r = blockIdx.y;
+  const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int r = logical % (gridDim.x / ntiles);
+  const int tile = logical / (gridDim.x / ntiles);
   for (int k = threadIdx.x; k < H; k += NT) {
     Wl[k] = W[k];
     twl[k] = tw[k];
@@ -214,11 +219,11 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   if (io.in != nullptr) {
     state_begin<NT>(io, r, &s_sh, red_sh);
     if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+      state_end(io, r, &s_sh, P_NONE, 0.0, tile, ntiles, tile == 0);
       return;
     }
   }
-  const int i0 = blockIdx.x * KS;
+  const int i0 = tile * KS;
   const long base = (long)r * g.d;
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
   double acc_rr = 0.0;
@@ -231,25 +236,42 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
       alpha = (T)s_sh.alpha;
       p = (s_sh.iter & 1) ? pa : pb;  // direction written by this iteration
     }
-    for (int e = threadIdx.x; e < g.Ltau * KS; e += NT) {
-      const int tau = e / KS, sidx = e - tau * KS;
-      T a = (T)0;
-      if (i0 + sidx < g.N) {
-        const long off = base + (long)tau * g.N + i0 + sidx;
-        a = in[off];
-        if (CGUPD) {
-          a -= alpha * Ap[off];
-          in[off] = a;
-          u[off] += alpha * p[off];
-          acc_rr += (double)a * (double)a;
+    // four elements per thread per pass, all loads issued first
+    const int nel = g.Ltau << lks;
+    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * NT) {
+      T a[4], av[4], pv[4], uv[4];
+      long off[4];
+      bool ok[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = e0 + j * NT;
+        const int tau = e >> lks, sidx = e & (KS - 1);
+        ok[j] = e < nel && i0 + sidx < g.N;
+        off[j] = base + (long)tau * g.N + i0 + sidx;
+        a[j] = ok[j] ? in[off[j]] : (T)0;
+        if (CGUPD && ok[j]) {
+          av[j] = Ap[off[j]];
+          pv[j] = p[off[j]];
+          uv[j] = u[off[j]];
         }
       }
-      Rt[e] = a;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = e0 + j * NT;
+        if (e >= nel) continue;
+        if (CGUPD && ok[j]) {
+          a[j] -= alpha * av[j];
+          in[off[j]] = a[j];
+          u[off[j]] = uv[j] + alpha * pv[j];
+          acc_rr += (double)a[j] * (double)a[j];
+        }
+        Rt[e] = a[j];
+      }
     }
   }
   __syncthreads();
   for (int it = threadIdx.x; it < KS * H2; it += NT) {
-    const int sidx = it % KS, n2 = it / KS;
+    const int sidx = it & (KS - 1), n2 = it >> lks;
     T2 y[H1];
 #pragma unroll
     for (int n1 = 0; n1 < H1; ++n1) {
@@ -275,8 +297,8 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   }
   __syncthreads();
   for (int it = threadIdx.x; it < KS * H; it += NT) {
-    const int sidx = it % KS;
-    const int kk = it / KS;
+    const int sidx = it & (KS - 1);
+    const int kk = it >> lks;
     const int k1 = kk % H1, k2 = kk / H1;
     if (i0 + sidx >= g.N) continue;
     const int step = (H1 * k2) % H;  // W_H2^{n2 k2} = W_H^{H1 n2 k2}
@@ -297,7 +319,7 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   if (io.in != nullptr) {
     double bs = 0.0;
     if (CGUPD) bs = block_sum<NT>(acc_rr, red_sh);
-    state_end(io, r, &s_sh, CGUPD ? P_RR : P_NONE, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
+    state_end(io, r, &s_sh, CGUPD ? P_RR : P_NONE, bs, tile, ntiles, tile == 0);
   }
 }
 
@@ -310,9 +332,9 @@ template <typename T, int H1, int NT>
 __global__ void __launch_bounds__(NT)
 k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
        const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ Zh,
-       T* __restrict__ out, int dot, const T* __restrict__ rdot, StIO io) {
+       T* __restrict__ out, int dot, const T* __restrict__ rdot, int lks, int ntiles, StIO io) {
   using T2 = typename Cplx<T>::type;
-  constexpr int KS = Tile<T>::kS;
+  const int KS = 1 << lks;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = H1 * H2;
   T2* Wl = reinterpret_cast<T2*>(smem_raw);
@@ -321,7 +343,9 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   T2* Zt = Y + H * KS;
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
-  const int r = blockIdx.y;
+  const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int r = logical % (gridDim.x / ntiles);
+  const int tile = logical / (gridDim.x / ntiles);
   for (int k = threadIdx.x; k < H; k += NT) {
     Wl[k] = W[k];
     twl[k] = tw[k];
@@ -329,22 +353,34 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   if (io.in != nullptr) {
     state_begin<NT>(io, r, &s_sh, red_sh);
     if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
+      state_end(io, r, &s_sh, P_NONE, 0.0, tile, ntiles, tile == 0);
       return;
     }
   }
-  const int i0 = blockIdx.x * KS;
+  const int i0 = tile * KS;
   const long base = (long)r * g.d;
   const T scale = (T)(2.0 / sqrt((double)g.Ltau));
   double acc_dot = 0.0;
 
-  for (int e = threadIdx.x; e < H * KS; e += NT) {
-    const int k = e / KS, sidx = e - k * KS;
-    Zt[e] = (i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx] : T2{(T)0, (T)0};
+  {
+    const int nel = H << lks;
+    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * NT) {
+      T2 v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = e0 + j * NT;
+        const int k = e >> lks, sidx = e & (KS - 1);
+        v[j] = (e < nel && i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx]
+                                           : T2{(T)0, (T)0};
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (e0 + j * NT < nel) Zt[e0 + j * NT] = v[j];
+    }
   }
   __syncthreads();
   for (int it = threadIdx.x; it < KS * H2; it += NT) {
-    const int sidx = it % KS, n2 = it / KS;
+    const int sidx = it & (KS - 1), n2 = it >> lks;
     T2 y[H1];
 #pragma unroll
     for (int n1 = 0; n1 < H1; ++n1) y[n1] = Zt[(H2 * n1 + n2) * KS + sidx];
@@ -366,8 +402,8 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   }
   __syncthreads();
   for (int it = threadIdx.x; it < KS * H; it += NT) {
-    const int sidx = it % KS;
-    const int kk = it / KS;
+    const int sidx = it & (KS - 1);
+    const int kk = it >> lks;
     const int k1 = kk % H1, k2 = kk / H1;
     if (i0 + sidx >= g.N) continue;
     const int step = (H1 * k2) % H;
@@ -394,90 +430,118 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   if (io.in != nullptr) {
     double bs = 0.0;
     if (dot) bs = block_sum<NT>(acc_dot, red_sh);
-    state_end(io, r, &s_sh, dot ? P_RZ : P_NONE, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
+    state_end(io, r, &s_sh, dot ? P_RZ : P_NONE, bs, tile, ntiles, tile == 0);
   }
 }
 
 // ------------------------------------------------------------ KPM kernel
 
-// Entry (j, k) of kron(C2, C2) in the local plaquette order index = dx + 2 dy.
+// Sites of the LDS window around the even plaquette with corner (x0, y0):
+// rows y0-1, y0, y0+1, y0+2 and columns x0-1, x0..x0+1, x0+2 (periodic).
+// The odd plaquettes of P_B that cover the plaquette's four sites lie in
+// it (site (dx, dy) of the even plaquette is local site (1-dx, 1-dy) of
+// its odd plaquette).
+struct Win {
+  int row[4];  // row offsets L * y
+  int x0, xm, xp;
+};
+
+FPH_DEVINL Win make_win(const Geom& g, int q) {
+  Win w;
+  const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
+  w.x0 = x0;
+  w.xm = (x0 == 0) ? g.L - 1 : x0 - 1;
+  w.xp = (x0 + 2 == g.L) ? 0 : x0 + 2;
+  w.row[0] = g.L * ((y0 == 0) ? g.L - 1 : y0 - 1);
+  w.row[1] = g.L * y0;
+  w.row[2] = g.L * (y0 + 1);
+  w.row[3] = g.L * ((y0 + 2 == g.L) ? 0 : y0 + 2);
+  return w;
+}
+
+// Two consecutive complex values (aligned: the index is even).
+FPH_DEVINL void ld2c(const float2* p, float2& a, float2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+FPH_DEVINL void ld2c(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
+}
+FPH_DEVINL void st2c(float2* p, float ar, float ai, float br, float bi) {
+  *reinterpret_cast<float4*>(p) = make_float4(ar, ai, br, bi);
+}
+FPH_DEVINL void st2c(double2* p, double ar, double ai, double br, double bi) {
+  p[0] = make_double2(ar, ai);
+  p[1] = make_double2(br, bi);
+}
+
+// P_B of a complex slice in LDS at the four sites of the thread's even
+// plaquette: with C2 = [[ch, sh], [sh, ch]] per axis,
+//   out(dx, dy) = sum_{a,b} c(1-dy, b) c(1-dx, a) W[2dy + b][2dx + a].
 template <typename T>
-FPH_DEVINL T kron_entry(int j, int k, T ch, T sh) {
-  const T cx = ((j ^ k) & 1) ? sh : ch;
-  const T cy = ((j ^ k) & 2) ? sh : ch;
-  return cx * cy;
+FPH_DEVINL void pb_window_c(const Win& w, const typename Cplx<T>::type* __restrict__ sl, T ch,
+                            T sh, T (&re)[4], T (&im)[4]) {
+  using T2 = typename Cplx<T>::type;
+  T h0r[4], h0i[4], h1r[4], h1i[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const T2* row = sl + w.row[rr];
+    T2 a, b;
+    ld2c(row + w.x0, a, b);
+    const T2 wm = row[w.xm], wp = row[w.xp];
+    h0r[rr] = sh * wm.x + ch * a.x;
+    h0i[rr] = sh * wm.y + ch * a.y;
+    h1r[rr] = ch * b.x + sh * wp.x;
+    h1i[rr] = ch * b.y + sh * wp.y;
+  }
+  re[0] = sh * h0r[0] + ch * h0r[1];
+  im[0] = sh * h0i[0] + ch * h0i[1];
+  re[1] = sh * h1r[0] + ch * h1r[1];
+  im[1] = sh * h1i[0] + ch * h1i[1];
+  re[2] = ch * h0r[2] + sh * h0r[3];
+  im[2] = ch * h0i[2] + sh * h0i[3];
+  re[3] = ch * h1r[2] + sh * h1r[3];
+  im[3] = ch * h1i[2] + sh * h1i[3];
 }
 
 // Bbar x (TRANS = false: dbar * P_A (P_B x)) or Bbar^T x (TRANS = true:
-// P_B (P_A (dbar * x))) for a complex vector held on even plaquettes.
-// One LDS exchange per apply: the thread publishes its four sites (x, or
-// P_A(dbar x)) into buffer `cur`, and after one barrier reads, for each of
-// its sites, the odd plaquette that covers the site and forms that site's
-// component of P_B.  Site m of the even plaquette at (x0, y0) lies in the
-// odd plaquette with corner (x0 + 1 - 2 [m even in x], y0 + 1 - 2 [m even
-// in y]) at local index 3 - m.  Buffers alternate between applies, so one
-// barrier per apply suffices.
-template <typename T, int NT, int MS, bool TRANS>
-FPH_DEVINL void bbar_apply(const Geom& g, int nslot, T (&xr)[MS][4], T (&xi)[MS][4],
-                           const T (&db)[MS][4], T* lbuf, int& cur, T ch, T sh) {
-  T* lr = lbuf + (long)cur * 2 * g.N;
-  T* li = lr + g.N;
-#pragma unroll
-  for (int k = 0; k < MS; ++k) {
-    const int q = threadIdx.x + k * NT;
-    if (k < nslot && q < g.Q) {
-      if (TRANS) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          xr[k][m] *= db[k][m];
-          xi[k][m] *= db[k][m];
-        }
-        plaq_rot(xr[k], ch, sh);
-        plaq_rot(xi[k], ch, sh);
-      }
-      int s[4];
-      even_sites(g, q, s);
+// P_B (P_A (dbar * x))) for a complex vector held one even plaquette per
+// thread.  One LDS exchange per apply: the thread publishes its four sites
+// (x, or P_A(dbar x)) into buffer `cur` and after one barrier forms P_B at
+// its sites from the window.  Buffers alternate between applies, so one
+// barrier per apply suffices.  Threads without a plaquette only keep the
+// barrier.
+template <typename T, bool TRANS>
+FPH_DEVINL void bbar_apply(const Win& w, bool own, int i0, int iL, T (&xr)[4], T (&xi)[4],
+                           const T (&db)[4], typename Cplx<T>::type* lbuf, int N, int& cur,
+                           T ch, T sh) {
+  using T2 = typename Cplx<T>::type;
+  T2* buf = lbuf + (long)cur * N;
+  if (own) {
+    if (TRANS) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        lr[s[m]] = xr[k][m];
-        li[s[m]] = xi[k][m];
+        xr[m] *= db[m];
+        xi[m] *= db[m];
       }
+      plaq_rot(xr, ch, sh);
+      plaq_rot(xi, ch, sh);
     }
+    st2c(buf + i0, xr[0], xi[0], xr[1], xi[1]);
+    st2c(buf + iL, xr[2], xi[2], xr[3], xi[3]);
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < MS; ++k) {
-    const int q = threadIdx.x + k * NT;
-    if (k < nslot && q < g.Q) {
-      const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
+  if (own) {
+    pb_window_c<T>(w, buf, ch, sh, xr, xi);
+    if (!TRANS) {
+      plaq_rot(xr, ch, sh);
+      plaq_rot(xi, ch, sh);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        int ox = x0 + 1 - ((m & 1) ? 0 : 2);
-        int oy = y0 + 1 - ((m & 2) ? 0 : 2);
-        if (ox < 0) ox += g.L;
-        if (oy < 0) oy += g.L;
-        const int xb = (ox + 1 == g.L) ? 0 : ox + 1;
-        const int yb = (oy + 1 == g.L) ? 0 : oy + 1;
-        const int os[4] = {ox + g.L * oy, xb + g.L * oy, ox + g.L * yb, xb + g.L * yb};
-        const int j = 3 - m;
-        T ar = (T)0, ai = (T)0;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const T c = kron_entry<T>(j, kk, ch, sh);
-          ar += c * lr[os[kk]];
-          ai += c * li[os[kk]];
-        }
-        xr[k][m] = ar;
-        xi[k][m] = ai;
-      }
-      if (!TRANS) {
-        plaq_rot(xr[k], ch, sh);
-        plaq_rot(xi[k], ch, sh);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          xr[k][m] *= db[k][m];
-          xi[k][m] *= db[k][m];
-        }
+        xr[m] *= db[m];
+        xi[m] *= db[m];
       }
     }
   }
@@ -485,65 +549,61 @@ FPH_DEVINL void bbar_apply(const Geom& g, int nslot, T (&xr)[MS][4], T (&xi)[MS]
 }
 
 // acc = sum_{m < NP} c'_m T_m(A') x with A' = A (TRANS false, c' = c) or
-// A' = A^T (TRANS true, c' = conj(c)); three-term recurrence of Eq.
-// alpha_recur.  x is consumed.
-template <typename T, int NT, int MS, bool TRANS>
-FPH_DEVINL void cheb_series(const Geom& g, int nslot, int NP, const typename Cplx<T>::type* cf,
-                            T sA, T cA, T (&xr)[MS][4], T (&xi)[MS][4], const T (&db)[MS][4],
-                            T* lbuf, int& cur, T ch, T sh, T (&ar)[MS][4], T (&ai)[MS][4]) {
+// A' = A^T (TRANS true, c' = conj(c)), A = sA Bbar - cA; three-term
+// recurrence of Eq. alpha_recur.  x is consumed.
+template <typename T, bool TRANS>
+FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int NP,
+                            const typename Cplx<T>::type* cf, T sA, T cA, T (&xr)[4],
+                            T (&xi)[4], const T (&db)[4], typename Cplx<T>::type* lbuf,
+                            int& cur, T ch, T sh, T (&ar)[4], T (&ai)[4]) {
   const T cj = TRANS ? (T)-1 : (T)1;
-  T pr[MS][4], pi_[MS][4];  // alpha_{m-1}
+  T pr[4], pi_[4];  // alpha_{m-1}
   {
     const auto c0 = cf[0];
 #pragma unroll
-    for (int k = 0; k < MS; ++k)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        ar[k][m] = c0.x * xr[k][m] - cj * c0.y * xi[k][m];
-        ai[k][m] = c0.x * xi[k][m] + cj * c0.y * xr[k][m];
-        pr[k][m] = xr[k][m];
-        pi_[k][m] = xi[k][m];
-      }
+    for (int q = 0; q < 4; ++q) {
+      ar[q] = c0.x * xr[q] - cj * c0.y * xi[q];
+      ai[q] = c0.x * xi[q] + cj * c0.y * xr[q];
+      pr[q] = xr[q];
+      pi_[q] = xi[q];
+    }
   }
   for (int m = 1; m < NP; ++m) {
     // x <- (m == 1 ? A x : 2 A x - prev), with x = alpha_{m-1} on entry
-    T cr[MS][4], ci[MS][4];
+    T cr[4], ci[4];
 #pragma unroll
-    for (int k = 0; k < MS; ++k)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cr[k][q] = xr[k][q];
-        ci[k][q] = xi[k][q];
-      }
-    bbar_apply<T, NT, MS, TRANS>(g, nslot, xr, xi, db, lbuf, cur, ch, sh);
+    for (int q = 0; q < 4; ++q) {
+      cr[q] = xr[q];
+      ci[q] = xi[q];
+    }
+    bbar_apply<T, TRANS>(w, own, i0, iL, xr, xi, db, lbuf, N, cur, ch, sh);
     const T two = (m == 1) ? (T)1 : (T)2;
     const auto cm = cf[m];
 #pragma unroll
-    for (int k = 0; k < MS; ++k)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        T nr = two * (sA * xr[k][q] - cA * cr[k][q]);
-        T ni = two * (sA * xi[k][q] - cA * ci[k][q]);
-        if (m > 1) {
-          nr -= pr[k][q];
-          ni -= pi_[k][q];
-        }
-        pr[k][q] = cr[k][q];
-        pi_[k][q] = ci[k][q];
-        xr[k][q] = nr;
-        xi[k][q] = ni;
-        ar[k][q] += cm.x * nr - cj * cm.y * ni;
-        ai[k][q] += cm.x * ni + cj * cm.y * nr;
+    for (int q = 0; q < 4; ++q) {
+      T nr = two * (sA * xr[q] - cA * cr[q]);
+      T ni = two * (sA * xi[q] - cA * ci[q]);
+      if (m > 1) {
+        nr -= pr[q];
+        ni -= pi_[q];
       }
+      pr[q] = cr[q];
+      pi_[q] = ci[q];
+      xr[q] = nr;
+      xi[q] = ni;
+      ar[q] += cm.x * nr - cj * cm.y * ni;
+      ai[q] += cm.x * ni + cj * cm.y * nr;
+    }
   }
 }
 
 // Per-block Chebyshev apply.  op 0: F (series in A), 1: F^T (conjugate
 // series in A^T), 2: F F^T (conjugate series, then series).  Block b
 // serves frequency order b / nrhs (longest series first: k = 0, H-1, 1,
-// H-2, ...) and right-hand side b % nrhs.  LDS: two complex exchange
-// buffers (4 N values of T) and the block's Chebyshev coefficients.
-template <typename T, int NT, int MS>
+// H-2, ...) and right-hand side b % nrhs; one even plaquette per thread
+// (NT >= Q).  LDS: two complex exchange slices (4 N values of T) and the
+// block's Chebyshev coefficients.
+template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
 k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       const int* __restrict__ np, const typename Cplx<T>::type* __restrict__ coef,
@@ -553,8 +613,8 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
-  T* lbuf = reinterpret_cast<T*>(smem_raw);          // 2 buffers x (re, im) x N
-  T2* cfs = reinterpret_cast<T2*>(lbuf + 4 * g.N);   // coefficients of this block's frequency
+  T2* lbuf = reinterpret_cast<T2*>(smem_raw);    // 2 slices x N complex
+  T2* cfs = lbuf + 2 * g.N;                      // coefficients of this block's frequency
   int cur = 0;
   const int ko = blockIdx.x / nrhs;
   const int r = blockIdx.x % nrhs;
@@ -568,56 +628,44 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   const int k = (ko % 2 == 0) ? ko / 2 : H - 1 - ko / 2;
   const int NP = np[2 * k];
   for (int m = threadIdx.x; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
+  const T sA = (T)info->s, cA = (T)info->c;
+  const int q = threadIdx.x;
+  const bool own = q < g.Q;
+  const Win w = make_win(g, own ? q : 0);
+  const int i0 = w.x0 + w.row[1], iL = i0 + g.L;
+
+  T xr[4], xi[4], db[4], ar[4], ai[4];
+  const T2* Zin = Z + ((long)r * H + k) * g.N;
+  if (own) {
+    T2 a, b, c, d;
+    ld2c(Zin + i0, a, b);
+    ld2c(Zin + iL, c, d);
+    xr[0] = a.x; xi[0] = a.y; xr[1] = b.x; xi[1] = b.y;
+    xr[2] = c.x; xi[2] = c.y; xr[3] = d.x; xi[3] = d.y;
+    db[0] = dbar[i0]; db[1] = dbar[i0 + 1]; db[2] = dbar[iL]; db[3] = dbar[iL + 1];
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) xr[m] = xi[m] = db[m] = (T)0;
+  }
   __syncthreads();
   const T2* cf = cfs;
-  const T sA = (T)info->s, cA = (T)info->c;
-  const int nslot = (g.Q + NT - 1) / NT;
-
-  T xr[MS][4], xi[MS][4], db[MS][4], ar[MS][4], ai[MS][4];
-  const T2* Zin = Z + ((long)r * H + k) * g.N;
-#pragma unroll
-  for (int kk = 0; kk < MS; ++kk) {
-    const int q = threadIdx.x + kk * NT;
-    int s[4];
-    if (kk < nslot && q < g.Q) {
-      even_sites(g, q, s);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const T2 v = Zin[s[m]];
-        xr[kk][m] = v.x;
-        xi[kk][m] = v.y;
-        db[kk][m] = dbar[s[m]];
-      }
-    } else {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) xr[kk][m] = xi[kk][m] = db[kk][m] = (T)0;
-    }
-  }
   if (op == 0) {
-    cheb_series<T, NT, MS, false>(g, nslot, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
+    cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
   } else {
-    cheb_series<T, NT, MS, true>(g, nslot, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
+    cheb_series<T, true>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
     if (op == 2) {
 #pragma unroll
-      for (int kk = 0; kk < MS; ++kk)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          xr[kk][m] = ar[kk][m];
-          xi[kk][m] = ai[kk][m];
-        }
-      cheb_series<T, NT, MS, false>(g, nslot, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
+      for (int m = 0; m < 4; ++m) {
+        xr[m] = ar[m];
+        xi[m] = ai[m];
+      }
+      cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
     }
   }
-  T2* Zout = Zo + ((long)r * H + k) * g.N;
-#pragma unroll
-  for (int kk = 0; kk < MS; ++kk) {
-    const int q = threadIdx.x + kk * NT;
-    if (kk < nslot && q < g.Q) {
-      int s[4];
-      even_sites(g, q, s);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) Zout[s[m]] = T2{ar[kk][m], ai[kk][m]};
-    }
+  if (own) {
+    T2* Zout = Zo + ((long)r * H + k) * g.N;
+    st2c(Zout + i0, ar[0], ai[0], ar[1], ai[1]);
+    st2c(Zout + iL, ar[2], ai[2], ar[3], ai[3]);
   }
   if (io.in != nullptr) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
 }
@@ -669,24 +717,37 @@ inline hipError_t pc_set_field(PcTables* pc, const Geom& g, const double* dbar64
   return hipGetLastError();
 }
 
+// Tile width (log2) of the transforms: up to 64 bytes of a slice row,
+// halved while there are fewer than 512 workgroups.
+template <typename T>
+int pc_tile_log2(const Geom& g, int nrhs) {
+  int lks = (sizeof(T) == 8) ? 3 : 4;
+  while (lks > 1 && (long)((g.N + (1 << lks) - 1) >> lks) * nrhs < 512) --lks;
+  return lks;
+}
+
 template <typename T, int H1>
 hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
                          typename Cplx<T>::type* Z, T* u, const T* pa, const T* pb, const T* Ap,
                          StIO io, bool cgupd, hipStream_t s) {
-  constexpr int KS = Tile<T>::kS;
+  const int lks = pc_tile_log2<T>(g, nrhs);
+  const int KS = 1 << lks;
+  const int ntiles = (g.N + KS - 1) / KS;
   const size_t lds = (size_t)pc->H * (KS + 2) * sizeof(typename Cplx<T>::type) +
                      (size_t)g.Ltau * KS * sizeof(T);
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
-  dim3 grid((g.N + KS - 1) / KS, nrhs);
+  dim3 grid(ntiles * nrhs);
   if (cgupd) {
     auto kern = k_tfwd<T, H1, 256, true>;
     if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, io);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, lks,
+                       ntiles, io);
   } else {
     auto kern = k_tfwd<T, H1, 256, false>;
     if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, io);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, lks,
+                       ntiles, io);
   }
   return hipGetLastError();
 }
@@ -695,14 +756,16 @@ template <typename T, int H1>
 hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs,
                          const typename Cplx<T>::type* Zh, T* out, int dot, const T* rdot,
                          StIO io, hipStream_t s) {
-  constexpr int KS = Tile<T>::kS;
+  const int lks = pc_tile_log2<T>(g, nrhs);
+  const int KS = 1 << lks;
+  const int ntiles = (g.N + KS - 1) / KS;
   const size_t lds = (size_t)pc->H * (2 * KS + 2) * sizeof(typename Cplx<T>::type);
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
   auto kern = k_tinv<T, H1, 256>;
   if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(kern, dim3((g.N + KS - 1) / KS, nrhs), dim3(256), lds, s, g, pc->H2, tw, W, Zh, out,
-                     dot, rdot, io);
+  hipLaunchKernelGGL(kern, dim3(ntiles * nrhs), dim3(256), lds, s, g, pc->H2, tw, W, Zh, out,
+                     dot, rdot, lks, ntiles, io);
   return hipGetLastError();
 }
 
@@ -733,12 +796,12 @@ hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cp
   }
 }
 
-template <typename T, int NT, int MS>
+template <typename T, int NT>
 hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
                          StIO io, T ch, T sh, hipStream_t s) {
-  const size_t lds = 4 * (size_t)g.N * sizeof(T) + kNPMax * sizeof(typename Cplx<T>::type);
-  auto kern = k_kpm<T, NT, MS>;
+  const size_t lds = (2 * (size_t)g.N + kNPMax) * sizeof(typename Cplx<T>::type);
+  auto kern = k_kpm<T, NT>;
   if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const auto* cf = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->coef64 : (const void*)pc->coef32);
   hipLaunchKernelGGL(kern, dim3(pc->H * nrhs), dim3(NT), lds, s, g, pc->H, nrhs, op, pc->info,
@@ -750,10 +813,10 @@ template <typename T>
 hipError_t pc_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                   const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, StIO io,
                   T ch, T sh, hipStream_t s) {
-  if (g.Q <= 64) return pc_launch_kpm<T, 64, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
-  if (g.Q <= 256) return pc_launch_kpm<T, 256, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
-  if (g.Q <= 512) return pc_launch_kpm<T, 512, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
-  return pc_launch_kpm<T, 1024, 1>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  if (g.Q <= 64) return pc_launch_kpm<T, 64>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  if (g.Q <= 256) return pc_launch_kpm<T, 256>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  if (g.Q <= 512) return pc_launch_kpm<T, 512>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  return pc_launch_kpm<T, 1024>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
 }
 
 // Ping-pong bookkeeping of the CG state for a sequence of launches: each

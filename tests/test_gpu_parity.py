@@ -12,8 +12,8 @@ from oracle import force as OF
 from oracle import lattice as OL
 from oracle import precond as OP
 from oracle import solve as OS
-from workloads import (gaussian_rhs, get_config, perturbed_field, phonon_field,
-                       rademacher_rhs)
+from workloads import (fd_sample_indices, gaussian_rhs, get_config, perturbed_field,
+                       phonon_field, rademacher_rhs)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -426,3 +426,56 @@ def test_full_size_solve_and_force_against_oracle(key, prec):
     print(f"{key} {prec}: iters {st['iters']} eps {st['rel_resid']:.2e} kappa*eps {kappa * eps:.2e}"
           f" rel err u {rel_u:.2e} force {rel_g:.2e} S_F {dS / abs(ref['S_F']):.2e}")
     assert rel_u < 1e-8 and rel_g < 1e-8
+
+
+def test_force_central_differences_c5_100_sites():
+    """L = 64, Ltau = 400: the force kernel at 100 sampled components
+    against central finite differences of S_F.  Each difference uses two
+    GPU solves at x +- h e_k and the exact rank-1 action-change identity
+    (tests/_rank1.py, pinned on the CPU against direct differences), so no
+    two actions of size ~1e6 are subtracted.  FD truncation at h = 1e-4 is
+    ~h^2 (dtau alpha)^2 ~ 1e-10 relative; solves to 1e-11."""
+    from ._rank1 import action_change, c_row
+    p = get_config("c5")
+    lat = OL.Lattice.from_params(p)
+    x0 = phonon_field(p)
+    x = perturbed_field(p, x0)
+    phi = gaussian_rhs(p, 1)[0]
+    Cs = OL.sparse_C(lat).tocsr()
+    Phi = (OL.sparse_M(lat, x0, Cs).T @ phi.reshape(-1)).reshape(lat.Ltau, lat.N)
+    E = OL.E_field(lat, x)
+    comps = fd_sample_indices(p, 100)
+    s = make_solver(lat)
+    xg = tgpu(x)
+    Phig = tgpu(Phi)
+    s.set_field(xg)
+    u, st = s.solve(Phig, tol=1e-11, maxiter=200000)
+    assert st[0]["status"] & 1
+    idx = np.array(comps)
+    g = s.force(u).cpu().numpy()[idx[:, 0], idx[:, 1]]
+    uh = u.cpu().numpy().reshape(lat.Ltau, lat.N)
+    h = 1e-4
+    fd = []
+    un = torch.empty_like(u)
+    for tau, i in comps:
+        ds = []
+        for sgn in (1.0, -1.0):
+            xp = xg.clone()
+            xp.view(lat.Ltau, lat.N)[tau, i] += sgn * h
+            s.set_field(xp)
+            _, st = s.solve(Phig, u=un.copy_(u), tol=1e-11, maxiter=200000)
+            assert st[0]["status"] & 1
+            tp = tau - 1 if tau >= 1 else lat.Ltau - 1
+            part = np.zeros((lat.Ltau, lat.N))
+            unv = un.view(lat.Ltau, lat.N)
+            part[tau] = unv[tau].cpu().numpy()
+            part[tp] = unv[tp].cpu().numpy()
+            ds.append(action_change(lat, E, c_row(Cs, i), (tau, i), x[tau, i] + sgn * h, uh, part))
+        fd.append((ds[0] - ds[1]) / (2 * h))
+    fd = np.array(fd)
+    err = rel(g, fd)
+    print(f"c5 force vs central differences at 100 components: rel err {err:.2e}")
+    assert err < 1e-8
+    ref = _golden("c5")
+    assert [list(c) for c in comps] == ref["samples"]
+    assert rel(fd, np.array(ref["force_samples"])) < 1e-8
