@@ -136,6 +136,29 @@ struct StIO {
   const double* pin;   // pending partials, [rhs][kPStride]
   double* pout;        // partials written by this kernel
   int precond;         // preconditioned CG (z != r)
+  int nhint;           // partials the previous kernel in the sequence wrote
+                       // (loaded before the state arrives; a wrong hint only
+                       // costs a second load)
+};
+
+// Ping-pong bookkeeping of the CG state for a sequence of launches: each
+// state-aware kernel reads copy `cur`, writes copy `cur ^ 1`; `np` is the
+// number of partials per right-hand side the launch will write (0: none).
+struct StateSeq {
+  RhsState* st[2];
+  double* part[2];
+  int cur;
+  int precond;
+  bool active;  // false: plain operator calls without solver state
+  int np_prev;
+  StIO next(int np) {
+    if (!active) return StIO{nullptr, nullptr, nullptr, nullptr, precond, 0};
+    StIO io{st[cur], st[cur ^ 1], part[cur], part[cur ^ 1], precond, np_prev};
+    cur ^= 1;
+    np_prev = np;
+    return io;
+  }
+  RhsState* latest() const { return st[cur]; }
 };
 
 // Device constants of the preconditioner for the current field.
@@ -269,12 +292,26 @@ FPH_DEVINL void state_begin(const StIO& io, int r, RhsState* s_sh, double* red_s
   if (threadIdx.x < 64) {
     // The first wave reads the state and, if partials are pending, sums
     // them: lane l adds partials l, l + 64, ... in order, then a fixed
-    // butterfly across the wave (same order in every block).
+    // butterfly across the wave (same order in every block).  The partials
+    // announced by the hint are loaded together with the state.
+    constexpr int kSpec = 16;
+    const double* part = io.pin + (long)r * kPStride;
+    double pre[kSpec];
+#pragma unroll
+    for (int j = 0; j < kSpec; ++j) {
+      const int k = threadIdx.x + 64 * j;
+      pre[j] = (k < io.nhint) ? part[k] : 0.0;
+    }
     const RhsState st = io.in[r];
     if (st.pend != P_NONE) {
-      const double* part = io.pin + (long)r * kPStride;
       double v = 0.0, v2 = 0.0;
-      for (int k = threadIdx.x; k < st.npart; k += 64) v += part[k];
+      if (st.npart <= io.nhint && st.npart <= 64 * kSpec) {
+#pragma unroll
+        for (int j = 0; j < kSpec; ++j)
+          if (threadIdx.x + 64 * j < st.npart) v += pre[j];
+      } else {
+        for (int k = threadIdx.x; k < st.npart; k += 64) v += part[k];
+      }
       if (st.pend == P_GD)
         for (int k = threadIdx.x; k < st.npart; k += 64) v2 += part[kPHalf + k];
 #pragma unroll

@@ -82,11 +82,13 @@ int elem_blocks(long d) {
 
 template <typename T, int NT, int MS, class In, class Epi>
 hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi epi,
-                          StIO io, hipStream_t s) {
+                          StateSeq* sq, hipStream_t s) {
   const Geom& g = h->g;
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
   const int nchunks = (g.Ltau + Tch - 1) / Tch;
   const int nblk = (nchunks + S - 1) / S;
+  const StIO io = sq ? sq->next(Epi::kKind != P_NONE ? nblk : 0)
+                     : StIO{nullptr, nullptr, nullptr, nullptr, 0, 0};
   const size_t lds = 4 * (size_t)S * g.N * sizeof(T);
   auto kern = k_mtm<T, NT, MS, In, Epi>;
   if (lds > 48 * 1024) {
@@ -115,17 +117,20 @@ int pick_chunk(const fph_handle_s* h, int nrhs, int NT) {
   return best;
 }
 
+// Fused operator launch; with sq the kernel takes part in the solver's
+// state sequence (sq == nullptr: plain operator call).
 template <typename T, class In, class Epi>
-hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, StIO io, hipStream_t s) {
+hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, StateSeq* sq,
+                      hipStream_t s) {
   // One plaquette per thread; up to 1024 plaquettes (L <= 64) per slice.
   const int Q = h->g.Q;
-  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, pick_chunk(h, nrhs, 64), in, epi, io, s);
-  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, io, s);
-  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, pick_chunk(h, nrhs, 512), in, epi, io, s);
-  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, pick_chunk(h, nrhs, 1024), in, epi, io, s);
+  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, pick_chunk(h, nrhs, 64), in, epi, sq, s);
+  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, sq, s);
+  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, pick_chunk(h, nrhs, 512), in, epi, sq, s);
+  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, pick_chunk(h, nrhs, 1024), in, epi, sq, s);
 }
 
-StIO no_state() { return StIO{nullptr, nullptr, nullptr, nullptr, 0}; }
+StIO no_state() { return StIO{nullptr, nullptr, nullptr, nullptr, 0, 0}; }
 
 template <typename T, int NT, int MS, int MODE>
 hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, double coef,
@@ -326,13 +331,13 @@ int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, const
     double* out = (double*)out_dev;
     if (op == FPH_OP_M) e = launch_M<double, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<double>(h, nrhs, in, out, s);
-    else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, no_state(), s);
+    else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, nullptr, s);
   } else {
     const float* in = (const float*)in_dev;
     float* out = (float*)out_dev;
     if (op == FPH_OP_M) e = launch_M<float, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<float>(h, nrhs, in, out, s);
-    else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, no_state(), s);
+    else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, nullptr, s);
   }
   if (e != hipSuccess) return fail_hip(e);
   return FPH_OK;
@@ -373,7 +378,7 @@ int fph_precond_apply(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, co
   if (op < 0 || op > 2 || (prec != FPH_F64 && prec != FPH_F32)) return FPH_E_PREC;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  StateSeq sq{{nullptr, nullptr}, {nullptr, nullptr}, 0, 0, false};
+  StateSeq sq{{nullptr, nullptr}, {nullptr, nullptr}, 0, 0, false, 0};
   if (prec == FPH_F64)
     e = pc_apply<double>(&h->pc, h->g, h->dbar64, op, nrhs, (const double*)in_dev,
                          (double*)out_dev, nullptr, sq, s);
@@ -414,11 +419,11 @@ hipError_t cg_iteration(fph_handle_s* h, int nrhs, bool precond, T* u, T* r, T* 
   const long d = h->g.d;
   const T* zz = precond ? z : r;
   InPUpdate<T> in{zz, pa, pb, nullptr, nullptr, (T)0, 0};
-  hipError_t e = launch_mtm<T>(h, nrhs, in, EpiDot<T>{Ap}, sq.next(), s);
+  hipError_t e = launch_mtm<T>(h, nrhs, in, EpiDot<T>{Ap}, &sq, s);
   if (e != hipSuccess) return e;
   if (!precond) {
     hipLaunchKernelGGL(k_cg_update<T>, dim3(elem_blocks(d), nrhs), dim3(256), 0, s, d, u,
-                       (const T*)pa, (const T*)pb, r, (const T*)Ap, sq.next());
+                       (const T*)pa, (const T*)pb, r, (const T*)Ap, sq.next(elem_blocks(d)));
     e = hipGetLastError();
   } else {
     e = pc_cg_update<T>(&h->pc, h->g, dbar, nrhs, u, pa, pb, r, Ap, z, sq, s);
@@ -448,7 +453,7 @@ template <typename T>
 hipError_t cgcg_start(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq, hipStream_t s) {
   InParity<T> in{w.r, w.rb, nullptr};
   EpiGD<T> epi{w.Ap, w.wb, 0, nullptr};
-  return launch_mtm<T>(h, nrhs, in, epi, sq.next(), s);
+  return launch_mtm<T>(h, nrhs, in, epi, &sq, s);
 }
 
 // One single-reduction CG iteration (one launch).
@@ -458,12 +463,12 @@ hipError_t cgcg_iteration(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq&
   InCGCG<T> in{w.r, w.rb, w.z, w.sb, w.pa, w.pb, w.Ap, w.wb, w.u,
                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (T)0, (T)0, 0};
   EpiGD<T> epi{w.Ap, w.wb, 1, nullptr};
-  return launch_mtm<T>(h, nrhs, in, epi, sq.next(), s);
+  return launch_mtm<T>(h, nrhs, in, epi, &sq, s);
 }
 
 // Fold pending partials, copy the state to the host and wait.
 hipError_t sync_state(fph_handle_s* h, int nrhs, StateSeq& sq, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(nrhs), dim3(256), 0, s, sq.next());
+  hipLaunchKernelGGL(k_advance, dim3(nrhs), dim3(256), 0, s, sq.next(0));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(h->st_host, sq.latest(), nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, s);
@@ -487,11 +492,11 @@ hipError_t fp64_residual(fph_handle_s* h, int nrhs, bool pre, bool cgcg, int par
                          hipStream_t s) {
   const long d = h->g.d;
   TR* r = (cgcg && par == 1) ? w.rb : w.r;
-  hipError_t e = launch_mtm<double>(h, nrhs, InPlain<double>{u}, EpiResidual<TR>{b, r}, sq.next(), s);
+  hipError_t e = launch_mtm<double>(h, nrhs, InPlain<double>{u}, EpiResidual<TR>{b, r}, &sq, s);
   if (e != hipSuccess) return e;
   if (cgcg) return cgcg_start<TR>(h, nrhs, w, sq, s);
   hipLaunchKernelGGL(k_norm2<TR>, dim3(elem_blocks(d), nrhs), dim3(256), 0, s, d, (const TR*)r,
-                     sq.next(), (int)P_NRM);
+                     sq.next(elem_blocks(d)), (int)P_NRM);
   e = hipGetLastError();
   if (e != hipSuccess || !pre) return e;
   return pc_apply<TR>(&h->pc, h->g, w.dbar, FPH_PC_FFT, nrhs, r, w.z, r, sq, s);
@@ -515,7 +520,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
   // Single-reduction CG only without preconditioner and when asked for.
   const bool cgcg = !pre && opts->variant == 1;
-  StateSeq sq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true};
+  StateSeq sq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true, 0};
 
   // Initial state, then |b|^2 (P_BB) and the first residual.
   for (int r = 0; r < nrhs; ++r) {
@@ -526,7 +531,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
     st.fresh = 1;
   }
   FPH_CHECK(push_state(h, nrhs, sq, s));
-  hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, b_dev, sq.next(),
+  hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, b_dev, sq.next(nb),
                      (int)P_BB);
   FPH_CHECK(hipGetLastError());
   if (opts->zero_guess) FPH_CHECK(hipMemsetAsync(u_dev, 0, nrhs * d * sizeof(double), s));
@@ -551,7 +556,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
         FPH_CHECK(cgcg_start<float>(h, nrhs, w32, sq, s));
       } else {
         hipLaunchKernelGGL(k_norm2<float>, dim3(nb, nrhs), dim3(256), 0, s, d, (const float*)w32.r,
-                           sq.next(), (int)P_NRM);
+                           sq.next(elem_blocks(d)), (int)P_NRM);
         FPH_CHECK(hipGetLastError());
         if (pre)
           FPH_CHECK(pc_apply<float>(&h->pc, h->g, w32.dbar, FPH_PC_FFT, nrhs, w32.r, w32.z, w32.r, sq, s));

@@ -729,10 +729,11 @@ int pc_tile_log2(const Geom& g, int nrhs) {
 template <typename T, int H1>
 hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
                          typename Cplx<T>::type* Z, T* u, const T* pa, const T* pb, const T* Ap,
-                         StIO io, bool cgupd, hipStream_t s) {
+                         StateSeq& sq, bool cgupd, hipStream_t s) {
   const int lks = pc_tile_log2<T>(g, nrhs);
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
+  const StIO io = sq.next(cgupd ? ntiles : 0);
   const size_t lds = (size_t)pc->H * (KS + 2) * sizeof(typename Cplx<T>::type) +
                      (size_t)g.Ltau * KS * sizeof(T);
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
@@ -755,10 +756,11 @@ hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
 template <typename T, int H1>
 hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs,
                          const typename Cplx<T>::type* Zh, T* out, int dot, const T* rdot,
-                         StIO io, hipStream_t s) {
+                         StateSeq& sq, hipStream_t s) {
   const int lks = pc_tile_log2<T>(g, nrhs);
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
+  const StIO io = sq.next(dot ? ntiles : 0);
   const size_t lds = (size_t)pc->H * (2 * KS + 2) * sizeof(typename Cplx<T>::type);
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
@@ -771,11 +773,11 @@ hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs,
 
 template <typename T>
 hipError_t pc_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in, typename Cplx<T>::type* Z,
-                  T* u, const T* pa, const T* pb, const T* Ap, StIO io, bool cgupd,
+                  T* u, const T* pa, const T* pb, const T* Ap, StateSeq& sq, bool cgupd,
                   hipStream_t s) {
   switch (pc->H1) {
 #define FPH_FWD_CASE(h1) \
-  case h1: return pc_launch_fwd<T, h1>(pc, g, nrhs, in, Z, u, pa, pb, Ap, io, cgupd, s);
+  case h1: return pc_launch_fwd<T, h1>(pc, g, nrhs, in, Z, u, pa, pb, Ap, sq, cgupd, s);
     FPH_FWD_CASE(1) FPH_FWD_CASE(2) FPH_FWD_CASE(3) FPH_FWD_CASE(4) FPH_FWD_CASE(5)
     FPH_FWD_CASE(8) FPH_FWD_CASE(10) FPH_FWD_CASE(16) FPH_FWD_CASE(20)
 #undef FPH_FWD_CASE
@@ -785,10 +787,10 @@ hipError_t pc_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in, typename C
 
 template <typename T>
 hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cplx<T>::type* Zh,
-                  T* out, int dot, const T* rdot, StIO io, hipStream_t s) {
+                  T* out, int dot, const T* rdot, StateSeq& sq, hipStream_t s) {
   switch (pc->H1) {
 #define FPH_INV_CASE(h1) \
-  case h1: return pc_launch_inv<T, h1>(pc, g, nrhs, Zh, out, dot, rdot, io, s);
+  case h1: return pc_launch_inv<T, h1>(pc, g, nrhs, Zh, out, dot, rdot, sq, s);
     FPH_INV_CASE(1) FPH_INV_CASE(2) FPH_INV_CASE(3) FPH_INV_CASE(4) FPH_INV_CASE(5)
     FPH_INV_CASE(8) FPH_INV_CASE(10) FPH_INV_CASE(16) FPH_INV_CASE(20)
 #undef FPH_INV_CASE
@@ -799,7 +801,8 @@ hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cp
 template <typename T, int NT>
 hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
-                         StIO io, T ch, T sh, hipStream_t s) {
+                         StateSeq& sq, T ch, T sh, hipStream_t s) {
+  const StIO io = sq.next(0);
   const size_t lds = (2 * (size_t)g.N + kNPMax) * sizeof(typename Cplx<T>::type);
   auto kern = k_kpm<T, NT>;
   if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -811,30 +814,13 @@ hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int o
 
 template <typename T>
 hipError_t pc_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
-                  const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, StIO io,
+                  const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, StateSeq& sq,
                   T ch, T sh, hipStream_t s) {
-  if (g.Q <= 64) return pc_launch_kpm<T, 64>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
-  if (g.Q <= 256) return pc_launch_kpm<T, 256>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
-  if (g.Q <= 512) return pc_launch_kpm<T, 512>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
-  return pc_launch_kpm<T, 1024>(pc, g, dbar, op, nrhs, Z, Zo, io, ch, sh, s);
+  if (g.Q <= 64) return pc_launch_kpm<T, 64>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
+  if (g.Q <= 256) return pc_launch_kpm<T, 256>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
+  if (g.Q <= 512) return pc_launch_kpm<T, 512>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
+  return pc_launch_kpm<T, 1024>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
 }
-
-// Ping-pong bookkeeping of the CG state for a sequence of launches: each
-// state-aware kernel reads copy `cur`, writes copy `cur ^ 1`.
-struct StateSeq {
-  RhsState* st[2];
-  double* part[2];
-  int cur;
-  int precond;
-  bool active;  // false: plain operator calls without solver state
-  StIO next() {
-    if (!active) return StIO{nullptr, nullptr, nullptr, nullptr, precond};
-    StIO io{st[cur], st[cur ^ 1], part[cur], part[cur ^ 1], precond};
-    cur ^= 1;
-    return io;
-  }
-  RhsState* latest() const { return st[cur]; }
-};
 
 // out = op(in) (op: 0 F, 1 F^T, 2 F F^T).  With rdot != nullptr the inverse
 // transform also publishes rdot . out as P_RZ partials.
@@ -845,11 +831,11 @@ hipError_t pc_apply(const PcTables* pc, const Geom& g, const T* dbar, int op, in
   T2* Z = reinterpret_cast<T2*>(pc->Z);
   T2* Z2 = reinterpret_cast<T2*>(pc->Z2);
   hipError_t e = pc_fwd<T>(pc, g, nrhs, const_cast<T*>(in), Z, nullptr, nullptr, nullptr,
-                           nullptr, sq.next(), false, s);
+                           nullptr, sq, false, s);
   if (e != hipSuccess) return e;
-  e = pc_kpm<T>(pc, g, dbar, op, nrhs, Z, Z2, sq.next(), (T)pc->ch, (T)pc->sh, s);
+  e = pc_kpm<T>(pc, g, dbar, op, nrhs, Z, Z2, sq, (T)pc->ch, (T)pc->sh, s);
   if (e != hipSuccess) return e;
-  return pc_inv<T>(pc, g, nrhs, Z2, out, rdot ? 1 : 0, rdot, sq.next(), s);
+  return pc_inv<T>(pc, g, nrhs, Z2, out, rdot ? 1 : 0, rdot, sq, s);
 }
 
 // Preconditioned CG update: u += alpha p, r -= alpha Ap (|r|^2 as P_RR),
@@ -862,11 +848,11 @@ hipError_t pc_cg_update(const PcTables* pc, const Geom& g, const T* dbar, int nr
   using T2 = typename Cplx<T>::type;
   T2* Z = reinterpret_cast<T2*>(pc->Z);
   T2* Z2 = reinterpret_cast<T2*>(pc->Z2);
-  hipError_t e = pc_fwd<T>(pc, g, nrhs, r, Z, u, pa, pb, Ap, sq.next(), true, s);
+  hipError_t e = pc_fwd<T>(pc, g, nrhs, r, Z, u, pa, pb, Ap, sq, true, s);
   if (e != hipSuccess) return e;
-  e = pc_kpm<T>(pc, g, dbar, 2, nrhs, Z, Z2, sq.next(), (T)pc->ch, (T)pc->sh, s);
+  e = pc_kpm<T>(pc, g, dbar, 2, nrhs, Z, Z2, sq, (T)pc->ch, (T)pc->sh, s);
   if (e != hipSuccess) return e;
-  return pc_inv<T>(pc, g, nrhs, Z2, z, 1, r, sq.next(), s);
+  return pc_inv<T>(pc, g, nrhs, Z2, z, 1, r, sq, s);
 }
 
 }  // namespace fph
