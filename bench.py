@@ -3,15 +3,16 @@
 
 One step = one pass of the hot path over the workload: per-field setup
 (E, dbar, preconditioner bounds and Chebyshev tables), the FP32-refined CG
-solve of (M^T M) u = Phi to relative residual 1e-8 (plain CG by default:
-on this synthetic field the adiabatic preconditioner cuts iterations ~7x
-but costs more per iteration; one preconditioned step is timed and
-reported beside it), the action S_F = Phi . u and the phonon force dS_F/dx.  Default workload: L = 32 (N = 1024), Ltau = 400
-(d = 409600), dtau = 0.05, mu = -0.2, alpha = 1.2, AR(1)-correlated field.
+solve of (M^T M) u = Phi to relative residual 1e-8, the action
+S_F = Phi . u and the phonon force dS_F/dx.  Default workload: L = 32
+(N = 1024), Ltau = 400 (d = 409600), dtau = 0.05, mu = -0.2, alpha = 1.2,
+AR(1)-correlated field; plain CG by default (--precond 1 times the
+preconditioned step instead).
 
-Prints one JSON line.  Besides the headline (FP32-refined solves/s) it
-reports the same step with plain FP64 CG, the M^T M matvec bandwidth with
-its HBM roofline fraction (HIP events on the stream the kernel runs on),
+Prints one JSON line: the headline (FP32-refined solves/s), the same step
+with FP64 CG, one step of every solver variant, the fused M^T M roofline
+(HIP events on the stream the kernel runs on) on a working set above the
+Infinity Cache and at the workload shape, the batched persistent solve,
 and the CPU oracle timed on a bounded sample.
 """
 
@@ -47,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the one-step timing of every solver variant")
     ap.add_argument("--profile-roofline", action="store_true",
                     help="only the roofline kernel (M^T M, FP32, L=64 Ltau=400 x 32 rhs) and a "
                          "plain copy of the same byte count, for hardware-counter runs")
@@ -65,20 +68,34 @@ def time_steps(step, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps, out
 
 
-def event_time_matvec(solver, v, op, reps, torch):
-    """Average duration (s) of back-to-back applies, HIP events on the stream used."""
+def event_time_matvec(solver, v, op, reps, torch, isolated=False):
+    """Average duration (s) of one apply, HIP events on the stream the
+    kernel runs on.  isolated=False: back-to-back launches (includes the
+    gaps between kernels); True: each launch bracketed by its own events
+    and waited for (the kernel's own duration, as a kernel trace reports)."""
     out = torch.empty_like(v)
     for _ in range(5):
         solver.matvec(v, op, out=out)
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    if not isolated:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            solver.matvec(v, op, out=out)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+    tot = 0.0
     for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         solver.matvec(v, op, out=out)
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
+        e1.record(stream)
+        e1.synchronize()
+        tot += e0.elapsed_time(e1) / 1e3
+    return tot / reps
 
 
 def bench_batched(torch, dev, log):
@@ -260,23 +277,33 @@ def main():
     tol = 1e-8
     last = {}
 
-    def make_step(prec, pre):
+    def make_step(prec, pre, variant=0):
         def step():
             s.set_field(x)                                   # setup
-            u, st = s.solve(Phi, tol=tol, prec=prec, precond=pre)   # PCG
+            u, st = s.solve(Phi, tol=tol, prec=prec, precond=pre, variant=variant)   # PCG
             S = s.action(Phi, u)                             # S_F
             g = s.force(u)                                   # dS_F/dx
             last["st"], last["S"], last["g"] = st, S, g
             return st
         return step
 
-    # One step each with and without the preconditioner (FP32-refined).
-    trial = {}
-    for pre in (False, True):
-        t, st = time_steps(make_step("f32_refined", pre), 1, 0, torch)
-        trial[pre] = (t, st[0]["iters"])
-        log(f"trial precond={pre}: {t * 1e3:.1f} ms, {st[0]['iters']} iterations, status {st[0]['status']}")
-    pre = min(trial, key=lambda k: trial[k][0]) if args.precond < 0 else bool(args.precond)
+    # One step of each solver variant: FP32-refined and FP64, with and
+    # without the preconditioner, and FP64 single-reduction CG.
+    variants = {}
+    all_variants = (("f32_refined_plain", "f32_refined", False, 0),
+                    ("f32_refined_precond", "f32_refined", True, 0),
+                    ("f64_plain", "f64", False, 0),
+                    ("f64_plain_single_reduction", "f64", False, 1),
+                    ("f64_precond", "f64", True, 0))
+    for name, prec, pre_v, var in (() if args.no_variants else all_variants):
+        t, st = time_steps(make_step(prec, pre_v, var), 1, 0, torch)
+        variants[name] = {"ms": t * 1e3, "iters": st[0]["iters"], "status": st[0]["status"],
+                          "rel_resid": st[0]["rel_resid"]}
+        log(f"variant {name}: {t * 1e3:.1f} ms, {st[0]['iters']} iterations, status {st[0]['status']}")
+    if args.precond < 0 and variants:
+        pre = variants["f32_refined_precond"]["ms"] < variants["f32_refined_plain"]["ms"]
+    else:
+        pre = args.precond > 0
 
     t32, st32 = time_steps(make_step("f32_refined", pre), args.steps, args.warmup, torch)
     st32 = [dict(v) for v in st32]
@@ -304,19 +331,23 @@ def main():
     if not args.no_large:
         # Same kernel on a working set far above the 256 MB Infinity Cache.
         p5, R5, s5, vl = large_matvec_setup(torch, dev)
-        tl64 = event_time_matvec(s5, vl, "MTM", 20, torch)
-        tl32 = event_time_matvec(s5, vl.float(), "MTM", 20, torch)
+        tl64 = event_time_matvec(s5, vl, "MTM", 20, torch, isolated=True)
+        vl32 = vl.float()
+        tl32 = event_time_matvec(s5, vl32, "MTM", 20, torch, isolated=True)
+        tl32_b2b = event_time_matvec(s5, vl32, "MTM", 20, torch)
         bl64 = (2 * R5 + 1) * p5.dim * 8
         bl32 = (2 * R5 + 1) * p5.dim * 4
         large = {
             "workload": f"{p5.name} x {R5} rhs sharing one field",
             "working_set_MB": {"f64": bl64 / 1e6, "f32": bl32 / 1e6},
             "f64": {"us": tl64 * 1e6, "GB/s": bl64 / tl64 / 1e9, "frac": bl64 / tl64 / 1e9 / HBM_PEAK_GBS},
-            "f32": {"us": tl32 * 1e6, "GB/s": bl32 / tl32 / 1e9, "frac": bl32 / tl32 / 1e9 / HBM_PEAK_GBS},
+            "f32": {"us": tl32 * 1e6, "GB/s": bl32 / tl32 / 1e9, "frac": bl32 / tl32 / 1e9 / HBM_PEAK_GBS,
+                    "back_to_back_us": tl32_b2b * 1e6,
+                    "back_to_back_GB/s": bl32 / tl32_b2b / 1e9},
         }
         log(f"large: {large}")
         s5.close()
-        del vl
+        del vl, vl32
 
     batch = None
     if not args.no_batch:
@@ -380,8 +411,7 @@ def main():
                     "bytes_per_launch": bytes64}},
         "matvec_large": large,
         "batched": batch,
-        "precond_trial": {("precond" if k else "plain"): {"ms": v[0] * 1e3, "iters": v[1]}
-                          for k, v in trial.items()},
+        "variants": variants,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -21,9 +21,31 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #define FPH_DEVINL __device__ __forceinline__
 
 namespace fph {
+
+// Dynamic LDS above 48 KB needs a per-kernel opt-in.  The limit set for
+// each (device, kernel) is remembered, so the launch path makes the runtime
+// call only when a launch needs more than any earlier one.
+inline hipError_t allow_lds(const void* kern, size_t bytes) {
+  if (bytes <= 48 * 1024) return hipSuccess;
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> granted;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t& have = granted[{dev, kern}];
+  if (have >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) have = bytes;
+  return e;
+}
 
 // ----------------------------------------------------------------- geometry
 

@@ -91,9 +91,8 @@ hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi e
                      : StIO{nullptr, nullptr, nullptr, nullptr, 0, 0};
   const size_t lds = 4 * (size_t)S * g.N * sizeof(T);
   auto kern = k_mtm<T, NT, MS, In, Epi>;
-  if (lds > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g,
@@ -140,9 +139,8 @@ hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, dou
   const int nblk = (g.Ltau + S - 1) / S;
   const size_t lds = (size_t)S * g.N * sizeof(T);
   auto kern = k_apply_M<T, NT, MS, MODE>;
-  if (lds > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
   }
   const T* E = (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32);
@@ -168,9 +166,8 @@ hipError_t launch_MT_cfg(const fph_handle_s* h, int nrhs, const T* w, T* out, hi
   const int nblk = (g.Ltau + S - 1) / S;
   const size_t lds = (size_t)S * g.N * sizeof(T);
   auto kern = k_apply_MT<T, NT, MS>;
-  if (lds > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
   }
   const T* E = (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32);
@@ -517,7 +514,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   const int nb = elem_blocks(d);
   const bool pre = opts->use_precond != 0;
   const bool mixed = opts->prec == FPH_F32_REFINED;
-  const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
+  const double delta0 = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3;
   // Single-reduction CG only without preconditioner and when asked for.
   const bool cgcg = !pre && opts->variant == 1;
   StateSeq sq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true, 0};
@@ -571,6 +568,13 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   std::vector<int> outer(nrhs, 0);
   std::vector<int> iter_at_ru(nrhs, 0);
   std::vector<double> rr_iter(nrhs, 0.0);
+  // FP32 residual-replacement interval per right-hand side: replace when
+  // the FP32 residual has fallen by delta since the last replacement.
+  // FP32 CG loses accuracy relative to its starting residual at a rate set
+  // by kappa * eps_32; when a replacement finds the true residual more than
+  // twice the iterated one, the interval is shortened (delta -> sqrt delta,
+  // at most 0.5).
+  std::vector<double> delta(nrhs, delta0);
   for (int r = 0; r < nrhs; ++r) {
     RhsState& st = h->st_host[r];
     if (st.bb == 0.0) {  // b = 0: u = 0 exactly
@@ -582,7 +586,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
       final_[r] = 1;
       st.done = 1;
     }
-    if (mixed && !st.done) st.ru_thresh = delta * delta * st.rr;
+    if (mixed && !st.done) st.ru_thresh = delta[r] * delta[r] * st.rr;
   }
   FPH_CHECK(push_state(h, nrhs, sq, s));
 
@@ -677,7 +681,8 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
         // them (reliable update) unless the replaced residual is far from
         // the iterated one.
         if (!mixed || st.rr > 100.0 * rr_iter[r]) st.fresh = 1;
-        st.ru_thresh = mixed ? delta * delta * st.rr : 0.0;
+        if (mixed && st.rr > 4.0 * rr_iter[r]) delta[r] = std::min(0.5, std::sqrt(delta[r]));
+        st.ru_thresh = mixed ? delta[r] * delta[r] * st.rr : 0.0;
       }
     }
     FPH_CHECK(push_state(h, nrhs, sq, s));
@@ -740,9 +745,8 @@ hipError_t batch_launch(fph_batch_s* b, double tol, int maxiter, double delta, h
   }
   const size_t lds = 4 * (size_t)sn * sizeof(double);
   auto kern = k_batch_solve<NT, MS>;
-  if (lds > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
   }
   const int grid = std::max(1, std::min(b->nitems, b->num_cu * b->per_cu));
@@ -915,7 +919,7 @@ int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* 
   if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
   if (opts->use_precond != 0 || !(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
+  const double delta = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3;
   if (!b->have_graph || b->g_tol != opts->tol || b->g_maxiter != opts->maxiter ||
       b->g_delta != delta)
     FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
@@ -942,7 +946,7 @@ int fph_batch_tune(fph_batch_t b, const fph_pcg_opts_t* opts, int32_t* best, voi
   if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
   if (opts->use_precond != 0 || !(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  const double delta = opts->ru_delta > 0.0 ? opts->ru_delta : 0.1;
+  const double delta = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3;
   struct Cfg { int nt, ms, per_cu; };
   std::vector<Cfg> cands;
   for (int pc : {1, 2, 4}) {

@@ -741,12 +741,14 @@ hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
   dim3 grid(ntiles * nrhs);
   if (cgupd) {
     auto kern = k_tfwd<T, H1, 256, true>;
-    if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, lks,
                        ntiles, io);
   } else {
     auto kern = k_tfwd<T, H1, 256, false>;
-    if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, lks,
                        ntiles, io);
   }
@@ -765,7 +767,8 @@ hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs,
   const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
   auto kern = k_tinv<T, H1, 256>;
-  if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_lds((const void*)kern, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(ntiles * nrhs), dim3(256), lds, s, g, pc->H2, tw, W, Zh, out,
                      dot, rdot, lks, ntiles, io);
   return hipGetLastError();
@@ -805,7 +808,8 @@ hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int o
   const StIO io = sq.next(0);
   const size_t lds = (2 * (size_t)g.N + kNPMax) * sizeof(typename Cplx<T>::type);
   auto kern = k_kpm<T, NT>;
-  if (lds > 48 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_lds((const void*)kern, lds);
+  if (e != hipSuccess) return e;
   const auto* cf = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->coef64 : (const void*)pc->coef32);
   hipLaunchKernelGGL(kern, dim3(pc->H * nrhs), dim3(NT), lds, s, g, pc->H, nrhs, op, pc->info,
                      pc->np, cf, dbar, ch, sh, Z, Zo, io);

@@ -98,7 +98,7 @@ class FermionSolver:
         return (b[0], b[1]), list(npt)
 
     def solve(self, b, u=None, tol=1e-10, maxiter=100000, precond=False, prec="f64",
-              ru_delta=0.1, chunk=0, variant=0):
+              ru_delta=0.0, chunk=0, variant=0):
         """Solve (M^T M) u = b for every right-hand side of b (float64).
         Returns (u, [stats dict per rhs]).  Blocks until done."""
         nrhs = self._vec(b)
@@ -164,13 +164,13 @@ class FermionBatch:
     def _opts(self, tol, maxiter, ru_delta):
         return PcgOpts(float(tol), int(maxiter), 0, FPH_F32_REFINED, 1, float(ru_delta), 0, 0)
 
-    def solve(self, tol=1e-8, maxiter=100000, ru_delta=0.1):
+    def solve(self, tol=1e-8, maxiter=100000, ru_delta=0.0):
         stats = (PcgStats * self.nrhs_total)()
         opts = self._opts(tol, maxiter, ru_delta)
         check(self.lib.fph_batch_solve(self.h, ctypes.byref(opts), stats, _stream()))
         return [s.as_dict() for s in stats]
 
-    def tune(self, tol=1e-8, maxiter=100000, ru_delta=0.1):
+    def tune(self, tol=1e-8, maxiter=100000, ru_delta=0.0):
         best = (ctypes.c_int32 * 3)()
         opts = self._opts(tol, maxiter, ru_delta)
         check(self.lib.fph_batch_tune(self.h, ctypes.byref(opts), best, _stream()))
