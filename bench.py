@@ -368,7 +368,7 @@ def main():
             traffic = TRAFFIC["bytes_per_launch"]
         roofline = {"bound": "hbm", "achieved": large["f32"]["GB/s"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": large["f32"]["frac"], "traffic": traffic,
-                    "kernel": "fused M^T M apply, FP32 (k_mtm<float, 1024, 1, InPlain, EpiStore>)",
+                    "kernel": "fused M^T M apply, FP32 (k_mtm<float, 1024, 1, InPlain, EpiStream>)",
                     "workload": large["workload"],
                     "bytes_per_launch": large["working_set_MB"]["f32"] * 1e6,
                     "avg_launch_us": large["f32"]["us"]}

@@ -9,6 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/holstein_hmc.h"
@@ -80,40 +83,67 @@ int elem_blocks(long d) {
 
 // ------------------------------------------------ operator launch helpers
 
+// Workgroups of `kern` resident per CU with `lds` bytes of dynamic LDS,
+// times the CU count (cached per device, kernel and LDS size).
+inline int resident_slots(const void* kern, int nt, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(dev, kern, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  const int slots = std::max(1, per_cu) * std::max(1, ncu);
+  cache[key] = slots;
+  return slots;
+}
+
+// Slices per chunk of the fused operator.  A chunk costs about Tch + 1
+// slice steps plus a start-up of ~2; the launch runs in ceil(blocks /
+// slots) rounds of resident workgroups.  Pick the chunk length with the
+// least rounds x steps (short chunks for small problems: one round of
+// one-slice chunks; for large ones exactly enough chunks to fill the
+// resident slots, which also keeps halo re-reads low).
+int pick_chunk(const Geom& g, int nrhs, int S, int slots) {
+  int best = 1;
+  long best_cost = -1;
+  for (int T = 1; T <= std::min(g.Ltau, 64); ++T) {
+    const long nblk = (long)(((g.Ltau + T - 1) / T + S - 1) / S) * nrhs;
+    const long rounds = (nblk + slots - 1) / slots;
+    const long cost = rounds * (T + 3);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = T;
+    }
+  }
+  return best;
+}
+
 template <typename T, int NT, int MS, class In, class Epi>
-hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, int Tch, In in, Epi epi,
-                          StateSeq* sq, hipStream_t s) {
+hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, In in, Epi epi, StateSeq* sq,
+                          hipStream_t s) {
   const Geom& g = h->g;
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
-  const int nchunks = (g.Ltau + Tch - 1) / Tch;
-  const int nblk = (nchunks + S - 1) / S;
-  const StIO io = sq ? sq->next(Epi::kKind != P_NONE ? nblk : 0)
-                     : StIO{nullptr, nullptr, nullptr, nullptr, 0, 0};
   const size_t lds = 4 * (size_t)S * g.N * sizeof(T);
   auto kern = k_mtm<T, NT, MS, In, Epi>;
   {
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
   }
+  const int Tch = pick_chunk(g, nrhs, S, resident_slots((const void*)kern, NT, lds));
+  const int nchunks = (g.Ltau + Tch - 1) / Tch;
+  const int nblk = (nchunks + S - 1) / S;
+  const StIO io = sq ? sq->next(Epi::kKind != P_NONE ? nblk : 0)
+                     : StIO{nullptr, nullptr, nullptr, nullptr, 0, 0};
   hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g,
                      (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32),
                      (T)h->ch, (T)h->sh, Tch, nblk, in, epi, io);
   return hipGetLastError();
-}
-
-// Slices per chunk of the fused operator: enough blocks to cover the chip.
-int pick_chunk(const fph_handle_s* h, int nrhs, int NT) {
-  const Geom& g = h->g;
-  const int S = (g.Q <= NT) ? NT / g.Q : 1;
-  int best = 1;
-  for (int T = 16; T >= 1; T >>= 1) {
-    const long nblk = (long)((g.Ltau + T - 1) / T + S - 1) / S * nrhs;
-    if (nblk >= 1024) {
-      best = T;
-      break;
-    }
-  }
-  return best;
 }
 
 // Fused operator launch; with sq the kernel takes part in the solver's
@@ -123,10 +153,10 @@ hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, StateSeq*
                       hipStream_t s) {
   // One plaquette per thread; up to 1024 plaquettes (L <= 64) per slice.
   const int Q = h->g.Q;
-  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, pick_chunk(h, nrhs, 64), in, epi, sq, s);
-  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, pick_chunk(h, nrhs, 256), in, epi, sq, s);
-  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, pick_chunk(h, nrhs, 512), in, epi, sq, s);
-  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, pick_chunk(h, nrhs, 1024), in, epi, sq, s);
+  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, in, epi, sq, s);
+  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, in, epi, sq, s);
+  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, in, epi, sq, s);
+  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, in, epi, sq, s);
 }
 
 StIO no_state() { return StIO{nullptr, nullptr, nullptr, nullptr, 0, 0}; }
@@ -323,17 +353,23 @@ int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, const
   if (op < 0 || op > 2 || (prec != FPH_F64 && prec != FPH_F32)) return FPH_E_PREC;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
+  // Fused applies that move more than the 256 MB Infinity Cache write their
+  // output with nontemporal stores.
+  const size_t wbytes = prec == FPH_F64 ? 8 : 4;
+  const bool stream_out = (size_t)(2 * nrhs + 1) * h->g.d * wbytes > ((size_t)256 << 20);
   if (prec == FPH_F64) {
     const double* in = (const double*)in_dev;
     double* out = (double*)out_dev;
     if (op == FPH_OP_M) e = launch_M<double, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<double>(h, nrhs, in, out, s);
+    else if (stream_out) e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStream<double>{out}, nullptr, s);
     else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, nullptr, s);
   } else {
     const float* in = (const float*)in_dev;
     float* out = (float*)out_dev;
     if (op == FPH_OP_M) e = launch_M<float, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<float>(h, nrhs, in, out, s);
+    else if (stream_out) e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStream<float>{out}, nullptr, s);
     else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, nullptr, s);
   }
   if (e != hipSuccess) return fail_hip(e);

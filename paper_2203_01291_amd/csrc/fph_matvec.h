@@ -246,6 +246,22 @@ struct EpiStore {
   static constexpr int kKind = P_NONE;
 };
 
+// Plain store that bypasses the caches (nontemporal): for applies whose
+// output is far larger than the caches and is not read back soon.
+template <typename T>
+struct EpiStream {
+  T* __restrict__ out;
+  FPH_DEVINL void begin(const RhsState&) {}
+  FPH_DEVINL void put2(long off, T o0, T o1, T, T, double&, double&) const {
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    V2 v;
+    v.x = o0;
+    v.y = o1;
+    __builtin_nontemporal_store(v, reinterpret_cast<V2*>(out + off));
+  }
+  static constexpr int kKind = P_NONE;
+};
+
 // Store out = A p and accumulate p . A p (consumed as P_PAP: alpha).
 template <typename T>
 struct EpiDot {
