@@ -77,6 +77,7 @@ struct InDir {
     load2(off, a, b);
     st2(pnew + off, a, b);
   }
+  FPH_FETCH_AFTER_STATE(T)
 };
 
 template <int NT, int MS>
@@ -121,8 +122,8 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
       InDir<float> in{it.r, pold, pnew, (float)beta, fresh};
       EpiDot<float> epi{it.Ap};
       double acc = 0.0, acc2 = 0.0;
-      mtm_sweep<float, NT, MS>(g, it.E32, (float)it.ch, (float)it.sh, Tch, tau0, Tc, active,
-                               lane, nslot, lds4, 0, in, epi, acc, acc2);
+      mtm_sweep<float, NT, MS, 1>(g, it.E32, (float)it.ch, (float)it.sh, Tch, tau0, Tc, active,
+                                  lane, nslot, lds4, 0, in, epi, acc, acc2, [] { return true; });
       const double pAp = block_allsum<NT>(acc, red_sh, bcast);
       matvecs += 1;
       if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -165,8 +166,8 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
       InPlain<double> in{it.u};
       EpiResidual<float> epi{it.b, it.r};
       double acc = 0.0, acc2 = 0.0;
-      mtm_sweep<double, NT, MS>(g, it.E64, it.ch, it.sh, Tch, tau0, Tc, active, lane, nslot,
-                                lds4, 0, in, epi, acc, acc2);
+      mtm_sweep<double, NT, MS, 1>(g, it.E64, it.ch, it.sh, Tch, tau0, Tc, active, lane, nslot,
+                                   lds4, 0, in, epi, acc, acc2, [] { return true; });
       rr_true = block_allsum<NT>(acc, red_sh, bcast);
     }
     matvecs += 1;

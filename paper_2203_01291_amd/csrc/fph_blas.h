@@ -104,21 +104,42 @@ k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__
   __shared__ double red_sh[4];
   __shared__ RhsState s_sh;
   const int rh = blockIdx.y;
+  const long off = (long)rh * d;
+  // The thread's first four elements are loaded (with both direction
+  // buffers) while the state is read.
+  const long k0 = 4 * (blockIdx.x * 256L + threadIdx.x);
+  using V = typename Vec4<T>::V;
+  V u0{}, r0{}, pa0{}, pb0{}, a0{};
+  if (k0 < d) {
+    u0 = Vec4<T>::ld(u + off + k0);
+    r0 = Vec4<T>::ld(r + off + k0);
+    pa0 = Vec4<T>::ld(pa + off + k0);
+    pb0 = Vec4<T>::ld(pb + off + k0);
+    a0 = Vec4<T>::ld(Ap + off + k0);
+  }
   state_begin<256>(io, rh, &s_sh, red_sh);
   if (s_sh.done) {
     state_end(io, rh, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
     return;
   }
-  const T* __restrict__ p = (s_sh.iter & 1) ? pa : pb;
+  const bool odd = (s_sh.iter & 1) != 0;
+  const T* __restrict__ p = odd ? pa : pb;
   const T a = (T)s_sh.alpha;
-  const long off = (long)rh * d;
   double acc = 0.0;
-  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
+  for (long k = k0; k < d; k += 4L * gridDim.x * 256) {
     const long o = off + k;
-    auto uu = Vec4<T>::ld(u + o);
-    auto rr = Vec4<T>::ld(r + o);
-    const auto pp = Vec4<T>::ld(p + o);
-    const auto aa = Vec4<T>::ld(Ap + o);
+    V uu, rr, pp, aa;
+    if (k == k0) {
+      uu = u0;
+      rr = r0;
+      pp = odd ? pa0 : pb0;
+      aa = a0;
+    } else {
+      uu = Vec4<T>::ld(u + o);
+      rr = Vec4<T>::ld(r + o);
+      pp = Vec4<T>::ld(p + o);
+      aa = Vec4<T>::ld(Ap + o);
+    }
     uu.x += a * pp.x; uu.y += a * pp.y; uu.z += a * pp.z; uu.w += a * pp.w;
     rr.x -= a * aa.x; rr.y -= a * aa.y; rr.z -= a * aa.z; rr.w -= a * aa.w;
     Vec4<T>::st(u + o, uu);

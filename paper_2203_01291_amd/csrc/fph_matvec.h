@@ -51,6 +51,18 @@ FPH_DEVINL P pick(bool c, P a, P b) {
   return (P)(((uintptr_t)a & ~m) | ((uintptr_t)b & m));
 }
 
+// The same for two values (bitwise, so the result is exactly a or b).
+FPH_DEVINL float pickv(bool c, float a, float b) {
+  const uint32_t m = 0u - (uint32_t)c;
+  return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a) & ~m) |
+                                       (__builtin_bit_cast(uint32_t, b) & m));
+}
+FPH_DEVINL double pickv(bool c, double a, double b) {
+  const uint64_t m = 0ull - (uint64_t)c;
+  return __builtin_bit_cast(double, (__builtin_bit_cast(uint64_t, a) & ~m) |
+                                        (__builtin_bit_cast(uint64_t, b) & m));
+}
+
 // v read directly.
 template <typename T>
 struct InPlain {
@@ -62,7 +74,36 @@ struct InPlain {
   FPH_DEVINL T load_owned(long off) const { return v[off]; }
   FPH_DEVINL void load2(long off, T& a, T& b) const { ld2(v + off, a, b); }
   FPH_DEVINL void load2_owned(long off, T& a, T& b) const { ld2(v + off, a, b); }
+  // Two-phase access used by the operator sweep (see mtm_sweep): fetch2
+  // issues the loads, use2 forms the pair where it is needed.
+  static constexpr bool kPrefetch = true;
+  struct Raw {
+    T a, b;
+  };
+  FPH_DEVINL void fetch2(long off, Raw& w, bool) const { ld2(v + off, w.a, w.b); }
+  FPH_DEVINL void use2(long, const Raw& w, T& a, T& b, bool, bool) const {
+    a = w.a;
+    b = w.b;
+  }
 };
+
+// fetch2 / use2 for inputs whose loads depend on the solver state: the
+// whole load (and the owner's stores) happens in fetch2, after the state.
+#define FPH_FETCH_AFTER_STATE(T)                                              \
+  static constexpr bool kPrefetch = false;                                    \
+  struct Raw {                                                                \
+    T a, b;                                                                   \
+  };                                                                          \
+  FPH_DEVINL void fetch2(long off, Raw& w, bool owned) const {                \
+    if (owned)                                                                \
+      load2_owned(off, w.a, w.b);                                             \
+    else                                                                      \
+      load2(off, w.a, w.b);                                                   \
+  }                                                                           \
+  FPH_DEVINL void use2(long, const Raw& w, T& a, T& b, bool, bool) const {   \
+    a = w.a;                                                                  \
+    b = w.b;                                                                  \
+  }
 
 // v = one of two buffers chosen by the parity of the iteration count
 // (single-reduction CG keeps its residual double-buffered).
@@ -78,6 +119,7 @@ struct InParity {
   FPH_DEVINL T load_owned(long off) const { return v[off]; }
   FPH_DEVINL void load2(long off, T& a, T& b) const { ld2(v + off, a, b); }
   FPH_DEVINL void load2_owned(long off, T& a, T& b) const { ld2(v + off, a, b); }
+  FPH_FETCH_AFTER_STATE(T)
 };
 
 // p = z + beta p_old computed on the fly (the CG direction update fused
@@ -94,12 +136,15 @@ struct InPUpdate {
   T* __restrict__ pnew;
   T beta;
   int fresh;
+  int odd;    // parity of the right-hand side's iteration count
+  int known;  // begin() has run: the state is known
   FPH_DEVINL void begin(const RhsState& s) {
     fresh = s.fresh;
     beta = fresh ? (T)0 : (T)(s.rz_next / s.rz);
-    const bool odd = (s.iter & 1) != 0;
-    pold = pick(odd, pa, pb);
-    pnew = pick(odd, pb, pa);
+    odd = (s.iter & 1) != 0;
+    pold = pick(odd != 0, pa, pb);
+    pnew = pick(odd != 0, pb, pa);
+    known = 1;
   }
   // Direction-update bookkeeping, applied once to the shared state.
   static FPH_DEVINL void on_state(RhsState& s) {
@@ -126,6 +171,37 @@ struct InPUpdate {
   FPH_DEVINL void load2_owned(long off, T& a, T& b) const {
     load2(off, a, b);
     st2(pnew + off, a, b);
+  }
+  // Before the state is known (the first slices of a chunk are fetched
+  // while the state is read) both direction buffers are loaded; use2 picks
+  // the one the parity selects.
+  static constexpr bool kPrefetch = true;
+  struct Raw {
+    T z0, z1, a0, a1, b0, b1;
+  };
+  FPH_DEVINL void fetch2(long off, Raw& w, bool) const {
+    // (locals, all fields written: keeps Raw in registers)
+    T z0, z1, a0 = (T)0, a1 = (T)0, b0 = (T)0, b1 = (T)0;
+    ld2(z + off, z0, z1);
+    if (!known || !fresh) ld2(pick<const T*>(known != 0, pa, pold) + off, a0, a1);
+    if (!known) ld2(pb + off, b0, b1);
+    w.z0 = z0;
+    w.z1 = z1;
+    w.a0 = a0;
+    w.a1 = a1;
+    w.b0 = b0;
+    w.b1 = b1;
+  }
+  FPH_DEVINL void use2(long off, const Raw& w, T& a, T& b, bool owned, bool prefetched) const {
+    a = w.z0;
+    b = w.z1;
+    if (!fresh) {
+      const bool second = prefetched && odd;
+      const T c = pickv(second, w.a0, w.b0), d = pickv(second, w.a1, w.b1);
+      a += beta * c;
+      b += beta * d;
+    }
+    if (owned) st2(pnew + off, a, b);
   }
 };
 
@@ -232,6 +308,7 @@ struct InCGCG {
     a = load_owned(off);
     b = load_owned(off + 1);
   }
+  FPH_FETCH_AFTER_STATE(T)
 };
 
 // ---------------------------------------------------- epilogue functors --
@@ -381,19 +458,29 @@ FPH_DEVINL void pb_window(const Geom& g, const T* __restrict__ sl, int x0, int y
 //        P_A t; y = P_A(E_tau w_tau) -> B[j&1]; v~_tau -> A[(j+1)&1]
 //   (ii) out_{tau-1} = w_{tau-1} - P_B y (read from B[j&1]).
 // LDS: 4 slices (A[2], B[2]) per chunk.
-template <typename T, int NT, int MAXSLOT, class In, class Epi>
-FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, int Tch, int tau0,
+// Loads run DEPTH slices ahead of their use.  `hook` folds the solver
+// state and configures `in` / `epi`; it returns false when the right-hand
+// side is finished (then the sweep returns false at once).  With
+// In::kPrefetch the loads of the first slices are issued before the hook,
+// so they overlap the state's memory round trip.
+template <typename T, int NT, int MAXSLOT, int DEPTH, class In, class Epi, class Hook>
+FPH_DEVINL bool mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, int Tch, int tau0,
                           int Tc, bool active, int lane, int nslot, T* lds4, long base,
-                          const In& in, const Epi& epi, double& acc, double& acc2) {
+                          In& in, Epi& epi, double& acc, double& acc2, Hook&& hook) {
+  static_assert(DEPTH == 1 || DEPTH == 2, "DEPTH is 1 or 2");
+  using Raw = typename In::Raw;
   T* A0 = lds4;
   T* A1 = lds4 + g.N;
   T* B0 = lds4 + 2 * g.N;
   T* B1 = lds4 + 3 * g.N;
-  T cv[MAXSLOT][4], ce[MAXSLOT][4];   // v_tau, E_tau (even layout)
+  Raw q0[MAXSLOT][2], q1[MAXSLOT][2];   // v of the next slices, as fetched
+  T e0[MAXSLOT][4], e1[MAXSLOT][4];     // E of the next slices
+  Raw pro[MAXSLOT][2];                  // v of slice tau0 - 1
   T wprev[MAXSLOT][4], vprev[MAXSLOT][4];
+  const int pt = (tau0 == 0) ? g.Ltau - 1 : tau0 - 1;
+  const long poff = base + (long)pt * g.N;
 
-  // loads of slice tau0 + jj into cv/ce (v owned when jj < Tc)
-  auto issue = [&](int jj) {
+  auto fetch = [&](int jj, Raw (&dst)[MAXSLOT][2], T (&e)[MAXSLOT][4]) {
     const int tau = tau0 + jj;
     const int tm = (tau >= g.Ltau) ? tau - g.Ltau : tau;
     const long toff = base + (long)tm * g.N;
@@ -403,37 +490,52 @@ FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
       const int q = lane + k * NT;
       if (k < nslot && q < g.Q) {
         const int i0 = 2 * (q % g.hL) + g.L * 2 * (q / g.hL);
-        if (jj < Tc) {
-          in.load2_owned(toff + i0, cv[k][0], cv[k][1]);
-          in.load2_owned(toff + i0 + g.L, cv[k][2], cv[k][3]);
-        } else {
-          in.load2(toff + i0, cv[k][0], cv[k][1]);
-          in.load2(toff + i0 + g.L, cv[k][2], cv[k][3]);
-        }
-        ld2(Et + i0, ce[k][0], ce[k][1]);
-        ld2(Et + i0 + g.L, ce[k][2], ce[k][3]);
+        in.fetch2(toff + i0, dst[k][0], jj < Tc);
+        in.fetch2(toff + i0 + g.L, dst[k][1], jj < Tc);
+        ld2(Et + i0, e[k][0], e[k][1]);
+        ld2(Et + i0 + g.L, e[k][2], e[k][3]);
       }
     }
   };
+  auto fetch_first = [&]() {
+    if (!active) return;
+#pragma unroll
+    for (int k = 0; k < MAXSLOT; ++k) {
+      const int q = lane + k * NT;
+      if (k < nslot && q < g.Q) {
+        const int i0 = 2 * (q % g.hL) + g.L * 2 * (q / g.hL);
+        in.fetch2(poff + i0, pro[k][0], false);
+        in.fetch2(poff + i0 + g.L, pro[k][1], false);
+      }
+    }
+    fetch(0, q0, e0);
+    if (DEPTH == 2 && 1 <= Tc) fetch(1, q1, e1);
+  };
+
+  if constexpr (In::kPrefetch) {
+    fetch_first();
+    if (!hook()) return false;
+  } else {
+    if (!hook()) return false;
+    fetch_first();
+  }
+  constexpr bool kEarly = In::kPrefetch;  // the first DEPTH slices were fetched before the hook
 
   // Prologue: v~_{tau0 - 1} into A0 (antiperiodic sign at the wrap).
   if (active) {
-    const int pt = (tau0 == 0) ? g.Ltau - 1 : tau0 - 1;
     const T psg = (tau0 == 0) ? (T)-1 : (T)1;
-    const long poff = base + (long)pt * g.N;
 #pragma unroll
     for (int k = 0; k < MAXSLOT; ++k) {
       const int q = lane + k * NT;
       if (k < nslot && q < g.Q) {
         const int i0 = 2 * (q % g.hL) + g.L * 2 * (q / g.hL);
         T a, b, c, d;
-        in.load2(poff + i0, a, b);
-        in.load2(poff + i0 + g.L, c, d);
+        in.use2(poff + i0, pro[k][0], a, b, false, kEarly);
+        in.use2(poff + i0 + g.L, pro[k][1], c, d, false, kEarly);
         st2(A0 + i0, psg * a, psg * b);
         st2(A0 + i0 + g.L, psg * c, psg * d);
       }
     }
-    issue(0);
   }
   __syncthreads();
 
@@ -443,25 +545,42 @@ FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
     const T* Acur = (j & 1) ? A1 : A0;
     T* Anext = (j & 1) ? A0 : A1;
     T* Bcur = (j & 1) ? B1 : B0;
-    T nv[MAXSLOT][4], ne[MAXSLOT][4];
+    Raw cr[MAXSLOT][2];
+    T ne[MAXSLOT][4];
 #pragma unroll
-    for (int k = 0; k < MAXSLOT; ++k)
+    for (int k = 0; k < MAXSLOT; ++k) {
+      cr[k][0] = q0[k][0];
+      cr[k][1] = q0[k][1];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        nv[k][m] = cv[k][m];
-        ne[k][m] = ce[k][m];
+      for (int m = 0; m < 4; ++m) ne[k][m] = e0[k][m];
+    }
+    if (DEPTH == 2) {
+#pragma unroll
+      for (int k = 0; k < MAXSLOT; ++k) {
+        q0[k][0] = q1[k][0];
+        q0[k][1] = q1[k][1];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) e0[k][m] = e1[k][m];
       }
-    if (active && j + 1 <= Tc) issue(j + 1);
-    T wcur[MAXSLOT][4];
+      if (active && j + 2 <= Tc) fetch(j + 2, q1, e1);
+    } else {
+      if (active && j + 1 <= Tc) fetch(j + 1, q0, e0);
+    }
+    T wcur[MAXSLOT][4], nv[MAXSLOT][4];
     if (act) {
       const T sg = (tau >= g.Ltau) ? (T)-1 : (T)1;          // w_{Ltau} = -w_0
       const T nsg = (tau + 1 == g.Ltau) ? (T)-1 : (T)1;     // v~ for the next step
+      const int tm = (tau >= g.Ltau) ? tau - g.Ltau : tau;
+      const long toff = base + (long)tm * g.N;
+      const bool early = kEarly && j < DEPTH;
 #pragma unroll
       for (int k = 0; k < MAXSLOT; ++k) {
         const int q = lane + k * NT;
         if (k < nslot && q < g.Q) {
           const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
           const int i0 = x0 + g.L * y0;
+          in.use2(toff + i0, cr[k][0], nv[k][0], nv[k][1], j < Tc, early);
+          in.use2(toff + i0 + g.L, cr[k][1], nv[k][2], nv[k][3], j < Tc, early);
           T t[4];
           pb_window(g, Acur, x0, y0, ch, sh, t);
           plaq_rot(t, ch, sh);
@@ -504,17 +623,25 @@ FPH_DEVINL void mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
       }
     }
   }
+  return true;
 }
 
 // Launch: grid (nblk * nrhs) (see xcd_contiguous).  Block b of right-hand side r serves `S`
 // chunks of `Tch` slices each; with Q <= NT plaquettes per slice, S = NT/Q
 // chunks run side by side (one plaquette per thread), otherwise S = 1 and a
 // thread serves up to MAXSLOT plaquettes.  LDS: 4 * S * N elements of T.
-// With io.in set, the kernel takes part in the CG state machine: it folds
-// pending partials, skips finished right-hand sides and publishes its own
-// partials (Epi::kKind).
+// With io.in set (and an epilogue that produces partial sums), the kernel
+// takes part in the CG state machine: it folds pending partials, skips
+// finished right-hand sides and publishes its own partials (Epi::kKind).
+// Plain FP32 applies in 1024-thread workgroups are held to 8 waves per SIMD
+// (64 VGPRs), so two workgroups share a CU.
+template <typename T, int NT, class Epi>
+constexpr int mtm_min_waves() {
+  return (NT == 1024 && sizeof(T) == 4 && Epi::kKind == P_NONE) ? 8 : 1;
+}
+
 template <typename T, int NT, int MAXSLOT, class In, class Epi>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, (mtm_min_waves<T, NT, Epi>()))
 k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi epi, StIO io) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
@@ -527,19 +654,23 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi
   const int nrhs = gridDim.x / nblk;
   const int r = logical % nrhs;
   const int bx = logical / nrhs;
-  if (io.in != nullptr) {
+  auto hook = [&]() -> bool {
+    // Plain applies (no partial sums) never carry solver state.
+    if constexpr (Epi::kKind == P_NONE) return true;
+    if (io.in == nullptr) return true;
     state_begin<NT>(io, r, &s_sh, red_sh);
     if (threadIdx.x == 0 && !s_sh.done) In::prepare(s_sh);
     __syncthreads();
     if (s_sh.done) {
       state_end(io, r, &s_sh, P_NONE, 0.0, bx, nblk, bx == 0);
-      return;
+      return false;
     }
     in.begin(s_sh);
     epi.begin(s_sh);
     __syncthreads();
     if (threadIdx.x == 0) In::on_state(s_sh);
-  }
+    return true;
+  };
 
   const int tid = threadIdx.x;
   int S, sub, lane, nslot;
@@ -551,14 +682,19 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi
   T* lds4 = reinterpret_cast<T*>(smem_raw) + 4L * (sub < S ? sub : 0) * g.N;
   const long base = (long)r * g.d;
   double acc = 0.0, acc2 = 0.0;
-  mtm_sweep<T, NT, MAXSLOT>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, lds4, base, in,
-                            epi, acc, acc2);
+  // Small workgroups (latency-bound lattices) fetch two slices ahead.
+  constexpr int kDepth = (NT <= 256) ? 2 : 1;
+  if (!mtm_sweep<T, NT, MAXSLOT, kDepth>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, lds4,
+                                         base, in, epi, acc, acc2, hook))
+    return;
 
-  if (io.in != nullptr) {
-    double bs = 0.0, bs2 = 0.0;
-    if constexpr (Epi::kKind != P_NONE) bs = block_sum<NT>(acc, red_sh);
-    if constexpr (Epi::kKind == P_GD) bs2 = block_sum<NT>(acc2, red_sh);
-    state_end(io, r, &s_sh, Epi::kKind, bs, bx, nblk, bx == 0, bs2);
+  if constexpr (Epi::kKind != P_NONE) {
+    if (io.in != nullptr) {
+      double bs2 = 0.0;
+      const double bs = block_sum<NT>(acc, red_sh);
+      if constexpr (Epi::kKind == P_GD) bs2 = block_sum<NT>(acc2, red_sh);
+      state_end(io, r, &s_sh, Epi::kKind, bs, bx, nblk, bx == 0, bs2);
+    }
   }
 }
 
