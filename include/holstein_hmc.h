@@ -77,6 +77,8 @@ extern "C" {
 #define FPH_ST_MAXITER 2      /* iteration cap reached                    */
 #define FPH_ST_BREAKDOWN 4    /* p.Ap <= 0 or r.z <= 0 in CG              */
 #define FPH_ST_NONFINITE 8    /* NaN or Inf met in a scalar of the solve  */
+#define FPH_ST_ABORTED 16     /* variant 2: a grid-wide wait ran over its
+                                 limit and the launch gave up             */
 
 typedef struct fph_handle_s* fph_handle_t;
 
@@ -110,11 +112,16 @@ typedef struct {
                            recomputation finds the true residual more than
                            twice the FP32 one                             */
   int32_t chunk;        /* CG iterations enqueued between host checks
-                           (0 -> library default)                         */
+                           (0 -> library default); variant 2: the largest
+                           number of workgroups (0 -> 128)                 */
   int32_t variant;      /* without preconditioner: 0 standard CG (two
                            reductions, two launches per iteration); 1
                            single-reduction CG (Chronopoulos and Gear, 1989:
-                           one launch per iteration, less stable in FP32)  */
+                           one launch per iteration, less stable in FP32);
+                           2 the whole FP32_REFINED solve in one cooperative
+                           launch (nrhs == 1, no preconditioner; all
+                           workgroups resident, grid-wide exchanges of
+                           partial sums instead of kernel boundaries)      */
 } fph_pcg_opts_t;
 
 typedef struct {

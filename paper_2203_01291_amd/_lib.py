@@ -14,7 +14,7 @@ FPH_OK = 0
 FPH_OP_M, FPH_OP_MT, FPH_OP_MTM = 0, 1, 2
 FPH_F64, FPH_F32, FPH_F32_REFINED = 0, 1, 2
 FPH_PC_F, FPH_PC_FT, FPH_PC_FFT = 0, 1, 2
-ST_CONVERGED, ST_MAXITER, ST_BREAKDOWN, ST_NONFINITE = 1, 2, 4, 8
+ST_CONVERGED, ST_MAXITER, ST_BREAKDOWN, ST_NONFINITE, ST_ABORTED = 1, 2, 4, 8, 16
 
 
 class Lattice(ctypes.Structure):

@@ -18,6 +18,7 @@
 #include "fph_batch.h"
 #include "fph_blas.h"
 #include "fph_common.h"
+#include "fph_coop.h"
 #include "fph_matvec.h"
 #include "fph_precond.h"
 
@@ -537,15 +538,115 @@ hipError_t fp64_residual(fph_handle_s* h, int nrhs, bool pre, bool cgcg, int par
 
 }  // namespace
 
+namespace {
+
+// The one-launch cooperative FP32-refined solve (fph_coop.h) for one
+// right-hand side.  Workgroups own chunks of slices; the chunk length is
+// the shortest that keeps the workgroup count within the exchange's limit
+// (kCoopMaxBlocks), co-residency, and `target` workgroups.
+template <int NT>
+hipError_t coop_launch(fph_handle_s* h, const double* b, double* u, const fph_pcg_opts_t* opts,
+                       double delta, int target, CoopStats* out, hipStream_t s) {
+  const Geom& g = h->g;
+  const int S = (g.Q <= NT) ? NT / g.Q : 1;
+  const size_t lds = 4 * (size_t)S * g.N * sizeof(double);
+  const void* kern = (const void*)k_cg_coop<NT>;
+  hipError_t e = allow_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, ncu = 0, dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds)) != hipSuccess)
+    return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  const int cap = std::min(kCoopMaxBlocks, std::max(1, per_cu) * ncu);
+  int Tch = 1, nblk = 0;
+  for (Tch = 1; Tch <= g.Ltau; ++Tch) {
+    nblk = ((g.Ltau + Tch - 1) / Tch + S - 1) / S;
+    if (nblk <= std::min(cap, target)) break;
+  }
+  if (nblk > cap) return hipErrorInvalidConfiguration;
+  // exchange regions (empty; kRegions * kCoopMaxBlocks * 2 words = the
+  // first kPStride partials of part[0]) and the abort flag (in part[1],
+  // after the statistics)
+  static_assert((long)kRegions * kCoopMaxBlocks * 2 <= kPStride, "exchange regions");
+  uint64_t* slots = reinterpret_cast<uint64_t*>(h->part[0]);
+  uint64_t* abort_flag = reinterpret_cast<uint64_t*>(h->part[1]) + 64;
+  const long nslots = (long)kRegions * kCoopMaxBlocks * 2;
+  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, s, slots, nslots, kEmptySlot);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, abort_flag, 1L, (uint64_t)0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  CoopArgs a;
+  a.g = g;
+  a.ch32 = (float)h->ch;
+  a.sh32 = (float)h->sh;
+  a.ch = h->ch;
+  a.sh = h->sh;
+  a.E32 = h->E32;
+  a.E64 = h->E64;
+  a.b = b;
+  a.u = u;
+  a.r = h->r32;
+  a.pa = h->pa32;
+  a.pb = h->pb32;
+  a.Ap = h->Ap32;
+  a.u32 = h->u32;
+  a.x = CoopExchange{slots, abort_flag, nblk};
+  a.out = out;
+  a.Tch = Tch;
+  a.tol = opts->tol;
+  a.maxiter = opts->maxiter;
+  a.delta = delta;
+  a.zero_guess = opts->zero_guess;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(kern, dim3(nblk), dim3(NT), args, (unsigned)lds, s);
+}
+
+int coop_solve(fph_handle_s* h, const double* b_dev, double* u_dev, const fph_pcg_opts_t* opts,
+               double delta, fph_pcg_stats_t* stats, hipStream_t s) {
+  CoopStats* out = reinterpret_cast<CoopStats*>(h->part[1]);
+  const int Q = h->g.Q;
+  const int target = opts->chunk > 0 ? opts->chunk : 128;
+  hipError_t e;
+  if (Q <= 64) e = coop_launch<64>(h, b_dev, u_dev, opts, delta, target, out, s);
+  else if (Q <= 256) e = coop_launch<256>(h, b_dev, u_dev, opts, delta, target, out, s);
+  else if (Q <= 512) e = coop_launch<512>(h, b_dev, u_dev, opts, delta, target, out, s);
+  else e = coop_launch<1024>(h, b_dev, u_dev, opts, delta, target, out, s);
+  if (e != hipSuccess) return fail_hip(e);
+  CoopStats res;
+  FPH_CHECK(hipMemcpyAsync(&res, out, sizeof(res), hipMemcpyDeviceToHost, s));
+  FPH_CHECK(fermion_action(h, 1, b_dev, u_dev, h->tmp64, s) == FPH_OK ? hipSuccess
+                                                                       : hipErrorUnknown);
+  FPH_CHECK(hipMemcpyAsync(h->tmp_host, h->tmp64, sizeof(double), hipMemcpyDeviceToHost, s));
+  FPH_CHECK(hipStreamSynchronize(s));
+  if (stats) {
+    stats[0].status = res.status;
+    stats[0].iters = res.iters;
+    stats[0].outer_iters = res.outer;
+    stats[0].matvecs = res.matvecs;
+    stats[0].rel_resid = res.bb > 0.0 ? std::sqrt(res.rr_true / res.bb) : 0.0;
+    stats[0].action = h->tmp_host[0];
+  }
+  return FPH_OK;
+}
+
+}  // namespace
+
 extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
                          const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats, void* stream) {
   if (h == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
   if (!h->have_field) return FPH_E_NOFIELD;
   if (nrhs < 1 || nrhs > h->max_rhs) return FPH_E_NRHS;
   if (opts->prec != FPH_F64 && opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
-  if (!(opts->tol >= 0.0) || opts->maxiter < 1 || opts->variant < 0 || opts->variant > 1)
+  if (!(opts->tol >= 0.0) || opts->maxiter < 1 || opts->variant < 0 || opts->variant > 2)
+    return FPH_E_ARG;
+  if (opts->variant == 2 &&
+      (opts->prec != FPH_F32_REFINED || opts->use_precond != 0 || nrhs != 1))
     return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
+  if (opts->variant == 2)
+    return coop_solve(h, b_dev, u_dev, opts,
+                      opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3, stats, s);
   const long d = h->g.d;
   const int nb = elem_blocks(d);
   const bool pre = opts->use_precond != 0;

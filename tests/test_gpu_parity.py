@@ -479,3 +479,59 @@ def test_force_central_differences_c5_100_sites():
     ref = _golden("c5")
     assert [list(c) for c in comps] == ref["samples"]
     assert rel(fd, np.array(ref["force_samples"])) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# The one-launch cooperative FP32-refined solve (variant 2).
+
+def test_cooperative_solve_c1_against_dense_oracle():
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=1)
+    u_ref = OS.solve_dense(lat, x, Phi)
+    s = make_solver(lat)
+    s.set_field(tgpu(x))
+    u, st = s.solve(tgpu(Phi[0]), tol=1e-13, maxiter=20000, prec="f32_refined", variant=2)
+    assert st[0]["status"] == 1, st
+    assert st[0]["rel_resid"] < 1e-13
+    assert rel(u.cpu().numpy(), u_ref[0]) < 1e-8
+    assert st[0]["action"] == pytest.approx(float(np.sum(Phi[0] * u_ref[0])), rel=1e-10)
+    # warm start from the solution: converged at once
+    u2, st2 = s.solve(tgpu(Phi[0]), u=u.clone(), tol=1e-12, prec="f32_refined", variant=2)
+    assert st2[0]["status"] == 1 and st2[0]["iters"] == 0
+
+
+@pytest.mark.parametrize("key", ["c2", "c3"])
+def test_cooperative_solve_full_size_against_oracle(key):
+    ref = _golden(key)
+    p = get_config(key)
+    lat = OL.Lattice.from_params(p)
+    x0 = phonon_field(p)
+    x = perturbed_field(p, x0)
+    phi = gaussian_rhs(p, 1)[0]
+    Cs = OL.sparse_C(lat)
+    Phi = (OL.sparse_M(lat, x0, Cs).T @ phi.reshape(-1)).reshape(lat.Ltau, lat.N)
+    s = make_solver(lat)
+    s.set_field(tgpu(x))
+    u, st = s.solve(tgpu(Phi), tol=1e-12, maxiter=200000, prec="f32_refined", variant=2)
+    st = st[0]
+    assert st["status"] == 1, st
+    idx = np.array(ref["samples"])
+    uh = u.cpu().numpy()[idx[:, 0], idx[:, 1]]
+    g = s.force(u).cpu().numpy()[idx[:, 0], idx[:, 1]]
+    rel_u, rel_g = rel(uh, ref["u_samples"]), rel(g, ref["force_samples"])
+    print(f"{key} cooperative: iters {st['iters']} outer {st['outer_iters']} rel err u {rel_u:.2e} force {rel_g:.2e}")
+    assert rel_u < 1e-8 and rel_g < 1e-8
+    dS = abs(st["action"] - ref["S_F"])
+    assert dS <= 1.01 * ref["u_norm"] * np.linalg.norm(Phi) * (st["rel_resid"] + ref["final_rel_resid"])
+
+
+def test_cooperative_solve_argument_checks():
+    p, lat, x0, x, phi, Phi = c1_problem(nrhs=2)
+    from paper_2203_01291_amd._lib import FphError
+    s = make_solver(lat, max_rhs=2)
+    s.set_field(tgpu(x))
+    with pytest.raises(FphError):
+        s.solve(tgpu(Phi), prec="f32_refined", variant=2)        # nrhs = 2
+    with pytest.raises(FphError):
+        s.solve(tgpu(Phi[0]), prec="f64", variant=2)             # FP64
+    with pytest.raises(FphError):
+        s.solve(tgpu(Phi[0]), prec="f32_refined", precond=True, variant=2)
