@@ -77,7 +77,29 @@ struct InDir {
     load2(off, a, b);
     st2(pnew + off, a, b);
   }
-  FPH_FETCH_AFTER_STATE(T)
+  // loads issued ahead, p formed (and stored by the owner) where used
+  static constexpr bool kPrefetch = true;
+  struct Raw {
+    T z0, z1, a0, a1;
+  };
+  FPH_DEVINL void fetch2(long off, Raw& w, bool) const {
+    T z0, z1, a0 = (T)0, a1 = (T)0;
+    ld2(z + off, z0, z1);
+    if (!fresh) ld2(pold + off, a0, a1);
+    w.z0 = z0;
+    w.z1 = z1;
+    w.a0 = a0;
+    w.a1 = a1;
+  }
+  FPH_DEVINL void use2(long off, const Raw& w, T& a, T& b, bool owned, bool) const {
+    a = w.z0;
+    b = w.z1;
+    if (!fresh) {
+      a += beta * w.a0;
+      b += beta * w.a1;
+    }
+    if (owned) st2(pnew + off, a, b);
+  }
 };
 
 template <int NT, int MS>
