@@ -297,9 +297,12 @@ def main():
     all_variants = (("f32_refined_plain", "f32_refined", False, 0),
                     ("f32_refined_precond", "f32_refined", True, 0),
                     ("f64_plain", "f64", False, 0),
+                    ("f32_refined_plain_one_launch", "f32_refined", False, 2),
                     ("f64_plain_single_reduction", "f64", False, 1),
                     ("f64_precond", "f64", True, 0))
     for name, prec, pre_v, var in (() if args.no_variants else all_variants):
+        if var == 2 and R != 1:
+            continue
         t, st = time_steps(make_step(prec, pre_v, var), 1, 0, torch)
         variants[name] = {"ms": t * 1e3, "iters": st[0]["iters"], "status": st[0]["status"],
                           "rel_resid": st[0]["rel_resid"]}

@@ -172,10 +172,11 @@ struct InPUpdate {
     load2(off, a, b);
     st2(pnew + off, a, b);
   }
-  // Before the state is known (the first slices of a chunk are fetched
-  // while the state is read) both direction buffers are loaded; use2 picks
-  // the one the parity selects.
-  static constexpr bool kPrefetch = true;
+  // Fetched after the state is known (loading both direction buffers
+  // ahead of it costs more than the round trip it saves); if fetched
+  // before, both buffers are loaded and use2 picks the one the parity
+  // selects.
+  static constexpr bool kPrefetch = false;
   struct Raw {
     T z0, z1, a0, a1, b0, b1;
   };
@@ -682,10 +683,8 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi
   T* lds4 = reinterpret_cast<T*>(smem_raw) + 4L * (sub < S ? sub : 0) * g.N;
   const long base = (long)r * g.d;
   double acc = 0.0, acc2 = 0.0;
-  // Small workgroups (latency-bound lattices) fetch two slices ahead.
-  constexpr int kDepth = (NT <= 256) ? 2 : 1;
-  if (!mtm_sweep<T, NT, MAXSLOT, kDepth>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, lds4,
-                                         base, in, epi, acc, acc2, hook))
+  if (!mtm_sweep<T, NT, MAXSLOT, 1>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, lds4,
+                                    base, in, epi, acc, acc2, hook))
     return;
 
   if constexpr (Epi::kKind != P_NONE) {
