@@ -506,42 +506,43 @@ FPH_DEVINL void pb_window_c(const Win& w, const typename Cplx<T>::type* __restri
   im[3] = ch * h1i[2] + sh * h1i[3];
 }
 
-// Bbar x (TRANS = false: dbar * P_A (P_B x)) or Bbar^T x (TRANS = true:
+// y = Bbar x (TRANS = false: dbar * P_A (P_B x)) or Bbar^T x (TRANS = true:
 // P_B (P_A (dbar * x))) for a complex vector held one even plaquette per
-// thread.  One LDS exchange per apply: the thread publishes its four sites
-// (x, or P_A(dbar x)) into buffer `cur` and after one barrier forms P_B at
-// its sites from the window.  Buffers alternate between applies, so one
-// barrier per apply suffices.  Threads without a plaquette only keep the
-// barrier.
+// thread; x is left unchanged.  One LDS exchange per apply: the thread
+// publishes its four sites (x, or P_A(dbar x)) into buffer `cur` and after
+// one barrier forms P_B at its sites from the window.  Buffers alternate
+// between applies, so one barrier per apply suffices.  Threads without a
+// plaquette only keep the barrier.  `db` may carry a scale factor.
 template <typename T, bool TRANS>
-FPH_DEVINL void bbar_apply(const Win& w, bool own, int i0, int iL, T (&xr)[4], T (&xi)[4],
-                           const T (&db)[4], typename Cplx<T>::type* lbuf, int N, int& cur,
-                           T ch, T sh) {
+FPH_DEVINL void bbar_apply(const Win& w, bool own, int i0, int iL, const T (&xr)[4],
+                           const T (&xi)[4], T (&yr)[4], T (&yi)[4], const T (&db)[4],
+                           typename Cplx<T>::type* lbuf, int N, int& cur, T ch, T sh) {
   using T2 = typename Cplx<T>::type;
   T2* buf = lbuf + (long)cur * N;
   if (own) {
-    if (TRANS) {
+    T tr[4], ti[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        xr[m] *= db[m];
-        xi[m] *= db[m];
-      }
-      plaq_rot(xr, ch, sh);
-      plaq_rot(xi, ch, sh);
+    for (int m = 0; m < 4; ++m) {
+      tr[m] = TRANS ? xr[m] * db[m] : xr[m];
+      ti[m] = TRANS ? xi[m] * db[m] : xi[m];
     }
-    st2c(buf + i0, xr[0], xi[0], xr[1], xi[1]);
-    st2c(buf + iL, xr[2], xi[2], xr[3], xi[3]);
+    if (TRANS) {
+      plaq_rot(tr, ch, sh);
+      plaq_rot(ti, ch, sh);
+    }
+    st2c(buf + i0, tr[0], ti[0], tr[1], ti[1]);
+    st2c(buf + iL, tr[2], ti[2], tr[3], ti[3]);
   }
   __syncthreads();
   if (own) {
-    pb_window_c<T>(w, buf, ch, sh, xr, xi);
+    pb_window_c<T>(w, buf, ch, sh, yr, yi);
     if (!TRANS) {
-      plaq_rot(xr, ch, sh);
-      plaq_rot(xi, ch, sh);
+      plaq_rot(yr, ch, sh);
+      plaq_rot(yi, ch, sh);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        xr[m] *= db[m];
-        xi[m] *= db[m];
+        yr[m] *= db[m];
+        yi[m] *= db[m];
       }
     }
   }
@@ -550,50 +551,57 @@ FPH_DEVINL void bbar_apply(const Win& w, bool own, int i0, int iL, T (&xr)[4], T
 
 // acc = sum_{m < NP} c'_m T_m(A') x with A' = A (TRANS false, c' = c) or
 // A' = A^T (TRANS true, c' = conj(c)), A = sA Bbar - cA; three-term
-// recurrence of Eq. alpha_recur.  x is consumed.
+// recurrence of Eq. alpha_recur.  For m >= 2 the factor 2 sA is folded
+// into the diagonal (alpha_m = (2 sA Bbar) alpha_{m-1} - 2 cA alpha_{m-1}
+// - alpha_{m-2}), and the two latest terms alternate between two register
+// sets, so no copies are made.
 template <typename T, bool TRANS>
 FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int NP,
-                            const typename Cplx<T>::type* cf, T sA, T cA, T (&xr)[4],
-                            T (&xi)[4], const T (&db)[4], typename Cplx<T>::type* lbuf,
+                            const typename Cplx<T>::type* cf, T sA, T cA, const T (&xr)[4],
+                            const T (&xi)[4], const T (&db)[4], typename Cplx<T>::type* lbuf,
                             int& cur, T ch, T sh, T (&ar)[4], T (&ai)[4]) {
   const T cj = TRANS ? (T)-1 : (T)1;
-  T pr[4], pi_[4];  // alpha_{m-1}
-  {
-    const auto c0 = cf[0];
+  auto accumulate = [&](const typename Cplx<T>::type c, const T (&vr)[4], const T (&vi)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      ar[q] = c0.x * xr[q] - cj * c0.y * xi[q];
-      ai[q] = c0.x * xi[q] + cj * c0.y * xr[q];
-      pr[q] = xr[q];
-      pi_[q] = xi[q];
+      ar[q] += c.x * vr[q] - cj * c.y * vi[q];
+      ai[q] += c.x * vi[q] + cj * c.y * vr[q];
     }
+  };
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ar[q] = ai[q] = (T)0;
+  accumulate(cf[0], xr, xi);
+  if (NP < 2) return;
+  T pr[4], pi_[4], qr[4], qi[4], yr[4], yi[4];  // p = alpha_{m-2}, q = alpha_{m-1}
+  bbar_apply<T, TRANS>(w, own, i0, iL, xr, xi, yr, yi, db, lbuf, N, cur, ch, sh);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    pr[q] = xr[q];
+    pi_[q] = xi[q];
+    qr[q] = sA * yr[q] - cA * xr[q];
+    qi[q] = sA * yi[q] - cA * xi[q];
   }
-  for (int m = 1; m < NP; ++m) {
-    // x <- (m == 1 ? A x : 2 A x - prev), with x = alpha_{m-1} on entry
-    T cr[4], ci[4];
+  accumulate(cf[1], qr, qi);
+  T db2[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) db2[q] = (T)2 * sA * db[q];
+  const T c2 = (T)2 * cA;
+  for (int m = 2; m < NP; m += 2) {
+    bbar_apply<T, TRANS>(w, own, i0, iL, qr, qi, yr, yi, db2, lbuf, N, cur, ch, sh);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      cr[q] = xr[q];
-      ci[q] = xi[q];
+      pr[q] = yr[q] - c2 * qr[q] - pr[q];
+      pi_[q] = yi[q] - c2 * qi[q] - pi_[q];
     }
-    bbar_apply<T, TRANS>(w, own, i0, iL, xr, xi, db, lbuf, N, cur, ch, sh);
-    const T two = (m == 1) ? (T)1 : (T)2;
-    const auto cm = cf[m];
+    accumulate(cf[m], pr, pi_);
+    if (m + 1 >= NP) break;
+    bbar_apply<T, TRANS>(w, own, i0, iL, pr, pi_, yr, yi, db2, lbuf, N, cur, ch, sh);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      T nr = two * (sA * xr[q] - cA * cr[q]);
-      T ni = two * (sA * xi[q] - cA * ci[q]);
-      if (m > 1) {
-        nr -= pr[q];
-        ni -= pi_[q];
-      }
-      pr[q] = cr[q];
-      pi_[q] = ci[q];
-      xr[q] = nr;
-      xi[q] = ni;
-      ar[q] += cm.x * nr - cj * cm.y * ni;
-      ai[q] += cm.x * ni + cj * cm.y * nr;
+      qr[q] = yr[q] - c2 * pr[q] - qr[q];
+      qi[q] = yi[q] - c2 * pi_[q] - qi[q];
     }
+    accumulate(cf[m + 1], qr, qi);
   }
 }
 

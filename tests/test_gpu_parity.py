@@ -202,13 +202,15 @@ def test_solve_parity_c2_with_and_without_precond():
 
 @pytest.mark.parametrize("shape", [(4, 8, 0.1, 1.0, 0.0, 1.0), (6, 6, 0.1, 1.0, 0.2, 1.3),
                                    (4, 40, 0.1, 1.0, 0.0, 1.0), (8, 10, 0.1, 0.9, 0.1, 1.2),
-                                   (16, 16, 0.1, 1.0, 0.0, 1.5), (8, 100, 0.1, 1.0, 0.0, 1.0)])
+                                   (16, 16, 0.1, 1.0, 0.0, 1.5), (8, 100, 0.1, 1.0, 0.0, 1.0),
+                                   # transform tiles of 4 (L = 32) and 8/16 sites (L = 64)
+                                   (32, 40, 0.05, 1.0, -0.2, 1.2), (64, 40, 0.05, 1.0, 0.0, 1.5)])
 def test_precond_apply_parity(shape):
     lat = OL.Lattice(*shape)
     rng = np.random.default_rng(11)
     x = rng.standard_normal((lat.Ltau, lat.N))
     v = rng.standard_normal((2, lat.Ltau, lat.N))
-    C = OL.checkerboard_C(lat)
+    C = OL.checkerboard_C(lat) if lat.N <= 256 else OL.sparse_C(lat).tocsr()
     pc = OP.Preconditioner(lat, x, C=C)
     s = make_solver(lat, max_rhs=2)
     s.set_field(tgpu(x))
