@@ -2,12 +2,12 @@
 """Benchmark of the Holstein fermion solve on one MI355X.
 
 One step = one pass of the hot path over the workload: per-field setup
-(E, dbar, preconditioner bounds and Chebyshev tables), the FP32-refined CG
-solve of (M^T M) u = Phi to relative residual 1e-8, the action
-S_F = Phi . u and the phonon force dS_F/dx.  Default workload: L = 32
-(N = 1024), Ltau = 400 (d = 409600), dtau = 0.05, mu = -0.2, alpha = 1.2,
-AR(1)-correlated field; plain CG by default (--precond 1 times the
-preconditioned step instead).
+(E, dbar, preconditioner bounds and Chebyshev tables), the FP32-refined
+preconditioned CG solve of (M^T M) u = Phi to relative residual 1e-8, the
+action S_F = Phi . u and the phonon force dS_F/dx.  Default workload:
+L = 32 (N = 1024), Ltau = 400 (d = 409600), dtau = 0.05, mu = -0.2,
+alpha = 1.2, AR(1)-correlated field.  The Chebyshev orders use
+N_P = floor(db (a1/phi + a2)) with a1 = 0.5, a2 = 1 (--a1, --a2).
 
 Prints one JSON line: the headline (FP32-refined solves/s), the same step
 with FP64 CG, one step of every solver variant, the fused M^T M roofline
@@ -40,10 +40,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--nrhs", type=int, default=1)
-    ap.add_argument("--precond", type=int, default=0,
-                    help="1: preconditioned CG in the timed step; 0: plain CG (default; faster "
-                         "on this workload, the preconditioned step is still timed once); "
+    ap.add_argument("--precond", type=int, default=1,
+                    help="1: preconditioned CG in the timed step (default); 0: plain CG; "
                          "-1: the faster of one trial each")
+    ap.add_argument("--a1", type=float, default=0.5,
+                    help="Chebyshev order coefficient a1 of N_P = floor(db (a1/phi + a2))")
+    ap.add_argument("--a2", type=float, default=1.0)
     ap.add_argument("--matvec-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
@@ -286,9 +288,9 @@ def main():
     tol = 1e-8
     last = {}
 
-    def make_step(prec, pre, variant=0):
+    def make_step(prec, pre, variant=0, a1=args.a1, a2=args.a2):
         def step():
-            s.set_field(x)                                   # setup
+            s.set_field(x, a1=a1, a2=a2)                     # setup
             u, st = s.solve(Phi, tol=tol, prec=prec, precond=pre, variant=variant)   # PCG
             S = s.action(Phi, u)                             # S_F
             g = s.force(u)                                   # dS_F/dx
@@ -297,18 +299,21 @@ def main():
         return step
 
     # One step of each solver variant: FP32-refined and FP64, with and
-    # without the preconditioner, and FP64 single-reduction CG.
+    # without the preconditioner (Chebyshev coefficients a1 as chosen, and
+    # a1 = a2 = 1), FP64 single-reduction CG, the one-launch FP32 solve.
     variants = {}
-    all_variants = (("f32_refined_plain", "f32_refined", False, 0),
-                    ("f32_refined_precond", "f32_refined", True, 0),
-                    ("f64_plain", "f64", False, 0),
-                    ("f32_refined_plain_one_launch", "f32_refined", False, 2),
-                    ("f64_plain_single_reduction", "f64", False, 1),
-                    ("f64_precond", "f64", True, 0))
-    for name, prec, pre_v, var in (() if args.no_variants else all_variants):
+    all_variants = (("f32_refined_plain", "f32_refined", False, 0, args.a1),
+                    ("f32_refined_precond", "f32_refined", True, 0, args.a1),
+                    ("f32_refined_precond_a1_1", "f32_refined", True, 0, 1.0),
+                    ("f64_plain", "f64", False, 0, args.a1),
+                    ("f32_refined_plain_one_launch", "f32_refined", False, 2, args.a1),
+                    ("f64_plain_single_reduction", "f64", False, 1, args.a1),
+                    ("f64_precond", "f64", True, 0, args.a1))
+    for name, prec, pre_v, var, a1v in (() if args.no_variants else all_variants):
         if var == 2 and R != 1:
             continue
-        t, st = time_steps(make_step(prec, pre_v, var), 1, 0, torch)
+        t, st = time_steps(make_step(prec, pre_v, var, a1=a1v, a2=1.0 if a1v == 1.0 else args.a2),
+                           1, 0, torch)
         variants[name] = {"ms": t * 1e3, "iters": st[0]["iters"], "status": st[0]["status"],
                           "rel_resid": st[0]["rel_resid"]}
         log(f"variant {name}: {t * 1e3:.1f} ms, {st[0]['iters']} iterations, status {st[0]['status']}")
@@ -405,6 +410,7 @@ def main():
                         f"mu={p.mu} alpha={p.alpha}; FP32-refined PCG to 1e-8 + S_F + force",
             "nrhs": R,
             "precond": pre,
+            "chebyshev_a1_a2": [args.a1, args.a2] if pre else None,
             "iters": [v["iters"] for v in st32],
             "fp64_refreshes": [v["outer_iters"] for v in st32],
             "rel_resid": [v["rel_resid"] for v in st32],
