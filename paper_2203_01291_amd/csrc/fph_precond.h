@@ -187,9 +187,9 @@ FPH_DEVINL T2 cmulc(T2 a, T2 b) {  // a * conj(b)
 // LDS; with CGUPD it first receives the CG update u += alpha p,
 // r -= alpha Ap (r is `in`, updated in place), publishing |r|^2 as P_RR
 // partials (the direction is pb on even iteration counts, pa on odd).
-// Step 1, item (site, n2): the H1-point DFT over n1 of the twisted input
-// y_tau = e^{-i pi tau/Ltau} (in_tau - i in_{tau+H}), tau = H2 n1 + n2,
-// times W_H^{n2 k1}, into LDS.  Step 2, item (site, k1, k2): the H2-point
+// Step 1, item (site, n2, k1): output k1 of the H1-point DFT over n1 of
+// the twisted input y_tau = e^{-i pi tau/Ltau} (in_tau - i in_{tau+H}),
+// tau = H2 n1 + n2, times W_H^{n2 k1}, into LDS.  Step 2, item (site, k1, k2): the H2-point
 // DFT over n2 -> Z_{k1 + H1 k2}.  Twiddles live in LDS.
 // Launch: grid ntiles * nrhs (ntiles = ceil(N / KS)), NT threads,
 // LDS 2H complex + Ltau KS reals + H KS complex.
@@ -270,30 +270,26 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     }
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < KS * H2; it += NT) {
-    const int sidx = it & (KS - 1), n2 = it >> lks;
-    T2 y[H1];
+  for (int it = threadIdx.x; it < KS * H; it += NT) {
+    // item (sidx, n2, k1): one output of the H1-point DFT over n1
+    const int sidx = it & (KS - 1);
+    const int rest = it >> lks;  // n2 * H1 + k1
+    const int n2 = rest / H1, k1 = rest - n2 * H1;
+    const int step = (H2 * k1) % H;  // W_H1^{n1 k1} = W_H^{H2 n1 k1}
+    int idx = 0;
+    T2 acc = T2{(T)0, (T)0};
 #pragma unroll
     for (int n1 = 0; n1 < H1; ++n1) {
       const int tau = H2 * n1 + n2;
       const T a = Rt[tau * KS + sidx], b = Rt[(tau + H) * KS + sidx];
-      y[n1] = cmul<T2, T>(twl[tau], T2{a, -b});
+      const T2 yv = cmul<T2, T>(twl[tau], T2{a, -b});
+      const T2 wv = Wl[idx];
+      acc.x += wv.x * yv.x - wv.y * yv.y;
+      acc.y += wv.x * yv.y + wv.y * yv.x;
+      idx += step;
+      if (idx >= H) idx -= H;
     }
-#pragma unroll
-    for (int k1 = 0; k1 < H1; ++k1) {
-      const int step = (H2 * k1) % H;  // W_H1^{n1 k1} = W_H^{H2 n1 k1}
-      int idx = 0;
-      T2 acc = T2{(T)0, (T)0};
-#pragma unroll
-      for (int n1 = 0; n1 < H1; ++n1) {
-        const T2 wv = Wl[idx];
-        acc.x += wv.x * y[n1].x - wv.y * y[n1].y;
-        acc.y += wv.x * y[n1].y + wv.y * y[n1].x;
-        idx += step;
-        if (idx >= H) idx -= H;
-      }
-      Y[(n2 * H1 + k1) * KS + sidx] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
-    }
+    Y[rest * KS + sidx] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < KS * H; it += NT) {
@@ -379,26 +375,24 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     }
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < KS * H2; it += NT) {
-    const int sidx = it & (KS - 1), n2 = it >> lks;
-    T2 y[H1];
+  for (int it = threadIdx.x; it < KS * H; it += NT) {
+    // item (sidx, n2, k1): one output of the H1-point DFT over n1
+    const int sidx = it & (KS - 1);
+    const int rest = it >> lks;  // n2 * H1 + k1
+    const int n2 = rest / H1, k1 = rest - n2 * H1;
+    const int step = (H2 * k1) % H;
+    int idx = 0;
+    T2 acc = T2{(T)0, (T)0};
 #pragma unroll
-    for (int n1 = 0; n1 < H1; ++n1) y[n1] = Zt[(H2 * n1 + n2) * KS + sidx];
-#pragma unroll
-    for (int k1 = 0; k1 < H1; ++k1) {
-      const int step = (H2 * k1) % H;
-      int idx = 0;
-      T2 acc = T2{(T)0, (T)0};
-#pragma unroll
-      for (int n1 = 0; n1 < H1; ++n1) {
-        const T2 wv = Wl[idx];  // used conjugated
-        acc.x += wv.x * y[n1].x + wv.y * y[n1].y;
-        acc.y += wv.x * y[n1].y - wv.y * y[n1].x;
-        idx += step;
-        if (idx >= H) idx -= H;
-      }
-      Y[(n2 * H1 + k1) * KS + sidx] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
+    for (int n1 = 0; n1 < H1; ++n1) {
+      const T2 yv = Zt[(H2 * n1 + n2) * KS + sidx];
+      const T2 wv = Wl[idx];  // used conjugated
+      acc.x += wv.x * yv.x + wv.y * yv.y;
+      acc.y += wv.x * yv.y - wv.y * yv.x;
+      idx += step;
+      if (idx >= H) idx -= H;
     }
+    Y[rest * KS + sidx] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < KS * H; it += NT) {
@@ -726,7 +720,8 @@ inline hipError_t pc_set_field(PcTables* pc, const Geom& g, const double* dbar64
 }
 
 // Tile width (log2) of the transforms: up to 64 bytes of a slice row,
-// halved while there are fewer than 512 workgroups.
+// halved while there are fewer than 512 workgroups (not below 2 sites:
+// one-site tiles measured slower).
 template <typename T>
 int pc_tile_log2(const Geom& g, int nrhs) {
   int lks = (sizeof(T) == 8) ? 3 : 4;
