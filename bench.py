@@ -294,7 +294,7 @@ def main():
             u, st = s.solve(Phi, tol=tol, prec=prec, precond=pre, variant=variant)   # PCG
             S = s.action(Phi, u)                             # S_F
             g = s.force(u)                                   # dS_F/dx
-            last["st"], last["S"], last["g"] = st, S, g
+            last["st"], last["S"], last["g"], last["u"] = st, S, g, u
             return st
         return step
 
@@ -325,6 +325,22 @@ def main():
     t32, st32 = time_steps(make_step("f32_refined", pre), args.steps, args.warmup, torch)
     st32 = [dict(v) for v in st32]
     S32 = last["S"].cpu().numpy().tolist()
+    # Error of the timed step's solution and force against the oracle's
+    # stored values (its FP64 CG to relative residual 1e-13, same inputs).
+    err = None
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
+    if R == 1 and os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        idx = np.array(gold["samples"])
+        uh = last["u"].reshape(p.Ltau, p.N).cpu().numpy()[idx[:, 0], idx[:, 1]]
+        gh = last["g"].reshape(p.Ltau, p.N).cpu().numpy()[idx[:, 0], idx[:, 1]]
+        ur, gr = np.array(gold["u_samples"]), np.array(gold["force_samples"])
+        err = {"reference": "oracle FP64 CG to relative residual 1e-13, same inputs (tests/golden)",
+               "components": int(len(idx)), "solve_tol": tol,
+               "u_rel": float(np.linalg.norm(uh - ur) / np.linalg.norm(ur)),
+               "force_rel": float(np.linalg.norm(gh - gr) / np.linalg.norm(gr)),
+               "S_F_rel": float(abs(S32[0] - gold["S_F"]) / abs(gold["S_F"]))}
+        log(f"error vs oracle: {err}")
     log(f"f32_refined: {t32 * 1e3:.2f} ms/step {st32}")
     t64, st64 = time_steps(make_step("f64", pre), max(1, args.steps // 2), min(args.warmup, 1), torch)
     st64 = [dict(v) for v in st64]
@@ -415,6 +431,7 @@ def main():
             "fp64_refreshes": [v["outer_iters"] for v in st32],
             "rel_resid": [v["rel_resid"] for v in st32],
         },
+        "error_vs_oracle": err,
         "fp64_cg": {"solves_per_s": R / t64, "ms_per_step": t64 * 1e3,
                     "iters": [v["iters"] for v in st64],
                     "speedup_fp32_refined": t64 / t32,
