@@ -348,3 +348,22 @@ def test_force_multi_rhs_shape():
     assert g.shape == u.shape
     for r in range(3):
         assert np.allclose(g[r], F.force_from_solution(lat, x, u[r]))
+
+
+def test_stored_full_size_values_match_sparse_direct_solve():
+    """The stored L=16, Ltau=160 values (written by the oracle's CG) against
+    a sparse LU solve of M and M^T at full size: two independent solvers."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_c2.json")))
+    p = get_config("c2")
+    lat = Lm.Lattice.from_params(p)
+    x0 = phonon_field(p)
+    x = perturbed_field(p, x0)
+    Cs = Lm.sparse_C(lat)
+    phi = gaussian_rhs(p, 1)[0]
+    Phi = (Lm.sparse_M(lat, x0, Cs).T @ phi.reshape(-1)).reshape(lat.Ltau, lat.N)
+    u = S.solve_sparse(lat, x, Phi[None], Cs)[0]
+    idx = np.array(ref["samples"])
+    us = u[idx[:, 0], idx[:, 1]]
+    assert np.linalg.norm(us - ref["u_samples"]) <= 1e-10 * np.linalg.norm(ref["u_samples"])
+    assert abs(float(np.sum(Phi * u)) - ref["S_F"]) <= 1e-12 * abs(ref["S_F"])
+    assert float(np.linalg.norm(u)) == pytest.approx(ref["u_norm"], rel=1e-11)
