@@ -152,6 +152,13 @@ def bench_batched(torch, dev, log):
     iters = [v["iters"] for v in st]
     conv = sum(1 for v in st if v["status"] & 1)
     dsum = sum(L * L * p.Ltau * (p.n_gauss + p.n_rademacher) for L in Ls)
+    # Algorithmic traffic of the whole batch: per FP32 CG iteration the
+    # operator pass (read r, p_old, E; write p, Ap) and the update pass (read
+    # u, p, r, Ap; write u, r), 11 vectors of 4 bytes; per FP64 residual
+    # replacement the FP64 operator on u with b (read u, E, b; write r32)
+    # and the accumulation of u (read u32, u; write u), 7 vectors of 8 bytes.
+    per_rhs_d = [L * L * p.Ltau for L in Ls for _ in range(p.n_gauss + p.n_rademacher)]
+    alg_bytes = sum(d_i * (44 * v["iters"] + 56 * v["outer_iters"]) for d_i, v in zip(per_rhs_d, st))
     res = {
         "workload": f"{p.name}: 64 systems, L in {sorted(set(Ls))}, Ltau={p.Ltau}, "
                     f"{p.n_gauss}+{p.n_rademacher} rhs each, FP32 CG + FP64 residual "
@@ -159,6 +166,7 @@ def bench_batched(torch, dev, log):
         "solves": nrhs, "converged": conv,
         "seconds": dt, "solves_per_s": nrhs / dt, "systems_per_s": len(Ls) / dt,
         "unknowns_total": dsum,
+        "algorithmic_bytes": alg_bytes, "algorithmic_GB/s": alg_bytes / dt / 1e9,
         "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
         "max_rel_resid": float(max(v["rel_resid"] for v in st)),
         "tuned_shape": best, "tune_seconds": tune_s,
@@ -317,6 +325,26 @@ def main():
         variants[name] = {"ms": t * 1e3, "iters": st[0]["iters"], "status": st[0]["status"],
                           "rel_resid": st[0]["rel_resid"]}
         log(f"variant {name}: {t * 1e3:.1f} ms, {st[0]['iters']} iterations, status {st[0]['status']}")
+    # The paper's action sums over two pseudofermion fields (spin up and
+    # down) sharing one phonon field: both solves in one call (two
+    # right-hand sides), action and force of both.
+    two_fields = None
+    if not args.no_variants and R == 1:
+        s2 = FermionSolver.from_params(p, max_rhs=2)
+        s2.set_field(x0)
+        Phi2 = s2.matvec(torch.from_numpy(gaussian_rhs(p, 2)).to(dev), "MT")
+
+        def step2():
+            s2.set_field(x, a1=args.a1, a2=args.a2)
+            u2, st = s2.solve(Phi2, tol=tol, prec="f32_refined", precond=True)
+            s2.action(Phi2, u2)
+            s2.force(u2, scale=0.5)
+            return st
+        t2, st2 = time_steps(step2, 1, 1, torch)
+        two_fields = {"ms_per_step": t2 * 1e3, "solves_per_s": 2 / t2,
+                      "iters": [v["iters"] for v in st2], "status": [v["status"] for v in st2]}
+        log(f"two fields: {two_fields}")
+        s2.close()
     if args.precond < 0 and variants:
         pre = variants["f32_refined_precond"]["ms"] < variants["f32_refined_plain"]["ms"]
     else:
@@ -446,6 +474,7 @@ def main():
         "matvec_large": large,
         "batched": batch,
         "variants": variants,
+        "two_fields": two_fields,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
