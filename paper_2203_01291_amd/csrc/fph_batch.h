@@ -20,7 +20,7 @@ namespace fph {
 
 struct BatchItem {
   Geom g;
-  double ch, sh;          // cosh(dtau t), sinh(dtau t)
+  double th;              // tanh(dtau t); E64/E32 hold ch^4 E
   const double* E64;      // [Ltau][N] of the item's system
   const float* E32;
   const double* b;        // right-hand side [Ltau][N]
@@ -144,7 +144,7 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
       InDir<float> in{it.r, pold, pnew, (float)beta, fresh};
       EpiDot<float> epi{it.Ap};
       double acc = 0.0, acc2 = 0.0;
-      mtm_sweep<float, NT, MS, 1>(g, it.E32, (float)it.ch, (float)it.sh, Tch, tau0, Tc, active,
+      mtm_sweep<float, NT, MS, 1>(g, it.E32, (float)it.th, Tch, tau0, Tc, active,
                                   lane, nslot, lds4, 0, in, epi, acc, acc2, [] { return true; });
       const double pAp = block_allsum<NT>(acc, red_sh, bcast);
       matvecs += 1;
@@ -188,7 +188,7 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
       InPlain<double> in{it.u};
       EpiResidual<float> epi{it.b, it.r};
       double acc = 0.0, acc2 = 0.0;
-      mtm_sweep<double, NT, MS, 1>(g, it.E64, it.ch, it.sh, Tch, tau0, Tc, active, lane, nslot,
+      mtm_sweep<double, NT, MS, 1>(g, it.E64, it.th, Tch, tau0, Tc, active, lane, nslot,
                                    lds4, 0, in, epi, acc, acc2, [] { return true; });
       rr_true = block_allsum<NT>(acc, red_sh, bcast);
     }

@@ -33,26 +33,29 @@ template <> struct Vec4<double> {
 
 // ------------------------------------------------------------- set field
 
-// E = exp(-dtau (alpha x - mu)) in FP64 and its FP32 rounding (Eq. B_def).
+// E = exp(-dtau (alpha x - mu)) (Eq. B_def) times c4 = cosh(dtau t)^4, the
+// factor the operator kernels take out of the checkerboard, in FP64 and its
+// FP32 rounding.
 __global__ void k_set_field(long n, const double* __restrict__ x, double dtau,
-                            double alpha, double mu, double* __restrict__ E64,
+                            double alpha, double mu, double c4, double* __restrict__ E64,
                             float* __restrict__ E32) {
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
        k += (long)gridDim.x * blockDim.x) {
-    const double e = exp(-dtau * (alpha * x[k] - mu));
+    const double e = c4 * exp(-dtau * (alpha * x[k] - mu));
     E64[k] = e;
     E32[k] = (float)e;
   }
 }
 
-// dbar_i = (1/Ltau) sum_tau E[tau][i] (Eq. expnVbar), summed in tau order.
-__global__ void k_dbar(int N, int Ltau, const double* __restrict__ E64,
+// dbar_i = (1/Ltau) sum_tau E[tau][i] (Eq. expnVbar), summed in tau order,
+// from the stored c4 E.
+__global__ void k_dbar(int N, int Ltau, const double* __restrict__ E64, double c4,
                        double* __restrict__ dbar64, float* __restrict__ dbar32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double s = 0.0;
   for (int tau = 0; tau < Ltau; ++tau) s += E64[(long)tau * N + i];
-  s /= (double)Ltau;
+  s /= (double)Ltau * c4;
   dbar64[i] = s;
   dbar32[i] = (float)s;
 }

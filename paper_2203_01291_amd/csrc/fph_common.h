@@ -2,7 +2,8 @@
 //
 // Layout (everything site-fastest): a right-hand side is [Ltau][N] with
 // site i = x + L*y; several right-hand sides follow each other.  The field
-// enters only through E[tau][i] = exp(-dtau*(alpha*x - mu)).
+// enters only through E[tau][i] = exp(-dtau*(alpha*x - mu)), which the
+// operator kernels read pre-multiplied by ch^4 (see below).
 //
 // Checkerboard: C = P_A P_B (P_B acts first).  P_A mixes the four sites of
 // each plaquette with even corner (x0, y0); P_B those with odd corner,
@@ -10,6 +11,13 @@
 // C2 = [[ch, sh], [sh, ch]], ch = cosh(dtau t), sh = sinh(dtau t)
 // (Sec. II D of the paper; the split itself is the reading documented with
 // the C header).  Both factors are symmetric, so C^T = P_B P_A.
+//
+// The kernels apply C2 = ch C2' with C2' = [[1, th], [th, 1]],
+// th = tanh(dtau t): then P_A P_B = ch^4 P'_A P'_B, each output of a primed
+// factor costs one fused multiply-add instead of a multiply and a
+// multiply-add, and ch^4 is folded into the stored E (M's off-diagonal
+// blocks are E C = (ch^4 E) C').  So every E buffer the operator kernels
+// read holds ch^4 exp(-dtau (alpha x - mu)).
 //
 // Thread mapping used by every operator kernel: a thread owns one or more
 // plaquettes of the even grid ("even layout": sites (x0,y0), (x0+1,y0),
@@ -80,17 +88,17 @@ FPH_DEVINL void odd_sites(const Geom& g, int q, int s[4]) {
   s[3] = xb + g.L * yb;
 }
 
-// kron(C2, C2) on one plaquette, local order index = dx + 2*dy.
+// kron(C2', C2') on one plaquette, local order index = dx + 2*dy.
 template <typename T>
-FPH_DEVINL void plaq_rot(T v[4], T ch, T sh) {
-  T a0 = ch * v[0] + sh * v[1];
-  T a1 = sh * v[0] + ch * v[1];
-  T a2 = ch * v[2] + sh * v[3];
-  T a3 = sh * v[2] + ch * v[3];
-  v[0] = ch * a0 + sh * a2;
-  v[2] = sh * a0 + ch * a2;
-  v[1] = ch * a1 + sh * a3;
-  v[3] = sh * a1 + ch * a3;
+FPH_DEVINL void plaq_rot(T v[4], T th) {
+  const T a0 = fma(th, v[1], v[0]);
+  const T a1 = fma(th, v[0], v[1]);
+  const T a2 = fma(th, v[3], v[2]);
+  const T a3 = fma(th, v[2], v[3]);
+  v[0] = fma(th, a2, a0);
+  v[2] = fma(th, a0, a2);
+  v[1] = fma(th, a3, a1);
+  v[3] = fma(th, a1, a3);
 }
 
 // ------------------------------------------------------------ solver state

@@ -230,8 +230,8 @@ struct CoopStats {
 
 struct CoopArgs {
   Geom g;
-  float ch32, sh32;
-  double ch, sh;
+  float th32;   // tanh(dtau t) (the E buffers hold ch^4 E)
+  double th;
   const float* E32;
   const double* E64;
   const double* b;
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(NT) k_cg_coop(CoopArgs a) {
     double acc = 0.0, acc2 = 0.0;
     InCoopU in{a.u};
     EpiCoopResidual epi{a.b, a.r};
-    mtm_sweep<double, NT, 1, 2>(g, a.E64, a.ch, a.sh, a.Tch, tau0, Tc, active, lane, nslot,
+    mtm_sweep<double, NT, 1, 2>(g, a.E64, a.th, a.Tch, tau0, Tc, active, lane, nslot,
                                 reinterpret_cast<double*>(lds), 0, in, epi, acc, acc2, no_hook);
     const bool ok = coop_exchange<NT>(a.x, phase++, blk, acc, acc2, red_sh, tot_sh, &ok_sh, tot);
     rr = tot[0];
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(NT) k_cg_coop(CoopArgs a) {
       double acc = 0.0, acc2 = 0.0;
       InCoopDir in{a.r, pold, pnew, (float)beta, fresh};
       EpiCoopAp epi{a.Ap};
-      mtm_sweep<float, NT, 1, 2>(g, a.E32, a.ch32, a.sh32, a.Tch, tau0, Tc, active, lane, nslot,
+      mtm_sweep<float, NT, 1, 2>(g, a.E32, a.th32, a.Tch, tau0, Tc, active, lane, nslot,
                                  reinterpret_cast<float*>(lds), 0, in, epi, acc, acc2, no_hook);
       ok = coop_exchange<NT>(a.x, phase++, blk, acc, 0.0, red_sh, tot_sh, &ok_sh, tot);
       if (!ok) break;

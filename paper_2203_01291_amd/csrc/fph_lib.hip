@@ -47,6 +47,7 @@ struct fph_handle_s {
   int max_rhs;
   int device;
   double ch, sh;  // cosh(dtau t), sinh(dtau t)
+  double th, c4;  // tanh(dtau t), ch^4 (operator kernels: C = c4 C', E stored as c4 E)
   bool have_field;
   double a1, a2;
   // field
@@ -143,7 +144,7 @@ hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, In in, Epi epi, State
                      : StIO{nullptr, nullptr, nullptr, nullptr, 0, 0};
   hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g,
                      (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32),
-                     (T)h->ch, (T)h->sh, Tch, nblk, in, epi, io);
+                     (T)h->th, Tch, nblk, in, epi, io);
   return hipGetLastError();
 }
 
@@ -176,7 +177,7 @@ hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, dou
   }
   const T* E = (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32);
   hipLaunchKernelGGL(kern, dim3(nblk, MODE == 0 ? nrhs : 1), dim3(NT), lds, s, g, E,
-                     (T)h->ch, (T)h->sh, 1, nrhs, v, out, coef);
+                     (T)h->th, 1, nrhs, v, out, coef);
   return hipGetLastError();
 }
 
@@ -202,7 +203,7 @@ hipError_t launch_MT_cfg(const fph_handle_s* h, int nrhs, const T* w, T* out, hi
     if (e != hipSuccess) return e;
   }
   const T* E = (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32);
-  hipLaunchKernelGGL(kern, dim3(nblk, nrhs), dim3(NT), lds, s, g, E, (T)h->ch, (T)h->sh, 1,
+  hipLaunchKernelGGL(kern, dim3(nblk, nrhs), dim3(NT), lds, s, g, E, (T)h->th, 1,
                      w, out);
   return hipGetLastError();
 }
@@ -263,6 +264,8 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   h->max_rhs = max_rhs;
   h->ch = std::cosh(lat->dtau * lat->t);
   h->sh = std::sinh(lat->dtau * lat->t);
+  h->th = std::tanh(lat->dtau * lat->t);
+  h->c4 = h->ch * h->ch * h->ch * h->ch;
   h->a1 = h->a2 = 1.0;
   hipError_t e = hipGetDevice(&h->device);
   const long d = h->g.d;
@@ -303,6 +306,8 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   if (e == hipSuccess) e = pc_create(&h->pc, h->g, max_rhs);
   h->pc.ch = h->ch;
   h->pc.sh = h->sh;
+  h->pc.th = h->th;
+  h->pc.c4 = h->c4;
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     fph_destroy(h);
@@ -336,10 +341,10 @@ int fph_set_field(fph_handle_t h, const double* x_dev, double a1, double a2, voi
   h->a1 = a1 > 0.0 ? a1 : 1.0;
   h->a2 = a2 > 0.0 ? a2 : 1.0;
   hipLaunchKernelGGL(k_set_field, dim3(elem_blocks(d)), dim3(256), 0, s, d, x_dev,
-                     h->lat.dtau, h->lat.alpha, h->lat.mu, h->E64, h->E32);
+                     h->lat.dtau, h->lat.alpha, h->lat.mu, h->c4, h->E64, h->E32);
   FPH_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_dbar, dim3((h->g.N + 255) / 256), dim3(256), 0, s, h->g.N, h->g.Ltau,
-                     h->E64, h->dbar64, h->dbar32);
+                     h->E64, h->c4, h->dbar64, h->dbar32);
   FPH_CHECK(hipGetLastError());
   FPH_CHECK(pc_set_field(&h->pc, h->g, h->dbar64, h->lat.dtau, h->lat.t, h->a1, h->a2, s));
   h->have_field = true;
@@ -578,10 +583,8 @@ hipError_t coop_launch(fph_handle_s* h, const double* b, double* u, const fph_pc
   if ((e = hipGetLastError()) != hipSuccess) return e;
   CoopArgs a;
   a.g = g;
-  a.ch32 = (float)h->ch;
-  a.sh32 = (float)h->sh;
-  a.ch = h->ch;
-  a.sh = h->sh;
+  a.th32 = (float)h->th;
+  a.th = h->th;
   a.E32 = h->E32;
   a.E64 = h->E64;
   a.b = b;
@@ -897,8 +900,10 @@ hipError_t batch_enqueue(fph_batch_s* b, double tol, int maxiter, double delta, 
   for (int k = 0; k < b->nsys; ++k) {
     const fph_lattice_t& L = b->sys[k].lat;
     const long d = (long)L.L * L.L * L.Ltau;
+    const double ch = std::cosh(L.dtau * L.t);
     hipLaunchKernelGGL(k_set_field, dim3(elem_blocks(d)), dim3(256), 0, s, d, b->sys[k].x_dev,
-                       L.dtau, L.alpha, L.mu, b->E64 + b->eoff[k], b->E32 + b->eoff[k]);
+                       L.dtau, L.alpha, L.mu, ch * ch * ch * ch, b->E64 + b->eoff[k],
+                       b->E32 + b->eoff[k]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1009,8 +1014,7 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
       BatchItem it;
       std::memset(&it, 0, sizeof(it));
       it.g = g;
-      it.ch = std::cosh(L.dtau * L.t);
-      it.sh = std::sinh(L.dtau * L.t);
+      it.th = std::tanh(L.dtau * L.t);
       it.E64 = b->E64 + eo;
       it.E32 = b->E32 + eo;
       it.b = sys[k].b_dev + (long)j * g.d;

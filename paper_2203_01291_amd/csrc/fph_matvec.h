@@ -424,10 +424,10 @@ FPH_DEVINL void block_layout(const Geom& g, int tid, int& S, int& sub, int& lane
 // from the slice in LDS: the odd plaquettes covering those sites span the
 // 4x4 window x0-1..x0+2, y0-1..y0+2 (periodic).  Site (dx, dy) of the even
 // plaquette is local site (1-dx, 1-dy) of its odd plaquette, so with
-// C2 = [[ch, sh], [sh, ch]] along each axis
-//   out(dx, dy) = sum_{a,b} c(1-dy, b) c(1-dx, a) W[2dy + b][2dx + a].
+// C2' = [[1, th], [th, 1]] along each axis (P'_B, P_B = ch^2 P'_B)
+//   out(dx, dy) = sum_{a,b} c'(1-dy, b) c'(1-dx, a) W[2dy + b][2dx + a].
 template <typename T>
-FPH_DEVINL void pb_window(const Geom& g, const T* __restrict__ sl, int x0, int y0, T ch, T sh,
+FPH_DEVINL void pb_window(const Geom& g, const T* __restrict__ sl, int x0, int y0, T th,
                           T out[4]) {
   const int xm = (x0 == 0) ? g.L - 1 : x0 - 1;
   const int xp = (x0 + 2 == g.L) ? 0 : x0 + 2;
@@ -441,13 +441,13 @@ FPH_DEVINL void pb_window(const Geom& g, const T* __restrict__ sl, int x0, int y
     T a, b;
     ld2(row + x0, a, b);
     const T wm = row[xm], wp = row[xp];
-    h0[rr] = sh * wm + ch * a;
-    h1[rr] = ch * b + sh * wp;
+    h0[rr] = fma(th, wm, a);
+    h1[rr] = fma(th, wp, b);
   }
-  out[0] = sh * h0[0] + ch * h0[1];
-  out[1] = sh * h1[0] + ch * h1[1];
-  out[2] = ch * h0[2] + sh * h0[3];
-  out[3] = ch * h1[2] + sh * h1[3];
+  out[0] = fma(th, h0[0], h0[1]);
+  out[1] = fma(th, h1[0], h1[1]);
+  out[2] = fma(th, h0[3], h0[2]);
+  out[3] = fma(th, h1[3], h1[2]);
 }
 
 // The fused M^T M sweep of one chunk of slices [tau0, tau0 + Tc) of one
@@ -465,7 +465,7 @@ FPH_DEVINL void pb_window(const Geom& g, const T* __restrict__ sl, int x0, int y
 // In::kPrefetch the loads of the first slices are issued before the hook,
 // so they overlap the state's memory round trip.
 template <typename T, int NT, int MAXSLOT, int DEPTH, class In, class Epi, class Hook>
-FPH_DEVINL bool mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, int Tch, int tau0,
+FPH_DEVINL bool mtm_sweep(const Geom& g, const T* __restrict__ E, T th, int Tch, int tau0,
                           int Tc, bool active, int lane, int nslot, T* lds4, long base,
                           In& in, Epi& epi, double& acc, double& acc2, Hook&& hook) {
   static_assert(DEPTH == 1 || DEPTH == 2, "DEPTH is 1 or 2");
@@ -583,14 +583,14 @@ FPH_DEVINL bool mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
           in.use2(toff + i0, cr[k][0], nv[k][0], nv[k][1], j < Tc, early);
           in.use2(toff + i0 + g.L, cr[k][1], nv[k][2], nv[k][3], j < Tc, early);
           T t[4];
-          pb_window(g, Acur, x0, y0, ch, sh, t);
-          plaq_rot(t, ch, sh);
+          pb_window(g, Acur, x0, y0, th, t);
+          plaq_rot(t, th);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             wcur[k][m] = sg * (nv[k][m] - ne[k][m] * t[m]);
             t[m] = ne[k][m] * wcur[k][m];
           }
-          plaq_rot(t, ch, sh);
+          plaq_rot(t, th);
           st2(Bcur + i0, t[0], t[1]);
           st2(Bcur + i0 + g.L, t[2], t[3]);
           st2(Anext + i0, nsg * nv[k][0], nsg * nv[k][1]);
@@ -609,7 +609,7 @@ FPH_DEVINL bool mtm_sweep(const Geom& g, const T* __restrict__ E, T ch, T sh, in
           const int i0 = x0 + g.L * y0;
           if (j >= 1) {
             T t[4];
-            pb_window(g, Bcur, x0, y0, ch, sh, t);
+            pb_window(g, Bcur, x0, y0, th, t);
             epi.put2(ooff + i0, wprev[k][0] - t[0], wprev[k][1] - t[1], vprev[k][0],
                      vprev[k][1], acc, acc2);
             epi.put2(ooff + i0 + g.L, wprev[k][2] - t[2], wprev[k][3] - t[3], vprev[k][2],
@@ -643,7 +643,7 @@ constexpr int mtm_min_waves() {
 
 template <typename T, int NT, int MAXSLOT, class In, class Epi>
 __global__ void __launch_bounds__(NT, (mtm_min_waves<T, NT, Epi>()))
-k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi epi, StIO io) {
+k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi, StIO io) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
@@ -683,7 +683,7 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi
   T* lds4 = reinterpret_cast<T*>(smem_raw) + 4L * (sub < S ? sub : 0) * g.N;
   const long base = (long)r * g.d;
   double acc = 0.0, acc2 = 0.0;
-  if (!mtm_sweep<T, NT, MAXSLOT, 1>(g, E, ch, sh, Tch, tau0, Tc, active, lane, nslot, lds4,
+  if (!mtm_sweep<T, NT, MAXSLOT, 1>(g, E, th, Tch, tau0, Tc, active, lane, nslot, lds4,
                                     base, in, epi, acc, acc2, hook))
     return;
 
@@ -706,7 +706,7 @@ k_mtm(Geom g, const T* __restrict__ E, T ch, T sh, int Tch, int nblk, In in, Epi
 // block handles `per` slices.  LDS: S * N elements.
 template <typename T, int NT, int MAXSLOT, int MODE>
 __global__ void __launch_bounds__(NT)
-k_apply_M(Geom g, const T* __restrict__ E, T ch, T sh, int per, int nrhs,
+k_apply_M(Geom g, const T* __restrict__ E, T th, int per, int nrhs,
           const T* __restrict__ v, T* __restrict__ out, double coef) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -753,7 +753,7 @@ k_apply_M(Geom g, const T* __restrict__ E, T ch, T sh, int per, int nrhs,
             T t[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) t[m] = psg * v[base + (long)pt * g.N + s[m]];
-            plaq_rot(t, ch, sh);
+            plaq_rot(t, th);
 #pragma unroll
             for (int m = 0; m < 4; ++m) buf[s[m]] = t[m];
           }
@@ -770,7 +770,7 @@ k_apply_M(Geom g, const T* __restrict__ E, T ch, T sh, int per, int nrhs,
             T t[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) t[m] = buf[s[m]];
-            plaq_rot(t, ch, sh);
+            plaq_rot(t, th);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
               const long off = (long)tau * g.N + s[m];
@@ -810,7 +810,7 @@ k_apply_M(Geom g, const T* __restrict__ E, T ch, T sh, int per, int nrhs,
 // out = M^T w.  Launch and LDS as k_apply_M (mode 0).
 template <typename T, int NT, int MAXSLOT>
 __global__ void __launch_bounds__(NT)
-k_apply_MT(Geom g, const T* __restrict__ E, T ch, T sh, int per,
+k_apply_MT(Geom g, const T* __restrict__ E, T th, int per,
            const T* __restrict__ w, T* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -852,7 +852,7 @@ k_apply_MT(Geom g, const T* __restrict__ E, T ch, T sh, int per,
             const long off = (long)nt * g.N + s[m];
             t[m] = sg * E[off] * w[base + off];
           }
-          plaq_rot(t, ch, sh);
+          plaq_rot(t, th);
 #pragma unroll
           for (int m = 0; m < 4; ++m) buf[s[m]] = t[m];
         }
@@ -869,7 +869,7 @@ k_apply_MT(Geom g, const T* __restrict__ E, T ch, T sh, int per,
           T t[4];
 #pragma unroll
           for (int m = 0; m < 4; ++m) t[m] = buf[s[m]];
-          plaq_rot(t, ch, sh);
+          plaq_rot(t, th);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             const long off = base + (long)tau * g.N + s[m];

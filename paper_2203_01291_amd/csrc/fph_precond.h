@@ -48,6 +48,7 @@ struct PcTables {
   void* Z;         // complex workspace, max_rhs * H * N (double2)
   void* Z2;
   double ch, sh;   // checkerboard rotation cosh(dtau t), sinh(dtau t)
+  double th, c4;   // tanh(dtau t) and ch^4: P_A P_B = c4 P'_A P'_B, C2' = [[1, th], [th, 1]]
 };
 
 // First factor of the length-H DFT split H = H1 * H2: at most 10 when
@@ -471,12 +472,16 @@ FPH_DEVINL void st2c(double2* p, double ar, double ai, double br, double bi) {
   p[1] = make_double2(br, bi);
 }
 
-// P_B of a complex slice in LDS at the four sites of the thread's even
-// plaquette: with C2 = [[ch, sh], [sh, ch]] per axis,
-//   out(dx, dy) = sum_{a,b} c(1-dy, b) c(1-dx, a) W[2dy + b][2dx + a].
+// The Chebyshev kernel applies the checkerboard in the primed form of the
+// operator kernels (C = ch^4 P'_A P'_B, C2' = [[1, th], [th, 1]]); here
+// ch^4 joins the diagonal dbar, which the recurrence applies anyway.
+
+// P'_B of a complex slice in LDS at the four sites of the thread's even
+// plaquette: with C2' = [[1, th], [th, 1]] per axis,
+//   out(dx, dy) = sum_{a,b} c'(1-dy, b) c'(1-dx, a) W[2dy + b][2dx + a].
 template <typename T>
-FPH_DEVINL void pb_window_c(const Win& w, const typename Cplx<T>::type* __restrict__ sl, T ch,
-                            T sh, T (&re)[4], T (&im)[4]) {
+FPH_DEVINL void pb_window_cn(const Win& w, const typename Cplx<T>::type* __restrict__ sl, T th,
+                             T (&re)[4], T (&im)[4]) {
   using T2 = typename Cplx<T>::type;
   T h0r[4], h0i[4], h1r[4], h1i[4];
 #pragma unroll
@@ -485,117 +490,132 @@ FPH_DEVINL void pb_window_c(const Win& w, const typename Cplx<T>::type* __restri
     T2 a, b;
     ld2c(row + w.x0, a, b);
     const T2 wm = row[w.xm], wp = row[w.xp];
-    h0r[rr] = sh * wm.x + ch * a.x;
-    h0i[rr] = sh * wm.y + ch * a.y;
-    h1r[rr] = ch * b.x + sh * wp.x;
-    h1i[rr] = ch * b.y + sh * wp.y;
+    h0r[rr] = fma(th, wm.x, a.x);
+    h0i[rr] = fma(th, wm.y, a.y);
+    h1r[rr] = fma(th, wp.x, b.x);
+    h1i[rr] = fma(th, wp.y, b.y);
   }
-  re[0] = sh * h0r[0] + ch * h0r[1];
-  im[0] = sh * h0i[0] + ch * h0i[1];
-  re[1] = sh * h1r[0] + ch * h1r[1];
-  im[1] = sh * h1i[0] + ch * h1i[1];
-  re[2] = ch * h0r[2] + sh * h0r[3];
-  im[2] = ch * h0i[2] + sh * h0i[3];
-  re[3] = ch * h1r[2] + sh * h1r[3];
-  im[3] = ch * h1i[2] + sh * h1i[3];
+  re[0] = fma(th, h0r[0], h0r[1]);
+  im[0] = fma(th, h0i[0], h0i[1]);
+  re[1] = fma(th, h1r[0], h1r[1]);
+  im[1] = fma(th, h1i[0], h1i[1]);
+  re[2] = fma(th, h0r[3], h0r[2]);
+  im[2] = fma(th, h0i[3], h0i[2]);
+  re[3] = fma(th, h1r[3], h1r[2]);
+  im[3] = fma(th, h1i[3], h1i[2]);
 }
 
-// y = Bbar x (TRANS = false: dbar * P_A (P_B x)) or Bbar^T x (TRANS = true:
-// P_B (P_A (dbar * x))) for a complex vector held one even plaquette per
-// thread; x is left unchanged.  One LDS exchange per apply: the thread
-// publishes its four sites (x, or P_A(dbar x)) into buffer `cur` and after
-// one barrier forms P_B at its sites from the window.  Buffers alternate
-// between applies, so one barrier per apply suffices.  Threads without a
-// plaquette only keep the barrier.  `db` may carry a scale factor.
+// y = C' x (TRANS = false: P'_A (P'_B x)) or C'^T x (TRANS = true:
+// P'_B (P'_A x)), C = ch^4 C', for a complex vector held one even
+// plaquette per thread; x is left
+// unchanged.  One LDS exchange per apply: the thread publishes its four
+// sites (x, or P_A x) into buffer `cur` and after one barrier forms P_B at
+// its sites from the window.  Buffers alternate between applies, so one
+// barrier per apply suffices.  Threads without a plaquette only keep the
+// barrier.  The diagonal (dbar ch^4) of Bbar is applied by the caller.
 template <typename T, bool TRANS>
-FPH_DEVINL void bbar_apply(const Win& w, bool own, int i0, int iL, const T (&xr)[4],
-                           const T (&xi)[4], T (&yr)[4], T (&yi)[4], const T (&db)[4],
-                           typename Cplx<T>::type* lbuf, int N, int& cur, T ch, T sh) {
+FPH_DEVINL void c_apply(const Win& w, bool own, int i0, int iL, const T (&xr)[4],
+                        const T (&xi)[4], T (&yr)[4], T (&yi)[4],
+                        typename Cplx<T>::type* lbuf, int N, int& cur, T th) {
   using T2 = typename Cplx<T>::type;
   T2* buf = lbuf + (long)cur * N;
   if (own) {
     T tr[4], ti[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      tr[m] = TRANS ? xr[m] * db[m] : xr[m];
-      ti[m] = TRANS ? xi[m] * db[m] : xi[m];
+      tr[m] = xr[m];
+      ti[m] = xi[m];
     }
     if (TRANS) {
-      plaq_rot(tr, ch, sh);
-      plaq_rot(ti, ch, sh);
+      plaq_rot(tr, th);
+      plaq_rot(ti, th);
     }
     st2c(buf + i0, tr[0], ti[0], tr[1], ti[1]);
     st2c(buf + iL, tr[2], ti[2], tr[3], ti[3]);
   }
   __syncthreads();
   if (own) {
-    pb_window_c<T>(w, buf, ch, sh, yr, yi);
+    pb_window_cn<T>(w, buf, th, yr, yi);
     if (!TRANS) {
-      plaq_rot(yr, ch, sh);
-      plaq_rot(yi, ch, sh);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        yr[m] *= db[m];
-        yi[m] *= db[m];
-      }
+      plaq_rot(yr, th);
+      plaq_rot(yi, th);
     }
   }
   cur ^= 1;
 }
 
 // acc = sum_{m < NP} c'_m T_m(A') x with A' = A (TRANS false, c' = c) or
-// A' = A^T (TRANS true, c' = conj(c)), A = sA Bbar - cA; three-term
-// recurrence of Eq. alpha_recur.  For m >= 2 the factor 2 sA is folded
-// into the diagonal (alpha_m = (2 sA Bbar) alpha_{m-1} - 2 cA alpha_{m-1}
-// - alpha_{m-2}), and the two latest terms alternate between two register
-// sets, so no copies are made.
+// A' = A^T (TRANS true, c' = conj(c)), A = sA D C' - cA, D = diag(dbar ch^4)
+// (db holds its entries);
+// three-term recurrence of Eq. alpha_recur,
+//   alpha_m = 2 sA D (C alpha_{m-1}) - 2 cA alpha_{m-1} - alpha_{m-2},
+// with D folded into the fused multiply-add that forms alpha_m.  For A^T
+// the recurrence runs on beta_m = D alpha_m, which obeys the same
+// relation with C'^T in place of C' (D A^T D^{-1} = sA D C'^T - cA):
+// beta_0 = D x, and the sum is scaled by D^{-1} at the end.  The two
+// latest terms alternate between two register sets, so no copies are made.
 template <typename T, bool TRANS>
 FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int NP,
                             const typename Cplx<T>::type* cf, T sA, T cA, const T (&xr)[4],
                             const T (&xi)[4], const T (&db)[4], typename Cplx<T>::type* lbuf,
-                            int& cur, T ch, T sh, T (&ar)[4], T (&ai)[4]) {
+                            int& cur, T th, T (&ar)[4], T (&ai)[4]) {
   const T cj = TRANS ? (T)-1 : (T)1;
   auto accumulate = [&](const typename Cplx<T>::type c, const T (&vr)[4], const T (&vi)[4]) {
+    const T cy = cj * c.y;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      ar[q] += c.x * vr[q] - cj * c.y * vi[q];
-      ai[q] += c.x * vi[q] + cj * c.y * vr[q];
+      ar[q] = fma(-cy, vi[q], fma(c.x, vr[q], ar[q]));
+      ai[q] = fma(cy, vr[q], fma(c.x, vi[q], ai[q]));
     }
   };
-#pragma unroll
-  for (int q = 0; q < 4; ++q) ar[q] = ai[q] = (T)0;
-  accumulate(cf[0], xr, xi);
-  if (NP < 2) return;
   T pr[4], pi_[4], qr[4], qi[4], yr[4], yi[4];  // p = alpha_{m-2}, q = alpha_{m-1}
-  bbar_apply<T, TRANS>(w, own, i0, iL, xr, xi, yr, yi, db, lbuf, N, cur, ch, sh);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    pr[q] = xr[q];
-    pi_[q] = xi[q];
-    qr[q] = sA * yr[q] - cA * xr[q];
-    qi[q] = sA * yi[q] - cA * xi[q];
+    ar[q] = ai[q] = (T)0;
+    pr[q] = TRANS ? db[q] * xr[q] : xr[q];
+    pi_[q] = TRANS ? db[q] * xi[q] : xi[q];
   }
-  accumulate(cf[1], qr, qi);
-  T db2[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) db2[q] = (T)2 * sA * db[q];
-  const T c2 = (T)2 * cA;
-  for (int m = 2; m < NP; m += 2) {
-    bbar_apply<T, TRANS>(w, own, i0, iL, qr, qi, yr, yi, db2, lbuf, N, cur, ch, sh);
+  accumulate(cf[0], pr, pi_);
+  if (NP >= 2) {
+    T sdb[4], db2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      pr[q] = yr[q] - c2 * qr[q] - pr[q];
-      pi_[q] = yi[q] - c2 * qi[q] - pi_[q];
+      sdb[q] = sA * db[q];
+      db2[q] = (T)2 * sdb[q];
     }
-    accumulate(cf[m], pr, pi_);
-    if (m + 1 >= NP) break;
-    bbar_apply<T, TRANS>(w, own, i0, iL, pr, pi_, yr, yi, db2, lbuf, N, cur, ch, sh);
+    c_apply<T, TRANS>(w, own, i0, iL, pr, pi_, yr, yi, lbuf, N, cur, th);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      qr[q] = yr[q] - c2 * pr[q] - qr[q];
-      qi[q] = yi[q] - c2 * pi_[q] - qi[q];
+      qr[q] = fma(sdb[q], yr[q], -cA * pr[q]);
+      qi[q] = fma(sdb[q], yi[q], -cA * pi_[q]);
     }
-    accumulate(cf[m + 1], qr, qi);
+    accumulate(cf[1], qr, qi);
+    const T c2 = (T)2 * cA;
+    for (int m = 2; m < NP; m += 2) {
+      c_apply<T, TRANS>(w, own, i0, iL, qr, qi, yr, yi, lbuf, N, cur, th);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        pr[q] = fma(db2[q], yr[q], fma(-c2, qr[q], -pr[q]));
+        pi_[q] = fma(db2[q], yi[q], fma(-c2, qi[q], -pi_[q]));
+      }
+      accumulate(cf[m], pr, pi_);
+      if (m + 1 >= NP) break;
+      c_apply<T, TRANS>(w, own, i0, iL, pr, pi_, yr, yi, lbuf, N, cur, th);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        qr[q] = fma(db2[q], yr[q], fma(-c2, pr[q], -qr[q]));
+        qi[q] = fma(db2[q], yi[q], fma(-c2, pi_[q], -qi[q]));
+      }
+      accumulate(cf[m + 1], qr, qi);
+    }
+  }
+  if (TRANS && own) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T inv = (T)1 / db[q];
+      ar[q] *= inv;
+      ai[q] *= inv;
+    }
   }
 }
 
@@ -609,7 +629,7 @@ template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
 k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       const int* __restrict__ np, const typename Cplx<T>::type* __restrict__ coef,
-      const T* __restrict__ dbar, T ch, T sh, const typename Cplx<T>::type* __restrict__ Z,
+      const T* __restrict__ dbar, T th, T c4, const typename Cplx<T>::type* __restrict__ Z,
       typename Cplx<T>::type* __restrict__ Zo, StIO io) {
   using T2 = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -644,7 +664,8 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
     ld2c(Zin + iL, c, d);
     xr[0] = a.x; xi[0] = a.y; xr[1] = b.x; xi[1] = b.y;
     xr[2] = c.x; xi[2] = c.y; xr[3] = d.x; xi[3] = d.y;
-    db[0] = dbar[i0]; db[1] = dbar[i0 + 1]; db[2] = dbar[iL]; db[3] = dbar[iL + 1];
+    db[0] = c4 * dbar[i0]; db[1] = c4 * dbar[i0 + 1];
+    db[2] = c4 * dbar[iL]; db[3] = c4 * dbar[iL + 1];
   } else {
 #pragma unroll
     for (int m = 0; m < 4; ++m) xr[m] = xi[m] = db[m] = (T)0;
@@ -652,16 +673,16 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   __syncthreads();
   const T2* cf = cfs;
   if (op == 0) {
-    cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
+    cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, th, ar, ai);
   } else {
-    cheb_series<T, true>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
+    cheb_series<T, true>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, th, ar, ai);
     if (op == 2) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         xr[m] = ar[m];
         xi[m] = ai[m];
       }
-      cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, ch, sh, ar, ai);
+      cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, th, ar, ai);
     }
   }
   if (own) {
@@ -807,7 +828,7 @@ hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cp
 template <typename T, int NT>
 hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
-                         StateSeq& sq, T ch, T sh, hipStream_t s) {
+                         StateSeq& sq, T th, T c4, hipStream_t s) {
   const StIO io = sq.next(0);
   const size_t lds = (2 * (size_t)g.N + kNPMax) * sizeof(typename Cplx<T>::type);
   auto kern = k_kpm<T, NT>;
@@ -815,18 +836,18 @@ hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int o
   if (e != hipSuccess) return e;
   const auto* cf = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->coef64 : (const void*)pc->coef32);
   hipLaunchKernelGGL(kern, dim3(pc->H * nrhs), dim3(NT), lds, s, g, pc->H, nrhs, op, pc->info,
-                     pc->np, cf, dbar, ch, sh, Z, Zo, io);
+                     pc->np, cf, dbar, th, c4, Z, Zo, io);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pc_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                   const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, StateSeq& sq,
-                  T ch, T sh, hipStream_t s) {
-  if (g.Q <= 64) return pc_launch_kpm<T, 64>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
-  if (g.Q <= 256) return pc_launch_kpm<T, 256>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
-  if (g.Q <= 512) return pc_launch_kpm<T, 512>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
-  return pc_launch_kpm<T, 1024>(pc, g, dbar, op, nrhs, Z, Zo, sq, ch, sh, s);
+                  T th, T c4, hipStream_t s) {
+  if (g.Q <= 64) return pc_launch_kpm<T, 64>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
+  if (g.Q <= 256) return pc_launch_kpm<T, 256>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
+  if (g.Q <= 512) return pc_launch_kpm<T, 512>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
+  return pc_launch_kpm<T, 1024>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
 }
 
 // out = op(in) (op: 0 F, 1 F^T, 2 F F^T).  With rdot != nullptr the inverse
@@ -840,7 +861,7 @@ hipError_t pc_apply(const PcTables* pc, const Geom& g, const T* dbar, int op, in
   hipError_t e = pc_fwd<T>(pc, g, nrhs, const_cast<T*>(in), Z, nullptr, nullptr, nullptr,
                            nullptr, sq, false, s);
   if (e != hipSuccess) return e;
-  e = pc_kpm<T>(pc, g, dbar, op, nrhs, Z, Z2, sq, (T)pc->ch, (T)pc->sh, s);
+  e = pc_kpm<T>(pc, g, dbar, op, nrhs, Z, Z2, sq, (T)pc->th, (T)pc->c4, s);
   if (e != hipSuccess) return e;
   return pc_inv<T>(pc, g, nrhs, Z2, out, rdot ? 1 : 0, rdot, sq, s);
 }
@@ -857,7 +878,7 @@ hipError_t pc_cg_update(const PcTables* pc, const Geom& g, const T* dbar, int nr
   T2* Z2 = reinterpret_cast<T2*>(pc->Z2);
   hipError_t e = pc_fwd<T>(pc, g, nrhs, r, Z, u, pa, pb, Ap, sq, true, s);
   if (e != hipSuccess) return e;
-  e = pc_kpm<T>(pc, g, dbar, 2, nrhs, Z, Z2, sq, (T)pc->ch, (T)pc->sh, s);
+  e = pc_kpm<T>(pc, g, dbar, 2, nrhs, Z, Z2, sq, (T)pc->th, (T)pc->c4, s);
   if (e != hipSuccess) return e;
   return pc_inv<T>(pc, g, nrhs, Z2, z, 1, r, sq, s);
 }
