@@ -39,8 +39,10 @@ struct PcTables {
   int H, H1, H2;
   double2* tw64;   // e^{-i pi tau / Ltau}, tau < H
   double2* W64;    // e^{-2 pi i k / H}, k < H
+  double2* F64;    // H1 x H1 then H2 x H2 small-DFT matrices (see k_pc_twiddles)
   float2* tw32;
   float2* W32;
+  float2* F32;
   PcInfo* info;    // bounds and series constants (device)
   int* np;         // N_P(w) for w < Ltau (device)
   double2* coef64; // [H][kNPMax]: c_m(2k)
@@ -64,17 +66,39 @@ inline bool pc_supported(int Ltau) { return Ltau >= 2 && Ltau % 2 == 0 && pick_h
 
 // ----------------------------------------------------------- setup kernels
 
-__global__ void k_pc_twiddles(int H, int Ltau, double2* tw64, double2* W64, float2* tw32,
-                              float2* W32) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < H; k += gridDim.x * blockDim.x) {
-    const double a = (double)k / (double)Ltau;      // twist angle / pi
-    const double b = 2.0 * (double)k / (double)H;   // DFT angle / pi
-    const double2 t = make_double2(cospi(a), -sinpi(a));
-    const double2 w = make_double2(cospi(b), -sinpi(b));
-    tw64[k] = t;
-    W64[k] = w;
-    tw32[k] = make_float2((float)t.x, (float)t.y);
-    W32[k] = make_float2((float)w.x, (float)w.y);
+// Twiddles: tw[tau] = e^{-i pi tau/Ltau}, W[k] = W_H^k, and the matrices of
+// the two short DFTs, F[k1 H1 + n1] = W_H1^{n1 k1} (H1 x H1) followed by
+// F[H1^2 + k2 H2 + n2] = W_H2^{n2 k2} (H2 x H2), so that a thread computing
+// one output reads its row with unit stride.
+__global__ void k_pc_twiddles(int H, int H1, int H2, int Ltau, double2* tw64, double2* W64,
+                              double2* F64, float2* tw32, float2* W32, float2* F32) {
+  const int nF = H1 * H1 + H2 * H2;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < H + nF; k += gridDim.x * blockDim.x) {
+    if (k < H) {
+      const double a = (double)k / (double)Ltau;      // twist angle / pi
+      const double b = 2.0 * (double)k / (double)H;   // DFT angle / pi
+      const double2 t = make_double2(cospi(a), -sinpi(a));
+      const double2 w = make_double2(cospi(b), -sinpi(b));
+      tw64[k] = t;
+      W64[k] = w;
+      tw32[k] = make_float2((float)t.x, (float)t.y);
+      W32[k] = make_float2((float)w.x, (float)w.y);
+    } else {
+      const int f = k - H;
+      int n, m;
+      if (f < H1 * H1) {
+        m = ((f / H1) * (f % H1)) % H1;
+        n = H1;
+      } else {
+        const int g = f - H1 * H1;
+        m = ((g / H2) * (g % H2)) % H2;
+        n = H2;
+      }
+      const double c = 2.0 * (double)m / (double)n;
+      const double2 w = make_double2(cospi(c), -sinpi(c));
+      F64[f] = w;
+      F32[f] = make_float2((float)w.x, (float)w.y);
+    }
   }
 }
 
@@ -181,42 +205,90 @@ FPH_DEVINL T2 cmulc(T2 a, T2 b) {  // a * conj(b)
 // slices of them): KS <= 64 bytes of a slice row, smaller when that leaves
 // too few workgroups to fill the chip.  Workgroups are numbered with
 // xcd_contiguous so neighbouring tiles (which share cache lines) run on
-// one XCD.
+// one XCD.  The two short DFTs read their matrix rows (F, see
+// k_pc_twiddles) and their inputs with unit and constant strides from LDS.
+
+template <typename T2>
+FPH_DEVINL void cmac(T2& acc, T2 w, T2 y) {  // acc += w y
+  acc.x = fma(w.x, y.x, fma(-w.y, y.y, acc.x));
+  acc.y = fma(w.x, y.y, fma(w.y, y.x, acc.y));
+}
+
+template <typename T2>
+FPH_DEVINL void cmacc(T2& acc, T2 w, T2 y) {  // acc += conj(w) y
+  acc.x = fma(w.x, y.x, fma(w.y, y.y, acc.x));
+  acc.y = fma(w.x, y.y, fma(-w.y, y.x, acc.y));
+}
 
 // Forward transform of one tile of sites: Z[r][k][i] = (U in)_{2k}.
-// Stage 0 (all threads, coalesced): the tile in[tau][i0..i0+kS) goes to
-// LDS; with CGUPD it first receives the CG update u += alpha p,
-// r -= alpha Ap (r is `in`, updated in place), publishing |r|^2 as P_RR
-// partials (the direction is pb on even iteration counts, pa on odd).
-// Step 1, item (site, n2, k1): output k1 of the H1-point DFT over n1 of
-// the twisted input y_tau = e^{-i pi tau/Ltau} (in_tau - i in_{tau+H}),
-// tau = H2 n1 + n2, times W_H^{n2 k1}, into LDS.  Step 2, item (site, k1, k2): the H2-point
-// DFT over n2 -> Z_{k1 + H1 k2}.  Twiddles live in LDS.
-// Launch: grid ntiles * nrhs (ntiles = ceil(N / KS)), NT threads,
-// LDS 2H complex + Ltau KS reals + H KS complex.
+// Stage 0, item (tau < H, site), coalesced: y_tau = e^{-i pi tau/Ltau}
+// (in_tau - i in_{tau+H}) into LDS.  With CGUPD both inputs first receive
+// the CG update u += alpha p, r -= alpha Ap (r is `in`, updated in place),
+// publishing |r|^2 as P_RR partials; the direction is pb on even iteration
+// counts, pa on odd.  The loads of the first pass (two items per thread)
+// other than the direction are issued before the solver state is read.
+// Step 1, item (site, n2, k1): output k1 of the H1-point DFT over
+// n1 of y_{H2 n1 + n2}, times W_H^{n2 k1}.  Step 2, item (site, k1, k2):
+// the H2-point DFT over n2 -> Z_{k1 + H1 k2}.
+// Launch: grid ntiles * nrhs, NT threads; LDS (H1^2 + H2^2 + H + 2 H KS)
+// complex values.
 template <typename T, int H1, int NT, bool CGUPD>
 __global__ void __launch_bounds__(NT)
 k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
-       const typename Cplx<T>::type* __restrict__ W, T* __restrict__ in,
-       typename Cplx<T>::type* __restrict__ Z, T* __restrict__ u, const T* pa, const T* pb,
-       const T* __restrict__ Ap, int lks, int ntiles, StIO io) {
+       const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ F,
+       T* __restrict__ in, typename Cplx<T>::type* __restrict__ Z, T* __restrict__ u,
+       const T* pa, const T* pb, const T* __restrict__ Ap, int lks, int ntiles, StIO io) {
   using T2 = typename Cplx<T>::type;
+  constexpr int kI = 2;  // stage-0 items per thread and pass
   const int KS = 1 << lks;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = H1 * H2;
-  T2* Wl = reinterpret_cast<T2*>(smem_raw);
-  T2* twl = Wl + H;
-  T2* Y = twl + H;
-  T* Rt = reinterpret_cast<T*>(Y + H * KS);
+  const int nF = H1 * H1 + H2 * H2;
+  T2* Fl = reinterpret_cast<T2*>(smem_raw);
+  T2* Wl = Fl + nF;
+  T2* Y0 = Wl + H;
+  T2* Y1 = Y0 + H * KS;
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
   const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
   const int r = logical % (gridDim.x / ntiles);
   const int tile = logical / (gridDim.x / ntiles);
-  for (int k = threadIdx.x; k < H; k += NT) {
-    Wl[k] = W[k];
-    twl[k] = tw[k];
-  }
+  const int i0 = tile * KS;
+  const long base = (long)r * g.d;
+  const long hN = (long)H * g.N;
+  const int npair = H << lks;
+
+  T ra[kI], rb[kI], aa[kI], ab[kI], ua[kI], ub[kI], pv0[kI], pv1[kI];
+  // Loads of pass e0: with all, r (and with CGUPD Ap, u); with dir, the
+  // direction p (CGUPD).
+  auto load = [&](int e0, bool all, bool dir, const T* p) {
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int e = e0 + j * NT;
+      const int tau = e >> lks, sidx = e & (KS - 1);
+      const bool ok = e < npair && i0 + sidx < g.N;
+      const long oa = base + (long)tau * g.N + i0 + sidx;
+      if (all) {
+        ra[j] = ok ? in[oa] : (T)0;
+        rb[j] = ok ? in[oa + hN] : (T)0;
+      }
+      if (CGUPD) {
+        if (all) {
+          aa[j] = ok ? Ap[oa] : (T)0;
+          ab[j] = ok ? Ap[oa + hN] : (T)0;
+          ua[j] = ok ? u[oa] : (T)0;
+          ub[j] = ok ? u[oa + hN] : (T)0;
+        }
+        if (dir) {
+          pv0[j] = ok ? p[oa] : (T)0;
+          pv1[j] = ok ? p[oa + hN] : (T)0;
+        }
+      }
+    }
+  };
+  load(threadIdx.x, true, false, pa);
+  for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
+  for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
   if (io.in != nullptr) {
     state_begin<NT>(io, r, &s_sh, red_sh);
     if (s_sh.done) {
@@ -224,93 +296,67 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
       return;
     }
   }
-  const int i0 = tile * KS;
-  const long base = (long)r * g.d;
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
   double acc_rr = 0.0;
 
   // Stage 0.
   {
     T alpha = (T)0;
-    const T* __restrict__ p = pa;
+    const T* p = pa;
     if (CGUPD) {
       alpha = (T)s_sh.alpha;
       p = (s_sh.iter & 1) ? pa : pb;  // direction written by this iteration
     }
-    // four elements per thread per pass, all loads issued first
-    const int nel = g.Ltau << lks;
-    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * NT) {
-      T a[4], av[4], pv[4], uv[4];
-      long off[4];
-      bool ok[4];
+    for (int e0 = threadIdx.x; e0 < npair; e0 += kI * NT) {
+      load(e0, e0 != (int)threadIdx.x, CGUPD, p);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kI; ++j) {
         const int e = e0 + j * NT;
+        if (e >= npair) continue;
         const int tau = e >> lks, sidx = e & (KS - 1);
-        ok[j] = e < nel && i0 + sidx < g.N;
-        off[j] = base + (long)tau * g.N + i0 + sidx;
-        a[j] = ok[j] ? in[off[j]] : (T)0;
-        if (CGUPD && ok[j]) {
-          av[j] = Ap[off[j]];
-          pv[j] = p[off[j]];
-          uv[j] = u[off[j]];
+        T a = ra[j], b = rb[j];
+        if (CGUPD && i0 + sidx < g.N) {
+          const long oa = base + (long)tau * g.N + i0 + sidx;
+          const T pva = pv0[j], pvb = pv1[j];
+          a -= alpha * aa[j];
+          b -= alpha * ab[j];
+          in[oa] = a;
+          in[oa + hN] = b;
+          u[oa] = ua[j] + alpha * pva;
+          u[oa + hN] = ub[j] + alpha * pvb;
+          acc_rr += (double)a * (double)a + (double)b * (double)b;
         }
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int e = e0 + j * NT;
-        if (e >= nel) continue;
-        if (CGUPD && ok[j]) {
-          a[j] -= alpha * av[j];
-          in[off[j]] = a[j];
-          u[off[j]] = uv[j] + alpha * pv[j];
-          acc_rr += (double)a[j] * (double)a[j];
-        }
-        Rt[e] = a[j];
+        const T2 t = tw[tau];
+        Y0[tau * KS + sidx] = T2{t.x * a + t.y * b, t.y * a - t.x * b};
       }
     }
   }
   __syncthreads();
+  const int s1 = H2 << lks;  // Y0 stride between consecutive n1
   for (int it = threadIdx.x; it < KS * H; it += NT) {
-    // item (sidx, n2, k1): one output of the H1-point DFT over n1
     const int sidx = it & (KS - 1);
     const int rest = it >> lks;  // n2 * H1 + k1
     const int n2 = rest / H1, k1 = rest - n2 * H1;
-    const int step = (H2 * k1) % H;  // W_H1^{n1 k1} = W_H^{H2 n1 k1}
-    int idx = 0;
+    const T2* yp = Y0 + n2 * KS + sidx;
+    const T2* fr = Fl + k1 * H1;
     T2 acc = T2{(T)0, (T)0};
 #pragma unroll
-    for (int n1 = 0; n1 < H1; ++n1) {
-      const int tau = H2 * n1 + n2;
-      const T a = Rt[tau * KS + sidx], b = Rt[(tau + H) * KS + sidx];
-      const T2 yv = cmul<T2, T>(twl[tau], T2{a, -b});
-      const T2 wv = Wl[idx];
-      acc.x += wv.x * yv.x - wv.y * yv.y;
-      acc.y += wv.x * yv.y + wv.y * yv.x;
-      idx += step;
-      if (idx >= H) idx -= H;
-    }
-    Y[rest * KS + sidx] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
+    for (int n1 = 0; n1 < H1; ++n1) cmac(acc, fr[n1], yp[n1 * s1]);
+    Y1[it] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
   }
   __syncthreads();
+  const int s2 = H1 << lks;  // Y1 stride between consecutive n2
   for (int it = threadIdx.x; it < KS * H; it += NT) {
     const int sidx = it & (KS - 1);
-    const int kk = it >> lks;
-    const int k1 = kk % H1, k2 = kk / H1;
+    const int kk = it >> lks;  // k1 + H1 k2 = output frequency
+    const int k2 = kk / H1, k1 = kk - k2 * H1;
     if (i0 + sidx >= g.N) continue;
-    const int step = (H1 * k2) % H;  // W_H2^{n2 k2} = W_H^{H1 n2 k2}
-    int idx = 0;
+    const T2* yp = Y1 + k1 * KS + sidx;
+    const T2* fr = Fl + H1 * H1 + k2 * H2;
     T2 x = T2{(T)0, (T)0};
-    for (int n2 = 0; n2 < H2; ++n2) {
-      const T2 wv = Wl[idx];
-      const T2 yv = Y[(n2 * H1 + k1) * KS + sidx];
-      x.x += wv.x * yv.x - wv.y * yv.y;
-      x.y += wv.x * yv.y + wv.y * yv.x;
-      idx += step;
-      if (idx >= H) idx -= H;
-    }
-    const int k = k1 + H1 * k2;
-    Z[((long)r * H + k) * g.N + i0 + sidx] = T2{x.x * scale, x.y * scale};
+#pragma unroll 4
+    for (int n2 = 0; n2 < H2; ++n2) cmac(x, fr[n2], yp[n2 * s2]);
+    Z[((long)r * H + kk) * g.N + i0 + sidx] = T2{x.x * scale, x.y * scale};
   }
 
   if (io.in != nullptr) {
@@ -320,33 +366,50 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   }
 }
 
-// Inverse transform: out[r][tau][i] from Zh[r][k][i] (the same two-step
-// DFT with conjugated twiddles, then the conjugate twist and the real
-// split into tau and tau + H).  Stage 0 copies the tile Zh[k][i0..i0+kS)
-// to LDS with coalesced loads.  With dot != 0 also publishes rdot . out as
-// P_RZ partials.  LDS: 2H complex + 2 H kS complex.
+// Inverse transform: out[r][tau][i] from Zh[r][k][i] (the same two short
+// DFTs with conjugated matrices, then the conjugate twist and the real
+// split into tau and tau + H).  Stage 0 copies the tile Zh[k][i0..i0+KS)
+// to LDS with coalesced loads, issued before the solver state is read.
+// With dot != 0 also publishes rdot . out as P_RZ partials.  LDS:
+// (H1^2 + H2^2 + H + 2 H KS) complex values.
 template <typename T, int H1, int NT>
 __global__ void __launch_bounds__(NT)
 k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
-       const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ Zh,
-       T* __restrict__ out, int dot, const T* __restrict__ rdot, int lks, int ntiles, StIO io) {
+       const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ F,
+       const typename Cplx<T>::type* __restrict__ Zh, T* __restrict__ out, int dot,
+       const T* __restrict__ rdot, int lks, int ntiles, StIO io) {
   using T2 = typename Cplx<T>::type;
+  constexpr int kI = 4;
   const int KS = 1 << lks;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = H1 * H2;
-  T2* Wl = reinterpret_cast<T2*>(smem_raw);
-  T2* twl = Wl + H;
-  T2* Y = twl + H;
-  T2* Zt = Y + H * KS;
+  const int nF = H1 * H1 + H2 * H2;
+  T2* Fl = reinterpret_cast<T2*>(smem_raw);
+  T2* Wl = Fl + nF;
+  T2* Zt = Wl + H;
+  T2* Y = Zt + H * KS;
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
   const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
   const int r = logical % (gridDim.x / ntiles);
   const int tile = logical / (gridDim.x / ntiles);
-  for (int k = threadIdx.x; k < H; k += NT) {
-    Wl[k] = W[k];
-    twl[k] = tw[k];
-  }
+  const int i0 = tile * KS;
+  const long base = (long)r * g.d;
+  const int nel = H << lks;
+
+  T2 v[kI];
+  auto load = [&](int e0) {
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int e = e0 + j * NT;
+      const int k = e >> lks, sidx = e & (KS - 1);
+      v[j] = (e < nel && i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx]
+                                         : T2{(T)0, (T)0};
+    }
+  };
+  load(threadIdx.x);
+  for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
+  for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
   if (io.in != nullptr) {
     state_begin<NT>(io, r, &s_sh, red_sh);
     if (s_sh.done) {
@@ -354,66 +417,41 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
       return;
     }
   }
-  const int i0 = tile * KS;
-  const long base = (long)r * g.d;
   const T scale = (T)(2.0 / sqrt((double)g.Ltau));
   double acc_dot = 0.0;
 
-  {
-    const int nel = H << lks;
-    for (int e0 = threadIdx.x; e0 < nel; e0 += 4 * NT) {
-      T2 v[4];
+  for (int e0 = threadIdx.x; e0 < nel; e0 += kI * NT) {
+    if (e0 != (int)threadIdx.x) load(e0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int e = e0 + j * NT;
-        const int k = e >> lks, sidx = e & (KS - 1);
-        v[j] = (e < nel && i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx]
-                                           : T2{(T)0, (T)0};
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (e0 + j * NT < nel) Zt[e0 + j * NT] = v[j];
-    }
+    for (int j = 0; j < kI; ++j)
+      if (e0 + j * NT < nel) Zt[e0 + j * NT] = v[j];
   }
   __syncthreads();
+  const int s1 = H2 << lks;
   for (int it = threadIdx.x; it < KS * H; it += NT) {
-    // item (sidx, n2, k1): one output of the H1-point DFT over n1
     const int sidx = it & (KS - 1);
     const int rest = it >> lks;  // n2 * H1 + k1
     const int n2 = rest / H1, k1 = rest - n2 * H1;
-    const int step = (H2 * k1) % H;
-    int idx = 0;
+    const T2* yp = Zt + n2 * KS + sidx;
+    const T2* fr = Fl + k1 * H1;
     T2 acc = T2{(T)0, (T)0};
 #pragma unroll
-    for (int n1 = 0; n1 < H1; ++n1) {
-      const T2 yv = Zt[(H2 * n1 + n2) * KS + sidx];
-      const T2 wv = Wl[idx];  // used conjugated
-      acc.x += wv.x * yv.x + wv.y * yv.y;
-      acc.y += wv.x * yv.y - wv.y * yv.x;
-      idx += step;
-      if (idx >= H) idx -= H;
-    }
-    Y[rest * KS + sidx] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
+    for (int n1 = 0; n1 < H1; ++n1) cmacc(acc, fr[n1], yp[n1 * s1]);
+    Y[it] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
   }
   __syncthreads();
+  const int s2 = H1 << lks;
   for (int it = threadIdx.x; it < KS * H; it += NT) {
     const int sidx = it & (KS - 1);
-    const int kk = it >> lks;
-    const int k1 = kk % H1, k2 = kk / H1;
+    const int tau = it >> lks;  // k1 + H1 k2
+    const int k2 = tau / H1, k1 = tau - k2 * H1;
     if (i0 + sidx >= g.N) continue;
-    const int step = (H1 * k2) % H;
-    int idx = 0;
+    const T2* yp = Y + k1 * KS + sidx;
+    const T2* fr = Fl + H1 * H1 + k2 * H2;
     T2 x = T2{(T)0, (T)0};
-    for (int n2 = 0; n2 < H2; ++n2) {
-      const T2 wv = Wl[idx];
-      const T2 yv = Y[(n2 * H1 + k1) * KS + sidx];
-      x.x += wv.x * yv.x + wv.y * yv.y;
-      x.y += wv.x * yv.y - wv.y * yv.x;
-      idx += step;
-      if (idx >= H) idx -= H;
-    }
-    const int tau = k1 + H1 * k2;
-    const T2 sv = cmulc<T2, T>(x, twl[tau]);
+#pragma unroll 4
+    for (int n2 = 0; n2 < H2; ++n2) cmacc(x, fr[n2], yp[n2 * s2]);
+    const T2 sv = cmulc<T2, T>(x, tw[tau]);
     const long oa = base + (long)tau * g.N + i0 + sidx;
     const long ob = oa + (long)H * g.N;
     const T va = scale * sv.x, vb = -scale * sv.y;
@@ -704,10 +742,13 @@ inline hipError_t pc_create(PcTables* pc, const Geom& g, int max_rhs) {
   hipError_t e = hipSuccess;
 #define PCALLOC(ptr, bytes) \
   if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes));
+  const int nF = pc->H1 * pc->H1 + pc->H2 * pc->H2;
   PCALLOC(pc->tw64, H * sizeof(double2));
   PCALLOC(pc->W64, H * sizeof(double2));
+  PCALLOC(pc->F64, nF * sizeof(double2));
   PCALLOC(pc->tw32, H * sizeof(float2));
   PCALLOC(pc->W32, H * sizeof(float2));
+  PCALLOC(pc->F32, nF * sizeof(float2));
   PCALLOC(pc->info, sizeof(PcInfo));
   PCALLOC(pc->np, g.Ltau * sizeof(int));
   PCALLOC(pc->coef64, (size_t)H * kNPMax * sizeof(double2));
@@ -716,13 +757,13 @@ inline hipError_t pc_create(PcTables* pc, const Geom& g, int max_rhs) {
   PCALLOC(pc->Z2, (size_t)max_rhs * H * g.N * sizeof(double2));
 #undef PCALLOC
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pc_twiddles, dim3((H + 255) / 256), dim3(256), 0, 0, H, g.Ltau, pc->tw64,
-                     pc->W64, pc->tw32, pc->W32);
+  hipLaunchKernelGGL(k_pc_twiddles, dim3((H + nF + 255) / 256), dim3(256), 0, 0, H, pc->H1,
+                     pc->H2, g.Ltau, pc->tw64, pc->W64, pc->F64, pc->tw32, pc->W32, pc->F32);
   return hipGetLastError();
 }
 
 inline void pc_destroy(PcTables* pc) {
-  void* ptrs[] = {pc->tw64, pc->W64, pc->tw32, pc->W32, pc->info, pc->np,
+  void* ptrs[] = {pc->tw64, pc->W64, pc->F64, pc->tw32, pc->W32, pc->F32, pc->info, pc->np,
                   pc->coef64, pc->coef32, pc->Z, pc->Z2};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -740,60 +781,73 @@ inline hipError_t pc_set_field(PcTables* pc, const Geom& g, const double* dbar64
   return hipGetLastError();
 }
 
-// Tile width (log2) of the transforms: up to 64 bytes of a slice row,
-// halved while there are fewer than 512 workgroups (not below 2 sites:
-// one-site tiles measured slower).
+// LDS bytes of a transform workgroup with tile width 2^lks.
 template <typename T>
-int pc_tile_log2(const Geom& g, int nrhs) {
-  int lks = (sizeof(T) == 8) ? 3 : 4;
-  while (lks > 1 && (long)((g.N + (1 << lks) - 1) >> lks) * nrhs < 512) --lks;
+size_t pc_tile_lds(const PcTables* pc, int lks) {
+  const size_t nF = (size_t)pc->H1 * pc->H1 + (size_t)pc->H2 * pc->H2;
+  return (nF + pc->H + 2 * (size_t)pc->H * ((size_t)1 << lks)) * sizeof(typename Cplx<T>::type);
+}
+
+// Tile width (log2) of the transforms, for workgroups of kTNT threads:
+// the widest tile up to 32 bytes of a slice row that leaves at least 256
+// tiles (each slice row of a tile is a separate short segment, so narrow
+// tiles cost more cache lines per byte; wide ones leave CUs idle), not
+// below 2 sites, and at most 64 KB of LDS per workgroup.
+constexpr int kTNT = 512;
+
+template <typename T>
+int pc_tile_log2(const PcTables* pc, const Geom& g, int nrhs) {
+  int lks = (sizeof(T) == 8) ? 2 : 3;
+  while (lks > 1 && (long)((g.N + (1 << lks) - 1) >> lks) * nrhs < 256) --lks;
+  while (lks > 0 && pc_tile_lds<T>(pc, lks) > ((size_t)64 << 10)) --lks;
   return lks;
 }
 
-template <typename T, int H1>
-hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in,
+template <typename T, int H1, int NT>
+hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, int lks, T* in,
                          typename Cplx<T>::type* Z, T* u, const T* pa, const T* pb, const T* Ap,
                          StateSeq& sq, bool cgupd, hipStream_t s) {
-  const int lks = pc_tile_log2<T>(g, nrhs);
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
   const StIO io = sq.next(cgupd ? ntiles : 0);
-  const size_t lds = (size_t)pc->H * (KS + 2) * sizeof(typename Cplx<T>::type) +
-                     (size_t)g.Ltau * KS * sizeof(T);
-  const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
-  const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
+  const size_t lds = pc_tile_lds<T>(pc, lks);
+  using T2 = typename Cplx<T>::type;
+  const auto* tw = (const T2*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
+  const auto* W = (const T2*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
+  const auto* F = (const T2*)(sizeof(T) == 8 ? (const void*)pc->F64 : (const void*)pc->F32);
   dim3 grid(ntiles * nrhs);
   if (cgupd) {
-    auto kern = k_tfwd<T, H1, 256, true>;
+    auto kern = k_tfwd<T, H1, NT, true>;
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, lks,
-                       ntiles, io);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, g, pc->H2, tw, W, F, in, Z, u, pa, pb, Ap,
+                       lks, ntiles, io);
   } else {
-    auto kern = k_tfwd<T, H1, 256, false>;
+    auto kern = k_tfwd<T, H1, NT, false>;
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, pc->H2, tw, W, in, Z, u, pa, pb, Ap, lks,
-                       ntiles, io);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, g, pc->H2, tw, W, F, in, Z, u, pa, pb, Ap,
+                       lks, ntiles, io);
   }
   return hipGetLastError();
 }
 
-template <typename T, int H1>
-hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs,
+template <typename T, int H1, int NT>
+hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs, int lks,
                          const typename Cplx<T>::type* Zh, T* out, int dot, const T* rdot,
                          StateSeq& sq, hipStream_t s) {
-  const int lks = pc_tile_log2<T>(g, nrhs);
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
   const StIO io = sq.next(dot ? ntiles : 0);
-  const size_t lds = (size_t)pc->H * (2 * KS + 2) * sizeof(typename Cplx<T>::type);
-  const auto* tw = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
-  const auto* W = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
-  auto kern = k_tinv<T, H1, 256>;
+  const size_t lds = pc_tile_lds<T>(pc, lks);
+  using T2 = typename Cplx<T>::type;
+  const auto* tw = (const T2*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
+  const auto* W = (const T2*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
+  const auto* F = (const T2*)(sizeof(T) == 8 ? (const void*)pc->F64 : (const void*)pc->F32);
+  auto kern = k_tinv<T, H1, NT>;
   hipError_t e = allow_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(ntiles * nrhs), dim3(256), lds, s, g, pc->H2, tw, W, Zh, out,
+  hipLaunchKernelGGL(kern, dim3(ntiles * nrhs), dim3(NT), lds, s, g, pc->H2, tw, W, F, Zh, out,
                      dot, rdot, lks, ntiles, io);
   return hipGetLastError();
 }
@@ -802,9 +856,10 @@ template <typename T>
 hipError_t pc_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in, typename Cplx<T>::type* Z,
                   T* u, const T* pa, const T* pb, const T* Ap, StateSeq& sq, bool cgupd,
                   hipStream_t s) {
+  const int lks = pc_tile_log2<T>(pc, g, nrhs);
   switch (pc->H1) {
 #define FPH_FWD_CASE(h1) \
-  case h1: return pc_launch_fwd<T, h1>(pc, g, nrhs, in, Z, u, pa, pb, Ap, sq, cgupd, s);
+  case h1: return pc_launch_fwd<T, h1, kTNT>(pc, g, nrhs, lks, in, Z, u, pa, pb, Ap, sq, cgupd, s);
     FPH_FWD_CASE(1) FPH_FWD_CASE(2) FPH_FWD_CASE(3) FPH_FWD_CASE(4) FPH_FWD_CASE(5)
     FPH_FWD_CASE(8) FPH_FWD_CASE(10) FPH_FWD_CASE(16) FPH_FWD_CASE(20)
 #undef FPH_FWD_CASE
@@ -815,9 +870,10 @@ hipError_t pc_fwd(const PcTables* pc, const Geom& g, int nrhs, T* in, typename C
 template <typename T>
 hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cplx<T>::type* Zh,
                   T* out, int dot, const T* rdot, StateSeq& sq, hipStream_t s) {
+  const int lks = pc_tile_log2<T>(pc, g, nrhs);
   switch (pc->H1) {
 #define FPH_INV_CASE(h1) \
-  case h1: return pc_launch_inv<T, h1>(pc, g, nrhs, Zh, out, dot, rdot, sq, s);
+  case h1: return pc_launch_inv<T, h1, kTNT>(pc, g, nrhs, lks, Zh, out, dot, rdot, sq, s);
     FPH_INV_CASE(1) FPH_INV_CASE(2) FPH_INV_CASE(3) FPH_INV_CASE(4) FPH_INV_CASE(5)
     FPH_INV_CASE(8) FPH_INV_CASE(10) FPH_INV_CASE(16) FPH_INV_CASE(20)
 #undef FPH_INV_CASE
