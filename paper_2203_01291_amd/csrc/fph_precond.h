@@ -545,35 +545,38 @@ FPH_DEVINL void pb_window_cn(const Win& w, const typename Cplx<T>::type* __restr
 
 // y = C' x (TRANS = false: P'_A (P'_B x)) or C'^T x (TRANS = true:
 // P'_B (P'_A x)), C = ch^4 C', for a complex vector held one even
-// plaquette per thread; x is left
-// unchanged.  One LDS exchange per apply: the thread publishes its four
-// sites (x, or P_A x) into buffer `cur` and after one barrier forms P_B at
-// its sites from the window.  Buffers alternate between applies, so one
-// barrier per apply suffices.  Threads without a plaquette only keep the
-// barrier.  The diagonal (dbar ch^4) of Bbar is applied by the caller.
+// plaquette per thread, in two halves with one LDS exchange between them:
+// c_publish writes the thread's four sites (x, or P'_A x) into buffer
+// `cur`; c_finish waits at the barrier, forms P'_B at the thread's sites
+// from the window (then P'_A for C') and flips `cur`.  Buffers alternate
+// between applies, so one barrier per apply suffices; work placed between
+// the halves overlaps the exchange.  Threads without a plaquette only keep
+// the barrier.  The diagonal (dbar ch^4) of Bbar is applied by the caller.
 template <typename T, bool TRANS>
-FPH_DEVINL void c_apply(const Win& w, bool own, int i0, int iL, const T (&xr)[4],
-                        const T (&xi)[4], T (&yr)[4], T (&yi)[4],
-                        typename Cplx<T>::type* lbuf, int N, int& cur, T th) {
-  using T2 = typename Cplx<T>::type;
-  T2* buf = lbuf + (long)cur * N;
-  if (own) {
-    T tr[4], ti[4];
+FPH_DEVINL void c_publish(bool own, int i0, int iL, const T (&xr)[4], const T (&xi)[4],
+                          typename Cplx<T>::type* lbuf, int N, int cur, T th) {
+  if (!own) return;
+  typename Cplx<T>::type* buf = lbuf + (long)cur * N;
+  T tr[4], ti[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      tr[m] = xr[m];
-      ti[m] = xi[m];
-    }
-    if (TRANS) {
-      plaq_rot(tr, th);
-      plaq_rot(ti, th);
-    }
-    st2c(buf + i0, tr[0], ti[0], tr[1], ti[1]);
-    st2c(buf + iL, tr[2], ti[2], tr[3], ti[3]);
+  for (int m = 0; m < 4; ++m) {
+    tr[m] = xr[m];
+    ti[m] = xi[m];
   }
+  if (TRANS) {
+    plaq_rot(tr, th);
+    plaq_rot(ti, th);
+  }
+  st2c(buf + i0, tr[0], ti[0], tr[1], ti[1]);
+  st2c(buf + iL, tr[2], ti[2], tr[3], ti[3]);
+}
+
+template <typename T, bool TRANS>
+FPH_DEVINL void c_finish(const Win& w, bool own, T (&yr)[4], T (&yi)[4],
+                         typename Cplx<T>::type* lbuf, int N, int& cur, T th) {
   __syncthreads();
   if (own) {
-    pb_window_cn<T>(w, buf, th, yr, yi);
+    pb_window_cn<T>(w, lbuf + (long)cur * N, th, yr, yi);
     if (!TRANS) {
       plaq_rot(yr, th);
       plaq_rot(yi, th);
@@ -584,21 +587,24 @@ FPH_DEVINL void c_apply(const Win& w, bool own, int i0, int iL, const T (&xr)[4]
 
 // acc = sum_{m < NP} c'_m T_m(A') x with A' = A (TRANS false, c' = c) or
 // A' = A^T (TRANS true, c' = conj(c)), A = sA D C' - cA, D = diag(dbar ch^4)
-// (db holds its entries);
-// three-term recurrence of Eq. alpha_recur,
-//   alpha_m = 2 sA D (C alpha_{m-1}) - 2 cA alpha_{m-1} - alpha_{m-2},
+// (db holds its entries); three-term recurrence of Eq. alpha_recur,
+//   alpha_m = 2 sA D (C' alpha_{m-1}) - 2 cA alpha_{m-1} - alpha_{m-2},
 // with D folded into the fused multiply-add that forms alpha_m.  For A^T
 // the recurrence runs on beta_m = D alpha_m, which obeys the same
 // relation with C'^T in place of C' (D A^T D^{-1} = sA D C'^T - cA):
-// beta_0 = D x, and the sum is scaled by D^{-1} at the end.  The two
-// latest terms alternate between two register sets, so no copies are made.
+// beta_0 = D x, and the sum is scaled by D^{-1} at the end.  Each new term
+// is published for the next apply before it is added to the sum, and the
+// coefficient is read before the barrier, so neither sits on the path from
+// one exchange to the next.  The two latest terms alternate between two
+// register sets, so no copies are made.
 template <typename T, bool TRANS>
 FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int NP,
                             const typename Cplx<T>::type* cf, T sA, T cA, const T (&xr)[4],
                             const T (&xi)[4], const T (&db)[4], typename Cplx<T>::type* lbuf,
                             int& cur, T th, T (&ar)[4], T (&ai)[4]) {
+  using T2 = typename Cplx<T>::type;
   const T cj = TRANS ? (T)-1 : (T)1;
-  auto accumulate = [&](const typename Cplx<T>::type c, const T (&vr)[4], const T (&vi)[4]) {
+  auto accumulate = [&](const T2 c, const T (&vr)[4], const T (&vi)[4]) {
     const T cy = cj * c.y;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -613,6 +619,7 @@ FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int N
     pr[q] = TRANS ? db[q] * xr[q] : xr[q];
     pi_[q] = TRANS ? db[q] * xi[q] : xi[q];
   }
+  if (NP >= 2) c_publish<T, TRANS>(own, i0, iL, pr, pi_, lbuf, N, cur, th);
   accumulate(cf[0], pr, pi_);
   if (NP >= 2) {
     T sdb[4], db2[4];
@@ -621,30 +628,36 @@ FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int N
       sdb[q] = sA * db[q];
       db2[q] = (T)2 * sdb[q];
     }
-    c_apply<T, TRANS>(w, own, i0, iL, pr, pi_, yr, yi, lbuf, N, cur, th);
+    T2 c = cf[1];
+    c_finish<T, TRANS>(w, own, yr, yi, lbuf, N, cur, th);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       qr[q] = fma(sdb[q], yr[q], -cA * pr[q]);
       qi[q] = fma(sdb[q], yi[q], -cA * pi_[q]);
     }
-    accumulate(cf[1], qr, qi);
+    if (NP > 2) c_publish<T, TRANS>(own, i0, iL, qr, qi, lbuf, N, cur, th);
+    accumulate(c, qr, qi);
     const T c2 = (T)2 * cA;
     for (int m = 2; m < NP; m += 2) {
-      c_apply<T, TRANS>(w, own, i0, iL, qr, qi, yr, yi, lbuf, N, cur, th);
+      c = cf[m];
+      c_finish<T, TRANS>(w, own, yr, yi, lbuf, N, cur, th);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         pr[q] = fma(db2[q], yr[q], fma(-c2, qr[q], -pr[q]));
         pi_[q] = fma(db2[q], yi[q], fma(-c2, qi[q], -pi_[q]));
       }
-      accumulate(cf[m], pr, pi_);
+      if (m + 1 < NP) c_publish<T, TRANS>(own, i0, iL, pr, pi_, lbuf, N, cur, th);
+      accumulate(c, pr, pi_);
       if (m + 1 >= NP) break;
-      c_apply<T, TRANS>(w, own, i0, iL, pr, pi_, yr, yi, lbuf, N, cur, th);
+      c = cf[m + 1];
+      c_finish<T, TRANS>(w, own, yr, yi, lbuf, N, cur, th);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         qr[q] = fma(db2[q], yr[q], fma(-c2, pr[q], -qr[q]));
         qi[q] = fma(db2[q], yi[q], fma(-c2, pi_[q], -qi[q]));
       }
-      accumulate(cf[m + 1], qr, qi);
+      if (m + 2 < NP) c_publish<T, TRANS>(own, i0, iL, qr, qi, lbuf, N, cur, th);
+      accumulate(c, qr, qi);
     }
   }
   if (TRANS && own) {
