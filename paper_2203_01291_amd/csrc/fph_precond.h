@@ -683,6 +683,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       const T* __restrict__ dbar, T th, T c4, const typename Cplx<T>::type* __restrict__ Z,
       typename Cplx<T>::type* __restrict__ Zo, StIO io) {
   using T2 = typename Cplx<T>::type;
+  static_assert(NT <= kNPMax, "one coefficient per thread is loaded ahead");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
@@ -691,22 +692,18 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   int cur = 0;
   const int ko = blockIdx.x / nrhs;
   const int r = blockIdx.x % nrhs;
-  if (io.in != nullptr) {
-    state_begin<NT>(io, r, &s_sh, red_sh);
-    if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
-      return;
-    }
-  }
   const int k = (ko % 2 == 0) ? ko / 2 : H - 1 - ko / 2;
-  const int NP = np[2 * k];
-  for (int m = threadIdx.x; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
-  const T sA = (T)info->s, cA = (T)info->c;
   const int q = threadIdx.x;
   const bool own = q < g.Q;
   const Win w = make_win(g, own ? q : 0);
   const int i0 = w.x0 + w.row[1], iL = i0 + g.L;
 
+  // Everything that does not depend on the solver state is loaded before
+  // it is read: the order N_P, the first NT coefficients (the table row has
+  // kNPMax entries, so the load needs no bound), the block's input and dbar.
+  const int NP = np[2 * k];
+  const T sA = (T)info->s, cA = (T)info->c;
+  const T2 c_first = coef[(long)k * kNPMax + threadIdx.x];
   T xr[4], xi[4], db[4], ar[4], ai[4];
   const T2* Zin = Z + ((long)r * H + k) * g.N;
   if (own) {
@@ -721,6 +718,15 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
 #pragma unroll
     for (int m = 0; m < 4; ++m) xr[m] = xi[m] = db[m] = (T)0;
   }
+  if (io.in != nullptr) {
+    state_begin<NT>(io, r, &s_sh, red_sh);
+    if (s_sh.done) {
+      state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+      return;
+    }
+  }
+  if ((int)threadIdx.x < NP) cfs[threadIdx.x] = c_first;
+  for (int m = threadIdx.x + NT; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
   __syncthreads();
   const T2* cf = cfs;
   if (op == 0) {
