@@ -469,26 +469,76 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 
 // ------------------------------------------------------------ KPM kernel
 
-// Sites of the LDS window around the even plaquette with corner (x0, y0):
-// rows y0-1, y0, y0+1, y0+2 and columns x0-1, x0..x0+1, x0+2 (periodic).
-// The odd plaquettes of P_B that cover the plaquette's four sites lie in
-// it (site (dx, dy) of the even plaquette is local site (1-dx, 1-dy) of
-// its odd plaquette).
+// Sites around the even plaquette with corner (x0, y0): rows y0-1, y0,
+// y0+1, y0+2 and columns x0-1, x0..x0+1, x0+2 (periodic).  The odd
+// plaquettes of P_B that cover the plaquette's four sites lie in this
+// window (site (dx, dy) of the even plaquette is local site (1-dx, 1-dy)
+// of its odd plaquette).  A slice in LDS is stored as two planes, even
+// and odd columns: site (x, y) at (x & 1) S L + (x >> 1) + S y, so the
+// single-site loads of consecutive plaquettes are consecutive; after the
+// 2 S L entries each slice buffer has kWinPad spare entries.  The row
+// stride S >= L/2 puts the plaquette rows a wave reads in one pass on
+// different banks (kpm_row_stride).  The thread's own four sites are never
+// read back: it keeps what it published.  A thread without a plaquette
+// points every index at the spare entries, so all threads run the same
+// branch-free steps (its values are never stored).
+constexpr int kWinPad = 4;
+
+// Plane row stride S for rows of hL plaquettes.  LDS has 64 banks of 4
+// bytes; a wave's 8-byte loads are served 32 lanes per pass, covering
+// 32 / hL plaquette rows whose starts differ by 2 S elements.  With
+// S = hL/2 (mod 16) those starts tile the 32 banks pairs evenly.  Rows of
+// 32 or more plaquettes fill a pass alone.  (16-byte elements are served
+// 16 lanes per pass, one row for hL >= 16.)
+__host__ __device__ inline int kpm_row_stride(int hL) {
+  if (hL % 32 == 0) return hL;
+  int S = hL;
+  while (S % 16 != (hL / 2) % 16) ++S;
+  return S;
+}
+
 struct Win {
-  int row[4];  // row offsets L * y
-  int x0, xm, xp;
+  int row[4];        // global row offsets L y of rows y0-1, y0, y0+1, y0+2
+  int x0;
+  int own[4];        // LDS: (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1)
+  int hm[4], hp[4];  // LDS: rows y0-1 and y0+2 at columns x0-1, x0, x0+1, x0+2
+  int cm[2], cp[2];  // LDS: rows y0 and y0+1 at columns x0-1 and x0+2
 };
 
-FPH_DEVINL Win make_win(const Geom& g, int q) {
+FPH_DEVINL Win make_win(const Geom& g, int q, bool own) {
   Win w;
-  const int x0 = 2 * (q % g.hL), y0 = 2 * (q / g.hL);
+  const int qq = own ? q : 0;
+  const int x0 = 2 * (qq % g.hL), y0 = 2 * (qq / g.hL);
+  const int ym = (y0 == 0) ? g.L - 1 : y0 - 1;
+  const int yp = (y0 + 2 == g.L) ? 0 : y0 + 2;
+  const int xm = (x0 == 0) ? g.L - 1 : x0 - 1;
+  const int xp = (x0 + 2 == g.L) ? 0 : x0 + 2;
   w.x0 = x0;
-  w.xm = (x0 == 0) ? g.L - 1 : x0 - 1;
-  w.xp = (x0 + 2 == g.L) ? 0 : x0 + 2;
-  w.row[0] = g.L * ((y0 == 0) ? g.L - 1 : y0 - 1);
+  w.row[0] = g.L * ym;
   w.row[1] = g.L * y0;
   w.row[2] = g.L * (y0 + 1);
-  w.row[3] = g.L * ((y0 + 2 == g.L) ? 0 : y0 + 2);
+  w.row[3] = g.L * yp;
+  const int S = kpm_row_stride(g.hL);
+  const int P = S * g.L;  // plane size; the spare entries start at 2 P
+  auto li = [&](int x, int y) { return own ? (x & 1) * P + (x >> 1) + S * y : 2 * P; };
+  w.own[0] = li(x0, y0);
+  w.own[1] = li(x0 + 1, y0);
+  w.own[2] = li(x0, y0 + 1);
+  w.own[3] = li(x0 + 1, y0 + 1);
+  const int cols[4] = {xm, x0, x0 + 1, xp};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    w.hm[c] = li(cols[c], ym);
+    w.hp[c] = li(cols[c], yp);
+  }
+  w.cm[0] = li(xm, y0);
+  w.cm[1] = li(xm, y0 + 1);
+  w.cp[0] = li(xp, y0);
+  w.cp[1] = li(xp, y0 + 1);
+  if (!own) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) w.own[m] = 2 * P + m;
+  }
   return w;
 }
 
@@ -502,87 +552,103 @@ FPH_DEVINL void ld2c(const double2* p, double2& a, double2& b) {
   a = p[0];
   b = p[1];
 }
-FPH_DEVINL void st2c(float2* p, float ar, float ai, float br, float bi) {
-  *reinterpret_cast<float4*>(p) = make_float4(ar, ai, br, bi);
+FPH_DEVINL void st2c(float2* p, float2 a, float2 b) {
+  *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
 }
-FPH_DEVINL void st2c(double2* p, double ar, double ai, double br, double bi) {
-  p[0] = make_double2(ar, ai);
-  p[1] = make_double2(br, bi);
+FPH_DEVINL void st2c(double2* p, double2 a, double2 b) {
+  p[0] = a;
+  p[1] = b;
 }
 
 // The Chebyshev kernel applies the checkerboard in the primed form of the
 // operator kernels (C = ch^4 P'_A P'_B, C2' = [[1, th], [th, 1]]); here
 // ch^4 joins the diagonal dbar, which the recurrence applies anyway.
+// Complex values stay interleaved (re, im) in registers, as in LDS.
+
+// P'_A on the four sites of one plaquette, both components.
+template <typename T2, typename T>
+FPH_DEVINL void plaq_rot_c(T2 (&v)[4], T th) {
+  T2 a[4];
+  a[0].x = fma(th, v[1].x, v[0].x);
+  a[0].y = fma(th, v[1].y, v[0].y);
+  a[1].x = fma(th, v[0].x, v[1].x);
+  a[1].y = fma(th, v[0].y, v[1].y);
+  a[2].x = fma(th, v[3].x, v[2].x);
+  a[2].y = fma(th, v[3].y, v[2].y);
+  a[3].x = fma(th, v[2].x, v[3].x);
+  a[3].y = fma(th, v[2].y, v[3].y);
+  v[0].x = fma(th, a[2].x, a[0].x);
+  v[0].y = fma(th, a[2].y, a[0].y);
+  v[2].x = fma(th, a[0].x, a[2].x);
+  v[2].y = fma(th, a[0].y, a[2].y);
+  v[1].x = fma(th, a[3].x, a[1].x);
+  v[1].y = fma(th, a[3].y, a[1].y);
+  v[3].x = fma(th, a[1].x, a[3].x);
+  v[3].y = fma(th, a[1].y, a[3].y);
+}
 
 // P'_B of a complex slice in LDS at the four sites of the thread's even
-// plaquette: with C2' = [[1, th], [th, 1]] per axis,
+// plaquette, whose own published values are c: with C2' = [[1, th],
+// [th, 1]] per axis,
 //   out(dx, dy) = sum_{a,b} c'(1-dy, b) c'(1-dx, a) W[2dy + b][2dx + a].
-template <typename T>
-FPH_DEVINL void pb_window_cn(const Win& w, const typename Cplx<T>::type* __restrict__ sl, T th,
-                             T (&re)[4], T (&im)[4]) {
-  using T2 = typename Cplx<T>::type;
-  T h0r[4], h0i[4], h1r[4], h1i[4];
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const T2* row = sl + w.row[rr];
-    T2 a, b;
-    ld2c(row + w.x0, a, b);
-    const T2 wm = row[w.xm], wp = row[w.xp];
-    h0r[rr] = fma(th, wm.x, a.x);
-    h0i[rr] = fma(th, wm.y, a.y);
-    h1r[rr] = fma(th, wp.x, b.x);
-    h1i[rr] = fma(th, wp.y, b.y);
-  }
-  re[0] = fma(th, h0r[0], h0r[1]);
-  im[0] = fma(th, h0i[0], h0i[1]);
-  re[1] = fma(th, h1r[0], h1r[1]);
-  im[1] = fma(th, h1i[0], h1i[1]);
-  re[2] = fma(th, h0r[3], h0r[2]);
-  im[2] = fma(th, h0i[3], h0i[2]);
-  re[3] = fma(th, h1r[3], h1r[2]);
-  im[3] = fma(th, h1i[3], h1i[2]);
+template <typename T2, typename T>
+FPH_DEVINL void pb_window_cn(const Win& w, const T2* __restrict__ sl, T th, const T2 (&c)[4],
+                             T2 (&out)[4]) {
+  const T2 a0 = sl[w.hm[0]], a1 = sl[w.hm[1]], a2 = sl[w.hm[2]], a3 = sl[w.hm[3]];
+  const T2 m0 = sl[w.cm[0]], m1 = sl[w.cm[1]], p0 = sl[w.cp[0]], p1 = sl[w.cp[1]];
+  const T2 b0 = sl[w.hp[0]], b1 = sl[w.hp[1]], b2 = sl[w.hp[2]], b3 = sl[w.hp[3]];
+  // x-direction pairs (x0-1, x0) and (x0+1, x0+2) on each row
+  T2 h0[4], h1[4];
+  h0[0].x = fma(th, a0.x, a1.x);
+  h0[0].y = fma(th, a0.y, a1.y);
+  h1[0].x = fma(th, a3.x, a2.x);
+  h1[0].y = fma(th, a3.y, a2.y);
+  h0[1].x = fma(th, m0.x, c[0].x);
+  h0[1].y = fma(th, m0.y, c[0].y);
+  h1[1].x = fma(th, p0.x, c[1].x);
+  h1[1].y = fma(th, p0.y, c[1].y);
+  h0[2].x = fma(th, m1.x, c[2].x);
+  h0[2].y = fma(th, m1.y, c[2].y);
+  h1[2].x = fma(th, p1.x, c[3].x);
+  h1[2].y = fma(th, p1.y, c[3].y);
+  h0[3].x = fma(th, b0.x, b1.x);
+  h0[3].y = fma(th, b0.y, b1.y);
+  h1[3].x = fma(th, b3.x, b2.x);
+  h1[3].y = fma(th, b3.y, b2.y);
+  // y-direction pairs (y0-1, y0) and (y0+1, y0+2)
+  out[0].x = fma(th, h0[0].x, h0[1].x);
+  out[0].y = fma(th, h0[0].y, h0[1].y);
+  out[1].x = fma(th, h1[0].x, h1[1].x);
+  out[1].y = fma(th, h1[0].y, h1[1].y);
+  out[2].x = fma(th, h0[3].x, h0[2].x);
+  out[2].y = fma(th, h0[3].y, h0[2].y);
+  out[3].x = fma(th, h1[3].x, h1[2].x);
+  out[3].y = fma(th, h1[3].y, h1[2].y);
 }
 
 // y = C' x (TRANS = false: P'_A (P'_B x)) or C'^T x (TRANS = true:
 // P'_B (P'_A x)), C = ch^4 C', for a complex vector held one even
 // plaquette per thread, in two halves with one LDS exchange between them:
-// c_publish writes the thread's four sites (x, or P'_A x) into buffer
-// `cur`; c_finish waits at the barrier, forms P'_B at the thread's sites
-// from the window (then P'_A for C') and flips `cur`.  Buffers alternate
-// between applies, so one barrier per apply suffices; work placed between
-// the halves overlaps the exchange.  Threads without a plaquette only keep
-// the barrier.  The diagonal (dbar ch^4) of Bbar is applied by the caller.
-template <typename T, bool TRANS>
-FPH_DEVINL void c_publish(bool own, int i0, int iL, const T (&xr)[4], const T (&xi)[4],
-                          typename Cplx<T>::type* lbuf, int N, int cur, T th) {
-  if (!own) return;
-  typename Cplx<T>::type* buf = lbuf + (long)cur * N;
-  T tr[4], ti[4];
+// c_publish writes the thread's four sites (x, or P'_A x) into an LDS
+// slice buffer and returns them in c; c_finish waits at the barrier and
+// forms P'_B at the thread's sites from the window and c (then P'_A for
+// C').  Two buffers alternate between applies, so one barrier per apply
+// suffices; work placed between the halves overlaps the exchange.  The
+// diagonal (dbar ch^4) of Bbar is applied by the caller.
+template <typename T2, typename T, bool TRANS>
+FPH_DEVINL void c_publish(const Win& w, const T2 (&x)[4], T2* buf, T th, T2 (&c)[4]) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    tr[m] = xr[m];
-    ti[m] = xi[m];
-  }
-  if (TRANS) {
-    plaq_rot(tr, th);
-    plaq_rot(ti, th);
-  }
-  st2c(buf + i0, tr[0], ti[0], tr[1], ti[1]);
-  st2c(buf + iL, tr[2], ti[2], tr[3], ti[3]);
+  for (int m = 0; m < 4; ++m) c[m] = x[m];
+  if (TRANS) plaq_rot_c(c, th);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) buf[w.own[m]] = c[m];
 }
 
-template <typename T, bool TRANS>
-FPH_DEVINL void c_finish(const Win& w, bool own, T (&yr)[4], T (&yi)[4],
-                         typename Cplx<T>::type* lbuf, int N, int& cur, T th) {
+template <typename T2, typename T, bool TRANS>
+FPH_DEVINL void c_finish(const Win& w, const T2 (&c)[4], T2 (&y)[4], const T2* buf, T th) {
   __syncthreads();
-  if (own) {
-    pb_window_cn<T>(w, lbuf + (long)cur * N, th, yr, yi);
-    if (!TRANS) {
-      plaq_rot(yr, th);
-      plaq_rot(yi, th);
-    }
-  }
-  cur ^= 1;
+  pb_window_cn(w, buf, th, c, y);
+  if (!TRANS) plaq_rot_c(y, th);
 }
 
 // acc = sum_{m < NP} c'_m T_m(A') x with A' = A (TRANS false, c' = c) or
@@ -595,77 +661,82 @@ FPH_DEVINL void c_finish(const Win& w, bool own, T (&yr)[4], T (&yi)[4],
 // beta_0 = D x, and the sum is scaled by D^{-1} at the end.  Each new term
 // is published for the next apply before it is added to the sum, and the
 // coefficient is read before the barrier, so neither sits on the path from
-// one exchange to the next.  The two latest terms alternate between two
-// register sets, so no copies are made.
+// one exchange to the next.  Exchange j of the series uses LDS buffer
+// (j - 1) mod 2, fixed per step of the unrolled loop; a series always
+// starts on buffer 0.  The two latest terms alternate between two register
+// sets, so no copies are made.
 template <typename T, bool TRANS>
-FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int NP,
-                            const typename Cplx<T>::type* cf, T sA, T cA, const T (&xr)[4],
-                            const T (&xi)[4], const T (&db)[4], typename Cplx<T>::type* lbuf,
-                            int& cur, T th, T (&ar)[4], T (&ai)[4]) {
+FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* cf, T sA, T cA,
+                            const typename Cplx<T>::type (&x)[4], const T (&db)[4],
+                            typename Cplx<T>::type* buf0, typename Cplx<T>::type* buf1, T th,
+                            typename Cplx<T>::type (&acc)[4]) {
   using T2 = typename Cplx<T>::type;
   const T cj = TRANS ? (T)-1 : (T)1;
-  auto accumulate = [&](const T2 c, const T (&vr)[4], const T (&vi)[4]) {
+  auto accumulate = [&](const T2 c, const T2 (&v)[4]) {
     const T cy = cj * c.y;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      ar[q] = fma(-cy, vi[q], fma(c.x, vr[q], ar[q]));
-      ai[q] = fma(cy, vr[q], fma(c.x, vi[q], ai[q]));
+      acc[q].x = fma(-cy, v[q].y, fma(c.x, v[q].x, acc[q].x));
+      acc[q].y = fma(cy, v[q].x, fma(c.x, v[q].y, acc[q].y));
     }
   };
-  T pr[4], pi_[4], qr[4], qi[4], yr[4], yi[4];  // p = alpha_{m-2}, q = alpha_{m-1}
+  // rec: v = fma(d2, y, -c2 u - v), the next term from C' u (in y), u, v
+  auto rec = [&](T2 (&v)[4], const T2 (&u)[4], const T2 (&y)[4], const T (&d2)[4], T c2) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    ar[q] = ai[q] = (T)0;
-    pr[q] = TRANS ? db[q] * xr[q] : xr[q];
-    pi_[q] = TRANS ? db[q] * xi[q] : xi[q];
+    for (int q = 0; q < 4; ++q) {
+      v[q].x = fma(d2[q], y[q].x, fma(-c2, u[q].x, -v[q].x));
+      v[q].y = fma(d2[q], y[q].y, fma(-c2, u[q].y, -v[q].y));
+    }
+  };
+  T2 p[4], q[4], y[4], c_[4];  // p = alpha_{m-2}, q = alpha_{m-1}; c_: last published
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    acc[k].x = acc[k].y = (T)0;
+    p[k].x = TRANS ? db[k] * x[k].x : x[k].x;
+    p[k].y = TRANS ? db[k] * x[k].y : x[k].y;
   }
-  if (NP >= 2) c_publish<T, TRANS>(own, i0, iL, pr, pi_, lbuf, N, cur, th);
-  accumulate(cf[0], pr, pi_);
+  if (NP >= 2) c_publish<T2, T, TRANS>(w, p, buf0, th, c_);
+  accumulate(cf[0], p);
   if (NP >= 2) {
     T sdb[4], db2[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      sdb[q] = sA * db[q];
-      db2[q] = (T)2 * sdb[q];
+    for (int k = 0; k < 4; ++k) {
+      sdb[k] = sA * db[k];
+      db2[k] = (T)2 * sdb[k];
     }
     T2 c = cf[1];
-    c_finish<T, TRANS>(w, own, yr, yi, lbuf, N, cur, th);
+    c_finish<T2, T, TRANS>(w, c_, y, buf0, th);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      qr[q] = fma(sdb[q], yr[q], -cA * pr[q]);
-      qi[q] = fma(sdb[q], yi[q], -cA * pi_[q]);
+    for (int k = 0; k < 4; ++k) {
+      q[k].x = fma(sdb[k], y[k].x, -cA * p[k].x);
+      q[k].y = fma(sdb[k], y[k].y, -cA * p[k].y);
     }
-    if (NP > 2) c_publish<T, TRANS>(own, i0, iL, qr, qi, lbuf, N, cur, th);
-    accumulate(c, qr, qi);
+    if (NP > 2) c_publish<T2, T, TRANS>(w, q, buf1, th, c_);
+    accumulate(c, q);
     const T c2 = (T)2 * cA;
     for (int m = 2; m < NP; m += 2) {
       c = cf[m];
-      c_finish<T, TRANS>(w, own, yr, yi, lbuf, N, cur, th);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        pr[q] = fma(db2[q], yr[q], fma(-c2, qr[q], -pr[q]));
-        pi_[q] = fma(db2[q], yi[q], fma(-c2, qi[q], -pi_[q]));
-      }
-      if (m + 1 < NP) c_publish<T, TRANS>(own, i0, iL, pr, pi_, lbuf, N, cur, th);
-      accumulate(c, pr, pi_);
+      c_finish<T2, T, TRANS>(w, c_, y, buf1, th);
+      rec(p, q, y, db2, c2);
+      if (m + 1 < NP) c_publish<T2, T, TRANS>(w, p, buf0, th, c_);
+      accumulate(c, p);
       if (m + 1 >= NP) break;
       c = cf[m + 1];
-      c_finish<T, TRANS>(w, own, yr, yi, lbuf, N, cur, th);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        qr[q] = fma(db2[q], yr[q], fma(-c2, pr[q], -qr[q]));
-        qi[q] = fma(db2[q], yi[q], fma(-c2, pi_[q], -qi[q]));
-      }
-      if (m + 2 < NP) c_publish<T, TRANS>(own, i0, iL, qr, qi, lbuf, N, cur, th);
-      accumulate(c, qr, qi);
+      c_finish<T2, T, TRANS>(w, c_, y, buf0, th);
+      rec(q, p, y, db2, c2);
+      if (m + 2 < NP) c_publish<T2, T, TRANS>(w, q, buf1, th, c_);
+      accumulate(c, q);
     }
+    // A following series first writes buffer 0; after an odd number of
+    // exchanges the last one read buffer 0, so every thread must be past it.
+    if ((NP - 1) & 1) __syncthreads();
   }
-  if (TRANS && own) {
+  if (TRANS) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T inv = (T)1 / db[q];
-      ar[q] *= inv;
-      ai[q] *= inv;
+    for (int k = 0; k < 4; ++k) {
+      const T inv = (T)1 / db[k];
+      acc[k].x *= inv;
+      acc[k].y *= inv;
     }
   }
 }
@@ -674,8 +745,8 @@ FPH_DEVINL void cheb_series(const Win& w, bool own, int i0, int iL, int N, int N
 // series in A^T), 2: F F^T (conjugate series, then series).  Block b
 // serves frequency order b / nrhs (longest series first: k = 0, H-1, 1,
 // H-2, ...) and right-hand side b % nrhs; one even plaquette per thread
-// (NT >= Q).  LDS: two complex exchange slices (4 N values of T) and the
-// block's Chebyshev coefficients.
+// (NT >= Q).  LDS: two complex slice buffers (2 S L + kWinPad values each)
+// and the block's Chebyshev coefficients.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
 k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
@@ -687,15 +758,16 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
-  T2* lbuf = reinterpret_cast<T2*>(smem_raw);    // 2 slices x N complex
-  T2* cfs = lbuf + 2 * g.N;                      // coefficients of this block's frequency
-  int cur = 0;
+  const int nbuf = 2 * kpm_row_stride(g.hL) * g.L + kWinPad;
+  T2* buf0 = reinterpret_cast<T2*>(smem_raw);
+  T2* buf1 = buf0 + nbuf;
+  T2* cfs = buf1 + nbuf;  // coefficients of this block's frequency
   const int ko = blockIdx.x / nrhs;
   const int r = blockIdx.x % nrhs;
   const int k = (ko % 2 == 0) ? ko / 2 : H - 1 - ko / 2;
   const int q = threadIdx.x;
   const bool own = q < g.Q;
-  const Win w = make_win(g, own ? q : 0);
+  const Win w = make_win(g, q, own);
   const int i0 = w.x0 + w.row[1], iL = i0 + g.L;
 
   // Everything that does not depend on the solver state is loaded before
@@ -704,19 +776,20 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   const int NP = np[2 * k];
   const T sA = (T)info->s, cA = (T)info->c;
   const T2 c_first = coef[(long)k * kNPMax + threadIdx.x];
-  T xr[4], xi[4], db[4], ar[4], ai[4];
+  T2 x[4], acc[4];
+  T db[4];
   const T2* Zin = Z + ((long)r * H + k) * g.N;
   if (own) {
-    T2 a, b, c, d;
-    ld2c(Zin + i0, a, b);
-    ld2c(Zin + iL, c, d);
-    xr[0] = a.x; xi[0] = a.y; xr[1] = b.x; xi[1] = b.y;
-    xr[2] = c.x; xi[2] = c.y; xr[3] = d.x; xi[3] = d.y;
+    ld2c(Zin + i0, x[0], x[1]);
+    ld2c(Zin + iL, x[2], x[3]);
     db[0] = c4 * dbar[i0]; db[1] = c4 * dbar[i0 + 1];
     db[2] = c4 * dbar[iL]; db[3] = c4 * dbar[iL + 1];
   } else {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) xr[m] = xi[m] = db[m] = (T)0;
+    for (int m = 0; m < 4; ++m) {
+      x[m].x = x[m].y = (T)0;
+      db[m] = (T)1;
+    }
   }
   if (io.in != nullptr) {
     state_begin<NT>(io, r, &s_sh, red_sh);
@@ -728,24 +801,20 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   if ((int)threadIdx.x < NP) cfs[threadIdx.x] = c_first;
   for (int m = threadIdx.x + NT; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
   __syncthreads();
-  const T2* cf = cfs;
   if (op == 0) {
-    cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, th, ar, ai);
+    cheb_series<T, false>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc);
   } else {
-    cheb_series<T, true>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, th, ar, ai);
+    cheb_series<T, true>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc);
     if (op == 2) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        xr[m] = ar[m];
-        xi[m] = ai[m];
-      }
-      cheb_series<T, false>(w, own, i0, iL, g.N, NP, cf, sA, cA, xr, xi, db, lbuf, cur, th, ar, ai);
+      for (int m = 0; m < 4; ++m) x[m] = acc[m];
+      cheb_series<T, false>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc);
     }
   }
   if (own) {
     T2* Zout = Zo + ((long)r * H + k) * g.N;
-    st2c(Zout + i0, ar[0], ai[0], ar[1], ai[1]);
-    st2c(Zout + iL, ar[2], ai[2], ar[3], ai[3]);
+    st2c(Zout + i0, acc[0], acc[1]);
+    st2c(Zout + iL, acc[2], acc[3]);
   }
   if (io.in != nullptr) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
 }
@@ -905,7 +974,8 @@ hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int o
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
                          StateSeq& sq, T th, T c4, hipStream_t s) {
   const StIO io = sq.next(0);
-  const size_t lds = (2 * (size_t)g.N + kNPMax) * sizeof(typename Cplx<T>::type);
+  const size_t nbuf = 2 * (size_t)kpm_row_stride(g.hL) * g.L + kWinPad;
+  const size_t lds = (2 * nbuf + kNPMax) * sizeof(typename Cplx<T>::type);
   auto kern = k_kpm<T, NT>;
   hipError_t e = allow_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
