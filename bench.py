@@ -273,7 +273,7 @@ def profile_roofline(torch, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU: --gpus must be 1 (see the sharding notes for several GPUs)"}))
         sys.exit(2)
     import numpy as np
     import torch
