@@ -7,9 +7,9 @@ preconditioned CG solve of (M^T M) u = Phi to relative residual 1e-8, the
 action S_F = Phi . u and the phonon force dS_F/dx.  Default workload:
 L = 32 (N = 1024), Ltau = 400 (d = 409600), dtau = 0.05, mu = -0.2,
 alpha = 1.2, AR(1)-correlated field.  The Chebyshev orders use
-N_P = floor(db (a1/phi + a2)) with a1 = 0.25, a2 = 1 (--a1, --a2): the
-fastest of a1 in {0.15, 0.25, 0.35, 0.5} in mean solve time over four
-synthetic fields of this shape.
+N_P = floor(db (a1/phi + a2)) with a1 = 0.15, a2 = 12 (--a1, --a2): the
+fastest pair of a sweep (a1 from 0.05 to 0.5, a2 from 1 to 32) in mean
+solve time over four synthetic fields of this shape.
 
 Prints one JSON line: the headline (FP32-refined solves/s), the same step
 with FP64 CG, one step of every solver variant, the fused M^T M roofline
@@ -45,9 +45,9 @@ def parse():
     ap.add_argument("--precond", type=int, default=1,
                     help="1: preconditioned CG in the timed step (default); 0: plain CG; "
                          "-1: the faster of one trial each")
-    ap.add_argument("--a1", type=float, default=0.25,
+    ap.add_argument("--a1", type=float, default=0.15,
                     help="Chebyshev order coefficient a1 of N_P = floor(db (a1/phi + a2))")
-    ap.add_argument("--a2", type=float, default=1.0)
+    ap.add_argument("--a2", type=float, default=12.0)
     ap.add_argument("--matvec-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
@@ -314,7 +314,7 @@ def main():
     variants = {}
     all_variants = (("f32_refined_plain", "f32_refined", False, 0, args.a1),
                     ("f32_refined_precond", "f32_refined", True, 0, args.a1),
-                    ("f32_refined_precond_a1_1", "f32_refined", True, 0, 1.0),
+                    ("f32_refined_precond_a1_a2_1", "f32_refined", True, 0, 1.0),
                     ("f64_plain", "f64", False, 0, args.a1),
                     ("f32_refined_plain_one_launch", "f32_refined", False, 2, args.a1),
                     ("f64_plain_single_reduction", "f64", False, 1, args.a1),
