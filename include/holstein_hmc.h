@@ -107,10 +107,11 @@ typedef struct {
   int32_t zero_guess;   /* 1: start from u = 0; 0: u_dev holds the guess   */
   double ru_delta;      /* FP32_REFINED: recompute the FP64 residual when
                            the FP32 residual has fallen by this factor
-                           since the last recomputation (0 -> 0.3, at most
-                           0.5); shortened automatically when a
-                           recomputation finds the true residual more than
-                           twice the FP32 one                             */
+                           since the last recomputation (0 -> 0.1 with the
+                           preconditioner, 0.3 without; at most 0.5); the
+                           interval is shortened automatically (delta ->
+                           sqrt delta) when a recomputation finds the true
+                           residual more than twice the FP32 one          */
   int32_t chunk;        /* CG iterations enqueued between host checks
                            (0 -> library default); variant 2: the largest
                            number of workgroups (0 -> 128)                 */
