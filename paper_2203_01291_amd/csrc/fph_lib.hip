@@ -46,8 +46,7 @@ struct fph_handle_s {
   Geom g;
   int max_rhs;
   int device;
-  double ch, sh;  // cosh(dtau t), sinh(dtau t)
-  double th, c4;  // tanh(dtau t), ch^4 (operator kernels: C = c4 C', E stored as c4 E)
+  double th, c4;  // tanh(dtau t), cosh(dtau t)^4 (operator kernels: C = c4 C', E stored as c4 E)
   bool have_field;
   double a1, a2;
   // field
@@ -262,10 +261,9 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   h->g.Ltau = lat->Ltau;
   h->g.d = (long)h->g.N * lat->Ltau;
   h->max_rhs = max_rhs;
-  h->ch = std::cosh(lat->dtau * lat->t);
-  h->sh = std::sinh(lat->dtau * lat->t);
+  const double ch = std::cosh(lat->dtau * lat->t);
   h->th = std::tanh(lat->dtau * lat->t);
-  h->c4 = h->ch * h->ch * h->ch * h->ch;
+  h->c4 = ch * ch * ch * ch;
   h->a1 = h->a2 = 1.0;
   hipError_t e = hipGetDevice(&h->device);
   const long d = h->g.d;
@@ -304,8 +302,6 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   if (e == hipSuccess) e = hipMemset(h->st[0], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = hipMemset(h->st[1], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = pc_create(&h->pc, h->g, max_rhs);
-  h->pc.ch = h->ch;
-  h->pc.sh = h->sh;
   h->pc.th = h->th;
   h->pc.c4 = h->c4;
   if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -49,8 +49,7 @@ struct PcTables {
   float2* coef32;
   void* Z;         // complex workspace, max_rhs * H * N (double2)
   void* Z2;
-  double ch, sh;   // checkerboard rotation cosh(dtau t), sinh(dtau t)
-  double th, c4;   // tanh(dtau t) and ch^4: P_A P_B = c4 P'_A P'_B, C2' = [[1, th], [th, 1]]
+  double th, c4;   // tanh(dtau t) and cosh(dtau t)^4: P_A P_B = c4 P'_A P'_B, C2' = [[1, th], [th, 1]]
 };
 
 // First factor of the length-H DFT split H = H1 * H2: at most 10 when
