@@ -201,8 +201,7 @@ FPH_DEVINL T2 cmulc(T2 a, T2 b) {  // a * conj(b)
 }
 
 // Transform workgroups own a tile of KS = 2^lks consecutive sites (all
-// slices of them): KS <= 64 bytes of a slice row, smaller when that leaves
-// too few workgroups to fill the chip.  Workgroups are numbered with
+// slices of them), as wide as pc_tile_log2 allows.  Workgroups are numbered with
 // xcd_contiguous so neighbouring tiles (which share cache lines) run on
 // one XCD.  The two short DFTs read their matrix rows (F, see
 // k_pc_twiddles) and their inputs with unit and constant strides from LDS.
