@@ -498,6 +498,7 @@ __host__ __device__ inline int kpm_row_stride(int hL) {
 struct Win {
   int row[4];        // global row offsets L y of rows y0-1, y0, y0+1, y0+2
   int x0;
+  int qa, qb;        // plaquettes above (y0-2) and below (y0+2), periodic
   int own[4];        // LDS: (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1)
   int hm[4], hp[4];  // LDS: rows y0-1 and y0+2 at columns x0-1, x0, x0+1, x0+2
   int cm[2], cp[2];  // LDS: rows y0 and y0+1 at columns x0-1 and x0+2
@@ -516,6 +517,10 @@ FPH_DEVINL Win make_win(const Geom& g, int q, bool own) {
   w.row[1] = g.L * y0;
   w.row[2] = g.L * (y0 + 1);
   w.row[3] = g.L * yp;
+  const int nrow = g.L / 2;  // plaquette rows
+  const int qy = qq / g.hL;
+  w.qa = qq + g.hL * ((qy == 0) ? nrow - 1 : -1);
+  w.qb = qq + g.hL * ((qy == nrow - 1) ? 1 - nrow : 1);
   const int S = kpm_row_stride(g.hL);
   const int P = S * g.L;  // plane size; the spare entries start at 2 P
   auto li = [&](int x, int y) { return own ? (x & 1) * P + (x >> 1) + S * y : 2 * P; };
@@ -624,28 +629,98 @@ FPH_DEVINL void pb_window_cn(const Win& w, const T2* __restrict__ sl, T th, cons
   out[3].y = fma(th, h1[3].y, h1[2].y);
 }
 
+// One 32-bit lane value from lane (i - n) mod 16 of the same 16-lane row
+// (DPP row rotation right by n).
+template <int N>
+FPH_DEVINL float row_ror(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + N, 0xf, 0xf, true));
+}
+template <int N>
+FPH_DEVINL double row_ror(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull), 0x120 + N, 0xf, 0xf,
+                                          true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x120 + N, 0xf, 0xf, true);
+  return __builtin_bit_cast(double,
+                            ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+template <int N, typename T2>
+FPH_DEVINL T2 row_ror2(T2 v) {
+  T2 r;
+  r.x = row_ror<N>(v.x);
+  r.y = row_ror<N>(v.y);
+  return r;
+}
+
 // y = C' x (TRANS = false: P'_A (P'_B x)) or C'^T x (TRANS = true:
 // P'_B (P'_A x)), C = ch^4 C', for a complex vector held one even
-// plaquette per thread, in two halves with one LDS exchange between them:
-// c_publish writes the thread's four sites (x, or P'_A x) into an LDS
-// slice buffer and returns them in c; c_finish waits at the barrier and
-// forms P'_B at the thread's sites from the window and c (then P'_A for
-// C').  Two buffers alternate between applies, so one barrier per apply
+// plaquette per thread, in two halves with one LDS exchange between them.
+// Two buffers alternate between applies, so one barrier per apply
 // suffices; work placed between the halves overlaps the exchange.  The
 // diagonal (dbar ch^4) of Bbar is applied by the caller.
-template <typename T2, typename T, bool TRANS>
-FPH_DEVINL void c_publish(const Win& w, const T2 (&x)[4], T2* buf, T th, T2 (&c)[4]) {
+//
+// Window form (any L): c_publish writes the thread's four sites (x, or
+// P'_A x) into the slice buffer and returns them in c; c_finish waits at
+// the barrier and forms P'_B at the thread's sites from the window and c
+// (then P'_A for C').
+//
+// Row form (ROW16: L = 32, one plaquette row per 16-lane row of a wave,
+// every lane owning a plaquette): P'_B pairs sites along x within a
+// plaquette row, whose neighbours the thread takes from lanes i -/+ 1 of
+// its row by DPP rotations (periodic in x as the row is).  c_publish forms
+// that x half of P'_B on its own two rows and writes it (two complex values
+// per row, rows y0 and y0+1 in separate arrays) and returns it in c;
+// c_finish waits and combines it along y with the same values of the
+// plaquettes above (their row y0-1) and below (their row y0+2): four loads
+// instead of twelve, and each row's x half is formed once.  The arithmetic
+// per output is the window form's, so the results are the same.
+template <typename T2, typename T, bool TRANS, bool ROW16>
+FPH_DEVINL void c_publish(const Win& w, const T2 (&x)[4], T2* buf, T th, T2 (&c)[4], int q,
+                          int Q) {
 #pragma unroll
   for (int m = 0; m < 4; ++m) c[m] = x[m];
   if (TRANS) plaq_rot_c(c, th);
+  if (!ROW16) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) buf[w.own[m]] = c[m];
+    for (int m = 0; m < 4; ++m) buf[w.own[m]] = c[m];
+  } else {
+    const T2 l1 = row_ror2<1>(c[1]), l3 = row_ror2<1>(c[3]);    // sites (x0-1, y0), (x0-1, y0+1)
+    const T2 r0 = row_ror2<15>(c[0]), r2 = row_ror2<15>(c[2]);  // sites (x0+2, y0), (x0+2, y0+1)
+    T2 h[4];
+    h[0].x = fma(th, l1.x, c[0].x);
+    h[0].y = fma(th, l1.y, c[0].y);
+    h[1].x = fma(th, r0.x, c[1].x);
+    h[1].y = fma(th, r0.y, c[1].y);
+    h[2].x = fma(th, l3.x, c[2].x);
+    h[2].y = fma(th, l3.y, c[2].y);
+    h[3].x = fma(th, r2.x, c[3].x);
+    h[3].y = fma(th, r2.y, c[3].y);
+    st2c(buf + 2 * q, h[0], h[1]);
+    st2c(buf + 2 * (Q + q), h[2], h[3]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) c[m] = h[m];
+  }
 }
 
-template <typename T2, typename T, bool TRANS>
-FPH_DEVINL void c_finish(const Win& w, const T2 (&c)[4], T2 (&y)[4], const T2* buf, T th) {
+template <typename T2, typename T, bool TRANS, bool ROW16>
+FPH_DEVINL void c_finish(const Win& w, const T2 (&c)[4], T2 (&y)[4], const T2* buf, T th, int Q) {
   __syncthreads();
-  pb_window_cn(w, buf, th, c, y);
+  if (!ROW16) {
+    pb_window_cn(w, buf, th, c, y);
+  } else {
+    T2 t0, t1, b0, b1;
+    ld2c(buf + 2 * (Q + w.qa), t0, t1);  // row y0-1: the plaquette above's second row
+    ld2c(buf + 2 * w.qb, b0, b1);        // row y0+2: the plaquette below's first row
+    y[0].x = fma(th, t0.x, c[0].x);
+    y[0].y = fma(th, t0.y, c[0].y);
+    y[1].x = fma(th, t1.x, c[1].x);
+    y[1].y = fma(th, t1.y, c[1].y);
+    y[2].x = fma(th, b0.x, c[2].x);
+    y[2].y = fma(th, b0.y, c[2].y);
+    y[3].x = fma(th, b1.x, c[3].x);
+    y[3].y = fma(th, b1.y, c[3].y);
+  }
   if (!TRANS) plaq_rot_c(y, th);
 }
 
@@ -663,11 +738,11 @@ FPH_DEVINL void c_finish(const Win& w, const T2 (&c)[4], T2 (&y)[4], const T2* b
 // (j - 1) mod 2, fixed per step of the unrolled loop; a series always
 // starts on buffer 0.  The two latest terms alternate between two register
 // sets, so no copies are made.
-template <typename T, bool TRANS>
+template <typename T, bool TRANS, bool ROW16>
 FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* cf, T sA, T cA,
                             const typename Cplx<T>::type (&x)[4], const T (&db)[4],
                             typename Cplx<T>::type* buf0, typename Cplx<T>::type* buf1, T th,
-                            typename Cplx<T>::type (&acc)[4]) {
+                            typename Cplx<T>::type (&acc)[4], int qid, int Q) {
   using T2 = typename Cplx<T>::type;
   const T cj = TRANS ? (T)-1 : (T)1;
   auto accumulate = [&](const T2 c, const T2 (&v)[4]) {
@@ -693,7 +768,7 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
     p[k].x = TRANS ? db[k] * x[k].x : x[k].x;
     p[k].y = TRANS ? db[k] * x[k].y : x[k].y;
   }
-  if (NP >= 2) c_publish<T2, T, TRANS>(w, p, buf0, th, c_);
+  if (NP >= 2) c_publish<T2, T, TRANS, ROW16>(w, p, buf0, th, c_, qid, Q);
   accumulate(cf[0], p);
   if (NP >= 2) {
     T sdb[4], db2[4];
@@ -703,26 +778,26 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
       db2[k] = (T)2 * sdb[k];
     }
     T2 c = cf[1];
-    c_finish<T2, T, TRANS>(w, c_, y, buf0, th);
+    c_finish<T2, T, TRANS, ROW16>(w, c_, y, buf0, th, Q);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       q[k].x = fma(sdb[k], y[k].x, -cA * p[k].x);
       q[k].y = fma(sdb[k], y[k].y, -cA * p[k].y);
     }
-    if (NP > 2) c_publish<T2, T, TRANS>(w, q, buf1, th, c_);
+    if (NP > 2) c_publish<T2, T, TRANS, ROW16>(w, q, buf1, th, c_, qid, Q);
     accumulate(c, q);
     const T c2 = (T)2 * cA;
     for (int m = 2; m < NP; m += 2) {
       c = cf[m];
-      c_finish<T2, T, TRANS>(w, c_, y, buf1, th);
+      c_finish<T2, T, TRANS, ROW16>(w, c_, y, buf1, th, Q);
       rec(p, q, y, db2, c2);
-      if (m + 1 < NP) c_publish<T2, T, TRANS>(w, p, buf0, th, c_);
+      if (m + 1 < NP) c_publish<T2, T, TRANS, ROW16>(w, p, buf0, th, c_, qid, Q);
       accumulate(c, p);
       if (m + 1 >= NP) break;
       c = cf[m + 1];
-      c_finish<T2, T, TRANS>(w, c_, y, buf0, th);
+      c_finish<T2, T, TRANS, ROW16>(w, c_, y, buf0, th, Q);
       rec(q, p, y, db2, c2);
-      if (m + 2 < NP) c_publish<T2, T, TRANS>(w, q, buf1, th, c_);
+      if (m + 2 < NP) c_publish<T2, T, TRANS, ROW16>(w, q, buf1, th, c_, qid, Q);
       accumulate(c, q);
     }
     // A following series first writes buffer 0; after an odd number of
@@ -745,7 +820,7 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
 // H-2, ...) and right-hand side b % nrhs; one even plaquette per thread
 // (NT >= Q).  LDS: two complex slice buffers (2 S L + kWinPad values each)
 // and the block's Chebyshev coefficients.
-template <typename T, int NT>
+template <typename T, int NT, bool ROW16>
 __global__ void __launch_bounds__(NT)
 k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       const int* __restrict__ np, const typename Cplx<T>::type* __restrict__ coef,
@@ -800,13 +875,13 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   for (int m = threadIdx.x + NT; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
   __syncthreads();
   if (op == 0) {
-    cheb_series<T, false>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc);
+    cheb_series<T, false, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
   } else {
-    cheb_series<T, true>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc);
+    cheb_series<T, true, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
     if (op == 2) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) x[m] = acc[m];
-      cheb_series<T, false>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc);
+      cheb_series<T, false, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
     }
   }
   if (own) {
@@ -967,14 +1042,14 @@ hipError_t pc_inv(const PcTables* pc, const Geom& g, int nrhs, const typename Cp
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool ROW16 = false>
 hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
                          StateSeq& sq, T th, T c4, hipStream_t s) {
   const StIO io = sq.next(0);
   const size_t nbuf = 2 * (size_t)kpm_row_stride(g.hL) * g.L + kWinPad;
   const size_t lds = (2 * nbuf + kNPMax) * sizeof(typename Cplx<T>::type);
-  auto kern = k_kpm<T, NT>;
+  auto kern = k_kpm<T, NT, ROW16>;
   hipError_t e = allow_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
   const auto* cf = (const typename Cplx<T>::type*)(sizeof(T) == 8 ? (const void*)pc->coef64 : (const void*)pc->coef32);
@@ -987,6 +1062,9 @@ template <typename T>
 hipError_t pc_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                   const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo, StateSeq& sq,
                   T th, T c4, hipStream_t s) {
+  // L = 32: each plaquette row is one 16-lane row of a wave (row form).
+  if (g.hL == 16 && g.Q == 256)
+    return pc_launch_kpm<T, 256, true>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
   if (g.Q <= 64) return pc_launch_kpm<T, 64>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
   if (g.Q <= 256) return pc_launch_kpm<T, 256>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
   if (g.Q <= 512) return pc_launch_kpm<T, 512>(pc, g, dbar, op, nrhs, Z, Zo, sq, th, c4, s);
