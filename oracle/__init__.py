@@ -21,9 +21,12 @@ definition in the paper (arXiv:2203.01291):
 * ``precond``  - the adiabatic preconditioner P, its Fourier-space block
                  form and its Chebyshev (KPM) apply (Sec. V A, Eqs. P_def,
                  Bbar, udef, Mww, P_change_basis; App. C).
+* ``hmc``      - the hybrid Monte Carlo update with A = M: bosonic action
+                 and force, Fourier-acceleration mass, time-step splitting
+                 leapfrog and the Metropolis test (Sec. III, Algorithm 1).
 
 Parity status of each function is stated in its docstring; a function with
 no independent pin says "parity unpinned".
 """
 
-from . import lattice, solve, force, precond  # noqa: F401
+from . import lattice, solve, force, precond, hmc  # noqa: F401

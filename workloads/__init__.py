@@ -7,7 +7,7 @@ Gaussian pseudofermion draws ``phi`` and Rademacher measurement vectors
 sharing any computation.
 """
 
-from .configs import CONFIGS, Params, get_config  # noqa: F401
+from .configs import CONFIGS, HmcParams, Params, get_config, hmc_params  # noqa: F401
 from .inputs import (  # noqa: F401
     rng_for,
     phonon_field,
@@ -16,4 +16,5 @@ from .inputs import (  # noqa: F401
     perturbed_field,
     batched_systems,
     fd_sample_indices,
+    hmc_draws,
 )

@@ -12,7 +12,7 @@ shape stand in for them.
 """
 
 from dataclasses import dataclass, field
-from typing import Tuple
+from typing import Optional, Tuple
 
 
 @dataclass(frozen=True)
@@ -69,3 +69,29 @@ CONFIGS = {
 
 def get_config(key: str) -> Params:
     return CONFIGS[key]
+
+
+@dataclass(frozen=True)
+class HmcParams:
+    """Settings of one hybrid Monte Carlo update (Sec. III).
+
+    The paper's benchmarks use dt = 1/(100 omega0), Nt = 100 steps, nt = 10
+    bosonic sub-steps and m_reg = omega0 (Sec. III C), two pseudofermion
+    fields, and solve to 1e-5 for forces and 1e-10 for the action difference
+    (Sec. V B).  m_reg = None means no Fourier acceleration (M = dtau I).
+    """
+    omega0: float
+    m_reg: Optional[float]
+    dt: float
+    Nt: int = 100
+    nt: int = 10
+    nfields: int = 2
+    tol_force: float = 1e-5
+    tol_action: float = 1e-10
+
+
+def hmc_params(p: Params, **over) -> HmcParams:
+    """The paper's HMC settings for configuration ``p`` (phonon frequency p.omega)."""
+    base = dict(omega0=p.omega, m_reg=p.omega, dt=1.0 / (100.0 * p.omega))
+    base.update(over)
+    return HmcParams(**base)

@@ -9,6 +9,9 @@ cfg_id, stream, *extra]))`` and is returned in FP64 on the host.  Streams:
     3  lattice sides of batched systems
     4  finite-difference component picks
     5  perturbation of x away from the field that defined Phi
+    6  HMC pseudofermion draws R_sigma         shape [nfields, Ltau, N]
+    7  HMC momentum draws R                    shape [Ltau, N]
+    8  HMC Metropolis uniform r                scalar in [0, 1)
 
 Layout convention: site index i = x + L*y is fastest, then the time slice
 tau = 0..Ltau-1, then the right-hand-side index.  The pseudofermion field
@@ -96,3 +99,19 @@ def fd_sample_indices(p, count, L=None):
     d = p.Ltau * L * L
     flat = rng_for(p.cfg_id, 4).choice(d, size=min(count, d), replace=False)
     return [(int(k) // (L * L), int(k) % (L * L)) for k in flat]
+
+
+def hmc_draws(p, nfields=2, traj=0, L=None):
+    """Random inputs of one HMC update: (R_fields, R_mom, r_uniform).
+
+    R_fields[sigma] ~ N(0, 1) defines Phi_sigma = M(x)^T R_sigma
+    (Eq. PhiSample-1), R_mom ~ N(0, 1) defines p = sqrt(M) R (Eq. sample_p)
+    and r ~ U[0, 1) is the Metropolis draw (Algorithm 1).  ``traj`` numbers
+    successive updates.
+    """
+    L = p.L if L is None else L
+    N = L * L
+    R_fields = rng_for(p.cfg_id, 6, traj).standard_normal((nfields, p.Ltau, N))
+    R_mom = rng_for(p.cfg_id, 7, traj).standard_normal((p.Ltau, N))
+    r = float(rng_for(p.cfg_id, 8, traj).random())
+    return R_fields, R_mom, r
