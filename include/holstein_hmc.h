@@ -149,6 +149,10 @@ int fph_create(fph_handle_t* h, const fph_lattice_t* lat, int32_t max_rhs);
 /* Release the handle and its workspace (synchronises the device). */
 int fph_destroy(fph_handle_t h);
 
+/* Copy the handle's lattice to *lat and its right-hand-side capacity to
+ * *max_rhs (either may be NULL).  Host only. */
+int fph_get_lattice(fph_handle_t h, fph_lattice_t* lat, int32_t* max_rhs);
+
 /* Per-field setup from x_dev[Ltau][N] (FP64, device): E = exp(-dtau V)
  * in FP64 and FP32 (Eq. B_def), dbar_i = mean_tau E[tau][i] (Eq. expnVbar),
  * spectral bounds of Bbar = diag(dbar) C enclosing its real eigenvalues,
@@ -245,6 +249,107 @@ int fph_batch_tune(fph_batch_t bh, const fph_pcg_opts_t* opts, int32_t* best_hos
 
 /* Release the batch (synchronises the device). */
 int fph_batch_destroy(fph_batch_t bh);
+
+
+/* ------------------------------------------------------------------ */
+/* Hybrid Monte Carlo update of the phonon field (Sec. III).           */
+/*
+ * Action sampled (A = M, Lambda = I; Eqs. S_prime, Z_path_orig, S_F):
+ *   S'(x) = S_B(x) - dtau*alpha*sum_{i,tau} x_{i,tau}
+ *           + 1/2 sum_sigma Phi_sigma . (M^T M)^{-1} Phi_sigma,
+ *   S_B   = dtau/2 sum_{i,tau} [omega0^2 x^2 + ((x_{tau+1} - x_tau)/dtau)^2]
+ *           with x_{i,Ltau} = x_{i,0}                          (Eq. S_B).
+ * Kinetic energy p^T Mass^{-1} p / 2 with the Fourier-acceleration mass
+ *   Mass = F^{-1} Mtilde F over imaginary time (Sec. III B 1),
+ *   Mtilde_w = dtau (m_reg^2 + omega0^2 + 4/dtau^2 sin^2(pi w/Ltau))
+ *              / (m_reg^2 + omega0^2),
+ * the sine argument being pi w/Ltau (the value the stencil of Eq. dSB_dx
+ * gives; the paper's Eq. Qww_def prints 2 pi w/Ltau).  m_reg < 0 or +inf
+ * selects Mass = dtau I (no Fourier acceleration).
+ * Momenta and forces share the field layout [Ltau][N] (FP64).
+ */
+
+typedef struct fph_hmc_s* fph_hmc_t;
+
+typedef struct {
+  double omega0;               /* phonon frequency (> 0)                       */
+  double m_reg;                /* mass regularisation; < 0 or inf: Mass = dtau I */
+  double dt;                   /* integration step Delta t (> 0)               */
+  int32_t Nt;                  /* steps per trajectory (>= 1; paper: 100)       */
+  int32_t nt;                  /* bosonic sub-steps per step (>= 1; paper: 10)  */
+  int32_t nfields;             /* pseudofermion fields, 1..max_rhs (paper: 2)   */
+  double a1, a2;               /* Chebyshev-order constants for fph_set_field   */
+  fph_pcg_opts_t force_solve;  /* solves for the force (paper: tol 1e-5)        */
+  fph_pcg_opts_t action_solve; /* solve for S_F at the end (paper: tol 1e-10)   */
+} fph_hmc_opts_t;
+
+typedef struct {
+  double H_i, H_f;      /* H = S' + K before and after the trajectory (FP64)    */
+  double SB_i, SB_f;    /* S_B - dtau*alpha*sum x                              */
+  double SF_i, SF_f;    /* 1/2 sum_sigma Phi.u; SF_i = 1/2 sum |R_sigma|^2      */
+  double K_i, K_f;      /* p^T Mass^{-1} p / 2                                  */
+  double accept_prob;   /* min(1, exp(-(H_f - H_i)))                            */
+  int32_t accepted;     /* 1 if x_dev now holds x_f                             */
+  int32_t status;       /* OR of the FPH_ST_* bits of every solve               */
+  int32_t solves;       /* pcg_solve calls                                      */
+  int32_t cg_iters;     /* CG iterations over all solves and fields             */
+  int32_t matvecs;      /* M^T M applications over all solves and fields        */
+  int32_t pad;
+} fph_hmc_stats_t;
+
+/* Create an HMC context on solver handle h (which must outlive it) with the
+ * given options: allocates its device workspace and enqueues, on `stream`,
+ * the imaginary-time kernels of the mass (Mass^{-1}, sqrt(Mass), Mass) and of
+ * the nt bosonic sub-steps (below).  Errors: FPH_E_NULL, FPH_E_ARG (a
+ * non-finite or out-of-range option), FPH_E_NRHS (nfields), FPH_E_HIP. */
+int fph_hmc_create(fph_hmc_t* hh, fph_handle_t h, const fph_hmc_opts_t* opts, void* stream);
+
+/* Release the context (synchronises the device). */
+int fph_hmc_destroy(fph_hmc_t hh);
+
+/* out_dev[0] = S_B(x) (Eq. S_B), out_dev[1] = -dtau*alpha*sum x (the linear
+ * term of Eq. Z_path_orig), both FP64 device scalars.  Enqueue only. */
+int bosonic_action(fph_hmc_t hh, const double* x_dev, double* out_dev, void* stream);
+
+/* grad_dev += scale * (dS_B/dx - dtau*alpha), dS_B/dx of Eq. (dSB_dx),
+ * periodic in tau.  Enqueue only. */
+int bosonic_force(fph_hmc_t hh, const double* x_dev, double* grad_dev, double scale,
+                  void* stream);
+
+typedef enum { FPH_MASS_INV = 0, FPH_MASS_SQRT = 1, FPH_MASS = 2 } fph_mass_op_t;
+
+/* out = op(in) for nvec vectors [Ltau][N]: Mass^{-1}, sqrt(Mass) or Mass
+ * (Sec. III B 1, Eq. dynamical_M_def), each a real symmetric circulant over
+ * imaginary time applied site by site.  in and out must not overlap.
+ * Enqueue only. */
+int hmc_mass_apply(fph_hmc_t hh, int32_t op, int32_t nvec, const double* in_dev, double* out_dev,
+                   void* stream);
+
+/* The nt bosonic sub-steps of one time step of Algorithm 1, in place:
+ *   nt times { p -= h/2 g(x); x += h Mass^{-1} p; p -= h/2 g(x) },
+ *   h = dt/nt, g = dS_B/dx - dtau*alpha.
+ * The force is linear in x and every operator is diagonal in the Fourier
+ * basis, so the nt sub-steps are applied as one exact map per Fourier mode
+ * (a 2x2 matrix, plus a constant in the w = 0 mode), i.e. four real
+ * circulants over imaginary time.  Enqueue only. */
+int hmc_boson_steps(fph_hmc_t hh, double* x_dev, double* p_dev, void* stream);
+
+/* One HMC trial update (Algorithm 1) of the field x_dev [Ltau][N]:
+ *   Phi_sigma = M(x_i)^T R_sigma (R_fields_dev [nfields][Ltau][N]);
+ *   p = sqrt(Mass) R (R_mom_dev [Ltau][N]);
+ *   Nt steps of: p -= dt/2 dS_F/dx; nt bosonic sub-steps; p -= dt/2 dS_F/dx,
+ *   the fermion force from pcg_solve with opts.force_solve (each solve
+ *   starting from the previous solution) and fermion_force (scale 1/2 per
+ *   field); S_F(x_f) from a solve with opts.action_solve;
+ *   accept if r_uniform < exp(-(H_f - H_i)).
+ * On acceptance x_dev receives x_f; otherwise it is left unchanged.  A
+ * trajectory with a non-finite energy, a solve that broke down or met a
+ * non-finite value, or an action solve that did not converge is rejected
+ * (stats.status tells which).  p_out_dev (may be NULL) receives p_f.  On
+ * return the solver handle's field is that of x_dev.  Blocks until done. */
+int hmc_trajectory(fph_hmc_t hh, double* x_dev, const double* R_fields_dev,
+                   const double* R_mom_dev, double r_uniform, double* p_out_dev,
+                   fph_hmc_stats_t* stats_host, void* stream);
 
 #ifdef __cplusplus
 }

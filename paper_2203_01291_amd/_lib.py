@@ -43,11 +43,35 @@ class System(ctypes.Structure):
                 ("b_dev", ctypes.c_void_p), ("u_dev", ctypes.c_void_p)]
 
 
+class HmcOpts(ctypes.Structure):
+    _fields_ = [("omega0", ctypes.c_double), ("m_reg", ctypes.c_double), ("dt", ctypes.c_double),
+                ("Nt", ctypes.c_int32), ("nt", ctypes.c_int32), ("nfields", ctypes.c_int32),
+                ("a1", ctypes.c_double), ("a2", ctypes.c_double),
+                ("force_solve", PcgOpts), ("action_solve", PcgOpts)]
+
+
+class HmcStats(ctypes.Structure):
+    _fields_ = [("H_i", ctypes.c_double), ("H_f", ctypes.c_double),
+                ("SB_i", ctypes.c_double), ("SB_f", ctypes.c_double),
+                ("SF_i", ctypes.c_double), ("SF_f", ctypes.c_double),
+                ("K_i", ctypes.c_double), ("K_f", ctypes.c_double),
+                ("accept_prob", ctypes.c_double), ("accepted", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("solves", ctypes.c_int32),
+                ("cg_iters", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+FPH_MASS_INV, FPH_MASS_SQRT, FPH_MASS = 0, 1, 2
+
 EXPORTS = {
     "fph_version": (ctypes.c_char_p, []),
     "fph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fph_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Lattice), ctypes.c_int32]),
     "fph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fph_get_lattice": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Lattice),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     "fph_set_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_void_p]),
     "fermion_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -69,6 +93,20 @@ EXPORTS = {
     "fph_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PcgOpts),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "fph_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fph_hmc_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                      ctypes.POINTER(HmcOpts), ctypes.c_void_p]),
+    "fph_hmc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "bosonic_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "bosonic_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_double, ctypes.c_void_p]),
+    "hmc_mass_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hmc_boson_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "hmc_trajectory": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                      ctypes.POINTER(HmcStats), ctypes.c_void_p]),
 }
 
 _lib = None

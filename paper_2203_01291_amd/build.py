@@ -5,7 +5,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "fph_lib.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("fph_lib.hip", "fph_hmc.hip")]
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libholstein_hmc.so")
 
@@ -25,7 +25,7 @@ def build(verbose=True):
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,542 @@
+// Hybrid Monte Carlo update of the phonon field (Sec. III, Algorithm 1),
+// built on the solver's C ABI (fph_set_field, fermion_matvec, pcg_solve,
+// fermion_force) plus the imaginary-time kernels of this file.
+//
+// Everything bosonic is diagonal in the Fourier basis over imaginary time:
+// the force dS_B/dx = Q x (Eq. bosonic_force), the mass Mass = F^-1 Mtilde F
+// (Eq. dynamical_M_def), and the constant force -dtau*alpha of the linear
+// term lives in the w = 0 mode only.  Each operator is therefore a real
+// symmetric circulant over tau, applied site by site, and the nt bosonic
+// sub-steps of one time step compose into one affine map per mode.  The
+// circulant kernels are built once per context from per-mode values.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/holstein_hmc.h"
+#include "fph_internal.h"
+
+namespace {
+
+constexpr int kRows = 8;         // output time slices per lane (circulant kernel)
+constexpr int kRedBlocks = 512;  // partial sums per reduction
+constexpr int kNTab = 7;         // circulant tables: 2x2 step map, Mass^-1, sqrt Mass, Mass
+constexpr int kEn = 16;          // device energy slots
+
+enum { TAB_XX = 0, TAB_XP = 1, TAB_PX = 2, TAB_PP = 3, TAB_MINV = 4, TAB_MSQRT = 5, TAB_MASS = 6 };
+enum { EN_SB_I = 0, EN_LIN_I, EN_R2, EN_K_I, EN_SB_F, EN_LIN_F, EN_K_F };
+
+// ------------------------------------------------------------------ tables
+
+// Per Fourier mode w: the nt-sub-step map of (x, p, 1) under
+//   p -= h/2 (q x - f); x += h p / m; p -= h/2 (q x - f),
+// with q = Qtilde_w (Eq. Qww_def, sine argument pi w/Ltau), m = Mtilde_w
+// and f the constant force per slice (w = 0 only), composed by running the
+// sub-steps on the three basis states.  vals[k][w]: the map's 2x2 block,
+// 1/m, sqrt m, m.  cst[0..1]: the map's constant column in the w = 0 mode.
+__global__ void __launch_bounds__(64)
+k_hmc_modes(int Ltau, double dtau, double omega0, double m_reg, double h, int nt, double f_lin,
+            double* __restrict__ vals, double* __restrict__ cst) {
+  const int w = blockIdx.x * 64 + threadIdx.x;
+  if (w >= Ltau) return;
+  const double s = sinpi((double)w / Ltau);
+  const double lap = 4.0 / (dtau * dtau) * s * s;
+  const double q = dtau * (omega0 * omega0 + lap);
+  double m = dtau;
+  if (m_reg >= 0.0) {
+    const double r = m_reg * m_reg + omega0 * omega0;
+    m = dtau * (r + lap) / r;
+  }
+  const double f = (w == 0) ? f_lin : 0.0;
+  double T[3][2];  // T[c] = (x, p) image of basis state c
+  for (int c = 0; c < 3; ++c) {
+    double x = (c == 0) ? 1.0 : 0.0, p = (c == 1) ? 1.0 : 0.0;
+    const double one = (c == 2) ? 1.0 : 0.0;
+    for (int k = 0; k < nt; ++k) {
+      p -= 0.5 * h * (q * x - f * one);
+      x += h * p / m;
+      p -= 0.5 * h * (q * x - f * one);
+    }
+    T[c][0] = x;
+    T[c][1] = p;
+  }
+  vals[TAB_XX * Ltau + w] = T[0][0];
+  vals[TAB_XP * Ltau + w] = T[1][0];
+  vals[TAB_PX * Ltau + w] = T[0][1];
+  vals[TAB_PP * Ltau + w] = T[1][1];
+  vals[TAB_MINV * Ltau + w] = 1.0 / m;
+  vals[TAB_MSQRT * Ltau + w] = sqrt(m);
+  vals[TAB_MASS * Ltau + w] = m;
+  if (w == 0) {
+    cst[0] = T[2][0];
+    cst[1] = T[2][1];
+  }
+}
+
+// tab[k][e] = K_k[(e - off) mod Ltau], K_k[j] = (1/Ltau) sum_w vals[k][w] cos(2 pi w j / Ltau):
+// the real circulant of the even mode values, stored over the index range the
+// sliding window of k_tau_circ reads (e in [0, ts)).  Launch: grid (ceil(ts/64), kNTab).
+__global__ void __launch_bounds__(64)
+k_hmc_tables(int Ltau, int ts, int off, const double* __restrict__ vals, double* __restrict__ tab) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (e >= ts) return;
+  const int j = (((e - off) % Ltau) + Ltau) % Ltau;
+  const double* v = vals + (long)k * Ltau;
+  double acc = 0.0;
+  for (int w = 0; w < Ltau; ++w) {
+    const int r = (int)(((long)w * j) % Ltau);
+    acc += v[w] * cospi(2.0 * r / Ltau);
+  }
+  tab[(long)k * ts + e] = acc / Ltau;
+}
+
+// ------------------------------------------------------- circulant apply
+
+// out_o[tau][i] = sum_n sum_s K_{o,n}[(tau - s) mod Ltau] in_n[s][i] + cst[o]
+// for o < NO, n < NI (NI = NO = 1: one circulant; 2: the 2x2 step map).
+// Lane = site, kRows output slices per wave.  The kernel values are uniform
+// across the wave (scalar loads); a ring of kRows of them per (o, n) slides
+// by one entry per input slice s: with t0 and s0 multiples of kRows, slot j
+// of the ring holds K[m] for the unique m = j (mod kRows) in the current
+// window, and output row j at step u reads slot (j - u) mod kRows.
+// tab_{o,n} = tab + (o*NI + n)*ts, indexed by m + off.
+// Launch: grid (ceil(N/64), ceil(Ltau/kRows), nvec), block 64.
+template <int NI, int NO>
+__global__ void __launch_bounds__(64)
+k_tau_circ(int N, int Ltau, long d, int ts, int off, const double* __restrict__ tab,
+           const double* __restrict__ cst, const double* __restrict__ in0,
+           const double* __restrict__ in1, double* __restrict__ out0, double* __restrict__ out1) {
+  constexpr int R = kRows;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const bool act = i < N;
+  const int ic = act ? i : 0;
+  const int t0 = blockIdx.y * R;
+  const long voff = (long)blockIdx.z * d;
+  const double* in[2] = {in0 + voff, (NI > 1) ? in1 + voff : nullptr};
+  double ring[NO][NI][R];
+  double acc[NO][R];
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int n = 0; n < NI; ++n)
+#pragma unroll
+      for (int j = 0; j < R; ++j) ring[o][n][j] = tab[(o * NI + n) * ts + off + t0 + j];
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[o][j] = 0.0;
+
+  for (int s0 = 0; s0 < Ltau; s0 += R) {
+    double v[NI][R];
+#pragma unroll
+    for (int n = 0; n < NI; ++n)
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int s = s0 + u;
+        v[n][u] = (s < Ltau) ? in[n][(long)s * N + ic] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+#pragma unroll
+      for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int n = 0; n < NI; ++n)
+#pragma unroll
+          for (int j = 0; j < R; ++j)
+            acc[o][j] = fma(ring[o][n][(j - u) & (R - 1)], v[n][u], acc[o][j]);
+      const int m = t0 - s0 - u - 1;  // entering the window; leaving: m + R
+#pragma unroll
+      for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int n = 0; n < NI; ++n) ring[o][n][(R - 1 - u) & (R - 1)] = tab[(o * NI + n) * ts + off + m];
+    }
+  }
+  if (!act) return;
+  double* out[2] = {out0 + voff, (NO > 1) ? out1 + voff : nullptr};
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const double c = cst ? cst[o] : 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int t = t0 + j;
+      if (t < Ltau) out[o][(long)t * N + i] = acc[o][j] + c;
+    }
+  }
+}
+
+// ------------------------------------------------------------- reductions
+
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NT / 64; ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// part[0][b], part[1][b]: block partial sums of the S_B summand of Eq. (S_B)
+// and of x, over x[Ltau][N] with x_{Ltau} = x_0.  Launch: grid kRedBlocks, block 256.
+__global__ void __launch_bounds__(256)
+k_sb_partials(int N, int Ltau, const double* __restrict__ x, double omega0, double dtau,
+              double* __restrict__ part) {
+  __shared__ double sh[4];
+  const long d = (long)N * Ltau;
+  const double w2 = omega0 * omega0, idt = 1.0 / dtau;
+  double a = 0.0, b = 0.0;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
+    const long kn = (k + N < d) ? k + N : k + N - d;
+    const double xv = x[k];
+    const double g = (x[kn] - xv) * idt;
+    a += w2 * xv * xv + g * g;
+    b += xv;
+  }
+  a = block_sum<256>(a, sh);
+  b = block_sum<256>(b, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[kRedBlocks + blockIdx.x] = b;
+  }
+}
+
+// part[b]: block partial sums of a . b over n values.  Launch: grid kRedBlocks, block 256.
+__global__ void __launch_bounds__(256)
+k_dot_part(long n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256) s += a[k] * b[k];
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out[c] = scale[c] * sum_b part[c][b] for c < blockIdx count, in block order.
+// Launch: grid ncol, block 256.
+__global__ void __launch_bounds__(256)
+k_sum_cols(const double* __restrict__ part, double s0, double s1, double* __restrict__ out0,
+           double* __restrict__ out1) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += 256) v += part[c * kRedBlocks + b];
+  v = block_sum<256>(v, sh);
+  if (threadIdx.x == 0) {
+    if (c == 0) *out0 = s0 * v;
+    else *out1 = s1 * v;
+  }
+}
+
+// grad += scale * (dtau (omega0^2 x - (x_{tau+1} - 2 x_tau + x_{tau-1})/dtau^2) - dtau alpha),
+// periodic in tau (Eq. dSB_dx plus the linear term).
+__global__ void __launch_bounds__(256)
+k_sb_force(int N, int Ltau, const double* __restrict__ x, double omega0, double dtau, double alpha,
+           double scale, double* __restrict__ grad) {
+  const long d = (long)N * Ltau;
+  const double w2 = omega0 * omega0, idt2 = 1.0 / (dtau * dtau);
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
+    const long kn = (k + N < d) ? k + N : k + N - d;
+    const long kp = (k >= N) ? k - N : k - N + d;
+    const double xv = x[k];
+    const double f = dtau * (w2 * xv - (x[kn] - 2.0 * xv + x[kp]) * idt2) - dtau * alpha;
+    grad[k] += scale * f;
+  }
+}
+
+int grid_for(long n) {
+  const long b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+bool opts_ok(const fph_pcg_opts_t& o) {
+  return std::isfinite(o.tol) && o.tol > 0.0 && o.maxiter >= 1;
+}
+
+}  // namespace
+
+struct fph_hmc_s {
+  fph_handle_t h;
+  fph_lattice_t lat;
+  int max_rhs;
+  int N, Ltau;
+  long d;
+  int ts, off;  // circulant table stride and index offset
+  fph_hmc_opts_t o;
+  double* tab;   // [kNTab][ts]
+  double* vals;  // [kNTab][Ltau]
+  double* cst;   // [2]
+  double *xi, *xa, *xb, *pa, *pb, *tmp, *Phi, *u;
+  double* part;  // [2][kRedBlocks]
+  double* en;    // [kEn]
+  double* en_host;
+};
+
+namespace {
+
+hipError_t circ1(const fph_hmc_s* c, int k, int nvec, const double* in, double* out, hipStream_t s) {
+  dim3 grid((c->N + 63) / 64, (c->Ltau + kRows - 1) / kRows, nvec);
+  hipLaunchKernelGGL((k_tau_circ<1, 1>), grid, dim3(64), 0, s, c->N, c->Ltau, c->d, c->ts, c->off,
+                     (const double*)(c->tab + (long)k * c->ts), (const double*)nullptr, in,
+                     (const double*)nullptr, out, (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t step_map(const fph_hmc_s* c, const double* x, const double* p, double* xo, double* po,
+                    hipStream_t s) {
+  dim3 grid((c->N + 63) / 64, (c->Ltau + kRows - 1) / kRows, 1);
+  hipLaunchKernelGGL((k_tau_circ<2, 2>), grid, dim3(64), 0, s, c->N, c->Ltau, c->d, c->ts, c->off,
+                     (const double*)c->tab, (const double*)c->cst, x, p, xo, po);
+  return hipGetLastError();
+}
+
+// en[i0] = S_B(x), en[i1] = -dtau alpha sum x
+hipError_t sb_into(const fph_hmc_s* c, const double* x, double* out0, double* out1, hipStream_t s) {
+  hipLaunchKernelGGL(k_sb_partials, dim3(kRedBlocks), dim3(256), 0, s, c->N, c->Ltau, x,
+                     c->o.omega0, c->lat.dtau, c->part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_cols, dim3(2), dim3(256), 0, s, (const double*)c->part, 0.5 * c->lat.dtau,
+                     -c->lat.dtau * c->lat.alpha, out0, out1);
+  return hipGetLastError();
+}
+
+// *out = scale * a . b over n values
+hipError_t dot_into(const fph_hmc_s* c, long n, const double* a, const double* b, double scale,
+                    double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_part, dim3(kRedBlocks), dim3(256), 0, s, n, a, b, c->part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(256), 0, s, (const double*)c->part, scale, 0.0, out,
+                     (double*)nullptr);
+  return hipGetLastError();
+}
+
+// *out = p^T Mass^{-1} p / 2 (uses c->tmp)
+hipError_t kinetic_into(const fph_hmc_s* c, const double* p, double* out, hipStream_t s) {
+  hipError_t e = circ1(c, TAB_MINV, 1, p, c->tmp, s);
+  if (e != hipSuccess) return e;
+  return dot_into(c, c->d, p, c->tmp, 0.5, out, s);
+}
+
+}  // namespace
+
+#define HMC_CHECK(call)                                         \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return fph::record_hip_error(e_);     \
+  } while (0)
+
+#define HMC_CALL(call)                 \
+  do {                                 \
+    int rc_ = (call);                  \
+    if (rc_ != FPH_OK) return rc_;     \
+  } while (0)
+
+extern "C" {
+
+int fph_hmc_destroy(fph_hmc_t c) {
+  if (c == nullptr) return FPH_E_NULL;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {c->tab, c->vals, c->cst, c->xi, c->xa, c->xb, c->pa, c->pb,
+                  c->tmp, c->Phi, c->u, c->part, c->en};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->en_host) (void)hipHostFree(c->en_host);
+  delete c;
+  return FPH_OK;
+}
+
+int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void* stream) {
+  if (out == nullptr || h == nullptr || o == nullptr) return FPH_E_NULL;
+  *out = nullptr;
+  fph_lattice_t lat;
+  int32_t max_rhs = 0;
+  HMC_CALL(fph_get_lattice(h, &lat, &max_rhs));
+  if (!(std::isfinite(o->omega0) && o->omega0 > 0.0) || !(std::isfinite(o->dt) && o->dt > 0.0) ||
+      std::isnan(o->m_reg) || o->Nt < 1 || o->nt < 1 || !std::isfinite(o->a1) ||
+      !std::isfinite(o->a2) || !opts_ok(o->force_solve) || !opts_ok(o->action_solve))
+    return FPH_E_ARG;
+  if (o->nfields < 1 || o->nfields > max_rhs) return FPH_E_NRHS;
+  fph_hmc_s* c = new fph_hmc_s();
+  std::memset(c, 0, sizeof(*c));
+  c->h = h;
+  c->lat = lat;
+  c->max_rhs = max_rhs;
+  c->N = lat.L * lat.L;
+  c->Ltau = lat.Ltau;
+  c->d = (long)c->N * lat.Ltau;
+  c->off = lat.Ltau + kRows;
+  c->ts = 2 * c->off;
+  c->o = *o;
+  if (!std::isfinite(c->o.m_reg)) c->o.m_reg = -1.0;
+  const long d = c->d;
+  const int nf = o->nfields;
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, n)                                        \
+  if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (size_t)(n) * sizeof(double));
+  ALLOC(c->tab, (long)kNTab * c->ts);
+  ALLOC(c->vals, (long)kNTab * c->Ltau);
+  ALLOC(c->cst, 2);
+  ALLOC(c->xi, d);
+  ALLOC(c->xa, d);
+  ALLOC(c->xb, d);
+  ALLOC(c->pa, d);
+  ALLOC(c->pb, d);
+  ALLOC(c->tmp, d);
+  ALLOC(c->Phi, nf * d);
+  ALLOC(c->u, nf * d);
+  ALLOC(c->part, 2 * kRedBlocks);
+  ALLOC(c->en, kEn);
+#undef ALLOC
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->en_host, kEn * sizeof(double), hipHostMallocDefault);
+  hipStream_t s = (hipStream_t)stream;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_hmc_modes, dim3((c->Ltau + 63) / 64), dim3(64), 0, s, c->Ltau, lat.dtau,
+                       c->o.omega0, c->o.m_reg, c->o.dt / c->o.nt, c->o.nt, lat.dtau * lat.alpha,
+                       c->vals, c->cst);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_hmc_tables, dim3((c->ts + 63) / 64, kNTab), dim3(64), 0, s, c->Ltau, c->ts,
+                       c->off, (const double*)c->vals, c->tab);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    fph_hmc_destroy(c);
+    return fph::record_hip_error(e);
+  }
+  *out = c;
+  return FPH_OK;
+}
+
+int bosonic_action(fph_hmc_t c, const double* x_dev, double* out_dev, void* stream) {
+  if (c == nullptr || x_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
+  HMC_CHECK(sb_into(c, x_dev, out_dev, out_dev + 1, (hipStream_t)stream));
+  return FPH_OK;
+}
+
+int bosonic_force(fph_hmc_t c, const double* x_dev, double* grad_dev, double scale, void* stream) {
+  if (c == nullptr || x_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
+  if (!std::isfinite(scale)) return FPH_E_ARG;
+  hipLaunchKernelGGL(k_sb_force, dim3(grid_for(c->d)), dim3(256), 0, (hipStream_t)stream, c->N,
+                     c->Ltau, x_dev, c->o.omega0, c->lat.dtau, c->lat.alpha, scale, grad_dev);
+  HMC_CHECK(hipGetLastError());
+  return FPH_OK;
+}
+
+int hmc_mass_apply(fph_hmc_t c, int32_t op, int32_t nvec, const double* in_dev, double* out_dev,
+                   void* stream) {
+  if (c == nullptr || in_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
+  if (op < FPH_MASS_INV || op > FPH_MASS) return FPH_E_PREC;
+  if (nvec < 1 || nvec > 65535) return FPH_E_ARG;
+  const long bytes = (long)nvec * c->d * 8;
+  const char *a = (const char*)in_dev, *b = (const char*)out_dev;
+  if (a < b + bytes && b < a + bytes) return FPH_E_ARG;
+  const int k = (op == FPH_MASS_INV) ? TAB_MINV : (op == FPH_MASS_SQRT) ? TAB_MSQRT : TAB_MASS;
+  HMC_CHECK(circ1(c, k, nvec, in_dev, out_dev, (hipStream_t)stream));
+  return FPH_OK;
+}
+
+int hmc_boson_steps(fph_hmc_t c, double* x_dev, double* p_dev, void* stream) {
+  if (c == nullptr || x_dev == nullptr || p_dev == nullptr) return FPH_E_NULL;
+  hipStream_t s = (hipStream_t)stream;
+  HMC_CHECK(step_map(c, x_dev, p_dev, c->xb, c->pb, s));
+  HMC_CHECK(hipMemcpyAsync(x_dev, c->xb, c->d * 8, hipMemcpyDeviceToDevice, s));
+  HMC_CHECK(hipMemcpyAsync(p_dev, c->pb, c->d * 8, hipMemcpyDeviceToDevice, s));
+  return FPH_OK;
+}
+
+int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const double* R_mom_dev,
+                   double r_uniform, double* p_out_dev, fph_hmc_stats_t* st, void* stream) {
+  if (c == nullptr || x_dev == nullptr || R_fields_dev == nullptr || R_mom_dev == nullptr)
+    return FPH_E_NULL;
+  if (!(r_uniform >= 0.0 && r_uniform <= 1.0)) return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const fph_hmc_opts_t& o = c->o;
+  const long d = c->d;
+  const int nf = o.nfields;
+  fph_hmc_stats_t S;
+  std::memset(&S, 0, sizeof(S));
+  fph_pcg_stats_t ps[64];
+  if (nf > 64) return FPH_E_NRHS;
+
+  auto solve = [&](const fph_pcg_opts_t& so, int zero_guess) -> int {
+    fph_pcg_opts_t oo = so;
+    oo.zero_guess = zero_guess;
+    int rc = pcg_solve(c->h, nf, c->Phi, c->u, &oo, ps, stream);
+    if (rc != FPH_OK) return rc;
+    S.solves++;
+    for (int r = 0; r < nf; ++r) {
+      S.status |= ps[r].status;
+      S.cg_iters += ps[r].iters;
+      S.matvecs += ps[r].matvecs;
+    }
+    return FPH_OK;
+  };
+
+  // Initial state: x_i, Phi_sigma = M(x_i)^T R_sigma, p = sqrt(Mass) R.
+  HMC_CHECK(hipMemcpyAsync(c->xi, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
+  HMC_CHECK(hipMemcpyAsync(c->xa, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
+  HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
+  HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->Phi, stream));
+  HMC_CHECK(circ1(c, TAB_MSQRT, 1, R_mom_dev, c->pa, s));
+  HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_I, c->en + EN_LIN_I, s));
+  HMC_CHECK(dot_into(c, (long)nf * d, R_fields_dev, R_fields_dev, 0.5, c->en + EN_R2, s));
+  HMC_CHECK(kinetic_into(c, c->pa, c->en + EN_K_I, s));
+
+  // Leapfrog with time-step splitting; the two half kicks between steps
+  // share one force evaluation (same x) and are applied as one kick of dt.
+  HMC_CHECK(hipMemsetAsync(c->u, 0, (size_t)nf * d * 8, s));
+  HMC_CALL(solve(o.force_solve, 1));
+  HMC_CALL(fermion_force(c->h, nf, c->u, c->pa, -0.25 * o.dt, stream));
+  for (int t = 0; t < o.Nt; ++t) {
+    HMC_CHECK(step_map(c, c->xa, c->pa, c->xb, c->pb, s));
+    std::swap(c->xa, c->xb);
+    std::swap(c->pa, c->pb);
+    HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
+    HMC_CALL(solve(o.force_solve, 0));
+    HMC_CALL(fermion_force(c->h, nf, c->u, c->pa, (t + 1 < o.Nt ? -0.5 : -0.25) * o.dt, stream));
+  }
+  const int force_status = S.status;
+
+  // Final energies; S_F(x_f) from a tight solve started at the last solution.
+  HMC_CALL(solve(o.action_solve, 0));
+  double sf_f = 0.0;
+  for (int r = 0; r < nf; ++r) sf_f += 0.5 * ps[r].action;
+  bool action_ok = true;
+  for (int r = 0; r < nf; ++r) action_ok = action_ok && (ps[r].status & FPH_ST_CONVERGED);
+  HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_F, c->en + EN_LIN_F, s));
+  HMC_CHECK(kinetic_into(c, c->pa, c->en + EN_K_F, s));
+  HMC_CHECK(hipMemcpyAsync(c->en_host, c->en, kEn * 8, hipMemcpyDeviceToHost, s));
+  HMC_CHECK(hipStreamSynchronize(s));
+  const double* en = c->en_host;
+  S.SB_i = en[EN_SB_I] + en[EN_LIN_I];
+  S.SB_f = en[EN_SB_F] + en[EN_LIN_F];
+  S.SF_i = en[EN_R2];
+  S.SF_f = sf_f;
+  S.K_i = en[EN_K_I];
+  S.K_f = en[EN_K_F];
+  S.H_i = S.SB_i + S.SF_i + S.K_i;
+  S.H_f = S.SB_f + S.SF_f + S.K_f;
+  const double dH = S.H_f - S.H_i;
+  const bool bad = !std::isfinite(dH) || ((S.status | force_status) & (FPH_ST_BREAKDOWN | FPH_ST_NONFINITE)) ||
+                   !action_ok;
+  S.accept_prob = bad ? 0.0 : (dH <= 0.0 ? 1.0 : std::exp(-dH));
+  S.accepted = (!bad && r_uniform < S.accept_prob) ? 1 : 0;
+
+  if (p_out_dev) HMC_CHECK(hipMemcpyAsync(p_out_dev, c->pa, d * 8, hipMemcpyDeviceToDevice, s));
+  if (S.accepted) {
+    HMC_CHECK(hipMemcpyAsync(x_dev, c->xa, d * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    HMC_CALL(fph_set_field(c->h, c->xi, o.a1, o.a2, stream));
+  }
+  HMC_CHECK(hipStreamSynchronize(s));
+  if (st) *st = S;
+  return FPH_OK;
+}
+
+}  // extern "C"

@@ -19,6 +19,7 @@
 #include "fph_blas.h"
 #include "fph_common.h"
 #include "fph_coop.h"
+#include "fph_internal.h"
 #include "fph_matvec.h"
 #include "fph_precond.h"
 
@@ -40,6 +41,8 @@ int fail_hip(hipError_t e) {
 }
 
 }  // namespace
+
+int fph::record_hip_error(hipError_t e) { return fail_hip(e); }
 
 struct fph_handle_s {
   fph_lattice_t lat;
@@ -310,6 +313,13 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
     return fail_hip(e);
   }
   *out = h;
+  return FPH_OK;
+}
+
+int fph_get_lattice(fph_handle_t h, fph_lattice_t* lat, int32_t* max_rhs) {
+  if (h == nullptr) return FPH_E_NULL;
+  if (lat) *lat = h->lat;
+  if (max_rhs) *max_rhs = h->max_rhs;
   return FPH_OK;
 }
 

@@ -1,0 +1,92 @@
+"""Python binding of the hybrid Monte Carlo update (Sec. III, Algorithm 1).
+
+Argument marshalling only: every step runs in the HIP library; tensors give
+device pointers and the current torch stream gives the hipStream_t.
+"""
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import FPH_MASS, FPH_MASS_INV, FPH_MASS_SQRT, HmcOpts, HmcStats, PcgOpts, check
+from .solver import _PRECS, _ptr, _stream
+
+_MASS_OPS = {"inv": FPH_MASS_INV, "sqrt": FPH_MASS_SQRT, "mass": FPH_MASS}
+
+
+def _pcg_opts(tol, precond=True, prec="f32_refined", maxiter=100000, ru_delta=0.0):
+    return PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], 1, float(ru_delta), 0, 0)
+
+
+class PhononHMC:
+    """HMC updates of the phonon field of one ``FermionSolver`` (which must
+    outlive this object).  m_reg=None disables Fourier acceleration."""
+
+    def __init__(self, solver, omega0, m_reg, dt, Nt=100, nt=10, nfields=2, a1=1.0, a2=1.0,
+                 force_tol=1e-5, action_tol=1e-10, precond=True, prec="f32_refined",
+                 maxiter=100000):
+        self.lib = _lib.load()
+        self.solver = solver
+        self.nfields = int(nfields)
+        mr = math.inf if m_reg is None else float(m_reg)
+        self.opts = HmcOpts(float(omega0), mr, float(dt), int(Nt), int(nt), self.nfields, float(a1),
+                            float(a2), _pcg_opts(force_tol, precond, prec, maxiter),
+                            _pcg_opts(action_tol, precond, prec, maxiter))
+        h = ctypes.c_void_p()
+        check(self.lib.fph_hmc_create(ctypes.byref(h), solver.h, ctypes.byref(self.opts), _stream()))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fph_hmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _v(self, t, n=1):
+        if t.numel() != n * self.solver.dim:
+            raise ValueError(f"expected {n} vector(s) of N*Ltau values")
+        self.solver._vec(t)
+        return t
+
+    def bosonic_action(self, x):
+        """Tensor [S_B(x), -dtau*alpha*sum x] (FP64, on the device)."""
+        out = torch.empty(2, dtype=torch.float64, device=x.device)
+        check(self.lib.bosonic_action(self.h, _ptr(self._v(x)), _ptr(out), _stream()))
+        return out
+
+    def bosonic_force(self, x, grad=None, scale=1.0):
+        """grad += scale * (dS_B/dx - dtau*alpha)."""
+        grad = torch.zeros_like(x) if grad is None else grad
+        check(self.lib.bosonic_force(self.h, _ptr(self._v(x)), _ptr(self._v(grad)), float(scale),
+                                     _stream()))
+        return grad
+
+    def mass_apply(self, v, op="inv"):
+        """Mass^{-1} v, sqrt(Mass) v or Mass v for one or more vectors [..., Ltau, N]."""
+        n = self.solver._vec(v)
+        out = torch.empty_like(v)
+        check(self.lib.hmc_mass_apply(self.h, _MASS_OPS[op], n, _ptr(v), _ptr(out), _stream()))
+        return out
+
+    def boson_steps(self, x, p):
+        """The nt bosonic sub-steps of one time step, in place on x and p."""
+        check(self.lib.hmc_boson_steps(self.h, _ptr(self._v(x)), _ptr(self._v(p)), _stream()))
+        return x, p
+
+    def trajectory(self, x, R_fields, R_mom, r_uniform, p_out=None):
+        """One HMC trial update of x (in place if accepted).  Returns the stats dict."""
+        self._v(x)
+        self._v(R_fields, self.nfields)
+        self._v(R_mom)
+        st = HmcStats()
+        pp = _ptr(p_out) if p_out is not None else None
+        check(self.lib.hmc_trajectory(self.h, _ptr(x), _ptr(R_fields), _ptr(R_mom), float(r_uniform),
+                                      pp, ctypes.byref(st), _stream()))
+        return st.as_dict()

@@ -60,3 +60,36 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_2203_01291_amd import _lib
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C sizes and offsets
+    (checked with a host program compiled by gcc against include/holstein_hmc.h)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2203_01291_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = {"fph_lattice_t": _lib.Lattice, "fph_pcg_opts_t": _lib.PcgOpts,
+               "fph_pcg_stats_t": _lib.PcgStats, "fph_system_t": _lib.System,
+               "fph_hmc_opts_t": _lib.HmcOpts, "fph_hmc_stats_t": _lib.HmcStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "holstein_hmc.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
