@@ -15,7 +15,8 @@ Prints one JSON line: the headline (FP32-refined solves/s), the same step
 with FP64 CG, one step of every solver variant, the fused M^T M roofline
 (HIP events on the stream the kernel runs on) on a working set above the
 Infinity Cache and at the workload shape, the batched persistent solve,
-and the CPU oracle timed on a bounded sample.
+one full HMC update with the paper's settings, and the CPU oracle timed on
+a bounded sample.
 """
 
 import argparse
@@ -54,6 +55,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the one-step timing of every solver variant")
+    ap.add_argument("--no-hmc", action="store_true", help="skip the HMC trajectory leg")
+    ap.add_argument("--hmc-only", action="store_true",
+                    help="only the HMC trajectory leg (one warm-up and one timed trajectory)")
     ap.add_argument("--profile-roofline", action="store_true",
                     help="only the roofline kernel (M^T M, FP32, L=64 Ltau=400 x 32 rhs) and a "
                          "plain copy of the same byte count, for hardware-counter runs")
@@ -178,6 +182,65 @@ def bench_batched(torch, dev, log):
     return res
 
 
+def bench_hmc(torch, dev, p, a1, a2, log):
+    """One HMC trial update (Algorithm 1) on the workload's lattice with the
+    paper's settings: dt = 1/(100 omega0), Nt = 100 steps of nt = 10 bosonic
+    sub-steps, Fourier acceleration with m_reg = omega0, two pseudofermion
+    fields, FP32-refined preconditioned solves to 1e-5 for the forces (each
+    from a zero guess) and to 1e-10 for the final action, FP64 energies.
+    Starts from the workload's synthetic field; one warm-up trajectory, then
+    one timed."""
+    from paper_2203_01291_amd.hmc import PhononHMC
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import hmc_draws, hmc_params, phonon_field
+
+    hp = hmc_params(p)
+    s = FermionSolver.from_params(p, max_rhs=hp.nfields)
+    x0 = torch.from_numpy(phonon_field(p)).to(dev)
+    Rf, Rm, r = hmc_draws(p, hp.nfields)
+    Rf = torch.from_numpy(Rf).to(dev)
+    Rm = torch.from_numpy(Rm).to(dev)
+    h = PhononHMC(s, hp.omega0, hp.m_reg, hp.dt, Nt=hp.Nt, nt=hp.nt, nfields=hp.nfields, a1=a1, a2=a2,
+                  force_tol=hp.tol_force, action_tol=hp.tol_action)
+    x = x0.clone()
+    h.trajectory(x, Rf, Rm, r)
+    x = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = h.trajectory(x, Rf, Rm, r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the bosonic sub-steps of one time step (composed map, two circulant
+    # passes over x and p, plus two device copies back in place)
+    xb, pb = x0.clone(), torch.randn_like(x0)
+    for _ in range(3):
+        h.boson_steps(xb, pb)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(50):
+        h.boson_steps(xb, pb)
+    e1.record(stream)
+    e1.synchronize()
+    boson_us = e0.elapsed_time(e1) / 50 * 1e3
+    res = {
+        "workload": f"{p.name}: one HMC update, dt={hp.dt:g}, Nt={hp.Nt}, nt={hp.nt}, "
+                    f"m_reg={hp.m_reg}, {hp.nfields} fields, FP32-refined PCG (a1={a1}, a2={a2}) "
+                    f"to {hp.tol_force:g} (forces, zero guess) and {hp.tol_action:g} (action)",
+        "ms_per_trajectory": dt * 1e3, "trajectories_per_s": 1.0 / dt,
+        "solves": st["solves"], "cg_iters": st["cg_iters"],
+        "cg_iters_per_force_solve_and_field": st["cg_iters"] / st["solves"] / hp.nfields,
+        "dH": st["H_f"] - st["H_i"], "accept_prob": st["accept_prob"], "accepted": st["accepted"],
+        "status": st["status"], "boson_step_us": boson_us,
+        "boson_fraction": boson_us * 1e-6 * hp.Nt / dt,
+    }
+    log(f"hmc: {res}")
+    h.close()
+    s.close()
+    return res
+
+
 def cpu_baseline(p, golden_iters):
     """Oracle CG (scipy CSR, FP64) on the workload for a bounded number of
     iterations; scaled to solves/s with the oracle's own iteration count."""
@@ -220,9 +283,9 @@ def cpu_baseline(p, golden_iters):
 # WRITE_SIZE runs of `bench.py --profile-roofline`, each scaled by the same
 # counter read for a copy kernel of known size.  Valid only while the
 # kernel sources hash to `source_sha1`; otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 443115293, "read_bytes": 233398659, "write_bytes": 209716634,
+TRAFFIC = {"bytes_per_launch": 443108645, "read_bytes": 233392933, "write_bytes": 209715712,
            "fetch_scale": 1.99977, "write_scale": 1.00000,
-           "source_sha1": "8023349795dbcf8fce54ca79561b1de8493774ed",
+           "source_sha1": "2e176da867b18d83f76aa3fd91a606c492d78524",
            "profile": "profiles/mtm_f32_L64_Ltau400_r32_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
@@ -280,6 +343,11 @@ def main():
 
     if args.profile_roofline:
         profile_roofline(torch, torch.device("cuda:0"))
+        return
+    if args.hmc_only:
+        from workloads import get_config as _gc
+        print(json.dumps(bench_hmc(torch, torch.device("cuda:0"), _gc(args.workload), args.a1, args.a2,
+                                   log)), flush=True)
         return
 
     from paper_2203_01291_amd.solver import FermionSolver
@@ -415,6 +483,10 @@ def main():
     if not args.no_batch:
         batch = bench_batched(torch, dev, log)
 
+    hmc = None
+    if not args.no_hmc and R == 1:
+        hmc = bench_hmc(torch, dev, p, args.a1, args.a2, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_iterations.json")))
@@ -477,6 +549,7 @@ def main():
         "batched": batch,
         "variants": variants,
         "two_fields": two_fields,
+        "hmc_trajectory": hmc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

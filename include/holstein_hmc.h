@@ -9,7 +9,8 @@
  * conjugate gradients, optionally preconditioned by the adiabatic
  * preconditioner of Sec. V (Eqs. P_def, CG_precon, P_change_basis, App. C),
  * evaluates the action S_F = Phi . u (Eq. Sf_Psi) and the phonon force
- * dS_F/dx of Eq. (dSF_dx).
+ * dS_F/dx of Eq. (dSF_dx), and runs the hybrid Monte Carlo update of the
+ * phonon field built on them (Sec. III, Algorithm 1; fph_hmc_* below).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -279,6 +280,16 @@ typedef struct {
   int32_t nt;                  /* bosonic sub-steps per step (>= 1; paper: 10)  */
   int32_t nfields;             /* pseudofermion fields, 1..max_rhs (paper: 2)   */
   double a1, a2;               /* Chebyshev-order constants for fph_set_field   */
+  int32_t guess;               /* initial guess of each force solve: 0 zero;
+                                  1 the previous solution; 2 the linear
+                                  extrapolation 2 u_t - u_{t-1} of the last two
+                                  (the first solve of a trajectory starts from
+                                  zero).  1 and 2 save CG iterations, but the
+                                  force error they leave depends on the history
+                                  and adds up along the trajectory: at loose
+                                  force tolerances they bias H_f - H_i and the
+                                  update is reversible only to the tolerance  */
+  int32_t pad;
   fph_pcg_opts_t force_solve;  /* solves for the force (paper: tol 1e-5)        */
   fph_pcg_opts_t action_solve; /* solve for S_F at the end (paper: tol 1e-10)   */
 } fph_hmc_opts_t;

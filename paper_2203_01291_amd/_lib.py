@@ -47,6 +47,7 @@ class HmcOpts(ctypes.Structure):
     _fields_ = [("omega0", ctypes.c_double), ("m_reg", ctypes.c_double), ("dt", ctypes.c_double),
                 ("Nt", ctypes.c_int32), ("nt", ctypes.c_int32), ("nfields", ctypes.c_int32),
                 ("a1", ctypes.c_double), ("a2", ctypes.c_double),
+                ("guess", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("force_solve", PcgOpts), ("action_solve", PcgOpts)]
 
 

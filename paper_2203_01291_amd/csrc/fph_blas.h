@@ -47,17 +47,25 @@ __global__ void k_set_field(long n, const double* __restrict__ x, double dtau,
   }
 }
 
-// dbar_i = (1/Ltau) sum_tau E[tau][i] (Eq. expnVbar), summed in tau order,
-// from the stored c4 E.
-__global__ void k_dbar(int N, int Ltau, const double* __restrict__ E64, double c4,
-                       double* __restrict__ dbar64, float* __restrict__ dbar32) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// dbar_i = (1/Ltau) sum_tau E[tau][i] (Eq. expnVbar) from the stored c4 E.
+// Block (64, 16): 64 sites, 16 interleaved groups of time slices, whose sums
+// are added in group order.  Launch: grid ceil(N/64).
+__global__ void __launch_bounds__(1024)
+k_dbar(int N, int Ltau, const double* __restrict__ E64, double c4, double* __restrict__ dbar64,
+       float* __restrict__ dbar32) {
+  __shared__ double part[16][64];
+  const int i = blockIdx.x * 64 + threadIdx.x;
   double s = 0.0;
-  for (int tau = 0; tau < Ltau; ++tau) s += E64[(long)tau * N + i];
-  s /= (double)Ltau * c4;
-  dbar64[i] = s;
-  dbar32[i] = (float)s;
+  if (i < N)
+    for (int tau = threadIdx.y; tau < Ltau; tau += 16) s += E64[(long)tau * N + i];
+  part[threadIdx.y][threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.y != 0 || i >= N) return;
+  double t = 0.0;
+  for (int g = 0; g < 16; ++g) t += part[g][threadIdx.x];
+  t /= (double)Ltau * c4;
+  dbar64[i] = t;
+  dbar32[i] = (float)t;
 }
 
 // ------------------------------------------------------- state kernels --

@@ -247,6 +247,17 @@ k_sb_force(int N, int Ltau, const double* __restrict__ x, double omega0, double 
   }
 }
 
+// g = 2 u - u_old; u_old = u; u = g  (linear extrapolation of the solution).
+__global__ void __launch_bounds__(256)
+k_extrapolate(long n, double* __restrict__ u, double* __restrict__ uold) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256) {
+    const double a = u[k];
+    const double g = 2.0 * a - uold[k];
+    uold[k] = a;
+    u[k] = g;
+  }
+}
+
 int grid_for(long n) {
   const long b = (n + 255) / 256;
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
@@ -269,7 +280,7 @@ struct fph_hmc_s {
   double* tab;   // [kNTab][ts]
   double* vals;  // [kNTab][Ltau]
   double* cst;   // [2]
-  double *xi, *xa, *xb, *pa, *pb, *tmp, *Phi, *u;
+  double *xi, *xa, *xb, *pa, *pb, *tmp, *Phi, *u, *uold;
   double* part;  // [2][kRedBlocks]
   double* en;    // [kEn]
   double* en_host;
@@ -342,7 +353,7 @@ int fph_hmc_destroy(fph_hmc_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->tab, c->vals, c->cst, c->xi, c->xa, c->xb, c->pa, c->pb,
-                  c->tmp, c->Phi, c->u, c->part, c->en};
+                  c->tmp, c->Phi, c->u, c->uold, c->part, c->en};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->en_host) (void)hipHostFree(c->en_host);
@@ -358,7 +369,8 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   HMC_CALL(fph_get_lattice(h, &lat, &max_rhs));
   if (!(std::isfinite(o->omega0) && o->omega0 > 0.0) || !(std::isfinite(o->dt) && o->dt > 0.0) ||
       std::isnan(o->m_reg) || o->Nt < 1 || o->nt < 1 || !std::isfinite(o->a1) ||
-      !std::isfinite(o->a2) || !opts_ok(o->force_solve) || !opts_ok(o->action_solve))
+      !std::isfinite(o->a2) || o->guess < 0 || o->guess > 2 || !opts_ok(o->force_solve) ||
+      !opts_ok(o->action_solve))
     return FPH_E_ARG;
   if (o->nfields < 1 || o->nfields > max_rhs) return FPH_E_NRHS;
   fph_hmc_s* c = new fph_hmc_s();
@@ -389,6 +401,7 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   ALLOC(c->tmp, d);
   ALLOC(c->Phi, nf * d);
   ALLOC(c->u, nf * d);
+  if (o->guess == 2) ALLOC(c->uold, nf * d);
   ALLOC(c->part, 2 * kRedBlocks);
   ALLOC(c->en, kEn);
 #undef ALLOC
@@ -498,7 +511,16 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
     std::swap(c->xa, c->xb);
     std::swap(c->pa, c->pb);
     HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
-    HMC_CALL(solve(o.force_solve, 0));
+    if (o.guess == 2) {
+      if (t == 0) {
+        HMC_CHECK(hipMemcpyAsync(c->uold, c->u, (size_t)nf * d * 8, hipMemcpyDeviceToDevice, s));
+      } else {
+        hipLaunchKernelGGL(k_extrapolate, dim3(grid_for((long)nf * d)), dim3(256), 0, s,
+                           (long)nf * d, c->u, c->uold);
+        HMC_CHECK(hipGetLastError());
+      }
+    }
+    HMC_CALL(solve(o.force_solve, o.guess == 0 ? 1 : 0));
     HMC_CALL(fermion_force(c->h, nf, c->u, c->pa, (t + 1 < o.Nt ? -0.5 : -0.25) * o.dt, stream));
   }
   const int force_status = S.status;

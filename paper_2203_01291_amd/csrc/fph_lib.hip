@@ -349,7 +349,7 @@ int fph_set_field(fph_handle_t h, const double* x_dev, double a1, double a2, voi
   hipLaunchKernelGGL(k_set_field, dim3(elem_blocks(d)), dim3(256), 0, s, d, x_dev,
                      h->lat.dtau, h->lat.alpha, h->lat.mu, h->c4, h->E64, h->E32);
   FPH_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_dbar, dim3((h->g.N + 255) / 256), dim3(256), 0, s, h->g.N, h->g.Ltau,
+  hipLaunchKernelGGL(k_dbar, dim3((h->g.N + 63) / 64), dim3(64, 16), 0, s, h->g.N, h->g.Ltau,
                      h->E64, h->c4, h->dbar64, h->dbar32);
   FPH_CHECK(hipGetLastError());
   FPH_CHECK(pc_set_field(&h->pc, h->g, h->dbar64, h->lat.dtau, h->lat.t, h->a1, h->a2, s));

@@ -14,6 +14,7 @@ from ._lib import FPH_MASS, FPH_MASS_INV, FPH_MASS_SQRT, HmcOpts, HmcStats, PcgO
 from .solver import _PRECS, _ptr, _stream
 
 _MASS_OPS = {"inv": FPH_MASS_INV, "sqrt": FPH_MASS_SQRT, "mass": FPH_MASS}
+_GUESS = {"zero": 0, "previous": 1, "extrapolate": 2}
 
 
 def _pcg_opts(tol, precond=True, prec="f32_refined", maxiter=100000, ru_delta=0.0):
@@ -26,13 +27,13 @@ class PhononHMC:
 
     def __init__(self, solver, omega0, m_reg, dt, Nt=100, nt=10, nfields=2, a1=1.0, a2=1.0,
                  force_tol=1e-5, action_tol=1e-10, precond=True, prec="f32_refined",
-                 maxiter=100000):
+                 maxiter=100000, guess="zero"):
         self.lib = _lib.load()
         self.solver = solver
         self.nfields = int(nfields)
         mr = math.inf if m_reg is None else float(m_reg)
         self.opts = HmcOpts(float(omega0), mr, float(dt), int(Nt), int(nt), self.nfields, float(a1),
-                            float(a2), _pcg_opts(force_tol, precond, prec, maxiter),
+                            float(a2), _GUESS[guess], 0, _pcg_opts(force_tol, precond, prec, maxiter),
                             _pcg_opts(action_tol, precond, prec, maxiter))
         h = ctypes.c_void_p()
         check(self.lib.fph_hmc_create(ctypes.byref(h), solver.h, ctypes.byref(self.opts), _stream()))

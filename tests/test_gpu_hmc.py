@@ -108,10 +108,10 @@ def test_boson_steps(shape, mreg):
     assert relmax(pg.cpu().numpy(), pr) < 1e-12
 
 
-def _oracle_and_gpu(lat, w0, m_reg, dt, Nt, nt, x, R_fields, R_mom, r, nfields=2):
+def _oracle_and_gpu(lat, w0, m_reg, dt, Nt, nt, x, R_fields, R_mom, r, nfields=2, guess="zero"):
     ref = OH.hmc_update(lat, w0, m_reg, dt, Nt, nt, x, R_fields, R_mom, r)
     s, h = make(lat, w0, m_reg, dt, Nt=Nt, nt=nt, nfields=nfields, force_tol=1e-13,
-                action_tol=1e-13, precond=False, prec="f64", maxiter=20000)
+                action_tol=1e-13, precond=False, prec="f64", maxiter=20000, guess=guess)
     xg = tgpu(x)
     pg = torch.empty_like(xg)
     st = h.trajectory(xg, tgpu(R_fields), tgpu(R_mom), r, p_out=pg)
@@ -119,17 +119,20 @@ def _oracle_and_gpu(lat, w0, m_reg, dt, Nt, nt, x, R_fields, R_mom, r, nfields=2
 
 
 TRAJ = [
-    # (L, Ltau, dtau, t, mu, alpha, omega0, m_reg, Nt, nt, nfields)
-    ("c1_paper", (4, 40, 0.1, 1.0, 0.0, 1.0, 1.0), "w0", 100, 10, 2),
-    ("L6_T42_inf", (6, 42, 0.1, 1.0, 0.2, 1.3, 0.7), None, 20, 4, 2),
-    ("L4_T10_one_field", (4, 10, 0.1, 1.0, -0.1, 1.2, 1.5), "w0", 7, 1, 1),
-    ("L8_T12_single_step", (8, 12, 0.1, 1.0, 0.0, 1.0, 1.0), 0.0, 1, 3, 2),
+    # name, (L, Ltau, dtau, t, mu, alpha, omega0), m_reg, Nt, nt, nfields, initial guesses
+    ("c1_paper", (4, 40, 0.1, 1.0, 0.0, 1.0, 1.0), "w0", 100, 10, 2, "zero"),
+    ("L6_T42_inf", (6, 42, 0.1, 1.0, 0.2, 1.3, 0.7), None, 20, 4, 2, "previous"),
+    ("L4_T10_one_field", (4, 10, 0.1, 1.0, -0.1, 1.2, 1.5), "w0", 7, 1, 1, "extrapolate"),
+    ("L8_T12_single_step", (8, 12, 0.1, 1.0, 0.0, 1.0, 1.0), 0.0, 1, 3, 2, "extrapolate"),
+    ("c1_extrapolate", (4, 40, 0.1, 1.0, 0.0, 1.0, 1.0), "w0", 30, 10, 2, "extrapolate"),
 ]
 
 
 @pytest.mark.parametrize("case", TRAJ, ids=[c[0] for c in TRAJ])
 def test_trajectory_parity(case):
-    name, shape, mreg, Nt, nt, nf = case
+    """Whole trajectories with tight FP64 solves agree with the oracle's LU trajectory,
+    whatever the initial guesses of the force solves."""
+    name, shape, mreg, Nt, nt, nf, guess = case
     lat, w0 = _lat(shape)
     m_reg = w0 if mreg == "w0" else mreg
     rng = np.random.default_rng(sum(map(ord, name)))
@@ -137,7 +140,7 @@ def test_trajectory_parity(case):
     R_fields = rng.standard_normal((nf, lat.Ltau, lat.N))
     R_mom = rng.standard_normal((lat.Ltau, lat.N))
     dt = 1.0 / (100 * w0)
-    ref, st, xo, pf, _ = _oracle_and_gpu(lat, w0, m_reg, dt, Nt, nt, x, R_fields, R_mom, 0.0, nf)
+    ref, st, xo, pf, _ = _oracle_and_gpu(lat, w0, m_reg, dt, Nt, nt, x, R_fields, R_mom, 0.0, nf, guess)
     assert st["status"] == 1, st
     assert relmax(pf, ref["p_f"]) < 1e-8
     for key, gk in (("H", None), ("S_B", "SB"), ("S_F", "SF"), ("K", "K")):
