@@ -24,9 +24,12 @@ definition in the paper (arXiv:2203.01291):
 * ``hmc``      - the hybrid Monte Carlo update with A = M: bosonic action
                  and force, Fourier-acceleration mass, time-step splitting
                  leapfrog and the Metropolis test (Sec. III, Algorithm 1).
+* ``lam``      - the Lambda reformulation A = M Lambda of the action, its
+                 force, and the reflection and swap updates (Secs. II C, IV;
+                 App. B).
 
 Parity status of each function is stated in its docstring; a function with
 no independent pin says "parity unpinned".
 """
 
-from . import lattice, solve, force, precond, hmc  # noqa: F401
+from . import lattice, solve, force, precond, hmc, lam  # noqa: F401

@@ -142,21 +142,30 @@ def fermion_force(lat, x, Phis, C=None, solve=solve_lu):
 
 # ----------------------------------------------------------- Hamiltonian dynamics
 
-def hamiltonian(lat, omega0, mt, x, p, Phis, C=None, solve=solve_lu):
-    """H(x, p) = S'(x) + p^T M^{-1} p / 2 and its parts."""
-    sb = x_action(lat, x, omega0)
-    sf = fermion_action(lat, x, Phis, C, solve)
+def hamiltonian(lat, omega0, mt, x, p, Phis, C=None, solve=solve_lu, lam=False):
+    """H(x, p) = S(x) + p^T M^{-1} p / 2 and its parts; S is S' (A = M) or,
+    with ``lam``, the action with A = M Lambda (Eq. S_again)."""
+    if lam:
+        from . import lam as lam_mod
+        sb = bosonic_action(lat, x, omega0)
+        sf = lam_mod.fermion_action(lat, x, Phis, C, solve)
+    else:
+        sb = x_action(lat, x, omega0)
+        sf = fermion_action(lat, x, Phis, C, solve)
     k = kinetic_energy(p, mt)
     return {"H": sb + sf + k, "S_B": sb, "S_F": sf, "K": k}
 
 
-def leapfrog_split(lat, omega0, mt, x, p, dt, Nt, nt, f_force):
+def leapfrog_split(lat, omega0, mt, x, p, dt, Nt, nt, f_force, b_force=None):
     """Time-step splitting leapfrog of Algorithm 1 (Eqs. leapfrog1-3).
 
     f_force(x) returns the fermion force dS_F/dx at x; the bosonic sub-steps
-    use ``x_force``.  Returns (x, p) after Nt steps of length dt, each holding
-    nt bosonic sub-steps of length dt/nt.  Inputs are not modified.
+    use b_force (default ``x_force``: S_B and the linear term of S').
+    Returns (x, p) after Nt steps of length dt, each holding nt bosonic
+    sub-steps of length dt/nt.  Inputs are not modified.
     """
+    if b_force is None:
+        b_force = lambda v: x_force(lat, v, omega0)
     x = np.array(x, dtype=np.float64)
     p = np.array(p, dtype=np.float64)
     h = dt / nt
@@ -165,17 +174,18 @@ def leapfrog_split(lat, omega0, mt, x, p, dt, Nt, nt, f_force):
     for _ in range(Nt):
         p = p - 0.5 * dt * fF
         for _ in range(nt):
-            p = p - 0.5 * h * x_force(lat, x, omega0)
+            p = p - 0.5 * h * b_force(x)
             x = x + h * tau_fourier_apply(p, minv)
-            p = p - 0.5 * h * x_force(lat, x, omega0)
+            p = p - 0.5 * h * b_force(x)
         fF = f_force(x)
         p = p - 0.5 * dt * fF
     return x, p
 
 
 def hmc_update(lat, omega0, m_reg, dt, Nt, nt, x_i, R_fields, R_mom, r_uniform,
-               C=None, solve=solve_lu):
-    """One HMC trial update (Algorithm 1) with the action S'.
+               C=None, solve=solve_lu, lam=False):
+    """One HMC trial update (Algorithm 1) with the action S' (A = M) or, with
+    ``lam``, the action S of Eq. (S_again) (A = M Lambda, bosonic part S_B).
 
     x_i: [Ltau, N]; R_fields: [nfields, Ltau, N] Gaussian draws for the
     pseudofermions; R_mom: [Ltau, N] Gaussian draws for the momentum;
@@ -185,13 +195,20 @@ def hmc_update(lat, omega0, m_reg, dt, Nt, nt, x_i, R_fields, R_mom, r_uniform,
     """
     C = lat_mod.checkerboard_C(lat) if C is None else C
     x_i = np.asarray(x_i, dtype=np.float64)
-    Phis = pseudofermions(lat, x_i, R_fields, C)
     mt = mass_tilde(lat.Ltau, lat.dtau, omega0, m_reg)
     p_i = sample_momentum(R_mom, mt)
-    Hi = hamiltonian(lat, omega0, mt, x_i, p_i, Phis, C, solve)
-    x_f, p_f = leapfrog_split(lat, omega0, mt, x_i, p_i, dt, Nt, nt,
-                              lambda x: fermion_force(lat, x, Phis, C, solve))
-    Hf = hamiltonian(lat, omega0, mt, x_f, p_f, Phis, C, solve)
+    if lam:
+        from . import lam as lam_mod
+        Phis = lam_mod.pseudofermions(lat, x_i, R_fields, C)
+        f_force = lambda x: lam_mod.fermion_force(lat, x, Phis, C, solve)
+        b_force = lambda x: bosonic_force(lat, x, omega0)
+    else:
+        Phis = pseudofermions(lat, x_i, R_fields, C)
+        f_force = lambda x: fermion_force(lat, x, Phis, C, solve)
+        b_force = None
+    Hi = hamiltonian(lat, omega0, mt, x_i, p_i, Phis, C, solve, lam)
+    x_f, p_f = leapfrog_split(lat, omega0, mt, x_i, p_i, dt, Nt, nt, f_force, b_force)
+    Hf = hamiltonian(lat, omega0, mt, x_f, p_f, Phis, C, solve, lam)
     dH = Hf["H"] - Hi["H"]
     prob = min(1.0, float(np.exp(-dH)))
     accepted = bool(r_uniform < prob)
