@@ -255,9 +255,18 @@ int fph_batch_destroy(fph_batch_t bh);
 /* ------------------------------------------------------------------ */
 /* Hybrid Monte Carlo update of the phonon field (Sec. III).           */
 /*
- * Action sampled (A = M, Lambda = I; Eqs. S_prime, Z_path_orig, S_F):
- *   S'(x) = S_B(x) - dtau*alpha*sum_{i,tau} x_{i,tau}
- *           + 1/2 sum_sigma Phi_sigma . (M^T M)^{-1} Phi_sigma,
+ * Two actions (opts.lambda_action):
+ *   0: A = M (Eqs. S_prime, Z_path_orig, S_F),
+ *      S'(x) = S_B(x) - dtau*alpha*sum_{i,tau} x_{i,tau}
+ *              + 1/2 sum_sigma Phi_sigma . (M^T M)^{-1} Phi_sigma;
+ *   1: A = M Lambda (Eqs. Z_path, Lambda_def, S_again),
+ *      S(x)  = S_B(x) + 1/2 sum_sigma b_sigma . (M^T M)^{-1} b_sigma,
+ *      b_sigma = Lambda(x)^{-T} Phi_sigma, where Lambda couples slice tau
+ *      to tau+1 of each site:
+ *        Lambda[(i,tau),(i,tau+1)] = s(tau+1) exp(dtau alpha x_{i,tau+1}/2),
+ *        s(t) = +1 for t = 0, -1 otherwise (slices mod Ltau);
+ * in both, Phi_sigma = A(x)^T R_sigma at the start of an update
+ * (Eq. PhiSample-1) and
  *   S_B   = dtau/2 sum_{i,tau} [omega0^2 x^2 + ((x_{tau+1} - x_tau)/dtau)^2]
  *           with x_{i,Ltau} = x_{i,0}                          (Eq. S_B).
  * Kinetic energy p^T Mass^{-1} p / 2 with the Fourier-acceleration mass
@@ -289,14 +298,14 @@ typedef struct {
                                   and adds up along the trajectory: at loose
                                   force tolerances they bias H_f - H_i and the
                                   update is reversible only to the tolerance  */
-  int32_t pad;
+  int32_t lambda_action;       /* 0: the action S' (A = M); 1: S (A = M Lambda) */
   fph_pcg_opts_t force_solve;  /* solves for the force (paper: tol 1e-5)        */
   fph_pcg_opts_t action_solve; /* solve for S_F at the end (paper: tol 1e-10)   */
 } fph_hmc_opts_t;
 
 typedef struct {
   double H_i, H_f;      /* H = S' + K before and after the trajectory (FP64)    */
-  double SB_i, SB_f;    /* S_B - dtau*alpha*sum x                              */
+  double SB_i, SB_f;    /* x-only action: S_B - dtau*alpha*sum x (S') or S_B (S) */
   double SF_i, SF_f;    /* 1/2 sum_sigma Phi.u; SF_i = 1/2 sum |R_sigma|^2      */
   double K_i, K_f;      /* p^T Mass^{-1} p / 2                                  */
   double accept_prob;   /* min(1, exp(-(H_f - H_i)))                            */
@@ -322,8 +331,9 @@ int fph_hmc_destroy(fph_hmc_t hh);
  * term of Eq. Z_path_orig), both FP64 device scalars.  Enqueue only. */
 int bosonic_action(fph_hmc_t hh, const double* x_dev, double* out_dev, void* stream);
 
-/* grad_dev += scale * (dS_B/dx - dtau*alpha), dS_B/dx of Eq. (dSB_dx),
- * periodic in tau.  Enqueue only. */
+/* grad_dev += scale * dS_x/dx for the x-only part of the context's action:
+ * dS_B/dx - dtau*alpha for S' (lambda_action 0), dS_B/dx for S, with dS_B/dx
+ * of Eq. (dSB_dx), periodic in tau.  Enqueue only. */
 int bosonic_force(fph_hmc_t hh, const double* x_dev, double* grad_dev, double scale,
                   void* stream);
 
@@ -346,7 +356,7 @@ int hmc_mass_apply(fph_hmc_t hh, int32_t op, int32_t nvec, const double* in_dev,
 int hmc_boson_steps(fph_hmc_t hh, double* x_dev, double* p_dev, void* stream);
 
 /* One HMC trial update (Algorithm 1) of the field x_dev [Ltau][N]:
- *   Phi_sigma = M(x_i)^T R_sigma (R_fields_dev [nfields][Ltau][N]);
+ *   Phi_sigma = A(x_i)^T R_sigma (R_fields_dev [nfields][Ltau][N]);
  *   p = sqrt(Mass) R (R_mom_dev [Ltau][N]);
  *   Nt steps of: p -= dt/2 dS_F/dx; nt bosonic sub-steps; p -= dt/2 dS_F/dx,
  *   the fermion force from pcg_solve with opts.force_solve (each solve
@@ -361,6 +371,54 @@ int hmc_boson_steps(fph_hmc_t hh, double* x_dev, double* p_dev, void* stream);
 int hmc_trajectory(fph_hmc_t hh, double* x_dev, const double* R_fields_dev,
                    const double* R_mom_dev, double r_uniform, double* p_out_dev,
                    fph_hmc_stats_t* stats_host, void* stream);
+
+typedef enum {
+  FPH_LAMBDA = 0,        /* Lambda      (Eq. Lambda_def)  */
+  FPH_LAMBDA_INV = 1,    /* Lambda^{-1} (Eq. Lambda_inv)  */
+  FPH_LAMBDA_T = 2,      /* Lambda^T                      */
+  FPH_LAMBDA_INV_T = 3   /* Lambda^{-T}                   */
+} fph_lambda_op_t;
+
+/* out = op(in) for nvec vectors [Ltau][N], Lambda of the field x_dev (any
+ * context; only the lattice's dtau and alpha are used).  Each is one shift
+ * in tau per site with a sign and an exponential factor.  in and out must not
+ * overlap.  Enqueue only. */
+int lambda_apply(fph_hmc_t hh, int32_t op, const double* x_dev, int32_t nvec, const double* in_dev,
+                 double* out_dev, void* stream);
+
+/* grad_dev[tau][i] += scale * (-dtau alpha) * sum_r b_r[tau-1][i] u_r[tau-1][i]
+ * (slice tau-1 mod Ltau): with A = M Lambda, the one-field force d(b.u)/dx is
+ * fermion_force(u) (with b as the right-hand side) plus this term, where
+ * b = Lambda^{-T} Phi and u = (M^T M)^{-1} b.  Enqueue only. */
+int lambda_force(fph_hmc_t hh, int32_t nrhs, const double* b_dev, const double* u_dev,
+                 double* grad_dev, double scale, void* stream);
+
+typedef enum { FPH_MOVE_REFLECT = 0, FPH_MOVE_SWAP = 1 } fph_move_t;
+
+typedef struct {
+  double dS;            /* S(x') - S(x)                                        */
+  double dS_B;          /* change of the x-only action                         */
+  double SF_old;        /* 1/2 sum |R_sigma|^2 = S_F(x)                        */
+  double SF_new;        /* S_F(x') from a solve with opts.action_solve          */
+  double accept_prob;   /* min(1, exp(-dS))                                    */
+  int32_t accepted;     /* 1 if x_dev now holds x'                              */
+  int32_t status;       /* OR of the FPH_ST_* bits of the solve                */
+  int32_t cg_iters;     /* CG iterations over the fields                        */
+  int32_t pad;
+} fph_update_stats_t;
+
+/* One Metropolis update by a global move (Sec. IV): kind FPH_MOVE_REFLECT
+ * proposes x_i -> -x_i at every tau; FPH_MOVE_SWAP exchanges x_i and x_j
+ * (i != j; the paper swaps neighbours).  Phi_sigma = A(x)^T R_sigma is drawn
+ * at the current x with the context's action, S_F(x') comes from one solve
+ * (opts.action_solve, zero guess), and x' is accepted if
+ * r_uniform < exp(-(S(x') - S(x))).  On acceptance x_dev receives x'; a
+ * non-converged or non-finite solve rejects.  On return the solver handle's
+ * field is that of x_dev.  Errors: FPH_E_ARG for a bad kind or site index.
+ * Blocks until done. */
+int hmc_global_update(fph_hmc_t hh, int32_t kind, int32_t i, int32_t j, double* x_dev,
+                      const double* R_fields_dev, double r_uniform, fph_update_stats_t* stats_host,
+                      void* stream);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,7 @@ class HmcOpts(ctypes.Structure):
     _fields_ = [("omega0", ctypes.c_double), ("m_reg", ctypes.c_double), ("dt", ctypes.c_double),
                 ("Nt", ctypes.c_int32), ("nt", ctypes.c_int32), ("nfields", ctypes.c_int32),
                 ("a1", ctypes.c_double), ("a2", ctypes.c_double),
-                ("guess", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("guess", ctypes.c_int32), ("lambda_action", ctypes.c_int32),
                 ("force_solve", PcgOpts), ("action_solve", PcgOpts)]
 
 
@@ -64,7 +64,19 @@ class HmcStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class UpdateStats(ctypes.Structure):
+    _fields_ = [("dS", ctypes.c_double), ("dS_B", ctypes.c_double), ("SF_old", ctypes.c_double),
+                ("SF_new", ctypes.c_double), ("accept_prob", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("cg_iters", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 FPH_MASS_INV, FPH_MASS_SQRT, FPH_MASS = 0, 1, 2
+FPH_LAMBDA, FPH_LAMBDA_INV, FPH_LAMBDA_T, FPH_LAMBDA_INV_T = 0, 1, 2, 3
+FPH_MOVE_REFLECT, FPH_MOVE_SWAP = 0, 1
 
 EXPORTS = {
     "fph_version": (ctypes.c_char_p, []),
@@ -108,6 +120,13 @@ EXPORTS = {
     "hmc_trajectory": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.POINTER(HmcStats), ctypes.c_void_p]),
+    "lambda_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lambda_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "hmc_global_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                         ctypes.POINTER(UpdateStats), ctypes.c_void_p]),
 }
 
 _lib = None

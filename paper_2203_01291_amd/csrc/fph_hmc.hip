@@ -258,6 +258,56 @@ k_extrapolate(long n, double* __restrict__ u, double* __restrict__ uold) {
   }
 }
 
+// The Lambda of Eq. (Lambda_def) and its relatives, site by site, one
+// time-slice shift each: out[tau] = s(ts) exp(e a x[ts] / 2) in[tau + dsh],
+// s(t) = +1 for t = 0 else -1, ts = tau + 1 if dsh = +1 else tau, a = dtau alpha:
+//   Lambda:      dsh = +1, e = +1      Lambda^{-1}:  dsh = -1, e = -1
+//   Lambda^T:    dsh = -1, e = +1      Lambda^{-T}:  dsh = +1, e = -1
+// (slices mod Ltau).  Launch: grid (blocks, nvec), block 256.
+__global__ void __launch_bounds__(256)
+k_lambda(int N, int Ltau, long d, const double* __restrict__ x, double a, int dsh, double e,
+         const double* __restrict__ in, double* __restrict__ out) {
+  const double* iv = in + (long)blockIdx.y * d;
+  double* ov = out + (long)blockIdx.y * d;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
+    const int tau = (int)(k / N);
+    const int i = (int)(k - (long)tau * N);
+    int src = tau + dsh;
+    src = src < 0 ? src + Ltau : (src >= Ltau ? src - Ltau : src);
+    const int ts = dsh > 0 ? src : tau;
+    const double sg = ts == 0 ? 1.0 : -1.0;
+    ov[k] = sg * exp(0.5 * e * a * x[(long)ts * N + i]) * iv[(long)src * N + i];
+  }
+}
+
+// grad[tau][i] += coef * sum_r b_r[tau-1][i] u_r[tau-1][i] (slice tau-1 mod Ltau): the
+// Lambda term of the force, coef = -dtau alpha times the caller's scale.
+__global__ void __launch_bounds__(256)
+k_lambda_force(int N, int Ltau, long d, int nrhs, const double* __restrict__ b,
+               const double* __restrict__ u, double coef, double* __restrict__ grad) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
+    const long km = (k >= N) ? k - N : k - N + d;
+    double acc = 0.0;
+    for (int r = 0; r < nrhs; ++r) acc += b[(long)r * d + km] * u[(long)r * d + km];
+    grad[k] += coef * acc;
+  }
+}
+
+// Global moves on column i (and j) of x[Ltau][N]: kind 0 reflects x_i, kind 1 swaps x_i, x_j.
+__global__ void __launch_bounds__(256)
+k_global_move(int N, int Ltau, int kind, int i, int j, double* __restrict__ x) {
+  for (int tau = blockIdx.x * 256 + threadIdx.x; tau < Ltau; tau += gridDim.x * 256) {
+    double* row = x + (long)tau * N;
+    if (kind == 0) {
+      row[i] = -row[i];
+    } else {
+      const double t = row[i];
+      row[i] = row[j];
+      row[j] = t;
+    }
+  }
+}
+
 int grid_for(long n) {
   const long b = (n + 255) / 256;
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
@@ -280,7 +330,7 @@ struct fph_hmc_s {
   double* tab;   // [kNTab][ts]
   double* vals;  // [kNTab][Ltau]
   double* cst;   // [2]
-  double *xi, *xa, *xb, *pa, *pb, *tmp, *Phi, *u, *uold;
+  double *xi, *xa, *xb, *pa, *pb, *tmp, *Phi, *u, *uold, *bvec;
   double* part;  // [2][kRedBlocks]
   double* en;    // [kEn]
   double* en_host;
@@ -333,6 +383,23 @@ hipError_t kinetic_into(const fph_hmc_s* c, const double* p, double* out, hipStr
   return dot_into(c, c->d, p, c->tmp, 0.5, out, s);
 }
 
+hipError_t lambda_into(const fph_hmc_s* c, int op, int nvec, const double* x, const double* in,
+                       double* out, hipStream_t s) {
+  static const int dsh[4] = {+1, -1, -1, +1};
+  static const double ex[4] = {+1.0, -1.0, +1.0, -1.0};
+  dim3 grid(grid_for(c->d), nvec);
+  hipLaunchKernelGGL(k_lambda, grid, dim3(256), 0, s, c->N, c->Ltau, c->d, x,
+                     c->lat.dtau * c->lat.alpha, dsh[op], ex[op], in, out);
+  return hipGetLastError();
+}
+
+hipError_t lambda_force_into(const fph_hmc_s* c, int nrhs, const double* b, const double* u,
+                             double* grad, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda_force, dim3(grid_for(c->d)), dim3(256), 0, s, c->N, c->Ltau, c->d,
+                     nrhs, b, u, -c->lat.dtau * c->lat.alpha * scale, grad);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 #define HMC_CHECK(call)                                         \
@@ -353,7 +420,7 @@ int fph_hmc_destroy(fph_hmc_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {c->tab, c->vals, c->cst, c->xi, c->xa, c->xb, c->pa, c->pb,
-                  c->tmp, c->Phi, c->u, c->uold, c->part, c->en};
+                  c->tmp, c->Phi, c->u, c->uold, c->bvec, c->part, c->en};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->en_host) (void)hipHostFree(c->en_host);
@@ -369,8 +436,8 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   HMC_CALL(fph_get_lattice(h, &lat, &max_rhs));
   if (!(std::isfinite(o->omega0) && o->omega0 > 0.0) || !(std::isfinite(o->dt) && o->dt > 0.0) ||
       std::isnan(o->m_reg) || o->Nt < 1 || o->nt < 1 || !std::isfinite(o->a1) ||
-      !std::isfinite(o->a2) || o->guess < 0 || o->guess > 2 || !opts_ok(o->force_solve) ||
-      !opts_ok(o->action_solve))
+      !std::isfinite(o->a2) || o->guess < 0 || o->guess > 2 || o->lambda_action < 0 ||
+      o->lambda_action > 1 || !opts_ok(o->force_solve) || !opts_ok(o->action_solve))
     return FPH_E_ARG;
   if (o->nfields < 1 || o->nfields > max_rhs) return FPH_E_NRHS;
   fph_hmc_s* c = new fph_hmc_s();
@@ -402,6 +469,7 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   ALLOC(c->Phi, nf * d);
   ALLOC(c->u, nf * d);
   if (o->guess == 2) ALLOC(c->uold, nf * d);
+  ALLOC(c->bvec, nf * d);
   ALLOC(c->part, 2 * kRedBlocks);
   ALLOC(c->en, kEn);
 #undef ALLOC
@@ -409,8 +477,8 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   hipStream_t s = (hipStream_t)stream;
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_hmc_modes, dim3((c->Ltau + 63) / 64), dim3(64), 0, s, c->Ltau, lat.dtau,
-                       c->o.omega0, c->o.m_reg, c->o.dt / c->o.nt, c->o.nt, lat.dtau * lat.alpha,
-                       c->vals, c->cst);
+                       c->o.omega0, c->o.m_reg, c->o.dt / c->o.nt, c->o.nt,
+                       c->o.lambda_action ? 0.0 : lat.dtau * lat.alpha, c->vals, c->cst);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
@@ -436,7 +504,8 @@ int bosonic_force(fph_hmc_t c, const double* x_dev, double* grad_dev, double sca
   if (c == nullptr || x_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
   if (!std::isfinite(scale)) return FPH_E_ARG;
   hipLaunchKernelGGL(k_sb_force, dim3(grid_for(c->d)), dim3(256), 0, (hipStream_t)stream, c->N,
-                     c->Ltau, x_dev, c->o.omega0, c->lat.dtau, c->lat.alpha, scale, grad_dev);
+                     c->Ltau, x_dev, c->o.omega0, c->lat.dtau,
+                     c->o.lambda_action ? 0.0 : c->lat.alpha, scale, grad_dev);
   HMC_CHECK(hipGetLastError());
   return FPH_OK;
 }
@@ -477,10 +546,12 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
   fph_pcg_stats_t ps[64];
   if (nf > 64) return FPH_E_NRHS;
 
+  const bool lam = o.lambda_action != 0;
+  const double* rhs = lam ? c->bvec : c->Phi;  // b = Lambda(x)^{-T} Phi, or Phi
   auto solve = [&](const fph_pcg_opts_t& so, int zero_guess) -> int {
     fph_pcg_opts_t oo = so;
     oo.zero_guess = zero_guess;
-    int rc = pcg_solve(c->h, nf, c->Phi, c->u, &oo, ps, stream);
+    int rc = pcg_solve(c->h, nf, rhs, c->u, &oo, ps, stream);
     if (rc != FPH_OK) return rc;
     S.solves++;
     for (int r = 0; r < nf; ++r) {
@@ -491,11 +562,31 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
     return FPH_OK;
   };
 
-  // Initial state: x_i, Phi_sigma = M(x_i)^T R_sigma, p = sqrt(Mass) R.
+  // The fermion force at the current field c->xa into p (scale per field
+  // times 1/2: S_F = 1/2 sum_sigma b_sigma . u_sigma).
+  auto kick = [&](double scale, int zero_guess) -> int {
+    if (lam) {
+      hipError_t e = lambda_into(c, 3, nf, c->xa, c->Phi, c->bvec, s);
+      if (e != hipSuccess) return fph::record_hip_error(e);
+    }
+    int rc = solve(o.force_solve, zero_guess);
+    if (rc != FPH_OK) return rc;
+    rc = fermion_force(c->h, nf, c->u, c->pa, 0.5 * scale, stream);
+    if (rc != FPH_OK || !lam) return rc;
+    hipError_t e = lambda_force_into(c, nf, c->bvec, c->u, c->pa, 0.5 * scale, s);
+    return e == hipSuccess ? FPH_OK : fph::record_hip_error(e);
+  };
+
+  // Initial state: x_i, Phi_sigma = A(x_i)^T R_sigma, p = sqrt(Mass) R.
   HMC_CHECK(hipMemcpyAsync(c->xi, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
   HMC_CHECK(hipMemcpyAsync(c->xa, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
   HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
-  HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->Phi, stream));
+  if (lam) {
+    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->bvec, stream));
+    HMC_CHECK(lambda_into(c, 2, nf, c->xa, c->bvec, c->Phi, s));
+  } else {
+    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->Phi, stream));
+  }
   HMC_CHECK(circ1(c, TAB_MSQRT, 1, R_mom_dev, c->pa, s));
   HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_I, c->en + EN_LIN_I, s));
   HMC_CHECK(dot_into(c, (long)nf * d, R_fields_dev, R_fields_dev, 0.5, c->en + EN_R2, s));
@@ -504,8 +595,7 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
   // Leapfrog with time-step splitting; the two half kicks between steps
   // share one force evaluation (same x) and are applied as one kick of dt.
   HMC_CHECK(hipMemsetAsync(c->u, 0, (size_t)nf * d * 8, s));
-  HMC_CALL(solve(o.force_solve, 1));
-  HMC_CALL(fermion_force(c->h, nf, c->u, c->pa, -0.25 * o.dt, stream));
+  HMC_CALL(kick(-0.5 * o.dt, 1));
   for (int t = 0; t < o.Nt; ++t) {
     HMC_CHECK(step_map(c, c->xa, c->pa, c->xb, c->pb, s));
     std::swap(c->xa, c->xb);
@@ -520,12 +610,12 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
         HMC_CHECK(hipGetLastError());
       }
     }
-    HMC_CALL(solve(o.force_solve, o.guess == 0 ? 1 : 0));
-    HMC_CALL(fermion_force(c->h, nf, c->u, c->pa, (t + 1 < o.Nt ? -0.5 : -0.25) * o.dt, stream));
+    HMC_CALL(kick((t + 1 < o.Nt ? -1.0 : -0.5) * o.dt, o.guess == 0 ? 1 : 0));
   }
   const int force_status = S.status;
 
-  // Final energies; S_F(x_f) from a tight solve started at the last solution.
+  // Final energies; S_F(x_f) from a tight solve started at the last solution
+  // (b of x_f is already in place).
   HMC_CALL(solve(o.action_solve, 0));
   double sf_f = 0.0;
   for (int r = 0; r < nf; ++r) sf_f += 0.5 * ps[r].action;
@@ -536,8 +626,8 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
   HMC_CHECK(hipMemcpyAsync(c->en_host, c->en, kEn * 8, hipMemcpyDeviceToHost, s));
   HMC_CHECK(hipStreamSynchronize(s));
   const double* en = c->en_host;
-  S.SB_i = en[EN_SB_I] + en[EN_LIN_I];
-  S.SB_f = en[EN_SB_F] + en[EN_LIN_F];
+  S.SB_i = en[EN_SB_I] + (lam ? 0.0 : en[EN_LIN_I]);
+  S.SB_f = en[EN_SB_F] + (lam ? 0.0 : en[EN_LIN_F]);
   S.SF_i = en[EN_R2];
   S.SF_f = sf_f;
   S.K_i = en[EN_K_I];
@@ -555,6 +645,98 @@ int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const
     HMC_CHECK(hipMemcpyAsync(x_dev, c->xa, d * 8, hipMemcpyDeviceToDevice, s));
   } else {
     HMC_CALL(fph_set_field(c->h, c->xi, o.a1, o.a2, stream));
+  }
+  HMC_CHECK(hipStreamSynchronize(s));
+  if (st) *st = S;
+  return FPH_OK;
+}
+
+int lambda_apply(fph_hmc_t c, int32_t op, const double* x_dev, int32_t nvec, const double* in_dev,
+                 double* out_dev, void* stream) {
+  if (c == nullptr || x_dev == nullptr || in_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
+  if (op < FPH_LAMBDA || op > FPH_LAMBDA_INV_T) return FPH_E_PREC;
+  if (nvec < 1 || nvec > 65535) return FPH_E_ARG;
+  const long bytes = (long)nvec * c->d * 8;
+  const char *a = (const char*)in_dev, *b = (const char*)out_dev;
+  if (a < b + bytes && b < a + bytes) return FPH_E_ARG;
+  HMC_CHECK(lambda_into(c, op, nvec, x_dev, in_dev, out_dev, (hipStream_t)stream));
+  return FPH_OK;
+}
+
+int lambda_force(fph_hmc_t c, int32_t nrhs, const double* b_dev, const double* u_dev,
+                 double* grad_dev, double scale, void* stream) {
+  if (c == nullptr || b_dev == nullptr || u_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
+  if (nrhs < 1) return FPH_E_NRHS;
+  if (!std::isfinite(scale)) return FPH_E_ARG;
+  HMC_CHECK(lambda_force_into(c, nrhs, b_dev, u_dev, grad_dev, scale, (hipStream_t)stream));
+  return FPH_OK;
+}
+
+int hmc_global_update(fph_hmc_t c, int32_t kind, int32_t i, int32_t j, double* x_dev,
+                      const double* R_fields_dev, double r_uniform, fph_update_stats_t* st,
+                      void* stream) {
+  if (c == nullptr || x_dev == nullptr || R_fields_dev == nullptr) return FPH_E_NULL;
+  if ((kind != FPH_MOVE_REFLECT && kind != FPH_MOVE_SWAP) || i < 0 || i >= c->N ||
+      (kind == FPH_MOVE_SWAP && (j < 0 || j >= c->N || j == i)) ||
+      !(r_uniform >= 0.0 && r_uniform <= 1.0))
+    return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const fph_hmc_opts_t& o = c->o;
+  const long d = c->d;
+  const int nf = o.nfields;
+  const bool lam = o.lambda_action != 0;
+  fph_update_stats_t S;
+  std::memset(&S, 0, sizeof(S));
+  fph_pcg_stats_t ps[64];
+  if (nf > 64) return FPH_E_NRHS;
+
+  // Phi = A(x)^T R at the current field, S_F(x) = 1/2 |R|^2, the x-only action.
+  HMC_CALL(fph_set_field(c->h, x_dev, o.a1, o.a2, stream));
+  if (lam) {
+    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->bvec, stream));
+    HMC_CHECK(lambda_into(c, 2, nf, x_dev, c->bvec, c->Phi, s));
+  } else {
+    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->Phi, stream));
+  }
+  HMC_CHECK(dot_into(c, (long)nf * d, R_fields_dev, R_fields_dev, 0.5, c->en + EN_R2, s));
+  HMC_CHECK(sb_into(c, x_dev, c->en + EN_SB_I, c->en + EN_LIN_I, s));
+  // Proposal x' in c->xa; its x-only action; S_F(x') from a solve to the action tolerance.
+  HMC_CHECK(hipMemcpyAsync(c->xa, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_global_move, dim3((c->Ltau + 255) / 256), dim3(256), 0, s, c->N, c->Ltau,
+                     (int)kind, (int)i, (int)j, c->xa);
+  HMC_CHECK(hipGetLastError());
+  HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_F, c->en + EN_LIN_F, s));
+  HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
+  const double* rhs = c->Phi;
+  if (lam) {
+    HMC_CHECK(lambda_into(c, 3, nf, c->xa, c->Phi, c->bvec, s));
+    rhs = c->bvec;
+  }
+  fph_pcg_opts_t oo = o.action_solve;
+  oo.zero_guess = 1;
+  HMC_CALL(pcg_solve(c->h, nf, rhs, c->u, &oo, ps, stream));
+  bool ok = true;
+  double sf_new = 0.0;
+  for (int r = 0; r < nf; ++r) {
+    S.status |= ps[r].status;
+    S.cg_iters += ps[r].iters;
+    ok = ok && (ps[r].status & FPH_ST_CONVERGED);
+    sf_new += 0.5 * ps[r].action;
+  }
+  HMC_CHECK(hipMemcpyAsync(c->en_host, c->en, kEn * 8, hipMemcpyDeviceToHost, s));
+  HMC_CHECK(hipStreamSynchronize(s));
+  const double* en = c->en_host;
+  S.dS_B = (en[EN_SB_F] - en[EN_SB_I]) + (lam ? 0.0 : en[EN_LIN_F] - en[EN_LIN_I]);
+  S.SF_old = en[EN_R2];
+  S.SF_new = sf_new;
+  S.dS = S.dS_B + S.SF_new - S.SF_old;
+  const bool bad = !ok || !std::isfinite(S.dS);
+  S.accept_prob = bad ? 0.0 : (S.dS <= 0.0 ? 1.0 : std::exp(-S.dS));
+  S.accepted = (!bad && r_uniform < S.accept_prob) ? 1 : 0;
+  if (S.accepted) {
+    HMC_CHECK(hipMemcpyAsync(x_dev, c->xa, d * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    HMC_CALL(fph_set_field(c->h, x_dev, o.a1, o.a2, stream));
   }
   HMC_CHECK(hipStreamSynchronize(s));
   if (st) *st = S;

@@ -10,11 +10,15 @@ import math
 import torch
 
 from . import _lib
-from ._lib import FPH_MASS, FPH_MASS_INV, FPH_MASS_SQRT, HmcOpts, HmcStats, PcgOpts, check
+from ._lib import (FPH_LAMBDA, FPH_LAMBDA_INV, FPH_LAMBDA_INV_T, FPH_LAMBDA_T, FPH_MASS, FPH_MASS_INV,
+                   FPH_MASS_SQRT, FPH_MOVE_REFLECT, FPH_MOVE_SWAP, HmcOpts, HmcStats, PcgOpts, UpdateStats,
+                   check)
 from .solver import _PRECS, _ptr, _stream
 
 _MASS_OPS = {"inv": FPH_MASS_INV, "sqrt": FPH_MASS_SQRT, "mass": FPH_MASS}
 _GUESS = {"zero": 0, "previous": 1, "extrapolate": 2}
+_LAMBDA_OPS = {"L": FPH_LAMBDA, "Linv": FPH_LAMBDA_INV, "LT": FPH_LAMBDA_T, "LinvT": FPH_LAMBDA_INV_T}
+_MOVES = {"reflect": FPH_MOVE_REFLECT, "swap": FPH_MOVE_SWAP}
 
 
 def _pcg_opts(tol, precond=True, prec="f32_refined", maxiter=100000, ru_delta=0.0):
@@ -22,18 +26,21 @@ def _pcg_opts(tol, precond=True, prec="f32_refined", maxiter=100000, ru_delta=0.
 
 
 class PhononHMC:
-    """HMC updates of the phonon field of one ``FermionSolver`` (which must
-    outlive this object).  m_reg=None disables Fourier acceleration."""
+    """HMC and global updates of the phonon field of one ``FermionSolver``
+    (which must outlive this object).  m_reg=None disables Fourier
+    acceleration; lambda_action=True samples the action with A = M Lambda,
+    False the action S' with A = M."""
 
     def __init__(self, solver, omega0, m_reg, dt, Nt=100, nt=10, nfields=2, a1=1.0, a2=1.0,
                  force_tol=1e-5, action_tol=1e-10, precond=True, prec="f32_refined",
-                 maxiter=100000, guess="zero"):
+                 maxiter=100000, guess="zero", lambda_action=False):
         self.lib = _lib.load()
         self.solver = solver
         self.nfields = int(nfields)
         mr = math.inf if m_reg is None else float(m_reg)
         self.opts = HmcOpts(float(omega0), mr, float(dt), int(Nt), int(nt), self.nfields, float(a1),
-                            float(a2), _GUESS[guess], 0, _pcg_opts(force_tol, precond, prec, maxiter),
+                            float(a2), _GUESS[guess], int(bool(lambda_action)),
+                            _pcg_opts(force_tol, precond, prec, maxiter),
                             _pcg_opts(action_tol, precond, prec, maxiter))
         h = ctypes.c_void_p()
         check(self.lib.fph_hmc_create(ctypes.byref(h), solver.h, ctypes.byref(self.opts), _stream()))
@@ -90,4 +97,29 @@ class PhononHMC:
         pp = _ptr(p_out) if p_out is not None else None
         check(self.lib.hmc_trajectory(self.h, _ptr(x), _ptr(R_fields), _ptr(R_mom), float(r_uniform),
                                       pp, ctypes.byref(st), _stream()))
+        return st.as_dict()
+
+    def lambda_apply(self, x, v, op="LinvT"):
+        """Lambda(x) v, Lambda^{-1} v, Lambda^T v or Lambda^{-T} v (op 'L', 'Linv', 'LT', 'LinvT')."""
+        n = self.solver._vec(v)
+        self._v(x)
+        out = torch.empty_like(v)
+        check(self.lib.lambda_apply(self.h, _LAMBDA_OPS[op], _ptr(x), n, _ptr(v), _ptr(out), _stream()))
+        return out
+
+    def lambda_force(self, b, u, grad, scale=1.0):
+        """grad += scale * (-dtau alpha) * shift_tau(sum_r b_r * u_r)."""
+        n = self.solver._vec(b)
+        check(self.lib.lambda_force(self.h, n, _ptr(b), _ptr(u), _ptr(self._v(grad)), float(scale),
+                                    _stream()))
+        return grad
+
+    def global_update(self, x, kind, i, j, R_fields, r_uniform):
+        """One reflection ('reflect', site i) or swap ('swap', sites i, j) Metropolis update of
+        x (in place if accepted).  Returns the stats dict."""
+        self._v(x)
+        self._v(R_fields, self.nfields)
+        st = UpdateStats()
+        check(self.lib.hmc_global_update(self.h, _MOVES[kind], int(i), int(j), _ptr(x), _ptr(R_fields),
+                                         float(r_uniform), ctypes.byref(st), _stream()))
         return st.as_dict()

@@ -74,7 +74,8 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc not available")
     structs = {"fph_lattice_t": _lib.Lattice, "fph_pcg_opts_t": _lib.PcgOpts,
                "fph_pcg_stats_t": _lib.PcgStats, "fph_system_t": _lib.System,
-               "fph_hmc_opts_t": _lib.HmcOpts, "fph_hmc_stats_t": _lib.HmcStats}
+               "fph_hmc_opts_t": _lib.HmcOpts, "fph_hmc_stats_t": _lib.HmcStats,
+               "fph_update_stats_t": _lib.UpdateStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "holstein_hmc.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
