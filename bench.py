@@ -189,7 +189,8 @@ def bench_hmc(torch, dev, p, a1, a2, log):
     fields, FP32-refined preconditioned solves to 1e-5 for the forces (each
     from a zero guess) and to 1e-10 for the final action, FP64 energies.
     Starts from the workload's synthetic field; one warm-up trajectory, then
-    one timed."""
+    one timed, with the action S' (A = M); then one with the action S
+    (A = M Lambda) and four reflection / swap updates with it."""
     from paper_2203_01291_amd.hmc import PhononHMC
     from paper_2203_01291_amd.solver import FermionSolver
     from workloads import hmc_draws, hmc_params, phonon_field
@@ -224,6 +225,28 @@ def bench_hmc(torch, dev, p, a1, a2, log):
     e1.record(stream)
     e1.synchronize()
     boson_us = e0.elapsed_time(e1) / 50 * 1e3
+    # The same update with the action S (A = M Lambda), and global updates
+    # (reflection of one site, swap of two neighbours) with that action: one
+    # solve to the action tolerance each.
+    hl = PhononHMC(s, hp.omega0, hp.m_reg, hp.dt, Nt=hp.Nt, nt=hp.nt, nfields=hp.nfields, a1=a1, a2=a2,
+                   force_tol=hp.tol_force, action_tol=hp.tol_action, lambda_action=True)
+    x = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stl = hl.trajectory(x, Rf, Rm, r)
+    torch.cuda.synchronize()
+    dtl = time.perf_counter() - t0
+    moves = []
+    for kind, i, j in (("reflect", 0, 0), ("reflect", 517, 0), ("swap", 0, 1), ("swap", 517, 549)):
+        xm = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su = hl.global_update(xm, kind, i, j, Rf, r)
+        torch.cuda.synchronize()
+        moves.append({"kind": kind, "sites": [i, j] if kind == "swap" else [i],
+                      "ms": (time.perf_counter() - t0) * 1e3, "dS": su["dS"], "cg_iters": su["cg_iters"],
+                      "status": su["status"]})
+    hl.close()
     res = {
         "workload": f"{p.name}: one HMC update, dt={hp.dt:g}, Nt={hp.Nt}, nt={hp.nt}, "
                     f"m_reg={hp.m_reg}, {hp.nfields} fields, FP32-refined PCG (a1={a1}, a2={a2}) "
@@ -234,6 +257,9 @@ def bench_hmc(torch, dev, p, a1, a2, log):
         "dH": st["H_f"] - st["H_i"], "accept_prob": st["accept_prob"], "accepted": st["accepted"],
         "status": st["status"], "boson_step_us": boson_us,
         "boson_fraction": boson_us * 1e-6 * hp.Nt / dt,
+        "lambda_action": {"ms_per_trajectory": dtl * 1e3, "cg_iters": stl["cg_iters"],
+                          "dH": stl["H_f"] - stl["H_i"], "status": stl["status"],
+                          "global_updates": moves},
     }
     log(f"hmc: {res}")
     h.close()

@@ -181,3 +181,42 @@ def test_lambda_trajectory_c3_paper_settings():
     assert st["K_f"] == pytest.approx(OH.kinetic_energy(pf.cpu().numpy(), mt), rel=1e-11)
     assert st["SF_i"] == pytest.approx(0.5 * np.sum(R ** 2), rel=1e-12)
     assert abs(st["H_f"] - st["H_i"]) < 5.0
+
+
+def test_reflection_acceptance_single_site_paper_values():
+    """The paper's printed acceptance of single-site reflections (Sec. IV): omega0 = 1,
+    alpha = 2, beta = 4, half filling; about 68 % with S and about 2 % with S'.  Sixteen
+    independent sites (t = 0) are sampled by this library's HMC with the action S (paper
+    settings, 40 trajectories to equilibrate from x = alpha/omega0^2), then after each of 60
+    further trajectories every site's reflection is proposed with fresh Phi under both actions
+    and the Metropolis probabilities are averaged (960 proposals each).  Statistical: the
+    bounds allow about four standard errors of a correlated sample."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))[
+        "reflection_acceptance"]
+    dtau = 0.1
+    Ltau = int(round(g["beta"] / dtau))
+    lat = OL.Lattice(4, Ltau, dtau, g["t"], g["mu"], g["alpha"])
+    w0 = g["omega0"]
+    kw = dict(Nt=100, nt=10, force_tol=1e-8, action_tol=1e-10, precond=False, prec="f64")
+    s, hS = make(lat, w0, w0, 0.01 / w0, lambda_action=True, **kw)
+    from paper_2203_01291_amd.hmc import PhononHMC
+    hP = PhononHMC(s, w0, w0, 0.01 / w0, nfields=2, lambda_action=False, **kw)
+    rng = np.random.default_rng(2203)
+    x = tgpu(g["alpha"] / w0 ** 2 + 0.1 * rng.standard_normal((Ltau, lat.N)))
+    accS, accP = [], []
+    for it in range(100):
+        st = hS.trajectory(x, tgpu(rng.standard_normal((2, Ltau, lat.N))),
+                           tgpu(rng.standard_normal((Ltau, lat.N))), rng.random())
+        assert st["status"] == 1
+        if it < 40:
+            continue
+        for i in range(lat.N):
+            R2 = tgpu(rng.standard_normal((2, Ltau, lat.N)))
+            accS.append(hS.global_update(x, "reflect", i, 0, R2, 1.0)["accept_prob"])
+            accP.append(hP.global_update(x, "reflect", i, 0, R2, 1.0)["accept_prob"])
+    aS, aP = float(np.mean(accS)), float(np.mean(accP))
+    print("reflection acceptance: S", aS, "S'", aP, flush=True)
+    assert abs(aS - g["S"]) < 0.08
+    assert abs(aP - g["S_prime"]) < 0.015
