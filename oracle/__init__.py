@@ -27,9 +27,11 @@ definition in the paper (arXiv:2203.01291):
 * ``lam``      - the Lambda reformulation A = M Lambda of the action, its
                  force, and the reflection and swap updates (Secs. II C, IV;
                  App. B).
+* ``measure``  - stochastic Green's-function estimates and their space-time
+                 averages by FFT cross-correlation (Sec. VI).
 
 Parity status of each function is stated in its docstring; a function with
 no independent pin says "parity unpinned".
 """
 
-from . import lattice, solve, force, precond, hmc, lam  # noqa: F401
+from . import lattice, solve, force, precond, hmc, lam, measure  # noqa: F401
