@@ -10,7 +10,8 @@
  * preconditioner of Sec. V (Eqs. P_def, CG_precon, P_change_basis, App. C),
  * evaluates the action S_F = Phi . u (Eq. Sf_Psi) and the phonon force
  * dS_F/dx of Eq. (dSF_dx), and runs the hybrid Monte Carlo update of the
- * phonon field built on them (Sec. III, Algorithm 1; fph_hmc_* below).
+ * phonon field built on them (Sec. III, Algorithm 1; fph_hmc_* below) and
+ * the stochastic Green's-function measurements (Sec. VI; fph_meas_*).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -419,6 +420,66 @@ typedef struct {
 int hmc_global_update(fph_hmc_t hh, int32_t kind, int32_t i, int32_t j, double* x_dev,
                       const double* R_fields_dev, double r_uniform, fph_update_stats_t* stats_host,
                       void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Stochastic Green's-function measurements (Sec. VI).                 */
+/*
+ * G = M^{-1} estimates the Green's function (Eq. Green_approx); for random
+ * vectors xi with <xi xi^T> = I, G ~ (G xi) xi^T (Eq. Hutch_approx), with
+ * G xi from (M^T M) v = M^T xi.  Space-time averages over displacements
+ * Delta = (dtau, dy, dx) are circular cross-correlations computed with
+ * discrete Fourier transforms (Eq. cross_corr).  Result arrays are
+ * [Ltau][L][L] doubles indexed [dtau][dy][dx] (the layout of a field).
+ * Ncal = N Ltau.  The lattice needs Ltau = P Q with P, Q <= 64.
+ */
+
+typedef struct fph_meas_s* fph_meas_t;
+
+/* Create a measurement context on solver handle h (which must outlive it):
+ * transform tables and device workspace (six complex grids and max_rhs real
+ * vectors).  Errors: FPH_E_NULL, FPH_E_LATTICE (Ltau not a product of two
+ * factors <= 64), FPH_E_HIP.  Enqueues the tables on `stream`. */
+int fph_meas_create(fph_meas_t* mh, fph_handle_t h, void* stream);
+
+/* Release the context (synchronises the device). */
+int fph_meas_destroy(fph_meas_t mh);
+
+/* Unnormalised 3-D DFT over (tau, y, x) of one complex grid (interleaved
+ * re/im doubles [Ltau][N][2]): forward exp(-2 pi i k.n / n_d) or inverse
+ * exp(+...).  twist = 1 transforms the antiperiodic extension of the grid to
+ * 2 Ltau slices on its Ltau odd frequencies: the forward transform first
+ * multiplies slice tau by exp(-i pi tau/Ltau), the inverse multiplies its
+ * output slice by exp(+i pi tau/Ltau).  in and out must differ.  Enqueue only. */
+int meas_fft(fph_meas_t mh, int32_t inverse, int32_t twist, const double* in_dev, double* out_dev,
+             void* stream);
+
+/* gxi_dev[n] = G xi_n for nvec real vectors [Ltau][N]: b = M^T xi with the
+ * current field, then pcg_solve with *opts (zero guess), in chunks of the
+ * handle's max_rhs (Sec. VI B).  stats_host: nvec entries (may be NULL).
+ * Blocks until done. */
+int green_vectors(fph_meas_t mh, int32_t nvec, const double* xi_dev, double* gxi_dev,
+                  const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host, void* stream);
+
+/* out_dev[dtau][dy][dx] = (1/nvec) sum_n (1/Ncal) sum_i (Q G xi_n)_{i+Delta} (Q xi_n)_i:
+ * the average over space-time of G^ext = Q G Q^T, Q = [I; -I] (Eqs. G_avg-1,
+ * G_def-1), estimated with nvec vector pairs (xi_n, G xi_n) (Eq.
+ * G_approx_better); dtau in [0, Ltau) (antiperiodic beyond).  The sum runs
+ * over the Ncal distinct space-time points.  Enqueue only. */
+int green_average(fph_meas_t mh, int32_t nvec, const double* xi_dev, const double* gxi_dev,
+                  double* out_dev, void* stream);
+
+/* out_dev[3][Ltau][N]: the averages over space-time of the three products of
+ * Green's functions of a four-point measurement (Sec. VI C),
+ *   T1 = (1/Ncal) sum_i G_{i+D,i} G_{i+D,i},   T2 = (1/Ncal) sum_i G_{i+D,i+D} G_{i,i},
+ *   T3 = (1/Ncal) sum_i G_{i+D,i} G_{i,i+D},
+ * each estimated by the average over all pairs n < m of independent vectors
+ * (Eq. GG_approx_better) as the cross-correlations
+ *   (xi_n . xi_m) * (Gxi_n . Gxi_m),  (xi_n . Gxi_n) * (xi_m . Gxi_m),
+ *   (xi_n . Gxi_m) * (xi_m . Gxi_n)   ('.' elementwise, '*' cross-correlation),
+ * on the original grid, periodic in tau (the signs of G^ext cancel in each
+ * product).  nvec >= 2.  Enqueue only. */
+int green_pair_products(fph_meas_t mh, int32_t nvec, const double* xi_dev, const double* gxi_dev,
+                        double* out_dev, void* stream);
 
 #ifdef __cplusplus
 }
