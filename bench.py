@@ -15,8 +15,8 @@ Prints one JSON line: the headline (FP32-refined solves/s), the same step
 with FP64 CG, one step of every solver variant, the fused M^T M roofline
 (HIP events on the stream the kernel runs on) on a working set above the
 Infinity Cache and at the workload shape, the batched persistent solve,
-one full HMC update with the paper's settings, and the CPU oracle timed on
-a bounded sample.
+one full HMC update with the paper's settings, the stochastic Green's-function
+measurements, and the CPU oracle timed on a bounded sample.
 """
 
 import argparse
@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC trajectory leg")
     ap.add_argument("--hmc-only", action="store_true",
                     help="only the HMC trajectory leg (one warm-up and one timed trajectory)")
+    ap.add_argument("--no-meas", action="store_true", help="skip the measurement leg")
+    ap.add_argument("--meas-only", action="store_true",
+                    help="only the stochastic Green's-function measurement leg")
+    ap.add_argument("--nrv", type=int, default=10, help="random vectors of the measurement leg")
     ap.add_argument("--profile-roofline", action="store_true",
                     help="only the roofline kernel (M^T M, FP32, L=64 Ltau=400 x 32 rhs) and a "
                          "plain copy of the same byte count, for hardware-counter runs")
@@ -267,6 +271,62 @@ def bench_hmc(torch, dev, p, a1, a2, log):
     return res
 
 
+def bench_measure(torch, dev, p, a1, a2, nrv, log):
+    """Stochastic Green's-function measurements (Sec. VI) on the workload's
+    field: nrv Rademacher vectors, G xi from FP32-refined preconditioned
+    solves to 1e-8 (nrv right-hand sides in one call), the space-time
+    average of G^ext and the three pair-averaged four-point products by FFT
+    cross-correlation; each part timed once after a warm-up."""
+    from paper_2203_01291_amd.measure import GreenMeasurement
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import phonon_field, rademacher_rhs
+
+    s = FermionSolver.from_params(p, max_rhs=nrv)
+    s.set_field(torch.from_numpy(phonon_field(p)).to(dev), a1=a1, a2=a2)
+    m = GreenMeasurement(s)
+    xi = torch.from_numpy(rademacher_rhs(p, nrv)).to(dev)
+    gx, _ = m.green_vectors(xi)
+    m.green_average(xi, gx)
+    m.pair_products(xi[:2], gx[:2])
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, r
+
+    t_vec, (gx, st) = timed(lambda: m.green_vectors(xi))
+    t_avg, _ = timed(lambda: m.green_average(xi, gx))
+    t_pair, _ = timed(lambda: m.pair_products(xi, gx))
+    z = torch.randn(p.Ltau, p.N, dtype=torch.complex128, device=dev)
+    for _ in range(3):
+        m.fft(z)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        m.fft(z)
+    e1.record(stream)
+    e1.synchronize()
+    fft_us = e0.elapsed_time(e1) / 20 * 1e3
+    npairs = nrv * (nrv - 1) // 2
+    res = {
+        "workload": f"{p.name}: {nrv} Rademacher vectors, G xi by FP32-refined PCG to 1e-8 "
+                    f"(a1={a1}, a2={a2}), average of G^ext and {npairs}-pair four-point products",
+        "green_vectors_ms": t_vec, "iters": [v["iters"] for v in st],
+        "green_average_ms": t_avg, "pair_products_ms": t_pair,
+        "fft3_us": fft_us, "grid": [p.Ltau, p.L, p.L],
+        "fft3_per_pair_products": 4 * npairs + nrv,
+    }
+    log(f"measure: {res}")
+    m.close()
+    s.close()
+    return res
+
+
 def cpu_baseline(p, golden_iters):
     """Oracle CG (scipy CSR, FP64) on the workload for a bounded number of
     iterations; scaled to solves/s with the oracle's own iteration count."""
@@ -369,6 +429,11 @@ def main():
 
     if args.profile_roofline:
         profile_roofline(torch, torch.device("cuda:0"))
+        return
+    if args.meas_only:
+        from workloads import get_config as _gc
+        print(json.dumps(bench_measure(torch, torch.device("cuda:0"), _gc(args.workload), args.a1, args.a2,
+                                       args.nrv, log)), flush=True)
         return
     if args.hmc_only:
         from workloads import get_config as _gc
@@ -513,6 +578,10 @@ def main():
     if not args.no_hmc and R == 1:
         hmc = bench_hmc(torch, dev, p, args.a1, args.a2, log)
 
+    meas = None
+    if not args.no_meas and R == 1:
+        meas = bench_measure(torch, dev, p, args.a1, args.a2, args.nrv, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_iterations.json")))
@@ -576,6 +645,7 @@ def main():
         "variants": variants,
         "two_fields": two_fields,
         "hmc_trajectory": hmc,
+        "measurements": meas,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
