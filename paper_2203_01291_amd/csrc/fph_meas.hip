@@ -29,10 +29,6 @@ namespace {
 
 constexpr int kLdsMax = 150 * 1024;  // dynamic LDS budget per workgroup
 
-struct C2 {
-  double x, y;
-};
-
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -55,8 +51,10 @@ enum { OUT_COMPLEX = 0, OUT_REAL = 1 };
 
 // Spatial DFT of one time slice per workgroup (grid: Ltau).  Input: complex
 // in_c, real a, or the product a*b of two real vectors (slice tau of each).
-// Output: complex, or the real part times `scale`.
-template <bool INV>
+// Output: complex, or the real part times `scale`.  Each thread computes G
+// adjacent outputs of a row (or column) at once: one LDS read of an input
+// feeds G independent multiply-add chains.
+template <bool INV, int G>
 __global__ void __launch_bounds__(256)
 k_fft_xy(int L, int N, int in_mode, const double2* __restrict__ in_c, const double* __restrict__ a,
          const double* __restrict__ b, int out_mode, double scale, double2* __restrict__ out_c,
@@ -75,37 +73,58 @@ k_fft_xy(int L, int N, int in_mode, const double2* __restrict__ in_c, const doub
     A[e] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < N; e += 256) {  // along x: B[y][kx]
-    const int kx = e % L, y = e / L;
-    double2 s = make_double2(0.0, 0.0);
-    int m = 0;
-    for (int xx = 0; xx < L; ++xx) {
-      s = cfma(A[y * L + xx], tw[m], s);
-      m += kx;
-      if (m >= L) m -= L;
+  const int ng = L / G;  // groups of G outputs per row
+  for (int gi = threadIdx.x; gi < ng * L; gi += 256) {  // along x: B[y][kx0 + j]
+    const int y = gi / ng, kx0 = (gi - y * ng) * G;
+    double2 acc[G];
+    int m[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      acc[j] = make_double2(0.0, 0.0);
+      m[j] = 0;
     }
-    B[e] = s;
+    for (int xx = 0; xx < L; ++xx) {
+      const double2 v = A[y * L + xx];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        acc[j] = cfma(v, tw[m[j]], acc[j]);
+        m[j] += kx0 + j;
+        if (m[j] >= L) m[j] -= L;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) B[y * L + kx0 + j] = acc[j];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < N; e += 256) {  // along y: out[ky][kx]
-    const int kx = e % L, ky = e / L;
-    double2 s = make_double2(0.0, 0.0);
+  for (int gi = threadIdx.x; gi < ng * L; gi += 256) {  // along y: out[ky][kx0 + j]
+    const int ky = gi / ng, kx0 = (gi - ky * ng) * G;
+    double2 acc[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) acc[j] = make_double2(0.0, 0.0);
     int m = 0;
     for (int y = 0; y < L; ++y) {
-      s = cfma(B[y * L + kx], tw[m], s);
+      const double2 w = tw[m];
+#pragma unroll
+      for (int j = 0; j < G; ++j) acc[j] = cfma(B[y * L + kx0 + j], w, acc[j]);
       m += ky;
       if (m >= L) m -= L;
     }
-    if (out_mode == OUT_COMPLEX) out_c[base + e] = s;
-    else out_r[base + e] = scale * s.x;
+    const long o = base + (long)ky * L + kx0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      if (out_mode == OUT_COMPLEX) out_c[o + j] = acc[j];
+      else out_r[o + j] = scale * acc[j].x;
+    }
   }
 }
 
 // Transform along tau of S sites per workgroup (grid: N/S), Ltau = P*Q.
-// in/out complex [Ltau][N]; twist as described at the top of the file.
-template <bool INV>
+// in/out complex [Ltau][N]; twist as described at the top of the file.  A
+// thread computes one output row for all S sites: one twiddle feeds S
+// independent multiply-add chains.
+template <bool INV, int S>
 __global__ void __launch_bounds__(256)
-k_fft_t(int N, int T, int P, int Q, int S, int twist, const double2* __restrict__ in,
+k_fft_t(int N, int T, int P, int Q, int twist, const double2* __restrict__ in,
         double2* __restrict__ out, const double2* __restrict__ twT) {
   extern __shared__ double2 sh[];
   double2* X = sh;              // [T][S]
@@ -125,38 +144,50 @@ k_fft_t(int N, int T, int P, int Q, int S, int twist, const double2* __restrict_
   }
   __syncthreads();
   // stage A: Y[q P + k1] = w_T^{q k1} sum_p X[Q p + q] w_P^{p k1},  w_P^j = tw[Q j]
-  for (int e = threadIdx.x; e < T * S; e += 256) {
-    const int s = e % S, r = e / S;
+  for (int r = threadIdx.x; r < T; r += 256) {
     const int k1 = r % P, q = r / P;
-    double2 acc = make_double2(0.0, 0.0);
+    double2 acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = make_double2(0.0, 0.0);
     int m = 0;
     const int step = (Q * k1) % T;
     for (int p = 0; p < P; ++p) {
-      acc = cfma(X[(Q * p + q) * S + s], tw[m], acc);
+      const double2 w = tw[m];
+      const double2* xr = X + (Q * p + q) * S;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] = cfma(xr[s], w, acc[s]);
       m += step;
       if (m >= T) m -= T;
     }
-    Y[e] = cmul(acc, tw[(q * k1) % T]);
+    const double2 post = tw[(q * k1) % T];
+#pragma unroll
+    for (int s = 0; s < S; ++s) Y[r * S + s] = cmul(acc[s], post);
   }
   __syncthreads();
   // stage B: out[k1 + P k2] = sum_q Y[q P + k1] w_Q^{q k2},  w_Q^j = tw[P j]
-  for (int e = threadIdx.x; e < T * S; e += 256) {
-    const int s = e % S, k = e / S;
+  for (int k = threadIdx.x; k < T; k += 256) {
     const int k1 = k % P, k2 = k / P;
-    double2 acc = make_double2(0.0, 0.0);
+    double2 acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = make_double2(0.0, 0.0);
     int m = 0;
     const int step = (P * k2) % T;
     for (int q = 0; q < Q; ++q) {
-      acc = cfma(Y[(q * P + k1) * S + s], tw[m], acc);
+      const double2 w = tw[m];
+      const double2* yr = Y + (q * P + k1) * S;
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] = cfma(yr[s], w, acc[s]);
       m += step;
       if (m >= T) m -= T;
     }
+    double2 tk = make_double2(1.0, 0.0);
     if (twist && INV) {
       double sn, cs;
       sincospi((double)k / T, &sn, &cs);
-      acc = cmul(acc, make_double2(cs, sn));
+      tk = make_double2(cs, sn);
     }
-    out[(long)k * N + site0 + s] = acc;
+#pragma unroll
+    for (int s = 0; s < S; ++s) out[(long)k * N + site0 + s] = cmul(acc[s], tk);
   }
 }
 
@@ -220,30 +251,63 @@ struct fph_meas_s {
 
 namespace {
 
+hipError_t launch_xy(const fph_meas_s* m, bool inv, int in_mode, const double2* in_c, const double* a,
+                     const double* b, int out_mode, double scale, double2* out_c, double* out_r,
+                     hipStream_t s) {
+  const bool g4 = (m->L % 4) == 0;
+  if (!inv && g4)
+    hipLaunchKernelGGL((k_fft_xy<false, 4>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, in_mode, in_c,
+                       a, b, out_mode, scale, out_c, out_r, (const double2*)m->twL);
+  else if (!inv)
+    hipLaunchKernelGGL((k_fft_xy<false, 2>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, in_mode, in_c,
+                       a, b, out_mode, scale, out_c, out_r, (const double2*)m->twL);
+  else if (g4)
+    hipLaunchKernelGGL((k_fft_xy<true, 4>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, in_mode, in_c,
+                       a, b, out_mode, scale, out_c, out_r, (const double2*)m->twL);
+  else
+    hipLaunchKernelGGL((k_fft_xy<true, 2>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, in_mode, in_c,
+                       a, b, out_mode, scale, out_c, out_r, (const double2*)m->twL);
+  return hipGetLastError();
+}
+
+template <bool INV>
+hipError_t launch_t_inv(const fph_meas_s* m, int twist, const double2* in, double2* out, hipStream_t s) {
+  dim3 g(m->N / m->S);
+#define FPH_T_CASE(SS)                                                                              \
+  case SS:                                                                                          \
+    hipLaunchKernelGGL((k_fft_t<INV, SS>), g, dim3(256), m->lds_t, s, m->N, m->T, m->P, m->Q, twist, \
+                       in, out, (const double2*)m->twT);                                          \
+    break;
+  switch (m->S) {
+    FPH_T_CASE(1)
+    FPH_T_CASE(2)
+    FPH_T_CASE(4)
+    FPH_T_CASE(8)
+    FPH_T_CASE(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef FPH_T_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_t(const fph_meas_s* m, bool inv, int twist, const double2* in, double2* out, hipStream_t s) {
+  return inv ? launch_t_inv<true>(m, twist, in, out, s) : launch_t_inv<false>(m, twist, in, out, s);
+}
+
 // Forward 3-D transform of a real input (in_mode IN_REAL / IN_PRODUCT) into `out`.
 hipError_t fwd3(const fph_meas_s* m, int in_mode, const double* a, const double* b, int twist,
                 double2* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_fft_xy<false>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, in_mode,
-                     (const double2*)nullptr, a, b, (int)OUT_COMPLEX, 0.0, m->tmp, (double*)nullptr,
-                     (const double2*)m->twL);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_xy(m, false, in_mode, nullptr, a, b, OUT_COMPLEX, 0.0, m->tmp, nullptr, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fft_t<false>), dim3(m->N / m->S), dim3(256), m->lds_t, s, m->N, m->T, m->P, m->Q,
-                     m->S, twist, (const double2*)m->tmp, out, (const double2*)m->twT);
-  return hipGetLastError();
+  return launch_t(m, false, twist, m->tmp, out, s);
 }
 
 // Inverse 3-D transform of `in` (complex), real part times `scale` into out_r.
 hipError_t inv3(const fph_meas_s* m, const double2* in, int twist, double scale, double* out_r,
                 hipStream_t s) {
-  hipLaunchKernelGGL((k_fft_t<true>), dim3(m->N / m->S), dim3(256), m->lds_t, s, m->N, m->T, m->P, m->Q,
-                     m->S, twist, in, m->tmp, (const double2*)m->twT);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_t(m, true, twist, in, m->tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fft_xy<true>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, (int)IN_COMPLEX,
-                     (const double2*)m->tmp, (const double*)nullptr, (const double*)nullptr,
-                     (int)OUT_REAL, scale, (double2*)nullptr, out_r, (const double2*)m->twL);
-  return hipGetLastError();
+  return launch_xy(m, true, IN_COMPLEX, m->tmp, nullptr, nullptr, OUT_REAL, scale, nullptr, out_r, s);
 }
 
 hipError_t zero2(const fph_meas_s* m, double2* p, hipStream_t s) {
@@ -329,14 +393,17 @@ int fph_meas_create(fph_meas_t* out, fph_handle_t h, void* stream) {
   ALLOC(m->run, m->d * sizeof(double2));
   ALLOC(m->bvec, (size_t)max_rhs * m->d * sizeof(double));
 #undef ALLOC
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_fft_xy<false>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_fft_xy<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_fft_t<false>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_fft_t<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+  {
+    const void* fns[] = {(const void*)k_fft_xy<false, 2>, (const void*)k_fft_xy<false, 4>,
+                         (const void*)k_fft_xy<true, 2>,  (const void*)k_fft_xy<true, 4>,
+                         (const void*)k_fft_t<false, 1>,  (const void*)k_fft_t<false, 2>,
+                         (const void*)k_fft_t<false, 4>,  (const void*)k_fft_t<false, 8>,
+                         (const void*)k_fft_t<false, 16>, (const void*)k_fft_t<true, 1>,
+                         (const void*)k_fft_t<true, 2>,   (const void*)k_fft_t<true, 4>,
+                         (const void*)k_fft_t<true, 8>,   (const void*)k_fft_t<true, 16>};
+    for (const void* f : fns)
+      if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+  }
   hipStream_t s = (hipStream_t)stream;
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_meas_twiddles, dim3(1), dim3(256), 0, s, m->L, m->twL);
@@ -361,22 +428,14 @@ int meas_fft(fph_meas_t m, int32_t inverse, int32_t twist, const double* in_dev,
   hipStream_t s = (hipStream_t)stream;
   const double2* in = (const double2*)in_dev;
   double2* out = (double2*)out_dev;
+  const int tw = twist != 0;
   if (!inverse) {
-    hipLaunchKernelGGL((k_fft_xy<false>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, (int)IN_COMPLEX,
-                       in, (const double*)nullptr, (const double*)nullptr, (int)OUT_COMPLEX, 0.0, m->tmp,
-                       (double*)nullptr, (const double2*)m->twL);
-    MEAS_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_fft_t<false>), dim3(m->N / m->S), dim3(256), m->lds_t, s, m->N, m->T, m->P, m->Q,
-                       m->S, (int)(twist != 0), (const double2*)m->tmp, out, (const double2*)m->twT);
+    MEAS_CHECK(launch_xy(m, false, IN_COMPLEX, in, nullptr, nullptr, OUT_COMPLEX, 0.0, m->tmp, nullptr, s));
+    MEAS_CHECK(launch_t(m, false, tw, m->tmp, out, s));
   } else {
-    hipLaunchKernelGGL((k_fft_t<true>), dim3(m->N / m->S), dim3(256), m->lds_t, s, m->N, m->T, m->P, m->Q,
-                       m->S, (int)(twist != 0), in, m->tmp, (const double2*)m->twT);
-    MEAS_CHECK(hipGetLastError());
-    hipLaunchKernelGGL((k_fft_xy<true>), dim3(m->T), dim3(256), m->lds_xy, s, m->L, m->N, (int)IN_COMPLEX,
-                       (const double2*)m->tmp, (const double*)nullptr, (const double*)nullptr,
-                       (int)OUT_COMPLEX, 0.0, out, (double*)nullptr, (const double2*)m->twL);
+    MEAS_CHECK(launch_t(m, true, tw, in, m->tmp, s));
+    MEAS_CHECK(launch_xy(m, true, IN_COMPLEX, m->tmp, nullptr, nullptr, OUT_COMPLEX, 0.0, out, nullptr, s));
   }
-  MEAS_CHECK(hipGetLastError());
   return FPH_OK;
 }
 

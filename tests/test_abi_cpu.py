@@ -94,3 +94,30 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_hmc_and_measurement_argument_errors_on_host():
+    """The HMC, Lambda and measurement entry points check their arguments before any device
+    work: null handles and pointers return FPH_E_NULL without touching the GPU."""
+    from paper_2203_01291_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    import ctypes
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.fph_hmc_create(ctypes.byref(h), None, None, None) == -1
+    assert lib.fph_hmc_create(None, None, None, None) == -1
+    assert lib.bosonic_action(None, None, None, None) == -1
+    assert lib.bosonic_force(None, None, None, 1.0, None) == -1
+    assert lib.hmc_mass_apply(None, 0, 1, None, None, None) == -1
+    assert lib.hmc_boson_steps(None, None, None, None) == -1
+    assert lib.hmc_trajectory(None, None, None, None, 0.5, None, None, None) == -1
+    assert lib.lambda_apply(None, 0, None, 1, None, None, None) == -1
+    assert lib.lambda_force(None, 1, None, None, None, 1.0, None) == -1
+    assert lib.hmc_global_update(None, 0, 0, 0, None, None, 0.5, None, None) == -1
+    assert lib.fph_meas_create(ctypes.byref(h), None, None) == -1
+    assert lib.meas_fft(None, 0, 0, None, None, None) == -1
+    assert lib.green_vectors(None, 1, None, None, None, None, None) == -1
+    assert lib.green_average(None, 1, None, None, None, None) == -1
+    assert lib.green_pair_products(None, 2, None, None, None, None) == -1
+    assert lib.fph_get_lattice(None, None, None) == -1
