@@ -422,6 +422,35 @@ int hmc_global_update(fph_hmc_t hh, int32_t kind, int32_t i, int32_t j, double* 
                       void* stream);
 
 /* ------------------------------------------------------------------ */
+/* Independent work on several streams at once.                        */
+/*
+ * At moderate sizes a single system's kernels are bound by launch and
+ * memory latency and leave most compute units idle, so independent systems
+ * (for example independent Markov chains) run faster side by side: each item
+ * runs on its own handle and its own stream from a host thread of its own,
+ * and the calls return when all items are done.  Results equal those of the
+ * same calls made one after the other.  n is 1..64; streams must be non-NULL
+ * and distinct, handles distinct (FPH_E_ARG otherwise).  The first error of
+ * any item is returned.
+ */
+
+/* pcg_solve(h[k], nrhs[k], b_dev[k], u_dev[k], &opts[k], stats_host[k], streams[k])
+ * for k < n, concurrently.  stats_host may be NULL, or hold NULL entries. */
+int pcg_solve_concurrent(int32_t n, fph_handle_t const* h, const int32_t* nrhs,
+                         const double* const* b_dev, double* const* u_dev,
+                         const fph_pcg_opts_t* opts, fph_pcg_stats_t* const* stats_host,
+                         void* const* streams);
+
+/* hmc_trajectory(hh[k], x_dev[k], R_fields_dev[k], R_mom_dev[k], r_uniform[k],
+ * p_out_dev ? p_out_dev[k] : NULL, &stats_host[k], streams[k]) for k < n,
+ * concurrently; the contexts must sit on distinct solver handles.  p_out_dev
+ * and stats_host may be NULL. */
+int hmc_trajectory_concurrent(int32_t n, fph_hmc_t const* hh, double* const* x_dev,
+                              const double* const* R_fields_dev, const double* const* R_mom_dev,
+                              const double* r_uniform, double* const* p_out_dev,
+                              fph_hmc_stats_t* stats_host, void* const* streams);
+
+/* ------------------------------------------------------------------ */
 /* Stochastic Green's-function measurements (Sec. VI).                 */
 /*
  * G = M^{-1} estimates the Green's function (Eq. Green_approx); for random

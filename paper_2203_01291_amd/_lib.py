@@ -127,6 +127,15 @@ EXPORTS = {
     "hmc_global_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                          ctypes.POINTER(UpdateStats), ctypes.c_void_p]),
+    "pcg_solve_concurrent": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PcgOpts),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
+    "hmc_trajectory_concurrent": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(HmcStats),
+                                                 ctypes.POINTER(ctypes.c_void_p)]),
     "fph_meas_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p]),
     "fph_meas_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "meas_fft": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,

@@ -5,7 +5,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("fph_lib.hip", "fph_hmc.hip", "fph_meas.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("fph_lib.hip", "fph_hmc.hip", "fph_meas.hip",
+                                                    "fph_concurrent.hip")]
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libholstein_hmc.so")
 

@@ -402,6 +402,8 @@ hipError_t lambda_force_into(const fph_hmc_s* c, int nrhs, const double* b, cons
 
 }  // namespace
 
+fph_handle_t fph::hmc_solver(fph_hmc_t c) { return c ? c->h : nullptr; }
+
 #define HMC_CHECK(call)                                         \
   do {                                                          \
     hipError_t e_ = (call);                                     \

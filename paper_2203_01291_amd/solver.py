@@ -128,6 +128,50 @@ class FermionSolver:
         return out
 
 
+def _side_streams(n):
+    """n new streams (default priority), each ordered after the current stream's work."""
+    cur = torch.cuda.current_stream()
+    streams = [torch.cuda.Stream() for _ in range(n)]
+    for st in streams:
+        st.wait_stream(cur)
+    return cur, streams
+
+
+def solve_concurrent(items, tol=1e-10, maxiter=100000, precond=False, prec="f64", ru_delta=0.0):
+    """Solve several independent systems side by side, each on its own stream
+    and host thread inside the library (pcg_solve_concurrent).  items: list of
+    (solver, b) or (solver, b, u) with distinct solvers (u is the initial guess
+    and receives the solution; None starts from zero).  Returns a list of
+    (u, [stats per rhs]).  Blocks until all are done."""
+    lib = _lib.load()
+    n = len(items)
+    hs, nr, bs, us, opts, sts, keep = [], [], [], [], [], [], []
+    for it in items:
+        s, b = it[0], it[1]
+        u = it[2] if len(it) > 2 else None
+        k = s._vec(b)
+        zero = u is None
+        u = torch.empty_like(b) if u is None else u
+        st = (PcgStats * k)()
+        hs.append(s.h.value)
+        nr.append(k)
+        bs.append(b.data_ptr())
+        us.append(u.data_ptr())
+        opts.append(PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero),
+                            float(ru_delta), 0, 0))
+        sts.append(st)
+        keep.append((u, st))
+    cur, streams = _side_streams(n)
+    arr = lambda T, v: (T * n)(*v)
+    stat_ptrs = arr(ctypes.c_void_p, [ctypes.cast(st, ctypes.c_void_p).value for st in sts])
+    check(lib.pcg_solve_concurrent(n, arr(ctypes.c_void_p, hs), arr(ctypes.c_int32, nr),
+                                   arr(ctypes.c_void_p, bs), arr(ctypes.c_void_p, us), arr(PcgOpts, opts),
+                                   stat_ptrs, arr(ctypes.c_void_p, [st.cuda_stream for st in streams])))
+    for st in streams:
+        cur.wait_stream(st)
+    return [(u, [v.as_dict() for v in st]) for u, st in keep]
+
+
 class FermionBatch:
     """Many independent systems (lattice, field x, right-hand sides b) solved
     in one persistent launch.  ``systems`` is a list of (params, x, b) with
