@@ -396,9 +396,9 @@ def cpu_baseline(p, golden_iters):
 # WRITE_SIZE runs of `bench.py --profile-roofline`, each scaled by the same
 # counter read for a copy kernel of known size.  Valid only while the
 # kernel sources hash to `source_sha1`; otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 443108645, "read_bytes": 233392933, "write_bytes": 209715712,
-           "fetch_scale": 1.99977, "write_scale": 1.00000,
-           "source_sha1": "2e176da867b18d83f76aa3fd91a606c492d78524",
+TRAFFIC = {"bytes_per_launch": 443106558, "read_bytes": 233390743, "write_bytes": 209715814,
+           "fetch_scale": 1.99976, "write_scale": 1.00000,
+           "source_sha1": "c1dc8bb5ca712456e385ea56f699533f711a0781",
            "profile": "profiles/mtm_f32_L64_Ltau400_r32_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
@@ -563,6 +563,31 @@ def main():
         log(f"concurrent: {concurrent}")
         for sk in sks:
             sk.close()
+    # Several independent systems of the workload's shape in the same launches
+    # (per-right-hand-side fields, fph_set_fields): K fields x0 + 0.01 k with
+    # Phi_k = M(x0 + 0.01 k)^T phi, solved at x + 0.01 k; one step = set the
+    # K fields + FP32-refined PCG of the K systems + their actions and forces.
+    multi = None
+    if not args.no_variants and R == 1:
+        multi = {}
+        for K in (4, 8):
+            sm = FermionSolver.from_params(p, max_rhs=K)
+            x0s = torch.stack([x0 + 0.01 * k for k in range(K)]).contiguous()
+            xs = torch.stack([x + 0.01 * k for k in range(K)]).contiguous()
+            sm.set_fields(x0s)
+            PhiK = sm.matvec(phi.expand(K, -1, -1).contiguous(), "MT")
+
+            def stepm():
+                sm.set_fields(xs, 1, a1=args.a1, a2=args.a2)
+                uK, stK = sm.solve(PhiK, tol=tol, prec="f32_refined", precond=True)
+                sm.action(PhiK, uK)
+                sm.force(uK)
+                return stK
+            tm, stm = time_steps(stepm, 2, 1, torch)
+            multi[f"fields_{K}"] = {"ms_per_step": tm * 1e3, "solves_per_s": K / tm,
+                                   "iters": [v["iters"] for v in stm], "status": [v["status"] for v in stm]}
+            log(f"multi-field K={K}: {multi[f'fields_{K}']}")
+            sm.close()
     if args.precond < 0 and variants:
         pre = variants["f32_refined_precond"]["ms"] < variants["f32_refined_plain"]["ms"]
     else:
@@ -702,6 +727,7 @@ def main():
         "variants": variants,
         "two_fields": two_fields,
         "concurrent_systems": concurrent,
+        "multi_field": multi,
         "hmc_trajectory": hmc,
         "measurements": meas,
         "cpu_baseline": cpu,

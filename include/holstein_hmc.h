@@ -165,6 +165,19 @@ int fph_get_lattice(fph_handle_t h, fph_lattice_t* lat, int32_t* max_rhs);
 int fph_set_field(fph_handle_t h, const double* x_dev, double a1, double a2,
                   void* stream);
 
+/* Per-right-hand-side fields, for independent systems of one lattice solved
+ * in the same launches (several Markov chains, say): x_dev holds nfields
+ * fields [nfields][Ltau][N] (FP64, device), and right-hand side r of the
+ * following calls uses field r / rhs_per_field (so at most
+ * nfields * rhs_per_field right-hand sides; FPH_E_NRHS otherwise).  Each
+ * field gets its own E, dbar, spectral bounds and Chebyshev tables as in
+ * fph_set_field, which switches back to one shared field.  fermion_force
+ * then writes one gradient per field: grad_dev[f] accumulates the
+ * right-hand sides of field f.  Not with pcg_solve variant 2.  nfields is
+ * 1..max_rhs.  Enqueue only. */
+int fph_set_fields(fph_handle_t h, int32_t nfields, int32_t rhs_per_field, const double* x_dev,
+                   double a1, double a2, void* stream);
+
 /* out = op(in) for nrhs right-hand sides sharing the current field
  * (Eq. M_def): op is FPH_OP_M, FPH_OP_MT or FPH_OP_MTM (fused M^T M; the
  * intermediate M v never leaves the chip).  prec FPH_F64: in/out are

@@ -87,6 +87,8 @@ EXPORTS = {
                                        ctypes.POINTER(ctypes.c_int32)]),
     "fph_set_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_void_p]),
+    "fph_set_fields": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
     "fermion_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,

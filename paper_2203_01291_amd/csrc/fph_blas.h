@@ -49,11 +49,15 @@ __global__ void k_set_field(long n, const double* __restrict__ x, double dtau,
 
 // dbar_i = (1/Ltau) sum_tau E[tau][i] (Eq. expnVbar) from the stored c4 E.
 // Block (64, 16): 64 sites, 16 interleaved groups of time slices, whose sums
-// are added in group order.  Launch: grid ceil(N/64).
+// are added in group order.  Launch: grid (ceil(N/64), fields); field y
+// reads E64 + y N Ltau and writes dbar + y N.
 __global__ void __launch_bounds__(1024)
 k_dbar(int N, int Ltau, const double* __restrict__ E64, double c4, double* __restrict__ dbar64,
        float* __restrict__ dbar32) {
   __shared__ double part[16][64];
+  E64 += (long)blockIdx.y * N * Ltau;
+  dbar64 += (long)blockIdx.y * N;
+  dbar32 += (long)blockIdx.y * N;
   const int i = blockIdx.x * 64 + threadIdx.x;
   double s = 0.0;
   if (i < N)

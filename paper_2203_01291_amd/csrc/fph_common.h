@@ -58,13 +58,20 @@ inline hipError_t allow_lds(const void* kern, size_t bytes) {
 // ----------------------------------------------------------------- geometry
 
 struct Geom {
-  int L;      // lattice side
-  int hL;     // L / 2
-  int N;      // L * L
-  int Q;      // N / 4 plaquettes per slice (per group)
-  int Ltau;   // time slices
-  long d;     // N * Ltau elements per right-hand side
+  int L;        // lattice side
+  int hL;       // L / 2
+  int N;        // L * L
+  int Q;        // N / 4 plaquettes per slice (per group)
+  int Ltau;     // time slices
+  long d;       // N * Ltau elements per right-hand side
+  long fs = 0;  // field stride: 0 when every right-hand side shares field 0,
+                // d when right-hand side r uses field r / rpf
+  int rpf = 1;  // right-hand sides per field
 };
+
+// Field of right-hand side r, and the offset of its E in the field buffers.
+FPH_DEVINL int field_of(const Geom& g, int r) { return g.fs ? r / g.rpf : 0; }
+FPH_DEVINL long field_off(const Geom& g, int r) { return (long)field_of(g, r) * g.fs; }
 
 // Site indices of even plaquette q: (corner, +x, +y, +x+y).
 FPH_DEVINL void even_sites(const Geom& g, int q, int s[4]) {

@@ -51,6 +51,7 @@ struct fph_handle_s {
   int device;
   double th, c4;  // tanh(dtau t), cosh(dtau t)^4 (operator kernels: C = c4 C', E stored as c4 E)
   bool have_field;
+  int nfields;  // 0: one field shared by every right-hand side; else fields set by fph_set_fields
   double a1, a2;
   // field
   double* E64;
@@ -178,8 +179,9 @@ hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, dou
     if (e != hipSuccess) return e;
   }
   const T* E = (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32);
-  hipLaunchKernelGGL(kern, dim3(nblk, MODE == 0 ? nrhs : 1), dim3(NT), lds, s, g, E,
-                     (T)h->th, 1, nrhs, v, out, coef);
+  const int ny = (MODE == 0) ? nrhs : (g.fs ? (nrhs + g.rpf - 1) / g.rpf : 1);
+  hipLaunchKernelGGL(kern, dim3(nblk, ny), dim3(NT), lds, s, g, E, (T)h->th, 1, nrhs, v, out,
+                     coef);
   return hipGetLastError();
 }
 
@@ -273,10 +275,11 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
 
 #define ALLOC(ptr, bytes)                                   \
   if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes));
-  ALLOC(h->E64, d * sizeof(double));
-  ALLOC(h->E32, d * sizeof(float));
-  ALLOC(h->dbar64, h->g.N * sizeof(double));
-  ALLOC(h->dbar32, h->g.N * sizeof(float));
+  // field tables for up to max_rhs fields (fph_set_fields)
+  ALLOC(h->E64, (size_t)max_rhs * d * sizeof(double));
+  ALLOC(h->E32, (size_t)max_rhs * d * sizeof(float));
+  ALLOC(h->dbar64, (size_t)max_rhs * h->g.N * sizeof(double));
+  ALLOC(h->dbar32, (size_t)max_rhs * h->g.N * sizeof(float));
   ALLOC(h->r64, vbytes(h, 8));
   ALLOC(h->rb64, vbytes(h, 8));
   ALLOC(h->pa64, vbytes(h, 8));
@@ -346,6 +349,9 @@ int fph_set_field(fph_handle_t h, const double* x_dev, double a1, double a2, voi
   const long d = h->g.d;
   h->a1 = a1 > 0.0 ? a1 : 1.0;
   h->a2 = a2 > 0.0 ? a2 : 1.0;
+  h->g.fs = 0;
+  h->g.rpf = 1;
+  h->nfields = 0;
   hipLaunchKernelGGL(k_set_field, dim3(elem_blocks(d)), dim3(256), 0, s, d, x_dev,
                      h->lat.dtau, h->lat.alpha, h->lat.mu, h->c4, h->E64, h->E32);
   FPH_CHECK(hipGetLastError());
@@ -357,11 +363,37 @@ int fph_set_field(fph_handle_t h, const double* x_dev, double a1, double a2, voi
   return FPH_OK;
 }
 
+int fph_set_fields(fph_handle_t h, int32_t nfields, int32_t rhs_per_field, const double* x_dev,
+                   double a1, double a2, void* stream) {
+  if (h == nullptr || x_dev == nullptr) return FPH_E_NULL;
+  if (!std::isfinite(a1) || !std::isfinite(a2) || rhs_per_field < 1) return FPH_E_ARG;
+  if (nfields < 1 || nfields > h->max_rhs) return FPH_E_NRHS;
+  hipStream_t s = (hipStream_t)stream;
+  const long d = h->g.d;
+  h->a1 = a1 > 0.0 ? a1 : 1.0;
+  h->a2 = a2 > 0.0 ? a2 : 1.0;
+  hipLaunchKernelGGL(k_set_field, dim3(elem_blocks((long)nfields * d)), dim3(256), 0, s,
+                     (long)nfields * d, x_dev, h->lat.dtau, h->lat.alpha, h->lat.mu, h->c4, h->E64,
+                     h->E32);
+  FPH_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_dbar, dim3((h->g.N + 63) / 64, nfields), dim3(64, 16), 0, s, h->g.N,
+                     h->g.Ltau, h->E64, h->c4, h->dbar64, h->dbar32);
+  FPH_CHECK(hipGetLastError());
+  for (int f = 0; f < nfields; ++f)
+    FPH_CHECK(pc_set_field(&h->pc, h->g, h->dbar64 + (long)f * h->g.N, h->lat.dtau, h->lat.t,
+                           h->a1, h->a2, s, f));
+  h->g.fs = d;
+  h->g.rpf = rhs_per_field;
+  h->nfields = nfields;
+  h->have_field = true;
+  return FPH_OK;
+}
+
 int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, const void* in_dev,
                    void* out_dev, void* stream) {
   if (h == nullptr || in_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
   if (!h->have_field) return FPH_E_NOFIELD;
-  if (nrhs < 1 || nrhs > 65535) return FPH_E_NRHS;
+  if (nrhs < 1 || nrhs > 65535 || (h->nfields && nrhs > h->nfields * h->g.rpf)) return FPH_E_NRHS;
   if (op < 0 || op > 2 || (prec != FPH_F64 && prec != FPH_F32)) return FPH_E_PREC;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
@@ -392,7 +424,7 @@ int fermion_force(fph_handle_t h, int32_t nrhs, const double* u_dev, double* gra
                   double scale, void* stream) {
   if (h == nullptr || u_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
   if (!h->have_field) return FPH_E_NOFIELD;
-  if (nrhs < 1) return FPH_E_NRHS;
+  if (nrhs < 1 || (h->nfields && nrhs > h->nfields * h->g.rpf)) return FPH_E_NRHS;
   if (!std::isfinite(scale)) return FPH_E_ARG;
   const double coef = -2.0 * h->lat.dtau * h->lat.alpha * scale;
   hipError_t e = launch_M<double, 1>(h, nrhs, u_dev, grad_dev, coef, (hipStream_t)stream);
@@ -419,7 +451,7 @@ int fph_precond_apply(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, co
                       void* out_dev, void* stream) {
   if (h == nullptr || in_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
   if (!h->have_field) return FPH_E_NOFIELD;
-  if (nrhs < 1 || nrhs > h->max_rhs) return FPH_E_NRHS;
+  if (nrhs < 1 || nrhs > h->max_rhs || (h->nfields && nrhs > h->nfields * h->g.rpf)) return FPH_E_NRHS;
   if (op < 0 || op > 2 || (prec != FPH_F64 && prec != FPH_F32)) return FPH_E_PREC;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
@@ -645,12 +677,12 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
                          const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats, void* stream) {
   if (h == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
   if (!h->have_field) return FPH_E_NOFIELD;
-  if (nrhs < 1 || nrhs > h->max_rhs) return FPH_E_NRHS;
+  if (nrhs < 1 || nrhs > h->max_rhs || (h->nfields && nrhs > h->nfields * h->g.rpf)) return FPH_E_NRHS;
   if (opts->prec != FPH_F64 && opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
   if (!(opts->tol >= 0.0) || opts->maxiter < 1 || opts->variant < 0 || opts->variant > 2)
     return FPH_E_ARG;
   if (opts->variant == 2 &&
-      (opts->prec != FPH_F32_REFINED || opts->use_precond != 0 || nrhs != 1))
+      (opts->prec != FPH_F32_REFINED || opts->use_precond != 0 || nrhs != 1 || h->nfields))
     return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   if (opts->variant == 2)
@@ -716,6 +748,7 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
   std::vector<int> outer(nrhs, 0);
   std::vector<int> iter_at_ru(nrhs, 0);
   std::vector<double> rr_iter(nrhs, 0.0);
+  std::vector<int> own_check(nrhs, 0);  // the rhs itself asked for this residual evaluation
   // FP32 residual-replacement interval per right-hand side: replace when
   // the FP32 residual has fallen by delta since the last replacement.
   // FP32 CG loses accuracy relative to its starting residual at a rate set
@@ -784,7 +817,10 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
     // Single-reduction CG keeps its residual in the buffer of the current
     // iteration parity; right-hand sides with another parity would need a
     // launch of their own, so each parity class is replaced separately.
-    for (int r = 0; r < nrhs; ++r) rr_iter[r] = h->st_host[r].rr;
+    for (int r = 0; r < nrhs; ++r) {
+      rr_iter[r] = h->st_host[r].rr;
+      own_check[r] = h->st_host[r].done;
+    }
     for (int par = 0; par < (cgcg ? 2 : 1); ++par) {
       bool any = false;
       for (int r = 0; r < nrhs; ++r) {
@@ -825,10 +861,13 @@ extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, doub
         st.done = 1;
       } else {
         st.done = 0;
-        // FP64: restart the directions from the true residual.  FP32: keep
-        // them (reliable update) unless the replaced residual is far from
-        // the iterated one.
-        if (!mixed || st.rr > 100.0 * rr_iter[r]) st.fresh = 1;
+        // FP64: restart the directions from the true residual when this
+        // rhs's own recursive residual said converged and the true one did
+        // not.  A rhs included only because another one stopped keeps its
+        // directions (restarting would throw its Krylov space away), as
+        // FP32 always does (reliable update), unless the replaced residual
+        // is far from the iterated one.
+        if ((!mixed && own_check[r]) || st.rr > 100.0 * rr_iter[r]) st.fresh = 1;
         if (mixed && st.rr > 4.0 * rr_iter[r]) delta[r] = std::min(0.5, std::sqrt(delta[r]));
         st.ru_thresh = mixed ? delta[r] * delta[r] * st.rr : 0.0;
       }

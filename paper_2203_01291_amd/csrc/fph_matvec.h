@@ -655,6 +655,7 @@ k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi, 
   const int nrhs = gridDim.x / nblk;
   const int r = logical % nrhs;
   const int bx = logical / nrhs;
+  E += field_off(g, r);
   auto hook = [&]() -> bool {
     // Plain applies (no partial sums) never carry solver state.
     if constexpr (Epi::kKind == P_NONE) return true;
@@ -702,8 +703,9 @@ k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi, 
 // out = M v (mode 0), or the force (mode 1):
 //   grad_tau += scale * sum_r (-2 dtau alpha) (M u)_tau * y_tau,
 //   y_tau = E_tau * (C u~_{tau-1}), (M u)_tau = u_tau - y_tau   (Eq. dSF_dx)
-// Launch: grid (ceil(Ltau / S / per), nrhs or 1).  Each (sub-)chunk of the
-// block handles `per` slices.  LDS: S * N elements.
+// Launch: grid (ceil(Ltau / S / per), nrhs in mode 0; in mode 1 the number
+// of fields, block y summing the right-hand sides of field y into grad[y]).
+// Each (sub-)chunk of the block handles `per` slices.  LDS: S * N elements.
 template <typename T, int NT, int MAXSLOT, int MODE>
 __global__ void __launch_bounds__(NT)
 k_apply_M(Geom g, const T* __restrict__ E, T th, int per, int nrhs,
@@ -724,8 +726,19 @@ k_apply_M(Geom g, const T* __restrict__ E, T th, int per, int nrhs,
   }
   T* buf = reinterpret_cast<T*>(smem_raw) + (long)(sub < S ? sub : 0) * g.N;
   const int tau_first = (blockIdx.x * S + sub) * per;
-  const int rb = (MODE == 0) ? blockIdx.y : 0;
-  const int re = (MODE == 0) ? blockIdx.y + 1 : nrhs;
+  int rb, re;
+  if (MODE == 0) {
+    rb = blockIdx.y;
+    re = rb + 1;
+  } else if (g.fs) {
+    rb = blockIdx.y * g.rpf;
+    re = min(rb + g.rpf, nrhs);
+    out += (long)blockIdx.y * g.d;
+  } else {
+    rb = 0;
+    re = nrhs;
+  }
+  E += field_off(g, rb);
 
   for (int j = 0; j < per; ++j) {
     const int tau = tau_first + j;
@@ -829,6 +842,7 @@ k_apply_MT(Geom g, const T* __restrict__ E, T th, int per,
   T* buf = reinterpret_cast<T*>(smem_raw) + (long)(sub < S ? sub : 0) * g.N;
   const int tau_first = (blockIdx.x * S + sub) * per;
   const long base = (long)blockIdx.y * g.d;
+  E += field_off(g, blockIdx.y);
 
   for (int j = 0; j < per; ++j) {
     const int tau = tau_first + j;

@@ -846,6 +846,11 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   // Everything that does not depend on the solver state is loaded before
   // it is read: the order N_P, the first NT coefficients (the table row has
   // kNPMax entries, so the load needs no bound), the block's input and dbar.
+  const int f = field_of(g, r);
+  info += f;
+  np += (long)f * g.Ltau;
+  coef += (long)f * H * kNPMax;
+  dbar += (long)f * g.N;
   const int NP = np[2 * k];
   const T sA = (T)info->s, cA = (T)info->c;
   const T2 c_first = coef[(long)k * kNPMax + threadIdx.x];
@@ -910,10 +915,11 @@ inline hipError_t pc_create(PcTables* pc, const Geom& g, int max_rhs) {
   PCALLOC(pc->tw32, H * sizeof(float2));
   PCALLOC(pc->W32, H * sizeof(float2));
   PCALLOC(pc->F32, nF * sizeof(float2));
-  PCALLOC(pc->info, sizeof(PcInfo));
-  PCALLOC(pc->np, g.Ltau * sizeof(int));
-  PCALLOC(pc->coef64, (size_t)H * kNPMax * sizeof(double2));
-  PCALLOC(pc->coef32, (size_t)H * kNPMax * sizeof(float2));
+  // one set of series tables per field (up to max_rhs fields)
+  PCALLOC(pc->info, (size_t)max_rhs * sizeof(PcInfo));
+  PCALLOC(pc->np, (size_t)max_rhs * g.Ltau * sizeof(int));
+  PCALLOC(pc->coef64, (size_t)max_rhs * H * kNPMax * sizeof(double2));
+  PCALLOC(pc->coef32, (size_t)max_rhs * H * kNPMax * sizeof(float2));
   PCALLOC(pc->Z, (size_t)max_rhs * H * g.N * sizeof(double2));
   PCALLOC(pc->Z2, (size_t)max_rhs * H * g.N * sizeof(double2));
 #undef PCALLOC
@@ -931,14 +937,18 @@ inline void pc_destroy(PcTables* pc) {
   std::memset(pc, 0, sizeof(*pc));
 }
 
+// Series tables of field f from its dbar (dbar64 points at that field's N values).
 inline hipError_t pc_set_field(PcTables* pc, const Geom& g, const double* dbar64, double dtau,
-                               double t, double a1, double a2, hipStream_t s) {
+                               double t, double a1, double a2, hipStream_t s, int f = 0) {
+  PcInfo* info = pc->info + f;
+  int* np = pc->np + (long)f * g.Ltau;
   hipLaunchKernelGGL(k_pc_bounds, dim3(1), dim3(256), 0, s, g.N, g.Ltau, dbar64, dtau, t, a1, a2,
-                     pc->info, pc->np);
+                     info, np);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pc_coef, dim3(pc->H), dim3(256), 0, s, g.Ltau, pc->info, pc->np,
-                     pc->coef64, pc->coef32);
+  hipLaunchKernelGGL(k_pc_coef, dim3(pc->H), dim3(256), 0, s, g.Ltau, (const PcInfo*)info,
+                     (const int*)np, pc->coef64 + (long)f * pc->H * kNPMax,
+                     pc->coef32 + (long)f * pc->H * kNPMax);
   return hipGetLastError();
 }
 

@@ -72,7 +72,17 @@ class FermionSolver:
         if self._vec(x) != 1:
             raise ValueError("x must hold exactly N*Ltau values")
         self._x = x
+        self._nfields = 0
         check(self.lib.fph_set_field(self.h, _ptr(x), float(a1), float(a2), _stream()))
+
+    def set_fields(self, xs, rhs_per_field=1, a1=1.0, a2=1.0):
+        """Per-right-hand-side fields: xs [nfields, Ltau, N]; right-hand side r of later calls
+        uses field r // rhs_per_field.  force() then returns one gradient per field."""
+        nf = self._vec(xs)
+        self._x = xs
+        self._nfields = nf
+        check(self.lib.fph_set_fields(self.h, nf, int(rhs_per_field), _ptr(xs), float(a1), float(a2),
+                                      _stream()))
 
     def matvec(self, v, op="MTM", out=None):
         """out = op(v) for op in {'M', 'MT', 'MTM'}; float64 or float32."""
@@ -116,7 +126,9 @@ class FermionSolver:
     def force(self, u, grad=None, scale=1.0):
         """grad += scale * sum_r dS_F/dx for solutions u (float64)."""
         nrhs = self._vec(u)
-        grad = torch.zeros(self.Ltau, self.N, dtype=torch.float64, device=u.device) if grad is None else grad
+        nf = getattr(self, "_nfields", 0) or 1
+        shape = (self.Ltau, self.N) if nf == 1 and not getattr(self, "_nfields", 0) else (nf, self.Ltau, self.N)
+        grad = torch.zeros(*shape, dtype=torch.float64, device=u.device) if grad is None else grad
         check(self.lib.fermion_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), _stream()))
         return grad
 
