@@ -188,7 +188,7 @@ def bench_batched(torch, dev, log):
     return res
 
 
-def bench_hmc(torch, dev, p, a1, a2, log, nchains=4):
+def bench_hmc(torch, dev, p, a1, a2, log, nchains=4, batch_chains=8):
     """One HMC trial update (Algorithm 1) on the workload's lattice with the
     paper's settings: dt = 1/(100 omega0), Nt = 100 steps of nt = 10 bosonic
     sub-steps, Fourier acceleration with m_reg = omega0, two pseudofermion
@@ -277,6 +277,28 @@ def bench_hmc(torch, dev, p, a1, a2, log, nchains=4):
         for sk, hk in ctx:
             hk.close()
             sk.close()
+    # The same chains in the same launches: chain k's pseudofermions are
+    # right-hand sides of its own field in every solve.
+    batched = None
+    if batch_chains > 1:
+        nb = batch_chains
+        sb = FermionSolver.from_params(p, max_rhs=nb * hp.nfields)
+        hb = PhononHMC(sb, hp.omega0, hp.m_reg, hp.dt, Nt=hp.Nt, nt=hp.nt, nfields=hp.nfields, a1=a1,
+                       a2=a2, force_tol=hp.tol_force, action_tol=hp.tol_action, nchains=nb)
+        Rfb = Rf.unsqueeze(0).expand(nb, *Rf.shape).contiguous()
+        Rmb = Rm.unsqueeze(0).expand(nb, *Rm.shape).contiguous()
+        xb = x0.unsqueeze(0).expand(nb, *x0.shape).contiguous()
+        hb.trajectories(xb.clone(), Rfb, Rmb, [r] * nb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stb = hb.trajectories(xb, Rfb, Rmb, [r] * nb)
+        torch.cuda.synchronize()
+        dtb = time.perf_counter() - t0
+        batched = {"chains": nb, "seconds": dtb, "trajectories_per_s": nb / dtb,
+                   "speedup_vs_one": (nb / dtb) * dt, "cg_iters": [v["cg_iters"] for v in stb],
+                   "dH": [v["H_f"] - v["H_i"] for v in stb], "status": [v["status"] for v in stb]}
+        hb.close()
+        sb.close()
     res = {
         "workload": f"{p.name}: one HMC update, dt={hp.dt:g}, Nt={hp.Nt}, nt={hp.nt}, "
                     f"m_reg={hp.m_reg}, {hp.nfields} fields, FP32-refined PCG (a1={a1}, a2={a2}) "
@@ -288,6 +310,7 @@ def bench_hmc(torch, dev, p, a1, a2, log, nchains=4):
         "status": st["status"], "boson_step_us": boson_us,
         "boson_fraction": boson_us * 1e-6 * hp.Nt / dt,
         "concurrent_chains": chains,
+        "chains_per_launch": batched,
         "lambda_action": {"ms_per_trajectory": dtl * 1e3, "cg_iters": stl["cg_iters"],
                           "dH": stl["H_f"] - stl["H_i"], "status": stl["status"],
                           "global_updates": moves},

@@ -313,6 +313,12 @@ typedef struct {
                                   force tolerances they bias H_f - H_i and the
                                   update is reversible only to the tolerance  */
   int32_t lambda_action;       /* 0: the action S' (A = M); 1: S (A = M Lambda) */
+  int32_t nchains;             /* independent chains advanced together by
+                                  hmc_trajectories (0 or 1: one chain); they
+                                  share every launch through per-right-hand-side
+                                  fields (fph_set_fields), so the solver handle
+                                  needs max_rhs >= nchains * nfields           */
+  int32_t pad;
   fph_pcg_opts_t force_solve;  /* solves for the force (paper: tol 1e-5)        */
   fph_pcg_opts_t action_solve; /* solve for S_F at the end (paper: tol 1e-10)   */
 } fph_hmc_opts_t;
@@ -369,7 +375,8 @@ int hmc_mass_apply(fph_hmc_t hh, int32_t op, int32_t nvec, const double* in_dev,
  * circulants over imaginary time.  Enqueue only. */
 int hmc_boson_steps(fph_hmc_t hh, double* x_dev, double* p_dev, void* stream);
 
-/* One HMC trial update (Algorithm 1) of the field x_dev [Ltau][N]:
+/* One HMC trial update (Algorithm 1) of the field x_dev [Ltau][N] (a context
+ * with one chain; FPH_E_ARG otherwise):
  *   Phi_sigma = A(x_i)^T R_sigma (R_fields_dev [nfields][Ltau][N]);
  *   p = sqrt(Mass) R (R_mom_dev [Ltau][N]);
  *   Nt steps of: p -= dt/2 dS_F/dx; nt bosonic sub-steps; p -= dt/2 dS_F/dx,
@@ -385,6 +392,20 @@ int hmc_boson_steps(fph_hmc_t hh, double* x_dev, double* p_dev, void* stream);
 int hmc_trajectory(fph_hmc_t hh, double* x_dev, const double* R_fields_dev,
                    const double* R_mom_dev, double r_uniform, double* p_out_dev,
                    fph_hmc_stats_t* stats_host, void* stream);
+
+/* One HMC trial update of each of the context's nchains independent chains
+ * at once (Algorithm 1 per chain, as hmc_trajectory): x_dev [nchains][Ltau][N],
+ * R_fields_dev [nchains][nfields][Ltau][N], R_mom_dev [nchains][Ltau][N],
+ * r_uniform_host [nchains], p_out_dev [nchains][Ltau][N] (may be NULL),
+ * stats_host [nchains] (may be NULL).  Chain k's fields live in the solver
+ * as field k of fph_set_fields, its pseudofermions as right-hand sides
+ * k*nfields .. k*nfields + nfields - 1; energies and the Metropolis test are
+ * per chain, and each accepted chain's x_f replaces its slice of x_dev.
+ * The solves of all chains run in the same launches and stop together per
+ * right-hand side.  Blocks until done. */
+int hmc_trajectories(fph_hmc_t hh, double* x_dev, const double* R_fields_dev,
+                     const double* R_mom_dev, const double* r_uniform_host, double* p_out_dev,
+                     fph_hmc_stats_t* stats_host, void* stream);
 
 typedef enum {
   FPH_LAMBDA = 0,        /* Lambda      (Eq. Lambda_def)  */
@@ -428,7 +449,8 @@ typedef struct {
  * (opts.action_solve, zero guess), and x' is accepted if
  * r_uniform < exp(-(S(x') - S(x))).  On acceptance x_dev receives x'; a
  * non-converged or non-finite solve rejects.  On return the solver handle's
- * field is that of x_dev.  Errors: FPH_E_ARG for a bad kind or site index.
+ * field is that of x_dev.  Errors: FPH_E_ARG for a bad kind or site index,
+ * or a context with more than one chain.
  * Blocks until done. */
 int hmc_global_update(fph_hmc_t hh, int32_t kind, int32_t i, int32_t j, double* x_dev,
                       const double* R_fields_dev, double r_uniform, fph_update_stats_t* stats_host,

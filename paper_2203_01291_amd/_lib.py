@@ -48,6 +48,7 @@ class HmcOpts(ctypes.Structure):
                 ("Nt", ctypes.c_int32), ("nt", ctypes.c_int32), ("nfields", ctypes.c_int32),
                 ("a1", ctypes.c_double), ("a2", ctypes.c_double),
                 ("guess", ctypes.c_int32), ("lambda_action", ctypes.c_int32),
+                ("nchains", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("force_solve", PcgOpts), ("action_solve", PcgOpts)]
 
 
@@ -122,6 +123,9 @@ EXPORTS = {
     "hmc_trajectory": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                       ctypes.POINTER(HmcStats), ctypes.c_void_p]),
+    "hmc_trajectories": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                        ctypes.POINTER(HmcStats), ctypes.c_void_p]),
     "lambda_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lambda_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,

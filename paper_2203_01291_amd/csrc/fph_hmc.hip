@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "../../include/holstein_hmc.h"
 #include "fph_internal.h"
@@ -263,12 +264,14 @@ k_extrapolate(long n, double* __restrict__ u, double* __restrict__ uold) {
 // s(t) = +1 for t = 0 else -1, ts = tau + 1 if dsh = +1 else tau, a = dtau alpha:
 //   Lambda:      dsh = +1, e = +1      Lambda^{-1}:  dsh = -1, e = -1
 //   Lambda^T:    dsh = -1, e = +1      Lambda^{-T}:  dsh = +1, e = -1
-// (slices mod Ltau).  Launch: grid (blocks, nvec), block 256.
+// (slices mod Ltau).  Vector v uses field x + (v / vpx) d (vpx = vectors per
+// field; 0: one field for all).  Launch: grid (blocks, nvec), block 256.
 __global__ void __launch_bounds__(256)
-k_lambda(int N, int Ltau, long d, const double* __restrict__ x, double a, int dsh, double e,
+k_lambda(int N, int Ltau, long d, const double* __restrict__ x, int vpx, double a, int dsh, double e,
          const double* __restrict__ in, double* __restrict__ out) {
   const double* iv = in + (long)blockIdx.y * d;
   double* ov = out + (long)blockIdx.y * d;
+  if (vpx > 0) x += (long)(blockIdx.y / vpx) * d;
   for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
     const int tau = (int)(k / N);
     const int i = (int)(k - (long)tau * N);
@@ -282,9 +285,14 @@ k_lambda(int N, int Ltau, long d, const double* __restrict__ x, double a, int ds
 
 // grad[tau][i] += coef * sum_r b_r[tau-1][i] u_r[tau-1][i] (slice tau-1 mod Ltau): the
 // Lambda term of the force, coef = -dtau alpha times the caller's scale.
+// Block row y sums right-hand sides y*nrhs .. y*nrhs + nrhs - 1 into grad + y d
+// (one row per field).  Launch: grid (blocks, fields), block 256.
 __global__ void __launch_bounds__(256)
 k_lambda_force(int N, int Ltau, long d, int nrhs, const double* __restrict__ b,
                const double* __restrict__ u, double coef, double* __restrict__ grad) {
+  b += (long)blockIdx.y * nrhs * d;
+  u += (long)blockIdx.y * nrhs * d;
+  grad += (long)blockIdx.y * d;
   for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) {
     const long km = (k >= N) ? k - N : k - N + d;
     double acc = 0.0;
@@ -327,12 +335,13 @@ struct fph_hmc_s {
   long d;
   int ts, off;  // circulant table stride and index offset
   fph_hmc_opts_t o;
+  int K;         // chains (independent systems sharing the launches)
   double* tab;   // [kNTab][ts]
   double* vals;  // [kNTab][Ltau]
   double* cst;   // [2]
   double *xi, *xa, *xb, *pa, *pb, *tmp, *Phi, *u, *uold, *bvec;
   double* part;  // [2][kRedBlocks]
-  double* en;    // [kEn]
+  double* en;    // [K][kEn]
   double* en_host;
 };
 
@@ -347,8 +356,8 @@ hipError_t circ1(const fph_hmc_s* c, int k, int nvec, const double* in, double* 
 }
 
 hipError_t step_map(const fph_hmc_s* c, const double* x, const double* p, double* xo, double* po,
-                    hipStream_t s) {
-  dim3 grid((c->N + 63) / 64, (c->Ltau + kRows - 1) / kRows, 1);
+                    hipStream_t s, int nvec = 1) {
+  dim3 grid((c->N + 63) / 64, (c->Ltau + kRows - 1) / kRows, nvec);
   hipLaunchKernelGGL((k_tau_circ<2, 2>), grid, dim3(64), 0, s, c->N, c->Ltau, c->d, c->ts, c->off,
                      (const double*)c->tab, (const double*)c->cst, x, p, xo, po);
   return hipGetLastError();
@@ -384,19 +393,20 @@ hipError_t kinetic_into(const fph_hmc_s* c, const double* p, double* out, hipStr
 }
 
 hipError_t lambda_into(const fph_hmc_s* c, int op, int nvec, const double* x, const double* in,
-                       double* out, hipStream_t s) {
+                       double* out, hipStream_t s, int vpx = 0) {
   static const int dsh[4] = {+1, -1, -1, +1};
   static const double ex[4] = {+1.0, -1.0, +1.0, -1.0};
   dim3 grid(grid_for(c->d), nvec);
-  hipLaunchKernelGGL(k_lambda, grid, dim3(256), 0, s, c->N, c->Ltau, c->d, x,
+  hipLaunchKernelGGL(k_lambda, grid, dim3(256), 0, s, c->N, c->Ltau, c->d, x, vpx,
                      c->lat.dtau * c->lat.alpha, dsh[op], ex[op], in, out);
   return hipGetLastError();
 }
 
+// nfld fields of nrhs right-hand sides each; grad holds nfld gradients.
 hipError_t lambda_force_into(const fph_hmc_s* c, int nrhs, const double* b, const double* u,
-                             double* grad, double scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_lambda_force, dim3(grid_for(c->d)), dim3(256), 0, s, c->N, c->Ltau, c->d,
-                     nrhs, b, u, -c->lat.dtau * c->lat.alpha * scale, grad);
+                             double* grad, double scale, hipStream_t s, int nfld = 1) {
+  hipLaunchKernelGGL(k_lambda_force, dim3(grid_for(c->d), nfld), dim3(256), 0, s, c->N, c->Ltau,
+                     c->d, nrhs, b, u, -c->lat.dtau * c->lat.alpha * scale, grad);
   return hipGetLastError();
 }
 
@@ -439,9 +449,11 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   if (!(std::isfinite(o->omega0) && o->omega0 > 0.0) || !(std::isfinite(o->dt) && o->dt > 0.0) ||
       std::isnan(o->m_reg) || o->Nt < 1 || o->nt < 1 || !std::isfinite(o->a1) ||
       !std::isfinite(o->a2) || o->guess < 0 || o->guess > 2 || o->lambda_action < 0 ||
-      o->lambda_action > 1 || !opts_ok(o->force_solve) || !opts_ok(o->action_solve))
+      o->lambda_action > 1 || !opts_ok(o->force_solve) || !opts_ok(o->action_solve) ||
+      o->nchains < 0 || o->nchains > 64)
     return FPH_E_ARG;
-  if (o->nfields < 1 || o->nfields > max_rhs) return FPH_E_NRHS;
+  const int K = o->nchains > 0 ? o->nchains : 1;
+  if (o->nfields < 1 || (long)o->nfields * K > max_rhs || K > max_rhs) return FPH_E_NRHS;
   fph_hmc_s* c = new fph_hmc_s();
   std::memset(c, 0, sizeof(*c));
   c->h = h;
@@ -453,8 +465,9 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   c->off = lat.Ltau + kRows;
   c->ts = 2 * c->off;
   c->o = *o;
+  c->K = K;
   if (!std::isfinite(c->o.m_reg)) c->o.m_reg = -1.0;
-  const long d = c->d;
+  const long d = c->d * K;  // per-chain vectors, chain-major
   const int nf = o->nfields;
   hipError_t e = hipSuccess;
 #define ALLOC(ptr, n)                                        \
@@ -473,9 +486,10 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   if (o->guess == 2) ALLOC(c->uold, nf * d);
   ALLOC(c->bvec, nf * d);
   ALLOC(c->part, 2 * kRedBlocks);
-  ALLOC(c->en, kEn);
+  ALLOC(c->en, (long)kEn * K);
 #undef ALLOC
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->en_host, kEn * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->en_host, (size_t)kEn * K * sizeof(double), hipHostMallocDefault);
   hipStream_t s = (hipStream_t)stream;
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_hmc_modes, dim3((c->Ltau + 63) / 64), dim3(64), 0, s, c->Ltau, lat.dtau,
@@ -534,123 +548,174 @@ int hmc_boson_steps(fph_hmc_t c, double* x_dev, double* p_dev, void* stream) {
   return FPH_OK;
 }
 
-int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const double* R_mom_dev,
-                   double r_uniform, double* p_out_dev, fph_hmc_stats_t* st, void* stream) {
-  if (c == nullptr || x_dev == nullptr || R_fields_dev == nullptr || R_mom_dev == nullptr)
-    return FPH_E_NULL;
-  if (!(r_uniform >= 0.0 && r_uniform <= 1.0)) return FPH_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 for the context's K chains at once: chain k's field is
+// x_dev + k d, its pseudofermions are right-hand sides k nf .. k nf + nf - 1
+// of every solve (per-right-hand-side fields when K > 1), its momentum
+// p + k d; energies and the Metropolis test are per chain.
+int traj_impl(fph_hmc_s* c, double* x_dev, const double* R_fields_dev, const double* R_mom_dev,
+              const double* r_uniform, double* p_out_dev, fph_hmc_stats_t* st, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const fph_hmc_opts_t& o = c->o;
+  const int K = c->K;
   const long d = c->d;
   const int nf = o.nfields;
-  fph_hmc_stats_t S;
-  std::memset(&S, 0, sizeof(S));
-  fph_pcg_stats_t ps[64];
-  if (nf > 64) return FPH_E_NRHS;
-
+  const int NR = nf * K;
   const bool lam = o.lambda_action != 0;
+  std::vector<fph_hmc_stats_t> S(K);
+  for (auto& v : S) std::memset(&v, 0, sizeof(v));
+  std::vector<fph_pcg_stats_t> ps(NR);
+  int nsolves = 0;
+
+  auto set_fields = [&](const double* x) -> int {
+    return K == 1 ? fph_set_field(c->h, x, o.a1, o.a2, stream)
+                  : fph_set_fields(c->h, K, nf, x, o.a1, o.a2, stream);
+  };
   const double* rhs = lam ? c->bvec : c->Phi;  // b = Lambda(x)^{-T} Phi, or Phi
   auto solve = [&](const fph_pcg_opts_t& so, int zero_guess) -> int {
     fph_pcg_opts_t oo = so;
     oo.zero_guess = zero_guess;
-    int rc = pcg_solve(c->h, nf, rhs, c->u, &oo, ps, stream);
+    int rc = pcg_solve(c->h, NR, rhs, c->u, &oo, ps.data(), stream);
     if (rc != FPH_OK) return rc;
-    S.solves++;
-    for (int r = 0; r < nf; ++r) {
-      S.status |= ps[r].status;
-      S.cg_iters += ps[r].iters;
-      S.matvecs += ps[r].matvecs;
+    ++nsolves;
+    for (int r = 0; r < NR; ++r) {
+      fph_hmc_stats_t& v = S[r / nf];
+      v.status |= ps[r].status;
+      v.cg_iters += ps[r].iters;
+      v.matvecs += ps[r].matvecs;
     }
     return FPH_OK;
   };
-
-  // The fermion force at the current field c->xa into p (scale per field
+  // The fermion force at the current fields c->xa into p (scale per field
   // times 1/2: S_F = 1/2 sum_sigma b_sigma . u_sigma).
   auto kick = [&](double scale, int zero_guess) -> int {
     if (lam) {
-      hipError_t e = lambda_into(c, 3, nf, c->xa, c->Phi, c->bvec, s);
+      hipError_t e = lambda_into(c, 3, NR, c->xa, c->Phi, c->bvec, s, nf);
       if (e != hipSuccess) return fph::record_hip_error(e);
     }
     int rc = solve(o.force_solve, zero_guess);
     if (rc != FPH_OK) return rc;
-    rc = fermion_force(c->h, nf, c->u, c->pa, 0.5 * scale, stream);
+    rc = fermion_force(c->h, NR, c->u, c->pa, 0.5 * scale, stream);
     if (rc != FPH_OK || !lam) return rc;
-    hipError_t e = lambda_force_into(c, nf, c->bvec, c->u, c->pa, 0.5 * scale, s);
+    hipError_t e = lambda_force_into(c, nf, c->bvec, c->u, c->pa, 0.5 * scale, s, K);
     return e == hipSuccess ? FPH_OK : fph::record_hip_error(e);
+  };
+  auto energies = [&](int sb_slot, int lin_slot, int k_slot) -> hipError_t {
+    hipError_t e = circ1(c, TAB_MINV, K, c->pa, c->tmp, s);
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      double* en = c->en + (long)k * kEn;
+      e = sb_into(c, c->xa + k * d, en + sb_slot, en + lin_slot, s);
+      if (e == hipSuccess) e = dot_into(c, d, c->pa + k * d, c->tmp + k * d, 0.5, en + k_slot, s);
+    }
+    return e;
   };
 
   // Initial state: x_i, Phi_sigma = A(x_i)^T R_sigma, p = sqrt(Mass) R.
-  HMC_CHECK(hipMemcpyAsync(c->xi, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
-  HMC_CHECK(hipMemcpyAsync(c->xa, x_dev, d * 8, hipMemcpyDeviceToDevice, s));
-  HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
+  HMC_CHECK(hipMemcpyAsync(c->xi, x_dev, K * d * 8, hipMemcpyDeviceToDevice, s));
+  HMC_CHECK(hipMemcpyAsync(c->xa, x_dev, K * d * 8, hipMemcpyDeviceToDevice, s));
+  HMC_CALL(set_fields(c->xa));
   if (lam) {
-    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->bvec, stream));
-    HMC_CHECK(lambda_into(c, 2, nf, c->xa, c->bvec, c->Phi, s));
+    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, NR, R_fields_dev, c->bvec, stream));
+    HMC_CHECK(lambda_into(c, 2, NR, c->xa, c->bvec, c->Phi, s, nf));
   } else {
-    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->Phi, stream));
+    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, NR, R_fields_dev, c->Phi, stream));
   }
-  HMC_CHECK(circ1(c, TAB_MSQRT, 1, R_mom_dev, c->pa, s));
-  HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_I, c->en + EN_LIN_I, s));
-  HMC_CHECK(dot_into(c, (long)nf * d, R_fields_dev, R_fields_dev, 0.5, c->en + EN_R2, s));
-  HMC_CHECK(kinetic_into(c, c->pa, c->en + EN_K_I, s));
+  HMC_CHECK(circ1(c, TAB_MSQRT, K, R_mom_dev, c->pa, s));
+  for (int k = 0; k < K; ++k)
+    HMC_CHECK(dot_into(c, (long)nf * d, R_fields_dev + (long)k * nf * d, R_fields_dev + (long)k * nf * d,
+                       0.5, c->en + (long)k * kEn + EN_R2, s));
+  HMC_CHECK(energies(EN_SB_I, EN_LIN_I, EN_K_I));
 
   // Leapfrog with time-step splitting; the two half kicks between steps
   // share one force evaluation (same x) and are applied as one kick of dt.
-  HMC_CHECK(hipMemsetAsync(c->u, 0, (size_t)nf * d * 8, s));
+  HMC_CHECK(hipMemsetAsync(c->u, 0, (size_t)NR * d * 8, s));
   HMC_CALL(kick(-0.5 * o.dt, 1));
   for (int t = 0; t < o.Nt; ++t) {
-    HMC_CHECK(step_map(c, c->xa, c->pa, c->xb, c->pb, s));
+    HMC_CHECK(step_map(c, c->xa, c->pa, c->xb, c->pb, s, K));
     std::swap(c->xa, c->xb);
     std::swap(c->pa, c->pb);
-    HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
+    HMC_CALL(set_fields(c->xa));
     if (o.guess == 2) {
       if (t == 0) {
-        HMC_CHECK(hipMemcpyAsync(c->uold, c->u, (size_t)nf * d * 8, hipMemcpyDeviceToDevice, s));
+        HMC_CHECK(hipMemcpyAsync(c->uold, c->u, (size_t)NR * d * 8, hipMemcpyDeviceToDevice, s));
       } else {
-        hipLaunchKernelGGL(k_extrapolate, dim3(grid_for((long)nf * d)), dim3(256), 0, s,
-                           (long)nf * d, c->u, c->uold);
+        hipLaunchKernelGGL(k_extrapolate, dim3(grid_for((long)NR * d)), dim3(256), 0, s,
+                           (long)NR * d, c->u, c->uold);
         HMC_CHECK(hipGetLastError());
       }
     }
     HMC_CALL(kick((t + 1 < o.Nt ? -1.0 : -0.5) * o.dt, o.guess == 0 ? 1 : 0));
   }
-  const int force_status = S.status;
+  std::vector<int> force_status(K);
+  for (int k = 0; k < K; ++k) force_status[k] = S[k].status;
 
   // Final energies; S_F(x_f) from a tight solve started at the last solution
   // (b of x_f is already in place).
   HMC_CALL(solve(o.action_solve, 0));
-  double sf_f = 0.0;
-  for (int r = 0; r < nf; ++r) sf_f += 0.5 * ps[r].action;
-  bool action_ok = true;
-  for (int r = 0; r < nf; ++r) action_ok = action_ok && (ps[r].status & FPH_ST_CONVERGED);
-  HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_F, c->en + EN_LIN_F, s));
-  HMC_CHECK(kinetic_into(c, c->pa, c->en + EN_K_F, s));
-  HMC_CHECK(hipMemcpyAsync(c->en_host, c->en, kEn * 8, hipMemcpyDeviceToHost, s));
-  HMC_CHECK(hipStreamSynchronize(s));
-  const double* en = c->en_host;
-  S.SB_i = en[EN_SB_I] + (lam ? 0.0 : en[EN_LIN_I]);
-  S.SB_f = en[EN_SB_F] + (lam ? 0.0 : en[EN_LIN_F]);
-  S.SF_i = en[EN_R2];
-  S.SF_f = sf_f;
-  S.K_i = en[EN_K_I];
-  S.K_f = en[EN_K_F];
-  S.H_i = S.SB_i + S.SF_i + S.K_i;
-  S.H_f = S.SB_f + S.SF_f + S.K_f;
-  const double dH = S.H_f - S.H_i;
-  const bool bad = !std::isfinite(dH) || ((S.status | force_status) & (FPH_ST_BREAKDOWN | FPH_ST_NONFINITE)) ||
-                   !action_ok;
-  S.accept_prob = bad ? 0.0 : (dH <= 0.0 ? 1.0 : std::exp(-dH));
-  S.accepted = (!bad && r_uniform < S.accept_prob) ? 1 : 0;
-
-  if (p_out_dev) HMC_CHECK(hipMemcpyAsync(p_out_dev, c->pa, d * 8, hipMemcpyDeviceToDevice, s));
-  if (S.accepted) {
-    HMC_CHECK(hipMemcpyAsync(x_dev, c->xa, d * 8, hipMemcpyDeviceToDevice, s));
-  } else {
-    HMC_CALL(fph_set_field(c->h, c->xi, o.a1, o.a2, stream));
+  std::vector<double> sf_f(K, 0.0);
+  std::vector<int> action_ok(K, 1);
+  for (int r = 0; r < NR; ++r) {
+    sf_f[r / nf] += 0.5 * ps[r].action;
+    if (!(ps[r].status & FPH_ST_CONVERGED)) action_ok[r / nf] = 0;
   }
+  HMC_CHECK(energies(EN_SB_F, EN_LIN_F, EN_K_F));
+  HMC_CHECK(hipMemcpyAsync(c->en_host, c->en, (size_t)kEn * K * 8, hipMemcpyDeviceToHost, s));
   HMC_CHECK(hipStreamSynchronize(s));
-  if (st) *st = S;
+  bool any_rejected = false;
+  for (int k = 0; k < K; ++k) {
+    const double* en = c->en_host + (long)k * kEn;
+    fph_hmc_stats_t& v = S[k];
+    v.solves = nsolves;
+    v.SB_i = en[EN_SB_I] + (lam ? 0.0 : en[EN_LIN_I]);
+    v.SB_f = en[EN_SB_F] + (lam ? 0.0 : en[EN_LIN_F]);
+    v.SF_i = en[EN_R2];
+    v.SF_f = sf_f[k];
+    v.K_i = en[EN_K_I];
+    v.K_f = en[EN_K_F];
+    v.H_i = v.SB_i + v.SF_i + v.K_i;
+    v.H_f = v.SB_f + v.SF_f + v.K_f;
+    const double dH = v.H_f - v.H_i;
+    const bool bad = !std::isfinite(dH) ||
+                     ((v.status | force_status[k]) & (FPH_ST_BREAKDOWN | FPH_ST_NONFINITE)) || !action_ok[k];
+    v.accept_prob = bad ? 0.0 : (dH <= 0.0 ? 1.0 : std::exp(-dH));
+    v.accepted = (!bad && r_uniform[k] < v.accept_prob) ? 1 : 0;
+    if (v.accepted)
+      HMC_CHECK(hipMemcpyAsync(x_dev + k * d, c->xa + k * d, d * 8, hipMemcpyDeviceToDevice, s));
+    else
+      any_rejected = true;
+  }
+  if (p_out_dev) HMC_CHECK(hipMemcpyAsync(p_out_dev, c->pa, K * d * 8, hipMemcpyDeviceToDevice, s));
+  if (any_rejected) HMC_CALL(set_fields(x_dev));
+  HMC_CHECK(hipStreamSynchronize(s));
+  if (st)
+    for (int k = 0; k < K; ++k) st[k] = S[k];
   return FPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hmc_trajectory(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const double* R_mom_dev,
+                   double r_uniform, double* p_out_dev, fph_hmc_stats_t* st, void* stream) {
+  if (c == nullptr || x_dev == nullptr || R_fields_dev == nullptr || R_mom_dev == nullptr)
+    return FPH_E_NULL;
+  if (!(r_uniform >= 0.0 && r_uniform <= 1.0) || c->K != 1) return FPH_E_ARG;
+  return traj_impl(c, x_dev, R_fields_dev, R_mom_dev, &r_uniform, p_out_dev, st, stream);
+}
+
+int hmc_trajectories(fph_hmc_t c, double* x_dev, const double* R_fields_dev, const double* R_mom_dev,
+                     const double* r_uniform_host, double* p_out_dev, fph_hmc_stats_t* stats_host,
+                     void* stream) {
+  if (c == nullptr || x_dev == nullptr || R_fields_dev == nullptr || R_mom_dev == nullptr ||
+      r_uniform_host == nullptr)
+    return FPH_E_NULL;
+  for (int k = 0; k < c->K; ++k)
+    if (!(r_uniform_host[k] >= 0.0 && r_uniform_host[k] <= 1.0)) return FPH_E_ARG;
+  return traj_impl(c, x_dev, R_fields_dev, R_mom_dev, r_uniform_host, p_out_dev, stats_host, stream);
 }
 
 int lambda_apply(fph_hmc_t c, int32_t op, const double* x_dev, int32_t nvec, const double* in_dev,
@@ -678,7 +743,7 @@ int hmc_global_update(fph_hmc_t c, int32_t kind, int32_t i, int32_t j, double* x
                       const double* R_fields_dev, double r_uniform, fph_update_stats_t* st,
                       void* stream) {
   if (c == nullptr || x_dev == nullptr || R_fields_dev == nullptr) return FPH_E_NULL;
-  if ((kind != FPH_MOVE_REFLECT && kind != FPH_MOVE_SWAP) || i < 0 || i >= c->N ||
+  if (c->K != 1 || (kind != FPH_MOVE_REFLECT && kind != FPH_MOVE_SWAP) || i < 0 || i >= c->N ||
       (kind == FPH_MOVE_SWAP && (j < 0 || j >= c->N || j == i)) ||
       !(r_uniform >= 0.0 && r_uniform <= 1.0))
     return FPH_E_ARG;

@@ -33,13 +33,14 @@ class PhononHMC:
 
     def __init__(self, solver, omega0, m_reg, dt, Nt=100, nt=10, nfields=2, a1=1.0, a2=1.0,
                  force_tol=1e-5, action_tol=1e-10, precond=True, prec="f32_refined",
-                 maxiter=100000, guess="zero", lambda_action=False):
+                 maxiter=100000, guess="zero", lambda_action=False, nchains=1):
         self.lib = _lib.load()
         self.solver = solver
         self.nfields = int(nfields)
+        self.nchains = int(nchains)
         mr = math.inf if m_reg is None else float(m_reg)
         self.opts = HmcOpts(float(omega0), mr, float(dt), int(Nt), int(nt), self.nfields, float(a1),
-                            float(a2), _GUESS[guess], int(bool(lambda_action)),
+                            float(a2), _GUESS[guess], int(bool(lambda_action)), self.nchains, 0,
                             _pcg_opts(force_tol, precond, prec, maxiter),
                             _pcg_opts(action_tol, precond, prec, maxiter))
         h = ctypes.c_void_p()
@@ -98,6 +99,24 @@ class PhononHMC:
         check(self.lib.hmc_trajectory(self.h, _ptr(x), _ptr(R_fields), _ptr(R_mom), float(r_uniform),
                                       pp, ctypes.byref(st), _stream()))
         return st.as_dict()
+
+    def trajectories(self, x, R_fields, R_mom, r_uniform, p_out=None):
+        """One HMC update of each of the nchains chains at once: x [nchains, Ltau, N] (accepted
+        chains updated in place), R_fields [nchains, nfields, Ltau, N], R_mom [nchains, Ltau, N],
+        r_uniform a sequence of nchains draws.  Returns one stats dict per chain."""
+        K = self.nchains
+        self._v(x, K)
+        self._v(R_fields, K * self.nfields)
+        self._v(R_mom, K)
+        r_uniform = [float(v) for v in r_uniform]
+        if len(r_uniform) != K:
+            raise ValueError(f"expected {K} uniform draws")
+        rs = (ctypes.c_double * K)(*r_uniform)
+        st = (HmcStats * K)()
+        pp = _ptr(p_out) if p_out is not None else None
+        check(self.lib.hmc_trajectories(self.h, _ptr(x), _ptr(R_fields), _ptr(R_mom), rs, pp, st,
+                                        _stream()))
+        return [v.as_dict() for v in st]
 
     def lambda_apply(self, x, v, op="LinvT"):
         """Lambda(x) v, Lambda^{-1} v, Lambda^T v or Lambda^{-T} v (op 'L', 'Linv', 'LT', 'LinvT')."""

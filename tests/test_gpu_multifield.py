@@ -6,7 +6,7 @@ argument limits are enforced."""
 import numpy as np
 import pytest
 
-from workloads import gaussian_rhs, get_config, phonon_field
+from workloads import gaussian_rhs, get_config, hmc_draws, hmc_params, phonon_field
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -93,3 +93,55 @@ def test_multifield_limits_and_reset():
     s2.set_field(xs[1].contiguous())
     u2, _ = s2.solve(b, tol=1e-10, prec="f64", precond=True)
     assert np.array_equal(u.cpu().numpy(), u2.cpu().numpy())
+
+
+@pytest.mark.parametrize("lam", [False, True], ids=["Sprime", "Lambda"])
+def test_chains_equal_single_chain(lam):
+    """K chains advanced together (hmc_trajectories) give, chain by chain, the single-chain
+    trajectory: with FP64 solves to 1e-12 the fields, energies and accept decisions agree to
+    the solves' rounding; with the paper's tolerances the energy changes stay close."""
+    from paper_2203_01291_amd._lib import FphError
+    from paper_2203_01291_amd.hmc import PhononHMC
+    from paper_2203_01291_amd.solver import FermionSolver
+    p = get_config("c1")
+    hp = hmc_params(p, Nt=20)
+    K, nf = 3, 2
+    x0 = np.stack([phonon_field(p) + 0.1 * k for k in range(K)])
+    draws = [hmc_draws(p, nf, traj=k) for k in range(K)]
+    Rf = np.stack([d[0] for d in draws])
+    Rm = np.stack([d[1] for d in draws])
+    rs = [d[2] for d in draws]
+    for tol, prec, xtol, htol in ((1e-12, "f64", 1e-8, 1e-7), (hp.tol_force, "f32_refined", None, 0.05)):
+        kw = dict(Nt=hp.Nt, nt=hp.nt, force_tol=tol, action_tol=hp.tol_action, prec=prec,
+                  lambda_action=lam)
+        sm = FermionSolver.from_params(p, max_rhs=K * nf)
+        hm = PhononHMC(sm, hp.omega0, hp.m_reg, hp.dt, nchains=K, **kw)
+        xg = tgpu(x0)
+        pm = torch.empty_like(xg)
+        st = hm.trajectories(xg, tgpu(Rf), tgpu(Rm), rs, p_out=pm)
+        assert len(st) == K
+        with pytest.raises(FphError):                      # one-chain entry points refuse K > 1
+            hm.trajectory(xg[0].contiguous(), tgpu(Rf[0]), tgpu(Rm[0]), 0.5)
+        with pytest.raises(FphError):
+            hm.global_update(xg[0].contiguous(), "reflect", 0, 0, tgpu(Rf[0]), 0.5)
+        ss = FermionSolver.from_params(p, max_rhs=nf)
+        hs = PhononHMC(ss, hp.omega0, hp.m_reg, hp.dt, **kw)
+        for k in range(K):
+            x1 = tgpu(x0[k])
+            p1 = torch.empty_like(x1)
+            s1 = hs.trajectory(x1, tgpu(Rf[k]), tgpu(Rm[k]), rs[k], p_out=p1)
+            dh, dh1 = st[k]["H_f"] - st[k]["H_i"], s1["H_f"] - s1["H_i"]
+            assert st[k]["H_i"] == pytest.approx(s1["H_i"], rel=1e-12)
+            if xtol is not None:
+                assert st[k]["accepted"] == s1["accepted"]
+                assert abs(dh - dh1) < htol, (k, dh, dh1)
+                assert rel(pm[k].cpu().numpy(), p1.cpu().numpy()) < xtol
+                if s1["accepted"]:
+                    assert rel(xg[k].cpu().numpy(), x1.cpu().numpy()) < xtol
+                else:
+                    assert np.array_equal(xg[k].cpu().numpy(), x0[k])
+            else:
+                assert abs(dh - dh1) < htol, (k, dh, dh1)
+            assert st[k]["solves"] == s1["solves"]
+        hm.close()
+        hs.close()
