@@ -29,9 +29,12 @@ definition in the paper (arXiv:2203.01291):
                  App. B).
 * ``measure``  - stochastic Green's-function estimates and their space-time
                  averages by FFT cross-correlation (Sec. VI).
+* ``ssh``      - the space-time matrix, action and product-rule force of an
+                 SSH-type coupling, where x enters the hopping inside the
+                 checkerboard factors (Sec. II C closing remark; Sec. III A).
 
 Parity status of each function is stated in its docstring; a function with
 no independent pin says "parity unpinned".
 """
 
-from . import lattice, solve, force, precond, hmc, lam, measure  # noqa: F401
+from . import lattice, solve, force, precond, hmc, lam, measure, ssh  # noqa: F401
