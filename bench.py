@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--meas-only", action="store_true",
                     help="only the stochastic Green's-function measurement leg")
     ap.add_argument("--nrv", type=int, default=10, help="random vectors of the measurement leg")
+    ap.add_argument("--no-ssh", action="store_true", help="skip the SSH-coupling leg")
+    ap.add_argument("--ssh-only", action="store_true", help="only the SSH-coupling leg")
+    ap.add_argument("--ssh-g", type=float, default=0.2, help="SSH coupling g of the SSH leg")
     ap.add_argument("--concurrent", type=int, default=4,
                     help="independent systems / chains run side by side in the concurrency legs")
     ap.add_argument("--profile-roofline", action="store_true",
@@ -377,6 +380,64 @@ def bench_measure(torch, dev, p, a1, a2, nrv, log):
     return res
 
 
+def bench_ssh(torch, dev, p, g, log):
+    """SSH-type coupling (x in the bond hoppings) on the workload's lattice and
+    field: the M and M^T kernels timed with events (one and eight right-hand
+    sides), and one step of set-field + FP64 CG to 1e-8 (no preconditioner)
+    + S_F + force."""
+    from paper_2203_01291_amd.ssh import SSHSolver
+    from workloads import gaussian_rhs, phonon_field
+
+    nr = 8
+    s = SSHSolver.from_params(p, g, max_rhs=nr)
+    x = torch.from_numpy(phonon_field(p)).to(dev)
+    s.set_field(x)
+    v = torch.from_numpy(gaussian_rhs(p, nr)).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def kernel_us(op, n, reps=50):
+        vin = v[:n].contiguous()
+        out = torch.empty_like(vin)
+        for _ in range(3):
+            s.matvec(vin, op, out=out)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            s.matvec(vin, op, out=out)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    # algorithmic bytes of one M (or M^T) launch per right-hand side: read
+    # v_tau, v_{tau-1} (or v_{tau+1}) and x, write out: 4 d doubles
+    kern = {}
+    for op in ("M", "MT"):
+        for n in (1, nr):
+            us = kernel_us(op, n)
+            byts = 4.0 * p.dim * 8 * n
+            kern[f"{op}_rhs{n}"] = {"us": us, "GB/s": byts / us * 1e-3, "frac": byts / us * 1e-3 / HBM_PEAK_GBS}
+    b = s.matvec(v[:1].contiguous(), "MT")
+    s.solve(b, tol=1e-8, chunk=128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_field(x)
+    u, st = s.solve(b, tol=1e-8, chunk=128)
+    grad = s.force(u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = {
+        "workload": f"{p.name}: SSH coupling g={g} (t_b = t - g (x_j - x_i)) with the Holstein on-site "
+                    f"factor, FP64 CG to 1e-8 without preconditioner, S_F and force",
+        "ms_per_step": dt * 1e3, "iters": st[0]["iters"], "rel_resid": st[0]["rel_resid"],
+        "us_per_iteration": dt * 1e6 / max(1, st[0]["iters"]), "status": st[0]["status"],
+        "grad_norm": float(grad.norm()), "kernels": kern,
+    }
+    log(f"ssh: {res}")
+    s.close()
+    return res
+
+
 def cpu_baseline(p, golden_iters):
     """Oracle CG (scipy CSR, FP64) on the workload for a bounded number of
     iterations; scaled to solves/s with the oracle's own iteration count."""
@@ -484,6 +545,11 @@ def main():
         from workloads import get_config as _gc
         print(json.dumps(bench_measure(torch, torch.device("cuda:0"), _gc(args.workload), args.a1, args.a2,
                                        args.nrv, log)), flush=True)
+        return
+    if args.ssh_only:
+        from workloads import get_config as _gc
+        print(json.dumps(bench_ssh(torch, torch.device("cuda:0"), _gc(args.workload), args.ssh_g, log)),
+              flush=True)
         return
     if args.hmc_only:
         from workloads import get_config as _gc
@@ -687,6 +753,10 @@ def main():
     if not args.no_meas and R == 1:
         meas = bench_measure(torch, dev, p, args.a1, args.a2, args.nrv, log)
 
+    ssh = None
+    if not args.no_ssh and R == 1:
+        ssh = bench_ssh(torch, dev, p, args.ssh_g, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_iterations.json")))
@@ -753,6 +823,7 @@ def main():
         "multi_field": multi,
         "hmc_trajectory": hmc,
         "measurements": meas,
+        "ssh": ssh,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -545,6 +545,61 @@ int green_average(fph_meas_t mh, int32_t nvec, const double* xi_dev, const doubl
 int green_pair_products(fph_meas_t mh, int32_t nvec, const double* xi_dev, const double* gxi_dev,
                         double* out_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * SSH-type coupling (Sec. II C, closing remark; Sec. III A, force of the SSH
+ * model).  The paper states only that the phonon coordinates of the sites
+ * enter the hopping matrix K_tau and that the force follows by the product
+ * rule through the checkerboard factors.  This library reads it as: bond
+ * b = (i, j), j = i + x^ or i + y^, hops with
+ *   t_b(x_tau) = t - g (x_{j,tau} - x_{i,tau}),
+ * B_tau = diag(E_tau) F_xe F_ye F_xo F_yo with E_tau = exp(-dtau (alpha x_tau - mu))
+ * as in the Holstein matrix and F_f = exp(-dtau K_f(x_tau)) for the four bond
+ * families (x-bonds from even x, y-bonds from even y, x-bonds from odd x,
+ * y-bonds from odd y; F_yo acts first), each a direct sum of two-site blocks
+ * [[cosh, sinh], [sinh, cosh]](dtau t_b).  M keeps the block structure of
+ * Eq. M_def.  g = 0 gives the Holstein M; alpha = 0 the pure SSH coupling.
+ * FP64 only.  Layouts as above: vectors [nrhs][Ltau][N], x [Ltau][N].
+ * ------------------------------------------------------------------------ */
+
+typedef struct fph_ssh_s* fph_ssh_t;
+
+/* Context for one lattice (L even in [4, 64], Ltau even >= 2), SSH coupling g
+ * and up to max_rhs right-hand sides; allocates its workspace (5 vectors per
+ * right-hand side).  Errors: FPH_E_NULL, FPH_E_LATTICE, FPH_E_ARG (g not
+ * finite), FPH_E_NRHS, FPH_E_HIP. */
+int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t max_rhs);
+
+/* Synchronises the device and frees the context. */
+int fph_ssh_destroy(fph_ssh_t c);
+
+/* Copies the field x_dev [Ltau][N] into the context (bond hoppings are
+ * formed from it inside the kernels).  Enqueue only. */
+int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream);
+
+/* out = M in, M^T in or M^T M in (op FPH_OP_M / _MT / _MTM) for nrhs vectors;
+ * in and out must not overlap (FPH_E_ARG).  FPH_E_NOFIELD before
+ * ssh_set_field.  Enqueue only. */
+int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, double* out_dev,
+               void* stream);
+
+/* CG on (M^T M) u = b in FP64 (Sec. II D, Eq. CG), no preconditioner:
+ * opts->prec must be FPH_F64 and opts->use_precond 0 (FPH_E_PREC
+ * otherwise); opts->chunk iterations (0 -> 64) are enqueued between host
+ * checks.  Each right-hand side stops on its own at |r| < tol |b| (recursive
+ * residual); stats_host (nrhs entries, may be NULL) then hold the
+ * iterations, the FP64 true relative residual and S_F = b . u.  Blocks
+ * until done. */
+int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev,
+              const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host, void* stream);
+
+/* grad_dev [Ltau][N] += scale * sum_r dS_F/dx with S_F = b . (M^T M)^{-1} b and
+ * u_dev [nrhs][Ltau][N] the solutions (Eq. dSF_dx):
+ *   dS_F/dx_{i,tau} = 2 (M u)_tau . (dB_tau/dx_{i,tau}) u~_{tau-1},  u~_{-1} = -u_{Ltau-1},
+ * dB by the product rule through the four family factors (Sec. III A) plus
+ * the on-site term.  Uses the context's workspace for M u.  Enqueue only. */
+int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, double scale,
+              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,11 +28,15 @@ S_F = Phi . (M^T M)^{-1} Phi per field (Eq. Sf_Psi with Lambda = I), and
 dS_F/dx = -2 (M u) . (dM/dx u) with u = (M^T M)^{-1} Phi (Eq. dSF_dx).  The
 derivative of each factor is taken with the Frechet derivative of the
 matrix exponential (scipy.linalg.expm_frechet): no closed form of the bond
-factors is used here.  Dense matrices: small lattices only.
+factors is used here.  Dense matrices for small lattices; ``sparse_M`` builds
+the same matrix from the exponentials of the two-site hopping blocks
+(scipy.linalg.expm per bond) for lattices up to L = 64.
 """
 
 import numpy as np
 import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import lattice as lat_mod
 
@@ -196,3 +200,60 @@ def force_complex_step(lat, g, x, Phi, h=1e-20):
             xc[tau, i] += 1j * h
             out[tau, i] = np.imag(action(lat, g, xc, Phi)) / h
     return out
+
+
+def sparse_M(lat, g, x):
+    """CSR form of the same M.  The bonds of a family are disjoint, so each
+    family factor is the direct sum of the exponentials of its two-site
+    hopping blocks, each taken with scipy.linalg.expm; complex x allowed."""
+    x = np.asarray(x)
+    N, T = lat.N, lat.Ltau
+    E = lat_mod.E_field(lat, x)
+    blocks = [[None] * T for _ in range(T)]
+    fam = lat_mod.bond_families(lat.L)
+    for tau in range(T):
+        C = None
+        for f in FAMILIES:
+            rows, cols, vals = [], [], []
+            for i, j in fam[f]:
+                tb = lat.t - g * (x[tau][j] - x[tau][i])
+                blk = scipy.linalg.expm(-lat.dtau * np.array([[0.0, -tb], [-tb, 0.0]]))
+                for a, ia in enumerate((i, j)):
+                    for b, jb in enumerate((i, j)):
+                        rows.append(ia)
+                        cols.append(jb)
+                        vals.append(blk[a, b])
+            F = sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+            C = F if C is None else C @ F
+        B = sp.diags(E[tau]) @ C
+        blocks[tau][tau] = sp.identity(N, format="csr", dtype=B.dtype)
+        if tau >= 1:
+            blocks[tau][tau - 1] = -B
+        else:
+            blocks[0][T - 1] = B
+    return sp.bmat(blocks, format="csr")
+
+
+def sparse_action(lat, g, x, Phi):
+    """S_F = sum over fields of Phi . (M^T M)^{-1} Phi with a sparse LU (complex x allowed)."""
+    M = sparse_M(lat, g, x)
+    A = (M.T @ M).tocsc()
+    Phi = np.asarray(Phi).reshape(-1, lat.dim)
+    u = spla.splu(A).solve(Phi.T.astype(A.dtype))
+    return np.sum(Phi.T * u)
+
+
+def sparse_solve(lat, g, x, Phi):
+    """u = (M^T M)^{-1} Phi by sparse LU (Phi [..., Ltau, N], real x)."""
+    M = sparse_M(lat, g, x)
+    A = (M.T @ M).tocsc()
+    Phi = np.asarray(Phi)
+    sh = Phi.shape
+    u = spla.splu(A).solve(Phi.reshape(-1, lat.dim).T)
+    return u.T.reshape(sh)
+
+
+def directional_derivative(lat, g, x, Phi, direction, h=1e-20):
+    """d S_F(x + s direction)/ds at s = 0 by one complex step of sparse_action."""
+    xc = np.asarray(x, dtype=np.complex128) + 1j * h * np.asarray(direction)
+    return float(np.imag(sparse_action(lat, g, xc, Phi)) / h)

@@ -80,6 +80,16 @@ FPH_LAMBDA, FPH_LAMBDA_INV, FPH_LAMBDA_T, FPH_LAMBDA_INV_T = 0, 1, 2, 3
 FPH_MOVE_REFLECT, FPH_MOVE_SWAP = 0, 1
 
 EXPORTS = {
+    "fph_ssh_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Lattice), ctypes.c_double,
+                                      ctypes.c_int32]),
+    "fph_ssh_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ssh_set_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ssh_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "ssh_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), ctypes.c_void_p]),
+    "ssh_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_double, ctypes.c_void_p]),
     "fph_version": (ctypes.c_char_p, []),
     "fph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fph_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Lattice), ctypes.c_int32]),

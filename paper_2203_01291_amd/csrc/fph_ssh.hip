@@ -1,0 +1,602 @@
+// SSH-type coupling: the phonon field enters the hopping of every bond,
+// t_b(x_tau) = t - g (x_{j,tau} - x_{i,tau}) for b = (i, j = i + x^ or i + y^),
+// inside the checkerboard factors of exp(-dtau K_tau) (Sec. II C, closing
+// remark), so B_tau = diag(E_tau) F_xe F_ye F_xo F_yo with each family factor
+// a direct sum of two-site blocks [[cosh, sinh], [sinh, cosh]](dtau t_b).  The
+// matrix M keeps the block structure of Eq. M_def; the force goes by the
+// product rule through the four factors (Sec. III A).
+//
+// Kernels work one time slice per workgroup: the slice (N values) sits in
+// LDS and the four family factors are applied in place, one barrier apart;
+// every thread owns the same BPT bonds of each family.  Bond hoppings are
+// recomputed from x_tau (held in LDS) at each use: one expm1 per bond, no
+// tables in HBM.  FP64 throughout.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/holstein_hmc.h"
+#include "fph_internal.h"
+
+namespace {
+
+constexpr int kNT = 256;        // threads of a slice workgroup
+constexpr int kRedBlocks = 256;  // partial sums per right-hand side in the CG reductions
+constexpr int kMaxChunk = 4096;
+
+struct SshGeom {
+  int L, N, Ltau;
+  long d;
+  double dtau, t, mu, alpha, g;
+};
+
+// Sites (i, j) of bond k of family f (0 x-even, 1 y-even, 2 x-odd, 3 y-odd).
+__device__ __forceinline__ void bond_sites(int L, int f, int k, int& i, int& j) {
+  const int hL = L >> 1;
+  const int par = f >> 1;
+  if ((f & 1) == 0) {  // x-bonds: row y, start column 2c + par
+    const int y = k / hL, x = 2 * (k - y * hL) + par;
+    i = x + L * y;
+    j = (x + 1 == L ? 0 : x + 1) + L * y;
+  } else {  // y-bonds: column x, start row 2r + par
+    const int x = k % L, y = 2 * (k / L) + par;
+    i = x + L * y;
+    j = x + L * (y + 1 == L ? 0 : y + 1);
+  }
+}
+
+// cosh and sinh of a = dtau t_b without cancellation: with m = expm1(a),
+// sinh a = m (1 + e^-a) / 2 and cosh a = 1 + m^2 e^-a / 2.
+__device__ __forceinline__ void bond_cs(const SshGeom& G, const double* xs, int i, int j, double& ch,
+                                        double& sh) {
+  const double a = G.dtau * (G.t - G.g * (xs[j] - xs[i]));
+  const double m = expm1(a);
+  const double ei = 1.0 / (1.0 + m);
+  sh = 0.5 * m * (1.0 + ei);
+  ch = 1.0 + 0.5 * m * m * ei;
+}
+
+// w <- F_f w in LDS for the workgroup's bonds of family f.
+template <int BPT>
+__device__ __forceinline__ void apply_family(const SshGeom& G, const double* xs, double* w, int f) {
+  const int nb = G.N >> 1;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int k = threadIdx.x + q * kNT;
+    if (k < nb) {
+      int i, j;
+      bond_sites(G.L, f, k, i, j);
+      double ch, sh;
+      bond_cs(G, xs, i, j, ch, sh);
+      const double wi = w[i], wj = w[j];
+      w[i] = ch * wi + sh * wj;
+      w[j] = sh * wi + ch * wj;
+    }
+  }
+}
+
+__device__ __forceinline__ double e_site(const SshGeom& G, double x) {
+  return exp(-G.dtau * (G.alpha * x - G.mu));
+}
+
+// out = M v (OP 0) or M^T v (OP 1) for right-hand side blockIdx.y, slice blockIdx.x.
+//   (M v)_tau   = v_tau - s_tau E_tau C(x_tau) v_{tau-1}
+//   (M^T v)_tau = v_tau - s_tau' C(x_tau')^T (E_tau' v_tau'),  tau' = tau + 1 (mod Ltau)
+// with s = +1, except s_0 = -1 (the +B_0 corner block).
+template <int OP, int BPT>
+__global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __restrict__ x,
+                                                   const double* __restrict__ in,
+                                                   double* __restrict__ out) {
+  extern __shared__ double sm[];
+  double* xs = sm;
+  double* w = sm + G.N;
+  const int tau = blockIdx.x;
+  const long ro = (long)blockIdx.y * G.d;
+  const int ts = OP == 0 ? tau : (tau + 1 == G.Ltau ? 0 : tau + 1);  // slice of x used
+  const int tv = OP == 0 ? (tau == 0 ? G.Ltau - 1 : tau - 1) : ts;   // slice of v transported
+  const double* xt = x + (long)ts * G.N;
+  const double* vt = in + ro + (long)tv * G.N;
+  for (int i = threadIdx.x; i < G.N; i += kNT) {
+    const double xv = xt[i];
+    xs[i] = xv;
+    w[i] = OP == 0 ? vt[i] : e_site(G, xv) * vt[i];
+  }
+  __syncthreads();
+  if (OP == 0) {
+#pragma unroll
+    for (int f = 3; f >= 0; --f) {
+      apply_family<BPT>(G, xs, w, f);
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      apply_family<BPT>(G, xs, w, f);
+      __syncthreads();
+    }
+  }
+  const double s = (OP == 0 ? tau : ts) == 0 ? -1.0 : 1.0;
+  const double* vi = in + ro + (long)tau * G.N;
+  double* vo = out + ro + (long)tau * G.N;
+  for (int i = threadIdx.x; i < G.N; i += kNT) {
+    const double bw = OP == 0 ? e_site(G, xs[i]) * w[i] : w[i];
+    vo[i] = vi[i] - s * bw;
+  }
+}
+
+// grad_tau += scale * sum_r dS_F/dx_tau with S_F = Phi . (M^T M)^{-1} Phi:
+//   dS_F/dx_{i,tau} = 2 s_tau sum_r y_{r,tau} . (dB_tau/dx_{i,tau}) u_{r,tau-1},  y = M u.
+// dB = d(diag E) C + diag(E) sum_f F_xe .. dF_f .. F_yo: the vector entering
+// F_f from the right (a_f) is kept per thread in registers while C u is
+// formed; the row vector (E y) is then carried through the factors from the
+// left, and each bond adds dtau [c_i c_j] [[sh, ch], [ch, sh]] [a_i a_j]^T
+// times dt_b/dx = +g (site i), -g (site j).
+template <int BPT>
+__global__ void __launch_bounds__(kNT) k_ssh_force(SshGeom G, int nrhs, const double* __restrict__ x,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ y, double scale,
+                                                   double* __restrict__ grad) {
+  extern __shared__ double sm[];
+  double* xs = sm;
+  double* w = sm + G.N;
+  double* cv = sm + 2 * G.N;
+  double* ga = sm + 3 * G.N;
+  const int tau = blockIdx.x;
+  const int tp = tau == 0 ? G.Ltau - 1 : tau - 1;
+  const double s = tau == 0 ? -1.0 : 1.0;
+  const double* xt = x + (long)tau * G.N;
+  const int nb = G.N >> 1;
+  for (int i = threadIdx.x; i < G.N; i += kNT) {
+    xs[i] = xt[i];
+    ga[i] = 0.0;
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    const double* ur = u + (long)r * G.d + (long)tp * G.N;
+    const double* yr = y + (long)r * G.d + (long)tau * G.N;
+    __syncthreads();  // xs/ga ready; the previous right-hand side is done with w, cv
+    for (int i = threadIdx.x; i < G.N; i += kNT) {
+      w[i] = ur[i];
+      cv[i] = e_site(G, xs[i]) * yr[i];
+    }
+    __syncthreads();
+    double A[4][BPT][2];
+#pragma unroll
+    for (int f = 3; f >= 0; --f) {
+#pragma unroll
+      for (int q = 0; q < BPT; ++q) {
+        const int k = threadIdx.x + q * kNT;
+        if (k < nb) {
+          int i, j;
+          bond_sites(G.L, f, k, i, j);
+          A[f][q][0] = w[i];
+          A[f][q][1] = w[j];
+        }
+      }
+      apply_family<BPT>(G, xs, w, f);
+      __syncthreads();
+    }
+    // on-site term: dE_i/dx_i (C u)_i y_i = -dtau alpha (E y)_i (C u)_i
+    for (int i = threadIdx.x; i < G.N; i += kNT) ga[i] -= G.dtau * G.alpha * cv[i] * w[i];
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+      for (int q = 0; q < BPT; ++q) {
+        const int k = threadIdx.x + q * kNT;
+        if (k < nb) {
+          int i, j;
+          bond_sites(G.L, f, k, i, j);
+          double ch, sh;
+          bond_cs(G, xs, i, j, ch, sh);
+          const double ci = cv[i], cj = cv[j];
+          const double ai = A[f][q][0], aj = A[f][q][1];
+          const double gb = G.g * G.dtau * (sh * (ci * ai + cj * aj) + ch * (ci * aj + cj * ai));
+          ga[i] += gb;
+          ga[j] -= gb;
+          cv[i] = ch * ci + sh * cj;  // c_{f+1} = F_f c_f
+          cv[j] = sh * ci + ch * cj;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double* gt = grad + (long)tau * G.N;
+  const double c = 2.0 * s * scale;
+  for (int i = threadIdx.x; i < G.N; i += kNT) gt[i] += c * ga[i];
+}
+
+// ------------------------------------------------------------ CG on M^T M
+
+// part[r][b] = sum over block b's share of a_r . c_r
+__global__ void __launch_bounds__(256) k_dot_parts(long d, const double* __restrict__ a,
+                                                   const double* __restrict__ c,
+                                                   double* __restrict__ part) {
+  const int r = blockIdx.y;
+  a += (long)r * d;
+  c += (long)r * d;
+  double acc = 0.0;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) acc += a[k] * c[k];
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)r * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__device__ double sum_parts(const double* part, int nb) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// Per right-hand side state: rr, bb (|b|^2), alpha, beta, iters, status.
+struct CgState {
+  double rr, bb, alpha, beta, tol2;
+  int iters, status, done, maxiter;
+};
+
+// stage 0: rr = bb = |r|^2 at the start; stage 1: alpha = rr / p.q;
+// stage 2: rr' = |r|^2, beta = rr'/rr, convergence and cap tests.
+__global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const double* __restrict__ part,
+                                                   CgState* __restrict__ st) {
+  const int r = blockIdx.x;
+  const double v = sum_parts(part + (long)r * nb, nb);
+  if (threadIdx.x != 0) return;
+  CgState& S = st[r];
+  if (stage == 0) {
+    S.rr = v;
+    S.alpha = S.beta = 0.0;
+    S.iters = 0;
+    S.status = 0;
+    S.done = !(v > S.tol2 * S.bb) ? 1 : 0;
+    if (!isfinite(v)) {
+      S.status |= FPH_ST_NONFINITE;
+      S.done = 1;
+    }
+    return;
+  }
+  if (S.done) {
+    S.alpha = S.beta = 0.0;
+    return;
+  }
+  if (stage == 1) {
+    if (!(v > 0.0) || !isfinite(v)) {
+      S.status |= isfinite(v) ? FPH_ST_BREAKDOWN : FPH_ST_NONFINITE;
+      S.done = 1;
+      S.alpha = 0.0;
+    } else {
+      S.alpha = S.rr / v;
+    }
+    return;
+  }
+  S.iters += 1;
+  if (!isfinite(v)) {
+    S.status |= FPH_ST_NONFINITE;
+    S.done = 1;
+    S.beta = 0.0;
+    return;
+  }
+  S.beta = v / S.rr;
+  S.rr = v;
+  if (v <= S.tol2 * S.bb || S.iters >= S.maxiter) S.done = 1;
+}
+
+// u += alpha p, r -= alpha q
+__global__ void __launch_bounds__(256) k_cg_xr(long d, const CgState* __restrict__ st,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               double* __restrict__ u, double* __restrict__ r) {
+  const int k = blockIdx.y;
+  const double a = st[k].alpha;
+  if (a == 0.0) return;
+  const long o = (long)k * d;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < d; i += (long)gridDim.x * 256) {
+    u[o + i] += a * p[o + i];
+    r[o + i] -= a * q[o + i];
+  }
+}
+
+// p = r + beta p (skipped once a right-hand side is done)
+__global__ void __launch_bounds__(256) k_cg_p(long d, const CgState* __restrict__ st,
+                                              const double* __restrict__ r, double* __restrict__ p) {
+  const int k = blockIdx.y;
+  if (st[k].done) return;
+  const double b = st[k].beta;
+  const long o = (long)k * d;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < d; i += (long)gridDim.x * 256) p[o + i] = r[o + i] + b * p[o + i];
+}
+
+// r = b - r (r holds M^T M u on entry)
+__global__ void __launch_bounds__(256) k_sub_from(long n, const double* __restrict__ b, double* __restrict__ r) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) r[i] = b[i] - r[i];
+}
+
+int grid_for(long n) {
+  const long b = (n + 255) / 256;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+}  // namespace
+
+struct fph_ssh_s {
+  SshGeom G;
+  int max_rhs;
+  int bpt;
+  bool have_field;
+  double* x;     // the field [Ltau][N]
+  double* tmp;   // [max_rhs][d]
+  double* r;     // CG residual
+  double* p;     // CG direction
+  double* q;     // M^T M p
+  double* part;  // [max_rhs][kRedBlocks]
+  CgState* st;   // [max_rhs]
+  CgState* st_host;
+};
+
+namespace {
+
+#define SSH_CHECK(call)                                      \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return fph::record_hip_error(e_);  \
+  } while (0)
+
+size_t apply_lds(const fph_ssh_s* c) { return 2 * (size_t)c->G.N * sizeof(double); }
+size_t force_lds(const fph_ssh_s* c) { return 4 * (size_t)c->G.N * sizeof(double); }
+
+// Dynamic LDS above the default 64 KiB (L = 64: the force kernel takes 128 KiB).
+template <typename K>
+hipError_t allow_lds(K kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int OP>
+hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s) {
+  const dim3 grid(c->G.Ltau, nrhs);
+  const size_t lds = apply_lds(c);
+  switch (c->bpt) {
+    case 1: hipLaunchKernelGGL((k_ssh_apply<OP, 1>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
+    case 2: hipLaunchKernelGGL((k_ssh_apply<OP, 2>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
+    case 4: hipLaunchKernelGGL((k_ssh_apply<OP, 4>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
+    default: hipLaunchKernelGGL((k_ssh_apply<OP, 8>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
+  }
+  return hipGetLastError();
+}
+
+// out = op(in); MTM goes through c->tmp (so in/out must not be c->tmp).
+hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, double* out, hipStream_t s) {
+  if (op == FPH_OP_M) return launch_apply_op<0>(c, nrhs, in, out, s);
+  if (op == FPH_OP_MT) return launch_apply_op<1>(c, nrhs, in, out, s);
+  hipError_t e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
+  if (e != hipSuccess) return e;
+  return launch_apply_op<1>(c, nrhs, c->tmp, out, s);
+}
+
+hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const double* y, double scale,
+                        double* grad, hipStream_t s) {
+  const dim3 grid(c->G.Ltau);
+  const size_t lds = force_lds(c);
+  if (c->bpt == 8) {
+    hipError_t e = allow_lds(k_ssh_force<8>, lds);
+    if (e != hipSuccess) return e;
+  }
+  switch (c->bpt) {
+    case 1: hipLaunchKernelGGL((k_ssh_force<1>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
+    case 2: hipLaunchKernelGGL((k_ssh_force<2>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
+    case 4: hipLaunchKernelGGL((k_ssh_force<4>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
+    default: hipLaunchKernelGGL((k_ssh_force<8>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t dots(const fph_ssh_s* c, int nrhs, const double* a, const double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_parts, dim3(kRedBlocks, nrhs), dim3(256), 0, s, c->G.d, a, b, c->part);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t max_rhs) {
+  if (out == nullptr || lat == nullptr) return FPH_E_NULL;
+  *out = nullptr;
+  if (lat->L < 4 || lat->L % 2 || lat->L > 64 || lat->Ltau < 2 || lat->Ltau % 2 || lat->Ltau > 65535 ||
+      !std::isfinite(lat->dtau) || !std::isfinite(lat->t) || !std::isfinite(lat->mu) ||
+      !std::isfinite(lat->alpha) || lat->dtau <= 0.0)
+    return FPH_E_LATTICE;
+  if (!std::isfinite(g)) return FPH_E_ARG;
+  if (max_rhs < 1 || max_rhs > 65535) return FPH_E_NRHS;
+  fph_ssh_s* c = new fph_ssh_s();
+  std::memset(c, 0, sizeof(*c));
+  c->G.L = lat->L;
+  c->G.N = lat->L * lat->L;
+  c->G.Ltau = lat->Ltau;
+  c->G.d = (long)c->G.N * lat->Ltau;
+  c->G.dtau = lat->dtau;
+  c->G.t = lat->t;
+  c->G.mu = lat->mu;
+  c->G.alpha = lat->alpha;
+  c->G.g = g;
+  c->max_rhs = max_rhs;
+  const int nb = c->G.N / 2;
+  c->bpt = nb <= kNT ? 1 : nb <= 2 * kNT ? 2 : nb <= 4 * kNT ? 4 : 8;
+  const long d = c->G.d;
+  hipError_t e = hipSuccess;
+#define SSH_ALLOC(ptr, bytes) \
+  if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes));
+  SSH_ALLOC(c->x, d * sizeof(double));
+  SSH_ALLOC(c->tmp, (size_t)max_rhs * d * sizeof(double));
+  SSH_ALLOC(c->r, (size_t)max_rhs * d * sizeof(double));
+  SSH_ALLOC(c->p, (size_t)max_rhs * d * sizeof(double));
+  SSH_ALLOC(c->q, (size_t)max_rhs * d * sizeof(double));
+  SSH_ALLOC(c->part, (size_t)max_rhs * kRedBlocks * sizeof(double));
+  SSH_ALLOC(c->st, (size_t)max_rhs * sizeof(CgState));
+#undef SSH_ALLOC
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->st_host, (size_t)max_rhs * sizeof(CgState), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    fph_ssh_destroy(c);
+    return fph::record_hip_error(e);
+  }
+  *out = c;
+  return FPH_OK;
+}
+
+int fph_ssh_destroy(fph_ssh_t c) {
+  if (c == nullptr) return FPH_E_NULL;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {c->x, c->tmp, c->r, c->p, c->q, c->part, c->st};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+  return FPH_OK;
+}
+
+int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream) {
+  if (c == nullptr || x_dev == nullptr) return FPH_E_NULL;
+  SSH_CHECK(hipMemcpyAsync(c->x, x_dev, c->G.d * sizeof(double), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  c->have_field = true;
+  return FPH_OK;
+}
+
+int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, double* out_dev,
+               void* stream) {
+  if (c == nullptr || in_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
+  if (!c->have_field) return FPH_E_NOFIELD;
+  if (op < FPH_OP_M || op > FPH_OP_MTM) return FPH_E_PREC;
+  if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
+  const long bytes = (long)nrhs * c->G.d * 8;
+  const char *a = (const char*)in_dev, *b = (const char*)out_dev;
+  if (a < b + bytes && b < a + bytes) return FPH_E_ARG;
+  SSH_CHECK(launch_apply(c, op, nrhs, in_dev, out_dev, (hipStream_t)stream));
+  return FPH_OK;
+}
+
+int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, double scale,
+              void* stream) {
+  if (c == nullptr || u_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
+  if (!c->have_field) return FPH_E_NOFIELD;
+  if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
+  if (!std::isfinite(scale)) return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  SSH_CHECK(launch_apply_op<0>(c, nrhs, u_dev, c->tmp, s));  // y = M u
+  SSH_CHECK(launch_force(c, nrhs, u_dev, c->tmp, scale, grad_dev, s));
+  return FPH_OK;
+}
+
+int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, const fph_pcg_opts_t* opts,
+              fph_pcg_stats_t* stats_host, void* stream) {
+  if (c == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
+  if (!c->have_field) return FPH_E_NOFIELD;
+  if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
+  if (opts->prec != FPH_F64 || opts->use_precond != 0) return FPH_E_PREC;
+  if (!(opts->tol > 0.0) || !std::isfinite(opts->tol) || opts->maxiter < 1 || opts->chunk < 0)
+    return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const long d = c->G.d;
+  const long n = (long)nrhs * d;
+  const int chunk = opts->chunk > 0 ? (opts->chunk < kMaxChunk ? opts->chunk : kMaxChunk) : 64;
+  const dim3 vg(grid_for(d), nrhs);
+  // state: tol^2, bb, caps
+  for (int r = 0; r < nrhs; ++r) {
+    CgState& S = c->st_host[r];
+    std::memset(&S, 0, sizeof(S));
+    S.tol2 = opts->tol * opts->tol;
+    S.maxiter = opts->maxiter;
+  }
+  SSH_CHECK(dots(c, nrhs, b_dev, b_dev, s));
+  SSH_CHECK(hipStreamSynchronize(s));
+  std::vector<double> part((size_t)nrhs * kRedBlocks);
+  SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> bb(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r) {
+    for (int k = 0; k < kRedBlocks; ++k) bb[r] += part[(size_t)r * kRedBlocks + k];
+    c->st_host[r].bb = bb[r];
+  }
+  SSH_CHECK(hipMemcpyAsync(c->st, c->st_host, nrhs * sizeof(CgState), hipMemcpyHostToDevice, s));
+  // r = b - A u (or b for a zero guess), p = r
+  if (opts->zero_guess) {
+    SSH_CHECK(hipMemsetAsync(u_dev, 0, n * sizeof(double), s));
+    SSH_CHECK(hipMemcpyAsync(c->r, b_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    SSH_CHECK(launch_apply(c, FPH_OP_MTM, nrhs, u_dev, c->r, s));
+    hipLaunchKernelGGL(k_sub_from, dim3(grid_for(n)), dim3(256), 0, s, n, b_dev, c->r);
+    SSH_CHECK(hipGetLastError());
+  }
+  SSH_CHECK(hipMemcpyAsync(c->p, c->r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
+  hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, (const double*)c->part, c->st);
+  SSH_CHECK(hipGetLastError());
+  int matvecs = opts->zero_guess ? 0 : 1;
+  for (int it = 0;;) {
+    for (int k = 0; k < chunk; ++k, ++it) {
+      SSH_CHECK(launch_apply(c, FPH_OP_MTM, nrhs, c->p, c->q, s));
+      SSH_CHECK(dots(c, nrhs, c->p, c->q, s));
+      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 1, kRedBlocks, (const double*)c->part, c->st);
+      SSH_CHECK(hipGetLastError());
+      hipLaunchKernelGGL(k_cg_xr, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)c->p,
+                         (const double*)c->q, u_dev, c->r);
+      SSH_CHECK(hipGetLastError());
+      SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
+      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part, c->st);
+      SSH_CHECK(hipGetLastError());
+      hipLaunchKernelGGL(k_cg_p, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)c->r, c->p);
+      SSH_CHECK(hipGetLastError());
+    }
+    SSH_CHECK(hipMemcpyAsync(c->st_host, c->st, nrhs * sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SSH_CHECK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) all = all && c->st_host[r].done;
+    if (all || it >= opts->maxiter) break;
+  }
+  // true residual and S_F = b . u
+  SSH_CHECK(launch_apply(c, FPH_OP_MTM, nrhs, u_dev, c->r, s));
+  hipLaunchKernelGGL(k_sub_from, dim3(grid_for(n)), dim3(256), 0, s, n, b_dev, c->r);
+  SSH_CHECK(hipGetLastError());
+  SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
+  SSH_CHECK(hipStreamSynchronize(s));
+  std::vector<double> rr(nrhs, 0.0), act(nrhs, 0.0);
+  SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int r = 0; r < nrhs; ++r)
+    for (int k = 0; k < kRedBlocks; ++k) rr[r] += part[(size_t)r * kRedBlocks + k];
+  SSH_CHECK(dots(c, nrhs, b_dev, u_dev, s));
+  SSH_CHECK(hipStreamSynchronize(s));
+  SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int r = 0; r < nrhs; ++r)
+    for (int k = 0; k < kRedBlocks; ++k) act[r] += part[(size_t)r * kRedBlocks + k];
+  if (stats_host) {
+    for (int r = 0; r < nrhs; ++r) {
+      const CgState& S = c->st_host[r];
+      fph_pcg_stats_t& o = stats_host[r];
+      std::memset(&o, 0, sizeof(o));
+      o.iters = S.iters;
+      o.outer_iters = 0;
+      o.matvecs = matvecs + S.iters + 1;
+      o.rel_resid = bb[r] > 0.0 ? std::sqrt(rr[r] / bb[r]) : std::sqrt(rr[r]);
+      o.action = act[r];
+      o.status = S.status;
+      if (std::isfinite(o.rel_resid) && o.rel_resid < opts->tol) o.status |= FPH_ST_CONVERGED;
+      else if (!(S.status & (FPH_ST_BREAKDOWN | FPH_ST_NONFINITE))) o.status |= FPH_ST_MAXITER;
+    }
+  }
+  return FPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+"""SSH-type coupling on the GPU (ssh_* entry points) against the oracle.
+
+Operator: M, M^T, M^T M element by element against the oracle's dense matrix
+on small lattices, and against its sparse matrix (per-bond exponentials) at
+L = 24, 40 and 64, which take the kernels' other bond-per-thread shapes.
+Solve: FP64 CG against the oracle's LU solution and S_F.  Force: against the
+oracle's product-rule force (itself pinned to complex-step derivatives) on
+small lattices, and at L = 24, 40, 64 projected on a random direction against
+the oracle's complex-step directional derivative of S_F.  g = 0 against the
+Holstein solver, at the L = 32, Ltau = 400 workload.  Argument errors.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import lattice as Lm
+from oracle import ssh as S
+from workloads import gaussian_rhs, get_config, phonon_field
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def tgpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def make(L, Ltau, g, alpha=0.9, max_rhs=3, seed=0, dtau=0.1, mu=-0.2):
+    from paper_2203_01291_amd.ssh import SSHSolver
+    lat = Lm.Lattice(L=L, Ltau=Ltau, dtau=dtau, t=1.0, mu=mu, alpha=alpha)
+    x = 0.6 * np.random.default_rng(seed).standard_normal((Ltau, L * L))
+    s = SSHSolver(L, Ltau, dtau, 1.0, mu, alpha, g, max_rhs=max_rhs)
+    s.set_field(tgpu(x))
+    return lat, x, s
+
+
+SMALL = [(4, 6, 0.45, 0.9), (6, 4, 0.3, 0.0), (8, 2, 0.6, 0.5), (4, 2, 0.0, 0.9)]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"L{c[0]}_T{c[1]}_g{c[2]}_a{c[3]}" for c in SMALL])
+def test_operator_small(case):
+    L, T, g, a = case
+    lat, x, s = make(L, T, g, a)
+    for nr in (1, 3):
+        v = np.random.default_rng(nr).standard_normal((nr, T, L * L))
+        for op in ("M", "MT", "MTM"):
+            got = s.matvec(tgpu(v), op).cpu().numpy()
+            assert rel(got, S.apply(lat, g, x, v, op)) < 1e-13, (op, nr)
+
+
+@pytest.mark.parametrize("L,T", [(24, 4), (40, 4), (64, 2)])
+def test_operator_large(L, T):
+    g = 0.35
+    lat, x, s = make(L, T, g, max_rhs=2)
+    M = S.sparse_M(lat, g, x)
+    v = np.random.default_rng(3).standard_normal((2, T, L * L))
+    w = v.reshape(2, -1).T
+    want = {"M": M @ w, "MT": M.T @ w, "MTM": M.T @ (M @ w)}
+    for op, ref in want.items():
+        got = s.matvec(tgpu(v), op).cpu().numpy().reshape(2, -1).T
+        assert rel(got, ref) < 1e-13, op
+
+
+@pytest.mark.parametrize("case", SMALL[:3], ids=[f"L{c[0]}_T{c[1]}" for c in SMALL[:3]])
+def test_solve_and_force_small(case):
+    L, T, g, a = case
+    lat, x, s = make(L, T, g, a)
+    phi = np.random.default_rng(5).standard_normal((2, T, L * L))
+    u, st = s.solve(tgpu(phi), tol=1e-12)
+    uo = S.solve(lat, g, x, phi)
+    assert rel(u.cpu().numpy(), uo) < 1e-9
+    for r, v in enumerate(st):
+        assert v["status"] & 1 and v["rel_resid"] < 1e-12
+        assert v["action"] == pytest.approx(float(np.sum(phi[r] * uo[r])), rel=1e-10)
+    f = s.force(tgpu(uo), scale=1.0).cpu().numpy()
+    assert rel(f, S.force(lat, g, x, phi)) < 1e-11
+    f2 = s.force(tgpu(uo[:1]), grad=tgpu(f), scale=-0.5).cpu().numpy()  # accumulates
+    assert rel(f2, f - 0.5 * S.force(lat, g, x, phi[:1])) < 1e-11
+
+
+@pytest.mark.parametrize("L,T", [(24, 4), (40, 4), (64, 2)])
+def test_force_large_directional(L, T):
+    g = 0.35
+    lat, x, s = make(L, T, g, max_rhs=1, dtau=0.05)
+    phi = np.random.default_rng(7).standard_normal((T, L * L))
+    uo = S.sparse_solve(lat, g, x, phi)
+    f = s.force(tgpu(uo)).cpu().numpy()
+    for seed in (8, 9):
+        d = np.random.default_rng(seed).standard_normal(x.shape)
+        dd = S.directional_derivative(lat, g, x, phi, d)
+        assert float(np.sum(f * d)) == pytest.approx(dd, rel=1e-9)
+
+
+def test_g0_matches_holstein_at_workload():
+    """g = 0 reproduces the Holstein operator, force and solve at L = 32, Ltau = 400."""
+    from paper_2203_01291_amd.solver import FermionSolver
+    from paper_2203_01291_amd.ssh import SSHSolver
+    p = get_config("c3")
+    x = tgpu(phonon_field(p))
+    s = SSHSolver.from_params(p, 0.0, max_rhs=2)
+    s.set_field(x)
+    h = FermionSolver.from_params(p, max_rhs=2)
+    h.set_field(x)
+    v = tgpu(gaussian_rhs(p, 2))
+    for op in ("M", "MT", "MTM"):
+        assert rel(s.matvec(v, op).cpu().numpy(), h.matvec(v, op).cpu().numpy()) < 1e-13, op
+    b = h.matvec(v, "MT")
+    u, st = s.solve(b, tol=1e-10, chunk=128)
+    uh, sth = h.solve(b, tol=1e-10, prec="f64", precond=True)
+    assert all(v_["status"] & 1 for v_ in st)
+    # both residuals below 1e-10 |b|; with cond(M^T M) ~ 2e6 the solutions agree to ~1e-6
+    assert rel(u.cpu().numpy(), uh.cpu().numpy()) < 1e-5
+    for a_, b_ in zip(st, sth):
+        assert a_["action"] == pytest.approx(b_["action"], rel=1e-9)
+    assert rel(s.force(uh).cpu().numpy(), h.force(uh).cpu().numpy()) < 1e-12
+
+
+def test_argument_errors():
+    from paper_2203_01291_amd._lib import FphError
+    from paper_2203_01291_amd.ssh import SSHSolver
+    s = SSHSolver(4, 4, 0.1, 1.0, 0.0, 1.0, 0.3, max_rhs=2)
+    v = tgpu(np.ones((1, 4, 16)))
+    with pytest.raises(FphError):  # no field yet
+        s.matvec(v, "M")
+    s.set_field(tgpu(np.zeros((4, 16))))
+    with pytest.raises(FphError):  # more right-hand sides than max_rhs
+        s.matvec(tgpu(np.ones((3, 4, 16))), "M")
+    with pytest.raises(FphError):  # in and out overlap
+        s.matvec(v, "M", out=v)
+    with pytest.raises(FphError):  # odd L
+        SSHSolver(5, 4, 0.1, 1.0, 0.0, 1.0, 0.3)
+    u, st = s.solve(tgpu(np.zeros((1, 4, 16))))  # b = 0: converged at once, u = 0
+    assert st[0]["status"] & 1 and st[0]["iters"] == 0 and not u.abs().max().item()
+    b = np.random.default_rng(4).standard_normal((2, 4, 16))
+    u, st = s.solve(tgpu(b), tol=1e-14, maxiter=3)
+    assert all(v_["status"] == 2 and v_["iters"] == 3 for v_ in st), st

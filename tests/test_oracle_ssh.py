@@ -120,3 +120,20 @@ def test_force_central_difference_and_g0():
         assert f[tau, i] == pytest.approx(fd, rel=1e-6, abs=1e-8)
     u = S.solve(lat, 0.0, x, phi)
     assert np.abs(S.force(lat, 0.0, x, phi) - Fh.force_from_solution(lat, x, u)).max() < 1e-10
+
+
+def test_sparse_matrix_and_directional_derivative():
+    """The sparse construction (sparse exponentials) equals the dense one; the complex-step
+    directional derivative of the sparse action equals the adjoint force projected on it."""
+    lat = lat4(L=6, Ltau=4)
+    x = field(lat, 9)
+    g = 0.4
+    assert np.abs(S.sparse_M(lat, g, x).toarray() - S.dense_M(lat, g, x)).max() < 1e-13
+    lat = lat4()
+    x = field(lat, 10)
+    phi = np.random.default_rng(11).standard_normal((2, lat.Ltau, lat.N))
+    v = np.random.default_rng(12).standard_normal(x.shape)
+    f = S.force(lat, g, x, phi)
+    dd = S.directional_derivative(lat, g, x, phi, v)
+    assert dd == pytest.approx(float(np.sum(f * v)), rel=1e-10)
+    assert np.abs(S.sparse_solve(lat, g, x, phi) - S.solve(lat, g, x, phi)).max() < 1e-10
