@@ -582,13 +582,22 @@ int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream);
 int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, double* out_dev,
                void* stream);
 
-/* CG on (M^T M) u = b in FP64 (Sec. II D, Eq. CG), no preconditioner:
- * opts->prec must be FPH_F64 and opts->use_precond 0 (FPH_E_PREC
- * otherwise); opts->chunk iterations (0 -> 64) are enqueued between host
- * checks.  Each right-hand side stops on its own at |r| < tol |b| (recursive
- * residual); stats_host (nrhs entries, may be NULL) then hold the
- * iterations, the FP64 true relative residual and S_F = b . u.  Blocks
- * until done. */
+/* Let ssh_solve precondition with the adiabatic preconditioner of the
+ * Holstein handle h (Sec. V A, Eq. CG_precon): uniform hopping t and the
+ * on-site factor of h's current field, so the caller sets h's field to the
+ * same x (fph_set_field) whenever it sets this context's.  h must have the
+ * same lattice (FPH_E_LATTICE otherwise) and outlive its use; NULL detaches.
+ * Host only. */
+int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h);
+
+/* (P)CG on (M^T M) u = b in FP64 (Sec. II D, Eq. CG; Eq. CG_precon with
+ * z = F F^T r from the attached Holstein handle when opts->use_precond is 1,
+ * FPH_E_ARG if none is attached; FPH_E_NRHS above that handle's max_rhs).
+ * opts->prec must be FPH_F64 (FPH_E_PREC otherwise); opts->chunk iterations
+ * (0 -> 64) are enqueued between host checks.  Each right-hand side stops on
+ * its own at |r| < tol |b| (recursive residual); stats_host (nrhs entries,
+ * may be NULL) then hold the iterations, the FP64 true relative residual and
+ * S_F = b . u.  Blocks until done. */
 int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev,
               const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host, void* stream);
 

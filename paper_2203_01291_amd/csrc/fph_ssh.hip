@@ -245,24 +245,32 @@ __device__ double sum_parts(const double* part, int nb) {
 
 // Per right-hand side state: rr, bb (|b|^2), alpha, beta, iters, status.
 struct CgState {
-  double rr, bb, alpha, beta, tol2;
+  double rr, rz, bb, alpha, beta, tol2;
   int iters, status, done, maxiter;
 };
 
-// stage 0: rr = bb = |r|^2 at the start; stage 1: alpha = rr / p.q;
-// stage 2: rr' = |r|^2, beta = rr'/rr, convergence and cap tests.
+// stage 0: rr = |r|^2, rz = r.z at the start; stage 1: alpha = rz / p.q;
+// stage 2: rr' = |r|^2 (convergence and cap tests), rz' = r.z, beta = rz'/rz.
+// part2 holds the r.z partials (part2 == part without a preconditioner, z = r).
 __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const double* __restrict__ part,
+                                                   const double* __restrict__ part2,
                                                    CgState* __restrict__ st) {
   const int r = blockIdx.x;
   const double v = sum_parts(part + (long)r * nb, nb);
+  const double vz = part2 == part ? v : sum_parts(part2 + (long)r * nb, nb);
   if (threadIdx.x != 0) return;
   CgState& S = st[r];
   if (stage == 0) {
     S.rr = v;
+    S.rz = vz;
     S.alpha = S.beta = 0.0;
     S.iters = 0;
     S.status = 0;
     S.done = !(v > S.tol2 * S.bb) ? 1 : 0;
+    if (!S.done && !(vz > 0.0)) {
+      S.status |= isfinite(vz) ? FPH_ST_BREAKDOWN : FPH_ST_NONFINITE;
+      S.done = 1;
+    }
     if (!isfinite(v)) {
       S.status |= FPH_ST_NONFINITE;
       S.done = 1;
@@ -279,20 +287,29 @@ __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const doub
       S.done = 1;
       S.alpha = 0.0;
     } else {
-      S.alpha = S.rr / v;
+      S.alpha = S.rz / v;
     }
     return;
   }
   S.iters += 1;
-  if (!isfinite(v)) {
+  if (!isfinite(v) || !isfinite(vz)) {
     S.status |= FPH_ST_NONFINITE;
     S.done = 1;
     S.beta = 0.0;
     return;
   }
-  S.beta = v / S.rr;
   S.rr = v;
-  if (v <= S.tol2 * S.bb || S.iters >= S.maxiter) S.done = 1;
+  if (v <= S.tol2 * S.bb || S.iters >= S.maxiter) {
+    S.done = 1;
+    return;
+  }
+  if (!(vz > 0.0)) {
+    S.status |= FPH_ST_BREAKDOWN;
+    S.done = 1;
+    return;
+  }
+  S.beta = vz / S.rz;
+  S.rz = vz;
 }
 
 // u += alpha p, r -= alpha q
@@ -309,7 +326,7 @@ __global__ void __launch_bounds__(256) k_cg_xr(long d, const CgState* __restrict
   }
 }
 
-// p = r + beta p (skipped once a right-hand side is done)
+// p = z + beta p (skipped once a right-hand side is done)
 __global__ void __launch_bounds__(256) k_cg_p(long d, const CgState* __restrict__ st,
                                               const double* __restrict__ r, double* __restrict__ p) {
   const int k = blockIdx.y;
@@ -341,9 +358,13 @@ struct fph_ssh_s {
   double* r;     // CG residual
   double* p;     // CG direction
   double* q;     // M^T M p
+  double* z;     // preconditioned residual
   double* part;  // [max_rhs][kRedBlocks]
+  double* part2; // r.z partials
   CgState* st;   // [max_rhs]
   CgState* st_host;
+  fph_handle_t pc;  // Holstein handle whose preconditioner serves the solves (or NULL)
+  int pc_max_rhs;
 };
 
 namespace {
@@ -403,8 +424,10 @@ hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const dou
   return hipGetLastError();
 }
 
-hipError_t dots(const fph_ssh_s* c, int nrhs, const double* a, const double* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_parts, dim3(kRedBlocks, nrhs), dim3(256), 0, s, c->G.d, a, b, c->part);
+hipError_t dots(const fph_ssh_s* c, int nrhs, const double* a, const double* b, hipStream_t s,
+                double* part = nullptr) {
+  hipLaunchKernelGGL(k_dot_parts, dim3(kRedBlocks, nrhs), dim3(256), 0, s, c->G.d, a, b,
+                     part ? part : c->part);
   return hipGetLastError();
 }
 
@@ -444,7 +467,9 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
   SSH_ALLOC(c->r, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->p, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->q, (size_t)max_rhs * d * sizeof(double));
+  SSH_ALLOC(c->z, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->part, (size_t)max_rhs * kRedBlocks * sizeof(double));
+  SSH_ALLOC(c->part2, (size_t)max_rhs * kRedBlocks * sizeof(double));
   SSH_ALLOC(c->st, (size_t)max_rhs * sizeof(CgState));
 #undef SSH_ALLOC
   if (e == hipSuccess)
@@ -460,7 +485,7 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 int fph_ssh_destroy(fph_ssh_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->x, c->tmp, c->r, c->p, c->q, c->part, c->st};
+  void* ptrs[] = {c->x, c->tmp, c->r, c->p, c->q, c->z, c->part, c->part2, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -501,12 +526,33 @@ int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, 
   return FPH_OK;
 }
 
+int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h) {
+  if (c == nullptr) return FPH_E_NULL;
+  if (h == nullptr) {
+    c->pc = nullptr;
+    return FPH_OK;
+  }
+  fph_lattice_t lat;
+  int32_t mr = 0;
+  const int rc = fph_get_lattice(h, &lat, &mr);
+  if (rc != FPH_OK) return rc;
+  if (lat.L != c->G.L || lat.Ltau != c->G.Ltau || lat.dtau != c->G.dtau || lat.t != c->G.t ||
+      lat.mu != c->G.mu || lat.alpha != c->G.alpha)
+    return FPH_E_LATTICE;
+  c->pc = h;
+  c->pc_max_rhs = mr;
+  return FPH_OK;
+}
+
 int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, const fph_pcg_opts_t* opts,
               fph_pcg_stats_t* stats_host, void* stream) {
   if (c == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
   if (!c->have_field) return FPH_E_NOFIELD;
   if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
-  if (opts->prec != FPH_F64 || opts->use_precond != 0) return FPH_E_PREC;
+  if (opts->prec != FPH_F64 || opts->use_precond < 0 || opts->use_precond > 1) return FPH_E_PREC;
+  const bool pre = opts->use_precond != 0;
+  if (pre && c->pc == nullptr) return FPH_E_ARG;
+  if (pre && nrhs > c->pc_max_rhs) return FPH_E_NRHS;
   if (!(opts->tol > 0.0) || !std::isfinite(opts->tol) || opts->maxiter < 1 || opts->chunk < 0)
     return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -514,24 +560,33 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   const long n = (long)nrhs * d;
   const int chunk = opts->chunk > 0 ? (opts->chunk < kMaxChunk ? opts->chunk : kMaxChunk) : 64;
   const dim3 vg(grid_for(d), nrhs);
-  // state: tol^2, bb, caps
+  double* z = pre ? c->z : c->r;  // z = F F^T r, or r itself
+  const double* p2 = pre ? c->part2 : c->part;
+  auto precondition = [&]() -> int {
+    return pre ? fph_precond_apply(c->pc, FPH_PC_FFT, FPH_F64, nrhs, c->r, c->z, stream) : FPH_OK;
+  };
+  auto sum_host = [&](std::vector<double>& out) -> int {
+    std::vector<double> part((size_t)nrhs * kRedBlocks);
+    SSH_CHECK(hipStreamSynchronize(s));
+    SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+    out.assign(nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+      for (int k = 0; k < kRedBlocks; ++k) out[r] += part[(size_t)r * kRedBlocks + k];
+    return FPH_OK;
+  };
+  std::vector<double> bb, rr, act;
+  SSH_CHECK(dots(c, nrhs, b_dev, b_dev, s));
+  int rc = sum_host(bb);
+  if (rc != FPH_OK) return rc;
   for (int r = 0; r < nrhs; ++r) {
     CgState& S = c->st_host[r];
     std::memset(&S, 0, sizeof(S));
     S.tol2 = opts->tol * opts->tol;
     S.maxiter = opts->maxiter;
-  }
-  SSH_CHECK(dots(c, nrhs, b_dev, b_dev, s));
-  SSH_CHECK(hipStreamSynchronize(s));
-  std::vector<double> part((size_t)nrhs * kRedBlocks);
-  SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
-  std::vector<double> bb(nrhs, 0.0);
-  for (int r = 0; r < nrhs; ++r) {
-    for (int k = 0; k < kRedBlocks; ++k) bb[r] += part[(size_t)r * kRedBlocks + k];
-    c->st_host[r].bb = bb[r];
+    S.bb = bb[r];
   }
   SSH_CHECK(hipMemcpyAsync(c->st, c->st_host, nrhs * sizeof(CgState), hipMemcpyHostToDevice, s));
-  // r = b - A u (or b for a zero guess), p = r
+  // r = b - A u (or b for a zero guess), z = F F^T r, p = z
   if (opts->zero_guess) {
     SSH_CHECK(hipMemsetAsync(u_dev, 0, n * sizeof(double), s));
     SSH_CHECK(hipMemcpyAsync(c->r, b_dev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -540,24 +595,32 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
     hipLaunchKernelGGL(k_sub_from, dim3(grid_for(n)), dim3(256), 0, s, n, b_dev, c->r);
     SSH_CHECK(hipGetLastError());
   }
-  SSH_CHECK(hipMemcpyAsync(c->p, c->r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rc = precondition();
+  if (rc != FPH_OK) return rc;
+  SSH_CHECK(hipMemcpyAsync(c->p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
-  hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, (const double*)c->part, c->st);
+  if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
+  hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, (const double*)c->part, p2, c->st);
   SSH_CHECK(hipGetLastError());
-  int matvecs = opts->zero_guess ? 0 : 1;
+  const int matvecs = opts->zero_guess ? 0 : 1;
   for (int it = 0;;) {
     for (int k = 0; k < chunk; ++k, ++it) {
       SSH_CHECK(launch_apply(c, FPH_OP_MTM, nrhs, c->p, c->q, s));
       SSH_CHECK(dots(c, nrhs, c->p, c->q, s));
-      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 1, kRedBlocks, (const double*)c->part, c->st);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 1, kRedBlocks, (const double*)c->part,
+                         (const double*)c->part, c->st);
       SSH_CHECK(hipGetLastError());
       hipLaunchKernelGGL(k_cg_xr, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)c->p,
                          (const double*)c->q, u_dev, c->r);
       SSH_CHECK(hipGetLastError());
+      rc = precondition();
+      if (rc != FPH_OK) return rc;
       SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
-      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part, c->st);
+      if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
+      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part, p2,
+                         c->st);
       SSH_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(k_cg_p, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)c->r, c->p);
+      hipLaunchKernelGGL(k_cg_p, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)z, c->p);
       SSH_CHECK(hipGetLastError());
     }
     SSH_CHECK(hipMemcpyAsync(c->st_host, c->st, nrhs * sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -571,16 +634,11 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   hipLaunchKernelGGL(k_sub_from, dim3(grid_for(n)), dim3(256), 0, s, n, b_dev, c->r);
   SSH_CHECK(hipGetLastError());
   SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
-  SSH_CHECK(hipStreamSynchronize(s));
-  std::vector<double> rr(nrhs, 0.0), act(nrhs, 0.0);
-  SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int r = 0; r < nrhs; ++r)
-    for (int k = 0; k < kRedBlocks; ++k) rr[r] += part[(size_t)r * kRedBlocks + k];
+  rc = sum_host(rr);
+  if (rc != FPH_OK) return rc;
   SSH_CHECK(dots(c, nrhs, b_dev, u_dev, s));
-  SSH_CHECK(hipStreamSynchronize(s));
-  SSH_CHECK(hipMemcpy(part.data(), c->part, part.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int r = 0; r < nrhs; ++r)
-    for (int k = 0; k < kRedBlocks; ++k) act[r] += part[(size_t)r * kRedBlocks + k];
+  rc = sum_host(act);
+  if (rc != FPH_OK) return rc;
   if (stats_host) {
     for (int r = 0; r < nrhs; ++r) {
       const CgState& S = c->st_host[r];

@@ -36,6 +36,7 @@ class SSHSolver:
         h = ctypes.c_void_p()
         check(self.lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(lat), self.g, self.max_rhs))
         self.h = h
+        self._pc = None
 
     @classmethod
     def from_params(cls, p, g, L=None, max_rhs=1):
@@ -59,10 +60,21 @@ class SSHSolver:
             raise ValueError(f"size {v.numel()} is not a multiple of N*Ltau = {self.dim}")
         return v.numel() // self.dim
 
+    def attach_preconditioner(self, fermion_solver, a1=1.0, a2=1.0):
+        """Precondition solves with the adiabatic preconditioner of a FermionSolver of the
+        same lattice (uniform hopping, on-site factor of the field); set_field then sets
+        that solver's field too, with Chebyshev-order constants a1, a2.  None detaches."""
+        h = fermion_solver.h if fermion_solver is not None else None
+        check(self.lib.ssh_set_preconditioner(self.h, h))
+        self._pc = None if fermion_solver is None else (fermion_solver, float(a1), float(a2))
+
     def set_field(self, x):
         if self._vec(x) != 1:
             raise ValueError("expected one field of N*Ltau values")
         check(self.lib.ssh_set_field(self.h, _ptr(x), _stream()))
+        if self._pc is not None:
+            fs, a1, a2 = self._pc
+            fs.set_field(x, a1=a1, a2=a2)
 
     def matvec(self, v, op="M", out=None):
         """M v, M^T v or M^T M v for every vector of v."""
@@ -71,12 +83,13 @@ class SSHSolver:
         check(self.lib.ssh_matvec(self.h, _OPS[op], nrhs, _ptr(v), _ptr(out), _stream()))
         return out
 
-    def solve(self, b, u=None, tol=1e-10, maxiter=100000, chunk=0):
-        """FP64 CG on (M^T M) u = b.  Returns (u, [stats dict per rhs]).  Blocks until done."""
+    def solve(self, b, u=None, tol=1e-10, maxiter=100000, chunk=0, precond=False):
+        """FP64 (P)CG on (M^T M) u = b (precond: the attached preconditioner).
+        Returns (u, [stats dict per rhs]).  Blocks until done."""
         nrhs = self._vec(b)
         zero = u is None
         u = torch.empty_like(b) if u is None else u
-        opts = PcgOpts(float(tol), int(maxiter), 0, 0, int(zero), 0.0, int(chunk), 0)
+        opts = PcgOpts(float(tol), int(maxiter), int(bool(precond)), 0, int(zero), 0.0, int(chunk), 0)
         stats = (PcgStats * nrhs)()
         check(self.lib.ssh_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats, _stream()))
         return u, [s.as_dict() for s in stats]
