@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "../../include/holstein_hmc.h"
@@ -77,6 +78,12 @@ __device__ __forceinline__ void apply_family(const SshGeom& G, const double* xs,
   }
 }
 
+// Per right-hand side CG state: rr = |r|^2, rz = r.z, bb = |b|^2, alpha, beta, iters, status.
+struct CgState {
+  double rr, rz, bb, alpha, beta, tol2;
+  int iters, status, done, maxiter;
+};
+
 __device__ __forceinline__ double e_site(const SshGeom& G, double x) {
   return exp(-G.dtau * (G.alpha * x - G.mu));
 }
@@ -85,10 +92,21 @@ __device__ __forceinline__ double e_site(const SshGeom& G, double x) {
 //   (M v)_tau   = v_tau - s_tau E_tau C(x_tau) v_{tau-1}
 //   (M^T v)_tau = v_tau - s_tau' C(x_tau')^T (E_tau' v_tau'),  tau' = tau + 1 (mod Ltau)
 // with s = +1, except s_0 = -1 (the +B_0 corner block).
-template <int OP, int BPT>
+// With dotv != nullptr the workgroup also writes part[r * Ltau + tau] =
+// dotv_{r,tau} . out_{r,tau} (the p . M^T M p partials of CG).  PUPD (M
+// only): the operand is the CG direction p = z + beta_r in, formed on the fly
+// from zv and the previous direction `in`; the workgroup stores its own slice
+// of p in pnew (a buffer other than `in`, so no workgroup reads a slice that
+// another one is rewriting).
+template <int OP, int BPT, bool PUPD>
 __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __restrict__ x,
                                                    const double* __restrict__ in,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out,
+                                                   const double* __restrict__ dotv,
+                                                   double* __restrict__ part,
+                                                   const double* __restrict__ zv,
+                                                   const CgState* __restrict__ st,
+                                                   double* __restrict__ pnew) {
   extern __shared__ double sm[];
   double* xs = sm;
   double* w = sm + G.N;
@@ -98,10 +116,15 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __re
   const int tv = OP == 0 ? (tau == 0 ? G.Ltau - 1 : tau - 1) : ts;   // slice of v transported
   const double* xt = x + (long)ts * G.N;
   const double* vt = in + ro + (long)tv * G.N;
+  const double beta = PUPD ? st[blockIdx.y].beta : 0.0;
+  const double* zt = PUPD ? zv + ro + (long)tv * G.N : nullptr;
   for (int i = threadIdx.x; i < G.N; i += kNT) {
     const double xv = xt[i];
     xs[i] = xv;
-    w[i] = OP == 0 ? vt[i] : e_site(G, xv) * vt[i];
+    if (PUPD)
+      w[i] = zt[i] + beta * vt[i];
+    else
+      w[i] = OP == 0 ? vt[i] : e_site(G, xv) * vt[i];
   }
   __syncthreads();
   if (OP == 0) {
@@ -120,9 +143,29 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __re
   const double s = (OP == 0 ? tau : ts) == 0 ? -1.0 : 1.0;
   const double* vi = in + ro + (long)tau * G.N;
   double* vo = out + ro + (long)tau * G.N;
+  double acc = 0.0;
+  const double* zi = PUPD ? zv + ro + (long)tau * G.N : nullptr;
+  double* pn = PUPD ? pnew + ro + (long)tau * G.N : nullptr;
   for (int i = threadIdx.x; i < G.N; i += kNT) {
     const double bw = OP == 0 ? e_site(G, xs[i]) * w[i] : w[i];
-    vo[i] = vi[i] - s * bw;
+    double v = vi[i];
+    if (PUPD) {
+      v = zi[i] + beta * v;
+      pn[i] = v;
+    }
+    const double o = v - s * bw;
+    vo[i] = o;
+    if (dotv != nullptr) acc += dotv[ro + (long)tau * G.N + i] * o;
+  }
+  if (dotv != nullptr) {
+    double* red = sm + 2 * G.N;  // kNT values past the slice buffers
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kNT / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)blockIdx.y * G.Ltau + tau] = red[0];
   }
 }
 
@@ -243,14 +286,9 @@ __device__ double sum_parts(const double* part, int nb) {
   return v;
 }
 
-// Per right-hand side state: rr, bb (|b|^2), alpha, beta, iters, status.
-struct CgState {
-  double rr, rz, bb, alpha, beta, tol2;
-  int iters, status, done, maxiter;
-};
-
-// stage 0: rr = |r|^2, rz = r.z at the start; stage 1: alpha = rz / p.q;
-// stage 2: rr' = |r|^2 (convergence and cap tests), rz' = r.z, beta = rz'/rz.
+// stage 0: rr = |r|^2, rz = r.z at the start; stage 2: rr' = |r|^2
+// (convergence and cap tests), rz' = r.z, beta = rz'/rz.  (alpha is formed
+// by k_cg_xr.)
 // part2 holds the r.z partials (part2 == part without a preconditioner, z = r).
 __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const double* __restrict__ part,
                                                    const double* __restrict__ part2,
@@ -281,16 +319,6 @@ __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const doub
     S.alpha = S.beta = 0.0;
     return;
   }
-  if (stage == 1) {
-    if (!(v > 0.0) || !isfinite(v)) {
-      S.status |= isfinite(v) ? FPH_ST_BREAKDOWN : FPH_ST_NONFINITE;
-      S.done = 1;
-      S.alpha = 0.0;
-    } else {
-      S.alpha = S.rz / v;
-    }
-    return;
-  }
   S.iters += 1;
   if (!isfinite(v) || !isfinite(vz)) {
     S.status |= FPH_ST_NONFINITE;
@@ -312,28 +340,50 @@ __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const doub
   S.rz = vz;
 }
 
-// u += alpha p, r -= alpha q
-__global__ void __launch_bounds__(256) k_cg_xr(long d, const CgState* __restrict__ st,
+// alpha = rz / p.q from the operator's per-slice partials (every block sums
+// them in the same order, so all blocks take the same decision; block 0
+// records it), then u += alpha p, r -= alpha q, and part[k][block] = the
+// block's share of |r|^2 (grid: kRedBlocks x nrhs).  A finished right-hand
+// side is left alone; its partials are then stale and its scalars ignore them.
+__global__ void __launch_bounds__(256) k_cg_xr(long d, CgState* __restrict__ st, int npq,
+                                               const double* __restrict__ part_pq,
                                                const double* __restrict__ p, const double* __restrict__ q,
-                                               double* __restrict__ u, double* __restrict__ r) {
+                                               double* __restrict__ u, double* __restrict__ r,
+                                               double* __restrict__ part) {
   const int k = blockIdx.y;
-  const double a = st[k].alpha;
-  if (a == 0.0) return;
+  // block 0 may set done below: read it once per block so the exit is uniform
+  __shared__ int done_sh;
+  if (threadIdx.x == 0) done_sh = st[k].done;
+  __syncthreads();
+  if (done_sh) return;
+  const double pq = sum_parts(part_pq + (long)k * npq, npq);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (lead) {
+      st[k].status |= isfinite(pq) ? FPH_ST_BREAKDOWN : FPH_ST_NONFINITE;
+      st[k].alpha = 0.0;
+      st[k].done = 1;
+    }
+    return;
+  }
+  const double a = st[k].rz / pq;
+  if (lead) st[k].alpha = a;
   const long o = (long)k * d;
+  double acc = 0.0;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < d; i += (long)gridDim.x * 256) {
     u[o + i] += a * p[o + i];
-    r[o + i] -= a * q[o + i];
+    const double rv = r[o + i] - a * q[o + i];
+    r[o + i] = rv;
+    acc += rv * rv;
   }
-}
-
-// p = z + beta p (skipped once a right-hand side is done)
-__global__ void __launch_bounds__(256) k_cg_p(long d, const CgState* __restrict__ st,
-                                              const double* __restrict__ r, double* __restrict__ p) {
-  const int k = blockIdx.y;
-  if (st[k].done) return;
-  const double b = st[k].beta;
-  const long o = (long)k * d;
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < d; i += (long)gridDim.x * 256) p[o + i] = r[o + i] + b * p[o + i];
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = sh[0];
 }
 
 // r = b - r (r holds M^T M u on entry)
@@ -357,6 +407,7 @@ struct fph_ssh_s {
   double* tmp;   // [max_rhs][d]
   double* r;     // CG residual
   double* p;     // CG direction
+  double* p2;    // the next direction (formed inside the operator launch)
   double* q;     // M^T M p
   double* z;     // preconditioned residual
   double* part;  // [max_rhs][kRedBlocks]
@@ -375,7 +426,7 @@ namespace {
     if (e_ != hipSuccess) return fph::record_hip_error(e_);  \
   } while (0)
 
-size_t apply_lds(const fph_ssh_s* c) { return 2 * (size_t)c->G.N * sizeof(double); }
+size_t apply_lds(const fph_ssh_s* c) { return (2 * (size_t)c->G.N + kNT) * sizeof(double); }
 size_t force_lds(const fph_ssh_s* c) { return 4 * (size_t)c->G.N * sizeof(double); }
 
 // Dynamic LDS above the default 64 KiB (L = 64: the force kernel takes 128 KiB).
@@ -385,26 +436,40 @@ hipError_t allow_lds(K kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int OP>
-hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s) {
+// PUPD launches (OP 0 only) take zv, the state and pnew as described at the kernel.
+template <int OP, bool PUPD = false>
+hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s,
+                           const double* dotv = nullptr, const double* zv = nullptr,
+                           double* pnew = nullptr, double* pt = nullptr) {
   const dim3 grid(c->G.Ltau, nrhs);
   const size_t lds = apply_lds(c);
-  switch (c->bpt) {
-    case 1: hipLaunchKernelGGL((k_ssh_apply<OP, 1>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
-    case 2: hipLaunchKernelGGL((k_ssh_apply<OP, 2>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
-    case 4: hipLaunchKernelGGL((k_ssh_apply<OP, 4>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
-    default: hipLaunchKernelGGL((k_ssh_apply<OP, 8>), grid, dim3(kNT), lds, s, c->G, c->x, in, out); break;
+  const CgState* st = c->st;
+  if (c->bpt == 8) {
+    hipError_t e = allow_lds(k_ssh_apply<OP, 8, PUPD>, lds);
+    if (e != hipSuccess) return e;
   }
+#define SSH_APPLY_CASE(b)                                                                              \
+  hipLaunchKernelGGL((k_ssh_apply<OP, b, PUPD>), grid, dim3(kNT), lds, s, c->G, (const double*)c->x, in, \
+                     out, dotv, pt, zv, st, pnew)
+  switch (c->bpt) {
+    case 1: SSH_APPLY_CASE(1); break;
+    case 2: SSH_APPLY_CASE(2); break;
+    case 4: SSH_APPLY_CASE(4); break;
+    default: SSH_APPLY_CASE(8); break;
+  }
+#undef SSH_APPLY_CASE
   return hipGetLastError();
 }
 
-// out = op(in); MTM goes through c->tmp (so in/out must not be c->tmp).
-hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, double* out, hipStream_t s) {
+// out = op(in); MTM goes through c->tmp (so in/out must not be c->tmp).  With
+// dotv (MTM only), c->part[r * Ltau + tau] receive the slices of dotv . out.
+hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, double* out, hipStream_t s,
+                        const double* dotv = nullptr) {
   if (op == FPH_OP_M) return launch_apply_op<0>(c, nrhs, in, out, s);
   if (op == FPH_OP_MT) return launch_apply_op<1>(c, nrhs, in, out, s);
   hipError_t e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
   if (e != hipSuccess) return e;
-  return launch_apply_op<1>(c, nrhs, c->tmp, out, s);
+  return launch_apply_op<1>(c, nrhs, c->tmp, out, s, dotv);
 }
 
 hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const double* y, double scale,
@@ -466,10 +531,12 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
   SSH_ALLOC(c->tmp, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->r, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->p, (size_t)max_rhs * d * sizeof(double));
+  SSH_ALLOC(c->p2, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->q, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->z, (size_t)max_rhs * d * sizeof(double));
-  SSH_ALLOC(c->part, (size_t)max_rhs * kRedBlocks * sizeof(double));
-  SSH_ALLOC(c->part2, (size_t)max_rhs * kRedBlocks * sizeof(double));
+  // partials: kRedBlocks per right-hand side from the vector kernels, Ltau from the operator
+  SSH_ALLOC(c->part, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
+  SSH_ALLOC(c->part2, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
   SSH_ALLOC(c->st, (size_t)max_rhs * sizeof(CgState));
 #undef SSH_ALLOC
   if (e == hipSuccess)
@@ -485,7 +552,7 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 int fph_ssh_destroy(fph_ssh_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->x, c->tmp, c->r, c->p, c->q, c->z, c->part, c->part2, c->st};
+  void* ptrs[] = {c->x, c->tmp, c->r, c->p, c->p2, c->q, c->z, c->part, c->part2, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -559,7 +626,6 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   const long d = c->G.d;
   const long n = (long)nrhs * d;
   const int chunk = opts->chunk > 0 ? (opts->chunk < kMaxChunk ? opts->chunk : kMaxChunk) : 64;
-  const dim3 vg(grid_for(d), nrhs);
   double* z = pre ? c->z : c->r;  // z = F F^T r, or r itself
   const double* p2 = pre ? c->part2 : c->part;
   auto precondition = [&]() -> int {
@@ -598,6 +664,8 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   rc = precondition();
   if (rc != FPH_OK) return rc;
   SSH_CHECK(hipMemcpyAsync(c->p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double* pc = c->p;   // the current direction
+  double* pn = c->p2;  // receives the next one
   SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
   if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
   hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, (const double*)c->part, p2, c->st);
@@ -605,23 +673,23 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   const int matvecs = opts->zero_guess ? 0 : 1;
   for (int it = 0;;) {
     for (int k = 0; k < chunk; ++k, ++it) {
-      SSH_CHECK(launch_apply(c, FPH_OP_MTM, nrhs, c->p, c->q, s));
-      SSH_CHECK(dots(c, nrhs, c->p, c->q, s));
-      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 1, kRedBlocks, (const double*)c->part,
-                         (const double*)c->part, c->st);
-      SSH_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(k_cg_xr, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)c->p,
-                         (const double*)c->q, u_dev, c->r);
+      // p = z + beta p (beta = 0 at the start, where p already holds z), formed
+      // inside the M launch into pn; q = M^T M p with the p . q partials per slice
+      SSH_CHECK((launch_apply_op<0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));
+      SSH_CHECK(launch_apply_op<1>(c, nrhs, c->tmp, c->q, s, pn, nullptr, nullptr, c->part2));
+      // alpha, u += alpha p, r -= alpha q with the |r|^2 partials (into part:
+      // the p.q partials in part2 are still being read by other blocks)
+      hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks, nrhs), dim3(256), 0, s, d, c->st, c->G.Ltau,
+                         (const double*)c->part2, (const double*)pn, (const double*)c->q, u_dev, c->r,
+                         c->part);
       SSH_CHECK(hipGetLastError());
       rc = precondition();
       if (rc != FPH_OK) return rc;
-      SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
       if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
       hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part, p2,
                          c->st);
       SSH_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(k_cg_p, vg, dim3(256), 0, s, d, (const CgState*)c->st, (const double*)z, c->p);
-      SSH_CHECK(hipGetLastError());
+      std::swap(pc, pn);
     }
     SSH_CHECK(hipMemcpyAsync(c->st_host, c->st, nrhs * sizeof(CgState), hipMemcpyDeviceToHost, s));
     SSH_CHECK(hipStreamSynchronize(s));
