@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-ssh", action="store_true", help="skip the SSH-coupling leg")
     ap.add_argument("--ssh-only", action="store_true", help="only the SSH-coupling leg")
     ap.add_argument("--ssh-g", type=float, default=0.2, help="SSH coupling g of the SSH leg")
+    ap.add_argument("--ssh-hmc", action="store_true",
+                    help="with --ssh-only: also time one HMC trajectory on the SSH operator (paper "
+                         "settings, FP64 preconditioned solves; about 10 s)")
     ap.add_argument("--concurrent", type=int, default=4,
                     help="independent systems / chains run side by side in the concurrency legs")
     ap.add_argument("--profile-roofline", action="store_true",
@@ -380,7 +383,7 @@ def bench_measure(torch, dev, p, a1, a2, nrv, log):
     return res
 
 
-def bench_ssh(torch, dev, p, g, a1, a2, log):
+def bench_ssh(torch, dev, p, g, a1, a2, log, hmc=False):
     """SSH-type coupling (x in the bond hoppings) on the workload's lattice and
     field: the M and M^T kernels timed with events (one and eight right-hand
     sides), and one step of set-field + FP64 CG to 1e-8 (no preconditioner)
@@ -451,6 +454,29 @@ def bench_ssh(torch, dev, p, g, a1, a2, log):
                            "grad_rel_diff": float((gradp - grad).norm() / grad.norm()),
                            "a1_a2": [a1, a2]},
     }
+    if hmc:
+        from paper_2203_01291_amd.hmc import PhononHMC
+        from workloads import hmc_draws, hmc_params
+        hp = hmc_params(p)
+        s2 = SSHSolver.from_params(p, g, max_rhs=hp.nfields)
+        fs2 = FermionSolver.from_params(p, max_rhs=hp.nfields)
+        s2.attach_preconditioner(fs2, a1=a1, a2=a2)
+        hh = PhononHMC(s2, hp.omega0, hp.m_reg, hp.dt, Nt=hp.Nt, nt=hp.nt, nfields=hp.nfields,
+                       force_tol=hp.tol_force, action_tol=hp.tol_action, precond=True, prec="f64")
+        Rf, Rm, r = hmc_draws(p, hp.nfields)
+        xh = x.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sth = hh.trajectory(xh, torch.from_numpy(Rf).to(dev), torch.from_numpy(Rm).to(dev), r)
+        torch.cuda.synchronize()
+        res["hmc_trajectory"] = {
+            "seconds": time.perf_counter() - t0, "solves": sth["solves"], "cg_iters": sth["cg_iters"],
+            "dH": sth["H_f"] - sth["H_i"], "accepted": sth["accepted"], "status": sth["status"],
+            "settings": f"dt={hp.dt:g}, Nt={hp.Nt}, nt={hp.nt}, m_reg={hp.m_reg}, {hp.nfields} fields, "
+                        f"FP64 PCG to {hp.tol_force:g} (forces) and {hp.tol_action:g} (action)"}
+        hh.close()
+        s2.close()
+        fs2.close()
     fs.close()
     log(f"ssh: {res}")
     s.close()
@@ -568,7 +594,7 @@ def main():
     if args.ssh_only:
         from workloads import get_config as _gc
         print(json.dumps(bench_ssh(torch, torch.device("cuda:0"), _gc(args.workload), args.ssh_g, args.a1,
-                                   args.a2, log)),
+                                   args.a2, log, hmc=args.ssh_hmc)),
               flush=True)
         return
     if args.hmc_only:

@@ -573,7 +573,8 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 int fph_ssh_destroy(fph_ssh_t c);
 
 /* Copies the field x_dev [Ltau][N] into the context (bond hoppings are
- * formed from it inside the kernels).  Enqueue only. */
+ * formed from it inside the kernels), and sets it on the attached
+ * preconditioner's handle.  Enqueue only. */
 int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream);
 
 /* out = M in, M^T in or M^T M in (op FPH_OP_M / _MT / _MTM) for nrhs vectors;
@@ -584,11 +585,11 @@ int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, doub
 
 /* Let ssh_solve precondition with the adiabatic preconditioner of the
  * Holstein handle h (Sec. V A, Eq. CG_precon): uniform hopping t and the
- * on-site factor of h's current field, so the caller sets h's field to the
- * same x (fph_set_field) whenever it sets this context's.  h must have the
- * same lattice (FPH_E_LATTICE otherwise) and outlive its use; NULL detaches.
- * Host only. */
-int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h);
+ * on-site factor of the field.  From now on ssh_set_field also sets h's
+ * field (fph_set_field with the Chebyshev-order constants a1, a2).  h must
+ * have the same lattice (FPH_E_LATTICE otherwise) and outlive its use; NULL
+ * detaches.  Host only. */
+int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h, double a1, double a2);
 
 /* (P)CG on (M^T M) u = b in FP64 (Sec. II D, Eq. CG; Eq. CG_precon with
  * z = F F^T r from the attached Holstein handle when opts->use_precond is 1,
@@ -608,6 +609,17 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev,
  * the on-site term.  Uses the context's workspace for M u.  Enqueue only. */
 int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, double scale,
               void* stream);
+
+/* HMC context (as fph_hmc_create) whose update runs on the SSH operator of
+ * ssh: trajectories (hmc_trajectory) and global updates (hmc_global_update)
+ * with the action S' = S_B - dtau alpha sum x + 1/2 sum_sigma Phi_sigma .
+ * (M^T M)^{-1} Phi_sigma, M the SSH-type matrix, Phi_sigma = M(x_i)^T R_sigma.
+ * Solves go through ssh_solve: both solve options must be FPH_F64
+ * (FPH_E_PREC), use_precond needs an attached preconditioner.
+ * lambda_action and nchains > 1 are refused (FPH_E_ARG): Lambda belongs to
+ * the Holstein coupling and the SSH context has one field.  ssh must outlive
+ * the context. */
+int fph_hmc_create_ssh(fph_hmc_t* hh, fph_ssh_t ssh, const fph_hmc_opts_t* opts, void* stream);
 
 #ifdef __cplusplus
 }

@@ -257,3 +257,45 @@ def directional_derivative(lat, g, x, Phi, direction, h=1e-20):
     """d S_F(x + s direction)/ds at s = 0 by one complex step of sparse_action."""
     xc = np.asarray(x, dtype=np.complex128) + 1j * h * np.asarray(direction)
     return float(np.imag(sparse_action(lat, g, xc, Phi)) / h)
+
+
+# ------------------------------------------------------------- HMC with the SSH operator
+
+def pseudofermions(lat, g, x, R_fields):
+    """Phi_sigma = M(x)^T R_sigma (Eq. PhiSample-1 with A = M, the SSH-type M)."""
+    M = sparse_M(lat, g, x)
+    R = np.asarray(R_fields).reshape(-1, lat.dim)
+    return (M.T @ R.T).T.reshape(np.shape(R_fields))
+
+
+def hmc_action(lat, g, omega0, x, Phis):
+    """S' = S_B - dtau alpha sum x + 1/2 sum_sigma Phi_sigma . (M^T M)^{-1} Phi_sigma."""
+    from . import hmc as hmc_mod
+    return hmc_mod.x_action(lat, x, omega0) + 0.5 * float(np.real(sparse_action(lat, g, x, Phis)))
+
+
+def hmc_update(lat, g, omega0, m_reg, dt, Nt, nt, x_i, R_fields, R_mom, r_uniform):
+    """One HMC trial update (Algorithm 1) of the action S' with the SSH-type M:
+    the Holstein update's mass, momenta, time-step splitting and Metropolis
+    test (oracle.hmc) with this operator's pseudofermions, action and force."""
+    from . import hmc as hmc_mod
+    x_i = np.asarray(x_i, dtype=np.float64)
+    mt = hmc_mod.mass_tilde(lat.Ltau, lat.dtau, omega0, m_reg)
+    p_i = hmc_mod.sample_momentum(R_mom, mt)
+    Phis = pseudofermions(lat, g, x_i, R_fields)
+    f_force = lambda x: 0.5 * force(lat, g, x, Phis)
+
+    def ham(x, p):
+        sb = hmc_mod.x_action(lat, x, omega0)
+        sf = 0.5 * float(np.real(sparse_action(lat, g, x, Phis)))
+        k = hmc_mod.kinetic_energy(p, mt)
+        return {"H": sb + sf + k, "S_B": sb, "S_F": sf, "K": k}
+
+    Hi = ham(x_i, p_i)
+    x_f, p_f = hmc_mod.leapfrog_split(lat, omega0, mt, x_i, p_i, dt, Nt, nt, f_force)
+    Hf = ham(x_f, p_f)
+    dH = Hf["H"] - Hi["H"]
+    prob = min(1.0, float(np.exp(-dH)))
+    accepted = bool(r_uniform < prob)
+    return {"x_f": x_f, "p_f": p_f, "p_i": p_i, "Phi": Phis, "H_i": Hi, "H_f": Hf, "dH": dH,
+            "accept_prob": prob, "accepted": accepted, "x_out": x_f if accepted else x_i}

@@ -77,7 +77,7 @@ int hmc_trajectory_concurrent(int32_t n, fph_hmc_t const* hh, double* const* x_d
   for (int k = 0; k < n; ++k) {
     if (hh[k] == nullptr) return FPH_E_NULL;
     for (int j = 0; j < k; ++j)  // distinct contexts on distinct solver handles
-      if (hh[j] == hh[k] || fph::hmc_solver(hh[j]) == fph::hmc_solver(hh[k])) return FPH_E_ARG;
+      if (hh[j] == hh[k] || fph::hmc_operator(hh[j]) == fph::hmc_operator(hh[k])) return FPH_E_ARG;
   }
   if (!distinct_streams(n, streams)) return FPH_E_ARG;
   return run_threads(n, [&](int k) {

@@ -328,7 +328,8 @@ bool opts_ok(const fph_pcg_opts_t& o) {
 }  // namespace
 
 struct fph_hmc_s {
-  fph_handle_t h;
+  fph_handle_t h;   // the Holstein handle, or NULL with
+  fph_ssh_t ssh;    // an SSH context (fph_hmc_create_ssh)
   fph_lattice_t lat;
   int max_rhs;
   int N, Ltau;
@@ -412,7 +413,37 @@ hipError_t lambda_force_into(const fph_hmc_s* c, int nrhs, const double* b, cons
 
 }  // namespace
 
-fph_handle_t fph::hmc_solver(fph_hmc_t c) { return c ? c->h : nullptr; }
+const void* fph::hmc_operator(fph_hmc_t c) {
+  if (c == nullptr) return nullptr;
+  return c->h ? (const void*)c->h : (const void*)c->ssh;
+}
+
+namespace {
+
+// The operator calls of the update, on the Holstein handle or the SSH context.
+int op_set_fields(const fph_hmc_s* c, int K, const double* x, void* stream) {
+  if (c->ssh) return ssh_set_field(c->ssh, x, stream);
+  return K == 1 ? fph_set_field(c->h, x, c->o.a1, c->o.a2, stream)
+                : fph_set_fields(c->h, K, c->o.nfields, x, c->o.a1, c->o.a2, stream);
+}
+
+int op_MT(const fph_hmc_s* c, int nr, const double* in, double* out, void* stream) {
+  if (c->ssh) return ssh_matvec(c->ssh, FPH_OP_MT, nr, in, out, stream);
+  return fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nr, in, out, stream);
+}
+
+int op_solve(const fph_hmc_s* c, int nr, const double* b, double* u, const fph_pcg_opts_t* o,
+             fph_pcg_stats_t* st, void* stream) {
+  if (c->ssh) return ssh_solve(c->ssh, nr, b, u, o, st, stream);
+  return pcg_solve(c->h, nr, b, u, o, st, stream);
+}
+
+int op_force(const fph_hmc_s* c, int nr, const double* u, double* grad, double scale, void* stream) {
+  if (c->ssh) return ssh_force(c->ssh, nr, u, grad, scale, stream);
+  return fermion_force(c->h, nr, u, grad, scale, stream);
+}
+
+}  // namespace
 
 #define HMC_CHECK(call)                                         \
   do {                                                          \
@@ -440,12 +471,10 @@ int fph_hmc_destroy(fph_hmc_t c) {
   return FPH_OK;
 }
 
-int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void* stream) {
-  if (out == nullptr || h == nullptr || o == nullptr) return FPH_E_NULL;
+// The context on a Holstein handle h or an SSH context ssh (the other NULL).
+static int create_impl(fph_hmc_t* out, fph_handle_t h, fph_ssh_t ssh, fph_lattice_t lat, int32_t max_rhs,
+                       const fph_hmc_opts_t* o, void* stream) {
   *out = nullptr;
-  fph_lattice_t lat;
-  int32_t max_rhs = 0;
-  HMC_CALL(fph_get_lattice(h, &lat, &max_rhs));
   if (!(std::isfinite(o->omega0) && o->omega0 > 0.0) || !(std::isfinite(o->dt) && o->dt > 0.0) ||
       std::isnan(o->m_reg) || o->Nt < 1 || o->nt < 1 || !std::isfinite(o->a1) ||
       !std::isfinite(o->a2) || o->guess < 0 || o->guess > 2 || o->lambda_action < 0 ||
@@ -457,6 +486,7 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   fph_hmc_s* c = new fph_hmc_s();
   std::memset(c, 0, sizeof(*c));
   c->h = h;
+  c->ssh = ssh;
   c->lat = lat;
   c->max_rhs = max_rhs;
   c->N = lat.L * lat.L;
@@ -508,6 +538,26 @@ int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void
   }
   *out = c;
   return FPH_OK;
+}
+
+int fph_hmc_create(fph_hmc_t* out, fph_handle_t h, const fph_hmc_opts_t* o, void* stream) {
+  if (out == nullptr || h == nullptr || o == nullptr) return FPH_E_NULL;
+  *out = nullptr;
+  fph_lattice_t lat;
+  int32_t max_rhs = 0;
+  HMC_CALL(fph_get_lattice(h, &lat, &max_rhs));
+  return create_impl(out, h, nullptr, lat, max_rhs, o, stream);
+}
+
+int fph_hmc_create_ssh(fph_hmc_t* out, fph_ssh_t ssh, const fph_hmc_opts_t* o, void* stream) {
+  if (out == nullptr || ssh == nullptr || o == nullptr) return FPH_E_NULL;
+  *out = nullptr;
+  fph_lattice_t lat;
+  int32_t max_rhs = 0;
+  HMC_CALL(fph::ssh_info(ssh, &lat, &max_rhs, nullptr));
+  if (o->lambda_action != 0 || o->nchains > 1) return FPH_E_ARG;
+  if (o->force_solve.prec != FPH_F64 || o->action_solve.prec != FPH_F64) return FPH_E_PREC;
+  return create_impl(out, nullptr, ssh, lat, max_rhs, o, stream);
 }
 
 int bosonic_action(fph_hmc_t c, const double* x_dev, double* out_dev, void* stream) {
@@ -571,14 +621,13 @@ int traj_impl(fph_hmc_s* c, double* x_dev, const double* R_fields_dev, const dou
   int nsolves = 0;
 
   auto set_fields = [&](const double* x) -> int {
-    return K == 1 ? fph_set_field(c->h, x, o.a1, o.a2, stream)
-                  : fph_set_fields(c->h, K, nf, x, o.a1, o.a2, stream);
+    return op_set_fields(c, K, x, stream);
   };
   const double* rhs = lam ? c->bvec : c->Phi;  // b = Lambda(x)^{-T} Phi, or Phi
   auto solve = [&](const fph_pcg_opts_t& so, int zero_guess) -> int {
     fph_pcg_opts_t oo = so;
     oo.zero_guess = zero_guess;
-    int rc = pcg_solve(c->h, NR, rhs, c->u, &oo, ps.data(), stream);
+    int rc = op_solve(c, NR, rhs, c->u, &oo, ps.data(), stream);
     if (rc != FPH_OK) return rc;
     ++nsolves;
     for (int r = 0; r < NR; ++r) {
@@ -598,7 +647,7 @@ int traj_impl(fph_hmc_s* c, double* x_dev, const double* R_fields_dev, const dou
     }
     int rc = solve(o.force_solve, zero_guess);
     if (rc != FPH_OK) return rc;
-    rc = fermion_force(c->h, NR, c->u, c->pa, 0.5 * scale, stream);
+    rc = op_force(c, NR, c->u, c->pa, 0.5 * scale, stream);
     if (rc != FPH_OK || !lam) return rc;
     hipError_t e = lambda_force_into(c, nf, c->bvec, c->u, c->pa, 0.5 * scale, s, K);
     return e == hipSuccess ? FPH_OK : fph::record_hip_error(e);
@@ -618,10 +667,10 @@ int traj_impl(fph_hmc_s* c, double* x_dev, const double* R_fields_dev, const dou
   HMC_CHECK(hipMemcpyAsync(c->xa, x_dev, K * d * 8, hipMemcpyDeviceToDevice, s));
   HMC_CALL(set_fields(c->xa));
   if (lam) {
-    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, NR, R_fields_dev, c->bvec, stream));
+    HMC_CALL(op_MT(c, NR, R_fields_dev, c->bvec, stream));
     HMC_CHECK(lambda_into(c, 2, NR, c->xa, c->bvec, c->Phi, s, nf));
   } else {
-    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, NR, R_fields_dev, c->Phi, stream));
+    HMC_CALL(op_MT(c, NR, R_fields_dev, c->Phi, stream));
   }
   HMC_CHECK(circ1(c, TAB_MSQRT, K, R_mom_dev, c->pa, s));
   for (int k = 0; k < K; ++k)
@@ -758,12 +807,12 @@ int hmc_global_update(fph_hmc_t c, int32_t kind, int32_t i, int32_t j, double* x
   if (nf > 64) return FPH_E_NRHS;
 
   // Phi = A(x)^T R at the current field, S_F(x) = 1/2 |R|^2, the x-only action.
-  HMC_CALL(fph_set_field(c->h, x_dev, o.a1, o.a2, stream));
+  HMC_CALL(op_set_fields(c, 1, x_dev, stream));
   if (lam) {
-    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->bvec, stream));
+    HMC_CALL(op_MT(c, nf, R_fields_dev, c->bvec, stream));
     HMC_CHECK(lambda_into(c, 2, nf, x_dev, c->bvec, c->Phi, s));
   } else {
-    HMC_CALL(fermion_matvec(c->h, FPH_OP_MT, FPH_F64, nf, R_fields_dev, c->Phi, stream));
+    HMC_CALL(op_MT(c, nf, R_fields_dev, c->Phi, stream));
   }
   HMC_CHECK(dot_into(c, (long)nf * d, R_fields_dev, R_fields_dev, 0.5, c->en + EN_R2, s));
   HMC_CHECK(sb_into(c, x_dev, c->en + EN_SB_I, c->en + EN_LIN_I, s));
@@ -773,7 +822,7 @@ int hmc_global_update(fph_hmc_t c, int32_t kind, int32_t i, int32_t j, double* x
                      (int)kind, (int)i, (int)j, c->xa);
   HMC_CHECK(hipGetLastError());
   HMC_CHECK(sb_into(c, c->xa, c->en + EN_SB_F, c->en + EN_LIN_F, s));
-  HMC_CALL(fph_set_field(c->h, c->xa, o.a1, o.a2, stream));
+  HMC_CALL(op_set_fields(c, 1, c->xa, stream));
   const double* rhs = c->Phi;
   if (lam) {
     HMC_CHECK(lambda_into(c, 3, nf, c->xa, c->Phi, c->bvec, s));
@@ -781,7 +830,7 @@ int hmc_global_update(fph_hmc_t c, int32_t kind, int32_t i, int32_t j, double* x
   }
   fph_pcg_opts_t oo = o.action_solve;
   oo.zero_guess = 1;
-  HMC_CALL(pcg_solve(c->h, nf, rhs, c->u, &oo, ps, stream));
+  HMC_CALL(op_solve(c, nf, rhs, c->u, &oo, ps, stream));
   bool ok = true;
   double sf_new = 0.0;
   for (int r = 0; r < nf; ++r) {
@@ -803,7 +852,7 @@ int hmc_global_update(fph_hmc_t c, int32_t kind, int32_t i, int32_t j, double* x
   if (S.accepted) {
     HMC_CHECK(hipMemcpyAsync(x_dev, c->xa, d * 8, hipMemcpyDeviceToDevice, s));
   } else {
-    HMC_CALL(fph_set_field(c->h, x_dev, o.a1, o.a2, stream));
+    HMC_CALL(op_set_fields(c, 1, x_dev, stream));
   }
   HMC_CHECK(hipStreamSynchronize(s));
   if (st) *st = S;

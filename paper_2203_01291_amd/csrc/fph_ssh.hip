@@ -416,6 +416,7 @@ struct fph_ssh_s {
   CgState* st_host;
   fph_handle_t pc;  // Holstein handle whose preconditioner serves the solves (or NULL)
   int pc_max_rhs;
+  double pc_a1, pc_a2;  // its Chebyshev-order constants (fph_set_field)
 };
 
 namespace {
@@ -565,6 +566,7 @@ int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream) {
   SSH_CHECK(hipMemcpyAsync(c->x, x_dev, c->G.d * sizeof(double), hipMemcpyDeviceToDevice,
                            (hipStream_t)stream));
   c->have_field = true;
+  if (c->pc != nullptr) return fph_set_field(c->pc, x_dev, c->pc_a1, c->pc_a2, stream);
   return FPH_OK;
 }
 
@@ -593,7 +595,7 @@ int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, 
   return FPH_OK;
 }
 
-int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h) {
+int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h, double a1, double a2) {
   if (c == nullptr) return FPH_E_NULL;
   if (h == nullptr) {
     c->pc = nullptr;
@@ -606,8 +608,11 @@ int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h) {
   if (lat.L != c->G.L || lat.Ltau != c->G.Ltau || lat.dtau != c->G.dtau || lat.t != c->G.t ||
       lat.mu != c->G.mu || lat.alpha != c->G.alpha)
     return FPH_E_LATTICE;
+  if (!std::isfinite(a1) || !std::isfinite(a2)) return FPH_E_ARG;
   c->pc = h;
   c->pc_max_rhs = mr;
+  c->pc_a1 = a1;
+  c->pc_a2 = a2;
   return FPH_OK;
 }
 
@@ -726,3 +731,18 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
 }
 
 }  // extern "C"
+
+int fph::ssh_info(fph_ssh_t c, fph_lattice_t* lat, int32_t* max_rhs, double* g) {
+  if (c == nullptr) return FPH_E_NULL;
+  if (lat) {
+    lat->L = c->G.L;
+    lat->Ltau = c->G.Ltau;
+    lat->dtau = c->G.dtau;
+    lat->t = c->G.t;
+    lat->mu = c->G.mu;
+    lat->alpha = c->G.alpha;
+  }
+  if (max_rhs) *max_rhs = c->max_rhs;
+  if (g) *g = c->G.g;
+  return FPH_OK;
+}

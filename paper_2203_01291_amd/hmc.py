@@ -26,8 +26,9 @@ def _pcg_opts(tol, precond=True, prec="f32_refined", maxiter=100000, ru_delta=0.
 
 
 class PhononHMC:
-    """HMC and global updates of the phonon field of one ``FermionSolver``
-    (which must outlive this object).  m_reg=None disables Fourier
+    """HMC and global updates of the phonon field of one ``FermionSolver`` or
+    ``SSHSolver`` (which must outlive this object; with an SSHSolver the solves
+    are FP64, prec="f64").  m_reg=None disables Fourier
     acceleration; lambda_action=True samples the action with A = M Lambda,
     False the action S' with A = M."""
 
@@ -44,7 +45,9 @@ class PhononHMC:
                             _pcg_opts(force_tol, precond, prec, maxiter),
                             _pcg_opts(action_tol, precond, prec, maxiter))
         h = ctypes.c_void_p()
-        check(self.lib.fph_hmc_create(ctypes.byref(h), solver.h, ctypes.byref(self.opts), _stream()))
+        from .ssh import SSHSolver
+        create = self.lib.fph_hmc_create_ssh if isinstance(solver, SSHSolver) else self.lib.fph_hmc_create
+        check(create(ctypes.byref(h), solver.h, ctypes.byref(self.opts), _stream()))
         self.h = h
 
     def close(self):

@@ -63,18 +63,16 @@ class SSHSolver:
     def attach_preconditioner(self, fermion_solver, a1=1.0, a2=1.0):
         """Precondition solves with the adiabatic preconditioner of a FermionSolver of the
         same lattice (uniform hopping, on-site factor of the field); set_field then sets
-        that solver's field too, with Chebyshev-order constants a1, a2.  None detaches."""
+        that solver's field too (in the library), with Chebyshev-order constants a1, a2.
+        None detaches."""
         h = fermion_solver.h if fermion_solver is not None else None
-        check(self.lib.ssh_set_preconditioner(self.h, h))
-        self._pc = None if fermion_solver is None else (fermion_solver, float(a1), float(a2))
+        check(self.lib.ssh_set_preconditioner(self.h, h, float(a1), float(a2)))
+        self._pc = fermion_solver  # kept alive while attached
 
     def set_field(self, x):
         if self._vec(x) != 1:
             raise ValueError("expected one field of N*Ltau values")
         check(self.lib.ssh_set_field(self.h, _ptr(x), _stream()))
-        if self._pc is not None:
-            fs, a1, a2 = self._pc
-            fs.set_field(x, a1=a1, a2=a2)
 
     def matvec(self, v, op="M", out=None):
         """M v, M^T v or M^T M v for every vector of v."""

@@ -137,3 +137,22 @@ def test_sparse_matrix_and_directional_derivative():
     dd = S.directional_derivative(lat, g, x, phi, v)
     assert dd == pytest.approx(float(np.sum(f * v)), rel=1e-10)
     assert np.abs(S.sparse_solve(lat, g, x, phi) - S.solve(lat, g, x, phi)).max() < 1e-10
+
+
+def test_hmc_reversible_and_second_order():
+    """The leapfrog with the SSH force runs back to its start under p -> -p, and its energy
+    error falls 4x when dt halves (it only does so if the force is the action's gradient)."""
+    from oracle import hmc as H
+    lat = lat4(Ltau=4, dtau=0.1, alpha=0.5)
+    g, om = 0.4, 1.0
+    x = field(lat, 13, scale=0.3)
+    rng = np.random.default_rng(14)
+    R = rng.standard_normal((1, lat.Ltau, lat.N))
+    Rm = rng.standard_normal((lat.Ltau, lat.N))
+    out = S.hmc_update(lat, g, om, 1.0, 0.1, 4, 2, x, R, Rm, 0.5)
+    mt = H.mass_tilde(lat.Ltau, lat.dtau, om, 1.0)
+    fF = lambda v: 0.5 * S.force(lat, g, v, out["Phi"])
+    xb, pb = H.leapfrog_split(lat, om, mt, out["x_f"], -out["p_f"], 0.1, 4, 2, fF)
+    assert np.abs(xb - x).max() < 1e-10 and np.abs(pb + out["p_i"]).max() < 1e-10
+    dh = [abs(S.hmc_update(lat, g, om, 1.0, 0.4 / n, n, 2, x, R, Rm, 0.5)["dH"]) for n in (4, 8)]
+    assert 3.3 < dh[0] / dh[1] < 4.7, dh
