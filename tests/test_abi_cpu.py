@@ -133,3 +133,32 @@ def test_concurrent_entry_points_check_arguments_on_host():
     assert lib.pcg_solve_concurrent(2, None, None, None, None, None, None, None) == -1
     assert lib.hmc_trajectory_concurrent(0, None, None, None, None, None, None, None, None) == -7
     assert lib.hmc_trajectory_concurrent(2, None, None, None, None, None, None, None, None) == -1
+
+
+def test_ssh_argument_errors_on_host():
+    """The SSH entry points check their arguments before any device work: bad lattices, a
+    non-finite coupling, bad right-hand-side counts and null pointers return negative codes."""
+    from paper_2203_01291_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    import ctypes
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    good = _lib.Lattice(4, 8, 0.1, 1.0, 0.0, 1.0)
+    assert lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(_lib.Lattice(5, 8, 0.1, 1.0, 0.0, 1.0)),
+                              0.2, 1) == -2
+    assert lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(_lib.Lattice(66, 8, 0.1, 1.0, 0.0, 1.0)),
+                              0.2, 1) == -2
+    assert lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(_lib.Lattice(4, 7, 0.1, 1.0, 0.0, 1.0)),
+                              0.2, 1) == -2
+    assert lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(good), float("nan"), 1) == -7
+    assert lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(good), 0.2, 0) == -3
+    assert lib.fph_ssh_create(None, ctypes.byref(good), 0.2, 1) == -1
+    assert lib.fph_ssh_destroy(None) == -1
+    assert lib.ssh_set_field(None, None, None) == -1
+    assert lib.ssh_matvec(None, 0, 1, None, None, None) == -1
+    assert lib.ssh_solve(None, 1, None, None, None, None, None) == -1
+    assert lib.ssh_force(None, 1, None, None, 1.0, None) == -1
+    assert lib.ssh_set_preconditioner(None, None, 1.0, 1.0) == -1
+    assert lib.fph_hmc_create_ssh(ctypes.byref(h), None, None, None) == -1
+    assert lib.fph_hmc_create_ssh(None, None, None, None) == -1

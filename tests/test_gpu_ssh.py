@@ -219,3 +219,18 @@ def test_hmc_trajectory_and_global_update():
         PhononHMC(s, om, mreg, dt, prec="f64", lambda_action=True)
     with pytest.raises(FphError):  # FP64 solves only
         PhononHMC(s, om, mreg, dt, prec="f32_refined")
+
+
+@pytest.mark.parametrize("L,T", [(40, 4), (64, 2)])
+def test_solve_large(L, T):
+    """FP64 CG at the largest lattices against the oracle's sparse LU, three right-hand sides
+    of different scales (each stops on its own), and S_F."""
+    g = 0.35
+    lat, x, s = make(L, T, g, max_rhs=3, dtau=0.05)
+    phi = np.random.default_rng(31).standard_normal((3, T, L * L)) * np.array([1.0, 1e-3, 1e3])[:, None, None]
+    u, st = s.solve(tgpu(phi), tol=1e-12)
+    uo = S.sparse_solve(lat, g, x, phi)
+    for r in range(3):
+        assert st[r]["status"] == 1 and st[r]["rel_resid"] < 1e-12
+        assert rel(u[r].cpu().numpy(), uo[r]) < 1e-9
+        assert st[r]["action"] == pytest.approx(float(np.sum(phi[r] * uo[r])), rel=1e-10)
