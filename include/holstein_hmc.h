@@ -569,7 +569,8 @@ typedef struct fph_ssh_s* fph_ssh_t;
  * finite), FPH_E_NRHS, FPH_E_HIP. */
 int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t max_rhs);
 
-/* Synchronises the device and frees the context. */
+/* Synchronises the device and frees the context.  A context serves one call
+ * at a time (its workspace is shared by all its entry points). */
 int fph_ssh_destroy(fph_ssh_t c);
 
 /* Copies the field x_dev [Ltau][N] into the context (bond hoppings are
@@ -588,7 +589,8 @@ int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, doub
  * on-site factor of the field.  From now on ssh_set_field also sets h's
  * field (fph_set_field with the Chebyshev-order constants a1, a2).  h must
  * have the same lattice (FPH_E_LATTICE otherwise) and outlive its use; NULL
- * detaches.  Host only. */
+ * detaches.  The preconditioner uses h's workspace: calls on contexts that
+ * share one h (or on h itself) must not overlap.  Host only. */
 int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h, double a1, double a2);
 
 /* (P)CG on (M^T M) u = b in FP64 (Sec. II D, Eq. CG; Eq. CG_precon with
