@@ -604,6 +604,11 @@ int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h, double a1, double a2);
 int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev,
               const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host, void* stream);
 
+/* out_dev[r] = b_r . u_r in FP64 for r < nrhs (S_F of Eq. Sf_Psi for the
+ * solutions u of ssh_solve).  Uses the context's workspace.  Enqueue only. */
+int ssh_action(fph_ssh_t c, int32_t nrhs, const double* b_dev, const double* u_dev, double* out_dev,
+               void* stream);
+
 /* grad_dev [Ltau][N] += scale * sum_r dS_F/dx with S_F = b . (M^T M)^{-1} b and
  * u_dev [nrhs][Ltau][N] the solutions (Eq. dSF_dx):
  *   dS_F/dx_{i,tau} = 2 (M u)_tau . (dB_tau/dx_{i,tau}) u~_{tau-1},  u~_{-1} = -u_{Ltau-1},

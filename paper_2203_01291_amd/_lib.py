@@ -92,6 +92,8 @@ EXPORTS = {
                                           ctypes.POINTER(HmcOpts), ctypes.c_void_p]),
     "ssh_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), ctypes.c_void_p]),
+    "ssh_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
     "ssh_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_double, ctypes.c_void_p]),
     "fph_version": (ctypes.c_char_p, []),

@@ -386,6 +386,13 @@ __global__ void __launch_bounds__(256) k_cg_xr(long d, CgState* __restrict__ st,
   if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = sh[0];
 }
 
+// out[r] = sum of the kRedBlocks partials of right-hand side r, in block order
+__global__ void __launch_bounds__(256) k_sum_rhs(int nb, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  const double v = sum_parts(part + (long)blockIdx.x * nb, nb);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
 // r = b - r (r holds M^T M u on entry)
 __global__ void __launch_bounds__(256) k_sub_from(long n, const double* __restrict__ b, double* __restrict__ r) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) r[i] = b[i] - r[i];
@@ -592,6 +599,17 @@ int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, 
   hipStream_t s = (hipStream_t)stream;
   SSH_CHECK(launch_apply_op<0>(c, nrhs, u_dev, c->tmp, s));  // y = M u
   SSH_CHECK(launch_force(c, nrhs, u_dev, c->tmp, scale, grad_dev, s));
+  return FPH_OK;
+}
+
+int ssh_action(fph_ssh_t c, int32_t nrhs, const double* b_dev, const double* u_dev, double* out_dev,
+               void* stream) {
+  if (c == nullptr || b_dev == nullptr || u_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
+  if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
+  hipStream_t s = (hipStream_t)stream;
+  SSH_CHECK(dots(c, nrhs, b_dev, u_dev, s));
+  hipLaunchKernelGGL(k_sum_rhs, dim3(nrhs), dim3(256), 0, s, kRedBlocks, (const double*)c->part, out_dev);
+  SSH_CHECK(hipGetLastError());
   return FPH_OK;
 }
 

@@ -246,7 +246,8 @@ class FermionBatch:
 
 class FermionAction(torch.autograd.Function):
     """S_F(x; Phi) = sum_r Phi_r^T (M(x)^T M(x))^{-1} Phi_r with the hand-written
-    adjoint force as its gradient (Eq. dSF_dx):
+    adjoint force as its gradient (Eq. dSF_dx; ``solver`` is a FermionSolver,
+    or an SSHSolver, whose force is the product rule through its bond factors):
         dS_F/dx = sum_r -2 dtau alpha (M u_r) * (E * C u~_r),
         dS_F/dPhi_r = 2 u_r.
     """

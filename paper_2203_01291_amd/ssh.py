@@ -8,7 +8,8 @@ or i + y^), keeps the Holstein on-site factor exp(-dtau (alpha x - mu)) and the
 four bond families of the checkerboard (F_xe F_ye F_xo F_yo); g = 0 is the
 Holstein matrix.  Argument marshalling only: every step runs in the HIP
 library; tensors give device pointers and the current torch stream the
-hipStream_t.  FP64 only.
+hipStream_t.  FP64 only.  ``solver.fermion_action(x, Phi, ssh_solver)`` gives
+a differentiable S_F on this operator (its gradient is ``force``).
 """
 
 import ctypes
@@ -91,6 +92,13 @@ class SSHSolver:
         stats = (PcgStats * nrhs)()
         check(self.lib.ssh_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats, _stream()))
         return u, [s.as_dict() for s in stats]
+
+    def action(self, b, u):
+        """S_F = b . u per right-hand side, FP64 on the device."""
+        nrhs = self._vec(b)
+        out = torch.empty(nrhs, dtype=torch.float64, device=b.device)
+        check(self.lib.ssh_action(self.h, nrhs, _ptr(b), _ptr(u), _ptr(out), _stream()))
+        return out
 
     def force(self, u, grad=None, scale=1.0):
         """grad += scale * sum_r dS_F/dx for solutions u (S_F = b . (M^T M)^{-1} b)."""

@@ -159,6 +159,7 @@ def test_ssh_argument_errors_on_host():
     assert lib.ssh_matvec(None, 0, 1, None, None, None) == -1
     assert lib.ssh_solve(None, 1, None, None, None, None, None) == -1
     assert lib.ssh_force(None, 1, None, None, 1.0, None) == -1
+    assert lib.ssh_action(None, 1, None, None, None, None) == -1
     assert lib.ssh_set_preconditioner(None, None, 1.0, 1.0) == -1
     assert lib.fph_hmc_create_ssh(ctypes.byref(h), None, None, None) == -1
     assert lib.fph_hmc_create_ssh(None, None, None, None) == -1

@@ -234,3 +234,20 @@ def test_solve_large(L, T):
         assert st[r]["status"] == 1 and st[r]["rel_resid"] < 1e-12
         assert rel(u[r].cpu().numpy(), uo[r]) < 1e-9
         assert st[r]["action"] == pytest.approx(float(np.sum(phi[r] * uo[r])), rel=1e-10)
+
+
+def test_autograd_action():
+    """fermion_action on the SSH operator: S_F, dS_F/dx (the product-rule force) and
+    dS_F/dPhi = 2u against the oracle."""
+    from paper_2203_01291_amd.solver import fermion_action
+    L, T, g = 4, 6, 0.45
+    lat, x, s = make(L, T, g, max_rhs=2)
+    phi = np.random.default_rng(41).standard_normal((2, T, L * L))
+    xg = tgpu(x).requires_grad_()
+    pg = tgpu(phi).requires_grad_()
+    S_F = fermion_action(xg, pg, s, tol=1e-13)
+    S_F.backward()
+    uo = S.solve(lat, g, x, phi)
+    assert S_F.item() == pytest.approx(float(np.sum(phi * uo)), rel=1e-10)
+    assert rel(xg.grad.cpu().numpy(), S.force(lat, g, x, phi)) < 1e-9
+    assert rel(pg.grad.cpu().numpy(), 2.0 * uo) < 1e-9
