@@ -414,13 +414,14 @@ def bench_ssh(torch, dev, p, g, a1, a2, log, hmc=False):
         e1.synchronize()
         return e0.elapsed_time(e1) / reps * 1e3
 
-    # algorithmic bytes of one M (or M^T) launch per right-hand side: read
-    # v_tau, v_{tau-1} (or v_{tau+1}) and x, write out: 4 d doubles
+    # algorithmic bytes of one M (or M^T) launch: per right-hand side read v_tau
+    # and the transported slice, write out (3 d doubles); once per launch the
+    # field's tables, bond (cosh, sinh) and E (5 d doubles)
     kern = {}
     for op in ("M", "MT"):
         for n in (1, nr):
             us = kernel_us(op, n)
-            byts = 4.0 * p.dim * 8 * n
+            byts = (3.0 * n + 5.0) * p.dim * 8
             kern[f"{op}_rhs{n}"] = {"us": us, "GB/s": byts / us * 1e-3, "frac": byts / us * 1e-3 / HBM_PEAK_GBS}
     b = s.matvec(v[:1].contiguous(), "MT")
     s.solve(b, tol=1e-8, chunk=128)

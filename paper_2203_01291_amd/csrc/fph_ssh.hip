@@ -92,6 +92,57 @@ __device__ __forceinline__ double e_site(const SshGeom& G, double x) {
 //   (M v)_tau   = v_tau - s_tau E_tau C(x_tau) v_{tau-1}
 //   (M^T v)_tau = v_tau - s_tau' C(x_tau')^T (E_tau' v_tau'),  tau' = tau + 1 (mod Ltau)
 // with s = +1, except s_0 = -1 (the +B_0 corner block).
+// Per-slice tables of the field, formed once per field (one workgroup per
+// slice): hop[tau][f][k] = (cosh, sinh)(dtau t_b) for bond k of family f,
+// Et[tau][i] = E_{tau,i}.  The operator kernels then start their slice with
+// plain loads instead of a chain of expm1 between the LDS passes.
+__global__ void __launch_bounds__(kNT) k_ssh_tables(SshGeom G, const double* __restrict__ x,
+                                                    double2* __restrict__ hop, double* __restrict__ Et) {
+  extern __shared__ double sm[];
+  double* xs = sm;
+  const int tau = blockIdx.x;
+  const double* xt = x + (long)tau * G.N;
+  for (int i = threadIdx.x; i < G.N; i += kNT) {
+    const double xv = xt[i];
+    xs[i] = xv;
+    Et[(long)tau * G.N + i] = e_site(G, xv);
+  }
+  __syncthreads();
+  const int nb = G.N >> 1;
+  double2* ht = hop + (long)tau * 2 * G.N;
+  for (int f = 0; f < 4; ++f)
+    for (int k = threadIdx.x; k < nb; k += kNT) {
+      int i, j;
+      bond_sites(G.L, f, k, i, j);
+      double ch, sh;
+      bond_cs(G, xs, i, j, ch, sh);
+      ht[f * nb + k] = make_double2(ch, sh);
+    }
+}
+
+// w <- F_f w with the thread's bond coefficients hc[q] = (cosh, sinh) of bond
+// threadIdx.x + q kNT of family f.
+template <int BPT>
+__device__ __forceinline__ void apply_family_t(const SshGeom& G, double* w, int f, const double2 (&hc)[BPT]) {
+  const int nb = G.N >> 1;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int k = threadIdx.x + q * kNT;
+    if (k < nb) {
+      int i, j;
+      bond_sites(G.L, f, k, i, j);
+      const double wi = w[i], wj = w[j];
+      w[i] = hc[q].x * wi + hc[q].y * wj;
+      w[j] = hc[q].y * wi + hc[q].x * wj;
+    }
+  }
+}
+
+// out = M v (OP 0) or M^T v (OP 1) for right-hand side blockIdx.y, slice blockIdx.x:
+//   (M v)_tau   = v_tau - s_tau E_tau C(x_tau) v_{tau-1}
+//   (M^T v)_tau = v_tau - s_tau' C(x_tau')^T (E_tau' v_tau'),  tau' = tau + 1 (mod Ltau)
+// with s = +1, except s_0 = -1 (the +B_0 corner block); bond coefficients and
+// E from the field's tables.
 // With dotv != nullptr the workgroup also writes part[r * Ltau + tau] =
 // dotv_{r,tau} . out_{r,tau} (the p . M^T M p partials of CG).  PUPD (M
 // only): the operand is the CG direction p = z + beta_r in, formed on the fly
@@ -99,7 +150,8 @@ __device__ __forceinline__ double e_site(const SshGeom& G, double x) {
 // of p in pnew (a buffer other than `in`, so no workgroup reads a slice that
 // another one is rewriting).
 template <int OP, int BPT, bool PUPD>
-__global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __restrict__ x,
+__global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __restrict__ hop,
+                                                   const double* __restrict__ Et,
                                                    const double* __restrict__ in,
                                                    double* __restrict__ out,
                                                    const double* __restrict__ dotv,
@@ -108,35 +160,42 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __re
                                                    const CgState* __restrict__ st,
                                                    double* __restrict__ pnew) {
   extern __shared__ double sm[];
-  double* xs = sm;
-  double* w = sm + G.N;
+  double* w = sm;
   const int tau = blockIdx.x;
   const long ro = (long)blockIdx.y * G.d;
-  const int ts = OP == 0 ? tau : (tau + 1 == G.Ltau ? 0 : tau + 1);  // slice of x used
+  const int ts = OP == 0 ? tau : (tau + 1 == G.Ltau ? 0 : tau + 1);  // slice of the field used
   const int tv = OP == 0 ? (tau == 0 ? G.Ltau - 1 : tau - 1) : ts;   // slice of v transported
-  const double* xt = x + (long)ts * G.N;
+  const int nb = G.N >> 1;
+  const double2* ht = hop + (long)ts * 2 * G.N;
+  const double* Es = Et + (long)ts * G.N;
+  double2 hc[4][BPT];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int k = threadIdx.x + q * kNT;
+      hc[f][q] = k < nb ? ht[f * nb + k] : make_double2(0.0, 0.0);
+    }
   const double* vt = in + ro + (long)tv * G.N;
   const double beta = PUPD ? st[blockIdx.y].beta : 0.0;
   const double* zt = PUPD ? zv + ro + (long)tv * G.N : nullptr;
   for (int i = threadIdx.x; i < G.N; i += kNT) {
-    const double xv = xt[i];
-    xs[i] = xv;
     if (PUPD)
       w[i] = zt[i] + beta * vt[i];
     else
-      w[i] = OP == 0 ? vt[i] : e_site(G, xv) * vt[i];
+      w[i] = OP == 0 ? vt[i] : Es[i] * vt[i];
   }
   __syncthreads();
   if (OP == 0) {
 #pragma unroll
     for (int f = 3; f >= 0; --f) {
-      apply_family<BPT>(G, xs, w, f);
+      apply_family_t<BPT>(G, w, f, hc[f]);
       __syncthreads();
     }
   } else {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      apply_family<BPT>(G, xs, w, f);
+      apply_family_t<BPT>(G, w, f, hc[f]);
       __syncthreads();
     }
   }
@@ -147,7 +206,7 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __re
   const double* zi = PUPD ? zv + ro + (long)tau * G.N : nullptr;
   double* pn = PUPD ? pnew + ro + (long)tau * G.N : nullptr;
   for (int i = threadIdx.x; i < G.N; i += kNT) {
-    const double bw = OP == 0 ? e_site(G, xs[i]) * w[i] : w[i];
+    const double bw = OP == 0 ? Es[i] * w[i] : w[i];
     double v = vi[i];
     if (PUPD) {
       v = zi[i] + beta * v;
@@ -158,7 +217,7 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double* __re
     if (dotv != nullptr) acc += dotv[ro + (long)tau * G.N + i] * o;
   }
   if (dotv != nullptr) {
-    double* red = sm + 2 * G.N;  // kNT values past the slice buffers
+    double* red = sm + G.N;  // kNT values past the slice buffer
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int o = kNT / 2; o > 0; o >>= 1) {
@@ -411,6 +470,8 @@ struct fph_ssh_s {
   int bpt;
   bool have_field;
   double* x;     // the field [Ltau][N]
+  double2* hop;  // bond (cosh, sinh) per slice and family [Ltau][4][N/2]
+  double* Et;    // E of the field [Ltau][N]
   double* tmp;   // [max_rhs][d]
   double* r;     // CG residual
   double* p;     // CG direction
@@ -434,7 +495,7 @@ namespace {
     if (e_ != hipSuccess) return fph::record_hip_error(e_);  \
   } while (0)
 
-size_t apply_lds(const fph_ssh_s* c) { return (2 * (size_t)c->G.N + kNT) * sizeof(double); }
+size_t apply_lds(const fph_ssh_s* c) { return ((size_t)c->G.N + kNT) * sizeof(double); }
 size_t force_lds(const fph_ssh_s* c) { return 4 * (size_t)c->G.N * sizeof(double); }
 
 // Dynamic LDS above the default 64 KiB (L = 64: the force kernel takes 128 KiB).
@@ -456,9 +517,9 @@ hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, doubl
     hipError_t e = allow_lds(k_ssh_apply<OP, 8, PUPD>, lds);
     if (e != hipSuccess) return e;
   }
-#define SSH_APPLY_CASE(b)                                                                              \
-  hipLaunchKernelGGL((k_ssh_apply<OP, b, PUPD>), grid, dim3(kNT), lds, s, c->G, (const double*)c->x, in, \
-                     out, dotv, pt, zv, st, pnew)
+#define SSH_APPLY_CASE(b)                                                                      \
+  hipLaunchKernelGGL((k_ssh_apply<OP, b, PUPD>), grid, dim3(kNT), lds, s, c->G,                  \
+                     (const double2*)c->hop, (const double*)c->Et, in, out, dotv, pt, zv, st, pnew)
   switch (c->bpt) {
     case 1: SSH_APPLY_CASE(1); break;
     case 2: SSH_APPLY_CASE(2); break;
@@ -536,6 +597,8 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 #define SSH_ALLOC(ptr, bytes) \
   if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes));
   SSH_ALLOC(c->x, d * sizeof(double));
+  SSH_ALLOC(c->hop, 2 * d * sizeof(double2));
+  SSH_ALLOC(c->Et, d * sizeof(double));
   SSH_ALLOC(c->tmp, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->r, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->p, (size_t)max_rhs * d * sizeof(double));
@@ -560,7 +623,7 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 int fph_ssh_destroy(fph_ssh_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->x, c->tmp, c->r, c->p, c->p2, c->q, c->z, c->part, c->part2, c->st};
+  void* ptrs[] = {c->x, c->hop, c->Et, c->tmp, c->r, c->p, c->p2, c->q, c->z, c->part, c->part2, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -570,8 +633,11 @@ int fph_ssh_destroy(fph_ssh_t c) {
 
 int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream) {
   if (c == nullptr || x_dev == nullptr) return FPH_E_NULL;
-  SSH_CHECK(hipMemcpyAsync(c->x, x_dev, c->G.d * sizeof(double), hipMemcpyDeviceToDevice,
-                           (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  SSH_CHECK(hipMemcpyAsync(c->x, x_dev, c->G.d * sizeof(double), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_ssh_tables, dim3(c->G.Ltau), dim3(kNT), c->G.N * sizeof(double), s, c->G,
+                     (const double*)c->x, c->hop, c->Et);
+  SSH_CHECK(hipGetLastError());
   c->have_field = true;
   if (c->pc != nullptr) return fph_set_field(c->pc, x_dev, c->pc_a1, c->pc_a2, stream);
   return FPH_OK;
