@@ -251,3 +251,37 @@ def test_autograd_action():
     assert S_F.item() == pytest.approx(float(np.sum(phi * uo)), rel=1e-10)
     assert rel(xg.grad.cpu().numpy(), S.force(lat, g, x, phi)) < 1e-9
     assert rel(pg.grad.cpu().numpy(), 2.0 * uo) < 1e-9
+
+
+def test_hmc_preconditioned_matches_plain():
+    """SSH HMC with the Holstein preconditioner (FP64 solves to 1e-12) follows the same trajectory
+    as with plain CG, which the oracle pins above: momenta, field and energies agree."""
+    from paper_2203_01291_amd.hmc import PhononHMC
+    from paper_2203_01291_amd.solver import FermionSolver
+    from paper_2203_01291_amd.ssh import SSHSolver
+    p = get_config("c1")
+    g = 0.3
+    x = phonon_field(p)
+    rng = np.random.default_rng(51)
+    R = rng.standard_normal((2, p.Ltau, p.N))
+    Rm = rng.standard_normal((p.Ltau, p.N))
+    out = []
+    for pre in (False, True):
+        s = SSHSolver.from_params(p, g, max_rhs=2)
+        fs = FermionSolver.from_params(p, max_rhs=2)
+        if pre:
+            s.attach_preconditioner(fs, a1=0.15, a2=12.0)
+        h = PhononHMC(s, 1.0, 1.0, 0.02, Nt=10, nt=5, nfields=2, force_tol=1e-12, action_tol=1e-12,
+                      precond=pre, prec="f64")
+        xg = tgpu(x)
+        pg = torch.empty_like(xg)
+        st = h.trajectory(xg, tgpu(R), tgpu(Rm), 0.5, p_out=pg)
+        out.append((xg.cpu().numpy(), pg.cpu().numpy(), st))
+        h.close()
+    (x0, p0, s0), (x1, p1, s1) = out
+    assert s0["status"] & 1 and s1["status"] & 1
+    assert s1["cg_iters"] < s0["cg_iters"]
+    assert rel(p1, p0) < 1e-8 and rel(x1, x0) < 1e-8
+    for k in ("H_i", "H_f", "SF_f"):
+        assert s1[k] == pytest.approx(s0[k], abs=1e-7), k
+    assert s1["accepted"] == s0["accepted"]
