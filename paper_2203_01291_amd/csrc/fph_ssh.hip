@@ -8,9 +8,10 @@
 //
 // Kernels work one time slice per workgroup: the slice (N values) sits in
 // LDS and the four family factors are applied in place, one barrier apart;
-// every thread owns the same BPT bonds of each family.  Bond hoppings are
-// recomputed from x_tau (held in LDS) at each use: one expm1 per bond, no
-// tables in HBM.  FP64 throughout.
+// every thread owns the same BPT bonds of each family.  Setting the field
+// forms per-slice tables of the bond coefficients (cosh, sinh) and of E (one
+// expm1 per bond), which the operator kernels load into registers; the force
+// kernel forms them from x_tau in LDS.  FP64 throughout.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
