@@ -229,6 +229,112 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __r
   }
 }
 
+// q = M^T M p in one launch (N <= 2048, BPT <= 4), slice blockIdx.x of
+// right-hand side blockIdx.y: with a = tau - 1, c = tau + 1 (mod Ltau),
+//   y_tau = p_tau - s_tau E_tau C_tau p_a,   y_c = p_c - s_c E_c C_c p_tau,
+//   q_tau = y_tau - s_c C_c^T (E_c y_c),
+// the two forward products sharing the four family passes (two LDS
+// buffers), then the transposed product: y_c is formed twice, by this
+// workgroup and by the next one, instead of a launch and a round trip of M p
+// through memory.  dotv, part, PUPD, zv, st and pnew as for k_ssh_apply
+// (the dot is p . q with p the direction used).
+template <int BPT, bool PUPD>
+__global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __restrict__ hop,
+                                                 const double* __restrict__ Et,
+                                                 const double* __restrict__ in,
+                                                 double* __restrict__ out, bool dot,
+                                                 double* __restrict__ part,
+                                                 const double* __restrict__ zv,
+                                                 const CgState* __restrict__ st,
+                                                 double* __restrict__ pnew) {
+  constexpr int kOwn = 2 * BPT;  // sites per thread: N <= 2 * BPT * kNT
+  extern __shared__ double sm[];
+  double* wA = sm;
+  double* wB = sm + G.N;
+  const int tau = blockIdx.x;
+  const long ro = (long)blockIdx.y * G.d;
+  const int ta = tau == 0 ? G.Ltau - 1 : tau - 1;
+  const int tc = tau + 1 == G.Ltau ? 0 : tau + 1;
+  const double sb = tau == 0 ? -1.0 : 1.0;
+  const double sc = tc == 0 ? -1.0 : 1.0;
+  const int nb = G.N >> 1;
+  const double2* hb = hop + (long)tau * 2 * G.N;
+  const double2* hcp = hop + (long)tc * 2 * G.N;
+  double2 cB[4][BPT], cC[4][BPT];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int k = threadIdx.x + q * kNT;
+      cB[f][q] = k < nb ? hb[f * nb + k] : make_double2(0.0, 0.0);
+      cC[f][q] = k < nb ? hcp[f * nb + k] : make_double2(0.0, 0.0);
+    }
+  const double* Eb = Et + (long)tau * G.N;
+  const double* Ec = Et + (long)tc * G.N;
+  const double beta = PUPD ? st[blockIdx.y].beta : 0.0;
+  auto dir = [&](int t, int i) -> double {  // the direction p at slice t, site i
+    const long o = ro + (long)t * G.N + i;
+    return PUPD ? zv[o] + beta * in[o] : in[o];
+  };
+  double pb[kOwn], pc[kOwn], yb[kOwn];
+#pragma unroll
+  for (int m = 0; m < kOwn; ++m) {
+    const int i = threadIdx.x + m * kNT;
+    pb[m] = pc[m] = 0.0;
+    if (i < G.N) {
+      wA[i] = dir(ta, i);
+      pb[m] = dir(tau, i);
+      pc[m] = dir(tc, i);
+      wB[i] = pb[m];
+      if (PUPD) pnew[ro + (long)tau * G.N + i] = pb[m];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 3; f >= 0; --f) {
+    apply_family_t<BPT>(G, wA, f, cB[f]);
+    apply_family_t<BPT>(G, wB, f, cC[f]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < kOwn; ++m) {
+    const int i = threadIdx.x + m * kNT;
+    yb[m] = 0.0;
+    if (i < G.N) {
+      yb[m] = pb[m] - sb * Eb[i] * wA[i];
+      const double e = Ec[i];
+      wB[i] = e * (pc[m] - sc * e * wB[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    apply_family_t<BPT>(G, wB, f, cC[f]);
+    __syncthreads();
+  }
+  double acc = 0.0;
+  double* vo = out + ro + (long)tau * G.N;
+#pragma unroll
+  for (int m = 0; m < kOwn; ++m) {
+    const int i = threadIdx.x + m * kNT;
+    if (i < G.N) {
+      const double q = yb[m] - sc * wB[i];
+      vo[i] = q;
+      acc += pb[m] * q;
+    }
+  }
+  if (dot) {
+    double* red = sm + 2 * G.N;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kNT / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)blockIdx.y * G.Ltau + tau] = red[0];
+  }
+}
+
 // grad_tau += scale * sum_r dS_F/dx_tau with S_F = Phi . (M^T M)^{-1} Phi:
 //   dS_F/dx_{i,tau} = 2 s_tau sum_r y_{r,tau} . (dB_tau/dx_{i,tau}) u_{r,tau-1},  y = M u.
 // dB = d(diag E) C + diag(E) sum_f F_xe .. dF_f .. F_yo: the vector entering
@@ -531,13 +637,36 @@ hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, doubl
   return hipGetLastError();
 }
 
+// q = M^T M p in one launch when the lattice allows it (BPT <= 4); returns
+// false (nothing launched) otherwise.  With dot, part[r * Ltau + tau] = p . q.
+template <bool PUPD>
+bool launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s, bool dot,
+                      double* pt, const double* zv, double* pnew, hipError_t* err) {
+  if (c->bpt > 4) return false;
+  const dim3 grid(c->G.Ltau, nrhs);
+  const size_t lds = (2 * (size_t)c->G.N + kNT) * sizeof(double);
+  const double2* hop = c->hop;
+  const double* Et = c->Et;
+  const CgState* st = c->st;
+  switch (c->bpt) {
+    case 1: hipLaunchKernelGGL((k_ssh_mtm<1, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, zv, st, pnew); break;
+    case 2: hipLaunchKernelGGL((k_ssh_mtm<2, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, zv, st, pnew); break;
+    default: hipLaunchKernelGGL((k_ssh_mtm<4, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, zv, st, pnew); break;
+  }
+  *err = hipGetLastError();
+  return true;
+}
+
 // out = op(in); MTM goes through c->tmp (so in/out must not be c->tmp).  With
 // dotv (MTM only), c->part[r * Ltau + tau] receive the slices of dotv . out.
 hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, double* out, hipStream_t s,
                         const double* dotv = nullptr) {
   if (op == FPH_OP_M) return launch_apply_op<0>(c, nrhs, in, out, s);
   if (op == FPH_OP_MT) return launch_apply_op<1>(c, nrhs, in, out, s);
-  hipError_t e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
+  hipError_t e = hipSuccess;
+  if (dotv == nullptr && launch_mtm_fused<false>(c, nrhs, in, out, s, false, nullptr, nullptr, nullptr, &e))
+    return e;
+  e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
   if (e != hipSuccess) return e;
   return launch_apply_op<1>(c, nrhs, c->tmp, out, s, dotv);
 }
@@ -765,8 +894,13 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
     for (int k = 0; k < chunk; ++k, ++it) {
       // p = z + beta p (beta = 0 at the start, where p already holds z), formed
       // inside the M launch into pn; q = M^T M p with the p . q partials per slice
-      SSH_CHECK((launch_apply_op<0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));
-      SSH_CHECK(launch_apply_op<1>(c, nrhs, c->tmp, c->q, s, pn, nullptr, nullptr, c->part2));
+      hipError_t fe = hipSuccess;
+      if (launch_mtm_fused<true>(c, nrhs, pc, c->q, s, true, c->part2, z, pn, &fe)) {
+        SSH_CHECK(fe);
+      } else {
+        SSH_CHECK((launch_apply_op<0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));
+        SSH_CHECK(launch_apply_op<1>(c, nrhs, c->tmp, c->q, s, pn, nullptr, nullptr, c->part2));
+      }
       // alpha, u += alpha p, r -= alpha q with the |r|^2 partials (into part:
       // the p.q partials in part2 are still being read by other blocks)
       hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks, nrhs), dim3(256), 0, s, d, c->st, c->G.Ltau,
