@@ -85,6 +85,49 @@ struct CgState {
   int iters, status, done, maxiter;
 };
 
+__device__ double sum_parts(const double* part, int nb) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// One CG step's scalars from |r|^2 = v and r.z = vz (in place): iteration
+// count, non-finite and breakdown tests, convergence and cap, beta = rz'/rz.
+__device__ void cg_step2(CgState& S, double v, double vz) {
+  if (S.done) {
+    S.alpha = S.beta = 0.0;
+    return;
+  }
+  S.iters += 1;
+  if (!isfinite(v) || !isfinite(vz)) {
+    S.status |= FPH_ST_NONFINITE;
+    S.done = 1;
+    S.beta = 0.0;
+    return;
+  }
+  S.rr = v;
+  if (v <= S.tol2 * S.bb || S.iters >= S.maxiter) {
+    S.done = 1;
+    return;
+  }
+  if (!(vz > 0.0)) {
+    S.status |= FPH_ST_BREAKDOWN;
+    S.done = 1;
+    return;
+  }
+  S.beta = vz / S.rz;
+  S.rz = vz;
+}
+
 __device__ __forceinline__ double e_site(const SshGeom& G, double x) {
   return exp(-G.dtau * (G.alpha * x - G.mu));
 }
@@ -238,6 +281,13 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __r
 // workgroup and by the next one, instead of a launch and a round trip of M p
 // through memory.  dotv, part, PUPD, zv, st and pnew as for k_ssh_apply
 // (the dot is p . q with p the direction used).
+// In CG (PUPD) the kernel also finishes the previous step's scalars: every
+// workgroup of right-hand side r forms beta and the convergence decision
+// from |r|^2 and r.z partials (part_rr, part_rz: kRedBlocks each) and the
+// state st_old[r], all the same way; workgroup 0 stores the new state in
+// st_new[r] (a second buffer: no workgroup reads what another one writes).
+// With from_state the state is taken as it is (first step of a chunk).  A
+// finished right-hand side is skipped.
 template <int BPT, bool PUPD>
 __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __restrict__ hop,
                                                  const double* __restrict__ Et,
@@ -245,7 +295,10 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
                                                  double* __restrict__ out, bool dot,
                                                  double* __restrict__ part,
                                                  const double* __restrict__ zv,
-                                                 const CgState* __restrict__ st,
+                                                 const CgState* __restrict__ st_old,
+                                                 CgState* __restrict__ st_new,
+                                                 const double* __restrict__ part_rr,
+                                                 const double* __restrict__ part_rz, int from_state,
                                                  double* __restrict__ pnew) {
   constexpr int kOwn = 2 * BPT;  // sites per thread: N <= 2 * BPT * kNT
   extern __shared__ double sm[];
@@ -271,7 +324,19 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
     }
   const double* Eb = Et + (long)tau * G.N;
   const double* Ec = Et + (long)tc * G.N;
-  const double beta = PUPD ? st[blockIdx.y].beta : 0.0;
+  double beta = 0.0;
+  if (PUPD) {
+    const int r = blockIdx.y;
+    CgState S = st_old[r];
+    if (!from_state) {
+      const double v = sum_parts(part_rr + (long)r * kRedBlocks, kRedBlocks);
+      const double vz = part_rz == part_rr ? v : sum_parts(part_rz + (long)r * kRedBlocks, kRedBlocks);
+      cg_step2(S, v, vz);  // the same inputs and steps in every thread: a uniform result
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_new[r] = S;
+    if (S.done) return;
+    beta = S.beta;
+  }
   auto dir = [&](int t, int i) -> double {  // the direction p at slice t, site i
     const long o = ro + (long)t * G.N + i;
     return PUPD ? zv[o] + beta * in[o] : in[o];
@@ -437,20 +502,6 @@ __global__ void __launch_bounds__(256) k_dot_parts(long d, const double* __restr
   if (threadIdx.x == 0) part[(long)r * gridDim.x + blockIdx.x] = sh[0];
 }
 
-__device__ double sum_parts(const double* part, int nb) {
-  __shared__ double sh[256];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double v = sh[0];
-  __syncthreads();
-  return v;
-}
 
 // stage 0: rr = |r|^2, rz = r.z at the start; stage 2: rr' = |r|^2
 // (convergence and cap tests), rz' = r.z, beta = rz'/rz.  (alpha is formed
@@ -481,29 +532,7 @@ __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const doub
     }
     return;
   }
-  if (S.done) {
-    S.alpha = S.beta = 0.0;
-    return;
-  }
-  S.iters += 1;
-  if (!isfinite(v) || !isfinite(vz)) {
-    S.status |= FPH_ST_NONFINITE;
-    S.done = 1;
-    S.beta = 0.0;
-    return;
-  }
-  S.rr = v;
-  if (v <= S.tol2 * S.bb || S.iters >= S.maxiter) {
-    S.done = 1;
-    return;
-  }
-  if (!(vz > 0.0)) {
-    S.status |= FPH_ST_BREAKDOWN;
-    S.done = 1;
-    return;
-  }
-  S.beta = vz / S.rz;
-  S.rz = vz;
+  cg_step2(S, v, vz);
 }
 
 // alpha = rz / p.q from the operator's per-slice partials (every block sums
@@ -587,7 +616,8 @@ struct fph_ssh_s {
   double* z;     // preconditioned residual
   double* part;  // [max_rhs][kRedBlocks]
   double* part2; // r.z partials
-  CgState* st;   // [max_rhs]
+  CgState* st;   // [2][max_rhs]: the fused CG alternates between the two
+  double* part3; // p.q partials of the fused CG
   CgState* st_host;
   fph_handle_t pc;  // Holstein handle whose preconditioner serves the solves (or NULL)
   int pc_max_rhs;
@@ -639,22 +669,38 @@ hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, doubl
 
 // q = M^T M p in one launch when the lattice allows it (BPT <= 4); returns
 // false (nothing launched) otherwise.  With dot, part[r * Ltau + tau] = p . q.
+bool mtm_fusable(const fph_ssh_s* c) { return c->bpt <= 4; }
+
+// CG arguments of a fused launch (see k_ssh_mtm).
+struct MtmCg {
+  const double* zv = nullptr;
+  double* pnew = nullptr;
+  const CgState* st_old = nullptr;
+  CgState* st_new = nullptr;
+  const double* part_rr = nullptr;
+  const double* part_rz = nullptr;
+  int from_state = 1;
+};
+
+// q = M^T M p in one launch (only where mtm_fusable).  With dot,
+// pt[r * Ltau + tau] = p . q.
 template <bool PUPD>
-bool launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s, bool dot,
-                      double* pt, const double* zv, double* pnew, hipError_t* err) {
-  if (c->bpt > 4) return false;
+hipError_t launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s,
+                            bool dot, double* pt, const MtmCg& a) {
   const dim3 grid(c->G.Ltau, nrhs);
   const size_t lds = (2 * (size_t)c->G.N + kNT) * sizeof(double);
   const double2* hop = c->hop;
   const double* Et = c->Et;
-  const CgState* st = c->st;
+#define SSH_MTM_CASE(b)                                                                                 \
+  hipLaunchKernelGGL((k_ssh_mtm<b, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, a.zv, \
+                     a.st_old, a.st_new, a.part_rr, a.part_rz, a.from_state, a.pnew)
   switch (c->bpt) {
-    case 1: hipLaunchKernelGGL((k_ssh_mtm<1, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, zv, st, pnew); break;
-    case 2: hipLaunchKernelGGL((k_ssh_mtm<2, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, zv, st, pnew); break;
-    default: hipLaunchKernelGGL((k_ssh_mtm<4, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, zv, st, pnew); break;
+    case 1: SSH_MTM_CASE(1); break;
+    case 2: SSH_MTM_CASE(2); break;
+    default: SSH_MTM_CASE(4); break;
   }
-  *err = hipGetLastError();
-  return true;
+#undef SSH_MTM_CASE
+  return hipGetLastError();
 }
 
 // out = op(in); MTM goes through c->tmp (so in/out must not be c->tmp).  With
@@ -663,10 +709,8 @@ hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, 
                         const double* dotv = nullptr) {
   if (op == FPH_OP_M) return launch_apply_op<0>(c, nrhs, in, out, s);
   if (op == FPH_OP_MT) return launch_apply_op<1>(c, nrhs, in, out, s);
-  hipError_t e = hipSuccess;
-  if (dotv == nullptr && launch_mtm_fused<false>(c, nrhs, in, out, s, false, nullptr, nullptr, nullptr, &e))
-    return e;
-  e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
+  if (dotv == nullptr && mtm_fusable(c)) return launch_mtm_fused<false>(c, nrhs, in, out, s, false, nullptr, MtmCg{});
+  hipError_t e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
   if (e != hipSuccess) return e;
   return launch_apply_op<1>(c, nrhs, c->tmp, out, s, dotv);
 }
@@ -738,7 +782,8 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
   // partials: kRedBlocks per right-hand side from the vector kernels, Ltau from the operator
   SSH_ALLOC(c->part, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
   SSH_ALLOC(c->part2, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
-  SSH_ALLOC(c->st, (size_t)max_rhs * sizeof(CgState));
+  SSH_ALLOC(c->part3, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
+  SSH_ALLOC(c->st, 2 * (size_t)max_rhs * sizeof(CgState));
 #undef SSH_ALLOC
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->st_host, (size_t)max_rhs * sizeof(CgState), hipHostMallocDefault);
@@ -753,7 +798,7 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 int fph_ssh_destroy(fph_ssh_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->x, c->hop, c->Et, c->tmp, c->r, c->p, c->p2, c->q, c->z, c->part, c->part2, c->st};
+  void* ptrs[] = {c->x, c->hop, c->Et, c->tmp, c->r, c->p, c->p2, c->q, c->z, c->part, c->part2, c->part3, c->st};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -890,32 +935,47 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, (const double*)c->part, p2, c->st);
   SSH_CHECK(hipGetLastError());
   const int matvecs = opts->zero_guess ? 0 : 1;
+  const bool fused = mtm_fusable(c);
+  CgState* sa = c->st;               // the current state
+  CgState* sb = c->st + c->max_rhs;  // the fused CG's next state
   for (int it = 0;;) {
     for (int k = 0; k < chunk; ++k, ++it) {
       // p = z + beta p (beta = 0 at the start, where p already holds z), formed
       // inside the M launch into pn; q = M^T M p with the p . q partials per slice
-      hipError_t fe = hipSuccess;
-      if (launch_mtm_fused<true>(c, nrhs, pc, c->q, s, true, c->part2, z, pn, &fe)) {
-        SSH_CHECK(fe);
+      const double* pq = c->part2;
+      if (fused) {
+        // also finishes the previous step's scalars (sa -> sb)
+        MtmCg a;
+        a.zv = z;
+        a.pnew = pn;
+        a.st_old = sa;
+        a.st_new = sb;
+        a.part_rr = c->part;
+        a.part_rz = p2;
+        a.from_state = k == 0;
+        SSH_CHECK(launch_mtm_fused<true>(c, nrhs, pc, c->q, s, true, c->part3, a));
+        std::swap(sa, sb);
+        pq = c->part3;
       } else {
-        SSH_CHECK((launch_apply_op<0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));
+        SSH_CHECK((launch_apply_op<0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));  // state in c->st
         SSH_CHECK(launch_apply_op<1>(c, nrhs, c->tmp, c->q, s, pn, nullptr, nullptr, c->part2));
       }
       // alpha, u += alpha p, r -= alpha q with the |r|^2 partials (into part:
-      // the p.q partials in part2 are still being read by other blocks)
-      hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks, nrhs), dim3(256), 0, s, d, c->st, c->G.Ltau,
-                         (const double*)c->part2, (const double*)pn, (const double*)c->q, u_dev, c->r,
-                         c->part);
+      // the p.q partials are still being read by other blocks)
+      hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks, nrhs), dim3(256), 0, s, d, sa, c->G.Ltau, pq,
+                         (const double*)pn, (const double*)c->q, u_dev, c->r, c->part);
       SSH_CHECK(hipGetLastError());
       rc = precondition();
       if (rc != FPH_OK) return rc;
       if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
-      hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part, p2,
-                         c->st);
-      SSH_CHECK(hipGetLastError());
+      if (!fused || k + 1 == chunk) {  // the fused launch of the next step does it otherwise
+        hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part,
+                           p2, sa);
+        SSH_CHECK(hipGetLastError());
+      }
       std::swap(pc, pn);
     }
-    SSH_CHECK(hipMemcpyAsync(c->st_host, c->st, nrhs * sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SSH_CHECK(hipMemcpyAsync(c->st_host, sa, nrhs * sizeof(CgState), hipMemcpyDeviceToHost, s));
     SSH_CHECK(hipStreamSynchronize(s));
     bool all = true;
     for (int r = 0; r < nrhs; ++r) all = all && c->st_host[r].done;
