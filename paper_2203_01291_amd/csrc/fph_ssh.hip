@@ -85,19 +85,24 @@ struct CgState {
   int iters, status, done, maxiter;
 };
 
+// Sum of acc over a 256-thread workgroup, returned to every thread: a
+// shuffle tree inside each wave, then the four wave sums in a fixed order
+// (deterministic; one barrier pair).
+__device__ double block_sum(double acc) {
+  __shared__ double sh[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  const double v = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();  // sh may be reused by the next call
+  return v;
+}
+
 __device__ double sum_parts(const double* part, int nb) {
-  __shared__ double sh[256];
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double v = sh[0];
-  __syncthreads();
-  return v;
+  return block_sum(acc);
 }
 
 // One CG step's scalars from |r|^2 = v and r.z = vz (in place): iteration
@@ -261,14 +266,8 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __r
     if (dotv != nullptr) acc += dotv[ro + (long)tau * G.N + i] * o;
   }
   if (dotv != nullptr) {
-    double* red = sm + G.N;  // kNT values past the slice buffer
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = kNT / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(long)blockIdx.y * G.Ltau + tau] = red[0];
+    const double v = block_sum(acc);
+    if (threadIdx.x == 0) part[(long)blockIdx.y * G.Ltau + tau] = v;
   }
 }
 
@@ -389,14 +388,8 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
     }
   }
   if (dot) {
-    double* red = sm + 2 * G.N;
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = kNT / 2; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(long)blockIdx.y * G.Ltau + tau] = red[0];
+    const double v = block_sum(acc);
+    if (threadIdx.x == 0) part[(long)blockIdx.y * G.Ltau + tau] = v;
   }
 }
 
@@ -492,14 +485,8 @@ __global__ void __launch_bounds__(256) k_dot_parts(long d, const double* __restr
   c += (long)r * d;
   double acc = 0.0;
   for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) acc += a[k] * c[k];
-  __shared__ double sh[256];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(long)r * gridDim.x + blockIdx.x] = sh[0];
+  const double v = block_sum(acc);
+  if (threadIdx.x == 0) part[(long)r * gridDim.x + blockIdx.x] = v;
 }
 
 
@@ -571,14 +558,8 @@ __global__ void __launch_bounds__(256) k_cg_xr(long d, CgState* __restrict__ st,
     r[o + i] = rv;
     acc += rv * rv;
   }
-  __shared__ double sh[256];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = sh[0];
+  const double v = block_sum(acc);
+  if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = v;
 }
 
 // out[r] = sum of the kRedBlocks partials of right-hand side r, in block order
