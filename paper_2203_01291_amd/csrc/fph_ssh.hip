@@ -613,7 +613,7 @@ namespace {
     if (e_ != hipSuccess) return fph::record_hip_error(e_);  \
   } while (0)
 
-size_t apply_lds(const fph_ssh_s* c) { return ((size_t)c->G.N + kNT) * sizeof(double); }
+size_t apply_lds(const fph_ssh_s* c) { return (size_t)c->G.N * sizeof(double); }
 size_t force_lds(const fph_ssh_s* c) { return 4 * (size_t)c->G.N * sizeof(double); }
 
 // Dynamic LDS above the default 64 KiB (L = 64: the force kernel takes 128 KiB).
@@ -669,7 +669,7 @@ template <bool PUPD>
 hipError_t launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s,
                             bool dot, double* pt, const MtmCg& a) {
   const dim3 grid(c->G.Ltau, nrhs);
-  const size_t lds = (2 * (size_t)c->G.N + kNT) * sizeof(double);
+  const size_t lds = 2 * (size_t)c->G.N * sizeof(double);
   const double2* hop = c->hop;
   const double* Et = c->Et;
 #define SSH_MTM_CASE(b)                                                                                 \
