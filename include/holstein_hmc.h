@@ -478,8 +478,10 @@ int pcg_solve_concurrent(int32_t n, fph_handle_t const* h, const int32_t* nrhs,
 
 /* hmc_trajectory(hh[k], x_dev[k], R_fields_dev[k], R_mom_dev[k], r_uniform[k],
  * p_out_dev ? p_out_dev[k] : NULL, &stats_host[k], streams[k]) for k < n,
- * concurrently; the contexts must sit on distinct solver handles.  p_out_dev
- * and stats_host may be NULL. */
+ * concurrently; the contexts must sit on distinct operators (solver handles
+ * or SSH contexts), and no Holstein handle may serve two of them, also as an
+ * SSH context's preconditioner (FPH_E_ARG otherwise).  p_out_dev and
+ * stats_host may be NULL. */
 int hmc_trajectory_concurrent(int32_t n, fph_hmc_t const* hh, double* const* x_dev,
                               const double* const* R_fields_dev, const double* const* R_mom_dev,
                               const double* r_uniform, double* const* p_out_dev,

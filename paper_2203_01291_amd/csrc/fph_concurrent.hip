@@ -76,8 +76,16 @@ int hmc_trajectory_concurrent(int32_t n, fph_hmc_t const* hh, double* const* x_d
     return FPH_E_NULL;
   for (int k = 0; k < n; ++k) {
     if (hh[k] == nullptr) return FPH_E_NULL;
-    for (int j = 0; j < k; ++j)  // distinct contexts on distinct solver handles
-      if (hh[j] == hh[k] || fph::hmc_operator(hh[j]) == fph::hmc_operator(hh[k])) return FPH_E_ARG;
+    // distinct contexts on distinct operators; no Holstein handle used twice,
+    // also as the preconditioner of an SSH context
+    const void* ok_ = fph::hmc_operator(hh[k]);
+    const void* ak = fph::hmc_aux(hh[k]);
+    for (int j = 0; j < k; ++j) {
+      const void* oj = fph::hmc_operator(hh[j]);
+      const void* aj = fph::hmc_aux(hh[j]);
+      if (hh[j] == hh[k] || oj == ok_ || (aj && (aj == ak || aj == ok_)) || (ak && ak == oj))
+        return FPH_E_ARG;
+    }
   }
   if (!distinct_streams(n, streams)) return FPH_E_ARG;
   return run_threads(n, [&](int k) {

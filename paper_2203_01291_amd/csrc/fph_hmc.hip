@@ -413,6 +413,8 @@ hipError_t lambda_force_into(const fph_hmc_s* c, int nrhs, const double* b, cons
 
 }  // namespace
 
+fph_handle_t fph::hmc_aux(fph_hmc_t c) { return (c && c->ssh) ? fph::ssh_precond(c->ssh) : nullptr; }
+
 const void* fph::hmc_operator(fph_hmc_t c) {
   if (c == nullptr) return nullptr;
   return c->h ? (const void*)c->h : (const void*)c->ssh;

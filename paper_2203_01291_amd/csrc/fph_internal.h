@@ -20,4 +20,9 @@ const void* hmc_operator(fph_hmc_t c);
 // output may be NULL).
 int ssh_info(fph_ssh_t c, fph_lattice_t* lat, int32_t* max_rhs, double* g);
 
+// The Holstein handle whose preconditioner an SSH context uses (or NULL),
+// and the one under an HMC context on an SSH context (NULL otherwise).
+fph_handle_t ssh_precond(fph_ssh_t c);
+fph_handle_t hmc_aux(fph_hmc_t c);
+
 }  // namespace fph

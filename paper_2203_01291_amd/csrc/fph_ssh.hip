@@ -992,6 +992,8 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
 
 }  // extern "C"
 
+fph_handle_t fph::ssh_precond(fph_ssh_t c) { return c ? c->pc : nullptr; }
+
 int fph::ssh_info(fph_ssh_t c, fph_lattice_t* lat, int32_t* max_rhs, double* g) {
   if (c == nullptr) return FPH_E_NULL;
   if (lat) {
