@@ -156,3 +156,81 @@ def test_hmc_reversible_and_second_order():
     assert np.abs(xb - x).max() < 1e-10 and np.abs(pb + out["p_i"]).max() < 1e-10
     dh = [abs(S.hmc_update(lat, g, om, 1.0, 0.4 / n, n, 2, x, R, Rm, 0.5)["dH"]) for n in (4, 8)]
     assert 3.3 < dh[0] / dh[1] < 4.7, dh
+
+
+def test_planted_mistakes_fail_the_pins(monkeypatch):
+    """Plausible mistakes planted in the oracle each fail one of the pins above: the sign of the
+    coupling in t_b, a dropped on-site term of the force, and the direction of dt_b/dx."""
+    import oracle.ssh as mod
+
+    # 1. t_b = t + g (x_j - x_i): the hand values around a displaced site catch it
+    good = mod.hoppings
+    flipped = lambda lat, g, x_tau: good(lat, -g, x_tau)
+    monkeypatch.setattr(mod, "hoppings", flipped)
+    with pytest.raises(AssertionError):
+        test_bond_factor_closed_form_and_hand_values()
+    monkeypatch.setattr(mod, "hoppings", good)
+
+    lat = lat4(alpha=0.7)
+    x = field(lat, 5)
+    phi = np.random.default_rng(6).standard_normal((1, lat.Ltau, lat.N))
+    fc = S.force_complex_step(lat, 0.45, x, phi)
+
+    # 2. the on-site term of dB/dx dropped: complex step catches it
+    good_E = mod.lat_mod.E_field
+    monkeypatch.setattr(mod, "dM_dx", _dM_dx_without_onsite)
+    f = mod.force(lat, 0.45, x, phi)
+    assert np.abs(f - fc).max() > 1e-3 * np.abs(fc).max()
+    monkeypatch.undo()
+
+    # 3. dt_b/dx with the bond's ends swapped: complex step catches it
+    monkeypatch.setattr(mod, "dM_dx", _dM_dx_swapped_ends)
+    f = mod.force(lat, 0.45, x, phi)
+    assert np.abs(f - fc).max() > 1e-3 * np.abs(fc).max()
+    monkeypatch.undo()
+    assert mod.lat_mod.E_field is good_E
+
+
+def _dM_dx_variant(lat, g, x, tau, i, onsite=True, swap=False):
+    # a copy of oracle.ssh.dM_dx with one term changed (planted mistakes)
+    N, T = lat.N, lat.Ltau
+    E = Lm.E_field(lat, x)[tau]
+    hp = S.hoppings(lat, g, x[tau])
+    Ks = [S.family_hopping(lat, hp[f]) for f in S.FAMILIES]
+    Fs = [scipy.linalg.expm(-lat.dtau * K) for K in Ks]
+    C = Fs[0] @ Fs[1] @ Fs[2] @ Fs[3]
+    dC = np.zeros((N, N))
+    fam = Lm.bond_families(lat.L)
+    for k, f in enumerate(S.FAMILIES):
+        dK = np.zeros((N, N))
+        for a, b in fam[f]:
+            dt = g * ((i == b) - (i == a)) if swap else g * ((i == a) - (i == b))
+            dK[a, b] -= dt
+            dK[b, a] -= dt
+        if not dK.any():
+            continue
+        dF = scipy.linalg.expm_frechet(-lat.dtau * Ks[k], -lat.dtau * dK, compute_expm=False)
+        left, right = np.eye(N), np.eye(N)
+        for m in range(k):
+            left = left @ Fs[m]
+        for m in range(k + 1, 4):
+            right = right @ Fs[m]
+        dC += left @ dF @ right
+    dE = np.zeros(N)
+    if onsite:
+        dE[i] = -lat.dtau * lat.alpha * E[i]
+    dB = dE[:, None] * C + E[:, None] * dC
+    dM = np.zeros((N * T, N * T))
+    if tau >= 1:
+        dM[tau * N:(tau + 1) * N, (tau - 1) * N:tau * N] = -dB
+    else:
+        dM[0:N, (T - 1) * N:T * N] = dB
+    return dM
+
+
+def _dM_dx_without_onsite(lat, g, x, tau, i):
+    return _dM_dx_variant(lat, g, x, tau, i, onsite=False)
+
+
+def _dM_dx_swapped_ends(lat, g, x, tau, i):
+    return _dM_dx_variant(lat, g, x, tau, i, swap=True)
