@@ -25,7 +25,8 @@
 namespace {
 
 constexpr int kNT = 256;        // threads of a slice workgroup
-constexpr int kRedBlocks = 256;  // partial sums per right-hand side in the CG reductions
+constexpr int kRedBlocks = 256;  // partial sums per right-hand side of the dot-product kernel
+constexpr int kXrBlocks = 512;   // |r|^2 partials per right-hand side of the CG update
 constexpr int kMaxChunk = 4096;
 
 struct SshGeom {
@@ -282,7 +283,7 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __r
 // (the dot is p . q with p the direction used).
 // In CG (PUPD) the kernel also finishes the previous step's scalars: every
 // workgroup of right-hand side r forms beta and the convergence decision
-// from |r|^2 and r.z partials (part_rr, part_rz: kRedBlocks each) and the
+// from |r|^2 and r.z partials (part_rr: kXrBlocks, part_rz: nbz each) and the
 // state st_old[r], all the same way; workgroup 0 stores the new state in
 // st_new[r] (a second buffer: no workgroup reads what another one writes).
 // With from_state the state is taken as it is (first step of a chunk).  A
@@ -297,7 +298,8 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
                                                  const CgState* __restrict__ st_old,
                                                  CgState* __restrict__ st_new,
                                                  const double* __restrict__ part_rr,
-                                                 const double* __restrict__ part_rz, int from_state,
+                                                 const double* __restrict__ part_rz, int nbz,
+                                                 int from_state,
                                                  double* __restrict__ pnew) {
   constexpr int kOwn = 2 * BPT;  // sites per thread: N <= 2 * BPT * kNT
   extern __shared__ double sm[];
@@ -328,8 +330,8 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
     const int r = blockIdx.y;
     CgState S = st_old[r];
     if (!from_state) {
-      const double v = sum_parts(part_rr + (long)r * kRedBlocks, kRedBlocks);
-      const double vz = part_rz == part_rr ? v : sum_parts(part_rz + (long)r * kRedBlocks, kRedBlocks);
+      const double v = sum_parts(part_rr + (long)r * kXrBlocks, kXrBlocks);
+      const double vz = part_rz == part_rr ? v : sum_parts(part_rz + (long)r * nbz, nbz);
       cg_step2(S, v, vz);  // the same inputs and steps in every thread: a uniform result
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st_new[r] = S;
@@ -494,12 +496,12 @@ __global__ void __launch_bounds__(256) k_dot_parts(long d, const double* __restr
 // (convergence and cap tests), rz' = r.z, beta = rz'/rz.  (alpha is formed
 // by k_cg_xr.)
 // part2 holds the r.z partials (part2 == part without a preconditioner, z = r).
-__global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const double* __restrict__ part,
+__global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, int nb2, const double* __restrict__ part,
                                                    const double* __restrict__ part2,
                                                    CgState* __restrict__ st) {
   const int r = blockIdx.x;
   const double v = sum_parts(part + (long)r * nb, nb);
-  const double vz = part2 == part ? v : sum_parts(part2 + (long)r * nb, nb);
+  const double vz = part2 == part ? v : sum_parts(part2 + (long)r * nb2, nb2);
   if (threadIdx.x != 0) return;
   CgState& S = st[r];
   if (stage == 0) {
@@ -525,7 +527,7 @@ __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, const doub
 // alpha = rz / p.q from the operator's per-slice partials (every block sums
 // them in the same order, so all blocks take the same decision; block 0
 // records it), then u += alpha p, r -= alpha q, and part[k][block] = the
-// block's share of |r|^2 (grid: kRedBlocks x nrhs).  A finished right-hand
+// block's share of |r|^2 (grid: kXrBlocks x nrhs).  A finished right-hand
 // side is left alone; its partials are then stale and its scalars ignore them.
 __global__ void __launch_bounds__(256) k_cg_xr(long d, CgState* __restrict__ st, int npq,
                                                const double* __restrict__ part_pq,
@@ -660,6 +662,7 @@ struct MtmCg {
   CgState* st_new = nullptr;
   const double* part_rr = nullptr;
   const double* part_rz = nullptr;
+  int nbz = kRedBlocks;  // r.z partials per right-hand side (kXrBlocks when part_rz == part_rr)
   int from_state = 1;
 };
 
@@ -674,7 +677,7 @@ hipError_t launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, doub
   const double* Et = c->Et;
 #define SSH_MTM_CASE(b)                                                                                 \
   hipLaunchKernelGGL((k_ssh_mtm<b, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, a.zv, \
-                     a.st_old, a.st_new, a.part_rr, a.part_rz, a.from_state, a.pnew)
+                     a.st_old, a.st_new, a.part_rr, a.part_rz, a.nbz, a.from_state, a.pnew)
   switch (c->bpt) {
     case 1: SSH_MTM_CASE(1); break;
     case 2: SSH_MTM_CASE(2); break;
@@ -761,7 +764,7 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
   SSH_ALLOC(c->q, (size_t)max_rhs * d * sizeof(double));
   SSH_ALLOC(c->z, (size_t)max_rhs * d * sizeof(double));
   // partials: kRedBlocks per right-hand side from the vector kernels, Ltau from the operator
-  SSH_ALLOC(c->part, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
+  SSH_ALLOC(c->part, (size_t)max_rhs * (lat->Ltau > kXrBlocks ? lat->Ltau : kXrBlocks) * sizeof(double));
   SSH_ALLOC(c->part2, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
   SSH_ALLOC(c->part3, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
   SSH_ALLOC(c->st, 2 * (size_t)max_rhs * sizeof(CgState));
@@ -913,7 +916,8 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   double* pn = c->p2;  // receives the next one
   SSH_CHECK(dots(c, nrhs, c->r, c->r, s));
   if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
-  hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, (const double*)c->part, p2, c->st);
+  hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 0, kRedBlocks, kRedBlocks, (const double*)c->part,
+                     p2, c->st);
   SSH_CHECK(hipGetLastError());
   const int matvecs = opts->zero_guess ? 0 : 1;
   const bool fused = mtm_fusable(c);
@@ -933,6 +937,7 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
         a.st_new = sb;
         a.part_rr = c->part;
         a.part_rz = p2;
+        a.nbz = pre ? kRedBlocks : kXrBlocks;
         a.from_state = k == 0;
         SSH_CHECK(launch_mtm_fused<true>(c, nrhs, pc, c->q, s, true, c->part3, a));
         std::swap(sa, sb);
@@ -943,14 +948,15 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
       }
       // alpha, u += alpha p, r -= alpha q with the |r|^2 partials (into part:
       // the p.q partials are still being read by other blocks)
-      hipLaunchKernelGGL(k_cg_xr, dim3(kRedBlocks, nrhs), dim3(256), 0, s, d, sa, c->G.Ltau, pq,
+      hipLaunchKernelGGL(k_cg_xr, dim3(kXrBlocks, nrhs), dim3(256), 0, s, d, sa, c->G.Ltau, pq,
                          (const double*)pn, (const double*)c->q, u_dev, c->r, c->part);
       SSH_CHECK(hipGetLastError());
       rc = precondition();
       if (rc != FPH_OK) return rc;
       if (pre) SSH_CHECK(dots(c, nrhs, c->r, c->z, s, c->part2));
       if (!fused || k + 1 == chunk) {  // the fused launch of the next step does it otherwise
-        hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kRedBlocks, (const double*)c->part,
+        hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kXrBlocks, pre ? kRedBlocks : kXrBlocks,
+                           (const double*)c->part,
                            p2, sa);
         SSH_CHECK(hipGetLastError());
       }
