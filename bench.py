@@ -519,7 +519,39 @@ def cpu_baseline(p, golden_iters):
                   f"{per_iter * 1e3:.2f} ms/iteration, scaled by the oracle's "
                   f"{golden_iters} iterations to 1e-8 (tests/golden/oracle_iterations.json)",
         "host_threads_available": os.cpu_count(),
+        "host_cpu": host_cpu_model(),
+        "blas_threads": blas_threads(),
     }
+
+
+def host_cpu_model():
+    """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def blas_threads():
+    """Threads of the BLAS numpy links against (the CG's SpMV is scipy's own
+    single-threaded code; BLAS serves only its dot products)."""
+    try:
+        from threadpoolctl import threadpool_info
+        return [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
+    except Exception:
+        return None
 
 
 # HBM traffic of the roofline kernel from rocprofv3 --pmc FETCH_SIZE and

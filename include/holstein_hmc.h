@@ -197,13 +197,16 @@ int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
               const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
               void* stream);
 
-/* grad_dev[Ltau][N] += scale * sum_r dS_F/dx for the solutions
+/* grad_dev[Ltau][N] += scale * s * sum_r dS_F/dx for the solutions
  * u_dev[nrhs][Ltau][N] of the current field (Eq. dSF_dx with Lambda = I):
  *   dS_F/dx_{i,tau} = -2 dtau alpha (u - y)_{i,tau} y_{i,tau},
  *   y_tau = E_tau * (C u~_{tau-1}),
- * so that (u - y) = M u.  Enqueue only. */
+ * so that (u - y) = M u.  s = *scale_dev, one double in device memory read
+ * when the kernel runs (an upstream gradient that stays on the device), or
+ * 1 when scale_dev is NULL.  scale must be finite (FPH_E_ARG).  Enqueue
+ * only. */
 int fermion_force(fph_handle_t h, int32_t nrhs, const double* u_dev,
-                  double* grad_dev, double scale, void* stream);
+                  double* grad_dev, double scale, const double* scale_dev, void* stream);
 
 /* out_dev[r] = b_r . u_r in FP64 for r < nrhs (S_F of Eq. Sf_Psi).
  * Enqueue only. */
@@ -611,13 +614,15 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev,
 int ssh_action(fph_ssh_t c, int32_t nrhs, const double* b_dev, const double* u_dev, double* out_dev,
                void* stream);
 
-/* grad_dev [Ltau][N] += scale * sum_r dS_F/dx with S_F = b . (M^T M)^{-1} b and
+/* grad_dev [Ltau][N] += scale * s * sum_r dS_F/dx with S_F = b . (M^T M)^{-1} b and
  * u_dev [nrhs][Ltau][N] the solutions (Eq. dSF_dx):
  *   dS_F/dx_{i,tau} = 2 (M u)_tau . (dB_tau/dx_{i,tau}) u~_{tau-1},  u~_{-1} = -u_{Ltau-1},
  * dB by the product rule through the four family factors (Sec. III A) plus
- * the on-site term.  Uses the context's workspace for M u.  Enqueue only. */
+ * the on-site term.  s = *scale_dev (device memory, read when the kernel
+ * runs) or 1 when scale_dev is NULL multiplies the result as in
+ * fermion_force.  Uses the context's workspace for M u.  Enqueue only. */
 int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, double scale,
-              void* stream);
+              const double* scale_dev, void* stream);
 
 /* HMC context (as fph_hmc_create) whose update runs on the SSH operator of
  * ssh: trajectories (hmc_trajectory) and global updates (hmc_global_update)

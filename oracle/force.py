@@ -22,7 +22,7 @@ def force_from_solution(lat, x, u, C=None):
     """dS_F/dx[tau, i] from the solution u (Eq. dSF_dx with Lambda = I).
 
     u may be [Ltau, N] or [R, Ltau, N]; the result has the same shape
-    (one force per right-hand side).
+    (one force per right-hand side).  C may be dense or scipy sparse.
     """
     C = lat_mod.checkerboard_C(lat) if C is None else C
     E = lat_mod.E_field(lat, x)
@@ -33,7 +33,7 @@ def force_from_solution(lat, x, u, C=None):
     dMu = np.empty_like(Mu)
     for tau in range(lat.Ltau):
         prev = u[..., tau - 1, :] if tau >= 1 else -u[..., lat.Ltau - 1, :]
-        dMu[..., tau, :] = lat.dtau * lat.alpha * E[tau] * (prev @ np.asarray(C).T)
+        dMu[..., tau, :] = lat.dtau * lat.alpha * E[tau] * (prev @ C.T)
     return -2.0 * Mu * dMu
 
 

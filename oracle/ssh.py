@@ -116,12 +116,15 @@ def apply(lat, g, x, v, op="M"):
 
 
 def solve(lat, g, x, Phi):
-    """u = (M^T M)^{-1} Phi by dense LU (Phi [..., Ltau, N])."""
+    """u = (M^T M)^{-1} Phi by LU of the dense M: w = M^{-T} Phi, then
+    u = M^{-1} w (Phi [..., Ltau, N]; complex x allowed).  M^T M is never
+    formed: that would square the condition number."""
     M = dense_M(lat, g, x)
-    A = M.T @ M
+    lu = scipy.linalg.lu_factor(M)
     Phi = np.asarray(Phi)
     sh = Phi.shape
-    u = scipy.linalg.solve(A, Phi.reshape(-1, lat.dim).T, assume_a="gen")
+    w = scipy.linalg.lu_solve(lu, Phi.reshape(-1, lat.dim).T.astype(M.dtype), trans=1)
+    u = scipy.linalg.lu_solve(lu, w, trans=0)
     return u.T.reshape(sh)
 
 
@@ -234,22 +237,28 @@ def sparse_M(lat, g, x):
     return sp.bmat(blocks, format="csr")
 
 
+def _sparse_normal_solve(M, Phi):
+    """(M^T M)^{-1} Phi for the columns of Phi with one sparse LU of M:
+    M^T w = Phi (plain transpose, so complex M stays analytic), then M u = w."""
+    lu = spla.splu(M.tocsc())
+    w = lu.solve(Phi.astype(M.dtype), trans="T")
+    return lu.solve(w, trans="N")
+
+
 def sparse_action(lat, g, x, Phi):
-    """S_F = sum over fields of Phi . (M^T M)^{-1} Phi with a sparse LU (complex x allowed)."""
+    """S_F = sum over fields of Phi . (M^T M)^{-1} Phi with a sparse LU of M (complex x allowed)."""
     M = sparse_M(lat, g, x)
-    A = (M.T @ M).tocsc()
     Phi = np.asarray(Phi).reshape(-1, lat.dim)
-    u = spla.splu(A).solve(Phi.T.astype(A.dtype))
+    u = _sparse_normal_solve(M, Phi.T)
     return np.sum(Phi.T * u)
 
 
 def sparse_solve(lat, g, x, Phi):
-    """u = (M^T M)^{-1} Phi by sparse LU (Phi [..., Ltau, N], real x)."""
+    """u = (M^T M)^{-1} Phi by a sparse LU of M (Phi [..., Ltau, N], real x)."""
     M = sparse_M(lat, g, x)
-    A = (M.T @ M).tocsc()
     Phi = np.asarray(Phi)
     sh = Phi.shape
-    u = spla.splu(A).solve(Phi.reshape(-1, lat.dim).T)
+    u = _sparse_normal_solve(M, Phi.reshape(-1, lat.dim).T)
     return u.T.reshape(sh)
 
 

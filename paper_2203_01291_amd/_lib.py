@@ -95,7 +95,7 @@ EXPORTS = {
     "ssh_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "ssh_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                 ctypes.c_double, ctypes.c_void_p]),
+                                 ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fph_version": (ctypes.c_char_p, []),
     "fph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fph_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Lattice), ctypes.c_int32]),
@@ -111,7 +111,7 @@ EXPORTS = {
     "pcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), ctypes.c_void_p]),
     "fermion_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                     ctypes.c_double, ctypes.c_void_p]),
+                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fermion_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fph_precond_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

@@ -441,8 +441,8 @@ int op_solve(const fph_hmc_s* c, int nr, const double* b, double* u, const fph_p
 }
 
 int op_force(const fph_hmc_s* c, int nr, const double* u, double* grad, double scale, void* stream) {
-  if (c->ssh) return ssh_force(c->ssh, nr, u, grad, scale, stream);
-  return fermion_force(c->h, nr, u, grad, scale, stream);
+  if (c->ssh) return ssh_force(c->ssh, nr, u, grad, scale, nullptr, stream);
+  return fermion_force(c->h, nr, u, grad, scale, nullptr, stream);
 }
 
 }  // namespace

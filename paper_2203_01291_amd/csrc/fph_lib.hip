@@ -168,7 +168,7 @@ StIO no_state() { return StIO{nullptr, nullptr, nullptr, nullptr, 0, 0}; }
 
 template <typename T, int NT, int MS, int MODE>
 hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, double coef,
-                        hipStream_t s) {
+                        const double* scale_dev, hipStream_t s) {
   const Geom& g = h->g;
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
   const int nblk = (g.Ltau + S - 1) / S;
@@ -181,18 +181,18 @@ hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, dou
   const T* E = (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32);
   const int ny = (MODE == 0) ? nrhs : (g.fs ? (nrhs + g.rpf - 1) / g.rpf : 1);
   hipLaunchKernelGGL(kern, dim3(nblk, ny), dim3(NT), lds, s, g, E, (T)h->th, 1, nrhs, v, out,
-                     coef);
+                     coef, scale_dev);
   return hipGetLastError();
 }
 
 template <typename T, int MODE>
 hipError_t launch_M(const fph_handle_s* h, int nrhs, const T* v, T* out, double coef,
-                    hipStream_t s) {
+                    hipStream_t s, const double* scale_dev = nullptr) {
   const int Q = h->g.Q;
-  if (Q <= 64) return launch_M_cfg<T, 64, 1, MODE>(h, nrhs, v, out, coef, s);
-  if (Q <= 256) return launch_M_cfg<T, 256, 1, MODE>(h, nrhs, v, out, coef, s);
-  if (Q <= 512) return launch_M_cfg<T, 512, 1, MODE>(h, nrhs, v, out, coef, s);
-  return launch_M_cfg<T, 1024, 1, MODE>(h, nrhs, v, out, coef, s);
+  if (Q <= 64) return launch_M_cfg<T, 64, 1, MODE>(h, nrhs, v, out, coef, scale_dev, s);
+  if (Q <= 256) return launch_M_cfg<T, 256, 1, MODE>(h, nrhs, v, out, coef, scale_dev, s);
+  if (Q <= 512) return launch_M_cfg<T, 512, 1, MODE>(h, nrhs, v, out, coef, scale_dev, s);
+  return launch_M_cfg<T, 1024, 1, MODE>(h, nrhs, v, out, coef, scale_dev, s);
 }
 
 template <typename T, int NT, int MS>
@@ -421,13 +421,13 @@ int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, const
 }
 
 int fermion_force(fph_handle_t h, int32_t nrhs, const double* u_dev, double* grad_dev,
-                  double scale, void* stream) {
+                  double scale, const double* scale_dev, void* stream) {
   if (h == nullptr || u_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
   if (!h->have_field) return FPH_E_NOFIELD;
   if (nrhs < 1 || (h->nfields && nrhs > h->nfields * h->g.rpf)) return FPH_E_NRHS;
   if (!std::isfinite(scale)) return FPH_E_ARG;
   const double coef = -2.0 * h->lat.dtau * h->lat.alpha * scale;
-  hipError_t e = launch_M<double, 1>(h, nrhs, u_dev, grad_dev, coef, (hipStream_t)stream);
+  hipError_t e = launch_M<double, 1>(h, nrhs, u_dev, grad_dev, coef, (hipStream_t)stream, scale_dev);
   if (e != hipSuccess) return fail_hip(e);
   return FPH_OK;
 }

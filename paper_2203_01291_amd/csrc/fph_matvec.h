@@ -701,16 +701,19 @@ k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi, 
 // ------------------------------------------------------------- M alone --
 
 // out = M v (mode 0), or the force (mode 1):
-//   grad_tau += scale * sum_r (-2 dtau alpha) (M u)_tau * y_tau,
-//   y_tau = E_tau * (C u~_{tau-1}), (M u)_tau = u_tau - y_tau   (Eq. dSF_dx)
+//   grad_tau += coef * s * sum_r (M u)_tau * y_tau,  coef = -2 dtau alpha scale,
+//   y_tau = E_tau * (C u~_{tau-1}), (M u)_tau = u_tau - y_tau   (Eq. dSF_dx),
+//   s = *scale_dev (device value read at run time) or 1 when scale_dev is null.
 // Launch: grid (ceil(Ltau / S / per), nrhs in mode 0; in mode 1 the number
 // of fields, block y summing the right-hand sides of field y into grad[y]).
 // Each (sub-)chunk of the block handles `per` slices.  LDS: S * N elements.
 template <typename T, int NT, int MAXSLOT, int MODE>
 __global__ void __launch_bounds__(NT)
 k_apply_M(Geom g, const T* __restrict__ E, T th, int per, int nrhs,
-          const T* __restrict__ v, T* __restrict__ out, double coef) {
+          const T* __restrict__ v, T* __restrict__ out, double coef,
+          const double* __restrict__ scale_dev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (MODE == 1 && scale_dev != nullptr) coef *= *scale_dev;
   const int tid = threadIdx.x;
   int S, sub, lane, nslot;
   if (g.Q <= NT) {

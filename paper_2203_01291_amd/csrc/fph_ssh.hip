@@ -395,7 +395,8 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
   }
 }
 
-// grad_tau += scale * sum_r dS_F/dx_tau with S_F = Phi . (M^T M)^{-1} Phi:
+// grad_tau += scale * s * sum_r dS_F/dx_tau with S_F = Phi . (M^T M)^{-1} Phi
+// (s = *scale_dev read at run time, 1 when scale_dev is null):
 //   dS_F/dx_{i,tau} = 2 s_tau sum_r y_{r,tau} . (dB_tau/dx_{i,tau}) u_{r,tau-1},  y = M u.
 // dB = d(diag E) C + diag(E) sum_f F_xe .. dF_f .. F_yo: the vector entering
 // F_f from the right (a_f) is kept per thread in registers while C u is
@@ -406,6 +407,7 @@ template <int BPT>
 __global__ void __launch_bounds__(kNT) k_ssh_force(SshGeom G, int nrhs, const double* __restrict__ x,
                                                    const double* __restrict__ u,
                                                    const double* __restrict__ y, double scale,
+                                                   const double* __restrict__ scale_dev,
                                                    double* __restrict__ grad) {
   extern __shared__ double sm[];
   double* xs = sm;
@@ -472,7 +474,7 @@ __global__ void __launch_bounds__(kNT) k_ssh_force(SshGeom G, int nrhs, const do
     }
   }
   double* gt = grad + (long)tau * G.N;
-  const double c = 2.0 * s * scale;
+  const double c = 2.0 * s * scale * (scale_dev != nullptr ? *scale_dev : 1.0);
   for (int i = threadIdx.x; i < G.N; i += kNT) gt[i] += c * ga[i];
 }
 
@@ -700,7 +702,7 @@ hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, 
 }
 
 hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const double* y, double scale,
-                        double* grad, hipStream_t s) {
+                        const double* scale_dev, double* grad, hipStream_t s) {
   const dim3 grid(c->G.Ltau);
   const size_t lds = force_lds(c);
   if (c->bpt == 8) {
@@ -708,10 +710,10 @@ hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const dou
     if (e != hipSuccess) return e;
   }
   switch (c->bpt) {
-    case 1: hipLaunchKernelGGL((k_ssh_force<1>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
-    case 2: hipLaunchKernelGGL((k_ssh_force<2>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
-    case 4: hipLaunchKernelGGL((k_ssh_force<4>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
-    default: hipLaunchKernelGGL((k_ssh_force<8>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, grad); break;
+    case 1: hipLaunchKernelGGL((k_ssh_force<1>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, scale_dev, grad); break;
+    case 2: hipLaunchKernelGGL((k_ssh_force<2>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, scale_dev, grad); break;
+    case 4: hipLaunchKernelGGL((k_ssh_force<4>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, scale_dev, grad); break;
+    default: hipLaunchKernelGGL((k_ssh_force<8>), grid, dim3(kNT), lds, s, c->G, nrhs, c->x, u, y, scale, scale_dev, grad); break;
   }
   return hipGetLastError();
 }
@@ -816,14 +818,14 @@ int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, doub
 }
 
 int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, double scale,
-              void* stream) {
+              const double* scale_dev, void* stream) {
   if (c == nullptr || u_dev == nullptr || grad_dev == nullptr) return FPH_E_NULL;
   if (!c->have_field) return FPH_E_NOFIELD;
   if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
   if (!std::isfinite(scale)) return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   SSH_CHECK(launch_apply_op<0>(c, nrhs, u_dev, c->tmp, s));  // y = M u
-  SSH_CHECK(launch_force(c, nrhs, u_dev, c->tmp, scale, grad_dev, s));
+  SSH_CHECK(launch_force(c, nrhs, u_dev, c->tmp, scale, scale_dev, grad_dev, s));
   return FPH_OK;
 }
 

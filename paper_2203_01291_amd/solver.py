@@ -26,6 +26,16 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _scale_ptr(scale_dev):
+    """Device pointer of a one-element float64 CUDA tensor, or NULL."""
+    if scale_dev is None:
+        return ctypes.c_void_p(None)
+    if not (scale_dev.is_cuda and scale_dev.dtype == torch.float64 and scale_dev.numel() == 1
+            and scale_dev.is_contiguous()):
+        raise ValueError("scale_dev must be a one-element contiguous float64 CUDA tensor")
+    return _ptr(scale_dev)
+
+
 class FermionSolver:
     """One lattice (L, Ltau, dtau, t, mu, alpha) and up to ``max_rhs``
     right-hand sides; owns the library handle and its workspace."""
@@ -42,6 +52,8 @@ class FermionSolver:
         check(self.lib.fph_create(ctypes.byref(h), ctypes.byref(lat), self.max_rhs))
         self.h = h
         self._x = None
+        self._field = None
+        self.field_version = 0
 
     @classmethod
     def from_params(cls, p, L=None, max_rhs=1):
@@ -74,6 +86,8 @@ class FermionSolver:
         self._x = x
         self._nfields = 0
         check(self.lib.fph_set_field(self.h, _ptr(x), float(a1), float(a2), _stream()))
+        self._field = ("one", x, dict(a1=a1, a2=a2))
+        self.field_version += 1
 
     def set_fields(self, xs, rhs_per_field=1, a1=1.0, a2=1.0):
         """Per-right-hand-side fields: xs [nfields, Ltau, N]; right-hand side r of later calls
@@ -83,6 +97,22 @@ class FermionSolver:
         self._nfields = nf
         check(self.lib.fph_set_fields(self.h, nf, int(rhs_per_field), _ptr(xs), float(a1), float(a2),
                                       _stream()))
+        self._field = ("many", xs, dict(rhs_per_field=rhs_per_field, a1=a1, a2=a2))
+        self.field_version += 1
+
+    def field_state(self):
+        """What the last set_field / set_fields call installed (see restore_field)."""
+        return self._field
+
+    def restore_field(self, state):
+        """Install again a field recorded by field_state (no-op for None)."""
+        if state is None:
+            return
+        kind, x, kw = state
+        if kind == "one":
+            self.set_field(x, **kw)
+        else:
+            self.set_fields(x, **kw)
 
     def matvec(self, v, op="MTM", out=None):
         """out = op(v) for op in {'M', 'MT', 'MTM'}; float64 or float32."""
@@ -123,13 +153,16 @@ class FermionSolver:
                                  _stream()))
         return u, [s.as_dict() for s in stats]
 
-    def force(self, u, grad=None, scale=1.0):
-        """grad += scale * sum_r dS_F/dx for solutions u (float64)."""
+    def force(self, u, grad=None, scale=1.0, scale_dev=None):
+        """grad += scale * s * sum_r dS_F/dx for solutions u (float64); s is the
+        one-element float64 CUDA tensor scale_dev, read on the device (no host
+        synchronisation), or 1."""
         nrhs = self._vec(u)
         nf = getattr(self, "_nfields", 0) or 1
         shape = (self.Ltau, self.N) if nf == 1 and not getattr(self, "_nfields", 0) else (nf, self.Ltau, self.N)
         grad = torch.zeros(*shape, dtype=torch.float64, device=u.device) if grad is None else grad
-        check(self.lib.fermion_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), _stream()))
+        sd = _scale_ptr(scale_dev)
+        check(self.lib.fermion_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), sd, _stream()))
         return grad
 
     def action(self, b, u):
@@ -250,30 +283,56 @@ class FermionAction(torch.autograd.Function):
     or an SSHSolver, whose force is the product rule through its bond factors):
         dS_F/dx = sum_r -2 dtau alpha (M u_r) * (E * C u~_r),
         dS_F/dPhi_r = 2 u_r.
+    forward installs x in the solver (field_kw: the Chebyshev constants a1, a2
+    of a FermionSolver) and raises if a right-hand side did not converge.
+    backward scales the force by the upstream gradient on the device; if the
+    solver holds another field by then (a later set_field or a second
+    action on the same solver), it installs x again for the force and then
+    puts the other field back.
     """
 
     @staticmethod
-    def forward(ctx, x, Phi, solver, solve_kw):
-        solver.set_field(x.contiguous())
-        u, stats = solver.solve(Phi.contiguous(), **(solve_kw or {}))
+    def forward(ctx, x, Phi, solver, field_kw, solve_kw):
+        xc = x.detach().contiguous()
+        Pc = Phi.detach().contiguous()
+        solver.set_field(xc, **field_kw)
+        u, stats = solver.solve(Pc, **solve_kw)
+        bad = [k for k, st in enumerate(stats) if not (st["status"] & _lib.ST_CONVERGED)]
+        if bad:
+            raise RuntimeError("fermion_action: the solve did not converge for right-hand side(s) "
+                               f"{bad}: {[stats[k] for k in bad]}")
         ctx.solver = solver
-        ctx.stats = stats
-        ctx.save_for_backward(u)
-        return solver.action(Phi.contiguous(), u).sum()
+        ctx.field_kw = field_kw
+        ctx.version = solver.field_version
+        ctx.save_for_backward(u, xc)
+        return solver.action(Pc, u).sum()
 
     @staticmethod
     def backward(ctx, g):
-        (u,) = ctx.saved_tensors
+        u, xc = ctx.saved_tensors
         solver = ctx.solver
         gx = gphi = None
-        scale = float(g.item())
+        gd = g.detach().to(torch.float64).reshape(1).contiguous()
         if ctx.needs_input_grad[0]:
-            gx = solver.force(u, scale=scale)
+            other = None
+            if solver.field_version != ctx.version:
+                other = solver.field_state()
+                solver.set_field(xc, **ctx.field_kw)
+            gx = solver.force(u, scale_dev=gd)
+            if other is not None:
+                solver.restore_field(other)
         if ctx.needs_input_grad[1]:
-            gphi = (2.0 * scale) * u
-        return gx, gphi, None, None
+            gphi = (2.0 * gd) * u
+        return gx, gphi, None, None, None
 
 
-def fermion_action(x, Phi, solver, **solve_kw):
-    """Differentiable S_F(x; Phi) (see FermionAction)."""
-    return FermionAction.apply(x, Phi, solver, solve_kw)
+def fermion_action(x, Phi, solver, a1=None, a2=None, **solve_kw):
+    """Differentiable S_F(x; Phi) (see FermionAction).  a1, a2: Chebyshev
+    order constants of the preconditioner (FermionSolver only); solve_kw go
+    to solver.solve."""
+    field_kw = {}
+    if a1 is not None:
+        field_kw["a1"] = a1
+    if a2 is not None:
+        field_kw["a2"] = a2
+    return FermionAction.apply(x, Phi, solver, field_kw, solve_kw)

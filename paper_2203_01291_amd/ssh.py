@@ -18,7 +18,7 @@ import torch
 
 from . import _lib
 from ._lib import FPH_OP_M, FPH_OP_MT, FPH_OP_MTM, Lattice, PcgOpts, PcgStats, check
-from .solver import _ptr, _stream
+from .solver import _ptr, _scale_ptr, _stream
 
 _OPS = {"M": FPH_OP_M, "MT": FPH_OP_MT, "MTM": FPH_OP_MTM}
 
@@ -38,6 +38,8 @@ class SSHSolver:
         check(self.lib.fph_ssh_create(ctypes.byref(h), ctypes.byref(lat), self.g, self.max_rhs))
         self.h = h
         self._pc = None
+        self._field = None
+        self.field_version = 0
 
     @classmethod
     def from_params(cls, p, g, L=None, max_rhs=1):
@@ -74,6 +76,15 @@ class SSHSolver:
         if self._vec(x) != 1:
             raise ValueError("expected one field of N*Ltau values")
         check(self.lib.ssh_set_field(self.h, _ptr(x), _stream()))
+        self._field = x
+        self.field_version += 1
+
+    def field_state(self):
+        return self._field
+
+    def restore_field(self, state):
+        if state is not None:
+            self.set_field(state)
 
     def matvec(self, v, op="M", out=None):
         """M v, M^T v or M^T M v for every vector of v."""
@@ -100,11 +111,13 @@ class SSHSolver:
         check(self.lib.ssh_action(self.h, nrhs, _ptr(b), _ptr(u), _ptr(out), _stream()))
         return out
 
-    def force(self, u, grad=None, scale=1.0):
-        """grad += scale * sum_r dS_F/dx for solutions u (S_F = b . (M^T M)^{-1} b)."""
+    def force(self, u, grad=None, scale=1.0, scale_dev=None):
+        """grad += scale * s * sum_r dS_F/dx for solutions u (S_F = b . (M^T M)^{-1} b);
+        s = scale_dev (one-element float64 CUDA tensor, read on the device) or 1."""
         nrhs = self._vec(u)
         grad = torch.zeros(self.Ltau, self.N, dtype=torch.float64, device=u.device) if grad is None else grad
         if self._vec(grad) != 1:
             raise ValueError("grad must hold one field")
-        check(self.lib.ssh_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), _stream()))
+        check(self.lib.ssh_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), _scale_ptr(scale_dev),
+                                 _stream()))
         return grad

@@ -52,7 +52,7 @@ def test_argument_errors_are_reported_on_the_host():
     assert lib.fph_create(None, ctypes.byref(good), 1) == -1
     assert lib.fermion_matvec(None, 0, 0, 1, None, None, None) == -1
     assert lib.pcg_solve(None, 1, None, None, None, None, None) == -1
-    assert lib.fermion_force(None, 1, None, None, 1.0, None) == -1
+    assert lib.fermion_force(None, 1, None, None, 1.0, None, None) == -1
     assert b"NULL" in lib.fph_strerror(-1)
 
 
@@ -158,7 +158,7 @@ def test_ssh_argument_errors_on_host():
     assert lib.ssh_set_field(None, None, None) == -1
     assert lib.ssh_matvec(None, 0, 1, None, None, None) == -1
     assert lib.ssh_solve(None, 1, None, None, None, None, None) == -1
-    assert lib.ssh_force(None, 1, None, None, 1.0, None) == -1
+    assert lib.ssh_force(None, 1, None, None, 1.0, None, None) == -1
     assert lib.ssh_action(None, 1, None, None, None, None) == -1
     assert lib.ssh_set_preconditioner(None, None, 1.0, 1.0) == -1
     assert lib.fph_hmc_create_ssh(ctypes.byref(h), None, None, None) == -1

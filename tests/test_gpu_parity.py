@@ -34,6 +34,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def relmax(a, b):
+    """Element by element: largest absolute difference over the largest reference entry."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 def make_solver(lat, max_rhs=1):
     from paper_2203_01291_amd.solver import FermionSolver
     return FermionSolver(lat.L, lat.Ltau, lat.dtau, lat.t, lat.mu, lat.alpha, max_rhs=max_rhs)
@@ -68,9 +75,11 @@ def test_operator_parity(shape):
     vg = tgpu(v)
     for op, ref in (("M", ref_M), ("MT", ref_MT), ("MTM", ref_MTM)):
         out = s.matvec(vg, op).cpu().numpy()
-        assert rel(out, ref) < 1e-13, op
+        assert relmax(out, ref) < 1e-13, op
         out32 = s.matvec(vg.float(), op).double().cpu().numpy()
-        assert rel(out32, ref) < 2e-6, op + " fp32"
+        # FP32: the input itself is rounded (6e-8 relative) and each output
+        # adds a few FP32 roundings of terms up to e^{4 dtau t} |E| times larger
+        assert relmax(out32, ref) < 2e-6, op + " fp32"
 
 
 @pytest.mark.parametrize("key", ["c2", "c3", "c5"])
@@ -101,7 +110,7 @@ def test_operator_full_size_sampled(key):
     for tau in (0, 1, lat.Ltau // 2, lat.Ltau - 1):
         prev = b[tau - 1] if tau >= 1 else -b[lat.Ltau - 1]
         ref = b[tau] - E[tau] * (Cs @ prev)
-        assert rel(Mb_h[tau], ref) < 1e-13
+        assert relmax(Mb_h[tau], ref) < 1e-13
 
 
 def c1_problem(nrhs=1, perturb=True):
@@ -221,9 +230,9 @@ def test_precond_apply_parity(shape):
     for op, ref in (("F", pc.apply_F(v)), ("FT", pc.apply_F(v, transpose=True)),
                     ("FFT", np.stack([pc.apply_FFt(v[r]) for r in range(2)]))):
         out = s.precond(vg, op).cpu().numpy()
-        assert rel(out, ref) < 1e-12, op
+        assert relmax(out, ref) < 1e-12, op
         out32 = s.precond(vg.float(), op).double().cpu().numpy()
-        assert rel(out32, ref) < 1e-4, op + " fp32"
+        assert relmax(out32, ref) < 1e-5, op + " fp32"
 
 
 def test_precond_symmetric_on_gpu():
@@ -428,6 +437,7 @@ def test_full_size_solve_and_force_against_oracle(key, prec):
     print(f"{key} {prec}: iters {st['iters']} eps {st['rel_resid']:.2e} kappa*eps {kappa * eps:.2e}"
           f" rel err u {rel_u:.2e} force {rel_g:.2e} S_F {dS / abs(ref['S_F']):.2e}")
     assert rel_u < 1e-8 and rel_g < 1e-8
+    assert relmax(uh, uref) < 1e-8 and relmax(g, gref) < 1e-8
 
 
 def test_force_central_differences_c5_100_sites():

@@ -236,6 +236,26 @@ def test_solve_large(L, T):
         assert st[r]["action"] == pytest.approx(float(np.sum(phi[r] * uo[r])), rel=1e-10)
 
 
+def test_solve_and_force_long_time_axis():
+    """g != 0 with Ltau = 40 (L = 8): FP64 CG against the oracle's sparse LU of M and M^T
+    (never M^T M), S_F, and the force on the GPU's solution projected on random directions
+    against the complex-step directional derivative of the oracle's S_F."""
+    L, T, g = 8, 40, 0.3
+    lat, x, s = make(L, T, g, max_rhs=2, seed=4)
+    phi = np.random.default_rng(43).standard_normal((2, T, L * L))
+    u, st = s.solve(tgpu(phi), tol=1e-12)
+    uo = S.sparse_solve(lat, g, x, phi)
+    for r in range(2):
+        assert st[r]["status"] & 1 and st[r]["rel_resid"] < 1e-12
+        assert rel(u[r].cpu().numpy(), uo[r]) < 1e-9
+        assert st[r]["action"] == pytest.approx(float(np.sum(phi[r] * uo[r])), rel=1e-10)
+    f = s.force(u[:1].contiguous()).cpu().numpy()
+    for seed in (44, 45):
+        d = np.random.default_rng(seed).standard_normal(x.shape)
+        dd = S.directional_derivative(lat, g, x, phi[0], d)
+        assert float(np.sum(f * d)) == pytest.approx(dd, rel=1e-9)
+
+
 def test_autograd_action():
     """fermion_action on the SSH operator: S_F, dS_F/dx (the product-rule force) and
     dS_F/dPhi = 2u against the oracle."""

@@ -32,6 +32,10 @@ class Params:
     cfg_id: int = 0        # seed component
     L_choices: Tuple[int, ...] = field(default_factory=tuple)  # batched only
     n_systems: int = 1
+    # Chebyshev order constants (a1, a2) of the preconditioner,
+    # N_P = floor(db (a1/phi + a2)) (App. C, Eq. NP_heuristic): the paper's
+    # order-one values, or the pair measured fastest for the workload.
+    cheb: Tuple[float, float] = (1.0, 1.0)
 
     @property
     def N(self) -> int:
@@ -56,14 +60,14 @@ CONFIGS = {
                  cfg_id=2),
     "c3": Params("holstein_L32_Ltau400", L=32, Ltau=400, dtau=0.05, t=1.0,
                  mu=-0.2, omega=1.0, alpha=1.2, field="ar1", tol=1e-8,
-                 cfg_id=3),
+                 cfg_id=3, cheb=(0.15, 12.0)),
     "c4": Params("holstein_batched64_L8to24_Ltau100", L=0, Ltau=100, dtau=0.1,
                  t=1.0, mu=0.0, omega=1.0, alpha=1.0, field="iid",
                  n_gauss=8, n_rademacher=32, tol=1e-8, cfg_id=4,
                  L_choices=(8, 12, 16, 20, 24), n_systems=64),
     "c5": Params("holstein_L64_Ltau400", L=64, Ltau=400, dtau=0.05, t=1.0,
                  mu=0.0, omega=1.0, alpha=1.5, field="iid_shift", tol=1e-8,
-                 cfg_id=5),
+                 cfg_id=5, cheb=(0.05, 12.0)),
 }
 
 
