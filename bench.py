@@ -68,8 +68,6 @@ def parse():
     ap.add_argument("--ssh-hmc", action="store_true",
                     help="with --ssh-only: also time one HMC trajectory on the SSH operator (paper "
                          "settings, FP64 preconditioned solves; about 10 s)")
-    ap.add_argument("--concurrent", type=int, default=4,
-                    help="independent systems / chains run side by side in the concurrency legs")
     ap.add_argument("--profile-roofline", action="store_true",
                     help="only the roofline kernel (M^T M, FP32, L=64 Ltau=400 x 32 rhs) and a "
                          "plain copy of the same byte count, for hardware-counter runs")
@@ -194,7 +192,7 @@ def bench_batched(torch, dev, log):
     return res
 
 
-def bench_hmc(torch, dev, p, a1, a2, log, nchains=4, batch_chains=8):
+def bench_hmc(torch, dev, p, a1, a2, log, batch_chains=8):
     """One HMC trial update (Algorithm 1) on the workload's lattice with the
     paper's settings: dt = 1/(100 omega0), Nt = 100 steps of nt = 10 bosonic
     sub-steps, Fourier acceleration with m_reg = omega0, two pseudofermion
@@ -203,7 +201,8 @@ def bench_hmc(torch, dev, p, a1, a2, log, nchains=4, batch_chains=8):
     Starts from the workload's synthetic field; one warm-up trajectory, then
     one timed, with the action S' (A = M); then one with the action S
     (A = M Lambda) and four reflection / swap updates with it; and
-    `nchains` independent chains side by side (one trajectory each)."""
+    `batch_chains` independent chains in the same launches (one trajectory
+    each)."""
     from paper_2203_01291_amd.hmc import PhononHMC
     from paper_2203_01291_amd.solver import FermionSolver
     from workloads import hmc_draws, hmc_params, phonon_field
@@ -260,29 +259,6 @@ def bench_hmc(torch, dev, p, a1, a2, log, nchains=4, batch_chains=8):
                       "ms": (time.perf_counter() - t0) * 1e3, "dS": su["dS"], "cg_iters": su["cg_iters"],
                       "status": su["status"]})
     hl.close()
-    # Independent chains side by side: one trajectory each, on their own
-    # streams and host threads inside the library.
-    chains = None
-    if nchains > 1:
-        from paper_2203_01291_amd.hmc import trajectories_concurrent
-        ctx = []
-        for _ in range(nchains):
-            sk = FermionSolver.from_params(p, max_rhs=hp.nfields)
-            hk = PhononHMC(sk, hp.omega0, hp.m_reg, hp.dt, Nt=hp.Nt, nt=hp.nt, nfields=hp.nfields, a1=a1,
-                           a2=a2, force_tol=hp.tol_force, action_tol=hp.tol_action)
-            ctx.append((sk, hk))
-        trajectories_concurrent([(hk, x0.clone(), Rf, Rm, r) for sk, hk in ctx])
-        xs = [x0.clone() for _ in ctx]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stc = trajectories_concurrent([(hk, xk, Rf, Rm, r) for (sk, hk), xk in zip(ctx, xs)])
-        torch.cuda.synchronize()
-        dtc = time.perf_counter() - t0
-        chains = {"chains": nchains, "seconds": dtc, "trajectories_per_s": nchains / dtc,
-                  "speedup_vs_one": (nchains / dtc) * dt, "status": [v["status"] for v in stc]}
-        for sk, hk in ctx:
-            hk.close()
-            sk.close()
     # The same chains in the same launches: chain k's pseudofermions are
     # right-hand sides of its own field in every solve.
     batched = None
@@ -315,7 +291,6 @@ def bench_hmc(torch, dev, p, a1, a2, log, nchains=4, batch_chains=8):
         "dH": st["H_f"] - st["H_i"], "accept_prob": st["accept_prob"], "accepted": st["accepted"],
         "status": st["status"], "boson_step_us": boson_us,
         "boson_fraction": boson_us * 1e-6 * hp.Nt / dt,
-        "concurrent_chains": chains,
         "chains_per_launch": batched,
         "lambda_action": {"ms_per_trajectory": dtl * 1e3, "cg_iters": stl["cg_iters"],
                           "dH": stl["H_f"] - stl["H_i"], "status": stl["status"],
@@ -633,7 +608,7 @@ def main():
     if args.hmc_only:
         from workloads import get_config as _gc
         print(json.dumps(bench_hmc(torch, torch.device("cuda:0"), _gc(args.workload), args.a1, args.a2,
-                                   log, args.concurrent)), flush=True)
+                                   log)), flush=True)
         return
 
     from paper_2203_01291_amd.solver import FermionSolver
@@ -664,14 +639,13 @@ def main():
 
     # One step of each solver variant: FP32-refined and FP64, with and
     # without the preconditioner (Chebyshev coefficients a1 as chosen, and
-    # a1 = a2 = 1), FP64 single-reduction CG, the one-launch FP32 solve.
+    # a1 = a2 = 1), the one-launch FP32 solve.
     variants = {}
     all_variants = (("f32_refined_plain", "f32_refined", False, 0, args.a1),
                     ("f32_refined_precond", "f32_refined", True, 0, args.a1),
                     ("f32_refined_precond_a1_a2_1", "f32_refined", True, 0, 1.0),
                     ("f64_plain", "f64", False, 0, args.a1),
                     ("f32_refined_plain_one_launch", "f32_refined", False, 2, args.a1),
-                    ("f64_plain_single_reduction", "f64", False, 1, args.a1),
                     ("f64_precond", "f64", True, 0, args.a1))
     for name, prec, pre_v, var, a1v in (() if args.no_variants else all_variants):
         if var == 2 and R != 1:
@@ -701,36 +675,6 @@ def main():
                       "iters": [v["iters"] for v in st2], "status": [v["status"] for v in st2]}
         log(f"two fields: {two_fields}")
         s2.close()
-    # Independent systems of the workload's shape side by side (fields x, x +
-    # 0.01, ...), each set-field + FP32-refined PCG + action + force on its own
-    # stream and host thread: the throughput of several Markov chains per GPU.
-    concurrent = None
-    if not args.no_variants and R == 1 and args.concurrent > 1:
-        from paper_2203_01291_amd.solver import solve_concurrent
-        K = args.concurrent
-        sks = [FermionSolver.from_params(p, max_rhs=1) for _ in range(K)]
-        Phis = []
-        for sk in sks:
-            sk.set_field(x0)
-            Phis.append(sk.matvec(phi, "MT"))
-        xs = [x + 0.01 * k for k in range(K)]
-
-        def stepc():
-            for sk, xk in zip(sks, xs):
-                sk.set_field(xk, a1=args.a1, a2=args.a2)
-            out = solve_concurrent(list(zip(sks, Phis)), tol=tol, prec="f32_refined", precond=True)
-            for sk, Pk, (uk, _) in zip(sks, Phis, out):
-                sk.action(Pk, uk)
-                sk.force(uk)
-            return out
-        tc, outc = time_steps(stepc, 2, 1, torch)
-        concurrent = {"systems": K, "ms_per_step": tc * 1e3, "solves_per_s": K / tc,
-                      "speedup_vs_one_at_a_time": (K / tc) / (1e3 / variants["f32_refined_precond"]["ms"])
-                      if "f32_refined_precond" in variants else None,
-                      "iters": [o[1][0]["iters"] for o in outc], "status": [o[1][0]["status"] for o in outc]}
-        log(f"concurrent: {concurrent}")
-        for sk in sks:
-            sk.close()
     # Several independent systems of the workload's shape in the same launches
     # (per-right-hand-side fields, fph_set_fields): K fields x0 + 0.01 k with
     # Phi_k = M(x0 + 0.01 k)^T phi, solved at x + 0.01 k; one step = set the
@@ -826,7 +770,7 @@ def main():
 
     hmc = None
     if not args.no_hmc and R == 1:
-        hmc = bench_hmc(torch, dev, p, args.a1, args.a2, log, args.concurrent)
+        hmc = bench_hmc(torch, dev, p, args.a1, args.a2, log)
 
     meas = None
     if not args.no_meas and R == 1:
@@ -898,7 +842,6 @@ def main():
         "batched": batch,
         "variants": variants,
         "two_fields": two_fields,
-        "concurrent_systems": concurrent,
         "multi_field": multi,
         "hmc_trajectory": hmc,
         "measurements": meas,

@@ -42,9 +42,10 @@
  * only the handle and the workspace allocated by fph_create.  Work is
  * enqueued on the caller's hipStream_t (passed as void*; NULL means the
  * null stream).  A handle must not be used from two streams at once.
- * Entry points that return results on the host (pcg_solve statistics,
- * fph_precond_info) synchronise that stream before returning; all others
- * only enqueue.
+ * Entry points that return results on the host (pcg_solve_sync and the
+ * other *_sync or host-statistics calls, fph_precond_info) synchronise that
+ * stream before returning; the hot path (fph_set_field, fermion_matvec,
+ * pcg_solve, fermion_action, fermion_force) only enqueues.
  *
  * Errors
  * ------
@@ -114,17 +115,21 @@ typedef struct {
                            interval is shortened automatically (delta ->
                            sqrt delta) when a recomputation finds the true
                            residual more than twice the FP32 one          */
-  int32_t chunk;        /* CG iterations enqueued between host checks
-                           (0 -> library default); variant 2: the largest
-                           number of workgroups (0 -> 128)                 */
-  int32_t variant;      /* without preconditioner: 0 standard CG (two
-                           reductions, two launches per iteration); 1
-                           single-reduction CG (Chronopoulos and Gear, 1989:
-                           one launch per iteration, less stable in FP32);
-                           2 the whole FP32_REFINED solve in one cooperative
-                           launch (nrhs == 1, no preconditioner; all
-                           workgroups resident, grid-wide exchanges of
-                           partial sums instead of kernel boundaries)      */
+  int32_t chunk;        /* pcg_solve_sync: solver slots (iterations or
+                           residual evaluations) enqueued between two
+                           progress probes (0 -> 16); variant 2: the
+                           largest number of workgroups (0 -> 128)         */
+  int32_t variant;      /* 0: the standard (P)CG of pcg_solve (two
+                           launches per iteration without preconditioner,
+                           four with it); 2: the whole FP32_REFINED solve
+                           in one cooperative launch (nrhs == 1, no
+                           preconditioner; all workgroups resident,
+                           grid-wide exchanges of partial sums instead of
+                           kernel boundaries)                              */
+  int32_t max_outer;    /* cap on the FP64 residual evaluations after the
+                           first one (0 -> 32); a right-hand side that
+                           reaches it stops with FPH_ST_MAXITER            */
+  int32_t pad;
 } fph_pcg_opts_t;
 
 typedef struct {
@@ -187,15 +192,41 @@ int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs,
                    const void* in_dev, void* out_dev, void* stream);
 
 /* Solve (M^T M) u = b for nrhs right-hand sides with (preconditioned)
- * conjugate gradients (Eqs. CG, CG_precon).  b_dev, u_dev: double
- * [nrhs][Ltau][N]; u_dev is the initial guess unless opts->zero_guess and
- * receives the solution.  stats_host: array of nrhs entries filled on
- * return (may be NULL).  Blocks the calling thread until the solve has
- * finished on `stream`.  Returns FPH_OK even when a right-hand side did
- * not converge: check stats.status. */
+ * conjugate gradients (Eqs. CG, CG_precon; stopping on the relative
+ * residual, Sec. V B).  b_dev, u_dev: double [nrhs][Ltau][N]; u_dev is the
+ * initial guess unless opts->zero_guess and receives the solution.
+ * stats_dev: device array of nrhs fph_pcg_stats_t, written when the solve
+ * ends in stream order (S_F = b . u included).
+ *
+ * Enqueue only: the call never synchronises and reads nothing back.  Every
+ * decision (convergence, FP64 residual evaluation and replacement of the
+ * FP32-refined residual, the iteration cap, breakdown) is taken on the
+ * device.  The call enqueues a fixed sequence: a start kernel, then
+ * 1 + maxiter + max_outer "slots" (each performs one CG iteration or one
+ * FP64 residual evaluation per right-hand side; slots after a right-hand
+ * side finished return at once, about 1.5 us per launch), then two final
+ * kernels; set maxiter near the expected iteration count, since every slot
+ * is enqueued.  Only kernel launches are enqueued (no memset or copy), so
+ * the sequence can be captured into a hipGraph and replayed.  The host
+ * thread may wait for space in the stream's queue while enqueueing a long
+ * solve.  Calls on one handle must be ordered on one stream (they share
+ * its workspace).  Returns FPH_OK even when a right-hand side did not
+ * converge: check stats.status once the stream has reached the end. */
 int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
-              const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
+              const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_dev,
               void* stream);
+
+/* The same solve for callers that want the statistics on the host:
+ * stats_host (nrhs entries, may be NULL) is filled on return.  Enqueues the
+ * slots of pcg_solve in chunks of opts->chunk (0 -> 16); after each chunk
+ * a one-wave kernel writes how many right-hand sides are still open into
+ * pinned host memory, the host waits for the previous chunk's count only
+ * (the GPU always has a chunk queued) and stops enqueueing once it is zero.
+ * The result is the one pcg_solve gives.  Blocks the calling thread until
+ * the solve has finished on `stream`. */
+int pcg_solve_sync(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
+                   const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
+                   void* stream);
 
 /* grad_dev[Ltau][N] += scale * s * sum_r dS_F/dx for the solutions
  * u_dev[nrhs][Ltau][N] of the current field (Eq. dSF_dx with Lambda = I):
@@ -254,9 +285,12 @@ int fph_batch_create(fph_batch_t* bh, const fph_system_t* sys, int32_t nsys);
  * FP64 residual replacement to opts->tol (Sec. II D, Eq. CG; the paper's
  * stochastic measurements solve many such vectors at once, Sec. VI).
  * opts->prec must be FPH_F32_REFINED and opts->use_precond 0 (FPH_E_PREC /
- * FPH_E_ARG otherwise).  stats_host: one entry per right-hand side in
- * system order (may be NULL).  Blocks until done. */
-int fph_batch_solve(fph_batch_t bh, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
+ * FPH_E_ARG otherwise).  stats_dev: device array with one entry per
+ * right-hand side in system order (may be NULL), written in stream order.
+ * Enqueue only (the first call, and a call with other tol, maxiter or
+ * ru_delta than the last, captures the graph on an internal stream first;
+ * fph_batch_tune also captures). */
+int fph_batch_solve(fph_batch_t bh, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_dev,
                     void* stream);
 
 /* Autotune the launch shape of fph_batch_solve (threads per workgroup and
@@ -458,37 +492,6 @@ typedef struct {
 int hmc_global_update(fph_hmc_t hh, int32_t kind, int32_t i, int32_t j, double* x_dev,
                       const double* R_fields_dev, double r_uniform, fph_update_stats_t* stats_host,
                       void* stream);
-
-/* ------------------------------------------------------------------ */
-/* Independent work on several streams at once.                        */
-/*
- * At moderate sizes a single system's kernels are bound by launch and
- * memory latency and leave most compute units idle, so independent systems
- * (for example independent Markov chains) run faster side by side: each item
- * runs on its own handle and its own stream from a host thread of its own,
- * and the calls return when all items are done.  Results equal those of the
- * same calls made one after the other.  n is 1..64; streams must be non-NULL
- * and distinct, handles distinct (FPH_E_ARG otherwise).  The first error of
- * any item is returned.
- */
-
-/* pcg_solve(h[k], nrhs[k], b_dev[k], u_dev[k], &opts[k], stats_host[k], streams[k])
- * for k < n, concurrently.  stats_host may be NULL, or hold NULL entries. */
-int pcg_solve_concurrent(int32_t n, fph_handle_t const* h, const int32_t* nrhs,
-                         const double* const* b_dev, double* const* u_dev,
-                         const fph_pcg_opts_t* opts, fph_pcg_stats_t* const* stats_host,
-                         void* const* streams);
-
-/* hmc_trajectory(hh[k], x_dev[k], R_fields_dev[k], R_mom_dev[k], r_uniform[k],
- * p_out_dev ? p_out_dev[k] : NULL, &stats_host[k], streams[k]) for k < n,
- * concurrently; the contexts must sit on distinct operators (solver handles
- * or SSH contexts), and no Holstein handle may serve two of them, also as an
- * SSH context's preconditioner (FPH_E_ARG otherwise).  p_out_dev and
- * stats_host may be NULL. */
-int hmc_trajectory_concurrent(int32_t n, fph_hmc_t const* hh, double* const* x_dev,
-                              const double* const* R_fields_dev, const double* const* R_mom_dev,
-                              const double* r_uniform, double* const* p_out_dev,
-                              fph_hmc_stats_t* stats_host, void* const* streams);
 
 /* ------------------------------------------------------------------ */
 /* Stochastic Green's-function measurements (Sec. VI).                 */

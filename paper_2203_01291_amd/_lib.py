@@ -26,7 +26,8 @@ class PcgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("use_precond", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("zero_guess", ctypes.c_int32), ("ru_delta", ctypes.c_double),
-                ("chunk", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class PcgStats(ctypes.Structure):
@@ -36,6 +37,16 @@ class PcgStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def stats_from_device(t):
+    """Decode a device array of fph_pcg_stats_t (a CUDA tensor of 32-byte
+    entries, as written by pcg_solve or fph_batch_solve) into dicts.
+    Copies to the host, so it waits for the stream."""
+    raw = t.detach().cpu().contiguous().numpy().tobytes()
+    n = len(raw) // ctypes.sizeof(PcgStats)
+    arr = (PcgStats * n).from_buffer_copy(raw[:n * ctypes.sizeof(PcgStats)])
+    return [s.as_dict() for s in arr]
 
 
 class System(ctypes.Structure):
@@ -109,7 +120,9 @@ EXPORTS = {
     "fermion_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                 ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), ctypes.c_void_p]),
+                                 ctypes.POINTER(PcgOpts), ctypes.c_void_p, ctypes.c_void_p]),
+    "pcg_solve_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgStats), ctypes.c_void_p]),
     "fermion_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fermion_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -121,7 +134,7 @@ EXPORTS = {
     "fph_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(System),
                                         ctypes.c_int32]),
     "fph_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PcgOpts),
-                                       ctypes.POINTER(PcgStats), ctypes.c_void_p]),
+                                       ctypes.c_void_p, ctypes.c_void_p]),
     "fph_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PcgOpts),
                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "fph_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -149,15 +162,6 @@ EXPORTS = {
     "hmc_global_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                          ctypes.POINTER(UpdateStats), ctypes.c_void_p]),
-    "pcg_solve_concurrent": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
-                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
-                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(PcgOpts),
-                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p)]),
-    "hmc_trajectory_concurrent": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
-                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
-                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
-                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(HmcStats),
-                                                 ctypes.POINTER(ctypes.c_void_p)]),
     "fph_meas_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p]),
     "fph_meas_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "meas_fft": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,

@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("fph_lib.hip", "fph_hmc.hip", "fph_meas.hip",
-                                                    "fph_concurrent.hip", "fph_ssh.hip")]
+                                                    "fph_ssh.hip")]
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libholstein_hmc.so")
 
@@ -23,10 +23,25 @@ HIPCC_FLAGS = [
 
 
 def build(verbose=True):
+    """Compile every translation unit to an object in parallel, then link."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    objs = [os.path.join(OUT_DIR, os.path.basename(src) + ".o") for src in SRCS]
+
+    def compile_one(pair):
+        src, obj = pair
+        cmd = [hipcc, *compile_flags, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+
+    with ThreadPoolExecutor(max_workers=len(SRCS)) as ex:
+        list(ex.map(compile_one, zip(SRCS, objs)))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *SRCS, "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

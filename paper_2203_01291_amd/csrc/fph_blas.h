@@ -72,46 +72,15 @@ k_dbar(int N, int Ltau, const double* __restrict__ E64, double c4, double* __res
   dbar32[i] = (float)t;
 }
 
-// ------------------------------------------------------- state kernels --
-
-// Fold pending partials and publish the state (one block per rhs).
-__global__ void __launch_bounds__(256) k_advance(StIO io) {
-  __shared__ double red_sh[4];
-  __shared__ RhsState s_sh;
-  const int r = blockIdx.x;
-  state_begin<256>(io, r, &s_sh, red_sh);
-  state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, true);
-}
-
-// |v|^2 published as partials of `kind` (P_BB at the start of a solve,
-// P_NRM for a replaced residual).  Launch: grid (nblk, nrhs).
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_norm2(long d, const T* __restrict__ v, StIO io, int kind) {
-  __shared__ double red_sh[4];
-  __shared__ RhsState s_sh;
-  const int r = blockIdx.y;
-  state_begin<256>(io, r, &s_sh, red_sh);
-  if (s_sh.done) {
-    state_end(io, r, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
-    return;
-  }
-  const T* vr = v + (long)r * d;
-  double acc = 0.0;
-  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
-    const auto a = Vec4<T>::ld(vr + k);
-    acc += (double)a.x * (double)a.x + (double)a.y * (double)a.y +
-           (double)a.z * (double)a.z + (double)a.w * (double)a.w;
-  }
-  const double bs = block_sum<256>(acc, red_sh);
-  state_end(io, r, &s_sh, kind, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
-}
+// ------------------------------------------------------- CG update ------
 
 // CG update without preconditioner: alpha = rz / pAp (from the pending
 // P_PAP partials), u += alpha p, r -= alpha Ap, and |r|^2 as P_RR partials.
 // The direction written by this iteration's operator kernel is pb when the
-// iteration count is even, pa when odd (see InPUpdate).
-// Launch: grid (nblk, nrhs), 256 threads.
+// iteration count is even, pa when odd (see InPUpdate).  After an FP64
+// residual evaluation (the pending partials were P_RES) the kernel only
+// folds the decision.  FP32-refined: u is the FP32 correction, read as zero
+// while the state says it is zero.  Launch: grid (nblk, nrhs), 256 threads.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__ r,
@@ -133,11 +102,12 @@ k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__
     a0 = Vec4<T>::ld(Ap + off + k0);
   }
   state_begin<256>(io, rh, &s_sh, red_sh);
-  if (s_sh.done) {
+  if (s_sh.done || s_sh.folded != P_PAP) {
     state_end(io, rh, &s_sh, P_NONE, 0.0, blockIdx.x, gridDim.x, blockIdx.x == 0);
     return;
   }
   const bool odd = (s_sh.iter & 1) != 0;
+  const bool uz = s_sh.u32z != 0;
   const T* __restrict__ p = odd ? pa : pb;
   const T a = (T)s_sh.alpha;
   double acc = 0.0;
@@ -155,6 +125,7 @@ k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__
       pp = Vec4<T>::ld(p + o);
       aa = Vec4<T>::ld(Ap + o);
     }
+    if (uz) uu = V{};
     uu.x += a * pp.x; uu.y += a * pp.y; uu.z += a * pp.z; uu.w += a * pp.w;
     rr.x -= a * aa.x; rr.y -= a * aa.y; rr.z -= a * aa.z; rr.w -= a * aa.w;
     Vec4<T>::st(u + o, uu);
@@ -163,25 +134,8 @@ k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__
            (double)rr.z * (double)rr.z + (double)rr.w * (double)rr.w;
   }
   const double bs = block_sum<256>(acc, red_sh);
+  if (threadIdx.x == 0) s_sh.u32z = 0;
   state_end(io, rh, &s_sh, P_RR, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
-}
-
-// u64 += u32 (FP64 accumulation of the FP32 correction); u32 = 0.  Skips
-// right-hand sides marked done in `st` (no pending partials expected).
-// Launch: grid (nblk, nrhs).
-__global__ void __launch_bounds__(256)
-k_flush(long d, float* __restrict__ u32, double* __restrict__ u64, const RhsState* st) {
-  const int r = blockIdx.y;
-  if (st[r].done) return;
-  float* a = u32 + (long)r * d;
-  double* b = u64 + (long)r * d;
-  for (long k = 4 * (blockIdx.x * 256L + threadIdx.x); k < d; k += 4L * gridDim.x * 256) {
-    const float4 x = Vec4<float>::ld(a + k);
-    auto y = Vec4<double>::ld(b + k);
-    y.x += (double)x.x; y.y += (double)x.y; y.z += (double)x.z; y.w += (double)x.w;
-    Vec4<double>::st(b + k, y);
-    Vec4<float>::st(a + k, make_float4(0.f, 0.f, 0.f, 0.f));
-  }
 }
 
 // ------------------------------------------------------------ plain BLAS

@@ -126,20 +126,20 @@ FPH_DEVINL int xcd_contiguous(int i, int n) {
 // folds the total into the state.  No kernel waits for another block.
 enum Pend : int {
   P_NONE = 0,
-  P_BB = 1,    // |b|^2 at the start of a solve
   P_RR = 2,    // |r|^2 after a CG update (an iteration completed)
   P_PAP = 3,   // p . A p
   P_RZ = 4,    // r . z after preconditioning
-  P_TRUE = 5,  // |b - A u|^2 evaluated in FP64
-  P_NRM = 6,   // |r|^2 of a replaced residual
-  P_GD = 7     // (|r|^2, r . A r): both dots of single-reduction CG
+  P_RES = 5    // (|b - A u|^2, |b|^2) of an FP64 residual evaluation
 };
 
 constexpr int kPStride = 4096;  // partial slots per right-hand side
-constexpr int kPHalf = 2048;    // second value of two-value partials (P_GD)
+constexpr int kPHalf = 2048;    // second value of two-value partials (P_RES)
 
 // Per right-hand-side scalars of a CG solve.  Two copies alternate: a
-// kernel reads copy `in` and its first block writes copy `out`.
+// kernel reads copy `in` and its first block writes copy `out`.  The whole
+// control of a solve lives here: the kernels of every iteration fold the
+// partial sums of the previous kernel and take the same decisions in every
+// block, so the host only enqueues.
 struct RhsState {
   double tol;       // relative residual target
   double bb;        // |b|^2
@@ -153,18 +153,27 @@ struct RhsState {
   double beta;      // rz_next / rz
   double rr_true;   // |b - A u|^2 from the last FP64 evaluation
   double ru_thresh; // > 0: pause once rr < ru_thresh (FP32 residual replacement)
-  double gamma;     // single-reduction CG: gamma_i = r_i . r_i
-  double delta;     //   delta_i = r_i . A r_i
-  double gamma_prev;//   gamma_{i-1}
-  double alpha_prev;//   alpha_{i-1}
+  double rdelta;    // FP32-refined: replacement factor, lengthened when needed
+  double rr_pause;  // iterated |r|^2 when the right-hand side paused
   int iter;         // CG iterations completed
-  int done;         // nonzero: kernels skip this right-hand side
+  int done;         // nonzero: the CG-iteration kernels skip this right-hand side
   int status;       // FPH_ST_* bits
   int fresh;        // 1: the next direction update starts p = z
   int matvecs;
   int maxiter;
   int pend;         // Pend kind of the partials waiting in `pin`
   int npart;        // number of waiting partials
+  int final_;       // 1: finished; every kernel skips it
+  int replace;      // 1: the next operator kernel evaluates the FP64 residual
+  int started;      // the first residual (and |b|^2) has been evaluated
+  int outer;        // FP64 residual replacements after the first residual
+  int max_outer;    // cap on `outer`
+  int refined;      // FP32 iteration on an FP64 iterate (FP32-refined solve)
+  int upar;         // refined: the FP64 iterate is in u_dev (0) or the workspace (1)
+  int u32z;         // refined: the FP32 correction is zero (not written since the
+                    // last replacement)
+  int own;          // the pause came from the iterated residual reaching tol
+  int folded;       // Pend kind the last state_begin folded (P_NONE: none)
 };
 
 struct StIO {
@@ -181,6 +190,8 @@ struct StIO {
 // Ping-pong bookkeeping of the CG state for a sequence of launches: each
 // state-aware kernel reads copy `cur`, writes copy `cur ^ 1`; `np` is the
 // number of partials per right-hand side the launch will write (0: none).
+// The sequence depends only on the launches, never on values, so the host
+// can enqueue a whole solve without reading anything back.
 struct StateSeq {
   RhsState* st[2];
   double* part[2];
@@ -233,45 +244,107 @@ FPH_DEVINL double reduce_partials(const double* part, int n, double* sh) {
   return block_sum<NT>(v, sh);
 }
 
-// Fold a completed reduction into the state (thread 0 only).
-FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, int precond) {
+// A right-hand side stops for good with status bits `bits`.
+FPH_DEVINL void rhs_finish(RhsState& s, int bits) {
+  s.status |= bits;
+  s.done = 1;
+  s.final_ = 1;
+  s.replace = 0;
+}
+
+// The iterated residual asks for an FP64 residual evaluation: the CG
+// kernels skip the right-hand side until the next operator kernel has
+// evaluated it.
+FPH_DEVINL void rhs_pause(RhsState& s, int own) {
+  s.done = 1;
+  s.replace = 1;
+  s.own = own;
+  s.rr_pause = s.rr;
+}
+
+// Decision after an FP64 residual evaluation r = b - A u (rr = |r|^2,
+// bb = |b|^2 at the first one).  FP32-refined: the evaluation also moved
+// the FP64 iterate to the other buffer with the FP32 correction added, so
+// the correction restarts from zero.  Continuing right-hand sides keep
+// their directions (reliable update) unless the evaluated residual is far
+// from the iterated one, or, in FP64, the iterated residual had claimed
+// convergence; FP32-refined shortens the replacement interval (delta ->
+// sqrt delta, at most 0.5) when the evaluated residual exceeds the
+// iterated one more than twice.
+FPH_DEVINL void rhs_after_residual(RhsState& s, double rr, double bb, int precond) {
+  s.matvecs += 1;
+  s.replace = 0;
+  if (s.refined) {
+    s.upar ^= 1;
+    s.u32z = 1;
+  }
+  const bool first = !s.started;
+  if (first) {
+    s.started = 1;
+    s.bb = bb;
+    s.tol2 = s.tol * s.tol * bb;
+    if (!isfinite(bb)) {
+      s.rr_true = rr;
+      rhs_finish(s, 8);
+      return;
+    }
+    if (bb == 0.0) {  // b = 0: u = 0 exactly (the final kernel writes it)
+      s.rr_true = 0.0;
+      rhs_finish(s, 1);
+      return;
+    }
+  } else {
+    s.outer += 1;
+  }
+  s.rr_true = rr;
+  s.rr = rr;
+  if (!precond) s.rz_next = rr;
+  if (!isfinite(rr)) {
+    rhs_finish(s, 8);
+    return;
+  }
+  if (rr <= s.tol2) {
+    rhs_finish(s, 1);
+    return;
+  }
+  if (s.iter >= s.maxiter || s.outer >= s.max_outer) {
+    rhs_finish(s, 2);
+    return;
+  }
+  if (first) {
+    s.fresh = 1;
+  } else if (s.refined) {
+    if (rr > 100.0 * s.rr_pause) s.fresh = 1;
+    if (rr > 4.0 * s.rr_pause) s.rdelta = fmin(0.5, sqrt(s.rdelta));
+  } else if (s.own) {
+    s.fresh = 1;  // FP64: the iterated residual said converged, the true one did not
+  }
+  s.ru_thresh = s.refined ? s.rdelta * s.rdelta * rr : 0.0;
+  s.own = 0;
+  s.done = 0;
+}
+
+// Fold a completed reduction into the state (thread 0 only).  tot2 is the
+// second value of two-value partials.
+FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, double tot2, int precond) {
   switch (kind) {
-    case P_BB:
-      s.bb = tot;
-      s.tol2 = s.tol * s.tol * tot;
-      s.rr = tot;
-      s.rr_true = tot;
-      s.rz_next = tot;
-      if (!isfinite(tot)) {
-        s.status |= 8;
-        s.done = 1;
-      } else if (tot == 0.0) {
-        s.status |= 1;
-        s.done = 1;
-      }
-      break;
     case P_RR:
       s.rr = tot;
       s.iter += 1;
       if (!precond) s.rz_next = tot;
       if (!isfinite(tot)) {
-        s.status |= 8;
-        s.done = 1;
+        rhs_finish(s, 8);
       } else if (tot <= s.tol2) {
-        s.done = 1;
-      } else if (s.iter >= s.maxiter) {
-        s.status |= 2;
-        s.done = 1;
-      } else if (tot < s.ru_thresh) {
-        s.done = 1;  // pause for an FP64 residual replacement
+        rhs_pause(s, 1);
+      } else if (s.iter >= s.maxiter || tot < s.ru_thresh) {
+        rhs_pause(s, 0);
       }
       break;
     case P_PAP:
       s.pAp = tot;
       s.matvecs += 1;
       if (!(tot > 0.0) || !isfinite(tot)) {
-        s.status |= isfinite(tot) ? 4 : 8;
-        s.done = 1;
+        rhs_finish(s, isfinite(tot) ? 4 : 8);
         s.alpha = 0.0;
       } else {
         s.alpha = s.rz / tot;
@@ -279,45 +352,15 @@ FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, int precond) {
       break;
     case P_RZ:
       s.rz_next = tot;
-      if (!(tot > 0.0) || !isfinite(tot)) {
-        s.status |= isfinite(tot) ? 4 : 8;
-        s.done = 1;
-      }
+      if (!(tot > 0.0) || !isfinite(tot)) rhs_finish(s, isfinite(tot) ? 4 : 8);
       break;
-    case P_TRUE:
-      s.rr_true = tot;
-      s.matvecs += 1;
-      if (!isfinite(tot)) {
-        s.status |= 8;
-        s.done = 1;
-      }
-      break;
-    case P_NRM:
-      s.rr = tot;
-      if (!precond) s.rz_next = tot;
-      if (!isfinite(tot)) {
-        s.status |= 8;
-        s.done = 1;
-      }
-      break;
-    case P_GD:  // tot = gamma; delta was stored by the caller
-      s.gamma = tot;
-      s.rr = tot;
-      if (!isfinite(tot) || !isfinite(s.delta)) {
-        s.status |= 8;
-        s.done = 1;
-      } else if (tot <= s.tol2) {
-        s.done = 1;
-      } else if (s.iter >= s.maxiter) {
-        s.status |= 2;
-        s.done = 1;
-      } else if (tot < s.ru_thresh) {
-        s.done = 1;  // pause for an FP64 residual replacement
-      }
+    case P_RES:
+      rhs_after_residual(s, tot, tot2, precond);
       break;
     default:
       break;
   }
+  s.folded = kind;
   s.pend = P_NONE;
 }
 
@@ -349,7 +392,7 @@ FPH_DEVINL void state_begin(const StIO& io, int r, RhsState* s_sh, double* red_s
       } else {
         for (int k = threadIdx.x; k < st.npart; k += 64) v += part[k];
       }
-      if (st.pend == P_GD)
+      if (st.pend == P_RES)
         for (int k = threadIdx.x; k < st.npart; k += 64) v2 += part[kPHalf + k];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -358,12 +401,13 @@ FPH_DEVINL void state_begin(const StIO& io, int r, RhsState* s_sh, double* red_s
       }
       if (threadIdx.x == 0) {
         RhsState t = st;
-        t.delta = v2;
-        apply_pending(t, st.pend, v, io.precond);
+        apply_pending(t, st.pend, v, v2, io.precond);
         *s_sh = t;
       }
     } else if (threadIdx.x == 0) {
-      *s_sh = st;
+      RhsState t = st;
+      t.folded = P_NONE;
+      *s_sh = t;
     }
   }
   __syncthreads();
@@ -376,7 +420,7 @@ FPH_DEVINL void state_end(const StIO& io, int r, RhsState* s_sh, int kind, doubl
   if (threadIdx.x == 0) {
     if (kind != P_NONE) {
       io.pout[(long)r * kPStride + block] = blocksum;
-      if (kind == P_GD) io.pout[(long)r * kPStride + kPHalf + block] = blocksum2;
+      if (kind == P_RES) io.pout[(long)r * kPStride + kPHalf + block] = blocksum2;
       s_sh->pend = kind;
       s_sh->npart = nblocks;
     }

@@ -437,7 +437,7 @@ int op_MT(const fph_hmc_s* c, int nr, const double* in, double* out, void* strea
 int op_solve(const fph_hmc_s* c, int nr, const double* b, double* u, const fph_pcg_opts_t* o,
              fph_pcg_stats_t* st, void* stream) {
   if (c->ssh) return ssh_solve(c->ssh, nr, b, u, o, st, stream);
-  return pcg_solve(c->h, nr, b, u, o, st, stream);
+  return pcg_solve_sync(c->h, nr, b, u, o, st, stream);
 }
 
 int op_force(const fph_hmc_s* c, int nr, const double* u, double* grad, double scale, void* stream) {

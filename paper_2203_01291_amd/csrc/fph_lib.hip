@@ -1,8 +1,8 @@
 // C ABI of the gfx950 fermion solver (declared in include/holstein_hmc.h).
 //
 // One translation unit: kernels come from the fph_*.h headers; this file
-// owns the handle, workspace, launch configuration and the host side of
-// the conjugate-gradient loop.
+// owns the handle, workspace, launch configuration and the enqueueing of
+// the conjugate-gradient solve (whose control runs on the device).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,8 +22,11 @@
 #include "fph_internal.h"
 #include "fph_matvec.h"
 #include "fph_precond.h"
+#include "fph_solve.h"
 
 using namespace fph;
+
+static_assert(sizeof(PcgStatsDev) == sizeof(fph_pcg_stats_t), "stats layout");
 
 #define FPH_CHECK(call)                          \
   do {                                           \
@@ -58,15 +61,19 @@ struct fph_handle_s {
   float* E32;
   double* dbar64;
   float* dbar32;
-  // CG workspace, max_rhs right-hand sides each.  Standard PCG uses r, z,
-  // pa/pb, Ap; single-reduction CG uses r/rb, w/wb (w = A r), s/sb
-  // (s = A p) and pa/pb.
-  double *r64, *rb64, *pa64, *pb64, *Ap64, *wb64, *z64, *sb64;
-  float *u32, *r32, *rb32, *pa32, *pb32, *Ap32, *wb32, *z32, *sb32;
+  // CG workspace, max_rhs right-hand sides each: r, z, the two direction
+  // buffers pa/pb, Ap in the iteration precision; FP32-refined also uses the
+  // FP32 correction u32 and the second FP64 iterate buffer u64b.
+  double *r64, *pa64, *pb64, *Ap64, *z64, *u64b;
+  float *u32, *r32, *pa32, *pb32, *Ap32, *z32;
   // CG state (two alternating copies) and partial sums (two buffers)
   RhsState* st[2];
   double* part[2];    // max_rhs * kPStride each
-  RhsState* st_host;  // pinned mirror
+  double* fin_part;   // partials of the final S_F, max_rhs * kPStride
+  PcgStatsDev* stats_dev;   // statistics of the last blocking solve
+  PcgStatsDev* stats_pin;   // pinned mirror
+  int* open_pin;            // pinned: right-hand sides not finished (two probes)
+  hipEvent_t probe_ev[2];
   double* tmp64;      // max_rhs doubles
   double* tmp_host;   // pinned, max_rhs doubles
   // preconditioner
@@ -76,6 +83,11 @@ struct fph_handle_s {
 };
 
 namespace {
+
+// Residual evaluations after the first that a solve may use (opts.max_outer
+// = 0), and slots between the probes of the blocking driver (opts.chunk = 0).
+constexpr int kDefaultMaxOuter = 32;
+constexpr long kDefaultSlotChunk = 16;
 
 size_t vbytes(const fph_handle_s* h, size_t elem) { return (size_t)h->g.d * h->max_rhs * elem; }
 
@@ -130,8 +142,7 @@ int pick_chunk(const Geom& g, int nrhs, int S, int slots) {
 }
 
 template <typename T, int NT, int MS, class In, class Epi>
-hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, In in, Epi epi, StateSeq* sq,
-                          hipStream_t s) {
+hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, In in, Epi epi, hipStream_t s) {
   const Geom& g = h->g;
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
   const size_t lds = 4 * (size_t)S * g.N * sizeof(T);
@@ -143,28 +154,54 @@ hipError_t launch_mtm_cfg(const fph_handle_s* h, int nrhs, In in, Epi epi, State
   const int Tch = pick_chunk(g, nrhs, S, resident_slots((const void*)kern, NT, lds));
   const int nchunks = (g.Ltau + Tch - 1) / Tch;
   const int nblk = (nchunks + S - 1) / S;
-  const StIO io = sq ? sq->next(Epi::kKind != P_NONE ? nblk : 0)
-                     : StIO{nullptr, nullptr, nullptr, nullptr, 0, 0};
   hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g,
                      (const T*)(sizeof(T) == 8 ? (const void*)h->E64 : (const void*)h->E32),
-                     (T)h->th, Tch, nblk, in, epi, io);
+                     (T)h->th, Tch, nblk, in, epi);
   return hipGetLastError();
 }
 
-// Fused operator launch; with sq the kernel takes part in the solver's
-// state sequence (sq == nullptr: plain operator call).
+// Fused operator launch (plain apply).
 template <typename T, class In, class Epi>
-hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, StateSeq* sq,
-                      hipStream_t s) {
+hipError_t launch_mtm(const fph_handle_s* h, int nrhs, In in, Epi epi, hipStream_t s) {
   // One plaquette per thread; up to 1024 plaquettes (L <= 64) per slice.
   const int Q = h->g.Q;
-  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, in, epi, sq, s);
-  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, in, epi, sq, s);
-  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, in, epi, sq, s);
-  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, in, epi, sq, s);
+  if (Q <= 64) return launch_mtm_cfg<T, 64, 1>(h, nrhs, in, epi, s);
+  if (Q <= 256) return launch_mtm_cfg<T, 256, 1>(h, nrhs, in, epi, s);
+  if (Q <= 512) return launch_mtm_cfg<T, 512, 1>(h, nrhs, in, epi, s);
+  return launch_mtm_cfg<T, 1024, 1>(h, nrhs, in, epi, s);
 }
 
-StIO no_state() { return StIO{nullptr, nullptr, nullptr, nullptr, 0, 0}; }
+// The operator kernel of a solver slot (k_slot_mtm), TI the iteration
+// precision; LDS sized for the FP64 residual path.
+template <typename TI, int NT>
+hipError_t launch_slot_mtm_cfg(const fph_handle_s* h, int nrhs, const SlotArgs<TI>& a,
+                               StateSeq& sq, hipStream_t s) {
+  const Geom& g = h->g;
+  const int S = (g.Q <= NT) ? NT / g.Q : 1;
+  const size_t lds = 4 * (size_t)S * g.N * sizeof(double);
+  auto kern = k_slot_mtm<TI, NT, 1>;
+  {
+    hipError_t e = allow_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+  }
+  const int Tch = pick_chunk(g, nrhs, S, resident_slots((const void*)kern, NT, lds));
+  const int nchunks = (g.Ltau + Tch - 1) / Tch;
+  const int nblk = (nchunks + S - 1) / S;
+  if (nblk > kPHalf) return hipErrorInvalidConfiguration;  // two-value partials
+  const StIO io = sq.next(nblk);
+  hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g, Tch, nblk, a, io);
+  return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_slot_mtm(const fph_handle_s* h, int nrhs, const SlotArgs<TI>& a, StateSeq& sq,
+                           hipStream_t s) {
+  const int Q = h->g.Q;
+  if (Q <= 64) return launch_slot_mtm_cfg<TI, 64>(h, nrhs, a, sq, s);
+  if (Q <= 256) return launch_slot_mtm_cfg<TI, 256>(h, nrhs, a, sq, s);
+  if (Q <= 512) return launch_slot_mtm_cfg<TI, 512>(h, nrhs, a, sq, s);
+  return launch_slot_mtm_cfg<TI, 1024>(h, nrhs, a, sq, s);
+}
 
 template <typename T, int NT, int MS, int MODE>
 hipError_t launch_M_cfg(const fph_handle_s* h, int nrhs, const T* v, T* out, double coef,
@@ -281,30 +318,30 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   ALLOC(h->dbar64, (size_t)max_rhs * h->g.N * sizeof(double));
   ALLOC(h->dbar32, (size_t)max_rhs * h->g.N * sizeof(float));
   ALLOC(h->r64, vbytes(h, 8));
-  ALLOC(h->rb64, vbytes(h, 8));
   ALLOC(h->pa64, vbytes(h, 8));
   ALLOC(h->pb64, vbytes(h, 8));
   ALLOC(h->Ap64, vbytes(h, 8));
-  ALLOC(h->wb64, vbytes(h, 8));
   ALLOC(h->z64, vbytes(h, 8));
-  ALLOC(h->sb64, vbytes(h, 8));
+  ALLOC(h->u64b, vbytes(h, 8));
   ALLOC(h->u32, vbytes(h, 4));
   ALLOC(h->r32, vbytes(h, 4));
-  ALLOC(h->rb32, vbytes(h, 4));
   ALLOC(h->pa32, vbytes(h, 4));
   ALLOC(h->pb32, vbytes(h, 4));
   ALLOC(h->Ap32, vbytes(h, 4));
-  ALLOC(h->wb32, vbytes(h, 4));
   ALLOC(h->z32, vbytes(h, 4));
-  ALLOC(h->sb32, vbytes(h, 4));
   ALLOC(h->st[0], max_rhs * sizeof(RhsState));
   ALLOC(h->st[1], max_rhs * sizeof(RhsState));
   ALLOC(h->part[0], (size_t)max_rhs * kPStride * sizeof(double));
   ALLOC(h->part[1], (size_t)max_rhs * kPStride * sizeof(double));
+  ALLOC(h->fin_part, (size_t)max_rhs * kPStride * sizeof(double));
+  ALLOC(h->stats_dev, max_rhs * sizeof(PcgStatsDev));
   ALLOC(h->tmp64, max_rhs * sizeof(double));
 #undef ALLOC
-  if (e == hipSuccess) e = hipHostMalloc((void**)&h->st_host, max_rhs * sizeof(RhsState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->stats_pin, max_rhs * sizeof(PcgStatsDev), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->open_pin, 2 * sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->tmp_host, max_rhs * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->probe_ev[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->probe_ev[1], hipEventDisableTiming);
   if (e == hipSuccess) e = hipMemset(h->st[0], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = hipMemset(h->st[1], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = pc_create(&h->pc, h->g, max_rhs);
@@ -329,14 +366,17 @@ int fph_get_lattice(fph_handle_t h, fph_lattice_t* lat, int32_t* max_rhs) {
 int fph_destroy(fph_handle_t h) {
   if (h == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* devptrs[] = {h->E64, h->E32, h->dbar64, h->dbar32, h->r64, h->rb64, h->pa64,
-                     h->pb64, h->Ap64, h->wb64, h->z64, h->sb64, h->u32, h->r32, h->rb32,
-                     h->pa32, h->pb32, h->Ap32, h->wb32, h->z32, h->sb32,
-                     h->st[0], h->st[1], h->part[0], h->part[1], h->tmp64};
+  void* devptrs[] = {h->E64, h->E32, h->dbar64, h->dbar32, h->r64, h->pa64, h->pb64,
+                     h->Ap64, h->z64, h->u64b, h->u32, h->r32, h->pa32, h->pb32, h->Ap32,
+                     h->z32, h->st[0], h->st[1], h->part[0], h->part[1], h->fin_part,
+                     h->stats_dev, h->tmp64};
   for (void* p : devptrs)
     if (p) (void)hipFree(p);
-  if (h->st_host) (void)hipHostFree(h->st_host);
+  if (h->stats_pin) (void)hipHostFree(h->stats_pin);
+  if (h->open_pin) (void)hipHostFree(h->open_pin);
   if (h->tmp_host) (void)hipHostFree(h->tmp_host);
+  for (hipEvent_t ev : h->probe_ev)
+    if (ev) (void)hipEventDestroy(ev);
   pc_destroy(&h->pc);
   delete h;
   return FPH_OK;
@@ -406,15 +446,15 @@ int fermion_matvec(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, const
     double* out = (double*)out_dev;
     if (op == FPH_OP_M) e = launch_M<double, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<double>(h, nrhs, in, out, s);
-    else if (stream_out) e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStream<double>{out}, nullptr, s);
-    else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, nullptr, s);
+    else if (stream_out) e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStream<double>{out}, s);
+    else e = launch_mtm<double>(h, nrhs, InPlain<double>{in}, EpiStore<double>{out}, s);
   } else {
     const float* in = (const float*)in_dev;
     float* out = (float*)out_dev;
     if (op == FPH_OP_M) e = launch_M<float, 0>(h, nrhs, in, out, 0.0, s);
     else if (op == FPH_OP_MT) e = launch_MT<float>(h, nrhs, in, out, s);
-    else if (stream_out) e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStream<float>{out}, nullptr, s);
-    else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, nullptr, s);
+    else if (stream_out) e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStream<float>{out}, s);
+    else e = launch_mtm<float>(h, nrhs, InPlain<float>{in}, EpiStore<float>{out}, s);
   }
   if (e != hipSuccess) return fail_hip(e);
   return FPH_OK;
@@ -486,102 +526,101 @@ int fph_precond_info(fph_handle_t h, double* bounds_host, int32_t* np_host, void
 
 namespace {
 
-// One CG iteration for right-hand sides 0..nrhs-1 in precision T.  The
-// direction buffers pa/pb alternate on the device with each right-hand
-// side's own iteration parity (right-hand sides that are paused or done
-// skip the iteration without flipping it).
-template <typename T>
-hipError_t cg_iteration(fph_handle_s* h, int nrhs, bool precond, T* u, T* r, T* z, T* pa,
-                        T* pb, T* Ap, const T* dbar, StateSeq& sq, hipStream_t s) {
-  const long d = h->g.d;
-  const T* zz = precond ? z : r;
-  InPUpdate<T> in{zz, pa, pb, nullptr, nullptr, (T)0, 0};
-  hipError_t e = launch_mtm<T>(h, nrhs, in, EpiDot<T>{Ap}, &sq, s);
-  if (e != hipSuccess) return e;
-  if (!precond) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(elem_blocks(d), nrhs), dim3(256), 0, s, d, u,
-                       (const T*)pa, (const T*)pb, r, (const T*)Ap, sq.next(elem_blocks(d)));
-    e = hipGetLastError();
-  } else {
-    e = pc_cg_update<T>(&h->pc, h->g, dbar, nrhs, u, pa, pb, r, Ap, z, sq, s);
-  }
-  return e;
-}
-
-// Buffers of one precision for the CG driver.
+// Buffers of one precision for a solve.
 template <typename T>
 struct Work {
-  T *u, *r, *rb, *z, *pa, *pb, *Ap, *wb, *sb;
+  T *r, *z, *pa, *pb, *Ap;
   const T* dbar;
 };
 
-Work<double> work64(fph_handle_s* h, double* u) {
-  return Work<double>{u, h->r64, h->rb64, h->z64, h->pa64, h->pb64, h->Ap64, h->wb64, h->sb64,
-                      h->dbar64};
-}
-Work<float> work32(fph_handle_s* h) {
-  return Work<float>{h->u32, h->r32, h->rb32, h->z32, h->pa32, h->pb32, h->Ap32, h->wb32,
-                     h->sb32, h->dbar32};
-}
-
-// Single-reduction CG: w = A r for the current residual buffer and both
-// dots (P_GD).  Starts a solve and follows every residual replacement.
-template <typename T>
-hipError_t cgcg_start(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq, hipStream_t s) {
-  InParity<T> in{w.r, w.rb, nullptr};
-  EpiGD<T> epi{w.Ap, w.wb, 0, nullptr};
-  return launch_mtm<T>(h, nrhs, in, epi, &sq, s);
-}
-
-// One single-reduction CG iteration (one launch).
-template <typename T>
-hipError_t cgcg_iteration(fph_handle_s* h, int nrhs, const Work<T>& w, StateSeq& sq,
-                          hipStream_t s) {
-  InCGCG<T> in{w.r, w.rb, w.z, w.sb, w.pa, w.pb, w.Ap, w.wb, w.u,
-               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (T)0, (T)0, 0};
-  EpiGD<T> epi{w.Ap, w.wb, 1, nullptr};
-  return launch_mtm<T>(h, nrhs, in, epi, &sq, s);
-}
-
-// Fold pending partials, copy the state to the host and wait.
-hipError_t sync_state(fph_handle_s* h, int nrhs, StateSeq& sq, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(nrhs), dim3(256), 0, s, sq.next(0));
-  hipError_t e = hipGetLastError();
+// One slot (fph_solve.h): the operator kernel, then the CG update (without
+// preconditioner) or the forward transform with the update, the series
+// F F^T and the inverse transform with r.z.  `uit` is the vector the update
+// advances: u_dev in FP64, the FP32 correction in FP32-refined solves.
+template <typename TI>
+hipError_t enqueue_slot(fph_handle_s* h, int nrhs, bool pre, const SlotArgs<TI>& a, TI* uit,
+                        const Work<TI>& w, StateSeq& sq, hipStream_t s) {
+  hipError_t e = launch_slot_mtm<TI>(h, nrhs, a, sq, s);
   if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(h->st_host, sq.latest(), nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
+  if (!pre) {
+    const int nb = elem_blocks(h->g.d);
+    hipLaunchKernelGGL(k_cg_update<TI>, dim3(nb, nrhs), dim3(256), 0, s, h->g.d, uit,
+                       (const TI*)w.pa, (const TI*)w.pb, w.r, (const TI*)w.Ap, sq.next(nb));
+    return hipGetLastError();
+  }
+  return pc_cg_update<TI>(&h->pc, h->g, w.dbar, nrhs, uit, w.pa, w.pb, w.r, w.Ap, w.z, sq, s);
 }
 
-hipError_t push_state(fph_handle_s* h, int nrhs, StateSeq& sq, hipStream_t s) {
-  return hipMemcpyAsync(sq.latest(), h->st_host, nrhs * sizeof(RhsState), hipMemcpyHostToDevice, s);
-}
+// A solve as a fixed sequence of launches: start, `total` slots, finish.
+struct SolveRun {
+  fph_handle_s* h;
+  int nrhs;
+  const double* b;
+  double* u;
+  bool pre, mixed, zero;
+  long total;  // 1 + maxiter + max_outer
+  SolveInit init;
+  StateSeq sq;
+  SlotArgs<double> a64;
+  SlotArgs<float> a32;
+  Work<double> w64;
+  Work<float> w32;
 
-// r = b - A u in FP64 (stored as TR), |r|^2 as P_NRM partials, and with a
-// preconditioner z = F F^T r with r.z.  Used to start a solve from a guess
-// and for every residual replacement.
-// For single-reduction CG (no preconditioner) the residual goes to the
-// buffer of the current iteration parity `par` and is followed by w = A r
-// and both dots; with the preconditioner r and z = F F^T r with r.z.
-template <typename TR>
-hipError_t fp64_residual(fph_handle_s* h, int nrhs, bool pre, bool cgcg, int par,
-                         const double* b, const double* u, const Work<TR>& w, StateSeq& sq,
-                         hipStream_t s) {
-  const long d = h->g.d;
-  TR* r = (cgcg && par == 1) ? w.rb : w.r;
-  hipError_t e = launch_mtm<double>(h, nrhs, InPlain<double>{u}, EpiResidual<TR>{b, r}, &sq, s);
-  if (e != hipSuccess) return e;
-  if (cgcg) return cgcg_start<TR>(h, nrhs, w, sq, s);
-  hipLaunchKernelGGL(k_norm2<TR>, dim3(elem_blocks(d), nrhs), dim3(256), 0, s, d, (const TR*)r,
-                     sq.next(elem_blocks(d)), (int)P_NRM);
-  e = hipGetLastError();
-  if (e != hipSuccess || !pre) return e;
-  return pc_apply<TR>(&h->pc, h->g, w.dbar, FPH_PC_FFT, nrhs, r, w.z, r, sq, s);
-}
+  SolveRun(fph_handle_s* hh, int nr, const double* bb, double* uu, const fph_pcg_opts_t* o)
+      : h(hh), nrhs(nr), b(bb), u(uu) {
+    pre = o->use_precond != 0;
+    mixed = o->prec == FPH_F32_REFINED;
+    zero = o->zero_guess != 0;
+    const int max_outer = o->max_outer > 0 ? o->max_outer : kDefaultMaxOuter;
+    total = 1L + o->maxiter + max_outer;
+    init.tol = o->tol;
+    // Replacement factor: FP32 CG drifts from the true residual at a rate
+    // set by the condition number, which the preconditioner lowers.
+    init.rdelta = o->ru_delta > 0.0 ? std::min(o->ru_delta, 0.5) : (pre ? 0.1 : 0.3);
+    init.maxiter = o->maxiter;
+    init.max_outer = max_outer;
+    init.refined = mixed ? 1 : 0;
+    init.pad = 0;
+    sq = StateSeq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true, 0};
+    w64 = Work<double>{h->r64, h->z64, h->pa64, h->pb64, h->Ap64, h->dbar64};
+    w32 = Work<float>{h->r32, h->z32, h->pa32, h->pb32, h->Ap32, h->dbar32};
+    a64 = SlotArgs<double>{h->E64, h->E64, h->th, h->th, pre ? w64.z : w64.r, w64.pa, w64.pb,
+                           w64.Ap, b, w64.r, u, h->u64b, h->u32};
+    a32 = SlotArgs<float>{h->E32, h->E64, (float)h->th, h->th, pre ? w32.z : w32.r, w32.pa,
+                          w32.pb, w32.Ap, b, w32.r, u, h->u64b, h->u32};
+  }
 
-}  // namespace
+  hipError_t start(hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, s, nrhs, init, sq.latest());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !zero) return e;
+    const long n = (long)nrhs * h->g.d;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<long>((n + 1023) / 1024, 2048)),
+                       dim3(256), 0, s, n, u);
+    return hipGetLastError();
+  }
 
-namespace {
+  hipError_t slots(long n, hipStream_t s) {
+    for (long k = 0; k < n; ++k) {
+      const hipError_t e = mixed ? enqueue_slot<float>(h, nrhs, pre, a32, h->u32, w32, sq, s)
+                                 : enqueue_slot<double>(h, nrhs, pre, a64, u, w64, sq, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  hipError_t finish(PcgStatsDev* stats, hipStream_t s) {
+    const int nb = elem_blocks(h->g.d);
+    hipLaunchKernelGGL(k_solve_final, dim3(nb, nrhs), dim3(256), 0, s, h->g.d,
+                       (const RhsState*)sq.latest(), b, u, (const double*)h->u64b,
+                       (const float*)h->u32, h->fin_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_solve_stats, dim3(nrhs), dim3(256), 0, s, nb,
+                       (const RhsState*)sq.latest(), (const double*)h->fin_part, stats);
+    return hipGetLastError();
+  }
+};
 
 // The one-launch cooperative FP32-refined solve (fph_coop.h) for one
 // right-hand side.  Workgroups own chunks of slices; the chunk length is
@@ -643,255 +682,122 @@ hipError_t coop_launch(fph_handle_s* h, const double* b, double* u, const fph_pc
   return hipLaunchCooperativeKernel(kern, dim3(nblk), dim3(NT), args, (unsigned)lds, s);
 }
 
-int coop_solve(fph_handle_s* h, const double* b_dev, double* u_dev, const fph_pcg_opts_t* opts,
-               double delta, fph_pcg_stats_t* stats, hipStream_t s) {
+// Statistics of a cooperative solve in the layout of fph_pcg_stats_t, with
+// S_F from the partials of b . u.
+__global__ void __launch_bounds__(256)
+k_coop_stats(int nb, const CoopStats* __restrict__ in, const double* __restrict__ part,
+             PcgStatsDev* __restrict__ out) {
+  __shared__ double red_sh[4];
+  const double act = reduce_partials<256>(part, nb, red_sh);
+  if (threadIdx.x == 0) {
+    const CoopStats c = *in;
+    PcgStatsDev o;
+    o.status = c.status;
+    o.iters = c.iters;
+    o.outer_iters = c.outer;
+    o.matvecs = c.matvecs;
+    o.rel_resid = c.bb > 0.0 ? sqrt(c.rr_true / c.bb) : 0.0;
+    o.action = act;
+    *out = o;
+  }
+}
+
+hipError_t coop_enqueue(fph_handle_s* h, const double* b_dev, double* u_dev,
+                        const fph_pcg_opts_t* opts, PcgStatsDev* stats, hipStream_t s) {
   CoopStats* out = reinterpret_cast<CoopStats*>(h->part[1]);
   const int Q = h->g.Q;
   const int target = opts->chunk > 0 ? opts->chunk : 128;
+  const double delta = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3;
   hipError_t e;
   if (Q <= 64) e = coop_launch<64>(h, b_dev, u_dev, opts, delta, target, out, s);
   else if (Q <= 256) e = coop_launch<256>(h, b_dev, u_dev, opts, delta, target, out, s);
   else if (Q <= 512) e = coop_launch<512>(h, b_dev, u_dev, opts, delta, target, out, s);
   else e = coop_launch<1024>(h, b_dev, u_dev, opts, delta, target, out, s);
-  if (e != hipSuccess) return fail_hip(e);
-  CoopStats res;
-  FPH_CHECK(hipMemcpyAsync(&res, out, sizeof(res), hipMemcpyDeviceToHost, s));
-  FPH_CHECK(fermion_action(h, 1, b_dev, u_dev, h->tmp64, s) == FPH_OK ? hipSuccess
-                                                                       : hipErrorUnknown);
-  FPH_CHECK(hipMemcpyAsync(h->tmp_host, h->tmp64, sizeof(double), hipMemcpyDeviceToHost, s));
-  FPH_CHECK(hipStreamSynchronize(s));
-  if (stats) {
-    stats[0].status = res.status;
-    stats[0].iters = res.iters;
-    stats[0].outer_iters = res.outer;
-    stats[0].matvecs = res.matvecs;
-    stats[0].rel_resid = res.bb > 0.0 ? std::sqrt(res.rr_true / res.bb) : 0.0;
-    stats[0].action = h->tmp_host[0];
-  }
+  if (e != hipSuccess) return e;
+  const int nb = elem_blocks(h->g.d);
+  hipLaunchKernelGGL(k_dot_partials, dim3(nb, 1), dim3(256), 0, s, h->g.d, b_dev,
+                     (const double*)u_dev, h->fin_part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_coop_stats, dim3(1), dim3(256), 0, s, nb, (const CoopStats*)out,
+                     (const double*)h->fin_part, stats);
+  return hipGetLastError();
+}
+
+int check_solve(const fph_handle_s* h, int nrhs, const double* b_dev, const double* u_dev,
+                const fph_pcg_opts_t* opts) {
+  if (h == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
+  if (!h->have_field) return FPH_E_NOFIELD;
+  if (nrhs < 1 || nrhs > h->max_rhs || (h->nfields && nrhs > h->nfields * h->g.rpf))
+    return FPH_E_NRHS;
+  if (opts->prec != FPH_F64 && opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
+  if (!(opts->tol >= 0.0) || opts->maxiter < 1 || opts->max_outer < 0 ||
+      (opts->variant != 0 && opts->variant != 2))
+    return FPH_E_ARG;
+  if (opts->variant == 2 &&
+      (opts->prec != FPH_F32_REFINED || opts->use_precond != 0 || nrhs != 1 || h->nfields))
+    return FPH_E_ARG;
   return FPH_OK;
 }
 
 }  // namespace
 
 extern "C" int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
-                         const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats, void* stream) {
-  if (h == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
-  if (!h->have_field) return FPH_E_NOFIELD;
-  if (nrhs < 1 || nrhs > h->max_rhs || (h->nfields && nrhs > h->nfields * h->g.rpf)) return FPH_E_NRHS;
-  if (opts->prec != FPH_F64 && opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
-  if (!(opts->tol >= 0.0) || opts->maxiter < 1 || opts->variant < 0 || opts->variant > 2)
-    return FPH_E_ARG;
-  if (opts->variant == 2 &&
-      (opts->prec != FPH_F32_REFINED || opts->use_precond != 0 || nrhs != 1 || h->nfields))
-    return FPH_E_ARG;
+                         const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_dev, void* stream) {
+  const int rc = check_solve(h, nrhs, b_dev, u_dev, opts);
+  if (rc != FPH_OK) return rc;
+  if (stats_dev == nullptr) return FPH_E_NULL;
   hipStream_t s = (hipStream_t)stream;
-  if (opts->variant == 2)
-    return coop_solve(h, b_dev, u_dev, opts,
-                      opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3, stats, s);
-  const long d = h->g.d;
-  const int nb = elem_blocks(d);
-  const bool pre = opts->use_precond != 0;
-  const bool mixed = opts->prec == FPH_F32_REFINED;
-  // Default replacement interval: FP32 CG drifts from the true residual at
-  // a rate set by the condition number, which the preconditioner lowers.
-  const double delta0 = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : (pre ? 0.1 : 0.3);
-  // Single-reduction CG only without preconditioner and when asked for.
-  const bool cgcg = !pre && opts->variant == 1;
-  StateSeq sq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true, 0};
-
-  // Initial state, then |b|^2 (P_BB) and the first residual.
-  for (int r = 0; r < nrhs; ++r) {
-    RhsState& st = h->st_host[r];
-    std::memset(&st, 0, sizeof(st));
-    st.tol = opts->tol;
-    st.maxiter = opts->maxiter;
-    st.fresh = 1;
+  PcgStatsDev* st = reinterpret_cast<PcgStatsDev*>(stats_dev);
+  if (opts->variant == 2) {
+    FPH_CHECK(coop_enqueue(h, b_dev, u_dev, opts, st, s));
+    return FPH_OK;
   }
-  FPH_CHECK(push_state(h, nrhs, sq, s));
-  hipLaunchKernelGGL(k_norm2<double>, dim3(nb, nrhs), dim3(256), 0, s, d, b_dev, sq.next(nb),
-                     (int)P_BB);
-  FPH_CHECK(hipGetLastError());
-  if (opts->zero_guess) FPH_CHECK(hipMemsetAsync(u_dev, 0, nrhs * d * sizeof(double), s));
-  const Work<double> w64 = work64(h, u_dev);
-  const Work<float> w32 = work32(h);
-  if (!mixed) {
-    if (opts->zero_guess) {
-      FPH_CHECK(hipMemcpyAsync(w64.r, b_dev, nrhs * d * sizeof(double), hipMemcpyDeviceToDevice, s));
-      if (pre)
-        FPH_CHECK(pc_apply<double>(&h->pc, h->g, w64.dbar, FPH_PC_FFT, nrhs, w64.r, w64.z, w64.r, sq, s));
-      else if (cgcg)
-        FPH_CHECK(cgcg_start<double>(h, nrhs, w64, sq, s));
-    } else {
-      FPH_CHECK(fp64_residual<double>(h, nrhs, pre, cgcg, 0, b_dev, u_dev, w64, sq, s));
-    }
+  SolveRun run(h, nrhs, b_dev, u_dev, opts);
+  FPH_CHECK(run.start(s));
+  FPH_CHECK(run.slots(run.total, s));
+  FPH_CHECK(run.finish(st, s));
+  return FPH_OK;
+}
+
+extern "C" int pcg_solve_sync(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
+                              const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host,
+                              void* stream) {
+  const int rc = check_solve(h, nrhs, b_dev, u_dev, opts);
+  if (rc != FPH_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (opts->variant == 2) {
+    FPH_CHECK(coop_enqueue(h, b_dev, u_dev, opts, h->stats_dev, s));
   } else {
-    FPH_CHECK(hipMemsetAsync(h->u32, 0, nrhs * d * sizeof(float), s));
-    if (opts->zero_guess) {
-      hipLaunchKernelGGL((k_cast<double, float>), dim3(nb), dim3(256), 0, s, nrhs * d, b_dev, w32.r);
+    // The same launches as pcg_solve, in chunks of slots; after each chunk
+    // a probe kernel writes how many right-hand sides are still open to
+    // pinned host memory.  The host waits for the probe of the previous
+    // chunk only (so the GPU always has a chunk queued) and stops
+    // enqueueing once it reads zero; slots already queued return at once.
+    SolveRun run(h, nrhs, b_dev, u_dev, opts);
+    FPH_CHECK(run.start(s));
+    int* open_dev = nullptr;
+    FPH_CHECK(hipHostGetDevicePointer((void**)&open_dev, h->open_pin, 0));
+    const long chunk = opts->chunk > 0 ? opts->chunk : kDefaultSlotChunk;
+    long enq = 0;
+    for (int k = 0; enq < run.total; ++k) {
+      const long n = std::min(chunk, run.total - enq);
+      FPH_CHECK(run.slots(n, s));
+      enq += n;
+      hipLaunchKernelGGL(k_solve_open, dim3(1), dim3(64), 0, s, nrhs,
+                         (const RhsState*)run.sq.latest(), open_dev + (k & 1));
       FPH_CHECK(hipGetLastError());
-      if (cgcg) {
-        FPH_CHECK(cgcg_start<float>(h, nrhs, w32, sq, s));
-      } else {
-        hipLaunchKernelGGL(k_norm2<float>, dim3(nb, nrhs), dim3(256), 0, s, d, (const float*)w32.r,
-                           sq.next(elem_blocks(d)), (int)P_NRM);
-        FPH_CHECK(hipGetLastError());
-        if (pre)
-          FPH_CHECK(pc_apply<float>(&h->pc, h->g, w32.dbar, FPH_PC_FFT, nrhs, w32.r, w32.z, w32.r, sq, s));
+      FPH_CHECK(hipEventRecord(h->probe_ev[k & 1], s));
+      if (k >= 1) {
+        FPH_CHECK(hipEventSynchronize(h->probe_ev[(k - 1) & 1]));
+        if (reinterpret_cast<volatile int*>(h->open_pin)[(k - 1) & 1] == 0) break;
       }
-    } else {
-      FPH_CHECK(fp64_residual<float>(h, nrhs, pre, cgcg, 0, b_dev, u_dev, w32, sq, s));
     }
+    FPH_CHECK(run.finish(h->stats_dev, s));
   }
-  FPH_CHECK(sync_state(h, nrhs, sq, s));
-
-  std::vector<int> final_(nrhs, 0);
-  std::vector<int> outer(nrhs, 0);
-  std::vector<int> iter_at_ru(nrhs, 0);
-  std::vector<double> rr_iter(nrhs, 0.0);
-  std::vector<int> own_check(nrhs, 0);  // the rhs itself asked for this residual evaluation
-  // FP32 residual-replacement interval per right-hand side: replace when
-  // the FP32 residual has fallen by delta since the last replacement.
-  // FP32 CG loses accuracy relative to its starting residual at a rate set
-  // by kappa * eps_32; when a replacement finds the true residual more than
-  // twice the iterated one, the interval is shortened (delta -> sqrt delta,
-  // at most 0.5).
-  std::vector<double> delta(nrhs, delta0);
-  for (int r = 0; r < nrhs; ++r) {
-    RhsState& st = h->st_host[r];
-    if (st.bb == 0.0) {  // b = 0: u = 0 exactly
-      final_[r] = 1;
-      st.status |= 1;
-      st.done = 1;
-      FPH_CHECK(hipMemsetAsync(u_dev + (long)r * d, 0, d * sizeof(double), s));
-    } else if (st.status & (4 | 8)) {  // non-finite input or breakdown
-      final_[r] = 1;
-      st.done = 1;
-    }
-    if (mixed && !st.done) st.ru_thresh = delta[r] * delta[r] * st.rr;
-  }
-  FPH_CHECK(push_state(h, nrhs, sq, s));
-
-  // Iterations enqueued between host checks.  FP32 with residual
-  // replacement: about 1.5 times the length of the last replacement cycle,
-  // so that few launches are wasted on paused right-hand sides.
-  int chunk = opts->chunk > 0 ? opts->chunk : (mixed ? 8 : 32);
-  long guard = 0;
-  while (true) {
-    bool all_final = true;
-    for (int r = 0; r < nrhs; ++r) all_final = all_final && final_[r];
-    if (all_final) break;
-    if (++guard > 100000000L) break;
-
-    for (int it = 0; it < chunk; ++it) {
-      hipError_t e;
-      if (cgcg && !mixed)
-        e = cgcg_iteration<double>(h, nrhs, w64, sq, s);
-      else if (cgcg)
-        e = cgcg_iteration<float>(h, nrhs, w32, sq, s);
-      else if (!mixed)
-        e = cg_iteration<double>(h, nrhs, pre, u_dev, w64.r, w64.z, w64.pa, w64.pb, w64.Ap,
-                                 w64.dbar, sq, s);
-      else
-        e = cg_iteration<float>(h, nrhs, pre, w32.u, w32.r, w32.z, w32.pa, w32.pb, w32.Ap,
-                                w32.dbar, sq, s);
-      if (e != hipSuccess) return fail_hip(e);
-    }
-    FPH_CHECK(sync_state(h, nrhs, sq, s));
-
-    // Right-hand sides that stopped (converged iterate, pause, cap) get an
-    // FP64 residual evaluation.
-    bool need = false;
-    for (int r = 0; r < nrhs; ++r) {
-      if (final_[r]) continue;
-      const RhsState& st = h->st_host[r];
-      if (st.status & (4 | 8)) {  // breakdown / non-finite: stop
-        final_[r] = 1;
-        continue;
-      }
-      if (st.done) need = true;
-    }
-    if (!need) continue;
-
-    // FP64 residual of the current iterate for every non-final rhs (the
-    // others are cheap to include and keep their direction).
-    // Single-reduction CG keeps its residual in the buffer of the current
-    // iteration parity; right-hand sides with another parity would need a
-    // launch of their own, so each parity class is replaced separately.
-    for (int r = 0; r < nrhs; ++r) {
-      rr_iter[r] = h->st_host[r].rr;
-      own_check[r] = h->st_host[r].done;
-    }
-    for (int par = 0; par < (cgcg ? 2 : 1); ++par) {
-      bool any = false;
-      for (int r = 0; r < nrhs; ++r) {
-        const bool mine = !final_[r] && (!cgcg || (h->st_host[r].iter & 1) == par);
-        h->st_host[r].done = mine ? 0 : 1;
-        any = any || mine;
-      }
-      if (!any) continue;
-      FPH_CHECK(push_state(h, nrhs, sq, s));
-      if (mixed) {
-        hipLaunchKernelGGL(k_flush, dim3(nb, nrhs), dim3(256), 0, s, d, h->u32, u_dev,
-                           (const RhsState*)sq.latest());
-        FPH_CHECK(hipGetLastError());
-        FPH_CHECK(fp64_residual<float>(h, nrhs, pre, cgcg, par, b_dev, u_dev, w32, sq, s));
-      } else {
-        FPH_CHECK(fp64_residual<double>(h, nrhs, pre, cgcg, par, b_dev, u_dev, w64, sq, s));
-      }
-      FPH_CHECK(sync_state(h, nrhs, sq, s));
-    }
-    for (int r = 0; r < nrhs; ++r) h->st_host[r].done = final_[r];
-    int cycle = 0;
-    for (int r = 0; r < nrhs; ++r) {
-      if (final_[r]) continue;
-      RhsState& st = h->st_host[r];
-      outer[r] += 1;
-      cycle = std::max(cycle, st.iter - iter_at_ru[r]);
-      iter_at_ru[r] = st.iter;
-      if (st.rr_true <= st.tol2) {
-        st.status |= 1;
-        final_[r] = 1;
-        st.done = 1;
-      } else if (st.status & (4 | 8)) {
-        final_[r] = 1;
-        st.done = 1;
-      } else if (st.iter >= st.maxiter) {
-        st.status |= 2;
-        final_[r] = 1;
-        st.done = 1;
-      } else {
-        st.done = 0;
-        // FP64: restart the directions from the true residual when this
-        // rhs's own recursive residual said converged and the true one did
-        // not.  A rhs included only because another one stopped keeps its
-        // directions (restarting would throw its Krylov space away), as
-        // FP32 always does (reliable update), unless the replaced residual
-        // is far from the iterated one.
-        if ((!mixed && own_check[r]) || st.rr > 100.0 * rr_iter[r]) st.fresh = 1;
-        if (mixed && st.rr > 4.0 * rr_iter[r]) delta[r] = std::min(0.5, std::sqrt(delta[r]));
-        st.ru_thresh = mixed ? delta[r] * delta[r] * st.rr : 0.0;
-      }
-    }
-    FPH_CHECK(push_state(h, nrhs, sq, s));
-    if (mixed && opts->chunk <= 0) chunk = std::max(2, std::min(64, cycle + cycle / 2 + 1));
-  }
-
-  // Final statistics: relative residual and action b.u in FP64.
-  FPH_CHECK(fermion_action(h, nrhs, b_dev, u_dev, h->tmp64, stream) == FPH_OK ? hipSuccess
-                                                                                : hipErrorUnknown);
-  FPH_CHECK(hipMemcpyAsync(h->tmp_host, h->tmp64, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  FPH_CHECK(hipMemcpyAsync(h->stats_pin, h->stats_dev, nrhs * sizeof(PcgStatsDev),
+                           hipMemcpyDeviceToHost, s));
   FPH_CHECK(hipStreamSynchronize(s));
-  if (stats) {
-    for (int r = 0; r < nrhs; ++r) {
-      const RhsState& st = h->st_host[r];
-      stats[r].status = st.status;
-      stats[r].iters = st.iter;
-      stats[r].outer_iters = outer[r];
-      stats[r].matvecs = st.matvecs;
-      stats[r].rel_resid = st.bb > 0.0 ? std::sqrt(st.rr_true / st.bb) : 0.0;
-      stats[r].action = h->tmp_host[r];
-    }
-  }
+  if (stats_host) std::memcpy(stats_host, h->stats_pin, nrhs * sizeof(PcgStatsDev));
   return FPH_OK;
 }
 
@@ -907,7 +813,6 @@ struct fph_batch_s {
   float* work;
   BatchItem* items;
   BatchStat* stats;
-  BatchStat* stats_host;      // pinned
   unsigned* queue;
   int nt, ms, per_cu;         // launch shape
   int num_cu;
@@ -961,6 +866,15 @@ hipError_t batch_enqueue(fph_batch_s* b, double tol, int maxiter, double delta, 
   if (b->nt == 128 && b->ms == 2) return batch_launch<128, 2>(b, tol, maxiter, delta, s);
   if (b->nt == 512 && b->ms == 1) return batch_launch<512, 1>(b, tol, maxiter, delta, s);
   return hipErrorInvalidValue;
+}
+
+// Batch statistics in the layout of fph_pcg_stats_t.
+__global__ void k_copy_batch_stats(int n, const BatchStat* __restrict__ in,
+                                   PcgStatsDev* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const BatchStat s = in[k];
+  out[k] = PcgStatsDev{s.status, s.iters, s.outer, s.matvecs, s.rel_resid, s.action};
 }
 
 hipError_t batch_graph(fph_batch_s* b, double tol, int maxiter, double delta) {
@@ -1019,7 +933,6 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
   b->work = nullptr;
   b->items = nullptr;
   b->stats = nullptr;
-  b->stats_host = nullptr;
   b->queue = nullptr;
   b->have_graph = false;
   b->nt = 256;
@@ -1036,7 +949,6 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
   if (e == hipSuccess) e = hipMalloc((void**)&b->items, nitems * sizeof(BatchItem));
   if (e == hipSuccess) e = hipMalloc((void**)&b->stats, nitems * sizeof(BatchStat));
   if (e == hipSuccess) e = hipMalloc((void**)&b->queue, sizeof(unsigned));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&b->stats_host, nitems * sizeof(BatchStat), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     fph_batch_destroy(b);
@@ -1095,13 +1007,12 @@ int fph_batch_destroy(fph_batch_t b) {
   void* ptrs[] = {b->E64, b->E32, b->work, b->items, b->stats, b->queue};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  if (b->stats_host) (void)hipHostFree(b->stats_host);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
   return FPH_OK;
 }
 
-int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats,
+int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_dev,
                     void* stream) {
   if (b == nullptr || opts == nullptr) return FPH_E_NULL;
   if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
@@ -1112,19 +1023,11 @@ int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* 
       b->g_delta != delta)
     FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
   FPH_CHECK(hipGraphLaunch(b->exec, s));
-  FPH_CHECK(hipMemcpyAsync(b->stats_host, b->stats, b->nitems * sizeof(BatchStat),
-                           hipMemcpyDeviceToHost, s));
-  FPH_CHECK(hipStreamSynchronize(s));
-  if (stats) {
-    for (int k = 0; k < b->nitems; ++k) {
-      const BatchStat& st = b->stats_host[k];
-      stats[k].status = st.status;
-      stats[k].iters = st.iters;
-      stats[k].outer_iters = st.outer;
-      stats[k].matvecs = st.matvecs;
-      stats[k].rel_resid = st.rel_resid;
-      stats[k].action = st.action;
-    }
+  if (stats_dev) {
+    hipLaunchKernelGGL(k_copy_batch_stats, dim3((b->nitems + 255) / 256), dim3(256), 0, s,
+                       b->nitems, (const BatchStat*)b->stats,
+                       reinterpret_cast<PcgStatsDev*>(stats_dev));
+    FPH_CHECK(hipGetLastError());
   }
   return FPH_OK;
 }

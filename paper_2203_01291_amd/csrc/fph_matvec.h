@@ -105,23 +105,6 @@ struct InPlain {
     b = w.b;                                                                  \
   }
 
-// v = one of two buffers chosen by the parity of the iteration count
-// (single-reduction CG keeps its residual double-buffered).
-template <typename T>
-struct InParity {
-  const T* buf0;
-  const T* buf1;
-  const T* __restrict__ v;
-  static FPH_DEVINL void prepare(RhsState&) {}
-  FPH_DEVINL void begin(const RhsState& s) { v = pick((s.iter & 1) != 0, buf0, buf1); }
-  static FPH_DEVINL void on_state(RhsState&) {}
-  FPH_DEVINL T load(long off) const { return v[off]; }
-  FPH_DEVINL T load_owned(long off) const { return v[off]; }
-  FPH_DEVINL void load2(long off, T& a, T& b) const { ld2(v + off, a, b); }
-  FPH_DEVINL void load2_owned(long off, T& a, T& b) const { ld2(v + off, a, b); }
-  FPH_FETCH_AFTER_STATE(T)
-};
-
 // p = z + beta p_old computed on the fly (the CG direction update fused
 // into the operator), beta = rz_next / rz (Eq. CG_precon in the standard
 // PCG form); the chunk owner stores p for its own slices.  The two
@@ -206,112 +189,6 @@ struct InPUpdate {
   }
 };
 
-// Single-reduction CG (Chronopoulos and Gear, 1989): with gamma_i = r_i.r_i,
-// delta_i = r_i.A r_i and w_i = A r_i,
-//   beta_i = gamma_i / gamma_{i-1},
-//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
-//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}  (= A p_i),
-//   x += alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,  w_{i+1} = A r_{i+1}.
-// The operator kernel forms r_{i+1} on the fly (also on halo slices), the
-// chunk owner stores p_i, s_i, x and r_{i+1}; the operator output is
-// w_{i+1} and the epilogue forms both dots of the next step, so one launch
-// is one iteration.  r, w, s, p alternate between two buffers by the
-// parity of i.
-template <typename T>
-struct InCGCG {
-  T* R0;
-  T* R1;
-  T* S0;
-  T* S1;
-  T* P0;
-  T* P1;
-  const T* W0;
-  const T* W1;
-  T* x;
-  const T* __restrict__ ri;
-  const T* __restrict__ wi;
-  const T* __restrict__ so;
-  const T* __restrict__ po;
-  T* __restrict__ rn;
-  T* __restrict__ sn;
-  T* __restrict__ pn;
-  T alpha, beta;
-  int fresh;
-  static FPH_DEVINL void prepare(RhsState& s) {
-    if (s.fresh) {
-      s.beta = 0.0;
-      if (!(s.delta > 0.0)) {
-        s.status |= 4;
-        s.done = 1;
-        return;
-      }
-      s.alpha = s.gamma / s.delta;
-    } else {
-      s.beta = s.gamma / s.gamma_prev;
-      const double den = s.delta - s.beta * s.gamma / s.alpha_prev;
-      if (!(den > 0.0)) {
-        s.status |= 4;
-        s.done = 1;
-        return;
-      }
-      s.alpha = s.gamma / den;
-    }
-  }
-  FPH_DEVINL void begin(const RhsState& s) {
-    const bool c = (s.iter & 1) != 0;
-    ri = pick(c, R0, R1);
-    wi = pick(c, W0, W1);
-    rn = pick(c, R1, R0);
-    so = pick(c, S1, S0);
-    sn = pick(c, S0, S1);
-    po = pick(c, P1, P0);
-    pn = pick(c, P0, P1);
-    alpha = (T)s.alpha;
-    beta = (T)s.beta;
-    fresh = s.fresh;
-  }
-  static FPH_DEVINL void on_state(RhsState& s) {
-    s.gamma_prev = s.gamma;
-    s.alpha_prev = s.alpha;
-    s.fresh = 0;
-    s.iter += 1;
-    s.matvecs += 1;
-  }
-  FPH_DEVINL T load(long off) const {
-    const T sv = fresh ? wi[off] : wi[off] + beta * so[off];
-    return ri[off] - alpha * sv;
-  }
-  FPH_DEVINL T load_owned(long off) const {
-    const T r = ri[off], w = wi[off];
-    const T sv = fresh ? w : w + beta * so[off];
-    const T pv = fresh ? r : r + beta * po[off];
-    const T rv = r - alpha * sv;
-    sn[off] = sv;
-    pn[off] = pv;
-    x[off] += alpha * pv;
-    rn[off] = rv;
-    return rv;
-  }
-  FPH_DEVINL void load2(long off, T& a, T& b) const {
-    T r0, r1, w0, w1;
-    ld2(ri + off, r0, r1);
-    ld2(wi + off, w0, w1);
-    if (!fresh) {
-      T s0, s1;
-      ld2(so + off, s0, s1);
-      w0 += beta * s0;
-      w1 += beta * s1;
-    }
-    a = r0 - alpha * w0;
-    b = r1 - alpha * w1;
-  }
-  FPH_DEVINL void load2_owned(long off, T& a, T& b) const {
-    a = load_owned(off);
-    b = load_owned(off + 1);
-  }
-  FPH_FETCH_AFTER_STATE(T)
-};
-
 // ---------------------------------------------------- epilogue functors --
 
 // Plain store of out.
@@ -356,48 +233,64 @@ struct EpiDot {
   static constexpr int kKind = P_PAP;
 };
 
-// Store w = A r into the buffer of parity (iter + shift) and accumulate
-// r.r and r.w (consumed as P_GD by single-reduction CG).
-template <typename T>
-struct EpiGD {
-  T* W0;
-  T* W1;
-  int shift;
-  T* __restrict__ out;
-  FPH_DEVINL void begin(const RhsState& s) { out = pick(((s.iter + shift) & 1) != 0, W0, W1); }
-  FPH_DEVINL void put(long off, T o, T v, double& acc, double& acc2) const {
-    out[off] = o;
-    acc += (double)v * (double)v;
-    acc2 += (double)v * (double)o;
-  }
-  FPH_DEVINL void put2(long off, T o0, T o1, T v0, T v1, double& acc, double& acc2) const {
-    st2(out + off, o0, o1);
-    acc += (double)v0 * (double)v0 + (double)v1 * (double)v1;
-    acc2 += (double)v0 * (double)o0 + (double)v1 * (double)o1;
-  }
-  static constexpr int kKind = P_GD;
-};
-
 // True residual r = b - A u in FP64, stored as TR (float or double);
-// accumulates |b - A u|^2 in FP64 (consumed as P_TRUE).
+// accumulates |b - A u|^2 and |b|^2 in FP64 (consumed as P_RES).
 template <typename TR>
 struct EpiResidual {
   const double* __restrict__ b;
   TR* __restrict__ r;
   FPH_DEVINL void begin(const RhsState&) {}
-  FPH_DEVINL void put(long off, double o, double /*v*/, double& acc, double& /*acc2*/) const {
-    const double res = b[off] - o;
-    r[off] = (TR)res;
-    acc += res * res;
-  }
-  FPH_DEVINL void put2(long off, double o0, double o1, double, double, double& acc, double&) const {
+  FPH_DEVINL void put2(long off, double o0, double o1, double, double, double& acc,
+                       double& acc2) const {
     double b0, b1;
     ld2(b + off, b0, b1);
     const double r0 = b0 - o0, r1 = b1 - o1;
     st2(r + off, (TR)r0, (TR)r1);
     acc += r0 * r0 + r1 * r1;
+    acc2 += b0 * b0 + b1 * b1;
   }
-  static constexpr int kKind = P_TRUE;
+  static constexpr int kKind = P_RES;
+};
+
+// The FP64 iterate of an FP32-refined solve with its FP32 correction added
+// on the fly: u = u64[upar] + u32 (u32 omitted while it is zero), read on
+// every slice the sweep visits (halo slices too); the chunk owner stores u
+// into the other FP64 buffer, so the correction is folded into the iterate
+// by the residual evaluation itself, with no race between neighbouring
+// chunks (nobody writes the buffer being read).
+struct InResid {
+  const double* u0;   // u_dev
+  double* u1;         // workspace buffer
+  const float* u32;
+  const double* src;
+  double* dst;
+  int z;              // the correction is zero
+  FPH_DEVINL void begin(const RhsState& s) {
+    src = pick(s.upar != 0, u0, (const double*)u1);
+    dst = pick(s.upar != 0, u1, const_cast<double*>(u0));
+    z = s.u32z;
+  }
+  static constexpr bool kPrefetch = false;
+  struct Raw {
+    double a, b;
+  };
+  FPH_DEVINL void fetch2(long off, Raw& w, bool) const {
+    double a, b;
+    ld2(src + off, a, b);
+    if (!z) {
+      float c, d;
+      ld2(u32 + off, c, d);
+      a += (double)c;
+      b += (double)d;
+    }
+    w.a = a;
+    w.b = b;
+  }
+  FPH_DEVINL void use2(long off, const Raw& w, double& a, double& b, bool owned, bool) const {
+    a = w.a;
+    b = w.b;
+    if (owned) st2(dst + off, a, b);
+  }
 };
 
 // ------------------------------------------------------ fused M^T M ------
@@ -631,49 +524,32 @@ FPH_DEVINL bool mtm_sweep(const Geom& g, const T* __restrict__ E, T th, int Tch,
 // chunks of `Tch` slices each; with Q <= NT plaquettes per slice, S = NT/Q
 // chunks run side by side (one plaquette per thread), otherwise S = 1 and a
 // thread serves up to MAXSLOT plaquettes.  LDS: 4 * S * N elements of T.
-// With io.in set (and an epilogue that produces partial sums), the kernel
-// takes part in the CG state machine: it folds pending partials, skips
-// finished right-hand sides and publishes its own partials (Epi::kKind).
-// Plain FP32 applies in 1024-thread workgroups are held to 8 waves per SIMD
+// A plain apply (no solver state; the CG iterations use k_slot_mtm).  Plain
+// FP32 applies in 1024-thread workgroups are held to 8 waves per SIMD
 // (64 VGPRs), so two workgroups share a CU.
-template <typename T, int NT, class Epi>
+template <typename T, int NT>
 constexpr int mtm_min_waves() {
-  return (NT == 1024 && sizeof(T) == 4 && Epi::kKind == P_NONE) ? 8 : 1;
+  return (NT == 1024 && sizeof(T) == 4) ? 8 : 1;
+}
+
+// Workgroups are handed to the 8 XCDs round robin; renumber them so each
+// XCD gets a contiguous range of (chunk-major, right-hand side minor) work:
+// neighbouring chunks (which share halo slices) and the chunks of all
+// right-hand sides at the same slices (which share E) meet in one L2.
+FPH_DEVINL void mtm_block(int nblk, int& r, int& bx) {
+  const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int nrhs = gridDim.x / nblk;
+  r = logical % nrhs;
+  bx = logical / nrhs;
 }
 
 template <typename T, int NT, int MAXSLOT, class In, class Epi>
-__global__ void __launch_bounds__(NT, (mtm_min_waves<T, NT, Epi>()))
-k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi, StIO io) {
+__global__ void __launch_bounds__(NT, (mtm_min_waves<T, NT>()))
+k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red_sh[NT / 64];
-  __shared__ RhsState s_sh;
-  // Workgroups are handed to the 8 XCDs round robin; renumber them so each
-  // XCD gets a contiguous range of (chunk-major, right-hand side minor)
-  // work: neighbouring chunks (which share halo slices) and the chunks of
-  // all right-hand sides at the same slices (which share E) meet in one L2.
-  const int logical = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int nrhs = gridDim.x / nblk;
-  const int r = logical % nrhs;
-  const int bx = logical / nrhs;
+  int r, bx;
+  mtm_block(nblk, r, bx);
   E += field_off(g, r);
-  auto hook = [&]() -> bool {
-    // Plain applies (no partial sums) never carry solver state.
-    if constexpr (Epi::kKind == P_NONE) return true;
-    if (io.in == nullptr) return true;
-    state_begin<NT>(io, r, &s_sh, red_sh);
-    if (threadIdx.x == 0 && !s_sh.done) In::prepare(s_sh);
-    __syncthreads();
-    if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, bx, nblk, bx == 0);
-      return false;
-    }
-    in.begin(s_sh);
-    epi.begin(s_sh);
-    __syncthreads();
-    if (threadIdx.x == 0) In::on_state(s_sh);
-    return true;
-  };
-
   const int tid = threadIdx.x;
   int S, sub, lane, nslot;
   block_layout<NT>(g, tid, S, sub, lane, nslot);
@@ -684,18 +560,8 @@ k_mtm(Geom g, const T* __restrict__ E, T th, int Tch, int nblk, In in, Epi epi, 
   T* lds4 = reinterpret_cast<T*>(smem_raw) + 4L * (sub < S ? sub : 0) * g.N;
   const long base = (long)r * g.d;
   double acc = 0.0, acc2 = 0.0;
-  if (!mtm_sweep<T, NT, MAXSLOT, 1>(g, E, th, Tch, tau0, Tc, active, lane, nslot, lds4,
-                                    base, in, epi, acc, acc2, hook))
-    return;
-
-  if constexpr (Epi::kKind != P_NONE) {
-    if (io.in != nullptr) {
-      double bs2 = 0.0;
-      const double bs = block_sum<NT>(acc, red_sh);
-      if constexpr (Epi::kKind == P_GD) bs2 = block_sum<NT>(acc2, red_sh);
-      state_end(io, r, &s_sh, Epi::kKind, bs, bx, nblk, bx == 0, bs2);
-    }
-  }
+  mtm_sweep<T, NT, MAXSLOT, 1>(g, E, th, Tch, tau0, Tc, active, lane, nslot, lds4, base, in, epi,
+                               acc, acc2, [] { return true; });
 }
 
 // ------------------------------------------------------------- M alone --

@@ -448,7 +448,7 @@ int green_vectors(fph_meas_t m, int32_t nvec, const double* xi_dev, double* gxi_
   for (int r0 = 0; r0 < nvec; r0 += m->max_rhs) {
     const int nr = (nvec - r0 < m->max_rhs) ? nvec - r0 : m->max_rhs;
     MEAS_CALL(fermion_matvec(m->h, FPH_OP_MT, FPH_F64, nr, xi_dev + (long)r0 * m->d, m->bvec, stream));
-    MEAS_CALL(pcg_solve(m->h, nr, m->bvec, gxi_dev + (long)r0 * m->d, &oo,
+    MEAS_CALL(pcg_solve_sync(m->h, nr, m->bvec, gxi_dev + (long)r0 * m->d, &oo,
                         stats_host ? stats_host + r0 : nullptr, stream));
   }
   return FPH_OK;

@@ -223,8 +223,11 @@ FPH_DEVINL void cmacc(T2& acc, T2 w, T2 y) {  // acc += conj(w) y
 // (in_tau - i in_{tau+H}) into LDS.  With CGUPD both inputs first receive
 // the CG update u += alpha p, r -= alpha Ap (r is `in`, updated in place),
 // publishing |r|^2 as P_RR partials; the direction is pb on even iteration
-// counts, pa on odd.  The loads of the first pass (two items per thread)
-// other than the direction are issued before the solver state is read.
+// counts, pa on odd.  A right-hand side whose FP64 residual was just
+// evaluated (the folded partials were P_RES) is transformed without the
+// update; an FP32 correction u the state marks as zero is read as zero.
+// The loads of the first pass (two items per thread) other than the
+// direction are issued before the solver state is read.
 // Step 1, item (site, n2, k1): output k1 of the H1-point DFT over
 // n1 of y_{H2 n1 + n2}, times W_H^{n2 k1}.  Step 2, item (site, k1, k2):
 // the H2-point DFT over n2 -> Z_{k1 + H1 k2}.
@@ -296,6 +299,8 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   }
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
   double acc_rr = 0.0;
+  const bool upd = CGUPD && s_sh.folded == P_PAP;
+  const bool uz = CGUPD && s_sh.u32z != 0;
 
   // Stage 0.
   {
@@ -313,15 +318,15 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
         if (e >= npair) continue;
         const int tau = e >> lks, sidx = e & (KS - 1);
         T a = ra[j], b = rb[j];
-        if (CGUPD && i0 + sidx < g.N) {
+        if (upd && i0 + sidx < g.N) {
           const long oa = base + (long)tau * g.N + i0 + sidx;
           const T pva = pv0[j], pvb = pv1[j];
           a -= alpha * aa[j];
           b -= alpha * ab[j];
           in[oa] = a;
           in[oa + hN] = b;
-          u[oa] = ua[j] + alpha * pva;
-          u[oa + hN] = ub[j] + alpha * pvb;
+          u[oa] = (uz ? (T)0 : ua[j]) + alpha * pva;
+          u[oa + hN] = (uz ? (T)0 : ub[j]) + alpha * pvb;
           acc_rr += (double)a * (double)a + (double)b * (double)b;
         }
         const T2 t = tw[tau];
@@ -359,8 +364,11 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 
   if (io.in != nullptr) {
     double bs = 0.0;
-    if (CGUPD) bs = block_sum<NT>(acc_rr, red_sh);
-    state_end(io, r, &s_sh, CGUPD ? P_RR : P_NONE, bs, tile, ntiles, tile == 0);
+    if (upd) {
+      bs = block_sum<NT>(acc_rr, red_sh);
+      if (threadIdx.x == 0) s_sh.u32z = 0;
+    }
+    state_end(io, r, &s_sh, upd ? P_RR : P_NONE, bs, tile, ntiles, tile == 0);
   }
 }
 

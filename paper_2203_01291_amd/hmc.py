@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import (FPH_LAMBDA, FPH_LAMBDA_INV, FPH_LAMBDA_INV_T, FPH_LAMBDA_T, FPH_MASS, FPH_MASS_INV,
                    FPH_MASS_SQRT, FPH_MOVE_REFLECT, FPH_MOVE_SWAP, HmcOpts, HmcStats, PcgOpts, UpdateStats,
                    check)
-from .solver import _PRECS, _ptr, _side_streams, _stream
+from .solver import _PRECS, _ptr, _stream
 
 _MASS_OPS = {"inv": FPH_MASS_INV, "sqrt": FPH_MASS_SQRT, "mass": FPH_MASS}
 _GUESS = {"zero": 0, "previous": 1, "extrapolate": 2}
@@ -145,36 +145,3 @@ class PhononHMC:
         check(self.lib.hmc_global_update(self.h, _MOVES[kind], int(i), int(j), _ptr(x), _ptr(R_fields),
                                          float(r_uniform), ctypes.byref(st), _stream()))
         return st.as_dict()
-
-
-def trajectories_concurrent(items):
-    """One HMC update for each of several independent chains side by side, each
-    on its own stream and host thread inside the library
-    (hmc_trajectory_concurrent).  items: list of (hmc, x, R_fields, R_mom, r)
-    or (hmc, x, R_fields, R_mom, r, p_out), with contexts on distinct solvers.
-    Returns the list of stats dicts.  Blocks until all are done."""
-    lib = _lib.load()
-    n = len(items)
-    hh, xs, rf, rm, ru, po = [], [], [], [], [], []
-    for it in items:
-        h, x, Rf, Rm, r = it[:5]
-        p_out = it[5] if len(it) > 5 else None
-        h._v(x)
-        h._v(Rf, h.nfields)
-        h._v(Rm)
-        hh.append(h.h.value)
-        xs.append(x.data_ptr())
-        rf.append(Rf.data_ptr())
-        rm.append(Rm.data_ptr())
-        ru.append(float(r))
-        po.append(p_out.data_ptr() if p_out is not None else None)
-    stats = (HmcStats * n)()
-    cur, streams = _side_streams(n)
-    arr = lambda T, v: (T * n)(*v)
-    check(lib.hmc_trajectory_concurrent(n, arr(ctypes.c_void_p, hh), arr(ctypes.c_void_p, xs),
-                                        arr(ctypes.c_void_p, rf), arr(ctypes.c_void_p, rm),
-                                        arr(ctypes.c_double, ru), arr(ctypes.c_void_p, po), stats,
-                                        arr(ctypes.c_void_p, [st.cuda_stream for st in streams])))
-    for st in streams:
-        cur.wait_stream(st)
-    return [v.as_dict() for v in stats]

@@ -11,7 +11,8 @@ import torch
 
 from . import _lib
 from ._lib import (FPH_F32, FPH_F32_REFINED, FPH_F64, FPH_OP_M, FPH_OP_MT, FPH_OP_MTM,
-                   FPH_PC_F, FPH_PC_FFT, FPH_PC_FT, Lattice, PcgOpts, PcgStats, System, check)
+                   FPH_PC_F, FPH_PC_FFT, FPH_PC_FT, Lattice, PcgOpts, PcgStats, System, check,
+                   stats_from_device)
 
 _OPS = {"M": FPH_OP_M, "MT": FPH_OP_MT, "MTM": FPH_OP_MTM}
 _PC_OPS = {"F": FPH_PC_F, "FT": FPH_PC_FT, "FFT": FPH_PC_FFT}
@@ -137,21 +138,49 @@ class FermionSolver:
         check(self.lib.fph_precond_info(self.h, b, npt, _stream()))
         return (b[0], b[1]), list(npt)
 
+    def _opts(self, zero, tol, maxiter, precond, prec, ru_delta, chunk, variant, max_outer):
+        return PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero),
+                       float(ru_delta), int(chunk), int(variant), int(max_outer), 0)
+
     def solve(self, b, u=None, tol=1e-10, maxiter=100000, precond=False, prec="f64",
-              ru_delta=0.0, chunk=0, variant=0):
+              ru_delta=0.0, chunk=0, variant=0, max_outer=0):
         """Solve (M^T M) u = b for every right-hand side of b (float64).
-        Returns (u, [stats dict per rhs]).  Blocks until done."""
+        Returns (u, [stats dict per rhs]).  Blocks until done (pcg_solve_sync:
+        the slots are enqueued in chunks until the device reports every
+        right-hand side finished)."""
         nrhs = self._vec(b)
         if nrhs > self.max_rhs:
             raise ValueError("more right-hand sides than max_rhs")
         zero = u is None
         u = torch.empty_like(b) if u is None else u
-        opts = PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero),
-                       float(ru_delta), int(chunk), int(variant))
+        opts = self._opts(zero, tol, maxiter, precond, prec, ru_delta, chunk, variant, max_outer)
         stats = (PcgStats * nrhs)()
-        check(self.lib.pcg_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats,
-                                 _stream()))
+        check(self.lib.pcg_solve_sync(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats,
+                                      _stream()))
         return u, [s.as_dict() for s in stats]
+
+    def solve_async(self, b, u=None, stats=None, tol=1e-10, maxiter=2000, precond=False,
+                    prec="f64", ru_delta=0.0, variant=0, max_outer=0, zero_guess=None):
+        """Enqueue the solve on the current stream and return at once
+        (pcg_solve): (u, stats) with stats a device tensor of nrhs
+        fph_pcg_stats_t entries (decode with _lib.stats_from_device once the
+        stream has reached it).  1 + maxiter + max_outer slots are enqueued,
+        so maxiter is the iteration budget.  u is the initial guess unless
+        zero_guess (default: u is None).  Allocates nothing when u and stats
+        are given (the call can then be captured in a graph)."""
+        nrhs = self._vec(b)
+        if nrhs > self.max_rhs:
+            raise ValueError("more right-hand sides than max_rhs")
+        zero = (u is None) if zero_guess is None else bool(zero_guess)
+        u = torch.empty_like(b) if u is None else u
+        if stats is None:
+            stats = torch.empty(nrhs * 4, dtype=torch.float64, device=b.device)
+        if not (stats.is_cuda and stats.is_contiguous() and stats.numel() * stats.element_size() >= 32 * nrhs):
+            raise ValueError("stats must be a contiguous CUDA tensor of at least 32 bytes per right-hand side")
+        opts = self._opts(zero, tol, maxiter, precond, prec, ru_delta, 0, variant, max_outer)
+        check(self.lib.pcg_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), _ptr(stats),
+                                 _stream()))
+        return u, stats
 
     def force(self, u, grad=None, scale=1.0, scale_dev=None):
         """grad += scale * s * sum_r dS_F/dx for solutions u (float64); s is the
@@ -165,56 +194,12 @@ class FermionSolver:
         check(self.lib.fermion_force(self.h, nrhs, _ptr(u), _ptr(grad), float(scale), sd, _stream()))
         return grad
 
-    def action(self, b, u):
+    def action(self, b, u, out=None):
         """S_F = b . u per right-hand side, FP64 on the device."""
         nrhs = self._vec(b)
-        out = torch.empty(nrhs, dtype=torch.float64, device=b.device)
+        out = torch.empty(nrhs, dtype=torch.float64, device=b.device) if out is None else out
         check(self.lib.fermion_action(self.h, nrhs, _ptr(b), _ptr(u), _ptr(out), _stream()))
         return out
-
-
-def _side_streams(n):
-    """n new streams (default priority), each ordered after the current stream's work."""
-    cur = torch.cuda.current_stream()
-    streams = [torch.cuda.Stream() for _ in range(n)]
-    for st in streams:
-        st.wait_stream(cur)
-    return cur, streams
-
-
-def solve_concurrent(items, tol=1e-10, maxiter=100000, precond=False, prec="f64", ru_delta=0.0):
-    """Solve several independent systems side by side, each on its own stream
-    and host thread inside the library (pcg_solve_concurrent).  items: list of
-    (solver, b) or (solver, b, u) with distinct solvers (u is the initial guess
-    and receives the solution; None starts from zero).  Returns a list of
-    (u, [stats per rhs]).  Blocks until all are done."""
-    lib = _lib.load()
-    n = len(items)
-    hs, nr, bs, us, opts, sts, keep = [], [], [], [], [], [], []
-    for it in items:
-        s, b = it[0], it[1]
-        u = it[2] if len(it) > 2 else None
-        k = s._vec(b)
-        zero = u is None
-        u = torch.empty_like(b) if u is None else u
-        st = (PcgStats * k)()
-        hs.append(s.h.value)
-        nr.append(k)
-        bs.append(b.data_ptr())
-        us.append(u.data_ptr())
-        opts.append(PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero),
-                            float(ru_delta), 0, 0))
-        sts.append(st)
-        keep.append((u, st))
-    cur, streams = _side_streams(n)
-    arr = lambda T, v: (T * n)(*v)
-    stat_ptrs = arr(ctypes.c_void_p, [ctypes.cast(st, ctypes.c_void_p).value for st in sts])
-    check(lib.pcg_solve_concurrent(n, arr(ctypes.c_void_p, hs), arr(ctypes.c_int32, nr),
-                                   arr(ctypes.c_void_p, bs), arr(ctypes.c_void_p, us), arr(PcgOpts, opts),
-                                   stat_ptrs, arr(ctypes.c_void_p, [st.cuda_stream for st in streams])))
-    for st in streams:
-        cur.wait_stream(st)
-    return [(u, [v.as_dict() for v in st]) for u, st in keep]
 
 
 class FermionBatch:
@@ -251,13 +236,20 @@ class FermionBatch:
         self.h = h
 
     def _opts(self, tol, maxiter, ru_delta):
-        return PcgOpts(float(tol), int(maxiter), 0, FPH_F32_REFINED, 1, float(ru_delta), 0, 0)
+        return PcgOpts(float(tol), int(maxiter), 0, FPH_F32_REFINED, 1, float(ru_delta), 0, 0, 0, 0)
+
+    def solve_async(self, tol=1e-8, maxiter=100000, ru_delta=0.0, stats=None):
+        """Enqueue the batched solve (fph_batch_solve) and return the device
+        statistics tensor (nrhs_total entries; see _lib.stats_from_device)."""
+        if stats is None:
+            stats = torch.empty(self.nrhs_total * 4, dtype=torch.float64, device=self.u[0].device)
+        opts = self._opts(tol, maxiter, ru_delta)
+        check(self.lib.fph_batch_solve(self.h, ctypes.byref(opts), _ptr(stats), _stream()))
+        return stats
 
     def solve(self, tol=1e-8, maxiter=100000, ru_delta=0.0):
-        stats = (PcgStats * self.nrhs_total)()
-        opts = self._opts(tol, maxiter, ru_delta)
-        check(self.lib.fph_batch_solve(self.h, ctypes.byref(opts), stats, _stream()))
-        return [s.as_dict() for s in stats]
+        """The batched solve, waiting for it: one stats dict per right-hand side."""
+        return stats_from_device(self.solve_async(tol, maxiter, ru_delta))
 
     def tune(self, tol=1e-8, maxiter=100000, ru_delta=0.0):
         best = (ctypes.c_int32 * 3)()

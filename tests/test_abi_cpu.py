@@ -52,6 +52,7 @@ def test_argument_errors_are_reported_on_the_host():
     assert lib.fph_create(None, ctypes.byref(good), 1) == -1
     assert lib.fermion_matvec(None, 0, 0, 1, None, None, None) == -1
     assert lib.pcg_solve(None, 1, None, None, None, None, None) == -1
+    assert lib.pcg_solve_sync(None, 1, None, None, None, None, None) == -1
     assert lib.fermion_force(None, 1, None, None, 1.0, None, None) == -1
     assert b"NULL" in lib.fph_strerror(-1)
 
@@ -121,18 +122,6 @@ def test_hmc_and_measurement_argument_errors_on_host():
     assert lib.green_average(None, 1, None, None, None, None) == -1
     assert lib.green_pair_products(None, 2, None, None, None, None) == -1
     assert lib.fph_get_lattice(None, None, None) == -1
-
-
-def test_concurrent_entry_points_check_arguments_on_host():
-    from paper_2203_01291_amd import _lib
-    if not os.path.exists(_lib.LIB_PATH):
-        pytest.skip("library not built")
-    lib = _lib.load()
-    assert lib.pcg_solve_concurrent(0, None, None, None, None, None, None, None) == -7
-    assert lib.pcg_solve_concurrent(65, None, None, None, None, None, None, None) == -7
-    assert lib.pcg_solve_concurrent(2, None, None, None, None, None, None, None) == -1
-    assert lib.hmc_trajectory_concurrent(0, None, None, None, None, None, None, None, None) == -7
-    assert lib.hmc_trajectory_concurrent(2, None, None, None, None, None, None, None, None) == -1
 
 
 def test_ssh_argument_errors_on_host():

@@ -305,37 +305,3 @@ def test_hmc_preconditioned_matches_plain():
     for k in ("H_i", "H_f", "SF_f"):
         assert s1[k] == pytest.approx(s0[k], abs=1e-7), k
     assert s1["accepted"] == s0["accepted"]
-
-
-def test_concurrent_hmc_refuses_shared_preconditioner():
-    """Two SSH HMC contexts whose SSH contexts share one Holstein preconditioner handle cannot
-    run side by side; with separate handles they can, and match the calls made in turn."""
-    from paper_2203_01291_amd._lib import FphError
-    from paper_2203_01291_amd.hmc import PhononHMC, trajectories_concurrent
-    from paper_2203_01291_amd.solver import FermionSolver
-    from paper_2203_01291_amd.ssh import SSHSolver
-    p = get_config("c1")
-    x = phonon_field(p)
-    rng = np.random.default_rng(61)
-    R = rng.standard_normal((2, p.Ltau, p.N))
-    Rm = rng.standard_normal((p.Ltau, p.N))
-    shared = FermionSolver.from_params(p, max_rhs=2)
-    hs, keep = [], []
-    for k in range(2):
-        s = SSHSolver.from_params(p, 0.3, max_rhs=2)
-        s.attach_preconditioner(shared, a1=0.15, a2=12.0)
-        keep.append(s)
-        hs.append(PhononHMC(s, 1.0, 1.0, 0.02, Nt=5, nt=5, prec="f64", force_tol=1e-10, action_tol=1e-12))
-    with pytest.raises(FphError):
-        trajectories_concurrent([(h, tgpu(x), tgpu(R), tgpu(Rm), 0.5) for h in hs])
-    own = [FermionSolver.from_params(p, max_rhs=2) for _ in range(2)]
-    for s, f in zip(keep, own):
-        s.attach_preconditioner(f, a1=0.15, a2=12.0)
-    seq = []
-    for h in hs:
-        xg = tgpu(x)
-        seq.append((h.trajectory(xg, tgpu(R), tgpu(Rm), 0.5), xg.cpu().numpy()))
-    xs = [tgpu(x) for _ in hs]
-    out = trajectories_concurrent([(h, xg, tgpu(R), tgpu(Rm), 0.5) for h, xg in zip(hs, xs)])
-    for st, xg, (st0, x0) in zip(out, xs, seq):
-        assert st == st0 and np.array_equal(xg.cpu().numpy(), x0)
