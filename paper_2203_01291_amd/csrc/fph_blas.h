@@ -140,10 +140,11 @@ k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__
 
 // ------------------------------------------------------------ plain BLAS
 
-// part[r][block] = partial sums of a_r . b_r (FP64).  Launch: grid (nblk, nrhs).
+// part[r * stride + block] = partial sums of a_r . b_r (FP64).  Launch:
+// grid (nblk, nrhs), nblk <= stride.
 __global__ void __launch_bounds__(256)
 k_dot_partials(long d, const double* __restrict__ a, const double* __restrict__ b,
-               double* __restrict__ part) {
+               double* __restrict__ part, long stride) {
   __shared__ double red_sh[4];
   const int r = blockIdx.y;
   const double* ar = a + (long)r * d;
@@ -155,15 +156,16 @@ k_dot_partials(long d, const double* __restrict__ a, const double* __restrict__ 
     acc += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
   }
   const double bs = block_sum<256>(acc, red_sh);
-  if (threadIdx.x == 0) part[(long)r * kPStride + blockIdx.x] = bs;
+  if (threadIdx.x == 0) part[(long)r * stride + blockIdx.x] = bs;
 }
 
-// out[r] = sum of the nb partials of rhs r, in block order.  One block per rhs.
+// out[r] = sum of the nb partials of rhs r (at part + r * stride), in block
+// order.  One block per rhs.
 __global__ void __launch_bounds__(256)
-k_sum_partials(int nb, const double* __restrict__ part, double* __restrict__ out) {
+k_sum_partials(int nb, const double* __restrict__ part, long stride, double* __restrict__ out) {
   __shared__ double red_sh[4];
   const int r = blockIdx.x;
-  const double tot = reduce_partials<256>(part + (long)r * kPStride, nb, red_sh);
+  const double tot = reduce_partials<256>(part + (long)r * stride, nb, red_sh);
   if (threadIdx.x == 0) out[r] = tot;
 }
 

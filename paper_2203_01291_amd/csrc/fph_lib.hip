@@ -479,10 +479,10 @@ int fermion_action(fph_handle_t h, int32_t nrhs, const double* b_dev, const doub
   hipStream_t s = (hipStream_t)stream;
   const int nb = elem_blocks(h->g.d);
   hipLaunchKernelGGL(k_dot_partials, dim3(nb, nrhs), dim3(256), 0, s, h->g.d, b_dev, u_dev,
-                     h->tmp_part());
+                     h->tmp_part(), (long)kPStride);
   FPH_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, s, nb, (const double*)h->tmp_part(),
-                     out_dev);
+                     (long)kPStride, out_dev);
   FPH_CHECK(hipGetLastError());
   return FPH_OK;
 }
@@ -716,7 +716,7 @@ hipError_t coop_enqueue(fph_handle_s* h, const double* b_dev, double* u_dev,
   if (e != hipSuccess) return e;
   const int nb = elem_blocks(h->g.d);
   hipLaunchKernelGGL(k_dot_partials, dim3(nb, 1), dim3(256), 0, s, h->g.d, b_dev,
-                     (const double*)u_dev, h->fin_part);
+                     (const double*)u_dev, h->fin_part, (long)kPStride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_coop_stats, dim3(1), dim3(256), 0, s, nb, (const CoopStats*)out,
                      (const double*)h->fin_part, stats);
