@@ -244,6 +244,18 @@ int fermion_force(fph_handle_t h, int32_t nrhs, const double* u_dev,
 int fermion_action(fph_handle_t h, int32_t nrhs, const double* b_dev,
                    const double* u_dev, double* out_dev, void* stream);
 
+/* fermion_action for callers that cannot allocate device memory at all
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result, bit for bit, with the partial sums of the
+ * dot products kept in a static device array of the library (512 KiB per
+ * GPU, held until the process ends) instead of the handle's workspace; the
+ * call allocates nothing.  nrhs <= 64 (and <= max_rhs), else FPH_E_NRHS;
+ * the current device must be the handle's (FPH_E_ARG).  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from different host threads) race.  Enqueue only. */
+int fermion_action_noalloc(fph_handle_t h, int32_t nrhs, const double* b_dev,
+                           const double* u_dev, double* out_dev, void* stream);
+
 /* out = op(in) with the preconditioner of the current field: F ~ P^{-1}
  * = U^dagger Ptilde^{-1} U (Eq. P_change_basis) with each block inverse
  * replaced by its truncated Chebyshev series (Eq. f_A_approx), F^T, or

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libholstein_hmc.so")
 
 FPH_OK = 0
+FPH_E_NULL, FPH_E_LATTICE, FPH_E_NRHS, FPH_E_PREC, FPH_E_NOFIELD, FPH_E_ALIGN, FPH_E_ARG = -1, -2, -3, -4, -5, -6, -7
 FPH_OP_M, FPH_OP_MT, FPH_OP_MTM = 0, 1, 2
 FPH_F64, FPH_F32, FPH_F32_REFINED = 0, 1, 2
 FPH_PC_F, FPH_PC_FT, FPH_PC_FFT = 0, 1, 2
@@ -127,6 +128,8 @@ EXPORTS = {
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "fermion_action": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fermion_action_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fph_precond_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fph_precond_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),

@@ -47,6 +47,41 @@ int fail_hip(hipError_t e) {
 
 int fph::record_hip_error(hipError_t e) { return fail_hip(e); }
 
+// ------------------------------------------- no-allocation scratch array --
+//
+// fermion_action_noalloc takes the partial sums of its dot products from
+// this file-scope device array instead of the handle's workspace: 64
+// right-hand sides x 1024 partials (512 KiB), held by every GPU the library
+// runs on until the process ends.  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress, taken once per
+// device with that device current (fph_create does it for the handle's
+// device) and kept in kScratchPtr[device].
+constexpr int kNoAllocMaxRhs = 64;
+constexpr int kNoAllocMaxBlocks = 1024;  // elem_blocks() never exceeds this
+static __device__ __align__(256) double scratch[kNoAllocMaxRhs * kNoAllocMaxBlocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), looked up once.
+hipError_t scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 struct fph_handle_s {
   fph_lattice_t lat;
   Geom g;
@@ -80,6 +115,8 @@ struct fph_handle_s {
   PcTables pc;
   // scratch partials for plain reductions outside a solve
   double* tmp_part() const { return part[1]; }
+  // device address of the library's static scratch array on this device
+  double* noalloc_part;
 };
 
 namespace {
@@ -345,6 +382,7 @@ int fph_create(fph_handle_t* out, const fph_lattice_t* lat, int32_t max_rhs) {
   if (e == hipSuccess) e = hipMemset(h->st[0], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = hipMemset(h->st[1], 0, max_rhs * sizeof(RhsState));
   if (e == hipSuccess) e = pc_create(&h->pc, h->g, max_rhs);
+  if (e == hipSuccess) e = scratch_address(h->device, &h->noalloc_part);
   h->pc.th = h->th;
   h->pc.c4 = h->c4;
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -483,6 +521,25 @@ int fermion_action(fph_handle_t h, int32_t nrhs, const double* b_dev, const doub
   FPH_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, s, nb, (const double*)h->tmp_part(),
                      (long)kPStride, out_dev);
+  FPH_CHECK(hipGetLastError());
+  return FPH_OK;
+}
+
+int fermion_action_noalloc(fph_handle_t h, int32_t nrhs, const double* b_dev,
+                           const double* u_dev, double* out_dev, void* stream) {
+  if (h == nullptr || b_dev == nullptr || u_dev == nullptr || out_dev == nullptr) return FPH_E_NULL;
+  if (nrhs < 1 || nrhs > h->max_rhs || nrhs > kNoAllocMaxRhs) return FPH_E_NRHS;
+  int dev = -1;
+  FPH_CHECK(hipGetDevice(&dev));
+  if (dev != h->device || h->noalloc_part == nullptr) return FPH_E_ARG;
+  const int nb = elem_blocks(h->g.d);
+  if (nb > kNoAllocMaxBlocks) return FPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_dot_partials, dim3(nb, nrhs), dim3(256), 0, s, h->g.d, b_dev, u_dev,
+                     h->noalloc_part, (long)kNoAllocMaxBlocks);
+  FPH_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_partials, dim3(nrhs), dim3(256), 0, s, nb,
+                     (const double*)h->noalloc_part, (long)kNoAllocMaxBlocks, out_dev);
   FPH_CHECK(hipGetLastError());
   return FPH_OK;
 }
