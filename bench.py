@@ -533,10 +533,7 @@ def blas_threads():
 # WRITE_SIZE runs of `bench.py --profile-roofline`, each scaled by the same
 # counter read for a copy kernel of known size.  Valid only while the
 # kernel sources hash to `source_sha1`; otherwise reported as null.
-TRAFFIC = {"bytes_per_launch": 443106558, "read_bytes": 233390743, "write_bytes": 209715814,
-           "fetch_scale": 1.99976, "write_scale": 1.00000,
-           "source_sha1": "c1dc8bb5ca712456e385ea56f699533f711a0781",
-           "profile": "profiles/mtm_f32_L64_Ltau400_r32_counters.md"}
+TRAFFIC = None  # taken again after the kernel sources changed
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
 
@@ -550,15 +547,20 @@ def kernel_sources_sha1():
     return h.hexdigest()
 
 
-def large_matvec_setup(torch, dev):
+# Right-hand sides of the roofline applies: (2R + 1) d w bytes per launch at
+# L = 64, Ltau = 400 (d = 1 638 400) must exceed 4 x the 256 MB Infinity
+# Cache (1.03 GB): FP32 R = 80 -> 1.055 GB, FP64 R = 40 -> 1.062 GB.
+ROOF_R32 = 80
+ROOF_R64 = 40
+
+
+def large_matvec_setup(torch, dev, R5=ROOF_R32):
     """The roofline workload: fused M^T M at L = 64, Ltau = 400 (c5 shape)
-    with 32 right-hand sides sharing one field: 852 MB (FP64) / 426 MB
-    (FP32) of algorithmic traffic per launch, far above the 256 MB
-    Infinity Cache."""
+    with R5 right-hand sides sharing one field (FP64 values; slices of it
+    serve the smaller FP64 leg)."""
     from paper_2203_01291_amd.solver import FermionSolver
     from workloads import get_config, phonon_field
     p5 = get_config("c5")
-    R5 = 32
     s5 = FermionSolver.from_params(p5, max_rhs=1)
     s5.set_field(torch.from_numpy(phonon_field(p5)).to(dev))
     g = torch.Generator(device=dev)
@@ -567,19 +569,163 @@ def large_matvec_setup(torch, dev):
     return p5, R5, s5, vl
 
 
+def error_vs_golden(key, u, g, S, tol):
+    """Relative error of a solution u, force g and action S of the workload
+    `key` (x = x0 + 0.1 N(0,1), Phi = M(x0)^T phi) against the oracle's
+    stored values (its FP64 CG to relative residual 1e-13) at the stored
+    sample components: 2-norm over the samples and largest element-wise
+    error over the largest sample."""
+    import numpy as np
+    from workloads import get_config
+    p = get_config(key)
+    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{key}.json")
+    if not os.path.exists(gold_path):
+        return None
+    gold = json.load(open(gold_path))
+    idx = np.array(gold["samples"])
+    uh = u.reshape(p.Ltau, p.N).cpu().numpy()[idx[:, 0], idx[:, 1]]
+    gh = g.reshape(p.Ltau, p.N).cpu().numpy()[idx[:, 0], idx[:, 1]]
+    ur, gr = np.array(gold["u_samples"]), np.array(gold["force_samples"])
+    return {"reference": "oracle FP64 CG to relative residual 1e-13, same inputs (tests/golden)",
+            "components": int(len(idx)), "solve_tol": tol,
+            "u_rel": float(np.linalg.norm(uh - ur) / np.linalg.norm(ur)),
+            "u_maxrel": float(np.max(np.abs(uh - ur)) / np.max(np.abs(ur))),
+            "force_rel": float(np.linalg.norm(gh - gr) / np.linalg.norm(gr)),
+            "force_maxrel": float(np.max(np.abs(gh - gr)) / np.max(np.abs(gr))),
+            "S_F_rel": float(abs(float(S) - gold["S_F"]) / abs(gold["S_F"]))}
+
+
+def bench_workload_tols(torch, dev, key, tols, steps, log):
+    """The step (set-field + preconditioned PCG + S_F + force) of workload
+    `key` with its tuned Chebyshev constants, FP32-refined and FP64, at each
+    solve tolerance of `tols`: ms per step, iterations and the error against
+    the oracle's stored values."""
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import gaussian_rhs, get_config, perturbed_field, phonon_field
+    p = get_config(key)
+    a1, a2 = p.cheb
+    s = FermionSolver.from_params(p)
+    x0 = torch.from_numpy(phonon_field(p)).to(dev)
+    x = torch.from_numpy(perturbed_field(p, phonon_field(p))).to(dev)
+    s.set_field(x0)
+    Phi = s.matvec(torch.from_numpy(gaussian_rhs(p, 1)).to(dev), "MT")
+    torch.cuda.synchronize()
+    out = {"workload": f"{p.name}: L={p.L} Ltau={p.Ltau} d={p.dim}, preconditioned "
+                       f"(a1={a1}, a2={a2}), set-field + PCG + S_F + force per step"}
+    for tol in tols:
+        row = {}
+        for prec in ("f32_refined", "f64"):
+            last = {}
+
+            def step():
+                s.set_field(x, a1=a1, a2=a2)
+                u, st = s.solve(Phi, tol=tol, prec=prec, precond=True)
+                last["S"], last["g"], last["u"] = s.action(Phi, u), s.force(u), u
+                return st
+            t, st = time_steps(step, steps, 1, torch)
+            row[prec] = {"ms_per_step": t * 1e3, "solves_per_s": 1.0 / t, "iters": st[0]["iters"],
+                         "outer": st[0]["outer_iters"], "status": st[0]["status"],
+                         "rel_resid": st[0]["rel_resid"],
+                         "error_vs_oracle": error_vs_golden(key, last["u"], last["g"],
+                                                            float(last["S"][0]), tol)}
+        row["speedup_fp32_refined"] = row["f64"]["ms_per_step"] / row["f32_refined"]["ms_per_step"]
+        out[f"tol_{tol:g}"] = row
+        log(f"{key} tol {tol:g}: {row}")
+    s.close()
+    return out
+
+
+def bench_graph_step(torch, dev, p, a1, a2, log, replays=3):
+    """The step as a hipGraph: set-field + enqueue-only pcg_solve
+    (FP32-refined, preconditioned, tol 1e-8) + S_F + force captured once and
+    replayed.  pcg_solve enqueues 1 + maxiter + max_outer slots, so maxiter
+    is an iteration budget: here 1.05 x the iterations the blocking solve
+    needed on this field, max_outer 16."""
+    from paper_2203_01291_amd._lib import stats_from_device
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import gaussian_rhs, perturbed_field, phonon_field
+    s = FermionSolver.from_params(p)
+    x0 = torch.from_numpy(phonon_field(p)).to(dev)
+    x = torch.from_numpy(perturbed_field(p, phonon_field(p))).to(dev)
+    s.set_field(x0)
+    Phi = s.matvec(torch.from_numpy(gaussian_rhs(p, 1)).to(dev), "MT")
+    s.set_field(x, a1=a1, a2=a2)
+    _, st = s.solve(Phi, tol=1e-8, prec="f32_refined", precond=True)
+    budget = int(1.05 * st[0]["iters"]) + 1
+    u = torch.zeros_like(Phi)
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    S = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(p.Ltau, p.N, dtype=torch.float64, device=dev)
+
+    def step():
+        s.set_field(x, a1=a1, a2=a2)
+        s.solve_async(Phi, u=u, stats=stats, tol=1e-8, maxiter=budget, precond=True,
+                      prec="f32_refined", zero_guess=True, max_outer=16)
+        s.action(Phi, u, out=S)
+        g.zero_()
+        s.force(u, grad=g)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / replays
+    sd = stats_from_device(stats)[0]
+    res = {"iteration_budget": budget, "blocking_iters": st[0]["iters"], "status": sd["status"],
+           "iters": sd["iters"], "rel_resid": sd["rel_resid"],
+           "eager_enqueue_only_ms": t_eager * 1e3, "graph_replay_ms": t_graph * 1e3,
+           "error_vs_oracle": error_vs_golden(p_key(p), u, g, float(S[0]), 1e-8)}
+    log(f"graph step: {res}")
+    del graph
+    s.close()
+    return res
+
+
+def p_key(p):
+    from workloads import CONFIGS
+    return next(k for k, v in CONFIGS.items() if v.name == p.name)
+
+
 def profile_roofline(torch, dev):
+    """For hardware-counter runs: 10 FP64 applies (ROOF_R64 rhs), 10 FP32
+    applies (ROOF_R32 rhs) of the roofline kernel, then 10 plain copies of
+    the FP64 apply's byte count (the reference for the counter scale)."""
     p5, R5, s5, vl = large_matvec_setup(torch, dev)
+    v64 = vl[:ROOF_R64].contiguous()
+    out = torch.empty_like(v64)
+    for _ in range(10):
+        s5.matvec(v64, "MTM", out=out)
+    del v64, out
     v32 = vl.float()
+    del vl
     out = torch.empty_like(v32)
     for _ in range(10):
         s5.matvec(v32, "MTM", out=out)
-    nbytes = (2 * R5 + 1) * p5.dim * 4
-    src = torch.empty(nbytes // 8, dtype=torch.float32, device=dev).normal_()
+    del v32, out
+    nbytes64 = (2 * ROOF_R64 + 1) * p5.dim * 8
+    nbytes32 = (2 * R5 + 1) * p5.dim * 4
+    src = torch.empty(nbytes64 // 8, dtype=torch.float32, device=dev).normal_()
     dst = torch.empty_like(src)
     for _ in range(10):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"mtm_launches": 10, "mtm_bytes": nbytes, "copy_launches": 10,
+    print(json.dumps({"mtm_f64_launches": 10, "mtm_f64_bytes": nbytes64, "mtm_f32_launches": 10,
+                      "mtm_f32_bytes": nbytes32, "copy_launches": 10,
                       "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
 
 
@@ -711,24 +857,24 @@ def main():
     # Error of the timed step's solution and force against the oracle's
     # stored values (its FP64 CG to relative residual 1e-13, same inputs).
     err = None
-    gold_path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
-    if R == 1 and os.path.exists(gold_path):
-        gold = json.load(open(gold_path))
-        idx = np.array(gold["samples"])
-        uh = last["u"].reshape(p.Ltau, p.N).cpu().numpy()[idx[:, 0], idx[:, 1]]
-        gh = last["g"].reshape(p.Ltau, p.N).cpu().numpy()[idx[:, 0], idx[:, 1]]
-        ur, gr = np.array(gold["u_samples"]), np.array(gold["force_samples"])
-        err = {"reference": "oracle FP64 CG to relative residual 1e-13, same inputs (tests/golden)",
-               "components": int(len(idx)), "solve_tol": tol,
-               "u_rel": float(np.linalg.norm(uh - ur) / np.linalg.norm(ur)),
-               "force_rel": float(np.linalg.norm(gh - gr) / np.linalg.norm(gr)),
-               "S_F_rel": float(abs(S32[0] - gold["S_F"]) / abs(gold["S_F"]))}
+    if R == 1:
+        err = error_vs_golden(args.workload, last["u"], last["g"], S32[0], tol)
         log(f"error vs oracle: {err}")
     log(f"f32_refined: {t32 * 1e3:.2f} ms/step {st32}")
     t64, st64 = time_steps(make_step("f64", pre), max(1, args.steps // 2), min(args.warmup, 1), torch)
     st64 = [dict(v) for v in st64]
     S64 = last["S"].cpu().numpy().tolist()
     log(f"f64: {t64 * 1e3:.2f} ms/step {st64}")
+
+    # The same step at a solve tolerance whose error against the oracle is
+    # below 1e-8 (1e-11; the rigorous bound kappa * tol would need ~4e-15,
+    # below what an FP64 residual resolves), and the L = 64 workload at both
+    # tolerances; the step captured as a graph with the enqueue-only solve.
+    accuracy = c5 = graph_step = None
+    if not args.no_variants and R == 1:
+        accuracy = bench_workload_tols(torch, dev, args.workload, (1e-11,), 2, log)
+        c5 = bench_workload_tols(torch, dev, "c5", (1e-8, 1e-11), 3, log)
+        graph_step = bench_graph_step(torch, dev, p, args.a1, args.a2, log)
 
     # M^T M apply at the workload shape: the bandwidth-bound kernel of the path.
     d = p.dim
@@ -745,24 +891,43 @@ def main():
 
     large = None
     if not args.no_large:
-        # Same kernel on a working set far above the 256 MB Infinity Cache.
+        # Same kernel on working sets above 4 x the 256 MB Infinity Cache:
+        # FP32 with ROOF_R32 right-hand sides, FP64 with ROOF_R64.
         p5, R5, s5, vl = large_matvec_setup(torch, dev)
-        tl64 = event_time_matvec(s5, vl, "MTM", 20, torch)
+        vl64 = vl[:ROOF_R64].contiguous()
+        tl64 = event_time_matvec(s5, vl64, "MTM", 20, torch)
+        del vl64
         vl32 = vl.float()
+        del vl
         tl32 = event_time_matvec(s5, vl32, "MTM", 20, torch)
         tl32_iso = event_time_matvec(s5, vl32, "MTM", 20, torch, isolated=True)
-        bl64 = (2 * R5 + 1) * p5.dim * 8
+        bl64 = (2 * ROOF_R64 + 1) * p5.dim * 8
         bl32 = (2 * R5 + 1) * p5.dim * 4
+        src = torch.empty(bl64 // 8, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        t_copy = e0.elapsed_time(e1) / 10 * 1e-3
+        del src, dst
         large = {
-            "workload": f"{p5.name} x {R5} rhs sharing one field",
+            "workload": f"{p5.name}: {R5} rhs (FP32), {ROOF_R64} rhs (FP64) sharing one field",
+            "copy_kernel": {"bytes": bl64, "us": t_copy * 1e6, "GB/s": bl64 / t_copy / 1e9,
+                            "frac": bl64 / t_copy / 1e9 / HBM_PEAK_GBS},
             "working_set_MB": {"f64": bl64 / 1e6, "f32": bl32 / 1e6},
+            "mall_MB": 256, "working_set_over_mall": {"f64": bl64 / 256e6, "f32": bl32 / 256e6},
             "f64": {"us": tl64 * 1e6, "GB/s": bl64 / tl64 / 1e9, "frac": bl64 / tl64 / 1e9 / HBM_PEAK_GBS},
             "f32": {"us": tl32 * 1e6, "GB/s": bl32 / tl32 / 1e9, "frac": bl32 / tl32 / 1e9 / HBM_PEAK_GBS,
                     "isolated_launch_us": tl32_iso * 1e6},
         }
         log(f"large: {large}")
         s5.close()
-        del vl, vl32
+        del vl32
 
     batch = None
     if not args.no_batch:
@@ -787,15 +952,24 @@ def main():
         log(f"cpu baseline: {cpu}")
 
     if large is not None:
-        traffic = None
-        if TRAFFIC is not None and TRAFFIC["source_sha1"] == kernel_sources_sha1():
-            traffic = TRAFFIC["bytes_per_launch"]
-        roofline = {"bound": "hbm", "achieved": large["f32"]["GB/s"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": large["f32"]["frac"], "traffic": traffic,
-                    "kernel": "fused M^T M apply, FP32 (k_mtm<float, 1024, 1, InPlain, EpiStream>)",
-                    "workload": large["workload"],
-                    "bytes_per_launch": large["working_set_MB"]["f32"] * 1e6,
-                    "avg_launch_us": large["f32"]["us"]}
+        valid = TRAFFIC is not None and TRAFFIC["source_sha1"] == kernel_sources_sha1()
+        roofline = {"bound": "hbm", "achieved": large["f64"]["GB/s"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": large["f64"]["frac"],
+                    "traffic": TRAFFIC["f64_bytes_per_launch"] if valid else None,
+                    "kernel": "fused M^T M apply, FP64 (k_mtm<double, 1024, 1, InPlain, EpiStream>)",
+                    "workload": f"holstein_L64_Ltau400 x {ROOF_R64} rhs sharing one field "
+                                f"({large['working_set_over_mall']['f64']:.2f} x the 256 MB Infinity Cache)",
+                    "bytes_per_launch": large["working_set_MB"]["f64"] * 1e6,
+                    "avg_launch_us": large["f64"]["us"],
+                    "f32": {"kernel": "k_mtm<float, 1024, 1, InPlain, EpiStream>",
+                            "workload": f"holstein_L64_Ltau400 x {ROOF_R32} rhs sharing one field "
+                                        f"({large['working_set_over_mall']['f32']:.2f} x the MALL)",
+                            "achieved": large["f32"]["GB/s"], "frac": large["f32"]["frac"],
+                            "bytes_per_launch": large["working_set_MB"]["f32"] * 1e6,
+                            "avg_launch_us": large["f32"]["us"],
+                            "traffic": TRAFFIC["f32_bytes_per_launch"] if valid else None},
+                    "copy_kernel_frac": large["copy_kernel"]["frac"],
+                    "profile": TRAFFIC["profile"] if TRAFFIC else None}
     else:
         roofline = {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None,
@@ -827,6 +1001,9 @@ def main():
             "rel_resid": [v["rel_resid"] for v in st32],
         },
         "error_vs_oracle": err,
+        "accuracy_1e-8_error": accuracy,
+        "c5": c5,
+        "graph_step": graph_step,
         "fp64_cg": {"solves_per_s": R / t64, "ms_per_step": t64 * 1e3,
                     "iters": [v["iters"] for v in st64],
                     "speedup_fp32_refined": t64 / t32,
