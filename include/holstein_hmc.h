@@ -130,6 +130,12 @@ typedef struct {
                            first one (0 -> 32); a right-hand side that
                            reaches it stops with FPH_ST_MAXITER            */
   int32_t pad;
+  double cheb_a1;       /* fph_batch_solve with use_precond: Chebyshev
+                           order constants of every system's tables,
+                           N_P = floor(db (a1/phi + a2)) (Eq. NP_heuristic;
+                           0 -> 1).  pcg_solve takes them from
+                           fph_set_field instead.                          */
+  double cheb_a2;
 } fph_pcg_opts_t;
 
 typedef struct {
@@ -296,12 +302,19 @@ int fph_batch_create(fph_batch_t* bh, const fph_system_t* sys, int32_t nsys);
  * items from a queue and runs the item's FP32 conjugate gradients with
  * FP64 residual replacement to opts->tol (Sec. II D, Eq. CG; the paper's
  * stochastic measurements solve many such vectors at once, Sec. VI).
- * opts->prec must be FPH_F32_REFINED and opts->use_precond 0 (FPH_E_PREC /
- * FPH_E_ARG otherwise).  stats_dev: device array with one entry per
- * right-hand side in system order (may be NULL), written in stream order.
- * Enqueue only (the first call, and a call with other tol, maxiter or
- * ru_delta than the last, captures the graph on an internal stream first;
- * fph_batch_tune also captures). */
+ * With opts->use_precond the iteration is preconditioned by F F^T
+ * (Eq. CG_precon; Sec. V A, App. C): each system's dbar, bounds, N_P and
+ * Chebyshev coefficients (constants opts->cheb_a1, cheb_a2) are set up with
+ * the fields, and the item's workgroup applies the two transforms and the
+ * series of every frequency block itself; this needs workgroups of at least
+ * L^2/4 threads (FPH_E_ARG otherwise; the default shape qualifies).
+ * opts->prec must be FPH_F32_REFINED (FPH_E_PREC).  The replacement factor
+ * opts->ru_delta defaults to 0.1 with the preconditioner, 0.3 without.
+ * stats_dev: device array with one entry per right-hand side in system
+ * order (may be NULL), written in stream order.  Enqueue only (the first
+ * call, and a call with another tol, maxiter, ru_delta, use_precond or
+ * Chebyshev constants than the last, captures the graph on an internal
+ * stream first; fph_batch_tune also captures). */
 int fph_batch_solve(fph_batch_t bh, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_dev,
                     void* stream);
 

@@ -28,7 +28,8 @@ class PcgOpts(ctypes.Structure):
                 ("use_precond", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("zero_guess", ctypes.c_int32), ("ru_delta", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("cheb_a1", ctypes.c_double), ("cheb_a2", ctypes.c_double)]
 
 
 class PcgStats(ctypes.Structure):

@@ -2,16 +2,18 @@
 //
 // A work item is one (system, right-hand side) pair.  Each workgroup takes
 // items from a queue (one atomic add per item, items sorted by size,
-// largest first) and runs the whole solve of its item: FP32 conjugate
-// gradients on M^T M (the operator sweep of fph_matvec.h over all slices
-// of the item, chunks side by side in the block), and, whenever the FP32
-// residual has fallen by `delta` or below the tolerance, an FP64 residual
-// replacement: u64 += u32, r = b - M^T M u64 evaluated in FP64 with the
-// FP64 field, iteration continues with the replaced residual.  All
-// reductions are workgroup-local, so no workgroup ever waits for another;
-// every workgroup leaves when the queue is empty.
+// largest first) and runs the whole solve of its item: FP32 (preconditioned)
+// conjugate gradients on M^T M (the operator sweep of fph_matvec.h over all
+// slices of the item, chunks side by side in the block; with the
+// preconditioner, z = F F^T r by fph_batch_pc.h in the same workgroup), and,
+// whenever the FP32 residual has fallen by `delta` or below the tolerance,
+// an FP64 residual replacement: u64 += u32, r = b - M^T M u64 evaluated in
+// FP64 with the FP64 field, iteration continues with the replaced residual.
+// All reductions are workgroup-local, so no workgroup ever waits for
+// another; every workgroup leaves when the queue is empty.
 #pragma once
 
+#include "fph_batch_pc.h"
 #include "fph_blas.h"
 #include "fph_common.h"
 #include "fph_matvec.h"
@@ -30,6 +32,9 @@ struct BatchItem {
   float* pb;
   float* Ap;
   float* u32;
+  float* z;               // preconditioned direction input z = F F^T r
+  float2* Zw;             // transform workspace, [H][N] complex (d floats)
+  BatchPc pc;             // the system's preconditioner tables
   int out;                // index into the statistics array
   int pad;
 };
@@ -50,7 +55,18 @@ FPH_DEVINL double block_allsum(double v, double* sh, double* bcast) {
   return out;
 }
 
-// Input: p = r + beta p_old on the fly (fresh: p = r); owner stores p.
+// z = F F^T r for one item (fph_batch_pc.h); returns r . z in every thread.
+template <int NT>
+FPH_DEVINL double bpc_apply(const BatchItem& it, const float* r, float* z, unsigned char* lds,
+                            double* red_sh, double* bcast) {
+  float2* l = reinterpret_cast<float2*>(lds);
+  bpc_forward<NT>(it.g, it.pc, r, it.Zw, l);
+  bpc_series<NT>(it.g, it.pc, (float)it.th, it.Zw, l);
+  const double part = bpc_inverse<NT>(it.g, it.pc, it.Zw, r, z, l);
+  return block_allsum<NT>(part, red_sh, bcast);
+}
+
+// Input: p = z + beta p_old on the fly (fresh: p = z); owner stores p.
 template <typename T>
 struct InDir {
   const T* __restrict__ z;
@@ -104,7 +120,7 @@ struct InDir {
 
 template <int NT, int MS>
 FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, double delta,
-                                 unsigned char* lds, double* red_sh, double* bcast,
+                                 int pre, unsigned char* lds, double* red_sh, double* bcast,
                                  BatchStat* stats) {
   const Geom& g = it.g;
   const long d = g.d;
@@ -115,6 +131,8 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
   const bool active = (sub < S) && (tau0 < g.Ltau);
   const int Tc = active ? min(Tch, g.Ltau - tau0) : 0;
   const int so = (sub < S) ? sub : 0;
+  // The direction update reads z = F F^T r with the preconditioner, r without.
+  const float* zdir = pre ? it.z : it.r;
 
   // Initial state: u = 0, r = b.
   double bb = 0.0, rr = 0.0;
@@ -130,18 +148,22 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
   bb = block_allsum<NT>(bb, red_sh, bcast);
   rr = block_allsum<NT>(rr, red_sh, bcast);
   const double tol2 = tol * tol * bb;
-  double rz = rr, rz_prev = rr, rr_ref = rr, rr_true = bb, beta = 0.0;
+  double rz = rr, rr_ref = rr, rr_true = bb, beta = 0.0;
   int fresh = 1, iter = 0, outer = 0, matvecs = 0, status = 0;
   float* pold = it.pa;
   float* pnew = it.pb;
   if (bb == 0.0) status = 1;
   if (!isfinite(bb)) status = 8;
+  if (status == 0 && pre) {
+    rz = bpc_apply<NT>(it, it.r, it.z, lds, red_sh, bcast);
+    if (!(rz > 0.0) || !isfinite(rz)) status = isfinite(rz) ? 4 : 8;
+  }
 
   while (status == 0) {
-    // Direction update fused into the operator: Ap = A (r + beta p).
+    // Direction update fused into the operator: Ap = A (z + beta p).
     {
       float* lds4 = reinterpret_cast<float*>(lds) + 4L * so * g.N;
-      InDir<float> in{it.r, pold, pnew, (float)beta, fresh};
+      InDir<float> in{zdir, pold, pnew, (float)beta, fresh};
       EpiDot<float> epi{it.Ap};
       double acc = 0.0, acc2 = 0.0;
       mtm_sweep<float, NT, MS, 1>(g, it.E32, (float)it.th, Tch, tau0, Tc, active,
@@ -162,11 +184,8 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
       }
       rr = block_allsum<NT>(acc_rr, red_sh, bcast);
     }
-    rz_prev = rz;
-    rz = rr;
-    beta = rz / rz_prev;
-    fresh = 0;
     iter += 1;
+    fresh = 0;
     float* t = pold;
     pold = pnew;
     pnew = t;
@@ -174,7 +193,16 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
       status = 8;
       break;
     }
-    if (!(rr <= tol2 || rr < delta * delta * rr_ref || iter >= maxiter)) continue;
+    if (!(rr <= tol2 || rr < delta * delta * rr_ref || iter >= maxiter)) {
+      const double rz_new = pre ? bpc_apply<NT>(it, it.r, it.z, lds, red_sh, bcast) : rr;
+      if (!(rz_new > 0.0) || !isfinite(rz_new)) {
+        status = isfinite(rz_new) ? 4 : 8;
+        break;
+      }
+      beta = rz_new / rz;
+      rz = rz_new;
+      continue;
+    }
 
     // FP64 residual replacement.
     const double rr_iter = rr;
@@ -209,8 +237,13 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
     }
     rr = block_allsum<NT>(acc_rr, red_sh, bcast);
     if (rr > 100.0 * rr_iter) fresh = 1;  // replaced residual far from the iterated one
-    rz = rr;
-    beta = rz / rz_prev;
+    const double rz_new = pre ? bpc_apply<NT>(it, it.r, it.z, lds, red_sh, bcast) : rr;
+    if (!(rz_new > 0.0) || !isfinite(rz_new)) {
+      status = isfinite(rz_new) ? 4 : 8;
+      break;
+    }
+    beta = rz_new / rz;
+    rz = rz_new;
     rr_ref = rr;
   }
 
@@ -232,11 +265,13 @@ FPH_DEVINL void batch_solve_item(const BatchItem& it, double tol, int maxiter, d
 }
 
 // Persistent batched solve.  Launch: any number of blocks of NT threads;
-// LDS 4 * S * Nmax doubles (S = NT / Qmax chunks).  `queue` must be 0.
+// LDS: the larger of 4 * S * Nmax doubles (S = NT / Qmax chunks) and, with
+// the preconditioner (pre != 0, NT >= Qmax), the transforms' and the
+// series' needs (bpc_lds_tf, bpc_lds_series).  `queue` must be 0.
 template <int NT, int MS>
 __global__ void __launch_bounds__(NT)
 k_batch_solve(const BatchItem* __restrict__ items, int nitems, unsigned* queue, double tol,
-              int maxiter, double delta, BatchStat* stats) {
+              int maxiter, double delta, int pre, BatchStat* stats) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red_sh[NT / 64];
   __shared__ double bcast;
@@ -247,7 +282,7 @@ k_batch_solve(const BatchItem* __restrict__ items, int nitems, unsigned* queue, 
     const int k = item_sh;
     __syncthreads();
     if (k >= nitems) break;
-    batch_solve_item<NT, MS>(items[k], tol, maxiter, delta, smem_raw, red_sh, &bcast, stats);
+    batch_solve_item<NT, MS>(items[k], tol, maxiter, delta, pre, smem_raw, red_sh, &bcast, stats);
   }
 }
 

@@ -860,68 +860,121 @@ extern "C" int pcg_solve_sync(fph_handle_t h, int32_t nrhs, const double* b_dev,
 
 // ============================================================ batches
 
+// What a captured batch graph was made for.
+struct BatchRunCfg {
+  double tol, delta, a1, a2;
+  int maxiter;
+  bool pre;
+};
+
 struct fph_batch_s {
   int nsys;
   int nitems;
   std::vector<fph_system_t> sys;
   std::vector<long> eoff;     // offset of each system's field in E64/E32
+  std::vector<long> noff;     // offset of each system's sites in the dbar arrays
   double* E64;
   float* E32;
   float* work;
   BatchItem* items;
   BatchStat* stats;
   unsigned* queue;
+  // preconditioner tables, per system
+  double* dbar64;
+  float* dbar32;
+  PcInfo* info;
+  int* np;                    // [Ltau] per system (offset eoff / N = tau offsets)
+  std::vector<long> npoff, coff, twoff, foff;
+  double2* coef64;
+  float2* coef32;
+  double2 *tw64, *W64, *F64;
+  float2 *tw32, *W32, *F32;
   int nt, ms, per_cu;         // launch shape
   int num_cu;
   int qmax;
+  size_t lds_pc;              // LDS of the transforms and the series (bytes, largest system)
   hipStream_t cap;            // capture stream
   hipGraphExec_t exec;
   bool have_graph;
-  double g_tol, g_delta;
-  int g_maxiter;
+  BatchRunCfg gcfg;           // configuration the graph was captured with
 };
 
 namespace {
 
+bool same_cfg(const BatchRunCfg& a, const BatchRunCfg& c) {
+  return a.tol == c.tol && a.maxiter == c.maxiter && a.delta == c.delta && a.pre == c.pre &&
+         a.a1 == c.a1 && a.a2 == c.a2;
+}
+
+BatchRunCfg batch_cfg(const fph_pcg_opts_t* o) {
+  BatchRunCfg c;
+  c.tol = o->tol;
+  c.maxiter = o->maxiter;
+  c.pre = o->use_precond != 0;
+  // FP32 residual-replacement factor (as pcg_solve): shorter with the preconditioner.
+  c.delta = o->ru_delta > 0.0 ? std::min(o->ru_delta, 0.5) : (c.pre ? 0.1 : 0.3);
+  c.a1 = o->cheb_a1 > 0.0 ? o->cheb_a1 : 1.0;
+  c.a2 = o->cheb_a2 > 0.0 ? o->cheb_a2 : 1.0;
+  return c;
+}
+
 template <int NT, int MS>
-hipError_t batch_launch(fph_batch_s* b, double tol, int maxiter, double delta, hipStream_t s) {
-  // LDS: four FP64 slices per chunk, chunks side by side (largest over systems).
+hipError_t batch_launch(fph_batch_s* b, const BatchRunCfg& c, hipStream_t s) {
+  // LDS: four FP64 slices per chunk, chunks side by side (largest over
+  // systems); with the preconditioner also the transforms and the series.
   long sn = 0;
   for (const auto& sy : b->sys) {
     const int N = sy.lat.L * sy.lat.L, Q = N / 4;
     const int S = (Q <= NT) ? NT / Q : 1;
     sn = std::max<long>(sn, (long)S * N);
   }
-  const size_t lds = 4 * (size_t)sn * sizeof(double);
+  size_t lds = 4 * (size_t)sn * sizeof(double);
+  if (c.pre) lds = std::max(lds, b->lds_pc);
   auto kern = k_batch_solve<NT, MS>;
   {
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
   }
   const int grid = std::max(1, std::min(b->nitems, b->num_cu * b->per_cu));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, b->items, b->nitems, b->queue, tol,
-                     maxiter, delta, b->stats);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, b->items, b->nitems, b->queue, c.tol,
+                     c.maxiter, c.delta, c.pre ? 1 : 0, b->stats);
   return hipGetLastError();
 }
 
-// Field setup of every system, queue reset and the persistent solve.
-hipError_t batch_enqueue(fph_batch_s* b, double tol, int maxiter, double delta, hipStream_t s) {
+// Field setup of every system (with the preconditioner: dbar, bounds,
+// N_P and the Chebyshev coefficients of App. C as in fph_set_field), queue
+// reset and the persistent solve.
+hipError_t batch_enqueue(fph_batch_s* b, const BatchRunCfg& c, hipStream_t s) {
   for (int k = 0; k < b->nsys; ++k) {
     const fph_lattice_t& L = b->sys[k].lat;
-    const long d = (long)L.L * L.L * L.Ltau;
+    const int N = L.L * L.L;
+    const long d = (long)N * L.Ltau;
     const double ch = std::cosh(L.dtau * L.t);
+    const double c4 = ch * ch * ch * ch;
     hipLaunchKernelGGL(k_set_field, dim3(elem_blocks(d)), dim3(256), 0, s, d, b->sys[k].x_dev,
-                       L.dtau, L.alpha, L.mu, ch * ch * ch * ch, b->E64 + b->eoff[k],
-                       b->E32 + b->eoff[k]);
+                       L.dtau, L.alpha, L.mu, c4, b->E64 + b->eoff[k], b->E32 + b->eoff[k]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (!c.pre) continue;
+    hipLaunchKernelGGL(k_dbar, dim3((N + 63) / 64), dim3(64, 16), 0, s, N, L.Ltau,
+                       (const double*)(b->E64 + b->eoff[k]), c4, b->dbar64 + b->noff[k],
+                       b->dbar32 + b->noff[k]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pc_bounds, dim3(1), dim3(256), 0, s, N, L.Ltau,
+                       (const double*)(b->dbar64 + b->noff[k]), L.dtau, L.t, c.a1, c.a2,
+                       b->info + k, b->np + b->npoff[k]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pc_coef, dim3(L.Ltau / 2), dim3(256), 0, s, L.Ltau,
+                       (const PcInfo*)(b->info + k), (const int*)(b->np + b->npoff[k]),
+                       b->coef64 + b->coff[k], b->coef32 + b->coff[k]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, b->queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (b->nt == 256 && b->ms == 1) return batch_launch<256, 1>(b, tol, maxiter, delta, s);
-  if (b->nt == 128 && b->ms == 2) return batch_launch<128, 2>(b, tol, maxiter, delta, s);
-  if (b->nt == 512 && b->ms == 1) return batch_launch<512, 1>(b, tol, maxiter, delta, s);
+  if (b->nt == 256 && b->ms == 1) return batch_launch<256, 1>(b, c, s);
+  if (b->nt == 128 && b->ms == 2) return batch_launch<128, 2>(b, c, s);
+  if (b->nt == 512 && b->ms == 1) return batch_launch<512, 1>(b, c, s);
   return hipErrorInvalidValue;
 }
 
@@ -934,7 +987,7 @@ __global__ void k_copy_batch_stats(int n, const BatchStat* __restrict__ in,
   out[k] = PcgStatsDev{s.status, s.iters, s.outer, s.matvecs, s.rel_resid, s.action};
 }
 
-hipError_t batch_graph(fph_batch_s* b, double tol, int maxiter, double delta) {
+hipError_t batch_graph(fph_batch_s* b, const BatchRunCfg& c) {
   if (b->have_graph) {
     (void)hipGraphExecDestroy(b->exec);
     b->have_graph = false;
@@ -942,7 +995,7 @@ hipError_t batch_graph(fph_batch_s* b, double tol, int maxiter, double delta) {
   hipGraph_t graph;
   hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t e2 = batch_enqueue(b, tol, maxiter, delta, b->cap);
+  hipError_t e2 = batch_enqueue(b, c, b->cap);
   e = hipStreamEndCapture(b->cap, &graph);
   if (e2 != hipSuccess) return e2;
   if (e != hipSuccess) return e;
@@ -950,10 +1003,18 @@ hipError_t batch_graph(fph_batch_s* b, double tol, int maxiter, double delta) {
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return e;
   b->have_graph = true;
-  b->g_tol = tol;
-  b->g_maxiter = maxiter;
-  b->g_delta = delta;
+  b->gcfg = c;
   return hipSuccess;
+}
+
+int check_batch_opts(const fph_batch_s* b, const fph_pcg_opts_t* opts) {
+  if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
+  if (!(opts->tol >= 0.0) || opts->maxiter < 1 || !std::isfinite(opts->cheb_a1) ||
+      !std::isfinite(opts->cheb_a2))
+    return FPH_E_ARG;
+  // the in-workgroup series needs one even plaquette per thread
+  if (opts->use_precond && b->nt < b->qmax) return FPH_E_ARG;
+  return FPH_OK;
 }
 
 }  // namespace
@@ -964,35 +1025,41 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
   if (out == nullptr || sys == nullptr) return FPH_E_NULL;
   *out = nullptr;
   if (nsys < 1) return FPH_E_ARG;
-  long etot = 0, wtot = 0;
+  long etot = 0, wtot = 0, ntot = 0, nptot = 0, ctot = 0, twtot = 0, ftot = 0;
   int nitems = 0, qmax = 1;
+  size_t lds_pc = 0;
   for (int k = 0; k < nsys; ++k) {
     const fph_lattice_t& L = sys[k].lat;
     if (sys[k].x_dev == nullptr || sys[k].b_dev == nullptr || sys[k].u_dev == nullptr)
       return FPH_E_NULL;
     if (L.L < 4 || L.L % 2 || L.L > 32 || L.Ltau < 2 || L.Ltau % 2 || L.Ltau > kPHalf ||
-        !(L.dtau > 0.0) || !std::isfinite(L.t) || !std::isfinite(L.mu) || !std::isfinite(L.alpha))
+        !pc_supported(L.Ltau) || !(L.dtau > 0.0) || !std::isfinite(L.t) ||
+        !std::isfinite(L.mu) || !std::isfinite(L.alpha))
       return FPH_E_LATTICE;
     if (sys[k].nrhs < 1) return FPH_E_NRHS;
-    const long d = (long)L.L * L.L * L.Ltau;
+    const int N = L.L * L.L;
+    const long d = (long)N * L.Ltau;
+    const int H = L.Ltau / 2, H1 = pick_h1(H), H2 = H / H1;
     etot += d;
-    wtot += 5 * d * sys[k].nrhs;
+    wtot += 7 * d * sys[k].nrhs;
+    ntot += N;
+    nptot += L.Ltau;
+    ctot += (long)H * kNPMax;
+    twtot += H;
+    ftot += (long)H1 * H1 + (long)H2 * H2;
     nitems += sys[k].nrhs;
-    qmax = std::max(qmax, L.L * L.L / 4);
+    qmax = std::max(qmax, N / 4);
+    lds_pc = std::max(lds_pc, (size_t)std::max(bpc_lds_tf(H, H1, H2, bpc_tile_n(N)),
+                                               bpc_lds_series(L.L)) * sizeof(float2));
   }
   fph_batch_s* b = new fph_batch_s();
   b->nsys = nsys;
   b->nitems = nitems;
   b->qmax = qmax;
+  b->lds_pc = lds_pc;
   b->sys.assign(sys, sys + nsys);
-  b->E64 = nullptr;
-  b->E32 = nullptr;
-  b->work = nullptr;
-  b->items = nullptr;
-  b->stats = nullptr;
-  b->queue = nullptr;
   b->have_graph = false;
-  b->nt = 256;
+  b->nt = qmax <= 256 ? 256 : 512;
   b->ms = 1;
   b->per_cu = 2;
   int dev = 0;
@@ -1000,13 +1067,72 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
   hipDeviceProp_t prop;
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
   b->num_cu = (e == hipSuccess) ? prop.multiProcessorCount : 256;
-  if (e == hipSuccess) e = hipMalloc((void**)&b->E64, etot * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->E32, etot * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->work, wtot * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->items, nitems * sizeof(BatchItem));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->stats, nitems * sizeof(BatchStat));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->queue, sizeof(unsigned));
+#define BALLOC(ptr, n) \
+  if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (size_t)(n) * sizeof(*(ptr)));
+  BALLOC(b->E64, etot);
+  BALLOC(b->E32, etot);
+  BALLOC(b->work, wtot);
+  BALLOC(b->items, nitems);
+  BALLOC(b->stats, nitems);
+  BALLOC(b->queue, 1);
+  BALLOC(b->dbar64, ntot);
+  BALLOC(b->dbar32, ntot);
+  BALLOC(b->info, nsys);
+  BALLOC(b->np, nptot);
+  BALLOC(b->coef64, ctot);
+  BALLOC(b->coef32, ctot);
+  BALLOC(b->tw64, twtot);
+  BALLOC(b->W64, twtot);
+  BALLOC(b->tw32, twtot);
+  BALLOC(b->W32, twtot);
+  BALLOC(b->F64, ftot);
+  BALLOC(b->F32, ftot);
+#undef BALLOC
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    fph_batch_destroy(b);
+    return fail_hip(e);
+  }
+  // Per-system offsets, twiddle tables (they depend on Ltau only), and the
+  // preconditioner view of each system.
+  std::vector<BatchPc> pcs(nsys);
+  {
+    long eo = 0, no = 0, npo = 0, co = 0, two = 0, fo = 0;
+    for (int k = 0; k < nsys; ++k) {
+      const fph_lattice_t& L = sys[k].lat;
+      const int N = L.L * L.L;
+      const int H = L.Ltau / 2, H1 = pick_h1(H), H2 = H / H1;
+      b->eoff.push_back(eo);
+      b->noff.push_back(no);
+      b->npoff.push_back(npo);
+      b->coff.push_back(co);
+      b->twoff.push_back(two);
+      b->foff.push_back(fo);
+      hipLaunchKernelGGL(k_pc_twiddles, dim3((H + H1 * H1 + H2 * H2 + 255) / 256), dim3(256), 0, 0,
+                         H, H1, H2, L.Ltau, b->tw64 + two, b->W64 + two, b->F64 + fo,
+                         b->tw32 + two, b->W32 + two, b->F32 + fo);
+      const double ch = std::cosh(L.dtau * L.t);
+      BatchPc& pc = pcs[k];
+      pc.info = b->info + k;
+      pc.np = b->np + npo;
+      pc.coef = b->coef32 + co;
+      pc.dbar = b->dbar32 + no;
+      pc.tw = b->tw32 + two;
+      pc.W = b->W32 + two;
+      pc.F = b->F32 + fo;
+      pc.c4 = (float)(ch * ch * ch * ch);
+      pc.H = H;
+      pc.H1 = H1;
+      pc.H2 = H2;
+      eo += (long)N * L.Ltau;
+      no += N;
+      npo += L.Ltau;
+      co += (long)H * kNPMax;
+      two += H;
+      fo += (long)H1 * H1 + (long)H2 * H2;
+    }
+  }
+  if ((e = hipGetLastError()) == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     fph_batch_destroy(b);
     return fail_hip(e);
@@ -1014,7 +1140,7 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
   // Work items, largest first (stable: system order within equal sizes).
   std::vector<BatchItem> items;
   items.reserve(nitems);
-  long eo = 0, wo = 0;
+  long wo = 0;
   int gidx = 0;
   for (int k = 0; k < nsys; ++k) {
     const fph_lattice_t& L = sys[k].lat;
@@ -1025,14 +1151,13 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
     g.Q = g.N / 4;
     g.Ltau = L.Ltau;
     g.d = (long)g.N * L.Ltau;
-    b->eoff.push_back(eo);
     for (int j = 0; j < sys[k].nrhs; ++j) {
       BatchItem it;
       std::memset(&it, 0, sizeof(it));
       it.g = g;
       it.th = std::tanh(L.dtau * L.t);
-      it.E64 = b->E64 + eo;
-      it.E32 = b->E32 + eo;
+      it.E64 = b->E64 + b->eoff[k];
+      it.E32 = b->E32 + b->eoff[k];
       it.b = sys[k].b_dev + (long)j * g.d;
       it.u = sys[k].u_dev + (long)j * g.d;
       it.r = b->work + wo;
@@ -1040,11 +1165,13 @@ int fph_batch_create(fph_batch_t* out, const fph_system_t* sys, int32_t nsys) {
       it.pb = it.pa + g.d;
       it.Ap = it.pb + g.d;
       it.u32 = it.Ap + g.d;
+      it.z = it.u32 + g.d;
+      it.Zw = reinterpret_cast<float2*>(it.z + g.d);
+      it.pc = pcs[k];
       it.out = gidx++;
-      wo += 5 * g.d;
+      wo += 7 * g.d;
       items.push_back(it);
     }
-    eo += g.d;
   }
   std::stable_sort(items.begin(), items.end(),
                    [](const BatchItem& a, const BatchItem& c) { return a.g.d > c.g.d; });
@@ -1061,7 +1188,9 @@ int fph_batch_destroy(fph_batch_t b) {
   if (b == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
   if (b->have_graph) (void)hipGraphExecDestroy(b->exec);
-  void* ptrs[] = {b->E64, b->E32, b->work, b->items, b->stats, b->queue};
+  void* ptrs[] = {b->E64, b->E32, b->work, b->items, b->stats, b->queue, b->dbar64, b->dbar32,
+                  b->info, b->np, b->coef64, b->coef32, b->tw64, b->W64, b->tw32, b->W32,
+                  b->F64, b->F32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -1072,13 +1201,11 @@ int fph_batch_destroy(fph_batch_t b) {
 int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_dev,
                     void* stream) {
   if (b == nullptr || opts == nullptr) return FPH_E_NULL;
-  if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
-  if (opts->use_precond != 0 || !(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
+  const int rc = check_batch_opts(b, opts);
+  if (rc != FPH_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  const double delta = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3;
-  if (!b->have_graph || b->g_tol != opts->tol || b->g_maxiter != opts->maxiter ||
-      b->g_delta != delta)
-    FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
+  const BatchRunCfg c = batch_cfg(opts);
+  if (!b->have_graph || !same_cfg(b->gcfg, c)) FPH_CHECK(batch_graph(b, c));
   FPH_CHECK(hipGraphLaunch(b->exec, s));
   if (stats_dev) {
     hipLaunchKernelGGL(k_copy_batch_stats, dim3((b->nitems + 255) / 256), dim3(256), 0, s,
@@ -1092,14 +1219,14 @@ int fph_batch_solve(fph_batch_t b, const fph_pcg_opts_t* opts, fph_pcg_stats_t* 
 int fph_batch_tune(fph_batch_t b, const fph_pcg_opts_t* opts, int32_t* best, void* stream) {
   if (b == nullptr || opts == nullptr) return FPH_E_NULL;
   if (opts->prec != FPH_F32_REFINED) return FPH_E_PREC;
-  if (opts->use_precond != 0 || !(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
+  if (!(opts->tol >= 0.0) || opts->maxiter < 1) return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  const double delta = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : 0.3;
+  const BatchRunCfg c = batch_cfg(opts);
   struct Cfg { int nt, ms, per_cu; };
   std::vector<Cfg> cands;
   for (int pc : {1, 2, 4}) {
     if (b->qmax <= 256) cands.push_back({256, 1, pc});
-    cands.push_back({128, 2, pc});
+    if (!c.pre) cands.push_back({128, 2, pc});
     if (b->qmax <= 512) cands.push_back({512, 1, pc});
   }
   hipEvent_t e0, e1;
@@ -1107,12 +1234,12 @@ int fph_batch_tune(fph_batch_t b, const fph_pcg_opts_t* opts, int32_t* best, voi
   FPH_CHECK(hipEventCreate(&e1));
   float best_ms = 1e30f;
   Cfg best_cfg = {b->nt, b->ms, b->per_cu};
-  for (const Cfg& c : cands) {
-    if (c.ms * c.nt < b->qmax) continue;  // a slice must fit one block
-    b->nt = c.nt;
-    b->ms = c.ms;
-    b->per_cu = c.per_cu;
-    FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
+  for (const Cfg& cf : cands) {
+    if (cf.ms * cf.nt < b->qmax) continue;  // a slice must fit one block
+    b->nt = cf.nt;
+    b->ms = cf.ms;
+    b->per_cu = cf.per_cu;
+    FPH_CHECK(batch_graph(b, c));
     FPH_CHECK(hipGraphLaunch(b->exec, s));  // warm-up
     FPH_CHECK(hipEventRecord(e0, s));
     FPH_CHECK(hipGraphLaunch(b->exec, s));
@@ -1122,7 +1249,7 @@ int fph_batch_tune(fph_batch_t b, const fph_pcg_opts_t* opts, int32_t* best, voi
     FPH_CHECK(hipEventElapsedTime(&ms, e0, e1));
     if (ms < best_ms) {
       best_ms = ms;
-      best_cfg = c;
+      best_cfg = cf;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1130,7 +1257,7 @@ int fph_batch_tune(fph_batch_t b, const fph_pcg_opts_t* opts, int32_t* best, voi
   b->nt = best_cfg.nt;
   b->ms = best_cfg.ms;
   b->per_cu = best_cfg.per_cu;
-  FPH_CHECK(batch_graph(b, opts->tol, opts->maxiter, delta));
+  FPH_CHECK(batch_graph(b, c));
   if (best) {
     best[0] = b->nt;
     best[1] = b->ms;

@@ -235,25 +235,29 @@ class FermionBatch:
         check(self.lib.fph_batch_create(ctypes.byref(h), arr, len(systems)))
         self.h = h
 
-    def _opts(self, tol, maxiter, ru_delta):
-        return PcgOpts(float(tol), int(maxiter), 0, FPH_F32_REFINED, 1, float(ru_delta), 0, 0, 0, 0)
+    def _opts(self, tol, maxiter, ru_delta, precond=False, a1=1.0, a2=1.0):
+        return PcgOpts(float(tol), int(maxiter), int(bool(precond)), FPH_F32_REFINED, 1,
+                       float(ru_delta), 0, 0, 0, 0, float(a1), float(a2))
 
-    def solve_async(self, tol=1e-8, maxiter=100000, ru_delta=0.0, stats=None):
+    def solve_async(self, tol=1e-8, maxiter=100000, ru_delta=0.0, stats=None, precond=False,
+                    a1=1.0, a2=1.0):
         """Enqueue the batched solve (fph_batch_solve) and return the device
-        statistics tensor (nrhs_total entries; see _lib.stats_from_device)."""
+        statistics tensor (nrhs_total entries; see _lib.stats_from_device).
+        precond: F F^T preconditioning with Chebyshev constants a1, a2."""
         if stats is None:
             stats = torch.empty(self.nrhs_total * 4, dtype=torch.float64, device=self.u[0].device)
-        opts = self._opts(tol, maxiter, ru_delta)
+        opts = self._opts(tol, maxiter, ru_delta, precond, a1, a2)
         check(self.lib.fph_batch_solve(self.h, ctypes.byref(opts), _ptr(stats), _stream()))
         return stats
 
-    def solve(self, tol=1e-8, maxiter=100000, ru_delta=0.0):
+    def solve(self, tol=1e-8, maxiter=100000, ru_delta=0.0, precond=False, a1=1.0, a2=1.0):
         """The batched solve, waiting for it: one stats dict per right-hand side."""
-        return stats_from_device(self.solve_async(tol, maxiter, ru_delta))
+        return stats_from_device(self.solve_async(tol, maxiter, ru_delta, precond=precond, a1=a1,
+                                                  a2=a2))
 
-    def tune(self, tol=1e-8, maxiter=100000, ru_delta=0.0):
+    def tune(self, tol=1e-8, maxiter=100000, ru_delta=0.0, precond=False, a1=1.0, a2=1.0):
         best = (ctypes.c_int32 * 3)()
-        opts = self._opts(tol, maxiter, ru_delta)
+        opts = self._opts(tol, maxiter, ru_delta, precond, a1, a2)
         check(self.lib.fph_batch_tune(self.h, ctypes.byref(opts), best, _stream()))
         return {"threads": best[0], "plaquettes_per_thread": best[1], "blocks_per_cu": best[2]}
 

@@ -355,6 +355,81 @@ def test_batched_solve_uneven_systems():
             j += 1
 
 
+@pytest.mark.parametrize("a1a2", [(1.0, 1.0), (0.3, 8.0)])
+def test_batched_preconditioned_solve_uneven_systems(a1a2):
+    """The batch with F F^T applied inside each item's workgroup (per-system
+    tables): systems of different L, Ltau (splits H = 4x1, 3x1, 3x2, 5x1,
+    10x2) and right-hand-side counts against the oracle's direct solve, with
+    fewer iterations than without the preconditioner."""
+    from paper_2203_01291_amd.solver import FermionBatch
+    shapes = [(4, 8, 0.1, 1.0, 0.0, 1.0, 3), (8, 10, 0.1, 0.9, 0.1, 1.2, 2),
+              (6, 6, 0.1, 1.0, 0.2, 1.3, 1), (12, 12, 0.08, 1.0, 0.0, 0.9, 2),
+              (4, 40, 0.1, 1.0, 0.0, 1.0, 1), (16, 40, 0.1, 1.0, 0.0, 1.0, 2)]
+    systems, refs = [], []
+    for k, (L, Ltau, dtau, t, mu, alpha, nrhs) in enumerate(shapes):
+        lat = OL.Lattice(L, Ltau, dtau, t, mu, alpha)
+        rng = np.random.default_rng(300 + k)
+        x = rng.standard_normal((Ltau, lat.N))
+        b = rng.standard_normal((nrhs, Ltau, lat.N))
+        refs.append(OS.solve_dense(lat, x, b) if lat.dim <= 2000 else OS.solve_sparse(lat, x, b))
+        systems.append((lat, tgpu(x), tgpu(b)))
+    batch = FermionBatch(systems)
+    a1, a2 = a1a2
+    st0 = batch.solve(tol=1e-11)
+    st = batch.solve(tol=1e-11, precond=True, a1=a1, a2=a2)
+    j = 0
+    for k, ref in enumerate(refs):
+        for r in range(ref.shape[0]):
+            assert st[j]["status"] == 1, (k, r, st[j])
+            assert st[j]["rel_resid"] < 1e-11
+            assert relmax(batch.u[k][r].cpu().numpy(), ref[r]) < 1e-8, (k, r)
+            assert st[j]["action"] == pytest.approx(
+                float(np.sum(systems[k][2][r].cpu().numpy() * ref[r])), rel=1e-10)
+            j += 1
+    it0 = sum(v["iters"] for v in st0)
+    it1 = sum(v["iters"] for v in st)
+    print(f"batched iterations without / with the preconditioner: {it0} / {it1}")
+    assert it1 < it0
+    # replay of the same graph: bit-identical
+    u0 = [u.clone() for u in batch.u]
+    st2 = batch.solve(tol=1e-11, precond=True, a1=a1, a2=a2)
+    for a, b_ in zip(u0, batch.u):
+        assert torch.equal(a, b_)
+    assert [v["iters"] for v in st] == [v["iters"] for v in st2]
+
+
+def test_batched_preconditioned_c4_subset_against_single_solver():
+    """c4 systems (Ltau = 100, the 10 x 5 split) with 2 Gaussian and 2 Rademacher
+    right-hand sides each: the preconditioned batch against the single-system
+    preconditioned solver (same Chebyshev tables), and its iteration counts."""
+    from paper_2203_01291_amd.solver import FermionBatch
+    from workloads import batched_systems
+    p = get_config("c4")
+    Ls = batched_systems(p)[:5]
+    systems = []
+    for k, L in enumerate(Ls):
+        lat = OL.Lattice(L, p.Ltau, p.dtau, p.t, p.mu, p.alpha)
+        x = phonon_field(p, L=L, system=k)
+        phi = gaussian_rhs(p, 2, L=L, system=k)
+        xi = rademacher_rhs(p, 2, L=L, system=k)
+        s = make_solver(lat, max_rhs=4)
+        s.set_field(tgpu(x))
+        B = s.matvec(tgpu(np.concatenate([phi, xi])), "MT")
+        systems.append((lat, tgpu(x), B.contiguous(), s))
+    batch = FermionBatch([(a, b, c) for a, b, c, _ in systems])
+    st = batch.solve(tol=1e-10, precond=True)
+    assert all(v["status"] == 1 for v in st), st
+    j = 0
+    for k, (lat, x, B, s) in enumerate(systems):
+        s.set_field(x)
+        u, st1 = s.solve(B, tol=1e-10, precond=True, prec="f32_refined")
+        assert relmax(batch.u[k].cpu().numpy(), u.cpu().numpy()) < 1e-7
+        for r in range(4):
+            # same method, different summation orders: iteration counts within a few
+            assert abs(st[j]["iters"] - st1[r]["iters"]) <= max(5, st1[r]["iters"] // 10), (st[j], st1[r])
+            j += 1
+
+
 def test_batched_matches_single_solver_on_c4_subset():
     """c4-style systems (L in {8..24}, Ltau = 100, Gaussian and Rademacher
     right-hand sides): the batched path agrees with pcg_solve."""
