@@ -69,8 +69,11 @@ def parse():
                     help="with --ssh-only: also time one HMC trajectory on the SSH operator (paper "
                          "settings, FP64 preconditioned solves; about 10 s)")
     ap.add_argument("--profile-roofline", action="store_true",
-                    help="only the roofline kernel (M^T M, FP32, L=64 Ltau=400 x 32 rhs) and a "
-                         "plain copy of the same byte count, for hardware-counter runs")
+                    help="only the roofline kernel (M^T M at L=64 Ltau=400: FP64 x 40 rhs, FP32 x "
+                         "80 rhs) and a plain copy of the FP64 byte count, for hardware-counter runs")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="only two steps (the first one a warm-up) of the workload's timed step, "
+                         "for kernel traces and hardware-counter runs")
     return ap.parse_args()
 
 
@@ -558,7 +561,13 @@ def blas_threads():
 # WRITE_SIZE runs of `bench.py --profile-roofline`, each scaled by the same
 # counter read for a copy kernel of known size.  Valid only while the
 # kernel sources hash to `source_sha1`; otherwise reported as null.
-TRAFFIC = None  # taken again after the kernel sources changed
+# FETCH_SIZE scale 518400 / 259212.55 = 1.99990 (a copy of 518 400 KiB reads
+# that much), WRITE_SIZE scale 1.0; bytes per launch = (FETCH * 1.99990 +
+# WRITE) KiB * 1024, means over 10 launches.
+TRAFFIC = {"f64_bytes_per_launch": 1098381164, "f32_bytes_per_launch": 1097980338,
+           "fetch_scale": 1.99990, "write_scale": 1.0,
+           "source_sha1": "4d26e80131a6ee1d629eb4ce959dd801ec254b23",
+           "profile": "profiles/mtm_L64_Ltau400_roofline_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
 
@@ -754,6 +763,30 @@ def profile_roofline(torch, dev):
                       "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
 
 
+def profile_step(torch, dev, p, a1, a2):
+    """For kernel traces and counter runs: two steps of the timed path
+    (set-field + FP32-refined PCG to 1e-8 + S_F + force, one right-hand
+    side), the first one a warm-up."""
+    from paper_2203_01291_amd.solver import FermionSolver
+    from workloads import gaussian_rhs, perturbed_field, phonon_field
+    s = FermionSolver.from_params(p, max_rhs=1)
+    x0 = torch.from_numpy(phonon_field(p)).to(dev)
+    x = torch.from_numpy(perturbed_field(p, phonon_field(p))).to(dev)
+    s.set_field(x0)
+    Phi = s.matvec(torch.from_numpy(gaussian_rhs(p, 1)).to(dev), "MT")
+    out = []
+    for _ in range(2):
+        s.set_field(x, a1=a1, a2=a2)
+        u, st = s.solve(Phi, tol=1e-8, prec="f32_refined", precond=True)
+        s.action(Phi, u)
+        s.force(u)
+        torch.cuda.synchronize()
+        out.append({"iters": st[0]["iters"], "status": st[0]["status"],
+                    "rel_resid": st[0]["rel_resid"]})
+    print(json.dumps({"workload": p.name, "steps": out}), flush=True)
+    s.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -764,6 +797,10 @@ def main():
 
     if args.profile_roofline:
         profile_roofline(torch, torch.device("cuda:0"))
+        return
+    if args.profile_step:
+        from workloads import get_config as _gc
+        profile_step(torch, torch.device("cuda:0"), _gc(args.workload), args.a1, args.a2)
         return
     if args.meas_only:
         from workloads import get_config as _gc
