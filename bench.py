@@ -20,6 +20,7 @@ measurements, and the CPU oracle timed on a bounded sample.
 """
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -561,12 +562,12 @@ def blas_threads():
 # WRITE_SIZE runs of `bench.py --profile-roofline`, each scaled by the same
 # counter read for a copy kernel of known size.  Valid only while the
 # kernel sources hash to `source_sha1`; otherwise reported as null.
-# FETCH_SIZE scale 518400 / 259212.55 = 1.99990 (a copy of 518 400 KiB reads
+# FETCH_SIZE scale 518400 / 259212.56 = 1.99990 (a copy of 518 400 KiB reads
 # that much), WRITE_SIZE scale 1.0; bytes per launch = (FETCH * 1.99990 +
 # WRITE) KiB * 1024, means over 10 launches.
-TRAFFIC = {"f64_bytes_per_launch": 1098381164, "f32_bytes_per_launch": 1097980338,
+TRAFFIC = {"f64_bytes_per_launch": 1091031502, "f32_bytes_per_launch": 1088264394,
            "fetch_scale": 1.99990, "write_scale": 1.0,
-           "source_sha1": "4d26e80131a6ee1d629eb4ce959dd801ec254b23",
+           "source_sha1": "9e5cc689dc12fd0292f9393830d726aeb0ae4b38",
            "profile": "profiles/mtm_L64_Ltau400_roofline_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
@@ -730,6 +731,57 @@ def bench_graph_step(torch, dev, p, a1, a2, log, replays=3):
     return res
 
 
+# Workgroups of the block-contiguous copies: the grids of the FP64 (40 rhs x
+# 6 chunks) and FP32 (80 rhs x 6 chunks) roofline applies.
+CEILING_BLOCKS = (240, 480)
+
+
+def hbm_ceilings(torch, dev, nbytes):
+    """Bandwidth of copies moving `nbytes` (half read, half written): the
+    runtime's own copy, and fph_hbm_copy with every workgroup sweeping one
+    window (the best pattern for HBM) and with each workgroup copying its own
+    contiguous part (the operator's pattern), at the operator's grids.
+    Median over 5 groups of 10 launches, HIP events on the launch stream."""
+    from paper_2203_01291_amd import _lib
+    lib = _lib.load()
+    src = torch.empty(nbytes // 8, dtype=torch.float32, device=dev).normal_()
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    half = src.numel() * 4
+
+    def fph_copy(pattern, nblocks):
+        def f():
+            rc = lib.fph_hbm_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  half, nblocks, pattern, sp)
+            if rc != 0:
+                raise RuntimeError(f"fph_hbm_copy: {lib.fph_strerror(rc).decode()}")
+        return f
+
+    def timed(f):
+        f()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                f()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 10 * 1e-3)
+        t = sorted(ts)[2]
+        return {"us": t * 1e6, "GB/s": nbytes / t / 1e9, "frac": nbytes / t / 1e9 / HBM_PEAK_GBS}
+
+    out = {"bytes": nbytes, "runtime_copy": timed(lambda: dst.copy_(src)),
+           "window_copy": timed(fph_copy(0, 0))}
+    for g in CEILING_BLOCKS:
+        out[f"block_copy_{g}wg"] = timed(fph_copy(1, g))
+    if not torch.equal(src, dst):
+        raise RuntimeError("fph_hbm_copy: copy differs from its source")
+    del src, dst
+    return out
+
+
 def p_key(p):
     from workloads import CONFIGS
     return next(k for k, v in CONFIGS.items() if v.name == p.name)
@@ -737,8 +789,9 @@ def p_key(p):
 
 def profile_roofline(torch, dev):
     """For hardware-counter runs: 10 FP64 applies (ROOF_R64 rhs), 10 FP32
-    applies (ROOF_R32 rhs) of the roofline kernel, then 10 plain copies of
-    the FP64 apply's byte count (the reference for the counter scale)."""
+    applies (ROOF_R32 rhs) of the roofline kernel, then 10 runtime copies of
+    the FP64 apply's byte count (the reference for the counter scale) and 10
+    of each of the library's copy patterns on the same buffers."""
     p5, R5, s5, vl = large_matvec_setup(torch, dev)
     v64 = vl[:ROOF_R64].contiguous()
     out = torch.empty_like(v64)
@@ -757,6 +810,16 @@ def profile_roofline(torch, dev):
     dst = torch.empty_like(src)
     for _ in range(10):
         dst.copy_(src)
+    # the library's copies of the same buffer: one window, then block-contiguous
+    from paper_2203_01291_amd import _lib
+    lib = _lib.load()
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for pattern, nblocks in [(0, 0)] + [(1, g) for g in CEILING_BLOCKS]:
+        for _ in range(10):
+            rc = lib.fph_hbm_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                  src.numel() * 4, nblocks, pattern, sp)
+            if rc != 0:
+                raise RuntimeError(f"fph_hbm_copy: {lib.fph_strerror(rc).decode()}")
     torch.cuda.synchronize()
     print(json.dumps({"mtm_f64_launches": 10, "mtm_f64_bytes": nbytes64, "mtm_f32_launches": 10,
                       "mtm_f32_bytes": nbytes32, "copy_launches": 10,
@@ -965,22 +1028,10 @@ def main():
         tl32_iso = event_time_matvec(s5, vl32, "MTM", 20, torch, isolated=True)
         bl64 = (2 * ROOF_R64 + 1) * p5.dim * 8
         bl32 = (2 * R5 + 1) * p5.dim * 4
-        src = torch.empty(bl64 // 8, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        stream = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(10):
-            dst.copy_(src)
-        e1.record(stream)
-        e1.synchronize()
-        t_copy = e0.elapsed_time(e1) / 10 * 1e-3
-        del src, dst
+        ceil = hbm_ceilings(torch, dev, bl64)
         large = {
             "workload": f"{p5.name}: {R5} rhs (FP32), {ROOF_R64} rhs (FP64) sharing one field",
-            "copy_kernel": {"bytes": bl64, "us": t_copy * 1e6, "GB/s": bl64 / t_copy / 1e9,
-                            "frac": bl64 / t_copy / 1e9 / HBM_PEAK_GBS},
+            "copy_ceilings": ceil,
             "working_set_MB": {"f64": bl64 / 1e6, "f32": bl32 / 1e6},
             "mall_MB": 256, "working_set_over_mall": {"f64": bl64 / 256e6, "f32": bl32 / 256e6},
             "f64": {"us": tl64 * 1e6, "GB/s": bl64 / tl64 / 1e9, "frac": bl64 / tl64 / 1e9 / HBM_PEAK_GBS},
@@ -1030,7 +1081,8 @@ def main():
                             "bytes_per_launch": large["working_set_MB"]["f32"] * 1e6,
                             "avg_launch_us": large["f32"]["us"],
                             "traffic": TRAFFIC["f32_bytes_per_launch"] if valid else None},
-                    "copy_kernel_frac": large["copy_kernel"]["frac"],
+                    "ceilings": {k: v["frac"] for k, v in large["copy_ceilings"].items() if k != "bytes"},
+                    "frac_of_window_copy": large["f64"]["frac"] / large["copy_ceilings"]["window_copy"]["frac"],
                     "profile": TRAFFIC["profile"] if TRAFFIC else None}
     else:
         roofline = {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",

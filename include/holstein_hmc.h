@@ -663,6 +663,23 @@ int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, 
  * the context. */
 int fph_hmc_create_ssh(fph_hmc_t* hh, fph_ssh_t ssh, const fph_hmc_opts_t* opts, void* stream);
 
+/* ---------------------------------------------------------- measurement */
+
+/* Copies `bytes` from src_dev to dst_dev (device buffers, 16-byte aligned,
+ * not overlapping; bytes a multiple of 16) with one of two access
+ * patterns, to measure the HBM bandwidth the GPU sustains: the ceiling
+ * against which the fused operator's bandwidth is read.
+ *   pattern 0: every workgroup sweeps one common window of the buffer
+ *     (grid-stride; nontemporal loads and stores);
+ *   pattern 1: workgroup b copies its own contiguous 1/nblocks of the
+ *     buffer, as each workgroup of the operator streams its own chunk of
+ *     time slices.
+ * nblocks <= 0 means one workgroup per compute unit; at most 2^20.
+ * 512 threads per workgroup.  FPH_E_NULL, FPH_E_ALIGN or FPH_E_ARG for bad
+ * arguments; bytes = 0 does nothing.  Enqueue only. */
+int fph_hbm_copy(const void* src_dev, void* dst_dev, int64_t bytes, int32_t nblocks,
+                 int32_t pattern, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

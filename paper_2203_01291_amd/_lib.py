@@ -109,6 +109,8 @@ EXPORTS = {
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "ssh_force": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    "fph_hbm_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_void_p]),
     "fph_version": (ctypes.c_char_p, []),
     "fph_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fph_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Lattice), ctypes.c_int32]),

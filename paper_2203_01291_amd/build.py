@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("fph_lib.hip", "fph_hmc.hip", "fph_meas.hip",
-                                                    "fph_ssh.hip")]
+                                                    "fph_ssh.hip", "fph_stream.hip")]
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libholstein_hmc.so")
 

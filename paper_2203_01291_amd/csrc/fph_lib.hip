@@ -162,11 +162,18 @@ inline int resident_slots(const void* kern, int nt, size_t lds) {
 // slots) rounds of resident workgroups.  Pick the chunk length with the
 // least rounds x steps (short chunks for small problems: one round of
 // one-slice chunks; for large ones exactly enough chunks to fill the
-// resident slots, which also keeps halo re-reads low).
+// resident slots, which also keeps halo re-reads low).  Chunks may span
+// the whole time axis.  Memoised: the solver asks once per launch.
 int pick_chunk(const Geom& g, int nrhs, int S, int slots) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int> cache;
+  const auto key = std::make_tuple(g.Ltau, nrhs, S, slots);
+  std::lock_guard<std::mutex> lk(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
   int best = 1;
   long best_cost = -1;
-  for (int T = 1; T <= std::min(g.Ltau, 64); ++T) {
+  for (int T = 1; T <= g.Ltau; ++T) {
     const long nblk = (long)(((g.Ltau + T - 1) / T + S - 1) / S) * nrhs;
     const long rounds = (nblk + slots - 1) / slots;
     const long cost = rounds * (T + 3);
@@ -175,6 +182,7 @@ int pick_chunk(const Geom& g, int nrhs, int S, int slots) {
       best = T;
     }
   }
+  cache[key] = best;
   return best;
 }
 

@@ -55,6 +55,15 @@ def test_argument_errors_are_reported_on_the_host():
     assert lib.pcg_solve_sync(None, 1, None, None, None, None, None) == -1
     assert lib.fermion_force(None, 1, None, None, 1.0, None, None) == -1
     assert b"NULL" in lib.fph_strerror(-1)
+    # the bandwidth copy checks pointers, alignment, size and pattern first
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)
+    assert lib.fph_hbm_copy(None, b, 16, 0, 0, None) == -1
+    assert lib.fph_hbm_copy(ctypes.c_void_p((1 << 20) + 8), b, 16, 0, 0, None) == -6
+    assert lib.fph_hbm_copy(a, b, 24, 0, 0, None) == -7
+    assert lib.fph_hbm_copy(a, b, -16, 0, 0, None) == -7
+    assert lib.fph_hbm_copy(a, b, 16, 0, 2, None) == -7
+    assert lib.fph_hbm_copy(a, b, 16, (1 << 20) + 1, 1, None) == -7
+    assert lib.fph_hbm_copy(a, b, 0, 0, 0, None) == 0
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
