@@ -391,8 +391,9 @@ def bench_ssh(torch, dev, p, g, a1, a2, log, hmc=False):
     """SSH-type coupling (x in the bond hoppings) on the workload's lattice and
     field: the M and M^T kernels timed with events (one and eight right-hand
     sides), and one step of set-field + FP64 CG to 1e-8 (no preconditioner)
-    + S_F + force, and the same step preconditioned with the Holstein adiabatic
-    preconditioner of the field (uniform hopping)."""
+    + S_F + force, the same step preconditioned with the Holstein adiabatic
+    preconditioner of the field (uniform hopping), in FP64 and FP32-refined,
+    and the preconditioned step with eight right-hand sides in both."""
     from paper_2203_01291_amd.solver import FermionSolver
     from paper_2203_01291_amd.ssh import SSHSolver
     from workloads import gaussian_rhs, phonon_field
@@ -436,17 +437,25 @@ def bench_ssh(torch, dev, p, g, a1, a2, log, hmc=False):
     grad = s.force(u)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    fs = FermionSolver.from_params(p, max_rhs=1)
+    fs = FermionSolver.from_params(p, max_rhs=nr)
     s.attach_preconditioner(fs, a1=a1, a2=a2)
-    s.set_field(x)
-    s.solve(b, tol=1e-8, chunk=32, precond=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.set_field(x)
-    up, stp = s.solve(b, tol=1e-8, chunk=32, precond=True)
-    gradp = s.force(up)
-    torch.cuda.synchronize()
-    dtp = time.perf_counter() - t0
+
+    def pc_step(bv, prec):
+        s.set_field(x)
+        s.solve(bv, tol=1e-8, chunk=32, precond=True, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_field(x)
+        uu, ss = s.solve(bv, tol=1e-8, chunk=32, precond=True, prec=prec)
+        gg = s.force(uu)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, uu, ss, gg
+
+    dtp, up, stp, gradp = pc_step(b, "f64")
+    dtr, ur, str_, gradr = pc_step(b, "f32_refined")
+    b8 = s.matvec(v, "MT")
+    dt8, u8, st8, _ = pc_step(b8, "f64")
+    dt8r, u8r, st8r, _ = pc_step(b8, "f32_refined")
     res = {
         "workload": f"{p.name}: SSH coupling g={g} (t_b = t - g (x_j - x_i)) with the Holstein on-site "
                     f"factor, FP64 CG to 1e-8 without preconditioner, S_F and force",
@@ -458,6 +467,20 @@ def bench_ssh(torch, dev, p, g, a1, a2, log, hmc=False):
                            "us_per_iteration": dtp * 1e6 / max(1, stp[0]["iters"]),
                            "grad_rel_diff": float((gradp - grad).norm() / grad.norm()),
                            "a1_a2": [a1, a2]},
+        "preconditioned_f32_refined": {
+            "ms_per_step": dtr * 1e3, "iters": str_[0]["iters"], "fp64_evaluations": str_[0]["outer_iters"],
+            "rel_resid": str_[0]["rel_resid"], "status": str_[0]["status"],
+            "speedup_vs_fp64": dtp / dtr,
+            "u_rel_diff_vs_fp64": float((ur - up).abs().max() / up.abs().max()),
+            "grad_rel_diff_vs_fp64": float((gradr - gradp).norm() / gradp.norm())},
+        "preconditioned_rhs8": {
+            "f64": {"ms_per_step": dt8 * 1e3, "solves_per_s": nr / dt8, "iters": [q["iters"] for q in st8],
+                    "status": [q["status"] for q in st8]},
+            "f32_refined": {"ms_per_step": dt8r * 1e3, "solves_per_s": nr / dt8r,
+                            "iters": [q["iters"] for q in st8r], "status": [q["status"] for q in st8r],
+                            "fp64_evaluations": [q["outer_iters"] for q in st8r]},
+            "speedup_fp32_refined": dt8 / dt8r,
+            "u_rel_diff": float((u8r - u8).abs().max() / u8.abs().max())},
     }
     if hmc:
         from paper_2203_01291_amd.hmc import PhononHMC

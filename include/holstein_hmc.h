@@ -626,14 +626,23 @@ int ssh_matvec(fph_ssh_t c, int32_t op, int32_t nrhs, const double* in_dev, doub
  * share one h (or on h itself) must not overlap.  Host only. */
 int ssh_set_preconditioner(fph_ssh_t c, fph_handle_t h, double a1, double a2);
 
-/* (P)CG on (M^T M) u = b in FP64 (Sec. II D, Eq. CG; Eq. CG_precon with
+/* (P)CG on (M^T M) u = b (Sec. II D, Eq. CG; Eq. CG_precon with
  * z = F F^T r from the attached Holstein handle when opts->use_precond is 1,
  * FPH_E_ARG if none is attached; FPH_E_NRHS above that handle's max_rhs).
- * opts->prec must be FPH_F64 (FPH_E_PREC otherwise); opts->chunk iterations
- * (0 -> 64) are enqueued between host checks.  Each right-hand side stops on
- * its own at |r| < tol |b| (recursive residual); stats_host (nrhs entries,
- * may be NULL) then hold the iterations, the FP64 true relative residual and
- * S_F = b . u.  Blocks until done. */
+ * opts->prec FPH_F64: FP64 CG; each right-hand side stops on its own at
+ * |r| < tol |b| (recursive residual).  FPH_F32_REFINED: FP32 CG (the bond
+ * and field tables rounded to FP32) on a correction, with reliable updates
+ * of the residual: when a right-hand side's FP32 residual has fallen by
+ * opts->ru_delta (0 -> 0.1 with the preconditioner, 0.3 without; at most
+ * 0.5) since the last FP64 evaluation, or its FP32 iteration stops, the
+ * correction joins the FP64 iterate and the FP64 residual b - M^T M u is
+ * evaluated; the right-hand side finishes when that residual is below
+ * tol |b|, after opts->max_outer evaluations (0 -> 32) or maxiter FP32
+ * iterations (FPH_ST_MAXITER).  Other precisions: FPH_E_PREC.
+ * opts->chunk iterations (0 -> 64) are enqueued between host checks.
+ * stats_host (nrhs entries, may be NULL) hold the iterations, the FP64
+ * evaluations after the first (outer_iters), the FP64 true relative
+ * residual and S_F = b . u.  Blocks until done. */
 int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev,
               const fph_pcg_opts_t* opts, fph_pcg_stats_t* stats_host, void* stream);
 
@@ -656,8 +665,9 @@ int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, 
  * ssh: trajectories (hmc_trajectory) and global updates (hmc_global_update)
  * with the action S' = S_B - dtau alpha sum x + 1/2 sum_sigma Phi_sigma .
  * (M^T M)^{-1} Phi_sigma, M the SSH-type matrix, Phi_sigma = M(x_i)^T R_sigma.
- * Solves go through ssh_solve: both solve options must be FPH_F64
- * (FPH_E_PREC), use_precond needs an attached preconditioner.
+ * Solves go through ssh_solve: both solve options must be FPH_F64 or
+ * FPH_F32_REFINED (FPH_E_PREC), use_precond needs an attached
+ * preconditioner.
  * lambda_action and nchains > 1 are refused (FPH_E_ARG): Lambda belongs to
  * the Holstein coupling and the SSH context has one field.  ssh must outlive
  * the context. */

@@ -558,7 +558,8 @@ int fph_hmc_create_ssh(fph_hmc_t* out, fph_ssh_t ssh, const fph_hmc_opts_t* o, v
   int32_t max_rhs = 0;
   HMC_CALL(fph::ssh_info(ssh, &lat, &max_rhs, nullptr));
   if (o->lambda_action != 0 || o->nchains > 1) return FPH_E_ARG;
-  if (o->force_solve.prec != FPH_F64 || o->action_solve.prec != FPH_F64) return FPH_E_PREC;
+  auto ssh_prec = [](int32_t p) { return p == FPH_F64 || p == FPH_F32_REFINED; };
+  if (!ssh_prec(o->force_solve.prec) || !ssh_prec(o->action_solve.prec)) return FPH_E_PREC;
   return create_impl(out, nullptr, ssh, lat, max_rhs, o, stream);
 }
 

@@ -11,9 +11,12 @@
 // every thread owns the same BPT bonds of each family.  Setting the field
 // forms per-slice tables of the bond coefficients (cosh, sinh) and of E (one
 // expm1 per bond), which the operator kernels load into registers; the force
-// kernel forms them from x_tau in LDS.  FP64 throughout.
+// kernel forms them from x_tau in LDS.  The operator and CG kernels take the
+// vector type as a parameter: FP64, or FP32 with the tables rounded to FP32
+// for the iterations of the FP32-refined solve (partial sums in FP64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -81,8 +84,10 @@ __device__ __forceinline__ void apply_family(const SshGeom& G, const double* xs,
 }
 
 // Per right-hand side CG state: rr = |r|^2, rz = r.z, bb = |b|^2, alpha, beta, iters, status.
+// FP32-refined solves also stop (pause) the iteration once |r|^2 <= delta2 rr_ref,
+// rr_ref the FP64 |r|^2 of the last evaluation (delta2 = 0 otherwise).
 struct CgState {
-  double rr, rz, bb, alpha, beta, tol2;
+  double rr, rz, bb, alpha, beta, tol2, rr_ref, delta2;
   int iters, status, done, maxiter;
 };
 
@@ -121,8 +126,8 @@ __device__ void cg_step2(CgState& S, double v, double vz) {
     return;
   }
   S.rr = v;
-  if (v <= S.tol2 * S.bb || S.iters >= S.maxiter) {
-    S.done = 1;
+  if (v <= S.tol2 * S.bb || v <= S.delta2 * S.rr_ref || S.iters >= S.maxiter) {
+    S.done = 1;  // rz keeps the last step's r.z
     return;
   }
   if (!(vz > 0.0)) {
@@ -145,9 +150,11 @@ __device__ __forceinline__ double e_site(const SshGeom& G, double x) {
 // Per-slice tables of the field, formed once per field (one workgroup per
 // slice): hop[tau][f][k] = (cosh, sinh)(dtau t_b) for bond k of family f,
 // Et[tau][i] = E_{tau,i}.  The operator kernels then start their slice with
-// plain loads instead of a chain of expm1 between the LDS passes.
+// plain loads instead of a chain of expm1 between the LDS passes.  hop32
+// and Et32 receive the same tables rounded to FP32.
 __global__ void __launch_bounds__(kNT) k_ssh_tables(SshGeom G, const double* __restrict__ x,
-                                                    double2* __restrict__ hop, double* __restrict__ Et) {
+                                                    double2* __restrict__ hop, double* __restrict__ Et,
+                                                    float2* __restrict__ hop32, float* __restrict__ Et32) {
   extern __shared__ double sm[];
   double* xs = sm;
   const int tau = blockIdx.x;
@@ -155,11 +162,14 @@ __global__ void __launch_bounds__(kNT) k_ssh_tables(SshGeom G, const double* __r
   for (int i = threadIdx.x; i < G.N; i += kNT) {
     const double xv = xt[i];
     xs[i] = xv;
-    Et[(long)tau * G.N + i] = e_site(G, xv);
+    const double e = e_site(G, xv);
+    Et[(long)tau * G.N + i] = e;
+    Et32[(long)tau * G.N + i] = (float)e;
   }
   __syncthreads();
   const int nb = G.N >> 1;
   double2* ht = hop + (long)tau * 2 * G.N;
+  float2* ht32 = hop32 + (long)tau * 2 * G.N;
   for (int f = 0; f < 4; ++f)
     for (int k = threadIdx.x; k < nb; k += kNT) {
       int i, j;
@@ -167,13 +177,20 @@ __global__ void __launch_bounds__(kNT) k_ssh_tables(SshGeom G, const double* __r
       double ch, sh;
       bond_cs(G, xs, i, j, ch, sh);
       ht[f * nb + k] = make_double2(ch, sh);
+      ht32[f * nb + k] = make_float2((float)ch, (float)sh);
     }
 }
 
+// (cosh, sinh) pairs of the bond tables in the vector type T.
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
 // w <- F_f w with the thread's bond coefficients hc[q] = (cosh, sinh) of bond
 // threadIdx.x + q kNT of family f.
-template <int BPT>
-__device__ __forceinline__ void apply_family_t(const SshGeom& G, double* w, int f, const double2 (&hc)[BPT]) {
+template <typename T, int BPT>
+__device__ __forceinline__ void apply_family_t(const SshGeom& G, T* w, int f,
+                                               const typename Pair<T>::type (&hc)[BPT]) {
   const int nb = G.N >> 1;
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -181,7 +198,7 @@ __device__ __forceinline__ void apply_family_t(const SshGeom& G, double* w, int 
     if (k < nb) {
       int i, j;
       bond_sites(G.L, f, k, i, j);
-      const double wi = w[i], wj = w[j];
+      const T wi = w[i], wj = w[j];
       w[i] = hc[q].x * wi + hc[q].y * wj;
       w[j] = hc[q].y * wi + hc[q].x * wj;
     }
@@ -198,37 +215,41 @@ __device__ __forceinline__ void apply_family_t(const SshGeom& G, double* w, int 
 // only): the operand is the CG direction p = z + beta_r in, formed on the fly
 // from zv and the previous direction `in`; the workgroup stores its own slice
 // of p in pnew (a buffer other than `in`, so no workgroup reads a slice that
-// another one is rewriting).
-template <int OP, int BPT, bool PUPD>
-__global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __restrict__ hop,
-                                                   const double* __restrict__ Et,
-                                                   const double* __restrict__ in,
-                                                   double* __restrict__ out,
-                                                   const double* __restrict__ dotv,
+// another one is rewriting); a right-hand side whose state says done is
+// skipped (its direction stays where it was last written).
+template <typename T, int OP, int BPT, bool PUPD>
+__global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const typename Pair<T>::type* __restrict__ hop,
+                                                   const T* __restrict__ Et,
+                                                   const T* __restrict__ in,
+                                                   T* __restrict__ out,
+                                                   const T* __restrict__ dotv,
                                                    double* __restrict__ part,
-                                                   const double* __restrict__ zv,
+                                                   const T* __restrict__ zv,
                                                    const CgState* __restrict__ st,
-                                                   double* __restrict__ pnew) {
+                                                   T* __restrict__ pnew) {
+  using V2 = typename Pair<T>::type;
   extern __shared__ double sm[];
-  double* w = sm;
+  T* w = reinterpret_cast<T*>(sm);
+  // a stopped right-hand side keeps its direction (as in k_ssh_mtm)
+  if (PUPD && st[blockIdx.y].done) return;
   const int tau = blockIdx.x;
   const long ro = (long)blockIdx.y * G.d;
   const int ts = OP == 0 ? tau : (tau + 1 == G.Ltau ? 0 : tau + 1);  // slice of the field used
   const int tv = OP == 0 ? (tau == 0 ? G.Ltau - 1 : tau - 1) : ts;   // slice of v transported
   const int nb = G.N >> 1;
-  const double2* ht = hop + (long)ts * 2 * G.N;
-  const double* Es = Et + (long)ts * G.N;
-  double2 hc[4][BPT];
+  const V2* ht = hop + (long)ts * 2 * G.N;
+  const T* Es = Et + (long)ts * G.N;
+  V2 hc[4][BPT];
 #pragma unroll
   for (int f = 0; f < 4; ++f)
 #pragma unroll
     for (int q = 0; q < BPT; ++q) {
       const int k = threadIdx.x + q * kNT;
-      hc[f][q] = k < nb ? ht[f * nb + k] : make_double2(0.0, 0.0);
+      hc[f][q] = k < nb ? ht[f * nb + k] : V2{(T)0, (T)0};
     }
-  const double* vt = in + ro + (long)tv * G.N;
-  const double beta = PUPD ? st[blockIdx.y].beta : 0.0;
-  const double* zt = PUPD ? zv + ro + (long)tv * G.N : nullptr;
+  const T* vt = in + ro + (long)tv * G.N;
+  const T beta = PUPD ? (T)st[blockIdx.y].beta : (T)0;
+  const T* zt = PUPD ? zv + ro + (long)tv * G.N : nullptr;
   for (int i = threadIdx.x; i < G.N; i += kNT) {
     if (PUPD)
       w[i] = zt[i] + beta * vt[i];
@@ -239,32 +260,32 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __r
   if (OP == 0) {
 #pragma unroll
     for (int f = 3; f >= 0; --f) {
-      apply_family_t<BPT>(G, w, f, hc[f]);
+      apply_family_t<T, BPT>(G, w, f, hc[f]);
       __syncthreads();
     }
   } else {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      apply_family_t<BPT>(G, w, f, hc[f]);
+      apply_family_t<T, BPT>(G, w, f, hc[f]);
       __syncthreads();
     }
   }
-  const double s = (OP == 0 ? tau : ts) == 0 ? -1.0 : 1.0;
-  const double* vi = in + ro + (long)tau * G.N;
-  double* vo = out + ro + (long)tau * G.N;
+  const T s = (OP == 0 ? tau : ts) == 0 ? (T)-1 : (T)1;
+  const T* vi = in + ro + (long)tau * G.N;
+  T* vo = out + ro + (long)tau * G.N;
   double acc = 0.0;
-  const double* zi = PUPD ? zv + ro + (long)tau * G.N : nullptr;
-  double* pn = PUPD ? pnew + ro + (long)tau * G.N : nullptr;
+  const T* zi = PUPD ? zv + ro + (long)tau * G.N : nullptr;
+  T* pn = PUPD ? pnew + ro + (long)tau * G.N : nullptr;
   for (int i = threadIdx.x; i < G.N; i += kNT) {
-    const double bw = OP == 0 ? Es[i] * w[i] : w[i];
-    double v = vi[i];
+    const T bw = OP == 0 ? Es[i] * w[i] : w[i];
+    T v = vi[i];
     if (PUPD) {
       v = zi[i] + beta * v;
       pn[i] = v;
     }
-    const double o = v - s * bw;
+    const T o = v - s * bw;
     vo[i] = o;
-    if (dotv != nullptr) acc += dotv[ro + (long)tau * G.N + i] * o;
+    if (dotv != nullptr) acc += (double)dotv[ro + (long)tau * G.N + i] * (double)o;
   }
   if (dotv != nullptr) {
     const double v = block_sum(acc);
@@ -288,44 +309,45 @@ __global__ void __launch_bounds__(kNT) k_ssh_apply(SshGeom G, const double2* __r
 // st_new[r] (a second buffer: no workgroup reads what another one writes).
 // With from_state the state is taken as it is (first step of a chunk).  A
 // finished right-hand side is skipped.
-template <int BPT, bool PUPD>
-__global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __restrict__ hop,
-                                                 const double* __restrict__ Et,
-                                                 const double* __restrict__ in,
-                                                 double* __restrict__ out, bool dot,
+template <typename T, int BPT, bool PUPD>
+__global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const typename Pair<T>::type* __restrict__ hop,
+                                                 const T* __restrict__ Et,
+                                                 const T* __restrict__ in,
+                                                 T* __restrict__ out, bool dot,
                                                  double* __restrict__ part,
-                                                 const double* __restrict__ zv,
+                                                 const T* __restrict__ zv,
                                                  const CgState* __restrict__ st_old,
                                                  CgState* __restrict__ st_new,
                                                  const double* __restrict__ part_rr,
                                                  const double* __restrict__ part_rz, int nbz,
                                                  int from_state,
-                                                 double* __restrict__ pnew) {
+                                                 T* __restrict__ pnew) {
+  using V2 = typename Pair<T>::type;
   constexpr int kOwn = 2 * BPT;  // sites per thread: N <= 2 * BPT * kNT
   extern __shared__ double sm[];
-  double* wA = sm;
-  double* wB = sm + G.N;
+  T* wA = reinterpret_cast<T*>(sm);
+  T* wB = wA + G.N;
   const int tau = blockIdx.x;
   const long ro = (long)blockIdx.y * G.d;
   const int ta = tau == 0 ? G.Ltau - 1 : tau - 1;
   const int tc = tau + 1 == G.Ltau ? 0 : tau + 1;
-  const double sb = tau == 0 ? -1.0 : 1.0;
-  const double sc = tc == 0 ? -1.0 : 1.0;
+  const T sb = tau == 0 ? (T)-1 : (T)1;
+  const T sc = tc == 0 ? (T)-1 : (T)1;
   const int nb = G.N >> 1;
-  const double2* hb = hop + (long)tau * 2 * G.N;
-  const double2* hcp = hop + (long)tc * 2 * G.N;
-  double2 cB[4][BPT], cC[4][BPT];
+  const V2* hb = hop + (long)tau * 2 * G.N;
+  const V2* hcp = hop + (long)tc * 2 * G.N;
+  V2 cB[4][BPT], cC[4][BPT];
 #pragma unroll
   for (int f = 0; f < 4; ++f)
 #pragma unroll
     for (int q = 0; q < BPT; ++q) {
       const int k = threadIdx.x + q * kNT;
-      cB[f][q] = k < nb ? hb[f * nb + k] : make_double2(0.0, 0.0);
-      cC[f][q] = k < nb ? hcp[f * nb + k] : make_double2(0.0, 0.0);
+      cB[f][q] = k < nb ? hb[f * nb + k] : V2{(T)0, (T)0};
+      cC[f][q] = k < nb ? hcp[f * nb + k] : V2{(T)0, (T)0};
     }
-  const double* Eb = Et + (long)tau * G.N;
-  const double* Ec = Et + (long)tc * G.N;
-  double beta = 0.0;
+  const T* Eb = Et + (long)tau * G.N;
+  const T* Ec = Et + (long)tc * G.N;
+  T beta = (T)0;
   if (PUPD) {
     const int r = blockIdx.y;
     CgState S = st_old[r];
@@ -336,17 +358,17 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st_new[r] = S;
     if (S.done) return;
-    beta = S.beta;
+    beta = (T)S.beta;
   }
-  auto dir = [&](int t, int i) -> double {  // the direction p at slice t, site i
+  auto dir = [&](int t, int i) -> T {  // the direction p at slice t, site i
     const long o = ro + (long)t * G.N + i;
     return PUPD ? zv[o] + beta * in[o] : in[o];
   };
-  double pb[kOwn], pc[kOwn], yb[kOwn];
+  T pb[kOwn], pc[kOwn], yb[kOwn];
 #pragma unroll
   for (int m = 0; m < kOwn; ++m) {
     const int i = threadIdx.x + m * kNT;
-    pb[m] = pc[m] = 0.0;
+    pb[m] = pc[m] = (T)0;
     if (i < G.N) {
       wA[i] = dir(ta, i);
       pb[m] = dir(tau, i);
@@ -358,35 +380,35 @@ __global__ void __launch_bounds__(kNT) k_ssh_mtm(SshGeom G, const double2* __res
   __syncthreads();
 #pragma unroll
   for (int f = 3; f >= 0; --f) {
-    apply_family_t<BPT>(G, wA, f, cB[f]);
-    apply_family_t<BPT>(G, wB, f, cC[f]);
+    apply_family_t<T, BPT>(G, wA, f, cB[f]);
+    apply_family_t<T, BPT>(G, wB, f, cC[f]);
     __syncthreads();
   }
 #pragma unroll
   for (int m = 0; m < kOwn; ++m) {
     const int i = threadIdx.x + m * kNT;
-    yb[m] = 0.0;
+    yb[m] = (T)0;
     if (i < G.N) {
       yb[m] = pb[m] - sb * Eb[i] * wA[i];
-      const double e = Ec[i];
+      const T e = Ec[i];
       wB[i] = e * (pc[m] - sc * e * wB[i]);
     }
   }
   __syncthreads();
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    apply_family_t<BPT>(G, wB, f, cC[f]);
+    apply_family_t<T, BPT>(G, wB, f, cC[f]);
     __syncthreads();
   }
   double acc = 0.0;
-  double* vo = out + ro + (long)tau * G.N;
+  T* vo = out + ro + (long)tau * G.N;
 #pragma unroll
   for (int m = 0; m < kOwn; ++m) {
     const int i = threadIdx.x + m * kNT;
     if (i < G.N) {
-      const double q = yb[m] - sc * wB[i];
+      const T q = yb[m] - sc * wB[i];
       vo[i] = q;
-      acc += pb[m] * q;
+      acc += (double)pb[m] * (double)q;
     }
   }
   if (dot) {
@@ -480,15 +502,17 @@ __global__ void __launch_bounds__(kNT) k_ssh_force(SshGeom G, int nrhs, const do
 
 // ------------------------------------------------------------ CG on M^T M
 
-// part[r][b] = sum over block b's share of a_r . c_r
-__global__ void __launch_bounds__(256) k_dot_parts(long d, const double* __restrict__ a,
-                                                   const double* __restrict__ c,
+// part[r][b] = sum over block b's share of a_r . c_r (FP64 sums)
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot_parts(long d, const T* __restrict__ a,
+                                                   const T* __restrict__ c,
                                                    double* __restrict__ part) {
   const int r = blockIdx.y;
   a += (long)r * d;
   c += (long)r * d;
   double acc = 0.0;
-  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256) acc += a[k] * c[k];
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < d; k += (long)gridDim.x * 256)
+    acc += (double)a[k] * (double)c[k];
   const double v = block_sum(acc);
   if (threadIdx.x == 0) part[(long)r * gridDim.x + blockIdx.x] = v;
 }
@@ -531,10 +555,11 @@ __global__ void __launch_bounds__(256) k_cg_scalar(int stage, int nb, int nb2, c
 // records it), then u += alpha p, r -= alpha q, and part[k][block] = the
 // block's share of |r|^2 (grid: kXrBlocks x nrhs).  A finished right-hand
 // side is left alone; its partials are then stale and its scalars ignore them.
+template <typename T>
 __global__ void __launch_bounds__(256) k_cg_xr(long d, CgState* __restrict__ st, int npq,
                                                const double* __restrict__ part_pq,
-                                               const double* __restrict__ p, const double* __restrict__ q,
-                                               double* __restrict__ u, double* __restrict__ r,
+                                               const T* __restrict__ p, const T* __restrict__ q,
+                                               T* __restrict__ u, T* __restrict__ r,
                                                double* __restrict__ part) {
   const int k = blockIdx.y;
   // block 0 may set done below: read it once per block so the exit is uniform
@@ -554,13 +579,14 @@ __global__ void __launch_bounds__(256) k_cg_xr(long d, CgState* __restrict__ st,
   }
   const double a = st[k].rz / pq;
   if (lead) st[k].alpha = a;
+  const T at = (T)a;
   const long o = (long)k * d;
   double acc = 0.0;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < d; i += (long)gridDim.x * 256) {
-    u[o + i] += a * p[o + i];
-    const double rv = r[o + i] - a * q[o + i];
+    u[o + i] += at * p[o + i];
+    const T rv = r[o + i] - at * q[o + i];
     r[o + i] = rv;
-    acc += rv * rv;
+    acc += (double)rv * (double)rv;
   }
   const double v = block_sum(acc);
   if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = v;
@@ -576,6 +602,19 @@ __global__ void __launch_bounds__(256) k_sum_rhs(int nb, const double* __restric
 // r = b - r (r holds M^T M u on entry)
 __global__ void __launch_bounds__(256) k_sub_from(long n, const double* __restrict__ b, double* __restrict__ r) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) r[i] = b[i] - r[i];
+}
+
+// dst = (float) src
+__global__ void __launch_bounds__(256) k_to_f32(long n, const double* __restrict__ src, float* __restrict__ dst) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) dst[i] = (float)src[i];
+}
+
+// u += (double) e, e = 0: the FP32 correction moved into the FP64 iterate
+__global__ void __launch_bounds__(256) k_fold_f32(long n, double* __restrict__ u, float* __restrict__ e) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    u[i] += (double)e[i];
+    e[i] = 0.0f;
+  }
 }
 
 int grid_for(long n) {
@@ -604,6 +643,16 @@ struct fph_ssh_s {
   CgState* st;   // [2][max_rhs]: the fused CG alternates between the two
   double* part3; // p.q partials of the fused CG
   CgState* st_host;
+  // FP32-refined solves: the tables rounded to FP32 and the FP32 vectors
+  float2* hop32;  // [Ltau][4][N/2]
+  float* Et32;    // [Ltau][N]
+  float* r32;     // FP32 residual
+  float* z32;     // preconditioned residual
+  float* pa32;    // directions (two buffers, as p / p2)
+  float* pb32;
+  float* q32;     // M^T M p
+  float* tmp32;   // M p (unfused operator)
+  float* u32;     // the correction since the last residual replacement
   fph_handle_t pc;  // Holstein handle whose preconditioner serves the solves (or NULL)
   int pc_max_rhs;
   double pc_a1, pc_a2;  // its Chebyshev-order constants (fph_set_field)
@@ -627,21 +676,34 @@ hipError_t allow_lds(K kern, size_t bytes) {
   return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// The field's tables and the operator workspace in the vector type T.
+template <typename T> struct Tabs;
+template <> struct Tabs<double> {
+  static const double2* hop(const fph_ssh_s* c) { return c->hop; }
+  static const double* Et(const fph_ssh_s* c) { return c->Et; }
+  static double* tmp(const fph_ssh_s* c) { return c->tmp; }
+};
+template <> struct Tabs<float> {
+  static const float2* hop(const fph_ssh_s* c) { return c->hop32; }
+  static const float* Et(const fph_ssh_s* c) { return c->Et32; }
+  static float* tmp(const fph_ssh_s* c) { return c->tmp32; }
+};
+
 // PUPD launches (OP 0 only) take zv, the state and pnew as described at the kernel.
-template <int OP, bool PUPD = false>
-hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s,
-                           const double* dotv = nullptr, const double* zv = nullptr,
-                           double* pnew = nullptr, double* pt = nullptr) {
+template <typename T, int OP, bool PUPD = false>
+hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const T* in, T* out, hipStream_t s,
+                           const T* dotv = nullptr, const T* zv = nullptr,
+                           T* pnew = nullptr, double* pt = nullptr) {
   const dim3 grid(c->G.Ltau, nrhs);
   const size_t lds = apply_lds(c);
   const CgState* st = c->st;
   if (c->bpt == 8) {
-    hipError_t e = allow_lds(k_ssh_apply<OP, 8, PUPD>, lds);
+    hipError_t e = allow_lds(k_ssh_apply<T, OP, 8, PUPD>, lds);
     if (e != hipSuccess) return e;
   }
 #define SSH_APPLY_CASE(b)                                                                      \
-  hipLaunchKernelGGL((k_ssh_apply<OP, b, PUPD>), grid, dim3(kNT), lds, s, c->G,                  \
-                     (const double2*)c->hop, (const double*)c->Et, in, out, dotv, pt, zv, st, pnew)
+  hipLaunchKernelGGL((k_ssh_apply<T, OP, b, PUPD>), grid, dim3(kNT), lds, s, c->G,               \
+                     Tabs<T>::hop(c), Tabs<T>::Et(c), in, out, dotv, pt, zv, st, pnew)
   switch (c->bpt) {
     case 1: SSH_APPLY_CASE(1); break;
     case 2: SSH_APPLY_CASE(2); break;
@@ -657,9 +719,10 @@ hipError_t launch_apply_op(const fph_ssh_s* c, int nrhs, const double* in, doubl
 bool mtm_fusable(const fph_ssh_s* c) { return c->bpt <= 4; }
 
 // CG arguments of a fused launch (see k_ssh_mtm).
+template <typename T>
 struct MtmCg {
-  const double* zv = nullptr;
-  double* pnew = nullptr;
+  const T* zv = nullptr;
+  T* pnew = nullptr;
   const CgState* st_old = nullptr;
   CgState* st_new = nullptr;
   const double* part_rr = nullptr;
@@ -670,15 +733,15 @@ struct MtmCg {
 
 // q = M^T M p in one launch (only where mtm_fusable).  With dot,
 // pt[r * Ltau + tau] = p . q.
-template <bool PUPD>
-hipError_t launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, double* out, hipStream_t s,
-                            bool dot, double* pt, const MtmCg& a) {
+template <typename T, bool PUPD>
+hipError_t launch_mtm_fused(const fph_ssh_s* c, int nrhs, const T* in, T* out, hipStream_t s,
+                            bool dot, double* pt, const MtmCg<T>& a) {
   const dim3 grid(c->G.Ltau, nrhs);
-  const size_t lds = 2 * (size_t)c->G.N * sizeof(double);
-  const double2* hop = c->hop;
-  const double* Et = c->Et;
-#define SSH_MTM_CASE(b)                                                                                 \
-  hipLaunchKernelGGL((k_ssh_mtm<b, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, a.zv, \
+  const size_t lds = 2 * (size_t)c->G.N * sizeof(T);
+  const auto* hop = Tabs<T>::hop(c);
+  const T* Et = Tabs<T>::Et(c);
+#define SSH_MTM_CASE(b)                                                                                    \
+  hipLaunchKernelGGL((k_ssh_mtm<T, b, PUPD>), grid, dim3(kNT), lds, s, c->G, hop, Et, in, out, dot, pt, a.zv, \
                      a.st_old, a.st_new, a.part_rr, a.part_rz, a.nbz, a.from_state, a.pnew)
   switch (c->bpt) {
     case 1: SSH_MTM_CASE(1); break;
@@ -689,16 +752,19 @@ hipError_t launch_mtm_fused(const fph_ssh_s* c, int nrhs, const double* in, doub
   return hipGetLastError();
 }
 
-// out = op(in); MTM goes through c->tmp (so in/out must not be c->tmp).  With
-// dotv (MTM only), c->part[r * Ltau + tau] receive the slices of dotv . out.
-hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const double* in, double* out, hipStream_t s,
-                        const double* dotv = nullptr) {
-  if (op == FPH_OP_M) return launch_apply_op<0>(c, nrhs, in, out, s);
-  if (op == FPH_OP_MT) return launch_apply_op<1>(c, nrhs, in, out, s);
-  if (dotv == nullptr && mtm_fusable(c)) return launch_mtm_fused<false>(c, nrhs, in, out, s, false, nullptr, MtmCg{});
-  hipError_t e = launch_apply_op<0>(c, nrhs, in, c->tmp, s);
+// out = op(in); MTM goes through the workspace of type T (so in/out must not
+// be it).  With dotv (MTM only), c->part[r * Ltau + tau] receive the slices
+// of dotv . out.
+template <typename T>
+hipError_t launch_apply(const fph_ssh_s* c, int op, int nrhs, const T* in, T* out, hipStream_t s,
+                        const T* dotv = nullptr) {
+  if (op == FPH_OP_M) return launch_apply_op<T, 0>(c, nrhs, in, out, s);
+  if (op == FPH_OP_MT) return launch_apply_op<T, 1>(c, nrhs, in, out, s);
+  if (dotv == nullptr && mtm_fusable(c))
+    return launch_mtm_fused<T, false>(c, nrhs, in, out, s, false, nullptr, MtmCg<T>{});
+  hipError_t e = launch_apply_op<T, 0>(c, nrhs, in, Tabs<T>::tmp(c), s);
   if (e != hipSuccess) return e;
-  return launch_apply_op<1>(c, nrhs, c->tmp, out, s, dotv);
+  return launch_apply_op<T, 1>(c, nrhs, Tabs<T>::tmp(c), out, s, dotv);
 }
 
 hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const double* y, double scale,
@@ -718,11 +784,242 @@ hipError_t launch_force(const fph_ssh_s* c, int nrhs, const double* u, const dou
   return hipGetLastError();
 }
 
-hipError_t dots(const fph_ssh_s* c, int nrhs, const double* a, const double* b, hipStream_t s,
+template <typename T>
+hipError_t dots(const fph_ssh_s* c, int nrhs, const T* a, const T* b, hipStream_t s,
                 double* part = nullptr) {
-  hipLaunchKernelGGL(k_dot_parts, dim3(kRedBlocks, nrhs), dim3(256), 0, s, c->G.d, a, b,
+  hipLaunchKernelGGL(k_dot_parts<T>, dim3(kRedBlocks, nrhs), dim3(256), 0, s, c->G.d, a, b,
                      part ? part : c->part);
   return hipGetLastError();
+}
+
+// FP32-refined (P)CG on M^T M (reliable updates of the residual, as the
+// Holstein solver's FP32-refined mode): FP32 CG on a correction u32 with the
+// FP32 tables.  The iteration of a right-hand side stops on the device
+// when its FP32 residual has fallen by delta since the last FP64 evaluation,
+// reaches the tolerance, hits the cap or breaks down; every `chunk`
+// iterations the host reads the state, and if any has stopped, the
+// corrections are moved into the FP64 iterate, the FP64 residual
+// r = b - M^T M u is evaluated with the FP64 tables, and the FP32 iteration
+// continues from it: r32 = r, z = F F^T r, |r|^2 and r.z replaced, and the
+// directions kept with beta = r.z (replaced) / r.z (previous step), unless
+// the evaluated residual is 100x the iterated one (then beta = 0).  A
+// right-hand side finishes when its FP64 residual reaches the tolerance, or
+// at the caps.
+int solve_refined(fph_ssh_s* c, int nrhs, const double* b_dev, double* u_dev, const fph_pcg_opts_t* opts,
+                  fph_pcg_stats_t* stats_host, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const long d = c->G.d;
+  const long n = (long)nrhs * d;
+  const bool pre = opts->use_precond != 0;
+  const int chunk = opts->chunk > 0 ? (opts->chunk < kMaxChunk ? opts->chunk : kMaxChunk) : 64;
+  double delta = opts->ru_delta > 0.0 ? std::min(opts->ru_delta, 0.5) : (pre ? 0.1 : 0.3);
+  const int max_outer = opts->max_outer > 0 ? opts->max_outer : 32;
+  const double tol2 = opts->tol * opts->tol;
+  float* z = pre ? c->z32 : c->r32;
+  const double* p2 = pre ? c->part2 : c->part;
+  auto sum_host = [&](const double* part_dev, std::vector<double>& out) -> int {
+    std::vector<double> part((size_t)nrhs * kRedBlocks);
+    SSH_CHECK(hipStreamSynchronize(s));
+    SSH_CHECK(hipMemcpy(part.data(), part_dev, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+    out.assign(nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+      for (int k = 0; k < kRedBlocks; ++k) out[r] += part[(size_t)r * kRedBlocks + k];
+    return FPH_OK;
+  };
+  // FP64 residual of the iterate into c->r and its |r|^2 on the host
+  auto residual64 = [&](std::vector<double>& rr) -> int {
+    SSH_CHECK(launch_apply<double>(c, FPH_OP_MTM, nrhs, u_dev, c->r, s));
+    hipLaunchKernelGGL(k_sub_from, dim3(grid_for(n)), dim3(256), 0, s, n, b_dev, c->r);
+    SSH_CHECK(hipGetLastError());
+    SSH_CHECK(dots<double>(c, nrhs, c->r, c->r, s));
+    return sum_host(c->part, rr);
+  };
+  // r32 = (float) r64, z = F F^T r32 (or r32), and |r32|^2, r32 . z
+  auto start32 = [&](std::vector<double>& rr32, std::vector<double>& rz32) -> int {
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, n, (const double*)c->r, c->r32);
+    SSH_CHECK(hipGetLastError());
+    if (pre) {
+      const int rc = fph_precond_apply(c->pc, FPH_PC_FFT, FPH_F32, nrhs, c->r32, c->z32, stream);
+      if (rc != FPH_OK) return rc;
+    }
+    SSH_CHECK(dots<float>(c, nrhs, c->r32, c->r32, s));
+    int rc = sum_host(c->part, rr32);
+    if (rc != FPH_OK) return rc;
+    if (!pre) {
+      rz32 = rr32;
+      return FPH_OK;
+    }
+    SSH_CHECK(dots<float>(c, nrhs, c->r32, c->z32, s, c->part2));
+    return sum_host(c->part2, rz32);
+  };
+
+  std::vector<double> bb, rr64, rr32, rz32, act;
+  SSH_CHECK(dots<double>(c, nrhs, b_dev, b_dev, s));
+  int rc = sum_host(c->part, bb);
+  if (rc != FPH_OK) return rc;
+  if (opts->zero_guess) SSH_CHECK(hipMemsetAsync(u_dev, 0, n * sizeof(double), s));
+  for (int r = 0; r < nrhs; ++r)  // b = 0: u = 0 exactly
+    if (bb[r] == 0.0) SSH_CHECK(hipMemsetAsync(u_dev + (long)r * d, 0, d * sizeof(double), s));
+  SSH_CHECK(hipMemsetAsync(c->u32, 0, n * sizeof(float), s));
+  rc = residual64(rr64);
+  if (rc != FPH_OK) return rc;
+  rc = start32(rr32, rz32);
+  if (rc != FPH_OK) return rc;
+  std::vector<int> fin(nrhs, 0), conv(nrhs, 0);
+  std::vector<double> rr_ref(rr64);
+  for (int r = 0; r < nrhs; ++r) {
+    CgState& S = c->st_host[r];
+    std::memset(&S, 0, sizeof(S));
+    S.tol2 = tol2;
+    S.maxiter = opts->maxiter;
+    S.bb = bb[r];
+    S.rr = rr32[r];
+    S.rz = rz32[r];
+    S.rr_ref = rr64[r];
+    S.delta2 = delta * delta;
+    if (!std::isfinite(rr64[r]) || !std::isfinite(rz32[r])) {
+      S.status |= FPH_ST_NONFINITE;
+      fin[r] = 1;
+    } else if (!(rr64[r] > tol2 * bb[r])) {
+      fin[r] = conv[r] = 1;
+    } else if (!(rz32[r] > 0.0)) {
+      S.status |= FPH_ST_BREAKDOWN;
+      fin[r] = 1;
+    }
+    S.done = fin[r];
+  }
+  SSH_CHECK(hipMemcpyAsync(c->st, c->st_host, nrhs * sizeof(CgState), hipMemcpyHostToDevice, s));
+  SSH_CHECK(hipMemcpyAsync(c->pa32, z, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  float* pc = c->pa32;  // the current direction
+  float* pn = c->pb32;  // receives the next one
+  const bool fused = mtm_fusable(c);
+  CgState* sa = c->st;
+  CgState* sb = c->st + c->max_rhs;
+  int outer = 0;
+  const int matvecs0 = opts->zero_guess ? 0 : 1;
+  std::vector<int> iters0(nrhs, 0);
+  for (;;) {
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) all = all && fin[r];
+    if (all) break;
+    for (int r = 0; r < nrhs; ++r) iters0[r] = c->st_host[r].iters;
+    for (int k = 0; k < chunk; ++k) {
+      const double* pq = c->part2;
+      if (fused) {
+        MtmCg<float> a;
+        a.zv = z;
+        a.pnew = pn;
+        a.st_old = sa;
+        a.st_new = sb;
+        a.part_rr = c->part;
+        a.part_rz = p2;
+        a.nbz = pre ? kRedBlocks : kXrBlocks;
+        a.from_state = k == 0;
+        SSH_CHECK((launch_mtm_fused<float, true>(c, nrhs, pc, c->q32, s, true, c->part3, a)));
+        std::swap(sa, sb);
+        pq = c->part3;
+      } else {
+        SSH_CHECK((launch_apply_op<float, 0, true>(c, nrhs, pc, c->tmp32, s, nullptr, z, pn)));
+        SSH_CHECK((launch_apply_op<float, 1>(c, nrhs, c->tmp32, c->q32, s, pn, nullptr, nullptr, c->part2)));
+      }
+      hipLaunchKernelGGL(k_cg_xr<float>, dim3(kXrBlocks, nrhs), dim3(256), 0, s, d, sa, c->G.Ltau, pq,
+                         (const float*)pn, (const float*)c->q32, c->u32, c->r32, c->part);
+      SSH_CHECK(hipGetLastError());
+      if (pre) {
+        rc = fph_precond_apply(c->pc, FPH_PC_FFT, FPH_F32, nrhs, c->r32, c->z32, stream);
+        if (rc != FPH_OK) return rc;
+        SSH_CHECK(dots<float>(c, nrhs, c->r32, c->z32, s, c->part2));
+      }
+      if (!fused || k + 1 == chunk) {
+        hipLaunchKernelGGL(k_cg_scalar, dim3(nrhs), dim3(256), 0, s, 2, kXrBlocks, pre ? kRedBlocks : kXrBlocks,
+                           (const double*)c->part, p2, sa);
+        SSH_CHECK(hipGetLastError());
+      }
+      std::swap(pc, pn);
+    }
+    SSH_CHECK(hipMemcpyAsync(c->st_host, sa, nrhs * sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SSH_CHECK(hipStreamSynchronize(s));
+    bool due = false;
+    for (int r = 0; r < nrhs; ++r) {
+      const CgState& S = c->st_host[r];
+      if (!fin[r] && (S.done || S.rr <= delta * delta * rr_ref[r])) due = true;
+    }
+    if (!due) continue;
+    // move the corrections into the FP64 iterate and evaluate its residual
+    hipLaunchKernelGGL(k_fold_f32, dim3(grid_for(n)), dim3(256), 0, s, n, u_dev, c->u32);
+    SSH_CHECK(hipGetLastError());
+    rc = residual64(rr64);
+    if (rc != FPH_OK) return rc;
+    ++outer;
+    std::vector<int> restart(nrhs, 0), paused(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+      if (fin[r]) continue;
+      CgState& S = c->st_host[r];
+      paused[r] = S.done;
+      // The launch of chunk step k writes the next direction into the buffer
+      // that is current after the step; a right-hand side that stopped after
+      // j = iters - iters0 iterations (its j-th scalars folded in step j)
+      // last wrote it in step j - 1, so after the chunk its direction is in
+      // the current buffer when chunk - j is even, else in the other one.
+      const int j = S.iters - iters0[r];
+      if (S.done && j >= 1 && ((chunk - j) & 1))
+        SSH_CHECK(hipMemcpyAsync(pc + (long)r * d, pn + (long)r * d, d * sizeof(float),
+                                 hipMemcpyDeviceToDevice, s));
+      if (!std::isfinite(rr64[r])) {
+        S.status |= FPH_ST_NONFINITE;
+        fin[r] = 1;
+      } else if (!(rr64[r] > tol2 * bb[r])) {
+        fin[r] = conv[r] = 1;
+      } else if (S.status & (FPH_ST_BREAKDOWN | FPH_ST_NONFINITE)) {
+        fin[r] = 1;
+      } else if (S.iters >= S.maxiter || outer >= max_outer) {
+        fin[r] = 1;
+      } else {
+        if (rr64[r] > 4.0 * S.rr) delta = std::sqrt(delta);  // FP32 recursion drifted: replace sooner
+        restart[r] = rr64[r] > 1e4 * S.rr;
+        rr_ref[r] = rr64[r];
+      }
+    }
+    rc = start32(rr32, rz32);
+    if (rc != FPH_OK) return rc;
+    for (int r = 0; r < nrhs; ++r) {
+      CgState& S = c->st_host[r];
+      S.done = fin[r];
+      if (fin[r]) continue;
+      // beta with the replaced r.z: a stopped iteration kept the previous
+      // step's r.z; a running one has already formed beta from its own
+      const double rz_prev = paused[r] ? S.rz : S.rz / S.beta;
+      S.beta = restart[r] || !(rz_prev > 0.0) ? 0.0 : rz32[r] / rz_prev;
+      S.rr = rr32[r];
+      S.rz = rz32[r];
+      S.rr_ref = rr64[r];
+      S.delta2 = delta * delta;
+      if (!(rz32[r] > 0.0)) {
+        S.status |= std::isfinite(rz32[r]) ? FPH_ST_BREAKDOWN : FPH_ST_NONFINITE;
+        S.done = fin[r] = 1;
+      }
+    }
+    SSH_CHECK(hipMemcpyAsync(sa, c->st_host, nrhs * sizeof(CgState), hipMemcpyHostToDevice, s));
+  }
+  SSH_CHECK(dots<double>(c, nrhs, b_dev, u_dev, s));
+  rc = sum_host(c->part, act);
+  if (rc != FPH_OK) return rc;
+  if (stats_host) {
+    for (int r = 0; r < nrhs; ++r) {
+      const CgState& S = c->st_host[r];
+      fph_pcg_stats_t& o = stats_host[r];
+      std::memset(&o, 0, sizeof(o));
+      o.iters = S.iters;
+      o.outer_iters = outer;
+      o.matvecs = matvecs0 + S.iters + outer;
+      o.rel_resid = bb[r] > 0.0 ? std::sqrt(rr64[r] / bb[r]) : 0.0;
+      o.action = act[r];
+      o.status = S.status & (FPH_ST_BREAKDOWN | FPH_ST_NONFINITE);
+      if (conv[r]) o.status |= FPH_ST_CONVERGED;
+      else if (!o.status) o.status |= FPH_ST_MAXITER;
+    }
+  }
+  return FPH_OK;
 }
 
 }  // namespace
@@ -770,6 +1067,15 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
   SSH_ALLOC(c->part2, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
   SSH_ALLOC(c->part3, (size_t)max_rhs * (lat->Ltau > kRedBlocks ? lat->Ltau : kRedBlocks) * sizeof(double));
   SSH_ALLOC(c->st, 2 * (size_t)max_rhs * sizeof(CgState));
+  SSH_ALLOC(c->hop32, 2 * d * sizeof(float2));
+  SSH_ALLOC(c->Et32, d * sizeof(float));
+  SSH_ALLOC(c->r32, (size_t)max_rhs * d * sizeof(float));
+  SSH_ALLOC(c->z32, (size_t)max_rhs * d * sizeof(float));
+  SSH_ALLOC(c->pa32, (size_t)max_rhs * d * sizeof(float));
+  SSH_ALLOC(c->pb32, (size_t)max_rhs * d * sizeof(float));
+  SSH_ALLOC(c->q32, (size_t)max_rhs * d * sizeof(float));
+  SSH_ALLOC(c->tmp32, (size_t)max_rhs * d * sizeof(float));
+  SSH_ALLOC(c->u32, (size_t)max_rhs * d * sizeof(float));
 #undef SSH_ALLOC
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->st_host, (size_t)max_rhs * sizeof(CgState), hipHostMallocDefault);
@@ -784,7 +1090,9 @@ int fph_ssh_create(fph_ssh_t* out, const fph_lattice_t* lat, double g, int32_t m
 int fph_ssh_destroy(fph_ssh_t c) {
   if (c == nullptr) return FPH_E_NULL;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {c->x, c->hop, c->Et, c->tmp, c->r, c->p, c->p2, c->q, c->z, c->part, c->part2, c->part3, c->st};
+  void* ptrs[] = {c->x,   c->hop,   c->Et,  c->tmp,  c->r,    c->p,    c->p2,   c->q,   c->z,
+                  c->part, c->part2, c->part3, c->st, c->hop32, c->Et32, c->r32, c->z32, c->pa32,
+                  c->pb32, c->q32, c->tmp32, c->u32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -797,7 +1105,7 @@ int ssh_set_field(fph_ssh_t c, const double* x_dev, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   SSH_CHECK(hipMemcpyAsync(c->x, x_dev, c->G.d * sizeof(double), hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_ssh_tables, dim3(c->G.Ltau), dim3(kNT), c->G.N * sizeof(double), s, c->G,
-                     (const double*)c->x, c->hop, c->Et);
+                     (const double*)c->x, c->hop, c->Et, c->hop32, c->Et32);
   SSH_CHECK(hipGetLastError());
   c->have_field = true;
   if (c->pc != nullptr) return fph_set_field(c->pc, x_dev, c->pc_a1, c->pc_a2, stream);
@@ -824,7 +1132,7 @@ int ssh_force(fph_ssh_t c, int32_t nrhs, const double* u_dev, double* grad_dev, 
   if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
   if (!std::isfinite(scale)) return FPH_E_ARG;
   hipStream_t s = (hipStream_t)stream;
-  SSH_CHECK(launch_apply_op<0>(c, nrhs, u_dev, c->tmp, s));  // y = M u
+  SSH_CHECK((launch_apply_op<double, 0>(c, nrhs, u_dev, c->tmp, s)));  // y = M u
   SSH_CHECK(launch_force(c, nrhs, u_dev, c->tmp, scale, scale_dev, grad_dev, s));
   return FPH_OK;
 }
@@ -866,12 +1174,18 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
   if (c == nullptr || b_dev == nullptr || u_dev == nullptr || opts == nullptr) return FPH_E_NULL;
   if (!c->have_field) return FPH_E_NOFIELD;
   if (nrhs < 1 || nrhs > c->max_rhs) return FPH_E_NRHS;
-  if (opts->prec != FPH_F64 || opts->use_precond < 0 || opts->use_precond > 1) return FPH_E_PREC;
+  if ((opts->prec != FPH_F64 && opts->prec != FPH_F32_REFINED) || opts->use_precond < 0 ||
+      opts->use_precond > 1)
+    return FPH_E_PREC;
   const bool pre = opts->use_precond != 0;
   if (pre && c->pc == nullptr) return FPH_E_ARG;
   if (pre && nrhs > c->pc_max_rhs) return FPH_E_NRHS;
   if (!(opts->tol > 0.0) || !std::isfinite(opts->tol) || opts->maxiter < 1 || opts->chunk < 0)
     return FPH_E_ARG;
+  if (opts->prec == FPH_F32_REFINED) {
+    if (opts->max_outer < 0 || !(opts->ru_delta >= 0.0)) return FPH_E_ARG;
+    return solve_refined(c, nrhs, b_dev, u_dev, opts, stats_host, stream);
+  }
   hipStream_t s = (hipStream_t)stream;
   const long d = c->G.d;
   const long n = (long)nrhs * d;
@@ -932,7 +1246,7 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
       const double* pq = c->part2;
       if (fused) {
         // also finishes the previous step's scalars (sa -> sb)
-        MtmCg a;
+        MtmCg<double> a;
         a.zv = z;
         a.pnew = pn;
         a.st_old = sa;
@@ -941,16 +1255,16 @@ int ssh_solve(fph_ssh_t c, int32_t nrhs, const double* b_dev, double* u_dev, con
         a.part_rz = p2;
         a.nbz = pre ? kRedBlocks : kXrBlocks;
         a.from_state = k == 0;
-        SSH_CHECK(launch_mtm_fused<true>(c, nrhs, pc, c->q, s, true, c->part3, a));
+        SSH_CHECK((launch_mtm_fused<double, true>(c, nrhs, pc, c->q, s, true, c->part3, a)));
         std::swap(sa, sb);
         pq = c->part3;
       } else {
-        SSH_CHECK((launch_apply_op<0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));  // state in c->st
-        SSH_CHECK(launch_apply_op<1>(c, nrhs, c->tmp, c->q, s, pn, nullptr, nullptr, c->part2));
+        SSH_CHECK((launch_apply_op<double, 0, true>(c, nrhs, pc, c->tmp, s, nullptr, z, pn)));  // state in c->st
+        SSH_CHECK((launch_apply_op<double, 1>(c, nrhs, c->tmp, c->q, s, pn, nullptr, nullptr, c->part2)));
       }
       // alpha, u += alpha p, r -= alpha q with the |r|^2 partials (into part:
       // the p.q partials are still being read by other blocks)
-      hipLaunchKernelGGL(k_cg_xr, dim3(kXrBlocks, nrhs), dim3(256), 0, s, d, sa, c->G.Ltau, pq,
+      hipLaunchKernelGGL(k_cg_xr<double>, dim3(kXrBlocks, nrhs), dim3(256), 0, s, d, sa, c->G.Ltau, pq,
                          (const double*)pn, (const double*)c->q, u_dev, c->r, c->part);
       SSH_CHECK(hipGetLastError());
       rc = precondition();

@@ -27,8 +27,8 @@ def _pcg_opts(tol, precond=True, prec="f32_refined", maxiter=100000, ru_delta=0.
 
 class PhononHMC:
     """HMC and global updates of the phonon field of one ``FermionSolver`` or
-    ``SSHSolver`` (which must outlive this object; with an SSHSolver the solves
-    are FP64, prec="f64").  m_reg=None disables Fourier
+    ``SSHSolver`` (which must outlive this object; with an SSHSolver prec is
+    "f64" or "f32_refined" as well).  m_reg=None disables Fourier
     acceleration; lambda_action=True samples the action with A = M Lambda,
     False the action S' with A = M."""
 

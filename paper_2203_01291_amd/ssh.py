@@ -93,13 +93,18 @@ class SSHSolver:
         check(self.lib.ssh_matvec(self.h, _OPS[op], nrhs, _ptr(v), _ptr(out), _stream()))
         return out
 
-    def solve(self, b, u=None, tol=1e-10, maxiter=100000, chunk=0, precond=False):
-        """FP64 (P)CG on (M^T M) u = b (precond: the attached preconditioner).
-        Returns (u, [stats dict per rhs]).  Blocks until done."""
+    def solve(self, b, u=None, tol=1e-10, maxiter=100000, chunk=0, precond=False, prec="f64",
+              ru_delta=0.0, max_outer=0):
+        """(P)CG on (M^T M) u = b (precond: the attached preconditioner), FP64
+        or FP32-refined (prec="f32_refined": FP32 iterations with FP64
+        residual replacement).  Returns (u, [stats dict per rhs]).  Blocks
+        until done."""
+        from .solver import _PRECS
         nrhs = self._vec(b)
         zero = u is None
         u = torch.empty_like(b) if u is None else u
-        opts = PcgOpts(float(tol), int(maxiter), int(bool(precond)), 0, int(zero), 0.0, int(chunk), 0)
+        opts = PcgOpts(float(tol), int(maxiter), int(bool(precond)), _PRECS[prec], int(zero), float(ru_delta),
+                       int(chunk), 0, int(max_outer))
         stats = (PcgStats * nrhs)()
         check(self.lib.ssh_solve(self.h, nrhs, _ptr(b), _ptr(u), ctypes.byref(opts), stats, _stream()))
         return u, [s.as_dict() for s in stats]

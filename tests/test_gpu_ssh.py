@@ -217,8 +217,19 @@ def test_hmc_trajectory_and_global_update():
     assert u["accepted"] == 1 and np.array_equal(xg.cpu().numpy(), x2)
     with pytest.raises(FphError):  # Lambda belongs to the Holstein coupling
         PhononHMC(s, om, mreg, dt, prec="f64", lambda_action=True)
-    with pytest.raises(FphError):  # FP64 solves only
-        PhononHMC(s, om, mreg, dt, prec="f32_refined")
+    # the same trajectory with FP32-refined solves to 1e-12: the oracle's momenta, field,
+    # energies and decision
+    xg = tgpu(x)
+    pg = torch.empty_like(xg)
+    h32 = PhononHMC(s, om, mreg, dt, Nt=Nt, nt=nt, nfields=2, force_tol=1e-12, action_tol=1e-12,
+                    precond=False, prec="f32_refined")
+    st = h32.trajectory(xg, tgpu(R), tgpu(Rm), 0.5, p_out=pg)
+    assert st["status"] & 1
+    assert rel(pg.cpu().numpy(), ref["p_f"]) < 1e-8
+    for a, b in (("SB_f", ref["H_f"]["S_B"]), ("SF_f", ref["H_f"]["S_F"]), ("K_f", ref["H_f"]["K"])):
+        assert st[a] == pytest.approx(b, abs=1e-7), a
+    assert bool(st["accepted"]) == ref["accepted"]
+    assert rel(xg.cpu().numpy(), ref["x_out"]) < 1e-8
 
 
 @pytest.mark.parametrize("L,T", [(40, 4), (64, 2)])
