@@ -398,6 +398,32 @@ def test_batched_preconditioned_solve_uneven_systems(a1a2):
     assert [v["iters"] for v in st] == [v["iters"] for v in st2]
 
 
+def test_batched_preconditioned_workload_system_against_oracle():
+    """The largest system of the batched workload (L = 24, Ltau = 100, its recipe's field) with a
+    Gaussian and a Rademacher right-hand side, solved in a preconditioned batch beside a small
+    system, against the oracle's sparse LU of M and M^T, element by element."""
+    from paper_2203_01291_amd.solver import FermionBatch
+    from workloads import batched_systems
+    p = get_config("c4")
+    Ls = batched_systems(p)
+    k = Ls.index(max(Ls))
+    L = Ls[k]
+    lat = OL.Lattice(L, p.Ltau, p.dtau, p.t, p.mu, p.alpha)
+    x = phonon_field(p, L=L, system=k)
+    b = np.concatenate([gaussian_rhs(p, 1, L=L, system=k), rademacher_rhs(p, 1, L=L, system=k)])
+    small = OL.Lattice(4, 8, 0.1, 1.0, 0.0, 1.0)
+    xs = np.random.default_rng(77).standard_normal((8, 16))
+    bs = np.random.default_rng(78).standard_normal((1, 8, 16))
+    batch = FermionBatch([(lat, tgpu(x), tgpu(b)), (small, tgpu(xs), tgpu(bs))])
+    st = batch.solve(tol=1e-11, precond=True)
+    assert all(v["status"] == 1 for v in st), st
+    ref = OS.solve_sparse(lat, x, b)
+    for r in range(2):
+        assert relmax(batch.u[0][r].cpu().numpy(), ref[r]) < 1e-8, r
+        assert st[r]["action"] == pytest.approx(float(np.sum(b[r] * ref[r])), rel=1e-10)
+    assert relmax(batch.u[1][0].cpu().numpy(), OS.solve_dense(small, xs, bs)[0]) < 1e-8
+
+
 def test_batched_preconditioned_c4_subset_against_single_solver():
     """c4 systems (Ltau = 100, the 10 x 5 split) with 2 Gaussian and 2 Rademacher
     right-hand sides each: the preconditioned batch against the single-system
