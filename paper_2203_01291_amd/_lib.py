@@ -193,6 +193,12 @@ def load(path=None):
         raise RuntimeError(
             f"HIP library {p} is missing; build it with "
             "`python -c 'import __graft_entry__ as g; g.build()'` (no CPU fallback exists)")
+    # The library and PyTorch must share one HIP runtime: torch ships its
+    # own libamdhip64.so.7 and HSA runtime, and the library's dependency of
+    # the same soname resolves to whichever copy is loaded first.  Loading
+    # the library first would bring in the system runtime beside torch's
+    # HSA runtime, after which torch finds no GPU.  So torch comes first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(p)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)

@@ -27,6 +27,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <map>
@@ -219,12 +220,47 @@ struct PcInfo {
 
 // ------------------------------------------------------------- reductions
 
+// One 32-bit lane value from lane (i - n) mod 16 of the same 16-lane row
+// (DPP row rotation right by n).
+template <int N>
+FPH_DEVINL float row_ror(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + N, 0xf, 0xf, true));
+}
+template <int N>
+FPH_DEVINL double row_ror(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull), 0x120 + N, 0xf, 0xf,
+                                          true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x120 + N, 0xf, 0xf, true);
+  return __builtin_bit_cast(double,
+                            ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+// Sum of v over the 64 lanes of a wave, valid in every lane: each 16-lane
+// row adds its rotations by 8, 4, 2 and 1 (DPP), then the totals held by
+// lanes 0, 16, 32 and 48 are added in that order.  The order of operations
+// is fixed, so every wave given the same values gets the same bits.
+FPH_DEVINL double readlane_d(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | (unsigned long long)lo);
+}
+
+FPH_DEVINL double wave_sum_fixed(double v) {
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
+}
+
+
 // Sum of one double over the workgroup; result valid in thread 0.
 template <int NT>
 FPH_DEVINL double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  v = wave_sum_fixed(v);
   if (lane == 0) sh[wid] = v;
   __syncthreads();
   double s = 0.0;
@@ -364,53 +400,83 @@ FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, double tot2, in
   s.pend = P_NONE;
 }
 
+// Reading the state of right-hand side r is split in two so that a kernel
+// can issue the loads first and fold them where it needs the result:
+// state_issue (first wave only) loads the pending partials announced by
+// the hint and the state itself, one 32-bit word per lane.  These are
+// vector loads: a barrier waits only for LDS and scalar loads, so they stay
+// in flight across the kernel's own LDS exchanges.  state_finish writes the
+// words into s_sh, sums the partials (lane l adds partials l, l + 64, ...
+// in order, then a fixed butterfly across the wave: the same order in every
+// block), folds them (thread 0) and ends with a workgroup barrier.
+constexpr int kStWords = (int)(sizeof(RhsState) / 4);
+static_assert(sizeof(RhsState) % 4 == 0 && kStWords <= 64, "one state word per lane of a wave");
+
+// NS: partials per lane loaded ahead (lane l: l, l + 64, ...); a kernel
+// that holds the loads for long takes few, and more pending partials than
+// 64 NS (or than the hint) are loaded when folded.
+template <int NS>
+struct StLoad {
+  double pre[NS > 0 ? NS : 1];
+  uint32_t w;  // state word `lane`
+};
+
+template <int NS>
+FPH_DEVINL void state_issue(const StIO& io, int r, StLoad<NS>& L) {
+  if (threadIdx.x < 64) {
+    const double* part = io.pin + (long)r * kPStride;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int k = threadIdx.x + 64 * j;
+      L.pre[j] = (k < io.nhint) ? part[k] : 0.0;
+    }
+    const uint32_t* sw = reinterpret_cast<const uint32_t*>(io.in + r);
+    L.w = ((int)threadIdx.x < kStWords) ? sw[threadIdx.x] : 0u;
+  }
+}
+
+template <int NT, int NS>
+FPH_DEVINL void state_finish(const StIO& io, int r, const StLoad<NS>& L, RhsState* s_sh) {
+  if (threadIdx.x < 64) {
+    const int pend = __builtin_amdgcn_readlane((int)L.w, (int)(offsetof(RhsState, pend) / 4));
+    const int npart = __builtin_amdgcn_readlane((int)L.w, (int)(offsetof(RhsState, npart) / 4));
+    if ((int)threadIdx.x < kStWords) reinterpret_cast<uint32_t*>(s_sh)[threadIdx.x] = L.w;
+    if (pend != P_NONE) {
+      const double* part = io.pin + (long)r * kPStride;
+      double v = 0.0, v2 = 0.0;
+      if (npart <= io.nhint && npart <= 64 * NS) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+          if ((int)threadIdx.x + 64 * j < npart) v += L.pre[j];
+      } else {
+        for (int k = threadIdx.x; k < npart; k += 64) v += part[k];
+      }
+      if (pend == P_RES)
+        for (int k = threadIdx.x; k < npart; k += 64) v2 += part[kPHalf + k];
+      v = wave_sum_fixed(v);
+      if (pend == P_RES) v2 = wave_sum_fixed(v2);
+      if (threadIdx.x == 0) {
+        // The wave's own LDS writes above are ordered before this read.
+        RhsState t;
+        __builtin_memcpy(&t, s_sh, sizeof(RhsState));
+        apply_pending(t, pend, v, v2, io.precond);
+        *s_sh = t;
+      }
+    } else if (threadIdx.x == 0) {
+      s_sh->folded = P_NONE;
+    }
+  }
+  __syncthreads();
+}
+
 // Load the state of right-hand side r into LDS and fold in any pending
 // partial sums.  Call from every thread; s_sh is valid afterwards.
 template <int NT>
 FPH_DEVINL void state_begin(const StIO& io, int r, RhsState* s_sh, double* red_sh) {
   (void)red_sh;
-  if (threadIdx.x < 64) {
-    // The first wave reads the state and, if partials are pending, sums
-    // them: lane l adds partials l, l + 64, ... in order, then a fixed
-    // butterfly across the wave (same order in every block).  The partials
-    // announced by the hint are loaded together with the state.
-    constexpr int kSpec = 16;
-    const double* part = io.pin + (long)r * kPStride;
-    double pre[kSpec];
-#pragma unroll
-    for (int j = 0; j < kSpec; ++j) {
-      const int k = threadIdx.x + 64 * j;
-      pre[j] = (k < io.nhint) ? part[k] : 0.0;
-    }
-    const RhsState st = io.in[r];
-    if (st.pend != P_NONE) {
-      double v = 0.0, v2 = 0.0;
-      if (st.npart <= io.nhint && st.npart <= 64 * kSpec) {
-#pragma unroll
-        for (int j = 0; j < kSpec; ++j)
-          if (threadIdx.x + 64 * j < st.npart) v += pre[j];
-      } else {
-        for (int k = threadIdx.x; k < st.npart; k += 64) v += part[k];
-      }
-      if (st.pend == P_RES)
-        for (int k = threadIdx.x; k < st.npart; k += 64) v2 += part[kPHalf + k];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        v += __shfl_xor(v, off, 64);
-        v2 += __shfl_xor(v2, off, 64);
-      }
-      if (threadIdx.x == 0) {
-        RhsState t = st;
-        apply_pending(t, st.pend, v, v2, io.precond);
-        *s_sh = t;
-      }
-    } else if (threadIdx.x == 0) {
-      RhsState t = st;
-      t.folded = P_NONE;
-      *s_sh = t;
-    }
-  }
-  __syncthreads();
+  StLoad<16> L;
+  state_issue(io, r, L);
+  state_finish<NT>(io, r, L, s_sh);
 }
 
 // Publish this block's partial (thread 0 passes its block sum) and, from

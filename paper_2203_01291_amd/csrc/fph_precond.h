@@ -226,8 +226,8 @@ FPH_DEVINL void cmacc(T2& acc, T2 w, T2 y) {  // acc += conj(w) y
 // counts, pa on odd.  A right-hand side whose FP64 residual was just
 // evaluated (the folded partials were P_RES) is transformed without the
 // update; an FP32 correction u the state marks as zero is read as zero.
-// The loads of the first pass (two items per thread) other than the
-// direction are issued before the solver state is read.
+// The state loads are issued first, then the loads of the first pass (two
+// items per thread) other than the direction, which needs the state.
 // Step 1, item (site, n2, k1): output k1 of the H1-point DFT over
 // n1 of y_{H2 n1 + n2}, times W_H^{n2 k1}.  Step 2, item (site, k1, k2):
 // the H2-point DFT over n2 -> Z_{k1 + H1 k2}.
@@ -259,10 +259,13 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   const long hN = (long)H * g.N;
   const int npair = H << lks;
 
-  T ra[kI], rb[kI], aa[kI], ab[kI], ua[kI], ub[kI], pv0[kI], pv1[kI];
-  // Loads of pass e0: with all, r (and with CGUPD Ap, u); with dir, the
-  // direction p (CGUPD).
-  auto load = [&](int e0, bool all, bool dir, const T* p) {
+  // Inputs of one pass of stage 0 (kI items per thread): r (and with
+  // CGUPD Ap, u, the direction p) at slices tau and tau + H, and the twist.
+  struct Pass {
+    T ra[kI], rb[kI], aa[kI], ab[kI], ua[kI], ub[kI], pa[kI], pb[kI];
+    T2 tw[kI];
+  };
+  auto load = [&](Pass& P, int e0, bool all, bool dir, const T* p) {
 #pragma unroll
     for (int j = 0; j < kI; ++j) {
       const int e = e0 + j * NT;
@@ -270,31 +273,58 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
       const bool ok = e < npair && i0 + sidx < g.N;
       const long oa = base + (long)tau * g.N + i0 + sidx;
       if (all) {
-        ra[j] = ok ? in[oa] : (T)0;
-        rb[j] = ok ? in[oa + hN] : (T)0;
+        P.ra[j] = ok ? in[oa] : (T)0;
+        P.rb[j] = ok ? in[oa + hN] : (T)0;
+        P.tw[j] = e < npair ? tw[tau] : T2{(T)0, (T)0};
       }
       if (CGUPD) {
         if (all) {
-          aa[j] = ok ? Ap[oa] : (T)0;
-          ab[j] = ok ? Ap[oa + hN] : (T)0;
-          ua[j] = ok ? u[oa] : (T)0;
-          ub[j] = ok ? u[oa + hN] : (T)0;
+          P.aa[j] = ok ? Ap[oa] : (T)0;
+          P.ab[j] = ok ? Ap[oa + hN] : (T)0;
+          P.ua[j] = ok ? u[oa] : (T)0;
+          P.ub[j] = ok ? u[oa + hN] : (T)0;
         }
         if (dir) {
-          pv0[j] = ok ? p[oa] : (T)0;
-          pv1[j] = ok ? p[oa + hN] : (T)0;
+          P.pa[j] = ok ? p[oa] : (T)0;
+          P.pb[j] = ok ? p[oa + hN] : (T)0;
         }
       }
     }
   };
-  load(threadIdx.x, true, false, pa);
-  for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
-  for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
+  // Issue order: the state (first, so that folding it waits for nothing
+  // else), the first pass of inputs, the DFT tables.  In FP32 the tables
+  // go to registers and reach LDS after the fold (before the barrier that
+  // ends stage 0); in FP64, where the registers would cost occupancy, they
+  // are stored before the fold.
+  constexpr bool kTabRegs = sizeof(T) == 4;
+  StLoad<16> sl;
+  if (io.in != nullptr) state_issue(io, r, sl);
+  Pass P0;
+  load(P0, threadIdx.x, true, false, pa);
+  constexpr int kTab = kTabRegs ? 6 : 1;  // (H1^2 + H2^2 + H) <= 6 NT: H1 <= 20, H2 <= 32
+  T2 tab[kTab];
+  if constexpr (kTabRegs) {
+#pragma unroll
+    for (int j = 0; j < kTab; ++j) {
+      const int k = threadIdx.x + j * NT;
+      tab[j] = (k < nF) ? F[k] : (k < nF + H ? W[k - nF] : T2{(T)0, (T)0});
+    }
+  } else {
+    for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
+    for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
+  }
   if (io.in != nullptr) {
-    state_begin<NT>(io, r, &s_sh, red_sh);
+    state_finish<NT>(io, r, sl, &s_sh);
     if (s_sh.done) {
       state_end(io, r, &s_sh, P_NONE, 0.0, tile, ntiles, tile == 0);
       return;
+    }
+  }
+  if constexpr (kTabRegs) {
+#pragma unroll
+    for (int j = 0; j < kTab; ++j) {
+      const int k = threadIdx.x + j * NT;
+      if (k < nF + H) Fl[k] = tab[j];  // Wl follows Fl
     }
   }
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
@@ -302,37 +332,52 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   const bool upd = CGUPD && s_sh.folded == P_PAP;
   const bool uz = CGUPD && s_sh.u32z != 0;
 
-  // Stage 0.
-  {
-    T alpha = (T)0;
-    const T* p = pa;
-    if (CGUPD) {
-      alpha = (T)s_sh.alpha;
-      p = (s_sh.iter & 1) ? pa : pb;  // direction written by this iteration
-    }
-    for (int e0 = threadIdx.x; e0 < npair; e0 += kI * NT) {
-      load(e0, e0 != (int)threadIdx.x, CGUPD, p);
+  // Stage 0.  The direction p (the buffer the state names) is used only
+  // to update u; for the first pass that update is deferred to the end of
+  // the kernel, so the loads of p issued here arrive while the DFT runs.
+  T alpha = (T)0;
+  const T* p = pa;
+  if (CGUPD) {
+    alpha = (T)s_sh.alpha;
+    p = (s_sh.iter & 1) ? pa : pb;  // direction written by this iteration
+    if (upd) load(P0, threadIdx.x, false, true, p);
+  }
+  auto update_u = [&](const Pass& P, int e0) {
 #pragma unroll
-      for (int j = 0; j < kI; ++j) {
-        const int e = e0 + j * NT;
-        if (e >= npair) continue;
-        const int tau = e >> lks, sidx = e & (KS - 1);
-        T a = ra[j], b = rb[j];
-        if (upd && i0 + sidx < g.N) {
-          const long oa = base + (long)tau * g.N + i0 + sidx;
-          const T pva = pv0[j], pvb = pv1[j];
-          a -= alpha * aa[j];
-          b -= alpha * ab[j];
-          in[oa] = a;
-          in[oa + hN] = b;
-          u[oa] = (uz ? (T)0 : ua[j]) + alpha * pva;
-          u[oa + hN] = (uz ? (T)0 : ub[j]) + alpha * pvb;
-          acc_rr += (double)a * (double)a + (double)b * (double)b;
-        }
-        const T2 t = tw[tau];
-        Y0[tau * KS + sidx] = T2{t.x * a + t.y * b, t.y * a - t.x * b};
-      }
+    for (int j = 0; j < kI; ++j) {
+      const int e = e0 + j * NT;
+      const int tau = e >> lks, sidx = e & (KS - 1);
+      if (e >= npair || i0 + sidx >= g.N) continue;
+      const long oa = base + (long)tau * g.N + i0 + sidx;
+      u[oa] = (uz ? (T)0 : P.ua[j]) + alpha * P.pa[j];
+      u[oa + hN] = (uz ? (T)0 : P.ub[j]) + alpha * P.pb[j];
     }
+  };
+  auto stage0 = [&](const Pass& P, int e0) {
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int e = e0 + j * NT;
+      if (e >= npair) continue;
+      const int tau = e >> lks, sidx = e & (KS - 1);
+      T a = P.ra[j], b = P.rb[j];
+      if (upd && i0 + sidx < g.N) {
+        const long oa = base + (long)tau * g.N + i0 + sidx;
+        a -= alpha * P.aa[j];
+        b -= alpha * P.ab[j];
+        in[oa] = a;
+        in[oa + hN] = b;
+        acc_rr += (double)a * (double)a + (double)b * (double)b;
+      }
+      const T2 t = P.tw[j];
+      Y0[tau * KS + sidx] = T2{t.x * a + t.y * b, t.y * a - t.x * b};
+    }
+  };
+  stage0(P0, threadIdx.x);
+  for (int e0 = threadIdx.x + kI * NT; e0 < npair; e0 += kI * NT) {
+    Pass P;
+    load(P, e0, true, upd, p);
+    stage0(P, e0);
+    if (upd) update_u(P, e0);
   }
   __syncthreads();
   const int s1 = H2 << lks;  // Y0 stride between consecutive n1
@@ -362,6 +407,7 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     Z[((long)r * H + kk) * g.N + i0 + sidx] = T2{x.x * scale, x.y * scale};
   }
 
+  if (upd) update_u(P0, threadIdx.x);
   if (io.in != nullptr) {
     double bs = 0.0;
     if (upd) {
@@ -375,8 +421,9 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 // Inverse transform: out[r][tau][i] from Zh[r][k][i] (the same two short
 // DFTs with conjugated matrices, then the conjugate twist and the real
 // split into tau and tau + H).  Stage 0 copies the tile Zh[k][i0..i0+KS)
-// to LDS with coalesced loads, issued before the solver state is read.
-// With dot != 0 also publishes rdot . out as P_RZ partials.  LDS:
+// to LDS with coalesced loads; the solver state, issued before them, is
+// folded after step 1 (it only decides whether the right-hand side is
+// skipped).  With dot != 0 also publishes rdot . out as P_RZ partials.  LDS:
 // (H1^2 + H2^2 + H + 2 H KS) complex values.
 template <typename T, int H1, int NT>
 __global__ void __launch_bounds__(NT)
@@ -403,6 +450,11 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   const long base = (long)r * g.d;
   const int nel = H << lks;
 
+  // The state is needed only to skip a finished right-hand side and to
+  // publish r.z, so its loads go first and are folded after the first
+  // short DFT, once they have arrived.
+  StLoad<0> sl;  // kpm, the kernel before in a solve, publishes no partials
+  if (io.in != nullptr) state_issue(io, r, sl);
   T2 v[kI];
   auto load = [&](int e0) {
 #pragma unroll
@@ -414,15 +466,24 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     }
   };
   load(threadIdx.x);
+  // In FP32 the twist and r (for r.z) of the first kPre passes of step 2
+  // are loaded with the inputs, not inside step 2 (in FP64 the registers
+  // would cost occupancy).
+  constexpr int kPre = sizeof(T) == 4 ? 2 : 0;
+  T2 twp[kPre > 0 ? kPre : 1];
+  T rda[kPre > 0 ? kPre : 1], rdb[kPre > 0 ? kPre : 1];
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const int it = threadIdx.x + j * NT;
+    const int sidx = it & (KS - 1), tau = it >> lks;
+    const bool ok = it < KS * H && i0 + sidx < g.N;
+    const long oa = base + (long)tau * g.N + i0 + sidx;
+    twp[j] = ok ? tw[tau] : T2{(T)0, (T)0};
+    rda[j] = (ok && dot) ? rdot[oa] : (T)0;
+    rdb[j] = (ok && dot) ? rdot[oa + (long)H * g.N] : (T)0;
+  }
   for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
   for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
-  if (io.in != nullptr) {
-    state_begin<NT>(io, r, &s_sh, red_sh);
-    if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, tile, ntiles, tile == 0);
-      return;
-    }
-  }
   const T scale = (T)(2.0 / sqrt((double)g.Ltau));
   double acc_dot = 0.0;
 
@@ -445,26 +506,48 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     for (int n1 = 0; n1 < H1; ++n1) cmacc(acc, fr[n1], yp[n1 * s1]);
     Y[it] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
   }
-  __syncthreads();
+  if (io.in != nullptr) {
+    state_finish<NT>(io, r, sl, &s_sh);  // its barrier also orders Y
+    if (s_sh.done) {
+      state_end(io, r, &s_sh, P_NONE, 0.0, tile, ntiles, tile == 0);
+      return;
+    }
+  } else {
+    __syncthreads();
+  }
   const int s2 = H1 << lks;
-  for (int it = threadIdx.x; it < KS * H; it += NT) {
+  auto step2 = [&](int it, T2 twt, T ra, T rb, bool pre) {
     const int sidx = it & (KS - 1);
     const int tau = it >> lks;  // k1 + H1 k2
     const int k2 = tau / H1, k1 = tau - k2 * H1;
-    if (i0 + sidx >= g.N) continue;
+    if (i0 + sidx >= g.N) return;
     const T2* yp = Y + k1 * KS + sidx;
     const T2* fr = Fl + H1 * H1 + k2 * H2;
     T2 x = T2{(T)0, (T)0};
 #pragma unroll 4
     for (int n2 = 0; n2 < H2; ++n2) cmacc(x, fr[n2], yp[n2 * s2]);
-    const T2 sv = cmulc<T2, T>(x, tw[tau]);
     const long oa = base + (long)tau * g.N + i0 + sidx;
     const long ob = oa + (long)H * g.N;
+    if (!pre) {
+      twt = tw[tau];
+      if (dot) {
+        ra = rdot[oa];
+        rb = rdot[ob];
+      }
+    }
+    const T2 sv = cmulc<T2, T>(x, twt);
     const T va = scale * sv.x, vb = -scale * sv.y;
     out[oa] = va;
     out[ob] = vb;
-    if (dot) acc_dot += (double)rdot[oa] * (double)va + (double)rdot[ob] * (double)vb;
+    if (dot) acc_dot += (double)ra * (double)va + (double)rb * (double)vb;
+  };
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const int it = threadIdx.x + j * NT;
+    if (it < KS * H) step2(it, twp[j], rda[j], rdb[j], true);
   }
+  for (int it = threadIdx.x + kPre * NT; it < KS * H; it += NT)
+    step2(it, T2{(T)0, (T)0}, (T)0, (T)0, false);
 
   if (io.in != nullptr) {
     double bs = 0.0;
@@ -637,22 +720,6 @@ FPH_DEVINL void pb_window_cn(const Win& w, const T2* __restrict__ sl, T th, cons
   out[3].y = fma(th, h1[3].y, h1[2].y);
 }
 
-// One 32-bit lane value from lane (i - n) mod 16 of the same 16-lane row
-// (DPP row rotation right by n).
-template <int N>
-FPH_DEVINL float row_ror(float v) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + N, 0xf, 0xf, true));
-}
-template <int N>
-FPH_DEVINL double row_ror(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(u & 0xffffffffull), 0x120 + N, 0xf, 0xf,
-                                          true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x120 + N, 0xf, 0xf, true);
-  return __builtin_bit_cast(double,
-                            ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
-}
 template <int N, typename T2>
 FPH_DEVINL T2 row_ror2(T2 v) {
   T2 r;
@@ -837,7 +904,6 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   using T2 = typename Cplx<T>::type;
   static_assert(NT <= kNPMax, "one coefficient per thread is loaded ahead");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red_sh[NT / 64];
   __shared__ RhsState s_sh;
   const int nbuf = 2 * kpm_row_stride(g.hL) * g.L + kWinPad;
   T2* buf0 = reinterpret_cast<T2*>(smem_raw);
@@ -851,9 +917,15 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   const Win w = make_win(g, q, own);
   const int i0 = w.x0 + w.row[1], iL = i0 + g.L;
 
-  // Everything that does not depend on the solver state is loaded before
-  // it is read: the order N_P, the first NT coefficients (the table row has
-  // kNPMax entries, so the load needs no bound), the block's input and dbar.
+  // The solver state is not needed before the series (the input is ready
+  // and the series depends on no scalar of the CG), so its loads are
+  // issued first and folded between the conjugate series and the series
+  // of F F^T, where they have long arrived; a right-hand side found
+  // finished or paused there skips the second series.  Only F or F^T alone
+  // (not used inside a solve) folds the state before the series.
+  const bool stt = io.in != nullptr;
+  StLoad<4> sl;
+  if (stt) state_issue(io, r, sl);
   const int f = field_of(g, r);
   info += f;
   np += (long)f * g.Ltau;
@@ -877,8 +949,11 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       db[m] = (T)1;
     }
   }
-  if (io.in != nullptr) {
-    state_begin<NT>(io, r, &s_sh, red_sh);
+  // Holding the state loads through the first series costs registers the
+  // 1024-thread blocks do not have.
+  const bool late = NT < 1024 && stt && op == 2;
+  if (stt && !late) {
+    state_finish<NT>(io, r, sl, &s_sh);
     if (s_sh.done) {
       state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
       return;
@@ -892,6 +967,13 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   } else {
     cheb_series<T, true, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
     if (op == 2) {
+      if (late) {
+        state_finish<NT>(io, r, sl, &s_sh);
+        if (s_sh.done) {
+          state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+          return;
+        }
+      }
 #pragma unroll
       for (int m = 0; m < 4; ++m) x[m] = acc[m];
       cheb_series<T, false, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
@@ -902,7 +984,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
     st2c(Zout + i0, acc[0], acc[1]);
     st2c(Zout + iL, acc[2], acc[3]);
   }
-  if (io.in != nullptr) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+  if (stt) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
 }
 
 // ----------------------------------------------------------------- host
@@ -988,6 +1070,7 @@ hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, int lks, T
                          StateSeq& sq, bool cgupd, hipStream_t s) {
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
+  if (pc->H1 * pc->H1 + pc->H2 * pc->H2 + pc->H > 6 * NT) return hipErrorInvalidValue;
   const StIO io = sq.next(cgupd ? ntiles : 0);
   const size_t lds = pc_tile_lds<T>(pc, lks);
   using T2 = typename Cplx<T>::type;
