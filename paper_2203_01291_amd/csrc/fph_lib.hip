@@ -224,7 +224,10 @@ hipError_t launch_slot_mtm_cfg(const fph_handle_s* h, int nrhs, const SlotArgs<T
   const Geom& g = h->g;
   const int S = (g.Q <= NT) ? NT / g.Q : 1;
   const size_t lds = 4 * (size_t)S * g.N * sizeof(double);
-  auto kern = k_slot_mtm<TI, NT, 1>;
+  // Small systems are latency bound: there the first slices are loaded
+  // ahead of the solver state, both direction buffers included.
+  const bool pf = (long)g.d * nrhs <= (1L << 20);
+  auto kern = pf ? k_slot_mtm<TI, NT, 1, true> : k_slot_mtm<TI, NT, 1, false>;
   {
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;

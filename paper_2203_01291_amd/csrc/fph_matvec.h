@@ -110,7 +110,9 @@ struct InPlain {
 // PCG form); the chunk owner stores p for its own slices.  The two
 // direction buffers alternate with the parity of the right-hand side's own
 // iteration count, so a paused right-hand side keeps a consistent pair.
-template <typename T>
+// PF: the first slices are fetched before the state is known (z and both
+// direction buffers; use2 picks the one the parity selects).
+template <typename T, bool PF = false>
 struct InPUpdate {
   const T* __restrict__ z;
   T* pa;
@@ -155,11 +157,7 @@ struct InPUpdate {
     load2(off, a, b);
     st2(pnew + off, a, b);
   }
-  // Fetched after the state is known (loading both direction buffers
-  // ahead of it costs more than the round trip it saves); if fetched
-  // before, both buffers are loaded and use2 picks the one the parity
-  // selects.
-  static constexpr bool kPrefetch = false;
+  static constexpr bool kPrefetch = PF;
   struct Raw {
     T z0, z1, a0, a1, b0, b1;
   };

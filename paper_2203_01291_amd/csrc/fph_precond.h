@@ -923,9 +923,12 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   // of F F^T, where they have long arrived; a right-hand side found
   // finished or paused there skips the second series.  Only F or F^T alone
   // (not used inside a solve) folds the state before the series.
+  // (The 1024-thread blocks have no registers to spare: they read the
+  // state after the block's input, as one step.)
+  constexpr bool kIssueFirst = NT < 1024;
   const bool stt = io.in != nullptr;
   StLoad<4> sl;
-  if (stt) state_issue(io, r, sl);
+  if (kIssueFirst && stt) state_issue(io, r, sl);
   const int f = field_of(g, r);
   info += f;
   np += (long)f * g.Ltau;
@@ -949,11 +952,12 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       db[m] = (T)1;
     }
   }
-  // Holding the state loads through the first series costs registers the
-  // 1024-thread blocks do not have.
-  const bool late = NT < 1024 && stt && op == 2;
+  const bool late = kIssueFirst && stt && op == 2;
   if (stt && !late) {
-    state_finish<NT>(io, r, sl, &s_sh);
+    if constexpr (kIssueFirst)
+      state_finish<NT>(io, r, sl, &s_sh);
+    else
+      state_begin<NT>(io, r, &s_sh, nullptr);
     if (s_sh.done) {
       state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
       return;

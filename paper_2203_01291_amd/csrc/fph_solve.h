@@ -64,8 +64,9 @@ struct SlotArgs {
 };
 
 // Launch: as k_mtm, grid nblk * nrhs, LDS 4 * S * N doubles (the residual
-// path runs in FP64).  Takes part in the state sequence (io).
-template <typename TI, int NT, int MS>
+// path runs in FP64).  Takes part in the state sequence (io).  PF: prefetch
+// ahead of the state (see below).
+template <typename TI, int NT, int MS, bool PF>
 __global__ void __launch_bounds__(NT)
 k_slot_mtm(Geom g, int Tch, int nblk, SlotArgs<TI> a, StIO io) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -73,13 +74,15 @@ k_slot_mtm(Geom g, int Tch, int nblk, SlotArgs<TI> a, StIO io) {
   __shared__ RhsState s_sh;
   int r, bx;
   mtm_block(nblk, r, bx);
+  // The state loads go first and the state is folded in the sweep's hook.
+  // With PF (small systems, where the kernel is latency bound) the first
+  // slices of a CG iteration (z and both direction buffers, as the parity
+  // is not known yet) are loaded while the state is in flight; a slot that
+  // turns out to evaluate the residual, or to have nothing to do, drops
+  // those loads.
+  StLoad<(PF ? 8 : 16)> sl;
+  state_issue(io, r, sl);
   const long fo = field_off(g, r);
-  state_begin<NT>(io, r, &s_sh, red_sh);
-  const int path = s_sh.final_ ? 0 : (s_sh.replace ? 2 : (s_sh.done ? 0 : 1));
-  if (path == 0) {
-    state_end(io, r, &s_sh, P_NONE, 0.0, bx, nblk, bx == 0);
-    return;
-  }
   int S, sub, lane, nslot;
   block_layout<NT>(g, threadIdx.x, S, sub, lane, nslot);
   const int chunk = bx * S + sub;
@@ -89,35 +92,47 @@ k_slot_mtm(Geom g, int Tch, int nblk, SlotArgs<TI> a, StIO io) {
   const long base = (long)r * g.d;
   const long lo = 4L * (sub < S ? sub : 0) * g.N;
   double acc = 0.0, acc2 = 0.0;
-  auto no_hook = [] { return true; };
-  if (path == 1) {
-    InPUpdate<TI> in{a.z, a.pa, a.pb, nullptr, nullptr, (TI)0, 0};
-    in.begin(s_sh);
+  int path = 0;
+  {
+    InPUpdate<TI, PF> in{a.z, a.pa, a.pb, nullptr, nullptr, (TI)0, 0};
     EpiDot<TI> epi{a.Ap};
-    __syncthreads();  // every thread has read the state
-    if (threadIdx.x == 0) InPUpdate<TI>::on_state(s_sh);
-    mtm_sweep<TI, NT, MS, 1>(g, a.E + fo, a.th, Tch, tau0, Tc, active, lane, nslot,
-                             reinterpret_cast<TI*>(smem_raw) + lo, base, in, epi, acc, acc2,
-                             no_hook);
-    const double bs = block_sum<NT>(acc, red_sh);
-    state_end(io, r, &s_sh, P_PAP, bs, bx, nblk, bx == 0);
-  } else {
-    EpiResidual<TI> epi{a.b, a.r};
-    double* lds4 = reinterpret_cast<double*>(smem_raw) + lo;
-    if constexpr (sizeof(TI) == 4) {
-      InResid in{a.u, a.u64b, a.u32, nullptr, nullptr, 0};
+    auto hook = [&]() {
+      state_finish<NT>(io, r, sl, &s_sh);
+      path = s_sh.final_ ? 0 : (s_sh.replace ? 2 : (s_sh.done ? 0 : 1));
+      if (path != 1) return false;
       in.begin(s_sh);
-      mtm_sweep<double, NT, MS, 1>(g, a.E64 + fo, a.th64, Tch, tau0, Tc, active, lane, nslot,
-                                   lds4, base, in, epi, acc, acc2, no_hook);
-    } else {
-      InPlain<double> in{a.u};
-      mtm_sweep<double, NT, MS, 1>(g, a.E64 + fo, a.th64, Tch, tau0, Tc, active, lane, nslot,
-                                   lds4, base, in, epi, acc, acc2, no_hook);
+      __syncthreads();  // every thread has read the state
+      if (threadIdx.x == 0) InPUpdate<TI, PF>::on_state(s_sh);
+      return true;
+    };
+    if (mtm_sweep<TI, NT, MS, 1>(g, a.E + fo, a.th, Tch, tau0, Tc, active, lane, nslot,
+                                 reinterpret_cast<TI*>(smem_raw) + lo, base, in, epi, acc, acc2,
+                                 hook)) {
+      const double bs = block_sum<NT>(acc, red_sh);
+      state_end(io, r, &s_sh, P_PAP, bs, bx, nblk, bx == 0);
+      return;
     }
-    const double bs = block_sum<NT>(acc, red_sh);
-    const double bs2 = block_sum<NT>(acc2, red_sh);
-    state_end(io, r, &s_sh, P_RES, bs, bx, nblk, bx == 0, bs2);
   }
+  if (path == 0) {
+    state_end(io, r, &s_sh, P_NONE, 0.0, bx, nblk, bx == 0);
+    return;
+  }
+  auto no_hook = [] { return true; };
+  EpiResidual<TI> epi{a.b, a.r};
+  double* lds4 = reinterpret_cast<double*>(smem_raw) + lo;
+  if constexpr (sizeof(TI) == 4) {
+    InResid in{a.u, a.u64b, a.u32, nullptr, nullptr, 0};
+    in.begin(s_sh);
+    mtm_sweep<double, NT, MS, 1>(g, a.E64 + fo, a.th64, Tch, tau0, Tc, active, lane, nslot,
+                                 lds4, base, in, epi, acc, acc2, no_hook);
+  } else {
+    InPlain<double> in{a.u};
+    mtm_sweep<double, NT, MS, 1>(g, a.E64 + fo, a.th64, Tch, tau0, Tc, active, lane, nslot,
+                                 lds4, base, in, epi, acc, acc2, no_hook);
+  }
+  const double bs = block_sum<NT>(acc, red_sh);
+  const double bs2 = block_sum<NT>(acc2, red_sh);
+  state_end(io, r, &s_sh, P_RES, bs, bx, nblk, bx == 0, bs2);
 }
 
 // Initial state of a solve: the first slot evaluates the residual of the
