@@ -218,6 +218,28 @@ FPH_DEVINL void cmacc(T2& acc, T2 w, T2 y) {  // acc += conj(w) y
   acc.y = fma(w.x, y.y, fma(-w.y, y.x, acc.y));
 }
 
+// Two outputs of a short DFT of even length n over the values y[j s],
+// j < n, from the row fr of its matrix (fr[j] = W_n^{j k}, conjugated with
+// CONJ): outputs k and k + n/2 share every product, as
+// W_n^{j (k + n/2)} = (-1)^j W_n^{j k}; the even and odd terms summed
+// apart give a = e + o (output k) and b = e - o (output k + n/2).
+template <bool CONJ, int NU, typename T2>
+FPH_DEVINL void dft_pair(const T2* fr, const T2* y, int s, int n, T2& a, T2& b) {
+  T2 e = T2{0, 0}, o = T2{0, 0};
+#pragma unroll NU
+  for (int j = 0; j < n; j += 2) {
+    if (CONJ) {
+      cmacc(e, fr[j], y[j * s]);
+      cmacc(o, fr[j + 1], y[(j + 1) * s]);
+    } else {
+      cmac(e, fr[j], y[j * s]);
+      cmac(o, fr[j + 1], y[(j + 1) * s]);
+    }
+  }
+  a = T2{e.x + o.x, e.y + o.y};
+  b = T2{e.x - o.x, e.y - o.y};
+}
+
 // Forward transform of one tile of sites: Z[r][k][i] = (U in)_{2k}.
 // Stage 0, item (tau < H, site), coalesced: y_tau = e^{-i pi tau/Ltau}
 // (in_tau - i in_{tau+H}) into LDS.  With CGUPD both inputs first receive
@@ -380,31 +402,62 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     if (upd) update_u(P, e0);
   }
   __syncthreads();
+  // Steps 1 and 2 compute their outputs in pairs (k, k + n/2, dft_pair)
+  // when the factor is even: half the items, each reading its inputs once.
   const int s1 = H2 << lks;  // Y0 stride between consecutive n1
-  for (int it = threadIdx.x; it < KS * H; it += NT) {
-    const int sidx = it & (KS - 1);
-    const int rest = it >> lks;  // n2 * H1 + k1
-    const int n2 = rest / H1, k1 = rest - n2 * H1;
-    const T2* yp = Y0 + n2 * KS + sidx;
-    const T2* fr = Fl + k1 * H1;
-    T2 acc = T2{(T)0, (T)0};
+  if constexpr (H1 % 2 == 0) {
+    constexpr int h1 = H1 / 2;
+    for (int it = threadIdx.x; it < (KS * H) / 2; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int rest = it >> lks;  // n2 * h1 + k1, k1 < H1 / 2
+      const int n2 = rest / h1, k1 = rest - n2 * h1;
+      T2 a, b;
+      dft_pair<false, H1 / 2>(Fl + k1 * H1, Y0 + n2 * KS + sidx, s1, H1, a, b);
+      const int ia = ((n2 * H1 + k1) << lks) + sidx;
+      Y1[ia] = cmul<T2, T>(a, Wl[(n2 * k1) % H]);
+      Y1[ia + (h1 << lks)] = cmul<T2, T>(b, Wl[(n2 * (k1 + h1)) % H]);
+    }
+  } else {
+    for (int it = threadIdx.x; it < KS * H; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int rest = it >> lks;  // n2 * H1 + k1
+      const int n2 = rest / H1, k1 = rest - n2 * H1;
+      const T2* yp = Y0 + n2 * KS + sidx;
+      const T2* fr = Fl + k1 * H1;
+      T2 acc = T2{(T)0, (T)0};
 #pragma unroll
-    for (int n1 = 0; n1 < H1; ++n1) cmac(acc, fr[n1], yp[n1 * s1]);
-    Y1[it] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
+      for (int n1 = 0; n1 < H1; ++n1) cmac(acc, fr[n1], yp[n1 * s1]);
+      Y1[it] = cmul<T2, T>(acc, Wl[(n2 * k1) % H]);
+    }
   }
   __syncthreads();
   const int s2 = H1 << lks;  // Y1 stride between consecutive n2
-  for (int it = threadIdx.x; it < KS * H; it += NT) {
-    const int sidx = it & (KS - 1);
-    const int kk = it >> lks;  // k1 + H1 k2 = output frequency
-    const int k2 = kk / H1, k1 = kk - k2 * H1;
-    if (i0 + sidx >= g.N) continue;
-    const T2* yp = Y1 + k1 * KS + sidx;
-    const T2* fr = Fl + H1 * H1 + k2 * H2;
-    T2 x = T2{(T)0, (T)0};
+  if (H2 % 2 == 0) {
+    const int h2 = H2 / 2;
+    for (int it = threadIdx.x; it < (KS * H) / 2; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int kk = it >> lks;  // k1 + H1 k2, k2 < H2 / 2
+      const int k2 = kk / H1, k1 = kk - k2 * H1;
+      if (i0 + sidx >= g.N) continue;
+      T2 a, b;
+      dft_pair<false, 2>(Fl + H1 * H1 + k2 * H2, Y1 + k1 * KS + sidx, s2, H2, a, b);
+      T2* zp = Z + ((long)r * H + kk) * g.N + i0 + sidx;
+      zp[0] = T2{a.x * scale, a.y * scale};
+      zp[(long)H1 * h2 * g.N] = T2{b.x * scale, b.y * scale};  // output kk + H1 H2 / 2
+    }
+  } else {
+    for (int it = threadIdx.x; it < KS * H; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int kk = it >> lks;  // k1 + H1 k2 = output frequency
+      const int k2 = kk / H1, k1 = kk - k2 * H1;
+      if (i0 + sidx >= g.N) continue;
+      const T2* yp = Y1 + k1 * KS + sidx;
+      const T2* fr = Fl + H1 * H1 + k2 * H2;
+      T2 x = T2{(T)0, (T)0};
 #pragma unroll 4
-    for (int n2 = 0; n2 < H2; ++n2) cmac(x, fr[n2], yp[n2 * s2]);
-    Z[((long)r * H + kk) * g.N + i0 + sidx] = T2{x.x * scale, x.y * scale};
+      for (int n2 = 0; n2 < H2; ++n2) cmac(x, fr[n2], yp[n2 * s2]);
+      Z[((long)r * H + kk) * g.N + i0 + sidx] = T2{x.x * scale, x.y * scale};
+    }
   }
 
   if (upd) update_u(P0, threadIdx.x);
@@ -466,21 +519,33 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     }
   };
   load(threadIdx.x);
-  // In FP32 the twist and r (for r.z) of the first kPre passes of step 2
-  // are loaded with the inputs, not inside step 2 (in FP64 the registers
-  // would cost occupancy).
+  // Steps 1 and 2 compute their outputs in pairs (dft_pair) when both
+  // factors are even; step 2 then writes slices tau and tau + H1 H2 / 2 of
+  // each pair item.  In FP32 the twist and r (for r.z) of the first kPre
+  // passes of paired step-2 items are loaded with the inputs, not inside
+  // step 2 (in FP64 the registers would cost occupancy).
+  constexpr bool kPair1 = H1 % 2 == 0;
+  const bool pair = kPair1 && H2 % 2 == 0;
+  const int hh = H / 2;  // H1 H2 / 2: tau of the second output of a pair item
   constexpr int kPre = sizeof(T) == 4 ? 2 : 0;
-  T2 twp[kPre > 0 ? kPre : 1];
-  T rda[kPre > 0 ? kPre : 1], rdb[kPre > 0 ? kPre : 1];
+  T2 twp[kPre > 0 ? kPre : 1][2];
+  T rdp[kPre > 0 ? kPre : 1][4];
+  const long hN = (long)H * g.N;
+  if (pair) {
 #pragma unroll
-  for (int j = 0; j < kPre; ++j) {
-    const int it = threadIdx.x + j * NT;
-    const int sidx = it & (KS - 1), tau = it >> lks;
-    const bool ok = it < KS * H && i0 + sidx < g.N;
-    const long oa = base + (long)tau * g.N + i0 + sidx;
-    twp[j] = ok ? tw[tau] : T2{(T)0, (T)0};
-    rda[j] = (ok && dot) ? rdot[oa] : (T)0;
-    rdb[j] = (ok && dot) ? rdot[oa + (long)H * g.N] : (T)0;
+    for (int j = 0; j < kPre; ++j) {
+      const int it = threadIdx.x + j * NT;
+      const int sidx = it & (KS - 1), pi = it >> lks;  // k1 + H1 k2, k2 < H2 / 2
+      const bool ok = it < (KS * H) / 2 && i0 + sidx < g.N;
+      const long oa = base + (long)pi * g.N + i0 + sidx;
+      const long oc = oa + (long)hh * g.N;
+      twp[j][0] = ok ? tw[pi] : T2{(T)0, (T)0};
+      twp[j][1] = ok ? tw[pi + hh] : T2{(T)0, (T)0};
+      rdp[j][0] = (ok && dot) ? rdot[oa] : (T)0;
+      rdp[j][1] = (ok && dot) ? rdot[oa + hN] : (T)0;
+      rdp[j][2] = (ok && dot) ? rdot[oc] : (T)0;
+      rdp[j][3] = (ok && dot) ? rdot[oc + hN] : (T)0;
+    }
   }
   for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
   for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
@@ -495,16 +560,30 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   }
   __syncthreads();
   const int s1 = H2 << lks;
-  for (int it = threadIdx.x; it < KS * H; it += NT) {
-    const int sidx = it & (KS - 1);
-    const int rest = it >> lks;  // n2 * H1 + k1
-    const int n2 = rest / H1, k1 = rest - n2 * H1;
-    const T2* yp = Zt + n2 * KS + sidx;
-    const T2* fr = Fl + k1 * H1;
-    T2 acc = T2{(T)0, (T)0};
+  if constexpr (kPair1) {
+    constexpr int h1 = H1 / 2;
+    for (int it = threadIdx.x; it < (KS * H) / 2; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int rest = it >> lks;  // n2 * h1 + k1, k1 < H1 / 2
+      const int n2 = rest / h1, k1 = rest - n2 * h1;
+      T2 a, b;
+      dft_pair<true, H1 / 2>(Fl + k1 * H1, Zt + n2 * KS + sidx, s1, H1, a, b);
+      const int ia = ((n2 * H1 + k1) << lks) + sidx;
+      Y[ia] = cmulc<T2, T>(a, Wl[(n2 * k1) % H]);
+      Y[ia + (h1 << lks)] = cmulc<T2, T>(b, Wl[(n2 * (k1 + h1)) % H]);
+    }
+  } else {
+    for (int it = threadIdx.x; it < KS * H; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int rest = it >> lks;  // n2 * H1 + k1
+      const int n2 = rest / H1, k1 = rest - n2 * H1;
+      const T2* yp = Zt + n2 * KS + sidx;
+      const T2* fr = Fl + k1 * H1;
+      T2 acc = T2{(T)0, (T)0};
 #pragma unroll
-    for (int n1 = 0; n1 < H1; ++n1) cmacc(acc, fr[n1], yp[n1 * s1]);
-    Y[it] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
+      for (int n1 = 0; n1 < H1; ++n1) cmacc(acc, fr[n1], yp[n1 * s1]);
+      Y[it] = cmulc<T2, T>(acc, Wl[(n2 * k1) % H]);
+    }
   }
   if (io.in != nullptr) {
     state_finish<NT>(io, r, sl, &s_sh);  // its barrier also orders Y
@@ -516,18 +595,10 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     __syncthreads();
   }
   const int s2 = H1 << lks;
-  auto step2 = [&](int it, T2 twt, T ra, T rb, bool pre) {
-    const int sidx = it & (KS - 1);
-    const int tau = it >> lks;  // k1 + H1 k2
-    const int k2 = tau / H1, k1 = tau - k2 * H1;
-    if (i0 + sidx >= g.N) return;
-    const T2* yp = Y + k1 * KS + sidx;
-    const T2* fr = Fl + H1 * H1 + k2 * H2;
-    T2 x = T2{(T)0, (T)0};
-#pragma unroll 4
-    for (int n2 = 0; n2 < H2; ++n2) cmacc(x, fr[n2], yp[n2 * s2]);
+  // Output slice tau (and tau + H) of one site from the step-2 sum x.
+  auto emit = [&](int tau, int sidx, const T2& x, T2 twt, T ra, T rb, bool pre) {
     const long oa = base + (long)tau * g.N + i0 + sidx;
-    const long ob = oa + (long)H * g.N;
+    const long ob = oa + hN;
     if (!pre) {
       twt = tw[tau];
       if (dot) {
@@ -541,13 +612,40 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     out[ob] = vb;
     if (dot) acc_dot += (double)ra * (double)va + (double)rb * (double)vb;
   };
+  if (pair) {
+    const int h2 = H2 / 2;
+    auto step2p = [&](int it, int j, bool pre) {
+      const int sidx = it & (KS - 1);
+      const int pi = it >> lks;  // k1 + H1 k2, k2 < H2 / 2
+      const int k2 = pi / H1, k1 = pi - k2 * H1;
+      if (i0 + sidx >= g.N) return;
+      T2 a, b;
+      dft_pair<true, 2>(Fl + H1 * H1 + k2 * H2, Y + k1 * KS + sidx, s2, H2, a, b);
+      const T2 z0 = T2{(T)0, (T)0};
+      emit(pi, sidx, a, pre ? twp[j][0] : z0, pre ? rdp[j][0] : (T)0, pre ? rdp[j][1] : (T)0, pre);
+      emit(pi + H1 * h2, sidx, b, pre ? twp[j][1] : z0, pre ? rdp[j][2] : (T)0,
+           pre ? rdp[j][3] : (T)0, pre);
+    };
 #pragma unroll
-  for (int j = 0; j < kPre; ++j) {
-    const int it = threadIdx.x + j * NT;
-    if (it < KS * H) step2(it, twp[j], rda[j], rdb[j], true);
+    for (int j = 0; j < kPre; ++j) {
+      const int it = threadIdx.x + j * NT;
+      if (it < (KS * H) / 2) step2p(it, j, true);
+    }
+    for (int it = threadIdx.x + kPre * NT; it < (KS * H) / 2; it += NT) step2p(it, 0, false);
+  } else {
+    for (int it = threadIdx.x; it < KS * H; it += NT) {
+      const int sidx = it & (KS - 1);
+      const int tau = it >> lks;  // k1 + H1 k2
+      const int k2 = tau / H1, k1 = tau - k2 * H1;
+      if (i0 + sidx >= g.N) continue;
+      const T2* yp = Y + k1 * KS + sidx;
+      const T2* fr = Fl + H1 * H1 + k2 * H2;
+      T2 x = T2{(T)0, (T)0};
+#pragma unroll 4
+      for (int n2 = 0; n2 < H2; ++n2) cmacc(x, fr[n2], yp[n2 * s2]);
+      emit(tau, sidx, x, T2{(T)0, (T)0}, (T)0, (T)0, false);
+    }
   }
-  for (int it = threadIdx.x + kPre * NT; it < KS * H; it += NT)
-    step2(it, T2{(T)0, (T)0}, (T)0, (T)0, false);
 
   if (io.in != nullptr) {
     double bs = 0.0;
