@@ -446,8 +446,10 @@ FPH_DEVINL void state_finish(const StIO& io, int r, const StLoad<NS>& L, RhsStat
       double v = 0.0, v2 = 0.0;
       if (npart <= io.nhint && npart <= 64 * NS) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j)
+        for (int j = 0; j < NS; ++j) {
+          if (64 * j >= npart) break;  // uniform
           if ((int)threadIdx.x + 64 * j < npart) v += L.pre[j];
+        }
       } else {
         for (int k = threadIdx.x; k < npart; k += 64) v += part[k];
       }
@@ -456,11 +458,12 @@ FPH_DEVINL void state_finish(const StIO& io, int r, const StLoad<NS>& L, RhsStat
       v = wave_sum_fixed(v);
       if (pend == P_RES) v2 = wave_sum_fixed(v2);
       if (threadIdx.x == 0) {
-        // The wave's own LDS writes above are ordered before this read.
-        RhsState t;
-        __builtin_memcpy(&t, s_sh, sizeof(RhsState));
-        apply_pending(t, pend, v, v2, io.precond);
-        *s_sh = t;
+        // The fold reads and writes the fields it needs in place.  The
+        // wave's own LDS writes above reach LDS first (one wave's LDS
+        // operations complete in order); the compiler barrier keeps the
+        // compiler from moving these accesses above the word writes.
+        asm volatile("" ::: "memory");
+        apply_pending(*s_sh, pend, v, v2, io.precond);
       }
     } else if (threadIdx.x == 0) {
       s_sh->folded = P_NONE;
