@@ -236,10 +236,7 @@ FPH_DEVINL double row_ror(double v) {
   return __builtin_bit_cast(double,
                             ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
 }
-// Sum of v over the 64 lanes of a wave, valid in every lane: each 16-lane
-// row adds its rotations by 8, 4, 2 and 1 (DPP), then the totals held by
-// lanes 0, 16, 32 and 48 are added in that order.  The order of operations
-// is fixed, so every wave given the same values gets the same bits.
+// The double held by lane `lane` (uniform result).
 FPH_DEVINL double readlane_d(double v, int lane) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), lane);
@@ -247,6 +244,10 @@ FPH_DEVINL double readlane_d(double v, int lane) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | (unsigned long long)lo);
 }
 
+// Sum of v over the 64 lanes of a wave, valid in every lane: each 16-lane
+// row adds its rotations by 8, 4, 2 and 1 (DPP), then the totals held by
+// lanes 0, 16, 32 and 48 are added in that order.  The order of operations
+// is fixed, so every wave given the same values gets the same bits.
 FPH_DEVINL double wave_sum_fixed(double v) {
   v += row_ror<8>(v);
   v += row_ror<4>(v);
@@ -254,7 +255,6 @@ FPH_DEVINL double wave_sum_fixed(double v) {
   v += row_ror<1>(v);
   return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
 }
-
 
 // Sum of one double over the workgroup; result valid in thread 0.
 template <int NT>
@@ -407,8 +407,8 @@ FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, double tot2, in
 // vector loads: a barrier waits only for LDS and scalar loads, so they stay
 // in flight across the kernel's own LDS exchanges.  state_finish writes the
 // words into s_sh, sums the partials (lane l adds partials l, l + 64, ...
-// in order, then a fixed butterfly across the wave: the same order in every
-// block), folds them (thread 0) and ends with a workgroup barrier.
+// in order, then wave_sum_fixed: the same order in every block), folds
+// them (thread 0) and ends with a workgroup barrier.
 constexpr int kStWords = (int)(sizeof(RhsState) / 4);
 static_assert(sizeof(RhsState) % 4 == 0 && kStWords <= 64, "one state word per lane of a wave");
 
