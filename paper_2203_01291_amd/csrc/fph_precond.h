@@ -24,6 +24,7 @@
 #pragma once
 
 #include <cstring>
+#include <type_traits>
 
 #include "fph_common.h"
 
@@ -987,6 +988,94 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
   }
 }
 
+// The window-form series on one real part of the block vector, for the
+// 1 024-thread FP64 blocks, whose 128 registers per thread do not hold the
+// complex recurrence without spilling.  A = sA D C' - cA is real, so the
+// recurrence of cheb_series runs on the real part (part 0) and on the
+// imaginary part (part 1) of the input separately; each part adds its
+// terms to the complex sum times c_m (conjugated for TRANS) and times 1 or
+// i.  The caller zeroes acc before the first part and, for TRANS, scales by
+// D^-1 after the second.  The thread's published values are read back from
+// LDS and 2 sA D is applied as two fused multiply-adds, both to save
+// registers.
+template <typename T, bool TRANS>
+FPH_DEVINL void cheb_series_part(const Win& w, int NP, const typename Cplx<T>::type* cf, T sA,
+                                 T cA, const T (&x)[4], const T (&db)[4], T* buf0, T* buf1, T th,
+                                 typename Cplx<T>::type (&acc)[4], int part) {
+  using T2 = typename Cplx<T>::type;
+  const T cj = TRANS ? (T)-1 : (T)1;
+  auto accumulate = [&](const T2 c, const T (&v)[4]) {
+    const T cr = c.x, ci = cj * c.y;
+    const T ax = part ? -ci : cr, ay = part ? cr : ci;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[q].x = fma(ax, v[q], acc[q].x);
+      acc[q].y = fma(ay, v[q], acc[q].y);
+    }
+  };
+  auto publish = [&](const T (&v)[4], T* buf) {
+    T c[4] = {v[0], v[1], v[2], v[3]};
+    if (TRANS) plaq_rot(c, th);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) buf[w.own[m]] = c[m];
+  };
+  // y = C' v (C'^T v) from the published slice: P'_B at the thread's sites
+  // from the 4x4 window (own values read back), then P'_A for C'.
+  auto finish = [&](T (&y)[4], const T* sl) {
+    __syncthreads();
+    const T c[4] = {sl[w.own[0]], sl[w.own[1]], sl[w.own[2]], sl[w.own[3]]};
+    const T a0 = sl[w.hm[0]], a1 = sl[w.hm[1]], a2 = sl[w.hm[2]], a3 = sl[w.hm[3]];
+    const T m0 = sl[w.cm[0]], m1 = sl[w.cm[1]], p0 = sl[w.cp[0]], p1 = sl[w.cp[1]];
+    const T b0 = sl[w.hp[0]], b1 = sl[w.hp[1]], b2 = sl[w.hp[2]], b3 = sl[w.hp[3]];
+    const T h00 = fma(th, a0, a1), h10 = fma(th, a3, a2);
+    const T h01 = fma(th, m0, c[0]), h11 = fma(th, p0, c[1]);
+    const T h02 = fma(th, m1, c[2]), h12 = fma(th, p1, c[3]);
+    const T h03 = fma(th, b0, b1), h13 = fma(th, b3, b2);
+    y[0] = fma(th, h00, h01);
+    y[1] = fma(th, h10, h11);
+    y[2] = fma(th, h03, h02);
+    y[3] = fma(th, h13, h12);
+    if (!TRANS) plaq_rot(y, th);
+  };
+  T sdb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sdb[k] = sA * db[k];
+  const T c2 = (T)2 * cA;
+  // v = 2 sA D y - c2 u - v
+  auto rec = [&](T (&v)[4], const T (&u)[4], const T (&y)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = fma(sdb[k], y[k], fma(sdb[k], y[k], fma(-c2, u[k], -v[k])));
+  };
+  T p[4], q[4], y[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = TRANS ? db[k] * x[k] : x[k];
+  if (NP >= 2) publish(p, buf0);
+  accumulate(cf[0], p);
+  if (NP < 2) return;
+  T2 c = cf[1];
+  finish(y, buf0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = fma(sdb[k], y[k], -cA * p[k]);
+  if (NP > 2) publish(q, buf1);
+  accumulate(c, q);
+  for (int m = 2; m < NP; m += 2) {
+    c = cf[m];
+    finish(y, buf1);
+    rec(p, q, y);
+    if (m + 1 < NP) publish(p, buf0);
+    accumulate(c, p);
+    if (m + 1 >= NP) break;
+    c = cf[m + 1];
+    finish(y, buf0);
+    rec(q, p, y);
+    if (m + 2 < NP) publish(q, buf1);
+    accumulate(c, q);
+  }
+  // A following series first writes buffer 0; after an odd number of
+  // exchanges the last one read buffer 0, so every thread must be past it.
+  if ((NP - 1) & 1) __syncthreads();
+}
+
 // Per-block Chebyshev apply.  op 0: F (series in A), 1: F^T (conjugate
 // series in A^T), 2: F F^T (conjugate series, then series).  Block b
 // serves frequency order b / nrhs (longest series first: k = 0, H-1, 1,
@@ -1064,10 +1153,38 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   if ((int)threadIdx.x < NP) cfs[threadIdx.x] = c_first;
   for (int m = threadIdx.x + NT; m < NP; m += NT) cfs[m] = coef[(long)k * kNPMax + m];
   __syncthreads();
+  // FP64 in 1 024-thread blocks: the series one real part at a time.
+  constexpr bool kParts = sizeof(T) == 8 && NT >= 1024 && !ROW16;
+  T* rb0 = reinterpret_cast<T*>(buf0);
+  T* rb1 = reinterpret_cast<T*>(buf1);
+  auto series = [&](auto trans_tag) {
+    constexpr bool TR = decltype(trans_tag)::value;
+    if constexpr (kParts) {
+      T xr[4], xi[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        xr[m] = x[m].x;
+        xi[m] = x[m].y;
+        acc[m].x = acc[m].y = (T)0;
+      }
+      cheb_series_part<T, TR>(w, NP, cfs, sA, cA, xr, db, rb0, rb1, th, acc, 0);
+      cheb_series_part<T, TR>(w, NP, cfs, sA, cA, xi, db, rb0, rb1, th, acc, 1);
+      if (TR) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const T inv = (T)1 / db[m];
+          acc[m].x *= inv;
+          acc[m].y *= inv;
+        }
+      }
+    } else {
+      cheb_series<T, TR, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
+    }
+  };
   if (op == 0) {
-    cheb_series<T, false, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
+    series(std::false_type{});
   } else {
-    cheb_series<T, true, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
+    series(std::true_type{});
     if (op == 2) {
       if (late) {
         state_finish<NT>(io, r, sl, &s_sh);
@@ -1078,7 +1195,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m) x[m] = acc[m];
-      cheb_series<T, false, ROW16>(w, NP, cfs, sA, cA, x, db, buf0, buf1, th, acc, q, g.Q);
+      series(std::false_type{});
     }
   }
   if (own) {
