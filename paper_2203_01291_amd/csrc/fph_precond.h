@@ -994,16 +994,23 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
 // recurrence of cheb_series runs on the real part (part 0) and on the
 // imaginary part (part 1) of the input separately; each part adds its
 // terms to the complex sum times c_m (conjugated for TRANS) and times 1 or
-// i.  The caller zeroes acc before the first part and, for TRANS, scales by
-// D^-1 after the second.  The thread's published values are read back from
-// LDS and 2 sA D is applied as two fused multiply-adds, both to save
-// registers.
+// i.  sdb holds sA D.  The caller zeroes acc before the first part and,
+// for TRANS, scales by D^-1 after the second.  The thread's published
+// values are read back from LDS and 2 sA D is applied as two fused
+// multiply-adds, both to save registers.
 template <typename T, bool TRANS>
 FPH_DEVINL void cheb_series_part(const Win& w, int NP, const typename Cplx<T>::type* cf, T sA,
-                                 T cA, const T (&x)[4], const T (&db)[4], T* buf0, T* buf1, T th,
+                                 T cA, const T (&x)[4], const T (&sdb)[4], T* buf0, T* buf1, T th,
                                  typename Cplx<T>::type (&acc)[4], int part) {
   using T2 = typename Cplx<T>::type;
   const T cj = TRANS ? (T)-1 : (T)1;
+  // The window's sixteen LDS indices from five values and the plane and
+  // row strides P, S (uniform): own sites B + {0, P, S, P + S}; columns
+  // x0 - 1 and x0 + 2 at row y0 from Cm and Cp; rows y0 - 1 and y0 + 2 are
+  // row y0 shifted by Rm and Rp (periodic).
+  const int B = w.own[0], Pp = w.own[1] - w.own[0], S = w.own[2] - w.own[0];
+  const int Cm = w.cm[0], Cp = w.cp[0];
+  const int Rm = w.hm[1] - B, Rp = w.hp[1] - B;
   auto accumulate = [&](const T2 c, const T (&v)[4]) {
     const T cr = c.x, ci = cj * c.y;
     const T ax = part ? -ci : cr, ay = part ? cr : ci;
@@ -1016,17 +1023,19 @@ FPH_DEVINL void cheb_series_part(const Win& w, int NP, const typename Cplx<T>::t
   auto publish = [&](const T (&v)[4], T* buf) {
     T c[4] = {v[0], v[1], v[2], v[3]};
     if (TRANS) plaq_rot(c, th);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) buf[w.own[m]] = c[m];
+    buf[B] = c[0];
+    buf[B + Pp] = c[1];
+    buf[B + S] = c[2];
+    buf[B + Pp + S] = c[3];
   };
   // y = C' v (C'^T v) from the published slice: P'_B at the thread's sites
   // from the 4x4 window (own values read back), then P'_A for C'.
   auto finish = [&](T (&y)[4], const T* sl) {
     __syncthreads();
-    const T c[4] = {sl[w.own[0]], sl[w.own[1]], sl[w.own[2]], sl[w.own[3]]};
-    const T a0 = sl[w.hm[0]], a1 = sl[w.hm[1]], a2 = sl[w.hm[2]], a3 = sl[w.hm[3]];
-    const T m0 = sl[w.cm[0]], m1 = sl[w.cm[1]], p0 = sl[w.cp[0]], p1 = sl[w.cp[1]];
-    const T b0 = sl[w.hp[0]], b1 = sl[w.hp[1]], b2 = sl[w.hp[2]], b3 = sl[w.hp[3]];
+    const T c[4] = {sl[B], sl[B + Pp], sl[B + S], sl[B + Pp + S]};
+    const T a0 = sl[Cm + Rm], a1 = sl[B + Rm], a2 = sl[B + Pp + Rm], a3 = sl[Cp + Rm];
+    const T m0 = sl[Cm], m1 = sl[Cm + S], p0 = sl[Cp], p1 = sl[Cp + S];
+    const T b0 = sl[Cm + Rp], b1 = sl[B + Rp], b2 = sl[B + Pp + Rp], b3 = sl[Cp + Rp];
     const T h00 = fma(th, a0, a1), h10 = fma(th, a3, a2);
     const T h01 = fma(th, m0, c[0]), h11 = fma(th, p0, c[1]);
     const T h02 = fma(th, m1, c[2]), h12 = fma(th, p1, c[3]);
@@ -1037,9 +1046,6 @@ FPH_DEVINL void cheb_series_part(const Win& w, int NP, const typename Cplx<T>::t
     y[3] = fma(th, h13, h12);
     if (!TRANS) plaq_rot(y, th);
   };
-  T sdb[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) sdb[k] = sA * db[k];
   const T c2 = (T)2 * cA;
   // v = 2 sA D y - c2 u - v
   auto rec = [&](T (&v)[4], const T (&u)[4], const T (&y)[4]) {
@@ -1048,7 +1054,7 @@ FPH_DEVINL void cheb_series_part(const Win& w, int NP, const typename Cplx<T>::t
   };
   T p[4], q[4], y[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) p[k] = TRANS ? db[k] * x[k] : x[k];
+  for (int k = 0; k < 4; ++k) p[k] = TRANS ? (sdb[k] / sA) * x[k] : x[k];
   if (NP >= 2) publish(p, buf0);
   accumulate(cf[0], p);
   if (NP < 2) return;
@@ -1160,19 +1166,26 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   auto series = [&](auto trans_tag) {
     constexpr bool TR = decltype(trans_tag)::value;
     if constexpr (kParts) {
-      T xr[4], xi[4];
+      // The imaginary part waits in the unused upper half of buffer 0
+      // (the real-valued exchanges use its first nbuf values) while the
+      // real part's series runs; each thread reads back what it wrote.
+      T* stash = rb0 + nbuf;
+      T xp[4], sdb[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        xr[m] = x[m].x;
-        xi[m] = x[m].y;
+        xp[m] = x[m].x;
+        stash[w.own[m]] = x[m].y;
         acc[m].x = acc[m].y = (T)0;
+        sdb[m] = sA * db[m];
       }
-      cheb_series_part<T, TR>(w, NP, cfs, sA, cA, xr, db, rb0, rb1, th, acc, 0);
-      cheb_series_part<T, TR>(w, NP, cfs, sA, cA, xi, db, rb0, rb1, th, acc, 1);
+      cheb_series_part<T, TR>(w, NP, cfs, sA, cA, xp, sdb, rb0, rb1, th, acc, 0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) xp[m] = stash[w.own[m]];
+      cheb_series_part<T, TR>(w, NP, cfs, sA, cA, xp, sdb, rb0, rb1, th, acc, 1);
       if (TR) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const T inv = (T)1 / db[m];
+          const T inv = sA / sdb[m];  // D^-1
           acc[m].x *= inv;
           acc[m].y *= inv;
         }
