@@ -588,9 +588,9 @@ def blas_threads():
 # FETCH_SIZE scale 518400 / 259212.56 = 1.99990 (a copy of 518 400 KiB reads
 # that much), WRITE_SIZE scale 1.0; bytes per launch = (FETCH * 1.99990 +
 # WRITE) KiB * 1024, means over 10 launches.
-TRAFFIC = {"f64_bytes_per_launch": 1091018408, "f32_bytes_per_launch": 1088486781,
+TRAFFIC = {"f64_bytes_per_launch": 1091000387, "f32_bytes_per_launch": 1088694773,
            "fetch_scale": 1.99990, "write_scale": 1.0,
-           "source_sha1": "3570febed2aa59d2bd88d381d125be242fbfdfad",
+           "source_sha1": "80fb8aff04373d3df6b9f6ec21d3a8bd1b3556d9",
            "profile": "profiles/mtm_L64_Ltau400_roofline_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
