@@ -1282,15 +1282,17 @@ size_t pc_tile_lds(const PcTables* pc, int lks) {
 }
 
 // Tile width (log2) of the transforms, for workgroups of kTNT threads:
-// the widest tile up to 32 bytes of a slice row that leaves at least 256
-// tiles (each slice row of a tile is a separate short segment, so narrow
-// tiles cost more cache lines per byte; wide ones leave CUs idle), not
-// below 2 sites, and at most 64 KB of LDS per workgroup.
+// the widest tile up to 8 sites that leaves at least 256 tiles (each slice
+// row of a tile is a separate short segment, so narrow tiles cost more
+// cache lines per byte; wide ones leave CUs idle), not below 2 sites, and
+// at most 64 KB of LDS per workgroup.  (At L = 64 FP64 tiles of 4 sites
+// would make 1 024 workgroups, two rounds at the two workgroups of this
+// kernel a CU holds; 8 sites make one.)
 constexpr int kTNT = 512;
 
 template <typename T>
 int pc_tile_log2(const PcTables* pc, const Geom& g, int nrhs) {
-  int lks = (sizeof(T) == 8) ? 2 : 3;
+  int lks = 3;
   while (lks > 1 && (long)((g.N + (1 << lks) - 1) >> lks) * nrhs < 256) --lks;
   while (lks > 0 && pc_tile_lds<T>(pc, lks) > ((size_t)64 << 10)) --lks;
   return lks;
