@@ -212,7 +212,7 @@ def test_solve_parity_c2_with_and_without_precond():
 @pytest.mark.parametrize("shape", [(4, 8, 0.1, 1.0, 0.0, 1.0), (6, 6, 0.1, 1.0, 0.2, 1.3),
                                    (4, 40, 0.1, 1.0, 0.0, 1.0), (8, 10, 0.1, 0.9, 0.1, 1.2),
                                    (16, 16, 0.1, 1.0, 0.0, 1.5), (8, 100, 0.1, 1.0, 0.0, 1.0),
-                                   # transform tiles of 4 (L = 32) and 8/16 sites (L = 64)
+                                   # transform tiles of 8 sites (L = 32 and 64, two right-hand sides)
                                    (32, 40, 0.05, 1.0, -0.2, 1.2), (64, 40, 0.05, 1.0, 0.0, 1.5)])
 def test_precond_apply_parity(shape):
     lat = OL.Lattice(*shape)
@@ -233,6 +233,46 @@ def test_precond_apply_parity(shape):
         assert relmax(out, ref) < 1e-12, op
         out32 = s.precond(vg.float(), op).double().cpu().numpy()
         assert relmax(out32, ref) < 1e-5, op + " fp32"
+
+
+@pytest.mark.parametrize("shape,nrhs", [((6, 8, 0.1, 1.0, 0.1, 1.1), 64),
+                                         ((10, 12, 0.1, 1.0, -0.1, 1.2), 20)])
+def test_precond_apply_ragged_tiles(shape, nrhs):
+    """Enough right-hand sides for 8-site transform tiles on a lattice whose site count is not a
+    multiple of 8 (N = 36, 100): the last tile of every right-hand side is partly empty."""
+    lat = OL.Lattice(*shape)
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal((lat.Ltau, lat.N))
+    v = rng.standard_normal((nrhs, lat.Ltau, lat.N))
+    s = make_solver(lat, max_rhs=nrhs)
+    s.set_field(tgpu(x), a1=2.0, a2=3.0)
+    pc = OP.Preconditioner(lat, x, C=OL.checkerboard_C(lat), a1=2.0, a2=3.0)
+    assert s.precond_info()[1] == pc.NP
+    vg = tgpu(v)
+    for op, ref in (("F", pc.apply_F(v)), ("FT", pc.apply_F(v, transpose=True)),
+                    ("FFT", np.stack([pc.apply_FFt(v[r]) for r in range(nrhs)]))):
+        out = s.precond(vg, op).cpu().numpy()
+        assert relmax(out, ref) < 1e-12, op
+        out32 = s.precond(vg.float(), op).double().cpu().numpy()
+        assert relmax(out32, ref) < 1e-5, op + " fp32"
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_refined"])
+def test_preconditioned_solve_ragged_tiles(prec):
+    """64 right-hand sides on N = 36 sites: the CG update fused into the forward transform and
+    the r.z of the inverse run on 8-site tiles whose last one is partly empty; every solution
+    against the dense LU solve."""
+    lat = OL.Lattice(6, 8, 0.1, 1.0, 0.1, 1.1)
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((lat.Ltau, lat.N))
+    Phi = rng.standard_normal((64, lat.Ltau, lat.N))
+    u_ref = OS.solve_dense(lat, x, Phi)
+    s = make_solver(lat, max_rhs=64)
+    s.set_field(tgpu(x), a1=2.0, a2=3.0)
+    u, st = s.solve(tgpu(Phi), tol=1e-12, maxiter=5000, precond=True, prec=prec)
+    for r in range(64):
+        assert st[r]["status"] & 1, (r, st[r])
+        assert relmax(u[r].cpu().numpy(), u_ref[r]) < 1e-8, r
 
 
 def test_precond_symmetric_on_gpu():
