@@ -1110,16 +1110,20 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   const Win w = make_win(g, q, own);
   const int i0 = w.x0 + w.row[1], iL = i0 + g.L;
 
-  // The solver state is not needed before the series (the input is ready
-  // and the series depends on no scalar of the CG), so its loads are
-  // issued first and folded between the conjugate series and the series
-  // of F F^T, where they have long arrived; a right-hand side found
-  // finished or paused there skips the second series.  Only F or F^T alone
-  // (not used inside a solve) folds the state before the series.
-  // (The 1024-thread blocks have no registers to spare: they read the
-  // state after the block's input, as one step.)
+  // The series depends on no scalar of the CG, so inside a solve only one
+  // block per right-hand side reads the solver state: the one with the
+  // shortest series (the last of the longest-first order), which folds the
+  // pending |r|^2 and writes the state for the next kernel.  The other
+  // blocks never wait for the state; for a right-hand side that has
+  // finished or paused they compute a transform the next kernel ignores.
+  // The reading block issues the state loads first and folds them between
+  // the conjugate series and the series of F F^T, where they have long
+  // arrived (a right-hand side found finished or paused there skips the
+  // second series); only F or F^T alone folds before the series.  (The
+  // 1024-thread blocks have no registers to spare: they read the state
+  // after the block's input, as one step.)
   constexpr bool kIssueFirst = NT < 1024;
-  const bool stt = io.in != nullptr;
+  const bool stt = io.in != nullptr && ko == H - 1;
   StLoad<4> sl;
   if (kIssueFirst && stt) state_issue(io, r, sl);
   const int f = field_of(g, r);
@@ -1152,7 +1156,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
     else
       state_begin<NT>(io, r, &s_sh, nullptr);
     if (s_sh.done) {
-      state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+      state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, true);
       return;
     }
   }
@@ -1202,7 +1206,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
       if (late) {
         state_finish<NT>(io, r, sl, &s_sh);
         if (s_sh.done) {
-          state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+          state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, true);
           return;
         }
       }
@@ -1216,7 +1220,7 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
     st2c(Zout + i0, acc[0], acc[1]);
     st2c(Zout + iL, acc[2], acc[3]);
   }
-  if (stt) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, ko == 0);
+  if (stt) state_end(io, r, &s_sh, P_NONE, 0.0, 0, 1, true);
 }
 
 // ----------------------------------------------------------------- host
