@@ -421,17 +421,19 @@ struct StLoad {
   uint32_t w;  // state word `lane`
 };
 
+// The loads are unconditional (no branch per load, so none waits for the
+// ones before it): slots past the announced partials are read but never
+// added (state_finish adds only the first npart), and lanes past the
+// state's last word read that word again.
 template <int NS>
 FPH_DEVINL void state_issue(const StIO& io, int r, StLoad<NS>& L) {
+  static_assert(64 * NS <= kPStride, "preloaded partial slots stay inside the right-hand side's");
   if (threadIdx.x < 64) {
     const double* part = io.pin + (long)r * kPStride;
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      const int k = threadIdx.x + 64 * j;
-      L.pre[j] = (k < io.nhint) ? part[k] : 0.0;
-    }
+    for (int j = 0; j < NS; ++j) L.pre[j] = part[threadIdx.x + 64 * j];
     const uint32_t* sw = reinterpret_cast<const uint32_t*>(io.in + r);
-    L.w = ((int)threadIdx.x < kStWords) ? sw[threadIdx.x] : 0u;
+    L.w = sw[min((int)threadIdx.x, kStWords - 1)];
   }
 }
 
@@ -443,7 +445,11 @@ FPH_DEVINL void state_finish(const StIO& io, int r, const StLoad<NS>& L, RhsStat
     if ((int)threadIdx.x < kStWords) reinterpret_cast<uint32_t*>(s_sh)[threadIdx.x] = L.w;
     if (pend != P_NONE) {
       const double* part = io.pin + (long)r * kPStride;
-      double v = 0.0, v2 = 0.0;
+      // The sums start from -0, the exact identity of addition, so the
+      // first partial is not added to anything: a lane's first add would
+      // otherwise be computed as soon as its load arrives, stalling the
+      // wave right behind the state loads.
+      double v = -0.0, v2 = -0.0;
       if (npart <= io.nhint && npart <= 64 * NS) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {

@@ -288,28 +288,34 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
     T ra[kI], rb[kI], aa[kI], ab[kI], ua[kI], ub[kI], pa[kI], pb[kI];
     T2 tw[kI];
   };
+  // Items past the last pair, or on a site past the end of a ragged tile,
+  // load a valid element instead (slice 0, the last site): the loads stay
+  // unconditional, so none waits for the others, and the values are never
+  // used (stage 0 skips such items and stores nothing for a ragged site; a
+  // ragged site's column of the transforms is not written out).
   auto load = [&](Pass& P, int e0, bool all, bool dir, const T* p) {
 #pragma unroll
     for (int j = 0; j < kI; ++j) {
       const int e = e0 + j * NT;
-      const int tau = e >> lks, sidx = e & (KS - 1);
-      const bool ok = e < npair && i0 + sidx < g.N;
-      const long oa = base + (long)tau * g.N + i0 + sidx;
+      const int ec = e < npair ? e : 0;
+      const int tau = ec >> lks;
+      const int site = min(i0 + (ec & (KS - 1)), g.N - 1);
+      const long oa = base + (long)tau * g.N + site;
       if (all) {
-        P.ra[j] = ok ? in[oa] : (T)0;
-        P.rb[j] = ok ? in[oa + hN] : (T)0;
-        P.tw[j] = e < npair ? tw[tau] : T2{(T)0, (T)0};
+        P.ra[j] = in[oa];
+        P.rb[j] = in[oa + hN];
+        P.tw[j] = tw[tau];
       }
       if (CGUPD) {
         if (all) {
-          P.aa[j] = ok ? Ap[oa] : (T)0;
-          P.ab[j] = ok ? Ap[oa + hN] : (T)0;
-          P.ua[j] = ok ? u[oa] : (T)0;
-          P.ub[j] = ok ? u[oa + hN] : (T)0;
+          P.aa[j] = Ap[oa];
+          P.ab[j] = Ap[oa + hN];
+          P.ua[j] = u[oa];
+          P.ub[j] = u[oa + hN];
         }
         if (dir) {
-          P.pa[j] = ok ? p[oa] : (T)0;
-          P.pb[j] = ok ? p[oa + hN] : (T)0;
+          P.pa[j] = p[oa];
+          P.pb[j] = p[oa + hN];
         }
       }
     }
@@ -325,12 +331,16 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   Pass P0;
   load(P0, threadIdx.x, true, false, pa);
   constexpr int kTab = kTabRegs ? 6 : 1;  // (H1^2 + H2^2 + H) <= 6 NT: H1 <= 20, H2 <= 32
-  T2 tab[kTab];
+  // Entry k of the LDS table is F[k] for k < nF, else W[k - nF]: both are
+  // loaded (indexes clamped into range, no branch) and the choice is made
+  // when the entry is stored.
+  T2 tab[kTab], tabw[kTab];
   if constexpr (kTabRegs) {
 #pragma unroll
     for (int j = 0; j < kTab; ++j) {
       const int k = threadIdx.x + j * NT;
-      tab[j] = (k < nF) ? F[k] : (k < nF + H ? W[k - nF] : T2{(T)0, (T)0});
+      tab[j] = F[min(k, nF - 1)];
+      tabw[j] = W[min(max(k - nF, 0), H - 1)];
     }
   } else {
     for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
@@ -347,7 +357,10 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 #pragma unroll
     for (int j = 0; j < kTab; ++j) {
       const int k = threadIdx.x + j * NT;
-      if (k < nF + H) Fl[k] = tab[j];  // Wl follows Fl
+      // Wl follows Fl.  (Two guarded stores: a select between the two
+      // register arrays can be compiled as an indexed private array.)
+      if (k < nF) Fl[k] = tab[j];
+      else if (k < nF + H) Fl[k] = tabw[j];
     }
   }
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
@@ -509,14 +522,38 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   // short DFT, once they have arrived.
   StLoad<0> sl;  // kpm, the kernel before in a solve, publishes no partials
   if (io.in != nullptr) state_issue(io, r, sl);
+  // DFT tables: LDS entry k is F[k] for k < nF, else W[k - nF].  The first
+  // kTabR NT entries are loaded into registers here, with the inputs, and
+  // stored once they have arrived (a load-and-store loop here would wait
+  // for every load issued before it); both arrays are read at clamped
+  // indexes and the choice is made at the store.
+  constexpr int kTabR = 2;
+  T2 tabf[kTabR], tabw[kTabR];
+#pragma unroll
+  for (int j = 0; j < kTabR; ++j) {
+    const int k = threadIdx.x + j * NT;
+    tabf[j] = F[min(k, nF - 1)];
+    tabw[j] = W[min(max(k - nF, 0), H - 1)];
+  }
+  // In FP32, out-of-range items load a valid element instead (no branch,
+  // so no load waits for the ones before it); their values are never
+  // used: only items in range reach LDS, and a ragged site's column is not
+  // written out.  (In FP64 that form puts v in private memory; there the
+  // loads stay conditional.)
   T2 v[kI];
   auto load = [&](int e0) {
 #pragma unroll
     for (int j = 0; j < kI; ++j) {
       const int e = e0 + j * NT;
-      const int k = e >> lks, sidx = e & (KS - 1);
-      v[j] = (e < nel && i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx]
-                                         : T2{(T)0, (T)0};
+      if constexpr (sizeof(T) == 4) {
+        const int ec = e < nel ? e : 0;
+        const int site = min(i0 + (ec & (KS - 1)), g.N - 1);
+        v[j] = Zh[((long)r * H + (ec >> lks)) * g.N + site];
+      } else {
+        const int k = e >> lks, sidx = e & (KS - 1);
+        v[j] = (e < nel && i0 + sidx < g.N) ? Zh[((long)r * H + k) * g.N + i0 + sidx]
+                                           : T2{(T)0, (T)0};
+      }
     }
   };
   load(threadIdx.x);
@@ -535,21 +572,30 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   if (pair) {
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
-      const int it = threadIdx.x + j * NT;
-      const int sidx = it & (KS - 1), pi = it >> lks;  // k1 + H1 k2, k2 < H2 / 2
-      const bool ok = it < (KS * H) / 2 && i0 + sidx < g.N;
-      const long oa = base + (long)pi * g.N + i0 + sidx;
+      // As above, out-of-range items load valid elements they never use
+      // (rdot is a readable buffer even without r.z).
+      const int it0 = threadIdx.x + j * NT;
+      const int it = it0 < (KS * H) / 2 ? it0 : 0;
+      const int pi = it >> lks;  // k1 + H1 k2, k2 < H2 / 2
+      const long oa = base + (long)pi * g.N + min(i0 + (it & (KS - 1)), g.N - 1);
       const long oc = oa + (long)hh * g.N;
-      twp[j][0] = ok ? tw[pi] : T2{(T)0, (T)0};
-      twp[j][1] = ok ? tw[pi + hh] : T2{(T)0, (T)0};
-      rdp[j][0] = (ok && dot) ? rdot[oa] : (T)0;
-      rdp[j][1] = (ok && dot) ? rdot[oa + hN] : (T)0;
-      rdp[j][2] = (ok && dot) ? rdot[oc] : (T)0;
-      rdp[j][3] = (ok && dot) ? rdot[oc + hN] : (T)0;
+      twp[j][0] = tw[pi];
+      twp[j][1] = tw[pi + hh];
+      rdp[j][0] = rdot[oa];
+      rdp[j][1] = rdot[oa + hN];
+      rdp[j][2] = rdot[oc];
+      rdp[j][3] = rdot[oc + hN];
     }
   }
-  for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
-  for (int k = threadIdx.x; k < H; k += NT) Wl[k] = W[k];
+#pragma unroll
+  for (int j = 0; j < kTabR; ++j) {
+    const int k = threadIdx.x + j * NT;
+    // Wl follows Fl.  (Two guarded stores: a select between the two
+    // register arrays can be compiled as an indexed private array.)
+    if (k < nF) Fl[k] = tabf[j];
+    else if (k < nF + H) Fl[k] = tabw[j];
+  }
+  for (int k = threadIdx.x + kTabR * NT; k < nF + H; k += NT) Fl[k] = k < nF ? F[k] : W[k - nF];
   const T scale = (T)(2.0 / sqrt((double)g.Ltau));
   double acc_dot = 0.0;
 
@@ -1137,18 +1183,13 @@ k_kpm(Geom g, int H, int nrhs, int op, const PcInfo* __restrict__ info,
   T2 x[4], acc[4];
   T db[4];
   const T2* Zin = Z + ((long)r * H + k) * g.N;
-  if (own) {
-    ld2c(Zin + i0, x[0], x[1]);
-    ld2c(Zin + iL, x[2], x[3]);
-    db[0] = c4 * dbar[i0]; db[1] = c4 * dbar[i0 + 1];
-    db[2] = c4 * dbar[iL]; db[3] = c4 * dbar[iL + 1];
-  } else {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      x[m].x = x[m].y = (T)0;
-      db[m] = (T)1;
-    }
-  }
+  // Unconditional loads (a thread without a plaquette reads plaquette 0's
+  // values, which only its spare LDS entry ever sees, and stores nothing),
+  // so that no load waits for the ones before it.
+  ld2c(Zin + i0, x[0], x[1]);
+  ld2c(Zin + iL, x[2], x[3]);
+  db[0] = c4 * dbar[i0]; db[1] = c4 * dbar[i0 + 1];
+  db[2] = c4 * dbar[iL]; db[3] = c4 * dbar[iL + 1];
   const bool late = kIssueFirst && stt && op == 2;
   if (stt && !late) {
     if constexpr (kIssueFirst)
@@ -1347,8 +1388,11 @@ hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs, int lks,
   auto kern = k_tinv<T, H1, NT>;
   hipError_t e = allow_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
+  // Without r.z the kernel still loads (and ignores) rdot: it then reads
+  // the input, which holds at least as many values.
+  const T* rd = dot ? rdot : reinterpret_cast<const T*>(Zh);
   hipLaunchKernelGGL(kern, dim3(ntiles * nrhs), dim3(NT), lds, s, g, pc->H2, tw, W, F, Zh, out,
-                     dot, rdot, lks, ntiles, io);
+                     dot, rd, lks, ntiles, io);
   return hipGetLastError();
 }
 
