@@ -331,16 +331,14 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   Pass P0;
   load(P0, threadIdx.x, true, false, pa);
   constexpr int kTab = kTabRegs ? 6 : 1;  // (H1^2 + H2^2 + H) <= 6 NT: H1 <= 20, H2 <= 32
-  // Entry k of the LDS table is F[k] for k < nF, else W[k - nF]: both are
-  // loaded (indexes clamped into range, no branch) and the choice is made
-  // when the entry is stored.
-  T2 tab[kTab], tabw[kTab];
+  // Entry k of the LDS table is F[k] for k < nF, else W[k - nF]: one load
+  // from a selected address (W's index clamped into range), no branch.
+  T2 tab[kTab];
   if constexpr (kTabRegs) {
 #pragma unroll
     for (int j = 0; j < kTab; ++j) {
       const int k = threadIdx.x + j * NT;
-      tab[j] = F[min(k, nF - 1)];
-      tabw[j] = W[min(max(k - nF, 0), H - 1)];
+      tab[j] = *(k < nF ? F + k : W + min(max(k - nF, 0), H - 1));
     }
   } else {
     for (int k = threadIdx.x; k < nF; k += NT) Fl[k] = F[k];
@@ -357,10 +355,7 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 #pragma unroll
     for (int j = 0; j < kTab; ++j) {
       const int k = threadIdx.x + j * NT;
-      // Wl follows Fl.  (Two guarded stores: a select between the two
-      // register arrays can be compiled as an indexed private array.)
-      if (k < nF) Fl[k] = tab[j];
-      else if (k < nF + H) Fl[k] = tabw[j];
+      if (k < nF + H) Fl[k] = tab[j];  // Wl follows Fl
     }
   }
   const T scale = (T)(1.0 / sqrt((double)g.Ltau));
@@ -525,15 +520,21 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   // DFT tables: LDS entry k is F[k] for k < nF, else W[k - nF].  The first
   // kTabR NT entries are loaded into registers here, with the inputs, and
   // stored once they have arrived (a load-and-store loop here would wait
-  // for every load issued before it); both arrays are read at clamped
-  // indexes and the choice is made at the store.
+  // for every load issued before it).  FP32: one load per entry from a
+  // selected address (W's index clamped into range); FP64, where that
+  // measured slower: both arrays at clamped indexes, one store of the two.
   constexpr int kTabR = 2;
-  T2 tabf[kTabR], tabw[kTabR];
+  constexpr bool kSel = sizeof(T) == 4;
+  T2 tabf[kTabR], tabw[kSel ? 1 : kTabR];
 #pragma unroll
   for (int j = 0; j < kTabR; ++j) {
     const int k = threadIdx.x + j * NT;
-    tabf[j] = F[min(k, nF - 1)];
-    tabw[j] = W[min(max(k - nF, 0), H - 1)];
+    if constexpr (kSel) {
+      tabf[j] = *(k < nF ? F + k : W + min(max(k - nF, 0), H - 1));
+    } else {
+      tabf[j] = F[min(k, nF - 1)];
+      tabw[j] = W[min(max(k - nF, 0), H - 1)];
+    }
   }
   // In FP32, out-of-range items load a valid element instead (no branch,
   // so no load waits for the ones before it); their values are never
@@ -590,10 +591,14 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 #pragma unroll
   for (int j = 0; j < kTabR; ++j) {
     const int k = threadIdx.x + j * NT;
-    // Wl follows Fl.  (Two guarded stores: a select between the two
-    // register arrays can be compiled as an indexed private array.)
-    if (k < nF) Fl[k] = tabf[j];
-    else if (k < nF + H) Fl[k] = tabw[j];
+    // Wl follows Fl.  (Guarded stores: a select between the two register
+    // arrays can be compiled as an indexed private array.)
+    if constexpr (kSel) {
+      if (k < nF + H) Fl[k] = tabf[j];
+    } else {
+      if (k < nF) Fl[k] = tabf[j];
+      else if (k < nF + H) Fl[k] = tabw[j];
+    }
   }
   for (int k = threadIdx.x + kTabR * NT; k < nF + H; k += NT) Fl[k] = k < nF ? F[k] : W[k - nF];
   const T scale = (T)(2.0 / sqrt((double)g.Ltau));
