@@ -183,28 +183,24 @@ struct StIO {
   const double* pin;   // pending partials, [rhs][kPStride]
   double* pout;        // partials written by this kernel
   int precond;         // preconditioned CG (z != r)
-  int nhint;           // partials the previous kernel in the sequence wrote
-                       // (loaded before the state arrives; a wrong hint only
-                       // costs a second load)
 };
 
 // Ping-pong bookkeeping of the CG state for a sequence of launches: each
-// state-aware kernel reads copy `cur`, writes copy `cur ^ 1`; `np` is the
-// number of partials per right-hand side the launch will write (0: none).
-// The sequence depends only on the launches, never on values, so the host
-// can enqueue a whole solve without reading anything back.
+// state-aware kernel reads copy `cur`, writes copy `cur ^ 1` (and its
+// partial sums, at most kPStride per right-hand side, to the partial
+// buffer of the same parity).  The sequence depends only on the launches,
+// never on values, so the host can enqueue a whole solve without reading
+// anything back.
 struct StateSeq {
   RhsState* st[2];
   double* part[2];
   int cur;
   int precond;
   bool active;  // false: plain operator calls without solver state
-  int np_prev;
-  StIO next(int np) {
-    if (!active) return StIO{nullptr, nullptr, nullptr, nullptr, precond, 0};
-    StIO io{st[cur], st[cur ^ 1], part[cur], part[cur ^ 1], precond, np_prev};
+  StIO next() {
+    if (!active) return StIO{nullptr, nullptr, nullptr, nullptr, precond};
+    StIO io{st[cur], st[cur ^ 1], part[cur], part[cur ^ 1], precond};
     cur ^= 1;
-    np_prev = np;
     return io;
   }
   RhsState* latest() const { return st[cur]; }
@@ -402,8 +398,8 @@ FPH_DEVINL void apply_pending(RhsState& s, int kind, double tot, double tot2, in
 
 // Reading the state of right-hand side r is split in two so that a kernel
 // can issue the loads first and fold them where it needs the result:
-// state_issue (first wave only) loads the pending partials announced by
-// the hint and the state itself, one 32-bit word per lane.  These are
+// state_issue (first wave only) loads the first 64 NS partial slots and
+// the state itself, one 32-bit word per lane.  These are
 // vector loads: a barrier waits only for LDS and scalar loads, so they stay
 // in flight across the kernel's own LDS exchanges.  state_finish writes the
 // words into s_sh, sums the partials (lane l adds partials l, l + 64, ...
@@ -414,7 +410,7 @@ static_assert(sizeof(RhsState) % 4 == 0 && kStWords <= 64, "one state word per l
 
 // NS: partials per lane loaded ahead (lane l: l, l + 64, ...); a kernel
 // that holds the loads for long takes few, and more pending partials than
-// 64 NS (or than the hint) are loaded when folded.
+// 64 NS are loaded when folded.
 template <int NS>
 struct StLoad {
   double pre[NS > 0 ? NS : 1];
@@ -450,7 +446,7 @@ FPH_DEVINL void state_finish(const StIO& io, int r, const StLoad<NS>& L, RhsStat
       // otherwise be computed as soon as its load arrives, stalling the
       // wave right behind the state loads.
       double v = -0.0, v2 = -0.0;
-      if (npart <= io.nhint && npart <= 64 * NS) {
+      if (npart <= 64 * NS) {  // all of them were loaded ahead
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
           if (64 * j >= npart) break;  // uniform

@@ -236,7 +236,7 @@ hipError_t launch_slot_mtm_cfg(const fph_handle_s* h, int nrhs, const SlotArgs<T
   const int nchunks = (g.Ltau + Tch - 1) / Tch;
   const int nblk = (nchunks + S - 1) / S;
   if (nblk > kPHalf) return hipErrorInvalidConfiguration;  // two-value partials
-  const StIO io = sq.next(nblk);
+  const StIO io = sq.next();
   hipLaunchKernelGGL(kern, dim3(nblk * nrhs), dim3(NT), lds, s, g, Tch, nblk, a, io);
   return hipGetLastError();
 }
@@ -563,7 +563,7 @@ int fph_precond_apply(fph_handle_t h, int32_t op, int32_t prec, int32_t nrhs, co
   if (op < 0 || op > 2 || (prec != FPH_F64 && prec != FPH_F32)) return FPH_E_PREC;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  StateSeq sq{{nullptr, nullptr}, {nullptr, nullptr}, 0, 0, false, 0};
+  StateSeq sq{{nullptr, nullptr}, {nullptr, nullptr}, 0, 0, false};
   if (prec == FPH_F64)
     e = pc_apply<double>(&h->pc, h->g, h->dbar64, op, nrhs, (const double*)in_dev,
                          (double*)out_dev, nullptr, sq, s);
@@ -613,7 +613,7 @@ hipError_t enqueue_slot(fph_handle_s* h, int nrhs, bool pre, const SlotArgs<TI>&
   if (!pre) {
     const int nb = elem_blocks(h->g.d);
     hipLaunchKernelGGL(k_cg_update<TI>, dim3(nb, nrhs), dim3(256), 0, s, h->g.d, uit,
-                       (const TI*)w.pa, (const TI*)w.pb, w.r, (const TI*)w.Ap, sq.next(nb));
+                       (const TI*)w.pa, (const TI*)w.pb, w.r, (const TI*)w.Ap, sq.next());
     return hipGetLastError();
   }
   return pc_cg_update<TI>(&h->pc, h->g, w.dbar, nrhs, uit, w.pa, w.pb, w.r, w.Ap, w.z, sq, s);
@@ -649,7 +649,7 @@ struct SolveRun {
     init.max_outer = max_outer;
     init.refined = mixed ? 1 : 0;
     init.pad = 0;
-    sq = StateSeq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true, 0};
+    sq = StateSeq{{h->st[0], h->st[1]}, {h->part[0], h->part[1]}, 0, pre ? 1 : 0, true};
     w64 = Work<double>{h->r64, h->z64, h->pa64, h->pb64, h->Ap64, h->dbar64};
     w32 = Work<float>{h->r32, h->z32, h->pa32, h->pb32, h->Ap32, h->dbar32};
     a64 = SlotArgs<double>{h->E64, h->E64, h->th, h->th, pre ? w64.z : w64.r, w64.pa, w64.pb,

@@ -1355,7 +1355,7 @@ hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, int lks, T
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
   if (pc->H1 * pc->H1 + pc->H2 * pc->H2 + pc->H > 6 * NT) return hipErrorInvalidValue;
-  const StIO io = sq.next(cgupd ? ntiles : 0);
+  const StIO io = sq.next();
   const size_t lds = pc_tile_lds<T>(pc, lks);
   using T2 = typename Cplx<T>::type;
   const auto* tw = (const T2*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
@@ -1384,7 +1384,7 @@ hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs, int lks,
                          StateSeq& sq, hipStream_t s) {
   const int KS = 1 << lks;
   const int ntiles = (g.N + KS - 1) / KS;
-  const StIO io = sq.next(dot ? ntiles : 0);
+  const StIO io = sq.next();
   const size_t lds = pc_tile_lds<T>(pc, lks);
   using T2 = typename Cplx<T>::type;
   const auto* tw = (const T2*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
@@ -1434,7 +1434,7 @@ template <typename T, int NT, bool ROW16 = false>
 hipError_t pc_launch_kpm(const PcTables* pc, const Geom& g, const T* dbar, int op, int nrhs,
                          const typename Cplx<T>::type* Z, typename Cplx<T>::type* Zo,
                          StateSeq& sq, T th, T c4, hipStream_t s) {
-  const StIO io = sq.next(0);
+  const StIO io = sq.next();
   const size_t nbuf = 2 * (size_t)kpm_row_stride(g.hL) * g.L + kWinPad;
   const size_t lds = (2 * nbuf + kNPMax) * sizeof(typename Cplx<T>::type);
   auto kern = k_kpm<T, NT, ROW16>;
