@@ -133,7 +133,7 @@ k_cg_update(long d, T* __restrict__ u, const T* pa, const T* pb, T* __restrict__
     acc += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y +
            (double)rr.z * (double)rr.z + (double)rr.w * (double)rr.w;
   }
-  const double bs = block_sum<256>(acc, red_sh);
+  const double bs = block_sum<256, true>(acc, red_sh);
   if (threadIdx.x == 0) s_sh.u32z = 0;
   state_end(io, rh, &s_sh, P_RR, bs, blockIdx.x, gridDim.x, blockIdx.x == 0);
 }

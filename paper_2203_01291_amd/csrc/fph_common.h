@@ -252,8 +252,10 @@ FPH_DEVINL double wave_sum_fixed(double v) {
   return ((readlane_d(v, 0) + readlane_d(v, 16)) + readlane_d(v, 32)) + readlane_d(v, 48);
 }
 
-// Sum of one double over the workgroup; result valid in thread 0.
-template <int NT>
+// Sum of one double over the workgroup; result valid in thread 0.  LAST:
+// the kernel's last use of sh, so no barrier is needed after thread 0 has
+// read it (the kernel ends without waiting for it at its tail).
+template <int NT, bool LAST = false>
 FPH_DEVINL double block_sum(double v, double* sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   v = wave_sum_fixed(v);
@@ -264,7 +266,7 @@ FPH_DEVINL double block_sum(double v, double* sh) {
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) s += sh[w];
   }
-  __syncthreads();
+  if (!LAST) __syncthreads();
   return s;
 }
 

@@ -473,7 +473,7 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
   if (io.in != nullptr) {
     double bs = 0.0;
     if (upd) {
-      bs = block_sum<NT>(acc_rr, red_sh);
+      bs = block_sum<NT, true>(acc_rr, red_sh);
       if (threadIdx.x == 0) s_sh.u32z = 0;
     }
     state_end(io, r, &s_sh, upd ? P_RR : P_NONE, bs, tile, ntiles, tile == 0);
@@ -701,7 +701,7 @@ k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 
   if (io.in != nullptr) {
     double bs = 0.0;
-    if (dot) bs = block_sum<NT>(acc_dot, red_sh);
+    if (dot) bs = block_sum<NT, true>(acc_dot, red_sh);
     state_end(io, r, &s_sh, dot ? P_RZ : P_NONE, bs, tile, ntiles, tile == 0);
   }
 }

@@ -108,7 +108,7 @@ k_slot_mtm(Geom g, int Tch, int nblk, SlotArgs<TI> a, StIO io) {
     if (mtm_sweep<TI, NT, MS, 1>(g, a.E + fo, a.th, Tch, tau0, Tc, active, lane, nslot,
                                  reinterpret_cast<TI*>(smem_raw) + lo, base, in, epi, acc, acc2,
                                  hook)) {
-      const double bs = block_sum<NT>(acc, red_sh);
+      const double bs = block_sum<NT, true>(acc, red_sh);
       state_end(io, r, &s_sh, P_PAP, bs, bx, nblk, bx == 0);
       return;
     }
@@ -131,7 +131,7 @@ k_slot_mtm(Geom g, int Tch, int nblk, SlotArgs<TI> a, StIO io) {
                                  lds4, base, in, epi, acc, acc2, no_hook);
   }
   const double bs = block_sum<NT>(acc, red_sh);
-  const double bs2 = block_sum<NT>(acc2, red_sh);
+  const double bs2 = block_sum<NT, true>(acc2, red_sh);
   state_end(io, r, &s_sh, P_RES, bs, bx, nblk, bx == 0, bs2);
 }
 
