@@ -588,9 +588,9 @@ def blas_threads():
 # FETCH_SIZE scale 518400 / 259212.56 = 1.99990 (a copy of 518 400 KiB reads
 # that much), WRITE_SIZE scale 1.0; bytes per launch = (FETCH * 1.99990 +
 # WRITE) KiB * 1024, means over 10 launches.
-TRAFFIC = {"f64_bytes_per_launch": 1091008056, "f32_bytes_per_launch": 1088451463,
+TRAFFIC = {"f64_bytes_per_launch": 1091005489, "f32_bytes_per_launch": 1088632272,
            "fetch_scale": 1.99990, "write_scale": 1.0,
-           "source_sha1": "c37bf4f6ca812721bb4ab19ed6cb07e90aa4add2",
+           "source_sha1": "86a0076e6a01fc6bb3fa4b5e71a76f952deb24ba",
            "profile": "profiles/mtm_L64_Ltau400_roofline_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]
