@@ -957,9 +957,12 @@ FPH_DEVINL void c_finish(const Win& w, const T2 (&c)[4], T2 (&y)[4], const T2* b
 // the recurrence runs on beta_m = D alpha_m, which obeys the same
 // relation with C'^T in place of C' (D A^T D^{-1} = sA D C'^T - cA):
 // beta_0 = D x, and the sum is scaled by D^{-1} at the end.  Each new term
-// is published for the next apply before it is added to the sum, and the
-// coefficient is read before the barrier, so neither sits on the path from
-// one exchange to the next.  Exchange j of the series uses LDS buffer
+// is published for the next apply before it is added to the sum, and each
+// coefficient is read one step ahead, after a barrier, beside the
+// neighbours' values: read just before a barrier its latency would add to
+// the barrier's wait, and read in its own step its wait would come before
+// the sum that overlaps the publishing stores.  So neither sits on the
+// path from one exchange to the next.  Exchange j of the series uses LDS buffer
 // (j - 1) mod 2, fixed per step of the unrolled loop; a series always
 // starts on buffer 0.  The two latest terms alternate between two register
 // sets, so no copies are made.
@@ -1004,6 +1007,7 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
     }
     T2 c = cf[1];
     c_finish<T2, T, TRANS, ROW16>(w, c_, y, buf0, th, Q);
+    T2 cn = cf[min(2, NP - 1)];  // the next step's, read beside this step's values
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       q[k].x = fma(sdb[k], y[k].x, -cA * p[k].x);
@@ -1013,14 +1017,16 @@ FPH_DEVINL void cheb_series(const Win& w, int NP, const typename Cplx<T>::type* 
     accumulate(c, q);
     const T c2 = (T)2 * cA;
     for (int m = 2; m < NP; m += 2) {
-      c = cf[m];
       c_finish<T2, T, TRANS, ROW16>(w, c_, y, buf1, th, Q);
+      c = cn;
+      cn = cf[min(m + 1, NP - 1)];
       rec(p, q, y, db2, c2);
       if (m + 1 < NP) c_publish<T2, T, TRANS, ROW16>(w, p, buf0, th, c_, qid, Q);
       accumulate(c, p);
       if (m + 1 >= NP) break;
-      c = cf[m + 1];
       c_finish<T2, T, TRANS, ROW16>(w, c_, y, buf0, th, Q);
+      c = cn;
+      cn = cf[min(m + 2, NP - 1)];
       rec(q, p, y, db2, c2);
       if (m + 2 < NP) c_publish<T2, T, TRANS, ROW16>(w, q, buf1, th, c_, qid, Q);
       accumulate(c, q);
@@ -1111,19 +1117,22 @@ FPH_DEVINL void cheb_series_part(const Win& w, int NP, const typename Cplx<T>::t
   if (NP < 2) return;
   T2 c = cf[1];
   finish(y, buf0);
+  T2 cn = cf[min(2, NP - 1)];  // one step ahead, as in cheb_series
 #pragma unroll
   for (int k = 0; k < 4; ++k) q[k] = fma(sdb[k], y[k], -cA * p[k]);
   if (NP > 2) publish(q, buf1);
   accumulate(c, q);
   for (int m = 2; m < NP; m += 2) {
-    c = cf[m];
     finish(y, buf1);
+    c = cn;
+    cn = cf[min(m + 1, NP - 1)];
     rec(p, q, y);
     if (m + 1 < NP) publish(p, buf0);
     accumulate(c, p);
     if (m + 1 >= NP) break;
-    c = cf[m + 1];
     finish(y, buf0);
+    c = cn;
+    cn = cf[min(m + 2, NP - 1)];
     rec(q, p, y);
     if (m + 2 < NP) publish(q, buf1);
     accumulate(c, q);
