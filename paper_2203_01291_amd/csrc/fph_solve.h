@@ -101,14 +101,15 @@ k_slot_mtm(Geom g, int Tch, int nblk, SlotArgs<TI> a, StIO io) {
       path = s_sh.final_ ? 0 : (s_sh.replace ? 2 : (s_sh.done ? 0 : 1));
       if (path != 1) return false;
       in.begin(s_sh);
-      __syncthreads();  // every thread has read the state
-      if (threadIdx.x == 0) InPUpdate<TI, PF>::on_state(s_sh);
       return true;
     };
     if (mtm_sweep<TI, NT, MS, 1>(g, a.E + fo, a.th, Tch, tau0, Tc, active, lane, nslot,
                                  reinterpret_cast<TI*>(smem_raw) + lo, base, in, epi, acc, acc2,
                                  hook)) {
       const double bs = block_sum<NT, true>(acc, red_sh);
+      // The direction update enters the state only now: every thread read
+      // the state (in.begin) before the block sum's barrier.
+      if (threadIdx.x == 0) InPUpdate<TI, PF>::on_state(s_sh);
       state_end(io, r, &s_sh, P_PAP, bs, bx, nblk, bx == 0);
       return;
     }
