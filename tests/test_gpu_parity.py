@@ -314,27 +314,34 @@ def test_multi_rhs_independent_and_deterministic():
         assert rel(u1[r].cpu().numpy(), u_single[0].cpu().numpy()) < 1e-9
 
 
-def test_edge_cases():
+@pytest.mark.parametrize("prec", ["f64", "f32_refined"])
+@pytest.mark.parametrize("precond", [False, True])
+def test_edge_cases(prec, precond):
     p, lat, x0, x, phi, Phi = c1_problem(nrhs=2)
     s = make_solver(lat, max_rhs=2)
     s.set_field(tgpu(x))
-    # zero right-hand side: u = 0 exactly, converged
+    kw = dict(prec=prec, precond=precond)
+    # zero right-hand side: u = 0 exactly, converged; the other one unaffected
     B = np.stack([np.zeros_like(Phi[0]), Phi[1]])
-    u, st = s.solve(tgpu(B), tol=1e-10, u=tgpu(np.ones_like(B)))
+    u, st = s.solve(tgpu(B), tol=1e-13, u=tgpu(np.ones_like(B)), **kw)
     assert torch.count_nonzero(u[0]) == 0 and st[0]["status"] & 1
     assert st[1]["status"] & 1
+    u1_ref = OS.solve_dense(lat, x, Phi[1:2])[0]
+    assert np.max(np.abs(u[1].cpu().numpy() - u1_ref)) < 1e-8 * np.max(np.abs(u1_ref))
     # iteration cap
-    u, st = s.solve(tgpu(Phi), tol=1e-14, maxiter=5)
+    u, st = s.solve(tgpu(Phi), tol=1e-14, maxiter=5, **kw)
     assert all(v["status"] & 2 for v in st) and all(v["iters"] <= 5 + 32 for v in st)
     # warm start from the solution converges immediately
     u_ref = OS.solve_dense(lat, x, Phi)
-    u, st = s.solve(tgpu(Phi), u=tgpu(u_ref), tol=1e-10)
+    u, st = s.solve(tgpu(Phi), u=tgpu(u_ref), tol=1e-10, **kw)
     assert all(v["status"] & 1 for v in st) and all(v["iters"] <= 1 for v in st)
-    # non-finite input is reported, not hidden
+    # non-finite input is reported, not hidden, and does not leak into the
+    # other right-hand side
     Bn = Phi.copy()
     Bn[0, 3, 2] = np.nan
-    u, st = s.solve(tgpu(Bn), tol=1e-10, maxiter=50)
+    u, st = s.solve(tgpu(Bn), tol=1e-10, maxiter=20000, **kw)
     assert st[0]["status"] & 8
+    assert st[1]["status"] & 1 and not st[1]["status"] & 8
 
 
 def test_autograd_matches_oracle():
