@@ -552,23 +552,36 @@ def cpu_baseline(p, golden_iters):
 
 
 def host_cpu_model():
-    """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
+    """CPU model of the host: lscpu's model name (else /proc/cpuinfo's), with
+    the family / model / stepping numbers appended when the name carries no
+    model number (virtual machines often report only the brand)."""
     import subprocess
+    name = None
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
         for line in out.splitlines():
             if line.startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+                name = line.split(":", 1)[1].strip()
+                break
     except Exception:
         pass
+    ids = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # first processor only
+                k, _, v = line.partition(":")
+                ids[k.strip()] = v.strip()
     except Exception:
         pass
-    return None
+    if name is None:
+        name = ids.get("model name")
+    if name is not None and not any(c.isdigit() for c in name):
+        extra = ", ".join(f"{k} {ids[k]}" for k in ("cpu family", "model", "stepping") if k in ids)
+        if extra:
+            name = f"{name} ({extra})"
+    return name
 
 
 def blas_threads():
