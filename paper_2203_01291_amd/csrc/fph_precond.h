@@ -255,15 +255,16 @@ FPH_DEVINL void dft_pair(const T2* fr, const T2* y, int s, int n, T2& a, T2& b) 
 // n1 of y_{H2 n1 + n2}, times W_H^{n2 k1}.  Step 2, item (site, k1, k2):
 // the H2-point DFT over n2 -> Z_{k1 + H1 k2}.
 // Launch: grid ntiles * nrhs, NT threads; LDS (H1^2 + H2^2 + H + 2 H KS)
-// complex values.
-template <typename T, int H1, int NT, bool CGUPD>
+// complex values.  KI stage-0 items per thread and pass: 4 where 2 would
+// take a second pass (each pass is one dependent round trip to memory).
+template <typename T, int H1, int NT, bool CGUPD, int KI>
 __global__ void __launch_bounds__(NT)
 k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
        const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ F,
        T* __restrict__ in, typename Cplx<T>::type* __restrict__ Z, T* __restrict__ u,
        const T* pa, const T* pb, const T* __restrict__ Ap, int lks, int ntiles, StIO io) {
   using T2 = typename Cplx<T>::type;
-  constexpr int kI = 2;  // stage-0 items per thread and pass
+  constexpr int kI = KI;  // stage-0 items per thread and pass
   const int KS = 1 << lks;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = H1 * H2;
@@ -1371,19 +1372,17 @@ hipError_t pc_launch_fwd(const PcTables* pc, const Geom& g, int nrhs, int lks, T
   const auto* W = (const T2*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
   const auto* F = (const T2*)(sizeof(T) == 8 ? (const void*)pc->F64 : (const void*)pc->F32);
   dim3 grid(ntiles * nrhs);
-  if (cgupd) {
-    auto kern = k_tfwd<T, H1, NT, true>;
-    hipError_t e = allow_lds((const void*)kern, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, g, pc->H2, tw, W, F, in, Z, u, pa, pb, Ap,
-                       lks, ntiles, io);
-  } else {
-    auto kern = k_tfwd<T, H1, NT, false>;
-    hipError_t e = allow_lds((const void*)kern, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, g, pc->H2, tw, W, F, in, Z, u, pa, pb, Ap,
-                       lks, ntiles, io);
+  // FP32: four stage-0 items per thread where two would need a second
+  // pass (FP64 keeps two: its registers would cost occupancy).
+  const bool wide = sizeof(T) == 4 && (pc->H << lks) > 2 * NT;
+  auto kern = cgupd ? k_tfwd<T, H1, NT, true, 2> : k_tfwd<T, H1, NT, false, 2>;
+  if constexpr (sizeof(T) == 4) {
+    if (wide) kern = cgupd ? k_tfwd<T, H1, NT, true, 4> : k_tfwd<T, H1, NT, false, 4>;
   }
+  hipError_t e = allow_lds((const void*)kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(NT), lds, s, g, pc->H2, tw, W, F, in, Z, u, pa, pb, Ap, lks,
+                     ntiles, io);
   return hipGetLastError();
 }
 

@@ -235,18 +235,21 @@ def test_precond_apply_parity(shape):
         assert relmax(out32, ref) < 1e-5, op + " fp32"
 
 
-@pytest.mark.parametrize("shape,nrhs", [((6, 8, 0.1, 1.0, 0.1, 1.1), 64),
-                                         ((10, 12, 0.1, 1.0, -0.1, 1.2), 20)])
-def test_precond_apply_ragged_tiles(shape, nrhs):
+@pytest.mark.parametrize("shape,nrhs,a12", [((6, 8, 0.1, 1.0, 0.1, 1.1), 64, (2.0, 3.0)),
+                                             ((10, 12, 0.1, 1.0, -0.1, 1.2), 20, (2.0, 3.0)),
+                                             ((10, 400, 0.05, 1.0, -0.1, 1.2), 20, (0.15, 12.0))])
+def test_precond_apply_ragged_tiles(shape, nrhs, a12):
     """Enough right-hand sides for 8-site transform tiles on a lattice whose site count is not a
-    multiple of 8 (N = 36, 100): the last tile of every right-hand side is partly empty."""
+    multiple of 8 (N = 36, 100): the last tile of every right-hand side is partly empty.  At
+    Ltau = 400 (200 frequencies, DFT split 10 x 20) a tile holds 1 600 stage-0 items, four per
+    thread of the forward transform in FP32."""
     lat = OL.Lattice(*shape)
     rng = np.random.default_rng(17)
     x = rng.standard_normal((lat.Ltau, lat.N))
     v = rng.standard_normal((nrhs, lat.Ltau, lat.N))
     s = make_solver(lat, max_rhs=nrhs)
-    s.set_field(tgpu(x), a1=2.0, a2=3.0)
-    pc = OP.Preconditioner(lat, x, C=OL.checkerboard_C(lat), a1=2.0, a2=3.0)
+    s.set_field(tgpu(x), a1=a12[0], a2=a12[1])
+    pc = OP.Preconditioner(lat, x, C=OL.checkerboard_C(lat), a1=a12[0], a2=a12[1])
     assert s.precond_info()[1] == pc.NP
     vg = tgpu(v)
     for op, ref in (("F", pc.apply_F(v)), ("FT", pc.apply_F(v, transpose=True)),
@@ -271,6 +274,23 @@ def test_preconditioned_solve_ragged_tiles(prec):
     s.set_field(tgpu(x), a1=2.0, a2=3.0)
     u, st = s.solve(tgpu(Phi), tol=1e-12, maxiter=5000, precond=True, prec=prec)
     for r in range(64):
+        assert st[r]["status"] & 1, (r, st[r])
+        assert relmax(u[r].cpu().numpy(), u_ref[r]) < 1e-8, r
+
+
+def test_preconditioned_solve_wide_transform_ragged_tiles():
+    """FP32-refined preconditioned solve with the CG update fused into a forward transform of four
+    stage-0 items per thread (L = 10, Ltau = 400: 8-site tiles of 1 600 items, the last tile of
+    each of the 20 right-hand sides partly empty), against the sparse LU solve."""
+    lat = OL.Lattice(10, 400, 0.05, 1.0, -0.1, 1.2)
+    rng = np.random.default_rng(29)
+    x = 0.5 * rng.standard_normal((lat.Ltau, lat.N))
+    Phi = rng.standard_normal((20, lat.Ltau, lat.N))
+    u_ref = OS.solve_sparse(lat, x, Phi)
+    s = make_solver(lat, max_rhs=20)
+    s.set_field(tgpu(x), a1=0.15, a2=12.0)
+    u, st = s.solve(tgpu(Phi), tol=1e-12, maxiter=20000, precond=True, prec="f32_refined")
+    for r in range(20):
         assert st[r]["status"] & 1, (r, st[r])
         assert relmax(u[r].cpu().numpy(), u_ref[r]) < 1e-8, r
 
