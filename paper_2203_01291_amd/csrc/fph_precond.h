@@ -487,15 +487,17 @@ k_tfwd(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
 // to LDS with coalesced loads; the solver state, issued before them, is
 // folded after step 1 (it only decides whether the right-hand side is
 // skipped).  With dot != 0 also publishes rdot . out as P_RZ partials.  LDS:
-// (H1^2 + H2^2 + H + 2 H KS) complex values.
-template <typename T, int H1, int NT>
+// (H1^2 + H2^2 + H + 2 H KS) complex values.  KI input items per thread and
+// pass: 4, or 2 where that already covers the tile in one pass (FP32 loads
+// every item slot, in range or not).
+template <typename T, int H1, int NT, int KI>
 __global__ void __launch_bounds__(NT)
 k_tinv(Geom g, int H2, const typename Cplx<T>::type* __restrict__ tw,
        const typename Cplx<T>::type* __restrict__ W, const typename Cplx<T>::type* __restrict__ F,
        const typename Cplx<T>::type* __restrict__ Zh, T* __restrict__ out, int dot,
        const T* __restrict__ rdot, int lks, int ntiles, StIO io) {
   using T2 = typename Cplx<T>::type;
-  constexpr int kI = 4;
+  constexpr int kI = KI;
   const int KS = 1 << lks;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = H1 * H2;
@@ -1398,7 +1400,10 @@ hipError_t pc_launch_inv(const PcTables* pc, const Geom& g, int nrhs, int lks,
   const auto* tw = (const T2*)(sizeof(T) == 8 ? (const void*)pc->tw64 : (const void*)pc->tw32);
   const auto* W = (const T2*)(sizeof(T) == 8 ? (const void*)pc->W64 : (const void*)pc->W32);
   const auto* F = (const T2*)(sizeof(T) == 8 ? (const void*)pc->F64 : (const void*)pc->F32);
-  auto kern = k_tinv<T, H1, NT>;
+  auto kern = k_tinv<T, H1, NT, 4>;
+  if constexpr (sizeof(T) == 4) {
+    if ((pc->H << lks) <= 2 * NT) kern = k_tinv<T, H1, NT, 2>;
+  }
   hipError_t e = allow_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
   // Without r.z the kernel still loads (and ignores) rdot: it then reads
