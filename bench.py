@@ -601,9 +601,9 @@ def blas_threads():
 # FETCH_SIZE scale 518400 / 259212.56 = 1.99990 (a copy of 518 400 KiB reads
 # that much), WRITE_SIZE scale 1.0; bytes per launch = (FETCH * 1.99990 +
 # WRITE) KiB * 1024, means over 10 launches.
-TRAFFIC = {"f64_bytes_per_launch": 1091005489, "f32_bytes_per_launch": 1088632272,
+TRAFFIC = {"f64_bytes_per_launch": 1091013026, "f32_bytes_per_launch": 1088841079,
            "fetch_scale": 1.99990, "write_scale": 1.0,
-           "source_sha1": "86a0076e6a01fc6bb3fa4b5e71a76f952deb24ba",
+           "source_sha1": "7ebe70fca504328e6af8a94048a62e021c1fd05e",
            "profile": "profiles/mtm_L64_Ltau400_roofline_counters.md"}
 KERNEL_SOURCES = ["paper_2203_01291_amd/csrc/fph_matvec.h", "paper_2203_01291_amd/csrc/fph_common.h",
                   "paper_2203_01291_amd/csrc/fph_lib.hip"]

@@ -117,7 +117,8 @@ typedef struct {
                            residual more than twice the FP32 one          */
   int32_t chunk;        /* pcg_solve_sync: solver slots (iterations or
                            residual evaluations) enqueued between two
-                           progress probes (0 -> 16); variant 2: the
+                           progress probes (0 -> 16, or 8 when
+                           N Ltau > 2^20); variant 2: the
                            largest number of workgroups (0 -> 128)         */
   int32_t variant;      /* 0: the standard (P)CG of pcg_solve (two
                            launches per iteration without preconditioner,
@@ -224,7 +225,8 @@ int pcg_solve(fph_handle_t h, int32_t nrhs, const double* b_dev, double* u_dev,
 
 /* The same solve for callers that want the statistics on the host:
  * stats_host (nrhs entries, may be NULL) is filled on return.  Enqueues the
- * slots of pcg_solve in chunks of opts->chunk (0 -> 16); after each chunk
+ * slots of pcg_solve in chunks of opts->chunk (0 -> 16, or 8 above 2^20
+ * unknowns per right-hand side); after each chunk
  * a one-wave kernel writes how many right-hand sides are still open into
  * pinned host memory, the host waits for the previous chunk's count only
  * (the GPU always has a chunk queued) and stops enqueueing once it is zero.

@@ -122,9 +122,16 @@ struct fph_handle_s {
 namespace {
 
 // Residual evaluations after the first that a solve may use (opts.max_outer
-// = 0), and slots between the probes of the blocking driver (opts.chunk = 0).
+// = 0), and slots between the probes of the blocking driver (opts.chunk = 0):
+// 16, or 8 above 2^20 unknowns per right-hand side.  Once a solve has
+// finished, the rest of its chunk and the chunk queued behind it still run
+// (as idle slots); a probe costs a few microseconds.  At 409 600 unknowns
+// (one or ten right-hand sides) 16 wins; at 1 638 400 the idle slots cost
+// more than the extra probes, and 8 wins.
 constexpr int kDefaultMaxOuter = 32;
 constexpr long kDefaultSlotChunk = 16;
+constexpr long kDefaultSlotChunkLarge = 8;
+constexpr long kSlotChunkLargeAbove = 1L << 20;
 
 size_t vbytes(const fph_handle_s* h, size_t elem) { return (size_t)h->g.d * h->max_rhs * elem; }
 
@@ -845,7 +852,9 @@ extern "C" int pcg_solve_sync(fph_handle_t h, int32_t nrhs, const double* b_dev,
     FPH_CHECK(run.start(s));
     int* open_dev = nullptr;
     FPH_CHECK(hipHostGetDevicePointer((void**)&open_dev, h->open_pin, 0));
-    const long chunk = opts->chunk > 0 ? opts->chunk : kDefaultSlotChunk;
+    const long chunk = opts->chunk > 0 ? opts->chunk
+                       : (h->g.d > kSlotChunkLargeAbove ? kDefaultSlotChunkLarge
+                                                         : kDefaultSlotChunk);
     long enq = 0;
     for (int k = 0; enq < run.total; ++k) {
       const long n = std::min(chunk, run.total - enq);
